@@ -1,0 +1,329 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and by mathematics
+(closed forms, invariants, brute force on tiny inputs), never against itself."""
+import itertools
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import philox, pts, sampling, statevector as sv, tn, upv
+
+
+# ----------------------------------------------------------------- bit order
+def _circuit(n, gates):
+    c = W.Circuit(n)
+    for qs, m in gates:
+        c.add_gate(qs, m)
+    return c
+
+
+def test_cnot_truth_table_and_bit_order():
+    # qubit q <-> bit q of the amplitude index; CNOT(q0 -> q1) index 2*x[q0] + x[q1]
+    for ctrl, tgt in [(0, 1), (1, 0), (2, 0), (0, 2)]:
+        for inp in range(8):
+            c = W.Circuit(3)
+            for q in range(3):
+                if (inp >> q) & 1:
+                    c.add_gate((q,), W.pauli_x)
+            c.add_gate((ctrl, tgt), W.CNOT)
+            psi = sv.ideal_state(c)
+            out = inp ^ ((((inp >> ctrl) & 1)) << tgt)
+            assert abs(psi[out] - 1) < 1e-15, (ctrl, tgt, inp)
+
+
+def test_ghz_marginals_closed_form():
+    n = 4
+    gates = [((0,), W.HADAMARD)] + [((q, q + 1), W.CNOT) for q in range(n - 1)]
+    psi = sv.ideal_state(_circuit(n, gates))
+    assert abs(np.linalg.norm(psi) - 1) < 1e-14
+    # batch 1 = qubits {0,1}: P(00) = P(11) = 1/2
+    m = sampling.marginal_from_state(psi, n, 0, 2, 0)
+    np.testing.assert_allclose(m, [0.5, 0, 0, 0.5], atol=1e-15)
+    # given prefix 11 the last batch is fixed to 11; given 01 it has weight 0
+    m = sampling.marginal_from_state(psi, n, 2, 2, 0b11)
+    np.testing.assert_allclose(m, [0, 0, 0, 0.5], atol=1e-15)
+    assert np.all(sampling.marginal_from_state(psi, n, 2, 2, 0b01) == 0)
+
+
+def test_product_state_marginals_factorise():
+    rng = np.random.default_rng(7)
+    n = 5
+    gates, probs = [], []
+    for q in range(n):
+        th = rng.uniform(0, np.pi)
+        gates.append(((q,), W.ry(th)))
+        probs.append(np.sin(th / 2) ** 2)        # P(x_q = 1) for RY(th)|0>
+    psi = sv.ideal_state(_circuit(n, gates))
+    m = sampling.marginal_from_state(psi, n, 1, 3, 1)
+    want = np.zeros(8)
+    for x in range(8):
+        pr = probs[0]                            # prefix qubit 0 = 1
+        for k in range(3):
+            bit = (x >> k) & 1
+            pr *= probs[1 + k] if bit else 1 - probs[1 + k]
+        want[x] = pr
+    np.testing.assert_allclose(m, want, atol=1e-14)
+
+
+# ------------------------------------------------------------------- channels
+@pytest.mark.parametrize("ch", [W.depolarizing(0.01), W.depolarizing(0.3), W.amplitude_damping(0.02),
+                                W.amplitude_damping(0.7), W.depolarizing2(0.1)])
+def test_channels_are_cptp(ch):
+    d = ch.kraus.shape[1]
+    s = sum(k.conj().T @ k for k in ch.kraus)
+    np.testing.assert_allclose(s, np.eye(d), atol=1e-14)
+    q = upv.proposal(ch)
+    assert abs(q.sum() - 1) < 1e-14 and np.all(q > 0)
+
+
+def test_pauli_inserted_operators_are_unitary():
+    for ch in [W.depolarizing(0.2), W.depolarizing2(0.1)]:
+        for k in range(len(ch.kraus)):
+            op = upv.inserted_operator(ch, k)
+            np.testing.assert_allclose(op.conj().T @ op, np.eye(op.shape[0]), atol=1e-14)
+
+
+def test_haar_su4():
+    rng = np.random.default_rng(3)
+    for _ in range(20):
+        u = W.haar_su4(rng)
+        np.testing.assert_allclose(u.conj().T @ u, np.eye(4), atol=1e-13)
+        assert abs(np.linalg.det(u) - 1) < 1e-12
+
+
+def test_embed_matches_kron():
+    rng = np.random.default_rng(4)
+    a = rng.standard_normal((2, 2)) + 1j * rng.standard_normal((2, 2))
+    np.testing.assert_allclose(upv.embed(a, (5,), (5, 9)), np.kron(a, np.eye(2)), atol=0)
+    np.testing.assert_allclose(upv.embed(a, (9,), (5, 9)), np.kron(np.eye(2), a), atol=0)
+    b = rng.standard_normal((4, 4))
+    swap = np.eye(4)[[0, 2, 1, 3]]
+    np.testing.assert_allclose(upv.embed(b, (9, 5), (5, 9)), swap @ b @ swap, atol=0)
+
+
+# ------------------------------------------------------------------------ UPV
+def _tiny_noisy(seed, n=4, gates=7, channels=None):
+    rng = np.random.default_rng(seed)
+    if channels is None:
+        channels = [W.depolarizing(0.2), W.amplitude_damping(0.3)]
+    return W.small_random_circuit(n, gates, rng, channels, site_prob=0.7)
+
+
+def _random_rows(c, rng, count):
+    qs = [upv.proposal(c.channels[ch]) for ch in c.site_channel]
+    return [np.array([rng.integers(0, len(q)) for q in qs], dtype=np.uint8) for _ in range(count)]
+
+
+def test_upv_merged_equals_explicit_insertion_statevector():
+    rng = np.random.default_rng(11)
+    for seed in range(4):
+        c = _tiny_noisy(seed, n=4, gates=9)
+        for row in _random_rows(c, rng, 5):
+            a = sv.trajectory_state(c, row)
+            b = sv.trajectory_state_explicit(c, row)
+            np.testing.assert_allclose(a, b, atol=1e-13)
+
+
+def test_upv_merged_network_equals_explicit_network():
+    """The paper's central UPV claim: merging the error operators into their gates
+    gives the same network value as inserting them as separate tensors."""
+    rng = np.random.default_rng(12)
+    c = _tiny_noisy(5, n=5, gates=10)
+    for row in _random_rows(c, rng, 3):
+        for (start, b, kind) in [(0, 2, "doubled"), (2, 2, "doubled"), (3, 2, "ket")]:
+            prefix = int(rng.integers(0, 2 ** start)) if start else 0
+            a = tn.batch_network_value(c, row, start, b, prefix, kind, explicit=False)
+            e = tn.batch_network_value(c, row, start, b, prefix, kind, explicit=True)
+            np.testing.assert_allclose(a, e, atol=1e-13)
+
+
+# ------------------------------------------- trajectory average == density matrix
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_exact_enumeration_equals_density_matrix(seed):
+    rng = np.random.default_rng(100 + seed)
+    chans = [W.depolarizing(0.15), W.amplitude_damping(0.25)]
+    c = W.small_random_circuit(3, 3, rng, chans, site_prob=1.0, two_qubit_frac=0.5)
+    # keep at most 6 sites so that enumeration stays tiny
+    keep = list(range(min(6, c.n_sites)))
+    c.site_gate = [c.site_gate[i] for i in keep]
+    c.site_qubits = [c.site_qubits[i] for i in keep]
+    c.site_channel = [c.site_channel[i] for i in keep]
+    rho = sv.density_matrix_diag(c)
+    acc = np.zeros(2 ** c.n_qubits)
+    for row, qk in sv.enumerate_trajectories(c):
+        acc += qk * np.abs(sv.trajectory_state(c, row)) ** 2
+    np.testing.assert_allclose(acc, rho, atol=1e-12)
+    assert abs(rho.sum() - 1) < 1e-12
+
+
+def test_pauli_trajectory_norm_is_one():
+    rng = np.random.default_rng(21)
+    c = W.random_brickwork(8, 4, rng, 0.3)          # unrounded FP64 gates
+    for row in _random_rows(c, rng, 10):
+        psi = sv.trajectory_state(c, row)
+        assert abs(np.vdot(psi, psi).real - 1) < 1e-12
+
+
+def test_monte_carlo_weighted_average_converges_to_density_matrix():
+    """PTS draws + self-normalised importance weights (non-unitary amplitude
+    damping) converge to the exact density-matrix diagonal within 5 sigma."""
+    rng = np.random.default_rng(31)
+    c = W.small_random_circuit(3, 4, rng, [W.depolarizing(0.2), W.amplitude_damping(0.4)], site_prob=1.0)
+    rho = sv.density_matrix_diag(c)
+    kr, mult, logq, nd = pts.presample(c, seed=77, n_unique=10 ** 6, max_draws=4000)
+    Z = np.empty(len(kr))
+    P = np.empty((len(kr), 2 ** c.n_qubits))
+    for i, row in enumerate(kr):
+        psi = sv.trajectory_state(c, row)
+        Z[i] = np.vdot(psi, psi).real
+        P[i] = np.abs(psi) ** 2 / Z[i]
+    Wt = sampling.trajectory_weights(Z, mult)
+    est = Wt @ P
+    # per-draw values of the ratio estimator and their spread
+    draws = np.repeat(np.arange(len(kr)), mult)
+    num = (Z[:, None] * P)[draws]
+    den = Z[draws]
+    resid = num - est[None, :] * den[:, None]
+    sigma = resid.std(axis=0) / den.mean() / math.sqrt(len(draws))
+    assert nd == 4000
+    assert np.all(np.abs(est - rho) <= 5 * sigma + 1e-12), (est, rho, sigma)
+
+
+# ------------------------------------------------------------ path independence
+def test_tn_orders_and_statevector_agree():
+    rng = np.random.default_rng(41)
+    c = W.random_brickwork(7, 4, rng, 0.2)
+    row = _random_rows(c, rng, 1)[0]
+    psi = sv.trajectory_state(c, row)
+    n = 7
+    for (start, b) in [(0, 3), (3, 2), (2, 5)]:
+        kind = "ket" if start + b == n else "doubled"
+        for prefix in range(min(2 ** start, 4)):
+            if kind == "ket":
+                want = sampling.amplitudes_from_state(psi, n, start, b, prefix)
+            else:
+                want = sampling.marginal_from_state(psi, n, start, b, prefix)
+            for order in ("ltr", "rtl", "inward"):
+                got = tn.batch_network_value(c, row, start, b, prefix, kind, order=order)
+                np.testing.assert_allclose(got, want, atol=1e-12)
+
+
+def test_chain_rule_of_marginals():
+    rng = np.random.default_rng(51)
+    c = W.random_brickwork(8, 5, rng, 0.1)
+    psi = sv.trajectory_state(c, _random_rows(c, rng, 1)[0])
+    n = 8
+    p1 = sampling.marginal_from_state(psi, n, 0, 3, 0)
+    assert abs(p1.sum() - 1) < 1e-12
+    for x in range(8):
+        p2 = sampling.marginal_from_state(psi, n, 3, 3, x)
+        assert abs(p2.sum() - p1[x]) < 1e-13
+
+
+# --------------------------------------------------------------------- sampling
+def test_inverse_cdf_brute_force():
+    pi = np.array([0.0, 0.25, 0.0, 0.5, 0.25, 0.0])
+    # boundaries of the strict rule C(x) > u Z
+    assert sampling.inverse_cdf(pi, 0.0) == 1
+    assert sampling.inverse_cdf(pi, 0.2499999) == 1
+    assert sampling.inverse_cdf(pi, 0.25) == 3
+    assert sampling.inverse_cdf(pi, 0.7499999) == 3
+    assert sampling.inverse_cdf(pi, 0.75) == 4
+    assert sampling.inverse_cdf(pi, 1 - 2 ** -53) == 4
+    # unnormalised input: the rule scales u by the total
+    assert sampling.inverse_cdf(4 * pi, 0.75) == 4
+    for u in np.linspace(0, 1 - 1e-12, 1001):
+        assert pi[sampling.inverse_cdf(pi, u)] > 0
+
+
+def test_shot_distribution_tvd_bound():
+    """Per-shot sampler vs the exact distribution: TVD <= 1/2 sqrt(K/M) + sqrt(ln(1/d)/(2M))."""
+    rng = np.random.default_rng(61)
+    c = W.random_brickwork(6, 4, rng, 0.0)
+    psi = sv.ideal_state(c)
+    n, bs = 6, [2, 2, 2]
+    starts = sampling.batch_starts(bs)
+
+    def mfn(j, prefix):
+        return sampling.marginal_from_state(psi, n, starts[j], bs[j], prefix)
+
+    M = 20000
+    shots, distinct = sampling.sample_trajectory(mfn, 0, n, bs, M, seed=5)
+    hist = np.bincount(np.array(shots), minlength=64) / M
+    tvd = 0.5 * np.abs(hist - np.abs(psi) ** 2).sum()
+    bound = 0.5 * math.sqrt(64 / M) + math.sqrt(math.log(1e9) / (2 * M))
+    assert tvd <= bound, (tvd, bound)
+    assert distinct[0] == 1 and distinct[1] <= 4 and distinct[2] <= 16
+
+
+def test_nbs_memo_matches_unmemoised_per_shot_sampling():
+    rng = np.random.default_rng(62)
+    c = W.random_brickwork(6, 3, rng, 0.0)
+    psi = sv.ideal_state(c)
+    n, bs = 6, [3, 3]
+    starts = sampling.batch_starts(bs)
+    calls = []
+
+    def mfn(j, prefix):
+        calls.append((j, prefix))
+        return sampling.marginal_from_state(psi, n, starts[j], bs[j], prefix)
+
+    shots, _ = sampling.sample_trajectory(mfn, 3, n, bs, 300, seed=9)
+    # redo every shot independently, without memoisation
+    for t in range(300):
+        prefix = 0
+        for j in range(2):
+            u = sampling.shot_uniforms(9, 3, j, 300)[t]
+            x = sampling.inverse_cdf(sampling.marginal_from_state(psi, n, starts[j], bs[j], prefix), u)
+            prefix |= x << starts[j]
+        assert prefix == shots[t]
+    assert len(calls) == len(set(calls))        # each (batch, prefix) contracted once
+
+
+# ------------------------------------------------------------------- Philox / PTS
+def test_philox_uniform_chi_square_and_streams():
+    t = np.arange(200000, dtype=np.uint64)
+    u = philox.uniform(123, philox.TAG_SHOTS, t, 0, 0)
+    assert u.min() >= 0 and u.max() < 1
+    h = np.bincount((u * 100).astype(int), minlength=100)
+    chi2 = ((h - 2000) ** 2 / 2000).sum()
+    assert chi2 < 180        # 99 dof, p ~ 1e-6
+    v = philox.uniform(123, philox.TAG_PTS, t, 0, 0)
+    assert np.mean(u == v) < 1e-4
+    w = philox.uniform(124, philox.TAG_SHOTS, t, 0, 0)
+    assert np.mean(u == w) < 1e-4
+    # counter words are not interchangeable
+    x = philox.uniform(123, philox.TAG_SHOTS, 0, t, 0)
+    assert np.mean(u == x) < 1e-4
+
+
+def test_pts_properties():
+    c = W.config1().circuit
+    kr, mult, logq, nd = pts.presample(c, seed=1002, n_unique=64)
+    assert kr.shape == (64, 72)
+    assert len({r.tobytes() for r in kr}) == 64
+    assert mult.sum() == nd and np.all(mult >= 1)
+    q = upv.proposal(c.channels[0])
+    for r, lq in zip(kr, logq):
+        assert abs(lq - np.log(q[r]).sum()) < 1e-9
+    # the error-free set is the most likely one (P ~ 0.485): present, largest multiplicity
+    free = [i for i, r in enumerate(kr) if not r.any()]
+    assert len(free) == 1 and mult[free[0]] == mult.max()
+    assert abs(mult[free[0]] / nd - 0.99 ** 72) < 5 * math.sqrt(0.25 / nd)
+
+
+def test_pts_site_frequencies():
+    c = W.Circuit(1)
+    g = c.add_gate((0,), np.eye(2))
+    ch = c.add_channel(W.depolarizing(0.3))
+    for _ in range(3):
+        c.add_site(g, (0,), ch)
+    kr, mult, _, nd = pts.presample(c, seed=5, n_unique=1000, max_draws=20000)
+    assert nd == 20000 and mult.sum() == 20000
+    counts = np.zeros(4)
+    for r, m in zip(kr, mult):
+        counts[r[0]] += m
+    p = np.array([0.7, 0.1, 0.1, 0.1])
+    sd = np.sqrt(20000 * p * (1 - p))
+    assert np.all(np.abs(counts - 20000 * p) < 5 * sd)

@@ -1,0 +1,336 @@
+"""Seeded synthetic inputs for PTSBE: circuits, noise channels and workloads.
+
+This module only *generates inputs*.  It holds none of the method's arithmetic
+(no contraction, no trajectory sampling, no marginals, no shot sampling), so both
+the FP64 oracle (``oracle/``) and the GPU library's tests and benchmark may draw
+their circuits from it.
+
+Conventions (shared by every consumer):
+
+* A circuit is a list of gates applied in order to ``n_qubits`` qubits that all
+  start in |0>.  A one-qubit gate is a 2x2 matrix, a two-qubit gate on
+  ``(q0, q1)`` a 4x4 matrix whose row/column index is ``2*x[q0] + x[q1]``
+  (first listed qubit = high bit); rows are outputs, columns inputs.
+* A noise *site* attaches a channel to a gate (noise acts right after the gate,
+  the reading of "errors are preceded or succeeded by a gate of the same size and
+  location", Sec. III-A).  A gate's sites act in list order.
+* A channel is a list of Kraus operators (2x2 or 4x4) plus, optionally, the
+  probability with which trajectory pre-sampling picks each one; when omitted the
+  proposal is ``tr(K^dag K)/d``.
+
+The workload recipes follow the paper's random-circuit family (Sec. IV-B) at the
+sizes of the five benchmark configurations documented in the design doc.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+
+__all__ = [
+    "Channel", "Circuit", "Workload", "haar_su4", "depolarizing", "amplitude_damping",
+    "pauli_x", "pauli_y", "pauli_z", "brickwork_1d", "config1", "config2", "config3",
+    "config5", "random_brickwork", "small_random_circuit", "grid_layers",
+]
+
+I2 = np.eye(2, dtype=np.complex128)
+pauli_x = np.array([[0, 1], [1, 0]], dtype=np.complex128)
+pauli_y = np.array([[0, -1j], [1j, 0]], dtype=np.complex128)
+pauli_z = np.array([[1, 0], [0, -1]], dtype=np.complex128)
+
+
+@dataclass
+class Channel:
+    """A CPTP map given by Kraus operators ``kraus[k]`` (d x d, d = 2 or 4)."""
+    kraus: np.ndarray                      # (K, d, d) complex128
+    probs: Optional[np.ndarray] = None     # (K,) float64 or None
+
+    @property
+    def arity(self) -> int:
+        return 1 if self.kraus.shape[1] == 2 else 2
+
+
+@dataclass
+class Circuit:
+    n_qubits: int
+    gate_qubits: List[Tuple[int, ...]] = field(default_factory=list)
+    gate_mats: List[np.ndarray] = field(default_factory=list)
+    channels: List[Channel] = field(default_factory=list)
+    site_gate: List[int] = field(default_factory=list)
+    site_qubits: List[Tuple[int, ...]] = field(default_factory=list)
+    site_channel: List[int] = field(default_factory=list)
+    # optional: per-gate parameter description for differentiable circuits
+    gate_param: List[Optional[Tuple[str, int]]] = field(default_factory=list)
+
+    @property
+    def n_gates(self) -> int:
+        return len(self.gate_qubits)
+
+    @property
+    def n_sites(self) -> int:
+        return len(self.site_gate)
+
+    def add_gate(self, qubits: Sequence[int], mat: np.ndarray, param=None) -> int:
+        qubits = tuple(int(q) for q in qubits)
+        assert mat.shape == (2 ** len(qubits),) * 2
+        self.gate_qubits.append(qubits)
+        self.gate_mats.append(np.asarray(mat, dtype=np.complex128))
+        self.gate_param.append(param)
+        return len(self.gate_qubits) - 1
+
+    def add_channel(self, ch: Channel) -> int:
+        self.channels.append(ch)
+        return len(self.channels) - 1
+
+    def add_site(self, gate: int, qubits: Sequence[int], channel: int) -> None:
+        self.site_gate.append(int(gate))
+        self.site_qubits.append(tuple(int(q) for q in qubits))
+        self.site_channel.append(int(channel))
+
+    def round_to_complex64(self) -> "Circuit":
+        """Round every gate matrix to complex64 (values kept as complex128)."""
+        self.gate_mats = [m.astype(np.complex64).astype(np.complex128) for m in self.gate_mats]
+        return self
+
+
+@dataclass
+class Workload:
+    name: str
+    circuit: Circuit
+    n_traj: int                    # unique (non-degenerate) error sets E
+    shots_per_traj: int            # m_i (same for every trajectory)
+    batch_sizes: List[int]         # b_j, contiguous ascending qubit batches
+    pts_seed: int
+    shot_seed: int
+    max_draws: int = 1 << 40
+
+
+# --------------------------------------------------------------------------- gates
+def haar_su4(rng: np.random.Generator) -> np.ndarray:
+    """Haar-random SU(4): QR of a complex Ginibre matrix with R's diagonal phases
+    moved into Q (Mezzadri 2007), divided by the principal 4th root of det."""
+    z = (rng.standard_normal((4, 4)) + 1j * rng.standard_normal((4, 4))) / np.sqrt(2.0)
+    q, r = np.linalg.qr(z)
+    d = np.diag(r)
+    q = q * (d / np.abs(d))[None, :]
+    det = np.linalg.det(q)
+    return q / det ** 0.25
+
+
+def _rot(pauli: np.ndarray, angle: float) -> np.ndarray:
+    """exp(-i angle/2 P) for a Pauli-like P with P^2 = I."""
+    return np.cos(angle / 2) * I2 - 1j * np.sin(angle / 2) * pauli
+
+
+SQRT_X = _rot(pauli_x, np.pi / 2)
+SQRT_Y = _rot(pauli_y, np.pi / 2)
+SQRT_W = _rot((pauli_x + pauli_y) / np.sqrt(2.0), np.pi / 2)
+CZ = np.diag([1, 1, 1, -1]).astype(np.complex128)
+CNOT = np.array([[1, 0, 0, 0], [0, 1, 0, 0], [0, 0, 0, 1], [0, 0, 1, 0]], dtype=np.complex128)
+HADAMARD = np.array([[1, 1], [1, -1]], dtype=np.complex128) / np.sqrt(2.0)
+
+
+def ry(theta: float) -> np.ndarray:
+    return _rot(pauli_y, theta)
+
+
+def rz(phi: float) -> np.ndarray:
+    return _rot(pauli_z, phi)
+
+
+# ------------------------------------------------------------------------ channels
+def depolarizing(p: float) -> Channel:
+    """Single-qubit depolarising channel, Kraus {sqrt(1-p) I, sqrt(p/3) X, Y, Z}."""
+    k = np.stack([np.sqrt(1 - p) * I2, np.sqrt(p / 3) * pauli_x,
+                  np.sqrt(p / 3) * pauli_y, np.sqrt(p / 3) * pauli_z])
+    return Channel(k, np.array([1 - p, p / 3, p / 3, p / 3]))
+
+
+def depolarizing2(p: float) -> Channel:
+    """Two-qubit depolarising channel: identity with prob 1-p, else one of the 15
+    non-identity two-qubit Paulis with prob p/15."""
+    paulis = [I2, pauli_x, pauli_y, pauli_z]
+    ks, ps = [], []
+    for a in range(4):
+        for b in range(4):
+            pr = (1 - p) if (a == 0 and b == 0) else p / 15
+            ks.append(np.sqrt(pr) * np.kron(paulis[a], paulis[b]))
+            ps.append(pr)
+    return Channel(np.stack(ks), np.array(ps))
+
+
+def pauli_channel(which: np.ndarray, p: float) -> Channel:
+    """Single Pauli error channel {sqrt(1-p) I, sqrt(p) P}."""
+    return Channel(np.stack([np.sqrt(1 - p) * I2, np.sqrt(p) * which]), np.array([1 - p, p]))
+
+
+def amplitude_damping(gamma: float) -> Channel:
+    """Amplitude damping, K0 = [[1,0],[0,sqrt(1-g)]], K1 = [[0,sqrt(g)],[0,0]].
+    Non-unitary: no probabilities given, the proposal is tr(K^dag K)/2."""
+    k0 = np.array([[1, 0], [0, np.sqrt(1 - gamma)]], dtype=np.complex128)
+    k1 = np.array([[0, np.sqrt(gamma)], [0, 0]], dtype=np.complex128)
+    return Channel(np.stack([k0, k1]), None)
+
+
+# ------------------------------------------------------------------------ layouts
+def brickwork_1d(n: int, depth: int) -> List[List[Tuple[int, int]]]:
+    """Layers of nearest-neighbour pairs on an open chain; even layers first."""
+    layers = []
+    for d in range(depth):
+        start = d % 2
+        layers.append([(q, q + 1) for q in range(start, n - 1, 2)])
+    return layers
+
+
+def grid_layers(rows: int, cols: int, n: int) -> List[List[Tuple[int, int]]]:
+    """The four nearest-neighbour pair patterns on a row-major grid (q = cols*r + c,
+    only q < n exist): horizontal-even, vertical-even, horizontal-odd, vertical-odd."""
+    def ok(q):
+        return q < n
+    pats = []
+    for kind, par in (("h", 0), ("v", 0), ("h", 1), ("v", 1)):
+        pairs = []
+        for r in range(rows):
+            for c in range(cols):
+                if kind == "h" and c % 2 == par and c + 1 < cols:
+                    a, b = cols * r + c, cols * r + c + 1
+                elif kind == "v" and r % 2 == par and r + 1 < rows:
+                    a, b = cols * r + c, cols * (r + 1) + c
+                else:
+                    continue
+                if ok(a) and ok(b):
+                    pairs.append((a, b))
+        pats.append(pairs)
+    return pats
+
+
+def _noisy_pair_circuit(n: int, layers, rng, noise: Sequence[Channel], two_qubit_gate=None) -> Circuit:
+    c = Circuit(n)
+    ch_ids = [c.add_channel(ch) for ch in noise]
+    for layer in layers:
+        for (a, b) in layer:
+            m = haar_su4(rng) if two_qubit_gate is None else two_qubit_gate
+            g = c.add_gate((a, b), m)
+            for q in (a, b):
+                for cid in ch_ids:
+                    c.add_site(g, (q,), cid)
+    return c
+
+
+def random_brickwork(n: int, depth: int, rng: np.random.Generator, p: float,
+                     layout: str = "1d") -> Circuit:
+    """Haar SU(4) brickwork (1D chain or 2D grid) with single-qubit depolarising
+    noise of strength p on both qubits after every gate."""
+    if layout == "1d":
+        layers = brickwork_1d(n, depth)
+    else:
+        rows = int(np.floor(np.sqrt(n)))
+        cols = int(np.ceil(n / rows))
+        pats = grid_layers(rows, cols, n)
+        layers = [pats[d % 4] for d in range(depth)]
+    return _noisy_pair_circuit(n, layers, rng, [depolarizing(p)])
+
+
+def small_random_circuit(n: int, n_gates: int, rng: np.random.Generator,
+                         channels: Sequence[Channel], site_prob: float = 1.0,
+                         two_qubit_frac: float = 0.5) -> Circuit:
+    """Random small circuit for tests: random 1q (Haar U(2)) and nearest-neighbour
+    2q (Haar SU(4)) gates; each listed channel is attached (with probability
+    site_prob) to every qubit the gate touches; 2q channels attach to 2q gates."""
+    c = Circuit(n)
+    ids = [c.add_channel(ch) for ch in channels]
+    for _ in range(n_gates):
+        if n > 1 and rng.random() < two_qubit_frac:
+            a = int(rng.integers(0, n - 1))
+            qs = (a, a + 1) if rng.random() < 0.5 else (a + 1, a)
+            m = haar_su4(rng)
+        else:
+            qs = (int(rng.integers(0, n)),)
+            m = haar_su4(rng)[:2, :2]
+            u, _, vh = np.linalg.svd(m)
+            m = u @ vh
+        g = c.add_gate(qs, m)
+        for cid, ch in zip(ids, channels):
+            if rng.random() >= site_prob:
+                continue
+            if ch.arity == 2:
+                if len(qs) == 2:
+                    c.add_site(g, qs, cid)
+            else:
+                for q in qs:
+                    c.add_site(g, (q,), cid)
+    return c
+
+
+# ----------------------------------------------------------------------- configs
+def config1() -> Workload:
+    """10-qubit open chain, 8 brickwork layers of Haar SU(4) (complex64-rounded),
+    depolarising p=0.01 on both qubits after each gate, 64 unique trajectories x
+    100 shots, one batch of 10 qubits."""
+    rng = np.random.default_rng(1001)
+    c = random_brickwork(10, 8, rng, 0.01).round_to_complex64()
+    return Workload("config1_n10_d8", c, 64, 100, [10], pts_seed=1002, shot_seed=1003)
+
+
+def config2() -> Workload:
+    """50-qubit open chain, 6 brickwork layers of Haar SU(4) (complex64-rounded),
+    depolarising p=0.005 per qubit after each gate, 4096 unique trajectories x
+    1000 shots, batches of 10 qubits."""
+    rng = np.random.default_rng(2001)
+    c = random_brickwork(50, 6, rng, 0.005).round_to_complex64()
+    return Workload("config2_n50_d6", c, 4096, 1000, [10] * 5, pts_seed=2002, shot_seed=2003)
+
+
+def config3(batch_sizes=(25,)) -> Workload:
+    """5x5 grid (q = 5r + c), 8 cycles of random sqrt(X)/sqrt(Y)/sqrt(W) on every
+    qubit then a CZ layer (patterns H-even, V-even, H-odd, V-odd); depolarising
+    p=0.01 then amplitude damping gamma=0.02 after every gate on each qubit it
+    touches; 16384 unique trajectories x 256 shots."""
+    rng = np.random.default_rng(3001)
+    c = Circuit(25)
+    dep = c.add_channel(depolarizing(0.01))
+    ad = c.add_channel(amplitude_damping(0.02))
+    pats = grid_layers(5, 5, 25)
+    choices = [SQRT_X, SQRT_Y, SQRT_W]
+    for cyc in range(8):
+        for q in range(25):
+            g = c.add_gate((q,), choices[int(rng.integers(0, 3))])
+            c.add_site(g, (q,), dep)
+            c.add_site(g, (q,), ad)
+        for (a, b) in pats[cyc % 4]:
+            g = c.add_gate((a, b), CZ)
+            for q in (a, b):
+                c.add_site(g, (q,), dep)
+                c.add_site(g, (q,), ad)
+    return Workload("config3_grid5x5_d8", c, 16384, 256, list(batch_sizes), pts_seed=3002, shot_seed=3003)
+
+
+def config5_angles() -> np.ndarray:
+    rng = np.random.default_rng(5005)
+    return rng.uniform(0.0, 2 * np.pi, size=400).astype(np.float32)
+
+
+def config5(angles: Optional[np.ndarray] = None) -> Workload:
+    """20-qubit hardware-efficient ansatz: 10 layers of RY on all, RZ on all, CNOT
+    ladder 0->1 ... 18->19; depolarising p=0.01 after each gate on each touched
+    qubit; 1024 trajectories.  Angle k of layer L: RY uses 40L + q, RZ 40L + 20 + q."""
+    if angles is None:
+        angles = config5_angles()
+    angles = np.asarray(angles, dtype=np.float64)
+    c = Circuit(20)
+    dep = c.add_channel(depolarizing(0.01))
+    for L in range(10):
+        for q in range(20):
+            k = 40 * L + q
+            g = c.add_gate((q,), ry(angles[k]), param=("ry", k))
+            c.add_site(g, (q,), dep)
+        for q in range(20):
+            k = 40 * L + 20 + q
+            g = c.add_gate((q,), rz(angles[k]), param=("rz", k))
+            c.add_site(g, (q,), dep)
+        for q in range(19):
+            g = c.add_gate((q, q + 1), CNOT)
+            c.add_site(g, (q,), dep)
+            c.add_site(g, (q + 1,), dep)
+    return Workload("config5_hea_n20", c, 1024, 0, [20], pts_seed=5002, shot_seed=5003)
