@@ -1,0 +1,215 @@
+/*
+ * ptsbe.h - C ABI of the MI355X-native PTSBE hot path.
+ *
+ * Pre-trajectory sampling with batched execution (PTSBE) for noisy tensor-network
+ * simulation, following "Accelerating Quantum Tensor Network Simulations with
+ * Unified Path Variations and Non-Degenerate Batched Sampling":
+ *
+ *   ptsbe_plan                 one unified, error-independent contraction path per
+ *                              qubit batch (Sec. III-A, unified path variations);
+ *                              host only, outside the timed hot path (Sec. IV-D).
+ *   ptsbe_sample_trajectories  pre-trajectory sampling of unique error sets with
+ *                              multiplicities (Sec. II-C); host only.
+ *   ptsbe_contract_batch       error injection (the UPV merge of each sampled
+ *                              Kraus operator into its gate) and the batch-wise
+ *                              contraction of one batch's marginals for a list of
+ *                              (trajectory, prefix) elements (Sec. II-B, III-A).
+ *   ptsbe_sample_shots         the whole non-degenerate batched sampling loop
+ *                              (Sec. III-B, proportional mode): contract once per
+ *                              unique prefix, FP64 cumulative sums, inverse-CDF
+ *                              draws, prefix deduplication, trajectory weights.
+ *
+ * Conventions
+ *   - Qubit q of a shot is bit (q % 64) of word (q / 64); 0 <-> |0>.
+ *   - Gate matrices are row-major, rows = outputs, interleaved complex128
+ *     (re, im).  A two-qubit gate on (q0, q1) is indexed 2*x[q0] + x[q1].
+ *   - Noise sites act right after their gate, in site order (the paper's "errors
+ *     are preceded or succeeded by a gate of the same size and location").
+ *   - Batches are contiguous ascending qubit ranges; batch j starts at
+ *     b_0 + ... + b_{j-1}.  Batch indices are 0-based.
+ *   - The marginal of batch j for element e = (trajectory i, prefix s_<j) is the
+ *     unnormalised pi_e(x) = sum_y |psi~_i(s_<j, x, y)|^2 over batch values x
+ *     (x = sum_k x_{start+k} 2^k) and later-qubit values y; psi~_i is built with
+ *     the inserted operators K_k / sqrt(q_k) (q_k: the proposal of Kraus k).
+ *   - Shot draws: u = Philox4x32-10(key = (lo32(seed), hi32(seed) ^ 2*0x9E3779B9),
+ *     counter = (trajectory, batch, shot index within trajectory, 0)), top 53
+ *     bits; x = min{x : C(x) > u * C(last)} with C the FP64 inclusive prefix sum
+ *     of pi_e in index order (the largest x with pi_e(x) > 0 if none).
+ *
+ * Memory ownership
+ *   - Host arrays passed in are copied before the call returns.
+ *   - Every d_* pointer is caller-owned device memory on the plan's device.
+ *     The library never allocates on the hot path: scratch comes from the
+ *     caller's workspace (d_workspace, workspace_bytes).  The plan owns small
+ *     constant tables (gate tensors, step tables) allocated in ptsbe_plan and
+ *     freed by ptsbe_plan_destroy.
+ *   - Device calls are asynchronous on the given stream except where noted: the
+ *     sampling loop reads data-dependent element counts back to the host once
+ *     per batch and so synchronises the stream.
+ *
+ * Errors
+ *   Every call returns a status; ptsbe_last_error() gives a thread-local message
+ *   for the last non-OK status.  Argument errors, unsupported shapes and
+ *   workspace shortfalls are detected before any launch.
+ */
+#ifndef PTSBE_H
+#define PTSBE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PTSBE_OK = 0,
+  PTSBE_ERR_INVALID_ARG = 1,   /* malformed circuit / options / pointers        */
+  PTSBE_ERR_UNSUPPORTED = 2,   /* gate arity > 2, batch size > 30, path shape   */
+  PTSBE_ERR_OUT_OF_MEMORY = 3, /* workspace or plan budget too small            */
+  PTSBE_ERR_DEVICE = 4,        /* HIP runtime error                             */
+  PTSBE_ERR_NUMERIC = 5        /* zero-norm element or non-finite marginal      */
+} ptsbe_status_t;
+
+enum { PTSBE_C64 = 0, PTSBE_SPLIT_BF16 = 1, PTSBE_SPLIT_F16 = 2 };
+enum { PTSBE_OUT_POPULATION = 0, PTSBE_OUT_AMPLITUDE = 1 };
+enum { PTSBE_MODE_PROPORTIONAL = 0 };
+
+typedef struct ptsbe_plan_s* ptsbe_plan_t;
+
+/* A circuit D with its noise model (Sec. II-B: coherent gates d_l, noise sites p).
+ * gate_mats packs gate g's d x d matrix (d = 2^arity) as 2*d*d doubles, gates in
+ * order.  ch_kraus packs channel c's Kraus operators (d x d each, d = 2^ch_arity)
+ * the same way, channels in order.  ch_prob (may be NULL) gives the pre-sampling
+ * probability of every Kraus operator in the same packed order; a negative entry,
+ * or NULL, means q_k = tr(K_k^dag K_k) / d.  Site s attaches channel
+ * site_channel[s] to gate site_gate[s] on qubits site_qubits[2s], [2s+1] (-1 if
+ * unused); site qubits must be qubits of that gate. */
+typedef struct {
+  int32_t n_qubits;
+  int32_t n_gates;
+  const int32_t* gate_arity;    /* [n_gates] 1 or 2                              */
+  const int32_t* gate_qubits;   /* [n_gates][2], second entry -1 for 1q gates    */
+  const double* gate_mats;      /* packed interleaved complex128                 */
+  int32_t n_channels;
+  const int32_t* ch_arity;      /* [n_channels] 1 or 2                           */
+  const int32_t* ch_nkraus;     /* [n_channels] >= 1, <= 256                     */
+  const double* ch_kraus;       /* packed interleaved complex128                 */
+  const double* ch_prob;        /* packed per Kraus operator, or NULL            */
+  int32_t n_sites;
+  const int32_t* site_gate;     /* [n_sites]                                     */
+  const int32_t* site_qubits;   /* [n_sites][2]                                  */
+  const int32_t* site_channel;  /* [n_sites]                                     */
+} ptsbe_circuit_t;
+
+/* Plan options (Sec. II-B / V-B: flexible per-batch sizes b_j; Sec. IV-C:
+ * hypersamples of the path search). */
+typedef struct {
+  int32_t n_batches;
+  const int32_t* batch_sizes;   /* [n_batches], each 1..30, sum == n_qubits     */
+  int32_t hypersamples;         /* randomised path-search restarts (>= 1)        */
+  uint64_t path_seed;
+  int32_t precision;            /* PTSBE_C64 (only value accepted so far)        */
+  int32_t device;               /* HIP device ordinal; -1: host-only plan (path,
+                                   query and pre-sampling only, no device calls) */
+  size_t device_budget_bytes;   /* 0: no limit; else plan constants must fit     */
+} ptsbe_plan_opts_t;
+
+typedef struct {
+  int32_t n_qubits, n_gates, n_sites, n_batches, n_words;  /* n_words = ceil(n/64) */
+  int32_t max_kraus;            /* largest channel size                          */
+  int64_t plan_device_bytes;    /* constants held by the plan                    */
+} ptsbe_plan_info_t;
+
+/* Per-batch description of the unified path P^j (host-side cost model). */
+typedef struct {
+  int32_t start, size;          /* batch qubits [start, start+size)              */
+  int32_t doubled;              /* 1: ket x bra network (j < f-1), 0: ket only   */
+  int32_t n_left_steps;         /* per-element steps (prefix-projected part)     */
+  int32_t n_right_steps;        /* per-trajectory steps                          */
+  int32_t left_rank, right_rank;/* ranks of the two partial results              */
+  int32_t left_peak_rank, right_peak_rank;
+  int32_t join_rows_log2;       /* open batch legs carried by the left part      */
+  int32_t crossing;             /* wires joining the left and right parts        */
+  double flops_per_traj;        /* algorithmic real flops, per-trajectory part   */
+  double flops_per_elem;        /* per element: left sweep + join                */
+  double join_flops_per_elem;   /* join only                                     */
+  double bytes_per_traj;        /* algorithmic HBM bytes of the per-traj part    */
+} ptsbe_batch_info_t;
+
+ptsbe_status_t ptsbe_plan(const ptsbe_circuit_t* circuit, const ptsbe_plan_opts_t* opts,
+                          ptsbe_plan_t* out);
+ptsbe_status_t ptsbe_plan_query(ptsbe_plan_t plan, ptsbe_plan_info_t* out);
+ptsbe_status_t ptsbe_plan_batch_info(ptsbe_plan_t plan, int32_t j, ptsbe_batch_info_t* out);
+void ptsbe_plan_destroy(ptsbe_plan_t plan);
+const char* ptsbe_last_error(void);
+
+/* Pre-trajectory sampling (host).  Draw d, site p uses Philox counter
+ * (lo32(d), p, hi32(d), 0)
+ * with tag 1; the Kraus index is the first k whose FP64 inclusive cumulative
+ * proposal exceeds u.  Draws continue until n_unique distinct error sets exist,
+ * every error set of non-zero probability has appeared, or max_draws draws were
+ * made.  Outputs (host, caller-owned):
+ *   kraus_idx [n_unique][n_sites] uint8, distinct sets in order of first draw
+ *   mult      [n_unique] draws that produced each set
+ *   log_q     [n_unique] sum of log proposals of the set
+ *   n_unique_out, n_draws_out (either may be NULL). */
+ptsbe_status_t ptsbe_sample_trajectories(ptsbe_plan_t plan, uint64_t seed, int64_t n_unique,
+                                         int64_t max_draws, uint8_t* kraus_idx, int64_t* mult,
+                                         double* log_q, int64_t* n_unique_out,
+                                         int64_t* n_draws_out);
+
+/* Workspace needed by ptsbe_contract_batch / ptsbe_sample_shots for E
+ * trajectories, n_elems elements (contract) and total_shots shots (sample). */
+ptsbe_status_t ptsbe_contract_workspace_size(ptsbe_plan_t plan, int32_t j, int64_t E,
+                                             int64_t n_elems, size_t* bytes);
+ptsbe_status_t ptsbe_sample_workspace_size(ptsbe_plan_t plan, int64_t E, int64_t total_shots,
+                                           size_t* bytes);
+
+/* Batch-wise contraction of batch j (Sec. II-B) for n_elems elements.
+ *   d_kraus_idx   [E][n_sites] uint8 error sets (device)
+ *   d_elem_traj   [n_elems] int32 trajectory of each element, non-decreasing
+ *   d_elem_prefix [n_elems][n_words] uint64 prefix bits (qubits < start; others 0)
+ *   out_kind      PTSBE_OUT_POPULATION: d_out is float [n_elems][2^b_j] pi_e(x)
+ *                 PTSBE_OUT_AMPLITUDE (last batch only): d_out is float2
+ *                 [n_elems][2^b_j] amplitudes
+ *   d_elem_total  [n_elems] double, FP64 sum of pi_e (may be NULL)
+ * Asynchronous on `stream` (a hipStream_t). */
+ptsbe_status_t ptsbe_contract_batch(ptsbe_plan_t plan, int32_t j, const uint8_t* d_kraus_idx,
+                                    int64_t E, const int32_t* d_elem_traj,
+                                    const uint64_t* d_elem_prefix, int64_t n_elems,
+                                    int32_t out_kind, void* d_out, double* d_elem_total,
+                                    void* d_workspace, size_t workspace_bytes, void* stream);
+
+/* Non-degenerate batched sampling, proportional mode (Sec. III-B).
+ *   d_kraus_idx       [E][n_sites] uint8
+ *   d_mult            [E] int64 multiplicities (NULL: all 1)
+ *   d_shots_per_traj  [E] int64 m_i
+ *   seed              shot seed (Philox tag 2)
+ *   d_shots           [M][n_words] uint64, M = sum m_i; trajectory i's shots occupy
+ *                     rows [sum_{k<i} m_k, ... + m_i) in shot-index order
+ *   d_shot_traj       [M] int32 (may be NULL)
+ *   d_traj_weight     [E] double W_i = mult_i Z_i / sum_k mult_k Z_k, Z_i the
+ *                     trajectory's squared norm (may be NULL)
+ *   d_traj_norm       [E] double Z_i (may be NULL)
+ *   stats_out         host int64 [n_batches]: distinct elements contracted per
+ *                     batch (may be NULL)
+ * Synchronises `stream` once per batch. */
+ptsbe_status_t ptsbe_sample_shots(ptsbe_plan_t plan, const uint8_t* d_kraus_idx, int64_t E,
+                                  const int64_t* d_mult, const int64_t* d_shots_per_traj,
+                                  int32_t mode, uint64_t seed, uint64_t* d_shots,
+                                  int32_t* d_shot_traj, double* d_traj_weight,
+                                  double* d_traj_norm, int64_t* stats_out, void* d_workspace,
+                                  size_t workspace_bytes, void* stream);
+
+/* Timing hook for measurement: when enabled, the library records HIP events
+ * around every launch of the batch join kernel and accumulates its total time
+ * (milliseconds), launch count and algorithmic flops. */
+ptsbe_status_t ptsbe_profile_enable(ptsbe_plan_t plan, int32_t on);
+ptsbe_status_t ptsbe_profile_read(ptsbe_plan_t plan, double* join_ms, int64_t* join_launches,
+                                  double* join_flops, double* sweep_ms, double* sweep_bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PTSBE_H */

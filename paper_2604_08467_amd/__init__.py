@@ -1,0 +1,197 @@
+"""MI355X-native PTSBE hot path: Python binding of the C ABI in include/ptsbe.h.
+
+Every step of the path runs in the HIP library ``libptsbe.so``; this module only
+marshals arguments.  PyTorch provides device memory and the stream.
+
+    plan = Plan(circuit, batch_sizes=[10] * 5)
+    kraus, mult, log_q, n_draws = plan.sample_trajectories(seed, n_unique)
+    out = plan.sample_shots(kraus_dev, shots_per_traj_dev, seed=...)
+"""
+import ctypes as C
+
+import numpy as np
+
+from . import _lib
+from ._lib import PtsbeError
+
+__all__ = ["Plan", "PtsbeError", "load_library", "OUT_POPULATION", "OUT_AMPLITUDE"]
+
+OUT_POPULATION = 0
+OUT_AMPLITUDE = 1
+
+
+def load_library():
+    return _lib.load()
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(C.POINTER(ctype))
+
+
+def _tptr(t):
+    return C.c_void_p(0 if t is None else t.data_ptr())
+
+
+class _CircuitArrays:
+    """Packs a circuit (workloads.Circuit-like object) into ptsbe_circuit_t."""
+
+    def __init__(self, c):
+        G = len(c.gate_qubits)
+        self.gate_arity = np.array([len(q) for q in c.gate_qubits], dtype=np.int32)
+        gq = np.full((max(G, 1), 2), -1, dtype=np.int32)
+        for g, qs in enumerate(c.gate_qubits):
+            gq[g, :len(qs)] = qs
+        self.gate_qubits = gq
+        self.gate_mats = np.concatenate(
+            [np.asarray(m, dtype=np.complex128).reshape(-1).view(np.float64) for m in c.gate_mats]
+            or [np.zeros(2)])
+        ch = c.channels
+        self.ch_arity = np.array([1 if k.kraus.shape[1] == 2 else 2 for k in ch] or [0], dtype=np.int32)
+        self.ch_nkraus = np.array([k.kraus.shape[0] for k in ch] or [0], dtype=np.int32)
+        self.ch_kraus = np.concatenate(
+            [np.asarray(k.kraus, dtype=np.complex128).reshape(-1).view(np.float64) for k in ch] or [np.zeros(2)])
+        probs = []
+        for k in ch:
+            if k.probs is None:
+                probs.append(-np.ones(k.kraus.shape[0]))
+            else:
+                probs.append(np.asarray(k.probs, dtype=np.float64))
+        self.ch_prob = np.concatenate(probs or [np.zeros(1)])
+        S = len(c.site_gate)
+        self.site_gate = np.array(c.site_gate or [0], dtype=np.int32)
+        sq = np.full((max(S, 1), 2), -1, dtype=np.int32)
+        for s, qs in enumerate(c.site_qubits):
+            sq[s, :len(qs)] = qs
+        self.site_qubits = sq
+        self.site_channel = np.array(c.site_channel or [0], dtype=np.int32)
+        self.struct = _lib.Circuit_t(
+            c.n_qubits, G, _ptr(self.gate_arity, C.c_int32), _ptr(self.gate_qubits, C.c_int32),
+            _ptr(self.gate_mats, C.c_double), len(ch), _ptr(self.ch_arity, C.c_int32),
+            _ptr(self.ch_nkraus, C.c_int32), _ptr(self.ch_kraus, C.c_double), _ptr(self.ch_prob, C.c_double),
+            S, _ptr(self.site_gate, C.c_int32), _ptr(self.site_qubits, C.c_int32),
+            _ptr(self.site_channel, C.c_int32))
+
+
+class Plan:
+    """ptsbe_plan: the unified contraction path of every batch (host, once)."""
+
+    def __init__(self, circuit, batch_sizes, hypersamples=4, path_seed=0, device=0, precision=0,
+                 device_budget_bytes=0):
+        self._lib = _lib.load()
+        self.n_qubits = circuit.n_qubits
+        self.n_sites = len(circuit.site_gate)
+        self.batch_sizes = list(batch_sizes)
+        arrs = _CircuitArrays(circuit)
+        bs = np.array(self.batch_sizes, dtype=np.int32)
+        opts = _lib.PlanOpts_t(len(bs), _ptr(bs, C.c_int32), int(hypersamples), int(path_seed), int(precision),
+                               int(device), int(device_budget_bytes))
+        h = C.c_void_p()
+        _lib.check(self._lib.ptsbe_plan(C.byref(arrs.struct), C.byref(opts), C.byref(h)))
+        self._h = h
+        self.device = device
+        info = _lib.PlanInfo_t()
+        _lib.check(self._lib.ptsbe_plan_query(self._h, C.byref(info)))
+        self.n_words = info.n_words
+        self.n_gates = info.n_gates
+        self.plan_device_bytes = info.plan_device_bytes
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.ptsbe_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def batch_info(self, j):
+        bi = _lib.BatchInfo_t()
+        _lib.check(self._lib.ptsbe_plan_batch_info(self._h, int(j), C.byref(bi)))
+        return {f: getattr(bi, f) for f, _ in bi._fields_}
+
+    # ----------------------------------------------------------------- host PTS
+    def sample_trajectories(self, seed, n_unique, max_draws=1 << 40):
+        S = self.n_sites
+        kr = np.zeros((n_unique, max(S, 1)), dtype=np.uint8)
+        mult = np.zeros(n_unique, dtype=np.int64)
+        lq = np.zeros(n_unique, dtype=np.float64)
+        nu, nd = C.c_int64(), C.c_int64()
+        _lib.check(self._lib.ptsbe_sample_trajectories(
+            self._h, int(seed), int(n_unique), int(max_draws), kr.ctypes.data_as(C.c_void_p),
+            mult.ctypes.data_as(C.c_void_p), lq.ctypes.data_as(C.c_void_p), C.byref(nu), C.byref(nd)))
+        k = nu.value
+        return kr[:k, :S].copy(), mult[:k].copy(), lq[:k].copy(), nd.value
+
+    # --------------------------------------------------------------- device calls
+    def contract_workspace_size(self, j, E, n_elems):
+        b = C.c_size_t()
+        _lib.check(self._lib.ptsbe_contract_workspace_size(self._h, int(j), int(E), int(n_elems), C.byref(b)))
+        return b.value
+
+    def sample_workspace_size(self, E, total_shots):
+        b = C.c_size_t()
+        _lib.check(self._lib.ptsbe_sample_workspace_size(self._h, int(E), int(total_shots), C.byref(b)))
+        return b.value
+
+    def contract_batch(self, j, kraus_dev, elem_traj_dev, elem_prefix_dev, out_kind=OUT_POPULATION,
+                       workspace=None, stream=None):
+        """ptsbe_contract_batch on torch device tensors; returns (out, totals)."""
+        import torch
+        E = kraus_dev.shape[0]
+        U = elem_traj_dev.shape[0]
+        b = self.batch_sizes[j]
+        dev = kraus_dev.device
+        if out_kind == OUT_AMPLITUDE:
+            out = torch.empty((U, 2 ** b, 2), dtype=torch.float32, device=dev)
+            totals = None
+        else:
+            out = torch.empty((U, 2 ** b), dtype=torch.float32, device=dev)
+            totals = torch.empty(U, dtype=torch.float64, device=dev)
+        if workspace is None:
+            workspace = torch.empty(self.contract_workspace_size(j, E, U), dtype=torch.uint8, device=dev)
+        if stream is None:
+            stream = torch.cuda.current_stream(dev).cuda_stream
+        _lib.check(self._lib.ptsbe_contract_batch(
+            self._h, int(j), _tptr(kraus_dev), int(E), _tptr(elem_traj_dev), _tptr(elem_prefix_dev), int(U),
+            int(out_kind), _tptr(out), _tptr(totals), _tptr(workspace), int(workspace.numel()),
+            C.c_void_p(stream)))
+        if out_kind == OUT_AMPLITUDE:
+            out = torch.view_as_complex(out)
+        return out, totals
+
+    def sample_shots(self, kraus_dev, shots_per_traj_dev, seed, mult_dev=None, workspace=None, stream=None,
+                     want_traj=True):
+        """ptsbe_sample_shots (proportional NBS); returns a dict of device tensors."""
+        import torch
+        E = kraus_dev.shape[0]
+        dev = kraus_dev.device
+        M = int(shots_per_traj_dev.sum().item())
+        shots = torch.empty((max(M, 1), self.n_words), dtype=torch.int64, device=dev)
+        shot_traj = torch.empty(max(M, 1), dtype=torch.int32, device=dev) if want_traj else None
+        weights = torch.empty(E, dtype=torch.float64, device=dev)
+        norms = torch.empty(E, dtype=torch.float64, device=dev)
+        stats = np.zeros(len(self.batch_sizes), dtype=np.int64)
+        if workspace is None:
+            workspace = torch.empty(self.sample_workspace_size(E, M), dtype=torch.uint8, device=dev)
+        if stream is None:
+            stream = torch.cuda.current_stream(dev).cuda_stream
+        _lib.check(self._lib.ptsbe_sample_shots(
+            self._h, _tptr(kraus_dev), int(E), _tptr(mult_dev), _tptr(shots_per_traj_dev), 0, int(seed),
+            _tptr(shots), _tptr(shot_traj), _tptr(weights), _tptr(norms),
+            stats.ctypes.data_as(C.c_void_p), _tptr(workspace), int(workspace.numel()), C.c_void_p(stream)))
+        return {"shots": shots[:M], "shot_traj": None if shot_traj is None else shot_traj[:M],
+                "weights": weights, "norms": norms, "elements_per_batch": stats}
+
+    # -------------------------------------------------------------- measurement
+    def profile_enable(self, on=True):
+        _lib.check(self._lib.ptsbe_profile_enable(self._h, 1 if on else 0))
+
+    def profile_read(self):
+        a, c, d, e = C.c_double(), C.c_double(), C.c_double(), C.c_double()
+        b = C.c_int64()
+        _lib.check(self._lib.ptsbe_profile_read(self._h, C.byref(a), C.byref(b), C.byref(c), C.byref(d),
+                                                C.byref(e)))
+        return {"join_ms": a.value, "join_launches": b.value, "join_flops": c.value, "sweep_ms": d.value,
+                "sweep_bytes": e.value}

@@ -1,0 +1,104 @@
+"""ctypes binding of libptsbe.so (argument marshalling only).
+
+The structures mirror include/ptsbe.h.  Loading fails loudly when the built
+library is missing: there is no fallback path.
+"""
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libptsbe.so")
+
+PTSBE_OK = 0
+STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "UNSUPPORTED", 3: "OUT_OF_MEMORY", 4: "DEVICE", 5: "NUMERIC"}
+EXPORTS = [
+    "ptsbe_plan", "ptsbe_plan_query", "ptsbe_plan_batch_info", "ptsbe_plan_destroy", "ptsbe_last_error",
+    "ptsbe_sample_trajectories", "ptsbe_contract_workspace_size", "ptsbe_sample_workspace_size",
+    "ptsbe_contract_batch", "ptsbe_sample_shots", "ptsbe_profile_enable", "ptsbe_profile_read",
+]
+
+
+class PtsbeError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"ptsbe {STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Circuit_t(C.Structure):
+    _fields_ = [
+        ("n_qubits", C.c_int32), ("n_gates", C.c_int32),
+        ("gate_arity", C.POINTER(C.c_int32)), ("gate_qubits", C.POINTER(C.c_int32)),
+        ("gate_mats", C.POINTER(C.c_double)),
+        ("n_channels", C.c_int32), ("ch_arity", C.POINTER(C.c_int32)), ("ch_nkraus", C.POINTER(C.c_int32)),
+        ("ch_kraus", C.POINTER(C.c_double)), ("ch_prob", C.POINTER(C.c_double)),
+        ("n_sites", C.c_int32), ("site_gate", C.POINTER(C.c_int32)), ("site_qubits", C.POINTER(C.c_int32)),
+        ("site_channel", C.POINTER(C.c_int32)),
+    ]
+
+
+class PlanOpts_t(C.Structure):
+    _fields_ = [
+        ("n_batches", C.c_int32), ("batch_sizes", C.POINTER(C.c_int32)), ("hypersamples", C.c_int32),
+        ("path_seed", C.c_uint64), ("precision", C.c_int32), ("device", C.c_int32),
+        ("device_budget_bytes", C.c_size_t),
+    ]
+
+
+class PlanInfo_t(C.Structure):
+    _fields_ = [
+        ("n_qubits", C.c_int32), ("n_gates", C.c_int32), ("n_sites", C.c_int32), ("n_batches", C.c_int32),
+        ("n_words", C.c_int32), ("max_kraus", C.c_int32), ("plan_device_bytes", C.c_int64),
+    ]
+
+
+class BatchInfo_t(C.Structure):
+    _fields_ = [
+        ("start", C.c_int32), ("size", C.c_int32), ("doubled", C.c_int32),
+        ("n_left_steps", C.c_int32), ("n_right_steps", C.c_int32),
+        ("left_rank", C.c_int32), ("right_rank", C.c_int32),
+        ("left_peak_rank", C.c_int32), ("right_peak_rank", C.c_int32),
+        ("join_rows_log2", C.c_int32), ("crossing", C.c_int32),
+        ("flops_per_traj", C.c_double), ("flops_per_elem", C.c_double),
+        ("join_flops_per_elem", C.c_double), ("bytes_per_traj", C.c_double),
+    ]
+
+
+_lib = None
+
+
+def load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                          "or python -m paper_2604_08467_amd.build")
+    lib = C.CDLL(LIB_PATH)
+    P = C.c_void_p
+    i32, i64, u64, sz = C.c_int32, C.c_int64, C.c_uint64, C.c_size_t
+    lib.ptsbe_last_error.restype = C.c_char_p
+    lib.ptsbe_plan.argtypes = [C.POINTER(Circuit_t), C.POINTER(PlanOpts_t), C.POINTER(P)]
+    lib.ptsbe_plan_query.argtypes = [P, C.POINTER(PlanInfo_t)]
+    lib.ptsbe_plan_batch_info.argtypes = [P, i32, C.POINTER(BatchInfo_t)]
+    lib.ptsbe_plan_destroy.argtypes = [P]
+    lib.ptsbe_plan_destroy.restype = None
+    lib.ptsbe_sample_trajectories.argtypes = [P, u64, i64, i64, P, P, P, C.POINTER(i64), C.POINTER(i64)]
+    lib.ptsbe_contract_workspace_size.argtypes = [P, i32, i64, i64, C.POINTER(sz)]
+    lib.ptsbe_sample_workspace_size.argtypes = [P, i64, i64, C.POINTER(sz)]
+    lib.ptsbe_contract_batch.argtypes = [P, i32, P, i64, P, P, i64, i32, P, P, P, sz, P]
+    lib.ptsbe_sample_shots.argtypes = [P, P, i64, P, P, i32, u64, P, P, P, P, P, P, sz, P]
+    lib.ptsbe_profile_enable.argtypes = [P, i32]
+    lib.ptsbe_profile_read.argtypes = [P, C.POINTER(C.c_double), C.POINTER(i64), C.POINTER(C.c_double),
+                                       C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    for name in EXPORTS:
+        f = getattr(lib, name)
+        if name not in ("ptsbe_last_error", "ptsbe_plan_destroy"):
+            f.restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def check(status):
+    if status != PTSBE_OK:
+        msg = load().ptsbe_last_error().decode(errors="replace")
+        raise PtsbeError(status, msg)

@@ -1,0 +1,823 @@
+// C ABI of the PTSBE library: argument checking, the plan (host constants and
+// the unified path of every batch), host-side pre-trajectory sampling, and the
+// executor that drives the HIP kernels of one batch and of the whole
+// non-degenerate batched sampling loop.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "internal.h"
+#include "philox.h"
+
+using ptsbe::Plan;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+ptsbe_status_t fail(ptsbe_status_t s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(PTSBE_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+using cd = std::complex<double>;
+
+// Matrix of `op` (acting on `sq`, first listed qubit = high bit) in the space of
+// the gate qubits `gq`; identity on gate qubits the operator does not touch.
+void embed_op(const cd* op, const std::vector<int>& sq, const std::vector<int>& gq, cd* out) {
+  const int nG = (int)gq.size(), nS = (int)sq.size();
+  const int D = 1 << nG, d = 1 << nS;
+  std::vector<int> spos(nS);
+  for (int i = 0; i < nS; ++i)
+    for (int k = 0; k < nG; ++k)
+      if (gq[k] == sq[i]) spos[i] = k;
+  for (int gx = 0; gx < D; ++gx)
+    for (int gy = 0; gy < D; ++gy) {
+      bool same = true;
+      for (int k = 0; k < nG; ++k) {
+        bool in_s = false;
+        for (int i = 0; i < nS; ++i) in_s |= spos[i] == k;
+        if (in_s) continue;
+        if (((gx >> (nG - 1 - k)) & 1) != ((gy >> (nG - 1 - k)) & 1)) same = false;
+      }
+      if (!same) { out[gx * D + gy] = 0.0; continue; }
+      int sx = 0, sy = 0;
+      for (int i = 0; i < nS; ++i) {
+        sx |= ((gx >> (nG - 1 - spos[i])) & 1) << (nS - 1 - i);
+        sy |= ((gy >> (nG - 1 - spos[i])) & 1) << (nS - 1 - i);
+      }
+      out[gx * D + gy] = op[sx * d + sy];
+    }
+}
+
+void matmul(const cd* a, const cd* b, cd* c, int d) {
+  for (int r = 0; r < d; ++r)
+    for (int cc = 0; cc < d; ++cc) {
+      cd acc = 0.0;
+      for (int x = 0; x < d; ++x) acc += a[r * d + x] * b[x * d + cc];
+      c[r * d + cc] = acc;
+    }
+}
+
+struct Arena {
+  char* base = nullptr;
+  size_t cap = 0, used = 0;
+  void* take(size_t bytes) {
+    size_t off = (used + 255) & ~(size_t)255;
+    if (off + bytes > cap) return nullptr;
+    used = off + bytes;
+    return base + off;
+  }
+  size_t left() const {
+    size_t off = (used + 255) & ~(size_t)255;
+    return off >= cap ? 0 : cap - off;
+  }
+};
+
+ptsbe::GateCtx gate_ctx(const Plan& p, const uint8_t* kraus) {
+  ptsbe::GateCtx g;
+  g.gates = p.d_gates;
+  g.gate_site_list = p.d_gate_site_list;
+  g.site_ops = p.d_site_ops;
+  g.kraus = kraus;
+  g.S = p.S;
+  g.max_kraus = p.max_kraus;
+  return g;
+}
+
+bool part_uses_vm(const ptsbe::PartPlan& pp) { return pp.peak <= ptsbe::kVmMaxRank; }
+
+size_t part_scratch_per_job(const ptsbe::PartPlan& pp) {
+  if (pp.steps.empty() || part_uses_vm(pp)) return 0;
+  return 2 * ((size_t)8 << pp.peak);
+}
+
+// Run one part (left or right) for n_jobs jobs; the result (rank = labels.size())
+// goes to out[job][2^rank].
+ptsbe_status_t run_part(Plan& p, const ptsbe::PartPlan& pp, const ptsbe::AbsorbStep* d_steps,
+                        const ptsbe::GateCtx& g, int64_t n_jobs, const int32_t* job_traj, int32_t traj_base,
+                        const uint64_t* job_prefix, float2* out, Arena& ar, hipStream_t s) {
+  if (n_jobs <= 0) return PTSBE_OK;
+  const int out_rank = (int)pp.labels.size();
+  if (pp.steps.empty()) {
+    HIP_TRY(ptsbe::launch_fill_one(out, n_jobs, s));
+    return PTSBE_OK;
+  }
+  if (part_uses_vm(pp)) {
+    HIP_TRY(ptsbe::launch_part_vm(d_steps, (int)pp.steps.size(), pp.peak, g, n_jobs, job_traj, traj_base,
+                                  job_prefix, p.NW, out, out_rank, s));
+    return PTSBE_OK;
+  }
+  const size_t mark = ar.used;
+  float2* b0 = (float2*)ar.take((size_t)n_jobs * ((size_t)8 << pp.peak));
+  float2* b1 = (float2*)ar.take((size_t)n_jobs * ((size_t)8 << pp.peak));
+  if (!b0 || !b1) return fail(PTSBE_ERR_OUT_OF_MEMORY, "workspace too small for a sweep");
+  HIP_TRY(ptsbe::launch_fill_one(b0, n_jobs, s));   // rank-0 start: the scalar 1 per job
+  const float2* A = b0;
+  for (size_t i = 0; i < pp.steps.size(); ++i) {
+    float2* C = (i + 1 == pp.steps.size()) ? out : (A == b0 ? b1 : b0);
+    HIP_TRY(ptsbe::launch_absorb_global(pp.steps[i], d_steps + i, g, n_jobs, job_traj, traj_base, job_prefix,
+                                        p.NW, A, C, s));
+    A = C;
+    if (p.profile) p.sweep_bytes += (double)n_jobs * 8.0 *
+                                    (std::ldexp(1.0, pp.steps[i].rA) + std::ldexp(1.0, pp.steps[i].rC));
+  }
+  ar.used = mark;
+  return PTSBE_OK;
+}
+
+struct BatchIO {
+  // elements of this batch (device)
+  const int32_t* elem_traj = nullptr;
+  const uint64_t* elem_prefix = nullptr;
+  int64_t U = 0;
+  // contraction output mode: external full-size output, or per-chunk sampling
+  float* pop_out = nullptr;     // [U][2^b] (contract_batch)
+  float2* amp_out = nullptr;    // [U][2^b] (contract_batch, last batch)
+  double* totals = nullptr;     // [U] FP64 sums (may be null for contract_batch)
+  bool sample = false;
+  ptsbe::SampleArgs sa{};       // template: per-element arrays at offset 0
+};
+
+struct EventPair { hipEvent_t a, b; };
+
+ptsbe_status_t run_batch(Plan& p, int j, const uint8_t* d_kraus, int64_t E, BatchIO& io, Arena& ar,
+                         hipStream_t s, std::vector<EventPair>& evs) {
+  const ptsbe::BatchPlan& bp = p.batches[j];
+  const ptsbe::GateCtx g = gate_ctx(p, d_kraus);
+  if (io.U <= 0) return PTSBE_OK;
+  const size_t mark0 = ar.used;
+  // element ranges per trajectory
+  int32_t* d_first = (int32_t*)ar.take((size_t)(E + 1) * 4);
+  if (!d_first) return fail(PTSBE_ERR_OUT_OF_MEMORY, "workspace too small (trajectory ranges)");
+  HIP_TRY(ptsbe::launch_traj_ranges(io.elem_traj, io.U, E, d_first, s));
+  std::vector<int32_t> first((size_t)E + 1);
+  HIP_TRY(hipMemcpyAsync(first.data(), d_first, (size_t)(E + 1) * 4, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  const int rT = (int)bp.right.labels.size(), rV = (int)bp.left.labels.size();
+  const size_t per_traj = ((size_t)8 << rT) + part_scratch_per_job(bp.right);
+  const size_t nb = (size_t)1 << bp.size;
+  const size_t per_elem = ((size_t)8 << rV) + part_scratch_per_job(bp.left) + (io.sample ? 4 * nb : 0);
+  const size_t avail = ar.left();
+  int64_t t_cap = (int64_t)std::min<size_t>((size_t)E, (avail / 2) / per_traj);
+  int64_t e_cap = (int64_t)((avail / 2) / per_elem);
+  if (t_cap < 1 || e_cap < 1)
+    return fail(PTSBE_ERR_OUT_OF_MEMORY, "workspace too small for one trajectory of batch " + std::to_string(j));
+  e_cap = std::min<int64_t>(e_cap, 1 << 22);
+  const ptsbe::AbsorbStep* d_left = p.d_steps + p.part_step_off[2 * j];
+  const ptsbe::AbsorbStep* d_right = p.d_steps + p.part_step_off[2 * j + 1];
+  for (int64_t t0 = 0; t0 < E; t0 += t_cap) {
+    const int64_t t1 = std::min<int64_t>(E, t0 + t_cap);
+    const int64_t e0 = first[t0], e1 = first[t1];
+    if (e1 <= e0) continue;                       // no elements for these trajectories
+    const size_t mark = ar.used;
+    float2* T = (float2*)ar.take((size_t)(t1 - t0) * ((size_t)8 << rT));
+    if (!T) return fail(PTSBE_ERR_OUT_OF_MEMORY, "workspace too small (right part)");
+    ptsbe_status_t st = run_part(p, bp.right, d_right, g, t1 - t0, nullptr, (int32_t)t0, nullptr, T, ar, s);
+    if (st != PTSBE_OK) return st;
+    for (int64_t a0 = e0; a0 < e1; a0 += e_cap) {
+      const int64_t a1 = std::min<int64_t>(e1, a0 + e_cap), ne = a1 - a0;
+      const size_t mark2 = ar.used;
+      float2* V = (float2*)ar.take((size_t)ne * ((size_t)8 << rV));
+      float* pop = io.sample ? (float*)ar.take((size_t)ne * nb * 4) : nullptr;
+      if (!V || (io.sample && !pop)) return fail(PTSBE_ERR_OUT_OF_MEMORY, "workspace too small (elements)");
+      st = run_part(p, bp.left, d_left, g, ne, io.elem_traj + a0, 0, io.elem_prefix + a0 * p.NW, V, ar, s);
+      if (st != PTSBE_OK) return st;
+      ptsbe::JoinArgs ja{};
+      ja.V = V; ja.v_stride = (int64_t)1 << rV;
+      ja.T = T; ja.t_stride = (int64_t)1 << rT;
+      ja.elem_traj = io.elem_traj + a0; ja.traj_base = (int32_t)t0;
+      ja.n_elems = ne;
+      ja.xb_bits = (int)bp.xb.size(); ja.lk_bits = (int)bp.lk.size(); ja.xT_bits = (int)bp.xT.size();
+      ja.tab = p.d_tables; ja.jd = p.join_dev[j];
+      ja.b = bp.size; ja.doubled = bp.doubled ? 1 : 0;
+      if (io.sample) {
+        ja.pop = pop;
+      } else {
+        ja.pop = io.pop_out ? io.pop_out + a0 * (int64_t)nb : nullptr;
+        ja.amp = io.amp_out ? io.amp_out + a0 * (int64_t)nb : nullptr;
+      }
+      EventPair ev{};
+      if (p.profile) {
+        HIP_TRY(hipEventCreate(&ev.a));
+        HIP_TRY(hipEventCreate(&ev.b));
+        HIP_TRY(hipEventRecord(ev.a, s));
+      }
+      HIP_TRY(ptsbe::launch_join(ja, s));
+      if (p.profile) {
+        HIP_TRY(hipEventRecord(ev.b, s));
+        evs.push_back(ev);
+        p.join_launches++;
+        p.join_flops += bp.join_flops_per_elem * (double)ne;
+      }
+      if (io.sample) {
+        ptsbe::SampleArgs sa = io.sa;
+        sa.pop = pop;
+        sa.n_elems = ne;
+        sa.elem_traj = io.elem_traj + a0;
+        sa.elem_shot_off = io.sa.elem_shot_off + a0;
+        sa.elem_shot_cnt = io.sa.elem_shot_cnt + a0;
+        sa.elem_total = io.sa.elem_total + a0;
+        sa.child_cnt = io.sa.child_cnt ? io.sa.child_cnt + a0 : nullptr;
+        HIP_TRY(ptsbe::launch_sample(sa, s));
+      } else if (io.totals && ja.pop) {
+        HIP_TRY(ptsbe::launch_row_totals(ja.pop, ne, bp.size, io.totals + a0, s));
+      }
+      ar.used = mark2;
+    }
+    ar.used = mark;
+  }
+  ar.used = mark0;
+  return PTSBE_OK;
+}
+
+ptsbe_status_t collect_events(Plan& p, std::vector<EventPair>& evs) {
+  for (auto& e : evs) {
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, e.a, e.b));
+    p.join_ms += ms;
+    hipEventDestroy(e.a);
+    hipEventDestroy(e.b);
+  }
+  evs.clear();
+  return PTSBE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ptsbe_last_error(void) { return g_last_error.c_str(); }
+
+ptsbe_status_t ptsbe_plan(const ptsbe_circuit_t* c, const ptsbe_plan_opts_t* o, ptsbe_plan_t* out) {
+  if (!c || !o || !out) return fail(PTSBE_ERR_INVALID_ARG, "null argument");
+  *out = nullptr;
+  if (c->n_qubits < 1 || c->n_qubits > ptsbe::kMaxQubits) return fail(PTSBE_ERR_INVALID_ARG, "n_qubits out of range");
+  if (c->n_gates < 0 || (c->n_gates > 0 && (!c->gate_arity || !c->gate_qubits || !c->gate_mats)))
+    return fail(PTSBE_ERR_INVALID_ARG, "bad gate arrays");
+  if (c->n_channels < 0 || c->n_sites < 0) return fail(PTSBE_ERR_INVALID_ARG, "bad channel/site counts");
+  if (c->n_sites > 0 && (!c->site_gate || !c->site_qubits || !c->site_channel))
+    return fail(PTSBE_ERR_INVALID_ARG, "bad site arrays");
+  if (c->n_channels > 0 && (!c->ch_arity || !c->ch_nkraus || !c->ch_kraus))
+    return fail(PTSBE_ERR_INVALID_ARG, "bad channel arrays");
+  if (o->n_batches < 1 || !o->batch_sizes) return fail(PTSBE_ERR_INVALID_ARG, "no batches");
+  if (o->precision != PTSBE_C64) return fail(PTSBE_ERR_UNSUPPORTED, "only complex64 precision is implemented");
+  auto p = new Plan();
+  std::unique_ptr<Plan> guard(p);
+  p->n = c->n_qubits;
+  p->NW = (p->n + 63) / 64;
+  p->device = o->device;
+  p->hypersamples = std::max(1, o->hypersamples);
+  p->path_seed = o->path_seed;
+  int sum = 0;
+  for (int j = 0; j < o->n_batches; ++j) {
+    int b = o->batch_sizes[j];
+    if (b < 1) return fail(PTSBE_ERR_INVALID_ARG, "batch size < 1");
+    if (b > ptsbe::kMaxBatch) return fail(PTSBE_ERR_UNSUPPORTED, "batch size > 30");
+    if (b > 12) return fail(PTSBE_ERR_UNSUPPORTED, "batch size > 12 not implemented by the sampler yet");
+    sum += b;
+    p->batch_sizes.push_back(b);
+  }
+  if (sum != p->n) return fail(PTSBE_ERR_INVALID_ARG, "batch sizes must sum to n_qubits");
+  // gates
+  std::vector<bool> touched(p->n, false);
+  size_t moff = 0;
+  for (int g = 0; g < c->n_gates; ++g) {
+    int ar = c->gate_arity[g];
+    if (ar > 2) return fail(PTSBE_ERR_UNSUPPORTED, "gate arity > 2");
+    if (ar < 1) return fail(PTSBE_ERR_INVALID_ARG, "gate arity < 1");
+    std::array<int, 2> q = {c->gate_qubits[2 * g], ar == 2 ? c->gate_qubits[2 * g + 1] : -1};
+    for (int a = 0; a < ar; ++a) {
+      if (q[a] < 0 || q[a] >= p->n) return fail(PTSBE_ERR_INVALID_ARG, "gate qubit out of range");
+      touched[q[a]] = true;
+    }
+    if (ar == 2 && q[0] == q[1]) return fail(PTSBE_ERR_INVALID_ARG, "two-qubit gate on one qubit");
+    int d = 1 << ar;
+    std::array<double, 32> m{};
+    for (int i = 0; i < 2 * d * d; ++i) {
+      m[i] = c->gate_mats[moff + i];
+      if (!std::isfinite(m[i])) return fail(PTSBE_ERR_INVALID_ARG, "non-finite gate entry");
+    }
+    moff += 2 * d * d;
+    p->arity.push_back(ar);
+    p->qubits.push_back(q);
+    p->mats.push_back(m);
+  }
+  // untouched qubits get an explicit identity so that every output leg is on a gate
+  for (int q = 0; q < p->n; ++q)
+    if (!touched[q]) {
+      std::array<double, 32> m{};
+      m[0] = 1.0; m[6] = 1.0;
+      p->arity.push_back(1);
+      p->qubits.push_back({q, -1});
+      p->mats.push_back(m);
+    }
+  p->G = (int)p->arity.size();
+  // channels
+  size_t koff = 0, poff = 0;
+  for (int ch = 0; ch < c->n_channels; ++ch) {
+    int ar = c->ch_arity[ch], nk = c->ch_nkraus[ch];
+    if (ar < 1 || ar > 2) return fail(PTSBE_ERR_UNSUPPORTED, "channel arity must be 1 or 2");
+    if (nk < 1 || nk > 256) return fail(PTSBE_ERR_INVALID_ARG, "channel Kraus count out of range");
+    int d = 1 << ar;
+    std::vector<std::vector<cd>> K(nk, std::vector<cd>(d * d));
+    for (int k = 0; k < nk; ++k)
+      for (int i = 0; i < d * d; ++i) {
+        const size_t o = koff + (size_t)k * 2 * d * d + 2 * (size_t)i;
+        K[k][i] = cd(c->ch_kraus[o], c->ch_kraus[o + 1]);
+        if (!std::isfinite(K[k][i].real()) || !std::isfinite(K[k][i].imag()))
+          return fail(PTSBE_ERR_INVALID_ARG, "non-finite Kraus entry");
+      }
+    koff += (size_t)nk * 2 * d * d;
+    // completeness: sum_k K^dag K = I
+    for (int r = 0; r < d; ++r)
+      for (int cc = 0; cc < d; ++cc) {
+        cd acc = 0.0;
+        for (int k = 0; k < nk; ++k)
+          for (int x = 0; x < d; ++x) acc += std::conj(K[k][x * d + r]) * K[k][x * d + cc];
+        if (std::abs(acc - (r == cc ? 1.0 : 0.0)) > 1e-10)
+          return fail(PTSBE_ERR_INVALID_ARG, "channel " + std::to_string(ch) + " is not trace preserving");
+      }
+    std::vector<double> q(nk);
+    double qs = 0;
+    for (int k = 0; k < nk; ++k) {
+      double given = c->ch_prob ? c->ch_prob[poff + k] : -1.0;
+      if (given >= 0) {
+        q[k] = given;
+      } else {
+        double tr = 0;
+        for (int i = 0; i < d * d; ++i) tr += std::norm(K[k][i]);
+        q[k] = tr / d;
+      }
+      qs += q[k];
+    }
+    poff += nk;
+    if (std::abs(qs - 1.0) > 1e-10) return fail(PTSBE_ERR_INVALID_ARG, "Kraus probabilities do not sum to 1");
+    std::vector<std::array<double, 32>> ops(nk);
+    for (int k = 0; k < nk; ++k) {
+      if (!(q[k] > 0)) {
+        double nrm = 0;
+        for (auto& v : K[k]) nrm += std::norm(v);
+        if (nrm > 0) return fail(PTSBE_ERR_INVALID_ARG, "zero probability for a non-zero Kraus operator");
+      }
+      double sc = q[k] > 0 ? 1.0 / std::sqrt(q[k]) : 0.0;
+      for (int i = 0; i < d * d; ++i) {
+        ops[k][2 * i] = K[k][i].real() * sc;
+        ops[k][2 * i + 1] = K[k][i].imag() * sc;
+      }
+    }
+    p->ch_ops.push_back(ops);
+    p->ch_q.push_back(q);
+    p->max_kraus = std::max(p->max_kraus, nk);
+  }
+  // sites
+  p->gate_sites.assign(p->G, {});
+  for (int s = 0; s < c->n_sites; ++s) {
+    int g = c->site_gate[s], ch = c->site_channel[s];
+    if (g < 0 || g >= c->n_gates) return fail(PTSBE_ERR_INVALID_ARG, "site gate out of range");
+    if (ch < 0 || ch >= c->n_channels) return fail(PTSBE_ERR_INVALID_ARG, "site channel out of range");
+    std::array<int, 2> sq = {c->site_qubits[2 * s], c->site_qubits[2 * s + 1]};
+    int ar = c->ch_arity[ch];
+    if ((ar == 1 && sq[1] != -1) || (ar == 2 && sq[1] < 0)) return fail(PTSBE_ERR_INVALID_ARG, "site qubits do not match channel arity");
+    for (int a = 0; a < ar; ++a) {
+      bool ok = false;
+      for (int b = 0; b < p->arity[g]; ++b) ok |= p->qubits[g][b] == sq[a];
+      if (!ok) return fail(PTSBE_ERR_INVALID_ARG, "site qubit is not a qubit of its gate");
+    }
+    if (ar == 2 && sq[0] == sq[1]) return fail(PTSBE_ERR_INVALID_ARG, "two-qubit site on one qubit");
+    p->site_gate.push_back(g);
+    p->site_channel.push_back(ch);
+    p->site_qubits.push_back(sq);
+    p->gate_sites[g].push_back(s);
+  }
+  p->S = c->n_sites;
+  // path
+  std::string err;
+  if (!ptsbe::build_batch_plans(*p, err)) return fail(PTSBE_ERR_UNSUPPORTED, err);
+  // device constants
+  std::vector<ptsbe::DeviceGate> dg(p->G);
+  std::vector<int32_t> site_list;
+  std::vector<float2> site_ops((size_t)std::max(1, p->S) * p->max_kraus * 16, make_float2(0.f, 0.f));
+  for (int g = 0; g < p->G; ++g) {
+    const int ar = p->arity[g], d = 1 << ar;
+    std::vector<int> gq = {p->qubits[g][0]};
+    if (ar == 2) gq.push_back(p->qubits[g][1]);
+    std::vector<cd> m(d * d), t(d * d), e(d * d);
+    for (int i = 0; i < d * d; ++i) m[i] = cd(p->mats[g][2 * i], p->mats[g][2 * i + 1]);
+    for (int i = 0; i < 16; ++i) dg[g].raw[i] = make_float2(0.f, 0.f);
+    for (int i = 0; i < d * d; ++i) dg[g].raw[i] = make_float2((float)m[i].real(), (float)m[i].imag());
+    dg[g].site_begin = (int)site_list.size();
+    for (int s : p->gate_sites[g]) {
+      site_list.push_back(s);
+      const int ch = p->site_channel[s];
+      const int car = c->ch_arity[ch];
+      std::vector<int> sq = {p->site_qubits[s][0]};
+      if (car == 2) sq.push_back(p->site_qubits[s][1]);
+      const int dk = 1 << car;
+      for (int k = 0; k < (int)p->ch_ops[ch].size(); ++k) {
+        std::vector<cd> op(dk * dk);
+        for (int i = 0; i < dk * dk; ++i) op[i] = cd(p->ch_ops[ch][k][2 * i], p->ch_ops[ch][k][2 * i + 1]);
+        embed_op(op.data(), sq, gq, e.data());
+        for (int i = 0; i < d * d; ++i)
+          site_ops[((size_t)s * p->max_kraus + k) * 16 + i] = make_float2((float)e[i].real(), (float)e[i].imag());
+        if (k == 0) {   // default branch: every site at Kraus index 0, later sites on the left
+          matmul(e.data(), m.data(), t.data(), d);
+          m = t;
+        }
+      }
+    }
+    dg[g].site_end = (int)site_list.size();
+    dg[g].arity = ar;
+    for (int i = 0; i < 16; ++i) dg[g].def[i] = make_float2(0.f, 0.f);
+    for (int i = 0; i < d * d; ++i) dg[g].def[i] = make_float2((float)m[i].real(), (float)m[i].imag());
+  }
+  std::vector<ptsbe::AbsorbStep> steps;
+  std::vector<int64_t> tables;
+  for (auto& bp : p->batches) {
+    p->part_step_off.push_back((int64_t)steps.size());
+    steps.insert(steps.end(), bp.left.steps.begin(), bp.left.steps.end());
+    p->part_step_off.push_back((int64_t)steps.size());
+    steps.insert(steps.end(), bp.right.steps.begin(), bp.right.steps.end());
+    Plan::JoinDev jd{};
+    auto put = [&](const ptsbe::SplitTable& t, int64_t& lo, int64_t& hi) {
+      lo = (int64_t)tables.size();
+      tables.insert(tables.end(), t.lo.begin(), t.lo.end());
+      hi = (int64_t)tables.size();
+      tables.insert(tables.end(), t.hi.begin(), t.hi.end());
+    };
+    put(bp.v_row, jd.vr_lo, jd.vr_hi);
+    put(bp.v_col, jd.vc_lo, jd.vc_hi);
+    put(bp.t_x, jd.tx_lo, jd.tx_hi);
+    put(bp.t_k, jd.tk_lo, jd.tk_hi);
+    put(bp.t_b, jd.tb_lo, jd.tb_hi);
+    put(bp.o_x, jd.ox_lo, jd.ox_hi);
+    put(bp.o_b, jd.ob_lo, jd.ob_hi);
+    p->join_dev.push_back(jd);
+  }
+  if (steps.empty()) steps.push_back(ptsbe::AbsorbStep{});
+  if (site_list.empty()) site_list.push_back(0);
+  size_t bytes = dg.size() * sizeof(ptsbe::DeviceGate) + site_list.size() * 4 + site_ops.size() * sizeof(float2) +
+                 steps.size() * sizeof(ptsbe::AbsorbStep) + tables.size() * 8;
+  p->device_bytes = (int64_t)bytes;
+  if (o->device_budget_bytes && bytes > o->device_budget_bytes)
+    return fail(PTSBE_ERR_OUT_OF_MEMORY, "plan constants exceed device_budget_bytes");
+  if (p->device < 0) {   // host-only plan: path and pre-sampling only, no device constants
+    *out = reinterpret_cast<ptsbe_plan_t>(guard.release());
+    return PTSBE_OK;
+  }
+  HIP_TRY(hipSetDevice(p->device));
+  HIP_TRY(hipMalloc(&p->d_gates, dg.size() * sizeof(ptsbe::DeviceGate)));
+  HIP_TRY(hipMalloc(&p->d_gate_site_list, site_list.size() * 4));
+  HIP_TRY(hipMalloc(&p->d_site_ops, site_ops.size() * sizeof(float2)));
+  HIP_TRY(hipMalloc(&p->d_steps, steps.size() * sizeof(ptsbe::AbsorbStep)));
+  HIP_TRY(hipMalloc(&p->d_tables, tables.size() * 8));
+  HIP_TRY(hipMemcpy(p->d_gates, dg.data(), dg.size() * sizeof(ptsbe::DeviceGate), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(p->d_gate_site_list, site_list.data(), site_list.size() * 4, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(p->d_site_ops, site_ops.data(), site_ops.size() * sizeof(float2), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(p->d_steps, steps.data(), steps.size() * sizeof(ptsbe::AbsorbStep), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(p->d_tables, tables.data(), tables.size() * 8, hipMemcpyHostToDevice));
+  *out = reinterpret_cast<ptsbe_plan_t>(guard.release());
+  return PTSBE_OK;
+}
+
+void ptsbe_plan_destroy(ptsbe_plan_t plan) {
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  if (!p) return;
+  if (p->d_gates) hipFree(p->d_gates);
+  if (p->d_gate_site_list) hipFree(p->d_gate_site_list);
+  if (p->d_site_ops) hipFree(p->d_site_ops);
+  if (p->d_steps) hipFree(p->d_steps);
+  if (p->d_tables) hipFree(p->d_tables);
+  delete p;
+}
+
+ptsbe_status_t ptsbe_plan_query(ptsbe_plan_t plan, ptsbe_plan_info_t* out) {
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  if (!p || !out) return fail(PTSBE_ERR_INVALID_ARG, "null argument");
+  out->n_qubits = p->n;
+  out->n_gates = p->G;
+  out->n_sites = p->S;
+  out->n_batches = (int32_t)p->batches.size();
+  out->n_words = p->NW;
+  out->max_kraus = p->max_kraus;
+  out->plan_device_bytes = p->device_bytes;
+  return PTSBE_OK;
+}
+
+ptsbe_status_t ptsbe_plan_batch_info(ptsbe_plan_t plan, int32_t j, ptsbe_batch_info_t* out) {
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  if (!p || !out) return fail(PTSBE_ERR_INVALID_ARG, "null argument");
+  if (j < 0 || j >= (int)p->batches.size()) return fail(PTSBE_ERR_INVALID_ARG, "batch index out of range");
+  const auto& bp = p->batches[j];
+  out->start = bp.start;
+  out->size = bp.size;
+  out->doubled = bp.doubled;
+  out->n_left_steps = (int32_t)bp.left.steps.size();
+  out->n_right_steps = (int32_t)bp.right.steps.size();
+  out->left_rank = (int32_t)bp.left.labels.size();
+  out->right_rank = (int32_t)bp.right.labels.size();
+  out->left_peak_rank = bp.left.peak;
+  out->right_peak_rank = bp.right.peak;
+  out->join_rows_log2 = (int32_t)bp.xb.size();
+  out->crossing = (int32_t)bp.lk.size();
+  out->flops_per_traj = bp.right.flops;
+  out->flops_per_elem = bp.left.flops + bp.join_flops_per_elem;
+  out->join_flops_per_elem = bp.join_flops_per_elem;
+  out->bytes_per_traj = bp.right.bytes;
+  return PTSBE_OK;
+}
+
+ptsbe_status_t ptsbe_sample_trajectories(ptsbe_plan_t plan, uint64_t seed, int64_t n_unique, int64_t max_draws,
+                                         uint8_t* kraus_idx, int64_t* mult, double* log_q, int64_t* n_unique_out,
+                                         int64_t* n_draws_out) {
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  if (!p) return fail(PTSBE_ERR_INVALID_ARG, "null plan");
+  if (n_unique < 0 || max_draws < 0) return fail(PTSBE_ERR_INVALID_ARG, "negative count");
+  if (n_unique > 0 && (!kraus_idx || !mult)) return fail(PTSBE_ERR_INVALID_ARG, "null output");
+  const int S = p->S;
+  std::vector<std::vector<double>> cum(S);
+  for (int s = 0; s < S; ++s) {
+    const auto& q = p->ch_q[p->site_channel[s]];
+    double acc = 0;
+    for (double v : q) { acc += v; cum[s].push_back(acc); }
+  }
+  // number of distinct error sets that can occur at all (capped): sampling stops
+  // once every one of them has appeared
+  double possible = 1.0;
+  for (int s = 0; s < S; ++s) {
+    int nz = 0;
+    for (double v : p->ch_q[p->site_channel[s]]) nz += v > 0;
+    possible *= nz;
+    if (possible > 9e18) break;
+  }
+  const int64_t target = (int64_t)std::min<double>((double)n_unique, possible);
+  std::unordered_map<std::string, int64_t> seen;
+  std::string row(S, '\0');
+  int64_t found = 0, d = 0;
+  for (; d < max_draws && found < target; ++d) {
+    for (int s = 0; s < S; ++s) {
+      const double u = ptsbe::philox_uniform(seed, 1u, (uint32_t)d, (uint32_t)s, (uint32_t)(d >> 32), 0u);
+      const auto& cs = cum[s];
+      const auto& q = p->ch_q[p->site_channel[s]];
+      int k = -1;
+      for (size_t i = 0; i < cs.size(); ++i)
+        if (cs[i] > u) { k = (int)i; break; }
+      if (k < 0)
+        for (int i = (int)q.size() - 1; i >= 0; --i)
+          if (q[i] > 0) { k = i; break; }
+      row[s] = (char)(uint8_t)k;
+    }
+    auto it = seen.find(row);
+    if (it != seen.end()) {
+      mult[it->second] += 1;
+    } else {
+      seen.emplace(row, found);
+      std::memcpy(kraus_idx + found * S, row.data(), S);
+      mult[found] = 1;
+      if (log_q) {
+        double lq = 0;
+        for (int s = 0; s < S; ++s) lq += std::log(p->ch_q[p->site_channel[s]][(uint8_t)row[s]]);
+        log_q[found] = lq;
+      }
+      ++found;
+    }
+  }
+  if (n_unique_out) *n_unique_out = found;
+  if (n_draws_out) *n_draws_out = d;
+  return PTSBE_OK;
+}
+
+ptsbe_status_t ptsbe_contract_workspace_size(ptsbe_plan_t plan, int32_t j, int64_t E, int64_t n_elems,
+                                             size_t* bytes) {
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  if (!p || !bytes) return fail(PTSBE_ERR_INVALID_ARG, "null argument");
+  if (j < 0 || j >= (int)p->batches.size()) return fail(PTSBE_ERR_INVALID_ARG, "batch index out of range");
+  const auto& bp = p->batches[j];
+  const size_t per_traj = ((size_t)8 << bp.right.labels.size()) + part_scratch_per_job(bp.right);
+  const size_t per_elem = ((size_t)8 << bp.left.labels.size()) + part_scratch_per_job(bp.left);
+  size_t t = (size_t)std::min<int64_t>(E, 256), e = (size_t)std::min<int64_t>(n_elems, 65536);
+  *bytes = (size_t)(E + 1) * 4 + 2 * (std::max<size_t>(t, 1) * per_traj + std::max<size_t>(e, 1) * per_elem) + (1 << 20);
+  return PTSBE_OK;
+}
+
+namespace {
+size_t sample_persistent_bytes(const Plan& p, int64_t E, int64_t M) {
+  const int64_t cap = std::max<int64_t>(E, M);
+  size_t b = 0;
+  auto add = [&](size_t x) { b += (x + 255) & ~(size_t)255; };
+  for (int k = 0; k < 2; ++k) {
+    add((size_t)cap * 4);                 // elem traj
+    add((size_t)cap * 8 * p.NW);          // elem prefix
+    add((size_t)cap * 4);                 // shot off
+    add((size_t)cap * 4);                 // shot cnt
+    add((size_t)std::max<int64_t>(M, 1) * 4);  // shot ids
+  }
+  add((size_t)std::max<int64_t>(M, 1) * 4);    // shot x
+  add((size_t)cap * 4);                   // child cnt
+  add((size_t)cap * 4);                   // child off
+  add((size_t)cap * 8);                   // totals
+  add((size_t)E * 8);                     // traj shot base
+  add((size_t)E * 8);                     // norms
+  add(ptsbe::scan_scratch_bytes(cap));
+  add(64);                                // counters
+  return b;
+}
+}  // namespace
+
+ptsbe_status_t ptsbe_sample_workspace_size(ptsbe_plan_t plan, int64_t E, int64_t total_shots, size_t* bytes) {
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  if (!p || !bytes) return fail(PTSBE_ERR_INVALID_ARG, "null argument");
+  size_t chunk = 0;
+  for (auto& bp : p->batches) {
+    const size_t per_traj = ((size_t)8 << bp.right.labels.size()) + part_scratch_per_job(bp.right);
+    const size_t per_elem = ((size_t)8 << bp.left.labels.size()) + part_scratch_per_job(bp.left) +
+                            ((size_t)4 << bp.size);
+    chunk = std::max(chunk, 2 * (std::min<size_t>(E, 256) * per_traj + 65536 * per_elem));
+  }
+  *bytes = sample_persistent_bytes(*p, E, total_shots) + (size_t)(E + 1) * 4 + chunk + (1 << 20);
+  return PTSBE_OK;
+}
+
+ptsbe_status_t ptsbe_contract_batch(ptsbe_plan_t plan, int32_t j, const uint8_t* d_kraus_idx, int64_t E,
+                                    const int32_t* d_elem_traj, const uint64_t* d_elem_prefix, int64_t n_elems,
+                                    int32_t out_kind, void* d_out, double* d_elem_total, void* d_workspace,
+                                    size_t workspace_bytes, void* stream) {
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  if (!p) return fail(PTSBE_ERR_INVALID_ARG, "null plan");
+  if (p->device < 0) return fail(PTSBE_ERR_INVALID_ARG, "plan was built without a device");
+  if (j < 0 || j >= (int)p->batches.size()) return fail(PTSBE_ERR_INVALID_ARG, "batch index out of range");
+  if (E < 1 || n_elems < 0) return fail(PTSBE_ERR_INVALID_ARG, "bad counts");
+  if (n_elems == 0) return PTSBE_OK;
+  if (!d_kraus_idx || !d_elem_traj || !d_elem_prefix || !d_out || !d_workspace)
+    return fail(PTSBE_ERR_INVALID_ARG, "null device pointer");
+  if (out_kind == PTSBE_OUT_AMPLITUDE && p->batches[j].doubled)
+    return fail(PTSBE_ERR_INVALID_ARG, "amplitudes exist only for the last batch");
+  if (out_kind != PTSBE_OUT_AMPLITUDE && out_kind != PTSBE_OUT_POPULATION)
+    return fail(PTSBE_ERR_INVALID_ARG, "bad out_kind");
+  HIP_TRY(hipSetDevice(p->device));
+  hipStream_t s = (hipStream_t)stream;
+  Arena ar;
+  ar.base = (char*)d_workspace;
+  ar.cap = workspace_bytes;
+  BatchIO io;
+  io.elem_traj = d_elem_traj;
+  io.elem_prefix = d_elem_prefix;
+  io.U = n_elems;
+  if (out_kind == PTSBE_OUT_AMPLITUDE) io.amp_out = (float2*)d_out;
+  else io.pop_out = (float*)d_out;
+  io.totals = out_kind == PTSBE_OUT_POPULATION ? d_elem_total : nullptr;
+  std::vector<EventPair> evs;
+  ptsbe_status_t st = run_batch(*p, j, d_kraus_idx, E, io, ar, s, evs);
+  if (st != PTSBE_OK) return st;
+  if (p->profile) {
+    HIP_TRY(hipStreamSynchronize(s));
+    st = collect_events(*p, evs);
+  }
+  return st;
+}
+
+ptsbe_status_t ptsbe_sample_shots(ptsbe_plan_t plan, const uint8_t* d_kraus_idx, int64_t E, const int64_t* d_mult,
+                                  const int64_t* d_shots_per_traj, int32_t mode, uint64_t seed, uint64_t* d_shots,
+                                  int32_t* d_shot_traj, double* d_traj_weight, double* d_traj_norm,
+                                  int64_t* stats_out, void* d_workspace, size_t workspace_bytes, void* stream) {
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  if (!p) return fail(PTSBE_ERR_INVALID_ARG, "null plan");
+  if (p->device < 0) return fail(PTSBE_ERR_INVALID_ARG, "plan was built without a device");
+  if (mode != PTSBE_MODE_PROPORTIONAL) return fail(PTSBE_ERR_UNSUPPORTED, "only proportional mode is implemented");
+  if (E < 1) return fail(PTSBE_ERR_INVALID_ARG, "E < 1");
+  if (!d_kraus_idx || !d_shots_per_traj || !d_shots || !d_workspace)
+    return fail(PTSBE_ERR_INVALID_ARG, "null device pointer");
+  HIP_TRY(hipSetDevice(p->device));
+  hipStream_t s = (hipStream_t)stream;
+  // shot layout: trajectory i owns rows [base_i, base_i + m_i)
+  std::vector<int64_t> m(E), base(E);
+  HIP_TRY(hipMemcpyAsync(m.data(), d_shots_per_traj, (size_t)E * 8, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  int64_t M = 0;
+  for (int64_t i = 0; i < E; ++i) {
+    if (m[i] < 0) return fail(PTSBE_ERR_INVALID_ARG, "negative shot count");
+    base[i] = M;
+    M += m[i];
+  }
+  if (M >= ((int64_t)1 << 31)) return fail(PTSBE_ERR_UNSUPPORTED, "more than 2^31 shots");
+  const int64_t cap = std::max<int64_t>(E, M);
+  Arena ar;
+  ar.base = (char*)d_workspace;
+  ar.cap = workspace_bytes;
+  struct Elems { int32_t* traj; uint64_t* prefix; int32_t* off; int32_t* cnt; int32_t* ids; } el[2];
+  for (int k = 0; k < 2; ++k) {
+    el[k].traj = (int32_t*)ar.take((size_t)cap * 4);
+    el[k].prefix = (uint64_t*)ar.take((size_t)cap * 8 * p->NW);
+    el[k].off = (int32_t*)ar.take((size_t)cap * 4);
+    el[k].cnt = (int32_t*)ar.take((size_t)cap * 4);
+    el[k].ids = (int32_t*)ar.take((size_t)std::max<int64_t>(M, 1) * 4);
+  }
+  int32_t* shot_x = (int32_t*)ar.take((size_t)std::max<int64_t>(M, 1) * 4);
+  int32_t* child_cnt = (int32_t*)ar.take((size_t)cap * 4);
+  int32_t* child_off = (int32_t*)ar.take((size_t)cap * 4);
+  double* totals = (double*)ar.take((size_t)cap * 8);
+  int64_t* d_base = (int64_t*)ar.take((size_t)E * 8);
+  double* norms = (double*)ar.take((size_t)E * 8);
+  int32_t* scan_scratch = (int32_t*)ar.take(ptsbe::scan_scratch_bytes(cap));
+  int32_t* counters = (int32_t*)ar.take(64);
+  bool ok = shot_x && child_cnt && child_off && totals && d_base && norms && scan_scratch && counters;
+  for (int k = 0; k < 2; ++k) ok = ok && el[k].traj && el[k].prefix && el[k].off && el[k].cnt && el[k].ids;
+  if (!ok) return fail(PTSBE_ERR_OUT_OF_MEMORY, "workspace too small for the shot and element arrays");
+  HIP_TRY(hipMemcpyAsync(d_base, base.data(), (size_t)E * 8, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemsetAsync(counters, 0, 64, s));
+  HIP_TRY(ptsbe::launch_init_elements(E, d_shots_per_traj, el[0].traj, el[0].prefix, p->NW, el[0].off, el[0].cnt,
+                                      d_base, el[0].ids, d_shot_traj, d_shots, M, s));
+  int cur = 0;
+  int64_t U = E;
+  std::vector<EventPair> evs;
+  const int f = (int)p->batches.size();
+  for (int j = 0; j < f; ++j) {
+    if (stats_out) stats_out[j] = U;
+    const auto& bp = p->batches[j];
+    BatchIO io;
+    io.elem_traj = el[cur].traj;
+    io.elem_prefix = el[cur].prefix;
+    io.U = U;
+    io.sample = true;
+    ptsbe::SampleArgs& sa = io.sa;
+    sa.b = bp.size; sa.start = bp.start; sa.NW = p->NW;
+    sa.elem_shot_off = el[cur].off; sa.elem_shot_cnt = el[cur].cnt;
+    sa.shot_ids = el[cur].ids;
+    sa.traj_shot_base = d_base;
+    sa.seed = seed; sa.j = j;
+    sa.shots = d_shots; sa.shot_x = shot_x;
+    sa.elem_total = totals;
+    sa.child_cnt = (j + 1 < f) ? child_cnt : nullptr;
+    sa.bad_flag = counters + 1;
+    ptsbe_status_t st = run_batch(*p, j, d_kraus_idx, E, io, ar, s, evs);
+    if (st != PTSBE_OK) return st;
+    if (j == 0) {
+      // elements of batch 0 are the trajectories themselves: totals = squared norms
+      HIP_TRY(hipMemcpyAsync(norms, totals, (size_t)E * 8, hipMemcpyDeviceToDevice, s));
+      ptsbe::WeightArgs wa{norms, d_mult, E, d_traj_weight, d_traj_norm};
+      if (d_traj_weight || d_traj_norm) HIP_TRY(ptsbe::launch_weights(wa, s));
+    }
+    if (j + 1 < f) {
+      HIP_TRY(ptsbe::launch_scan_i32(child_cnt, child_off, U, counters, scan_scratch, s));
+      int32_t nU = 0;
+      HIP_TRY(hipMemcpyAsync(&nU, counters, 4, hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      ptsbe::ChildArgs ca{};
+      ca.n_elems = U; ca.b = bp.size; ca.start = bp.start; ca.NW = p->NW;
+      ca.elem_traj = el[cur].traj; ca.elem_prefix = el[cur].prefix;
+      ca.elem_shot_off = el[cur].off; ca.elem_shot_cnt = el[cur].cnt;
+      ca.shot_ids = el[cur].ids; ca.shot_x = shot_x; ca.child_off = child_off;
+      ca.out_traj = el[1 - cur].traj; ca.out_prefix = el[1 - cur].prefix;
+      ca.out_shot_off = el[1 - cur].off; ca.out_shot_cnt = el[1 - cur].cnt; ca.out_shot_ids = el[1 - cur].ids;
+      HIP_TRY(ptsbe::launch_children(ca, s));
+      cur = 1 - cur;
+      U = nU;
+    }
+  }
+  int32_t bad = 0;
+  HIP_TRY(hipMemcpyAsync(&bad, counters + 1, 4, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (p->profile) {
+    ptsbe_status_t st = collect_events(*p, evs);
+    if (st != PTSBE_OK) return st;
+  }
+  if (bad) return fail(PTSBE_ERR_NUMERIC, "an element had a zero or non-finite marginal total");
+  return PTSBE_OK;
+}
+
+ptsbe_status_t ptsbe_profile_enable(ptsbe_plan_t plan, int32_t on) {
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  if (!p) return fail(PTSBE_ERR_INVALID_ARG, "null plan");
+  p->profile = on != 0;
+  p->join_ms = p->sweep_ms = p->join_flops = p->sweep_bytes = 0;
+  p->join_launches = 0;
+  return PTSBE_OK;
+}
+
+ptsbe_status_t ptsbe_profile_read(ptsbe_plan_t plan, double* join_ms, int64_t* join_launches, double* join_flops,
+                                  double* sweep_ms, double* sweep_bytes) {
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  if (!p) return fail(PTSBE_ERR_INVALID_ARG, "null plan");
+  if (join_ms) *join_ms = p->join_ms;
+  if (join_launches) *join_launches = p->join_launches;
+  if (join_flops) *join_flops = p->join_flops;
+  if (sweep_ms) *sweep_ms = p->sweep_ms;
+  if (sweep_bytes) *sweep_bytes = p->sweep_bytes;
+  return PTSBE_OK;
+}
+
+}  // extern "C"

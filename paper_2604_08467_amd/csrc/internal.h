@@ -1,0 +1,194 @@
+// Internal structures shared by the planner (host C++), the executor and the
+// HIP kernels of the PTSBE library.  Nothing here is part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <array>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "ptsbe.h"
+
+namespace ptsbe {
+
+constexpr int kMaxBatch = 30;       // largest b_j accepted
+constexpr int kMaxQubits = 1024;
+constexpr int kVmMaxRank = 11;      // parts whose tensors fit 2^11 c64 run in LDS
+constexpr int kMaxSlices = 4;
+
+// ----------------------------------------------------------------------------
+// One absorb step of a sweep: C = A (x) B where A is the running tensor of the
+// part (rank rA; it starts as the scalar 1) and B is one (merged) gate tensor.
+// Labels of A that B contracts sit at bit positions kpos[] of A (ascending);
+// the remaining ("kept") labels keep their relative order in C; B's new labels
+// are inserted into C at positions npos[] (ascending).  Hyper labels (kept, and
+// also indexing B) are bits hm[] of the kept index.  The index into B's 4x4 (or
+// 2x2) matrix is the sum of the leg weights of the set bits.
+struct AbsorbStep {
+  int32_t gate, conj;
+  int32_t rA, rC, nK, nN, nH, nS;
+  int32_t kpos[4], kw[4];
+  int32_t npos[4], nw[4];
+  int32_t hm[4], hw[4];
+  int32_t sq[kMaxSlices], sw[kMaxSlices];   // prefix-sliced legs: qubit, weight
+};
+
+struct PartPlan {
+  std::vector<AbsorbStep> steps;
+  std::vector<int> labels;          // final labels, bit order (bit 0 first)
+  int peak = 0;                     // largest rank of any A or C
+  double flops = 0, bytes = 0, cost = 0;
+  std::string order_name;
+};
+
+// Offsets of a labelled result tensor used by the join: offset of a group of
+// labels as a function of the group's index is a sum over set bits, stored as
+// two tables (low / high halves of the group index).
+struct SplitTable {
+  int bits = 0, lo_bits = 0;
+  std::vector<int64_t> lo, hi;
+};
+
+struct BatchPlan {
+  int start = 0, size = 0;
+  bool doubled = false;
+  PartPlan left, right;             // left: per element (ket, prefix projected)
+  std::vector<int> lk, lb, xb, xT;  // join label groups
+  // join tables
+  SplitTable v_row, v_col;          // V[e]: rows over xb, cols over lk
+  SplitTable t_x, t_k, t_b;         // T[t]: xT, lk, lb
+  SplitTable o_x, o_b;              // output index: xT, xb
+  double join_flops_per_elem = 0;
+};
+
+// Per-gate tensor data uploaded at plan time.
+struct DeviceGate {
+  float2 def[16];                   // default-branch merged matrix (all sites k=0)
+  float2 raw[16];                   // bare gate matrix
+  int32_t site_begin, site_end;     // range into the gate-site list
+  int32_t arity, pad;
+};
+
+struct Plan {
+  int device = 0;
+  int n = 0, G = 0, S = 0, NW = 1, max_kraus = 1;
+  std::vector<int> arity;
+  std::vector<std::array<int, 2>> qubits;
+  std::vector<std::array<double, 32>> mats;       // complex128, 4x4 or 2x2 row-major
+  std::vector<int> site_gate, site_channel;
+  std::vector<std::array<int, 2>> site_qubits;
+  std::vector<std::vector<std::array<double, 32>>> ch_ops;  // per channel, inserted K/sqrt(q)
+  std::vector<std::vector<double>> ch_q;          // proposals
+  std::vector<std::vector<int>> gate_sites;       // per gate, sites in order
+  std::vector<int> batch_sizes;
+  std::vector<BatchPlan> batches;
+  int hypersamples = 1;
+  uint64_t path_seed = 0;
+
+  // device constants
+  DeviceGate* d_gates = nullptr;
+  int32_t* d_gate_site_list = nullptr;            // site ids ordered by gate
+  float2* d_site_ops = nullptr;                   // [S][max_kraus][16] embedded K/sqrt(q)
+  AbsorbStep* d_steps = nullptr;                  // all parts' steps, concatenated
+  int64_t* d_tables = nullptr;                    // all join tables, concatenated
+  std::vector<int64_t> part_step_off;             // per batch: left, right offsets
+  struct JoinDev { int64_t vr_lo, vr_hi, vc_lo, vc_hi, tx_lo, tx_hi, tk_lo, tk_hi, tb_lo, tb_hi, ox_lo, ox_hi, ob_lo, ob_hi; };
+  std::vector<JoinDev> join_dev;
+  int64_t device_bytes = 0;
+
+  // measurement
+  bool profile = false;
+  double join_ms = 0, sweep_ms = 0, join_flops = 0, sweep_bytes = 0;
+  int64_t join_launches = 0;
+};
+
+// planner.cpp
+bool build_batch_plans(Plan& p, std::string& err);
+
+// kernels.hip: launchers (all asynchronous on `stream`)
+struct GateCtx {
+  const DeviceGate* gates;
+  const int32_t* gate_site_list;
+  const float2* site_ops;
+  const uint8_t* kraus;     // [E][S]
+  int32_t S, max_kraus;
+};
+
+// Run all steps of one part in LDS, one workgroup per job.
+// jobs: traj of job = job_traj ? job_traj[job] : job0 + job; prefix words of job.
+hipError_t launch_part_vm(const AbsorbStep* d_steps, int n_steps, int peak, GateCtx g,
+                          int64_t n_jobs, const int32_t* job_traj, int32_t traj_base,
+                          const uint64_t* job_prefix, int NW, float2* out, int out_rank,
+                          hipStream_t stream);
+// One absorb step over all jobs in global memory.
+hipError_t launch_absorb_global(const AbsorbStep& st, const AbsorbStep* d_st, GateCtx g,
+                                int64_t n_jobs, const int32_t* job_traj, int32_t traj_base,
+                                const uint64_t* job_prefix, int NW, const float2* A,
+                                float2* C, hipStream_t stream);
+hipError_t launch_fill_one(float2* buf, int64_t n, hipStream_t stream);
+
+struct JoinArgs {
+  const float2* V; int64_t v_stride;     // per element
+  const float2* T; int64_t t_stride;     // per trajectory (indexed traj - traj_base)
+  const int32_t* elem_traj; int32_t traj_base;
+  int64_t n_elems;
+  int xb_bits, lk_bits, xT_bits;
+  const int64_t* tab;                    // plan table base
+  Plan::JoinDev jd;
+  int b;                                 // output has 2^b entries per element
+  int doubled;
+  float* pop;                            // [n_elems][2^b] (population out) or null
+  float2* amp;                           // [n_elems][2^b] (amplitude out) or null
+};
+hipError_t launch_join(const JoinArgs& a, hipStream_t stream);
+hipError_t launch_row_totals(const float* pop, int64_t n_elems, int b, double* totals,
+                             hipStream_t stream);
+
+struct SampleArgs {
+  const float* pop; int b; int start; int NW;
+  int64_t n_elems;
+  const int32_t* elem_traj;
+  const int32_t* elem_shot_off; const int32_t* elem_shot_cnt;
+  const int32_t* shot_ids;               // shots grouped by element (global rows)
+  const int64_t* traj_shot_base;         // [E] first global row of each trajectory
+  uint64_t seed; int j;
+  uint64_t* shots;                       // [M][NW]
+  int32_t* shot_x;                       // [M] batch value of each shot (by row)
+  double* elem_total;                    // [n_elems]
+  int32_t* child_cnt;                    // [n_elems] or null
+  int32_t* bad_flag;                     // set to 1 on a zero / non-finite total
+};
+hipError_t launch_sample(const SampleArgs& a, hipStream_t stream);
+
+struct ChildArgs {
+  int64_t n_elems; int b; int start; int NW;
+  const int32_t* elem_traj; const uint64_t* elem_prefix;
+  const int32_t* elem_shot_off; const int32_t* elem_shot_cnt;
+  const int32_t* shot_ids; const int32_t* shot_x;
+  const int32_t* child_off;
+  int32_t* out_traj; uint64_t* out_prefix; int32_t* out_shot_off; int32_t* out_shot_cnt;
+  int32_t* out_shot_ids;
+};
+hipError_t launch_children(const ChildArgs& a, hipStream_t stream);
+
+// exclusive scan of n int32 values into int32 out, total written to *d_total
+hipError_t launch_scan_i32(const int32_t* in, int32_t* out, int64_t n, int32_t* d_total,
+                           int32_t* d_scratch, hipStream_t stream);
+size_t scan_scratch_bytes(int64_t n);
+
+struct WeightArgs {
+  const double* norms; const int64_t* mult; int64_t E;
+  double* weights; double* norm_out;
+};
+hipError_t launch_weights(const WeightArgs& a, hipStream_t stream);
+hipError_t launch_init_elements(int64_t E, const int64_t* shots_per_traj, int32_t* elem_traj,
+                                uint64_t* elem_prefix, int NW, int32_t* shot_off,
+                                int32_t* shot_cnt, int64_t* traj_shot_base, int32_t* shot_ids,
+                                int32_t* shot_traj, uint64_t* shots, int64_t M,
+                                hipStream_t stream);
+hipError_t launch_traj_ranges(const int32_t* elem_traj, int64_t n_elems, int64_t E,
+                              int32_t* traj_first, hipStream_t stream);
+
+}  // namespace ptsbe

@@ -1,0 +1,634 @@
+// HIP kernels of the PTSBE hot path for CDNA4 (gfx950, 64-wide wavefronts).
+//
+//  * gate operand load with the unified-path-variation merge fused in (Sec.
+//    III-A): the default-branch merged tensor is shared; a (trajectory, gate)
+//    whose sampled Kraus indices deviate gets (prod K/sqrt(q)) . d_l on the fly.
+//  * part_vm_kernel: a whole sweep (a list of absorb steps) for one job with the
+//    running tensor in LDS (small per-element / per-trajectory parts).
+//  * absorb_global_kernel: one absorb step over all jobs in HBM (large parts).
+//  * join kernels: the per-element contraction of the prefix part with the
+//    per-trajectory part, giving marginals (doubled network) or amplitudes.
+//  * sample_kernel: FP64 inclusive prefix sum of a marginal in LDS and
+//    inverse-CDF draws for every shot routed through the element (Sec. II-B).
+//  * children_kernel: non-degenerate batching (Sec. III-B): the distinct
+//    (prefix, x) of an element's shots become the next batch's elements.
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+#include "philox.h"
+
+namespace ptsbe {
+namespace {
+
+__device__ inline float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ inline float2 cfma(float2 a, float2 b, float2 c) {
+  return make_float2(fmaf(a.x, b.x, fmaf(-a.y, b.y, c.x)), fmaf(a.x, b.y, fmaf(a.y, b.x, c.y)));
+}
+
+__device__ inline uint32_t bit_of_prefix(const uint64_t* pw, int q) {
+  return (uint32_t)((pw[q >> 6] >> (q & 63)) & 1ull);
+}
+
+// Load the (merged) gate matrix of `gate` for trajectory `traj` into out[16]
+// (LDS).  Must be called by all threads of the block; uses threads 0..15.
+__device__ void load_gate_block(const GateCtx& g, int gate, int traj, int conj, float2* out) {
+  const DeviceGate* G = g.gates + gate;
+  const int sb = G->site_begin, se = G->site_end;
+  const uint8_t* kr = g.kraus + (int64_t)traj * g.S;
+  bool dev = false;
+  for (int s = sb; s < se; ++s) dev |= kr[g.gate_site_list[s]] != 0;
+  const int tid = threadIdx.x;
+  if (!dev) {
+    if (tid < 16) {
+      float2 v = G->def[tid];
+      if (conj) v.y = -v.y;
+      out[tid] = v;
+    }
+    return;
+  }
+  if (tid == 0) {
+    const int d = G->arity == 2 ? 4 : 2;
+    float2 m[16], t[16];
+    for (int i = 0; i < 16; ++i) m[i] = G->raw[i];
+    for (int s = sb; s < se; ++s) {
+      int site = g.gate_site_list[s];
+      int k = kr[site];
+      const float2* op = g.site_ops + ((int64_t)site * g.max_kraus + k) * 16;
+      for (int r = 0; r < d; ++r)
+        for (int c = 0; c < d; ++c) {
+          float2 acc = make_float2(0.f, 0.f);
+          for (int x = 0; x < d; ++x) acc = cfma(op[r * d + x], m[x * d + c], acc);
+          t[r * d + c] = acc;
+        }
+      for (int i = 0; i < d * d; ++i) m[i] = t[i];
+    }
+    for (int i = 0; i < 16; ++i) {
+      float2 v = m[i];
+      if (conj) v.y = -v.y;
+      out[i] = v;
+    }
+  }
+}
+
+struct StepRegs {
+  int rA, rC, nK, nN, nH;
+  uint32_t kbase_mask;
+  int kpos[4], npos[4], hm[4], hw[4];
+  int koff[16], noff[16], kB[16], nB[16];
+  int sbase;
+};
+
+__device__ inline uint32_t insert_zero_bits(uint32_t m, const int* pos, int n) {
+  for (int i = 0; i < n; ++i) {
+    const int p = pos[i];
+    const uint32_t lo = m & ((1u << p) - 1u);
+    m = ((m >> p) << (p + 1)) | lo;
+  }
+  return m;
+}
+
+__device__ inline void prepare_step(const AbsorbStep& st, const uint64_t* prefix, StepRegs& r) {
+  r.rA = st.rA; r.rC = st.rC; r.nK = st.nK; r.nN = st.nN; r.nH = st.nH;
+  for (int i = 0; i < 4; ++i) { r.kpos[i] = st.kpos[i]; r.npos[i] = st.npos[i]; r.hm[i] = st.hm[i]; r.hw[i] = st.hw[i]; }
+  for (int k = 0; k < (1 << st.nK); ++k) {
+    int o = 0, w = 0;
+    for (int i = 0; i < st.nK; ++i)
+      if ((k >> i) & 1) { o += 1 << st.kpos[i]; w += st.kw[i]; }
+    r.koff[k] = o; r.kB[k] = w;
+  }
+  for (int n = 0; n < (1 << st.nN); ++n) {
+    int o = 0, w = 0;
+    for (int i = 0; i < st.nN; ++i)
+      if ((n >> i) & 1) { o += 1 << st.npos[i]; w += st.nw[i]; }
+    r.noff[n] = o; r.nB[n] = w;
+  }
+  int sb = 0;
+  for (int i = 0; i < st.nS; ++i) sb += (int)bit_of_prefix(prefix, st.sq[i]) * st.sw[i];
+  r.sbase = sb;
+}
+
+// out[c] for all n of one kept index m
+__device__ inline void absorb_one(const StepRegs& r, uint32_t m, const float2* A, float2* C,
+                                  const float2* Gm) {
+  float2 a[16];
+  const uint32_t abase = insert_zero_bits(m, r.kpos, r.nK);
+  const int nk = 1 << r.nK;
+  // A always holds the running tensor; before the first step it is the scalar 1
+  for (int k = 0; k < nk; ++k) a[k] = A[abase + r.koff[k]];
+  int hidx = r.sbase;
+  for (int i = 0; i < r.nH; ++i) hidx += (int)((m >> r.hm[i]) & 1u) * r.hw[i];
+  const uint32_t cbase = insert_zero_bits(m, r.npos, r.nN);
+  const int nn = 1 << r.nN;
+  for (int n = 0; n < nn; ++n) {
+    float2 acc = make_float2(0.f, 0.f);
+    const int bn = hidx + r.nB[n];
+    for (int k = 0; k < nk; ++k) acc = cfma(a[k], Gm[bn + r.kB[k]], acc);
+    C[cbase + r.noff[n]] = acc;
+  }
+}
+
+// ------------------------------------------------------------------ LDS sweep
+__global__ void part_vm_kernel(const AbsorbStep* __restrict__ steps, int n_steps, int buf_elems,
+                               GateCtx g, int64_t n_jobs, const int32_t* __restrict__ job_traj,
+                               int32_t traj_base, const uint64_t* __restrict__ job_prefix, int NW,
+                               float2* __restrict__ out, int out_rank) {
+  extern __shared__ float2 lds[];
+  float2* bufA = lds;
+  float2* bufC = lds + buf_elems;
+  float2* Gm = lds + 2 * buf_elems;
+  uint64_t* pw = reinterpret_cast<uint64_t*>(Gm + 16);
+  const int64_t job = blockIdx.x;
+  if (job >= n_jobs) return;
+  const int traj = job_traj ? job_traj[job] : traj_base + (int)job;
+  if (job_prefix) {
+    for (int w = threadIdx.x; w < NW; w += blockDim.x) pw[w] = job_prefix[job * NW + w];
+  } else {
+    for (int w = threadIdx.x; w < NW; w += blockDim.x) pw[w] = 0;
+  }
+  if (threadIdx.x == 0) bufA[0] = make_float2(1.f, 0.f);
+  __syncthreads();
+  for (int s = 0; s < n_steps; ++s) {
+    const AbsorbStep& st = steps[s];
+    load_gate_block(g, st.gate, traj, st.conj, Gm);
+    __syncthreads();
+    StepRegs r;
+    prepare_step(st, pw, r);
+    const uint32_t nm = 1u << (r.rC - r.nN);
+    for (uint32_t m = threadIdx.x; m < nm; m += blockDim.x) absorb_one(r, m, bufA, bufC, Gm);
+    __syncthreads();
+    float2* t = bufA; bufA = bufC; bufC = t;
+  }
+  const int64_t n_out = (int64_t)1 << out_rank;
+  float2* o = out + job * n_out;
+  for (int64_t i = threadIdx.x; i < n_out; i += blockDim.x) o[i] = bufA[i];
+}
+
+// --------------------------------------------------------------- HBM sweep step
+__global__ void absorb_global_kernel(const AbsorbStep* __restrict__ st_dev, GateCtx g, int64_t n_jobs,
+                                     int64_t blocks_per_job, const int32_t* __restrict__ job_traj,
+                                     int32_t traj_base, const uint64_t* __restrict__ job_prefix, int NW,
+                                     const float2* __restrict__ A, float2* __restrict__ C) {
+  __shared__ float2 Gm[16];
+  __shared__ uint64_t pw[16];
+  const int64_t job = blockIdx.x / blocks_per_job;
+  const int64_t chunk = blockIdx.x % blocks_per_job;
+  if (job >= n_jobs) return;
+  const AbsorbStep& st = *st_dev;
+  const int traj = job_traj ? job_traj[job] : traj_base + (int)job;
+  if (threadIdx.x < NW) pw[threadIdx.x] = job_prefix ? job_prefix[job * NW + threadIdx.x] : 0ull;
+  load_gate_block(g, st.gate, traj, st.conj, Gm);
+  __syncthreads();
+  StepRegs r;
+  prepare_step(st, pw, r);
+  const uint32_t nm = 1u << (r.rC - r.nN);
+  const uint32_t m = (uint32_t)(chunk * blockDim.x + threadIdx.x);
+  if (m >= nm) return;
+  const float2* Aj = A + (job << st.rA);
+  float2* Cj = C + (job << st.rC);
+  absorb_one(r, m, Aj, Cj, Gm);
+}
+
+__global__ void fill_one_kernel(float2* buf, int64_t n) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) buf[i] = make_float2(1.f, 0.f);
+}
+
+// ------------------------------------------------------------------------ join
+__device__ inline int64_t tab(const int64_t* base, int64_t lo_off, int64_t hi_off, int lo_bits, uint32_t g) {
+  return base[lo_off + (g & ((1u << lo_bits) - 1u))] + base[hi_off + (g >> lo_bits)];
+}
+
+__global__ void join_kernel(JoinArgs a) {
+  const int64_t rows = (int64_t)1 << a.xb_bits;
+  const int64_t nx = (int64_t)1 << a.xT_bits;
+  const int64_t total = a.n_elems * rows * nx;
+  const int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (id >= total) return;
+  const uint32_t x = (uint32_t)(id % nx);
+  const uint32_t row = (uint32_t)((id / nx) % rows);
+  const int64_t e = id / (nx * rows);
+  const int lo_x = a.xT_bits < 12 ? a.xT_bits : 12;
+  const int lo_b = a.xb_bits < 12 ? a.xb_bits : 12;
+  const int lo_k = a.lk_bits < 12 ? a.lk_bits : 12;
+  const float2* V = a.V + e * a.v_stride;
+  const float2* T = a.T + (int64_t)(a.elem_traj[e] - a.traj_base) * a.t_stride;
+  const int64_t vr = tab(a.tab, a.jd.vr_lo, a.jd.vr_hi, lo_b, row);
+  const int64_t tx = tab(a.tab, a.jd.tx_lo, a.jd.tx_hi, lo_x, x);
+  const int nk = 1 << a.lk_bits;
+  const int64_t oidx = tab(a.tab, a.jd.ox_lo, a.jd.ox_hi, lo_x, x) + tab(a.tab, a.jd.ob_lo, a.jd.ob_hi, lo_b, row);
+  const int64_t nout = (int64_t)1 << a.b;
+  if (a.doubled) {
+    float acc = 0.f;
+    for (int k2 = 0; k2 < nk; ++k2) {
+      const float2 v2 = V[vr + tab(a.tab, a.jd.vc_lo, a.jd.vc_hi, lo_k, k2)];
+      const int64_t tb = tab(a.tab, a.jd.tb_lo, a.jd.tb_hi, lo_k, k2);
+      float2 y = make_float2(0.f, 0.f);
+      for (int k = 0; k < nk; ++k) {
+        const float2 v = V[vr + tab(a.tab, a.jd.vc_lo, a.jd.vc_hi, lo_k, k)];
+        y = cfma(v, T[tx + tab(a.tab, a.jd.tk_lo, a.jd.tk_hi, lo_k, k) + tb], y);
+      }
+      acc += y.x * v2.x + y.y * v2.y;   // Re(y * conj(v2))
+    }
+    a.pop[e * nout + oidx] = acc;
+  } else {
+    float2 y = make_float2(0.f, 0.f);
+    for (int k = 0; k < nk; ++k) {
+      const float2 v = V[vr + tab(a.tab, a.jd.vc_lo, a.jd.vc_hi, lo_k, k)];
+      y = cfma(v, T[tx + tab(a.tab, a.jd.tk_lo, a.jd.tk_hi, lo_k, k)], y);
+    }
+    if (a.amp) a.amp[e * nout + oidx] = y;
+    if (a.pop) a.pop[e * nout + oidx] = y.x * y.x + y.y * y.y;
+  }
+}
+
+__global__ void row_totals_kernel(const float* pop, int64_t n_elems, int b, double* totals) {
+  __shared__ double red[256];
+  const int64_t e = blockIdx.x;
+  const int64_t n = (int64_t)1 << b;
+  // sequential chunks per thread, then a fixed tree: deterministic
+  double s = 0.0;
+  const int64_t per = (n + blockDim.x - 1) / blockDim.x;
+  const int64_t lo = threadIdx.x * per, hi = lo + per < n ? lo + per : n;
+  for (int64_t i = lo; i < hi; ++i) s += (double)pop[e * n + i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) totals[e] = red[0];
+}
+
+// --------------------------------------------------------------------- sampling
+constexpr int kSampleThreads = 256;
+
+// Block-wide inclusive FP64 scan of c[0..n) in LDS (n a power of two <= 4096):
+// each thread scans a contiguous chunk sequentially, chunk totals are scanned
+// by a fixed tree, then added back.
+__device__ void block_scan_f64(double* c, int n, double* part) {
+  const int T = kSampleThreads;
+  const int per = (n + T - 1) / T;
+  const int lo = threadIdx.x * per;
+  const int hi = lo + per < n ? lo + per : n;
+  double s = 0.0;
+  for (int i = lo; i < hi; ++i) { s += c[i]; c[i] = s; }
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 1; off < T; off <<= 1) {
+    double v = (int)threadIdx.x >= off ? part[threadIdx.x - off] : 0.0;
+    __syncthreads();
+    part[threadIdx.x] += v;
+    __syncthreads();
+  }
+  const double add = threadIdx.x > 0 ? part[threadIdx.x - 1] : 0.0;
+  for (int i = lo; i < hi; ++i) c[i] += add;
+  __syncthreads();
+}
+
+__global__ void __launch_bounds__(kSampleThreads) sample_kernel(SampleArgs a) {
+  extern __shared__ double sm[];
+  const int n = 1 << a.b;
+  double* C = sm;
+  double* part = sm + n;
+  int* hist = reinterpret_cast<int*>(part + kSampleThreads);
+  __shared__ int last_pos;
+  __shared__ int nchild;
+  const int64_t e = blockIdx.x;
+  if (e >= a.n_elems) return;
+  const float* pi = a.pop + e * (int64_t)n;
+  for (int i = threadIdx.x; i < n; i += kSampleThreads) {
+    C[i] = (double)pi[i];
+    hist[i] = 0;
+  }
+  if (threadIdx.x == 0) { last_pos = -1; nchild = 0; }
+  __syncthreads();
+  // largest x with pi(x) > 0
+  {
+    int lp = -1;
+    for (int i = threadIdx.x; i < n; i += kSampleThreads)
+      if (C[i] > 0.0) lp = i;
+    atomicMax(&last_pos, lp);
+  }
+  __syncthreads();
+  block_scan_f64(C, n, part);
+  const double Z = C[n - 1];
+  if (threadIdx.x == 0) {
+    a.elem_total[e] = Z;
+    if (!(Z > 0.0) || !isfinite(Z)) atomicExch(a.bad_flag, 1);
+  }
+  const int traj = a.elem_traj[e];
+  const int off = a.elem_shot_off[e];
+  const int cnt = a.elem_shot_cnt[e];
+  const int64_t tbase = a.traj_shot_base[traj];
+  for (int i = threadIdx.x; i < cnt; i += kSampleThreads) {
+    const int row = a.shot_ids[off + i];
+    const uint32_t t = (uint32_t)(row - tbase);
+    const double u = philox_uniform(a.seed, 2u, (uint32_t)traj, (uint32_t)a.j, t, 0u);
+    const double target = u * Z;
+    // first x with C[x] > target
+    int lo = 0, hi = n;   // invariant: answer in [lo, hi]
+    while (lo < hi) {
+      int mid = (lo + hi) >> 1;
+      if (C[mid] > target) hi = mid; else lo = mid + 1;
+    }
+    int x = lo < n ? lo : last_pos;
+    if (x < 0) x = 0;
+    a.shot_x[row] = x;
+    // write the batch bits at qubits [start, start + b)
+    uint64_t* w = a.shots + (int64_t)row * a.NW;
+    const int q0 = a.start;
+    const int wi = q0 >> 6, sh = q0 & 63;
+    w[wi] |= (uint64_t)x << sh;
+    if (sh + a.b > 64) w[wi + 1] |= (uint64_t)x >> (64 - sh);
+    if (a.child_cnt) atomicAdd(&hist[x], 1);
+  }
+  if (a.child_cnt) {
+    __syncthreads();
+    int c = 0;
+    for (int i = threadIdx.x; i < n; i += kSampleThreads) c += hist[i] > 0;
+    atomicAdd(&nchild, c);
+    __syncthreads();
+    if (threadIdx.x == 0) a.child_cnt[e] = nchild;
+  }
+}
+
+__global__ void __launch_bounds__(kSampleThreads) children_kernel(ChildArgs a) {
+  extern __shared__ int ism[];
+  const int n = 1 << a.b;
+  int* hist = ism;          // counts per x
+  int* start = ism + n;     // exclusive scan of counts
+  int* rank = ism + 2 * n;  // exclusive scan of (count > 0)
+  __shared__ int part_s[kSampleThreads];
+  __shared__ int part_r[kSampleThreads];
+  const int64_t e = blockIdx.x;
+  if (e >= a.n_elems) return;
+  for (int i = threadIdx.x; i < n; i += kSampleThreads) hist[i] = 0;
+  __syncthreads();
+  const int off = a.elem_shot_off[e], cnt = a.elem_shot_cnt[e];
+  for (int i = threadIdx.x; i < cnt; i += kSampleThreads) atomicAdd(&hist[a.shot_x[a.shot_ids[off + i]]], 1);
+  __syncthreads();
+  // exclusive scans of hist and of (hist > 0), chunked per thread
+  const int per = (n + kSampleThreads - 1) / kSampleThreads;
+  const int lo = threadIdx.x * per, hi = lo + per < n ? lo + per : n;
+  int s = 0, r = 0;
+  for (int i = lo; i < hi; ++i) { s += hist[i]; r += hist[i] > 0; }
+  part_s[threadIdx.x] = s;
+  part_r[threadIdx.x] = r;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int as = 0, ar = 0;
+    for (int t = 0; t < kSampleThreads; ++t) {
+      int ts = part_s[t], tr = part_r[t];
+      part_s[t] = as; part_r[t] = ar;
+      as += ts; ar += tr;
+    }
+  }
+  __syncthreads();
+  s = part_s[threadIdx.x];
+  r = part_r[threadIdx.x];
+  for (int i = lo; i < hi; ++i) {
+    start[i] = s; rank[i] = r;
+    s += hist[i]; r += hist[i] > 0;
+  }
+  __syncthreads();
+  const int traj = a.elem_traj[e];
+  const int64_t cbase = a.child_off[e];
+  const uint64_t* pp = a.elem_prefix + e * a.NW;
+  for (int x = threadIdx.x; x < n; x += kSampleThreads) {
+    if (hist[x] == 0) continue;
+    const int64_t c = cbase + rank[x];
+    a.out_traj[c] = traj;
+    a.out_shot_off[c] = off + start[x];
+    a.out_shot_cnt[c] = hist[x];
+    uint64_t* op = a.out_prefix + c * a.NW;
+    for (int w = 0; w < a.NW; ++w) op[w] = pp[w];
+    const int wi = a.start >> 6, sh = a.start & 63;
+    op[wi] |= (uint64_t)x << sh;
+    if (sh + a.b > 64) op[wi + 1] |= (uint64_t)x >> (64 - sh);
+  }
+  __syncthreads();
+  // scatter shot ids into the children's ranges (order within a child is free)
+  for (int i = threadIdx.x; i < cnt; i += kSampleThreads) {
+    const int row = a.shot_ids[off + i];
+    const int x = a.shot_x[row];
+    const int pos = atomicAdd(&start[x], 1);
+    a.out_shot_ids[off + pos] = row;
+  }
+}
+
+// ---------------------------------------------------------------------- scans
+constexpr int kScanBlock = 1024;
+
+__global__ void scan_block_sums(const int32_t* in, int64_t n, int32_t* sums) {
+  __shared__ int32_t red[256];
+  const int64_t base = blockIdx.x * (int64_t)kScanBlock;
+  int32_t s = 0;
+  for (int i = threadIdx.x; i < kScanBlock; i += 256)
+    if (base + i < n) s += in[base + i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) sums[blockIdx.x] = red[0];
+}
+
+__global__ void scan_sums_serial(int32_t* sums, int64_t nb, int32_t* total) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  int32_t acc = 0;
+  for (int64_t i = 0; i < nb; ++i) { int32_t v = sums[i]; sums[i] = acc; acc += v; }
+  *total = acc;
+}
+
+__global__ void scan_apply(const int32_t* in, int64_t n, const int32_t* sums, int32_t* out) {
+  __shared__ int32_t vals[kScanBlock];
+  __shared__ int32_t part[256];
+  const int64_t base = blockIdx.x * (int64_t)kScanBlock;
+  for (int i = threadIdx.x; i < kScanBlock; i += 256) vals[i] = base + i < n ? in[base + i] : 0;
+  __syncthreads();
+  const int per = kScanBlock / 256;
+  const int lo = threadIdx.x * per;
+  int32_t s = 0;
+  for (int i = 0; i < per; ++i) s += vals[lo + i];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int32_t acc = sums[blockIdx.x];
+    for (int t = 0; t < 256; ++t) { int32_t v = part[t]; part[t] = acc; acc += v; }
+  }
+  __syncthreads();
+  int32_t acc = part[threadIdx.x];
+  for (int i = 0; i < per; ++i) {
+    int32_t v = vals[lo + i];
+    if (base + lo + i < n) out[base + lo + i] = acc;
+    acc += v;
+  }
+}
+
+// -------------------------------------------------------------------- weights
+__global__ void weights_kernel(WeightArgs a) {
+  __shared__ double red[1024];
+  double s = 0.0;
+  // fixed assignment of trajectories to threads and a fixed tree: deterministic
+  for (int64_t i = threadIdx.x; i < a.E; i += blockDim.x) {
+    double m = a.mult ? (double)a.mult[i] : 1.0;
+    s += m * a.norms[i];
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double tot = red[0];
+  for (int64_t i = threadIdx.x; i < a.E; i += blockDim.x) {
+    double m = a.mult ? (double)a.mult[i] : 1.0;
+    if (a.weights) a.weights[i] = m * a.norms[i] / tot;
+    if (a.norm_out) a.norm_out[i] = a.norms[i];
+  }
+}
+
+__global__ void init_traj_kernel(int64_t E, const int64_t* m, const int64_t* base, int32_t* elem_traj,
+                                 uint64_t* elem_prefix, int NW, int32_t* shot_off, int32_t* shot_cnt) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= E) return;
+  elem_traj[i] = (int32_t)i;
+  for (int w = 0; w < NW; ++w) elem_prefix[i * NW + w] = 0ull;
+  shot_off[i] = (int32_t)base[i];
+  shot_cnt[i] = (int32_t)m[i];
+}
+
+__global__ void init_shots_kernel(int64_t M, int64_t E, const int64_t* base, int32_t* shot_ids,
+                                  int32_t* shot_traj, uint64_t* shots, int NW) {
+  int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (g >= M) return;
+  shot_ids[g] = (int32_t)g;
+  for (int w = 0; w < NW; ++w) shots[g * NW + w] = 0ull;
+  if (shot_traj) {
+    // trajectory owning row g: last i with base[i] <= g (base non-decreasing)
+    int64_t lo = 0, hi = E - 1;
+    while (lo < hi) {
+      int64_t mid = (lo + hi + 1) >> 1;
+      if (base[mid] <= g) lo = mid; else hi = mid - 1;
+    }
+    // the last such i is the one that owns rows (earlier ones with equal base have no shots)
+    shot_traj[g] = (int32_t)lo;
+  }
+}
+
+__global__ void traj_first_kernel(const int32_t* elem_traj, int64_t U, int64_t E, int32_t* first) {
+  int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e > U) return;
+  int lo_t = (e == 0) ? 0 : elem_traj[e - 1] + 1;
+  int hi_t = (e == U) ? (int)E : elem_traj[e];
+  for (int t = lo_t; t <= hi_t; ++t) first[t] = (int32_t)e;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------- launchers
+hipError_t launch_part_vm(const AbsorbStep* d_steps, int n_steps, int peak, GateCtx g, int64_t n_jobs,
+                          const int32_t* job_traj, int32_t traj_base, const uint64_t* job_prefix, int NW,
+                          float2* out, int out_rank, hipStream_t stream) {
+  if (n_jobs <= 0) return hipSuccess;
+  const int buf = 1 << (peak > 0 ? peak : 0);
+  const size_t shmem = (size_t)(2 * buf + 16) * sizeof(float2) + (size_t)NW * sizeof(uint64_t);
+  int threads = buf / 2 < 64 ? 64 : (buf / 2 > 256 ? 256 : buf / 2);
+  hipLaunchKernelGGL(part_vm_kernel, dim3((unsigned)n_jobs), dim3(threads), shmem, stream, d_steps, n_steps,
+                     buf, g, n_jobs, job_traj, traj_base, job_prefix, NW, out, out_rank);
+  return hipGetLastError();
+}
+
+hipError_t launch_absorb_global(const AbsorbStep& st, const AbsorbStep* d_st, GateCtx g, int64_t n_jobs,
+                                const int32_t* job_traj, int32_t traj_base, const uint64_t* job_prefix,
+                                int NW, const float2* A, float2* C, hipStream_t stream) {
+  if (n_jobs <= 0) return hipSuccess;
+  const int64_t nm = (int64_t)1 << (st.rC - st.nN);
+  const int threads = 256;
+  const int64_t bpj = (nm + threads - 1) / threads;
+  hipLaunchKernelGGL(absorb_global_kernel, dim3((unsigned)(bpj * n_jobs)), dim3(threads), 0, stream, d_st, g,
+                     n_jobs, bpj, job_traj, traj_base, job_prefix, NW, A, C);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_one(float2* buf, int64_t n, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_one_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, buf, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_join(const JoinArgs& a, hipStream_t stream) {
+  const int64_t total = a.n_elems * ((int64_t)1 << (a.xb_bits + a.xT_bits));
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(join_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_row_totals(const float* pop, int64_t n_elems, int b, double* totals, hipStream_t stream) {
+  if (n_elems <= 0) return hipSuccess;
+  hipLaunchKernelGGL(row_totals_kernel, dim3((unsigned)n_elems), dim3(256), 0, stream, pop, n_elems, b, totals);
+  return hipGetLastError();
+}
+
+hipError_t launch_sample(const SampleArgs& a, hipStream_t stream) {
+  if (a.n_elems <= 0) return hipSuccess;
+  const int n = 1 << a.b;
+  const size_t shmem = (size_t)n * sizeof(double) + kSampleThreads * sizeof(double) + (size_t)n * sizeof(int);
+  hipLaunchKernelGGL(sample_kernel, dim3((unsigned)a.n_elems), dim3(kSampleThreads), shmem, stream, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_children(const ChildArgs& a, hipStream_t stream) {
+  if (a.n_elems <= 0) return hipSuccess;
+  const int n = 1 << a.b;
+  const size_t shmem = (size_t)3 * n * sizeof(int);
+  hipLaunchKernelGGL(children_kernel, dim3((unsigned)a.n_elems), dim3(kSampleThreads), shmem, stream, a);
+  return hipGetLastError();
+}
+
+size_t scan_scratch_bytes(int64_t n) {
+  return (size_t)((n + kScanBlock - 1) / kScanBlock + 1) * sizeof(int32_t);
+}
+
+hipError_t launch_scan_i32(const int32_t* in, int32_t* out, int64_t n, int32_t* d_total, int32_t* d_scratch,
+                           hipStream_t stream) {
+  const int64_t nb = (n + kScanBlock - 1) / kScanBlock;
+  if (n <= 0) {
+    hipLaunchKernelGGL(scan_sums_serial, dim3(1), dim3(1), 0, stream, d_scratch, (int64_t)0, d_total);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(scan_block_sums, dim3((unsigned)nb), dim3(256), 0, stream, in, n, d_scratch);
+  hipLaunchKernelGGL(scan_sums_serial, dim3(1), dim3(1), 0, stream, d_scratch, nb, d_total);
+  hipLaunchKernelGGL(scan_apply, dim3((unsigned)nb), dim3(256), 0, stream, in, n, d_scratch, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_weights(const WeightArgs& a, hipStream_t stream) {
+  hipLaunchKernelGGL(weights_kernel, dim3(1), dim3(1024), 0, stream, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_elements(int64_t E, const int64_t* shots_per_traj, int32_t* elem_traj, uint64_t* elem_prefix,
+                                int NW, int32_t* shot_off, int32_t* shot_cnt, int64_t* traj_shot_base,
+                                int32_t* shot_ids, int32_t* shot_traj, uint64_t* shots, int64_t M,
+                                hipStream_t stream) {
+  if (E > 0)
+    hipLaunchKernelGGL(init_traj_kernel, dim3((unsigned)((E + 255) / 256)), dim3(256), 0, stream, E,
+                       shots_per_traj, traj_shot_base, elem_traj, elem_prefix, NW, shot_off, shot_cnt);
+  if (M > 0)
+    hipLaunchKernelGGL(init_shots_kernel, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, stream, M, E,
+                       traj_shot_base, shot_ids, shot_traj, shots, NW);
+  return hipGetLastError();
+}
+
+hipError_t launch_traj_ranges(const int32_t* elem_traj, int64_t n_elems, int64_t E, int32_t* traj_first,
+                              hipStream_t stream) {
+  hipLaunchKernelGGL(traj_first_kernel, dim3((unsigned)((n_elems + 1 + 255) / 256)), dim3(256), 0, stream,
+                     elem_traj, n_elems, E, traj_first);
+  return hipGetLastError();
+}
+
+}  // namespace ptsbe

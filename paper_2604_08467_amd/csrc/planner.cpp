@@ -1,0 +1,439 @@
+// Host planner: one unified, error-independent contraction path per qubit batch.
+//
+// Unified path variations (Sec. III-A): every sampled noise operator is merged
+// into the gate it follows, so every trajectory's network has the structure of
+// the noiseless circuit and one path serves all error sets and all shots.  The
+// path is found once per batch, on the host, outside the timed loop.
+//
+// Network of batch j (Sec. II-B; prefix s_<j projected):
+//   * j < f-1: ket network x conjugate (bra) network; prefix outputs sliced to
+//     the element's bits on both sides, batch outputs shared by ket and bra and
+//     left open (diagonal), later outputs shared and summed (trace);
+//   * j = f-1: ket network only, prefix outputs sliced, batch outputs open.
+// The network is split into a per-element LEFT part (ket gates touching a
+// prefix qubit; its bra copy is its complex conjugate and is never formed) and
+// a per-trajectory RIGHT part (all other gates, ket and bra).  Each part is
+// contracted as a sweep that absorbs one gate tensor at a time into a running
+// tensor; the order is the cheapest of several structured sweeps and of
+// `hypersamples` randomised greedy sweeps.  A final join contracts the two parts:
+//   doubled: pi[xT, xb] = sum_{k,k'} V[xb, k] T[xT, k, k'] conj(V[xb, k'])
+//   ket:     amp[xT, xb] = sum_k V[xb, k] T[xT, k]
+// with k the wires crossing from the left to the right part.
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <numeric>
+#include <random>
+#include <set>
+
+#include "internal.h"
+
+namespace ptsbe {
+namespace {
+
+enum : int8_t { SL_NONE = 0, SL_ZERO = 1, SL_PREFIX = 2 };
+
+struct NetTensor {
+  int gate = 0, conj = 0, nlegs = 0, col = 0, time = 0;
+  int label[4] = {-1, -1, -1, -1};
+  int8_t slice[4] = {0, 0, 0, 0};
+  int sq[4] = {0, 0, 0, 0};
+  int weight[4] = {0, 0, 0, 0};
+};
+
+struct KetNet {
+  std::vector<std::array<int, 2>> in_label, out_label;  // per gate, per qubit slot
+  std::vector<int> final_label, last_gate;
+  int n_labels = 0;
+};
+
+KetNet build_ket(const Plan& p) {
+  KetNet k;
+  k.in_label.assign(p.G, {-1, -1});
+  k.out_label.assign(p.G, {-1, -1});
+  std::vector<int> wire(p.n, -1);
+  k.last_gate.assign(p.n, -1);
+  int next = 0;
+  for (int g = 0; g < p.G; ++g) {
+    for (int a = 0; a < p.arity[g]; ++a) {
+      int q = p.qubits[g][a];
+      k.in_label[g][a] = wire[q];
+      k.out_label[g][a] = next++;
+      wire[q] = k.out_label[g][a];
+      k.last_gate[q] = g;
+    }
+  }
+  k.final_label = wire;
+  k.n_labels = next;
+  return k;
+}
+
+// Simulate absorbing `order` into a running tensor; keep_open labels survive.
+bool simulate(const std::vector<const NetTensor*>& order, const std::set<int>& keep_open,
+              PartPlan& out, std::string& err) {
+  std::map<int, int> cnt;
+  for (const NetTensor* t : order)
+    for (int i = 0; i < t->nlegs; ++i)
+      if (t->label[i] >= 0) cnt[t->label[i]]++;
+  std::vector<int> cur;
+  out.steps.clear();
+  out.peak = 0;
+  out.flops = out.bytes = 0;
+  for (const NetTensor* t : order) {
+    AbsorbStep st{};
+    st.gate = t->gate;
+    st.conj = t->conj;
+    st.rA = (int)cur.size();
+    std::vector<std::pair<int, int>> K;   // (pos in A, weight)
+    std::vector<std::pair<int, int>> H;   // (label, weight)
+    std::vector<std::pair<int, int>> N;   // (label, weight)
+    for (int i = 0; i < t->nlegs; ++i) {
+      if (t->slice[i] == SL_ZERO) continue;
+      if (t->slice[i] == SL_PREFIX) {
+        if (st.nS >= kMaxSlices) { err = "too many sliced legs on one gate"; return false; }
+        st.sq[st.nS] = t->sq[i];
+        st.sw[st.nS] = t->weight[i];
+        st.nS++;
+        continue;
+      }
+      int L = t->label[i];
+      cnt[L]--;
+      auto it = std::find(cur.begin(), cur.end(), L);
+      if (it != cur.end()) {
+        int pos = (int)(it - cur.begin());
+        if (cnt[L] == 0 && !keep_open.count(L)) K.push_back({pos, t->weight[i]});
+        else H.push_back({L, t->weight[i]});
+      } else {
+        if (cnt[L] == 0 && !keep_open.count(L)) { err = "dangling label in network"; return false; }
+        N.push_back({L, t->weight[i]});
+      }
+    }
+    std::sort(K.begin(), K.end());
+    std::vector<int> kept;
+    {
+      std::vector<char> drop(cur.size(), 0);
+      for (auto& kk : K) drop[kk.first] = 1;
+      for (size_t i = 0; i < cur.size(); ++i)
+        if (!drop[i]) kept.push_back(cur[i]);
+    }
+    // C layout: new labels replace contracted ones in place (lowest first),
+    // surplus contracted positions are dropped, surplus new labels go on top.
+    std::vector<int> C = cur;
+    size_t nrep = std::min(K.size(), N.size());
+    for (size_t i = 0; i < nrep; ++i) C[K[i].first] = N[i].first;
+    if (K.size() > N.size()) {
+      std::vector<char> drop(C.size(), 0);
+      for (size_t i = nrep; i < K.size(); ++i) drop[K[i].first] = 1;
+      std::vector<int> c2;
+      for (size_t i = 0; i < C.size(); ++i)
+        if (!drop[i]) c2.push_back(C[i]);
+      C.swap(c2);
+    } else {
+      for (size_t i = nrep; i < N.size(); ++i) C.push_back(N[i].first);
+    }
+    st.nK = (int)K.size();
+    for (int i = 0; i < st.nK; ++i) { st.kpos[i] = K[i].first; st.kw[i] = K[i].second; }
+    std::map<int, int> wN;
+    for (auto& nn : N) wN[nn.first] = nn.second;
+    std::vector<std::pair<int, int>> npos;
+    for (size_t i = 0; i < C.size(); ++i)
+      if (wN.count(C[i])) npos.push_back({(int)i, wN[C[i]]});
+    std::sort(npos.begin(), npos.end());
+    st.nN = (int)npos.size();
+    for (int i = 0; i < st.nN; ++i) { st.npos[i] = npos[i].first; st.nw[i] = npos[i].second; }
+    st.nH = (int)H.size();
+    for (int i = 0; i < st.nH; ++i) {
+      auto it = std::find(kept.begin(), kept.end(), H[i].first);
+      st.hm[i] = (int)(it - kept.begin());
+      st.hw[i] = H[i].second;
+    }
+    // sanity: C without the new positions equals kept
+    {
+      std::vector<int> chk;
+      std::set<int> np;
+      for (int i = 0; i < st.nN; ++i) np.insert(st.npos[i]);
+      for (size_t i = 0; i < C.size(); ++i)
+        if (!np.count((int)i)) chk.push_back(C[i]);
+      if (chk != kept) { err = "internal layout error"; return false; }
+    }
+    st.rC = (int)C.size();
+    if (st.rC > 40 || st.rA > 40) { err = "intermediate too large"; return false; }
+    out.peak = std::max(out.peak, std::max(st.rA, st.rC));
+    double m = std::ldexp(1.0, st.rC - st.nN);
+    out.flops += 8.0 * m * std::ldexp(1.0, st.nN + st.nK);
+    out.bytes += 8.0 * (std::ldexp(1.0, st.rA) + std::ldexp(1.0, st.rC));
+    out.steps.push_back(st);
+    cur = C;
+  }
+  for (int L : cur)
+    if (!keep_open.count(L)) { err = "label left open"; return false; }
+  out.labels = cur;
+  out.cost = out.bytes + out.flops / 16.0;
+  return true;
+}
+
+std::vector<const NetTensor*> sorted_order(const std::vector<NetTensor>& ts, int colsign, int timesign,
+                                           bool time_major) {
+  std::vector<const NetTensor*> o;
+  for (auto& t : ts) o.push_back(&t);
+  std::stable_sort(o.begin(), o.end(), [&](const NetTensor* a, const NetTensor* b) {
+    if (time_major) {
+      if (a->time != b->time) return timesign * a->time < timesign * b->time;
+      if (a->col != b->col) return colsign * a->col < colsign * b->col;
+      return a->conj < b->conj;
+    }
+    if (a->col != b->col) return colsign * a->col < colsign * b->col;
+    if (a->time != b->time) return timesign * a->time < timesign * b->time;
+    return a->conj < b->conj;
+  });
+  return o;
+}
+
+// Randomised greedy sweep: repeatedly absorb the tensor that gives the smallest
+// running rank (ties: most contracted legs, then random).
+std::vector<const NetTensor*> greedy_order(const std::vector<NetTensor>& ts, const std::set<int>& keep_open,
+                                           std::mt19937_64& rng) {
+  std::map<int, int> cnt;
+  for (auto& t : ts)
+    for (int i = 0; i < t.nlegs; ++i)
+      if (t.label[i] >= 0) cnt[t.label[i]]++;
+  std::set<int> cur;
+  std::vector<char> used(ts.size(), 0);
+  std::vector<const NetTensor*> order;
+  std::uniform_real_distribution<double> U(0.0, 1.0);
+  for (size_t step = 0; step < ts.size(); ++step) {
+    double best = 1e300;
+    int bi = -1;
+    for (size_t i = 0; i < ts.size(); ++i) {
+      if (used[i]) continue;
+      const NetTensor& t = ts[i];
+      int delta = 0, kk = 0;
+      bool touches = cur.empty();
+      for (int l = 0; l < t.nlegs; ++l) {
+        int L = t.label[l];
+        if (L < 0) continue;
+        if (cur.count(L)) {
+          touches = true;
+          if (cnt[L] == 1 && !keep_open.count(L)) { delta--; kk++; }
+        } else {
+          delta++;
+        }
+      }
+      double score = (double)(cur.size() + delta) * 4.0 - kk + (touches ? 0.0 : 100.0) + U(rng) * 0.9;
+      if (score < best) { best = score; bi = (int)i; }
+    }
+    used[bi] = 1;
+    const NetTensor& t = ts[bi];
+    order.push_back(&t);
+    for (int l = 0; l < t.nlegs; ++l) {
+      int L = t.label[l];
+      if (L < 0) continue;
+      cnt[L]--;
+      if (cur.count(L)) {
+        if (cnt[L] == 0 && !keep_open.count(L)) cur.erase(L);
+      } else {
+        cur.insert(L);
+      }
+    }
+  }
+  return order;
+}
+
+bool plan_part(const std::vector<NetTensor>& ts, const std::set<int>& keep_open, int hypersamples,
+               uint64_t seed, PartPlan& best, std::string& err) {
+  best = PartPlan();
+  best.cost = 1e300;
+  if (ts.empty()) {
+    best.cost = 0;
+    best.order_name = "empty";
+    return true;
+  }
+  struct Cand { const char* name; int cs, tsg; bool tm; };
+  const Cand cands[] = {{"col+time+", 1, 1, false}, {"col+time-", 1, -1, false},
+                        {"col-time+", -1, 1, false}, {"col-time-", -1, -1, false},
+                        {"time+", 1, 1, true},       {"time-", 1, -1, true}};
+  bool any = false;
+  std::string last_err;
+  for (const Cand& c : cands) {
+    PartPlan pp;
+    std::string e;
+    if (!simulate(sorted_order(ts, c.cs, c.tsg, c.tm), keep_open, pp, e)) { last_err = e; continue; }
+    pp.order_name = c.name;
+    if (pp.cost < best.cost) best = pp;
+    any = true;
+  }
+  std::mt19937_64 rng(seed);
+  for (int h = 0; h < hypersamples; ++h) {
+    PartPlan pp;
+    std::string e;
+    if (!simulate(greedy_order(ts, keep_open, rng), keep_open, pp, e)) { last_err = e; continue; }
+    pp.order_name = "greedy";
+    if (pp.cost < best.cost) best = pp;
+    any = true;
+  }
+  if (!any) { err = "no feasible sweep: " + last_err; return false; }
+  return true;
+}
+
+SplitTable make_table(const std::vector<int>& group, const std::vector<int>& labels, int64_t unit = 1) {
+  // offset of group index g = sum over set bits i of g of (unit << position of group[i])
+  SplitTable t;
+  t.bits = (int)group.size();
+  t.lo_bits = std::min(t.bits, 12);
+  std::vector<int64_t> w(group.size());
+  for (size_t i = 0; i < group.size(); ++i) {
+    auto it = std::find(labels.begin(), labels.end(), group[i]);
+    w[i] = unit << (int)(it - labels.begin());
+  }
+  int hb = t.bits - t.lo_bits;
+  t.lo.assign((size_t)1 << t.lo_bits, 0);
+  t.hi.assign((size_t)1 << hb, 0);
+  for (size_t g = 0; g < t.lo.size(); ++g)
+    for (int i = 0; i < t.lo_bits; ++i)
+      if ((g >> i) & 1) t.lo[g] += w[i];
+  for (size_t g = 0; g < t.hi.size(); ++g)
+    for (int i = 0; i < hb; ++i)
+      if ((g >> i) & 1) t.hi[g] += w[t.lo_bits + i];
+  return t;
+}
+
+SplitTable make_out_table(const std::vector<int>& group, const std::vector<int>& group_qubit, int start) {
+  SplitTable t;
+  t.bits = (int)group.size();
+  t.lo_bits = std::min(t.bits, 12);
+  int hb = t.bits - t.lo_bits;
+  t.lo.assign((size_t)1 << t.lo_bits, 0);
+  t.hi.assign((size_t)1 << hb, 0);
+  for (size_t g = 0; g < t.lo.size(); ++g)
+    for (int i = 0; i < t.lo_bits; ++i)
+      if ((g >> i) & 1) t.lo[g] += (int64_t)1 << (group_qubit[i] - start);
+  for (size_t g = 0; g < t.hi.size(); ++g)
+    for (int i = 0; i < hb; ++i)
+      if ((g >> i) & 1) t.hi[g] += (int64_t)1 << (group_qubit[t.lo_bits + i] - start);
+  return t;
+}
+
+}  // namespace
+
+bool build_batch_plans(Plan& p, std::string& err) {
+  KetNet k = build_ket(p);
+  const int NL = k.n_labels;
+  int f = (int)p.batch_sizes.size();
+  p.batches.clear();
+  int start = 0;
+  for (int j = 0; j < f; ++j) {
+    BatchPlan bp;
+    bp.start = start;
+    bp.size = p.batch_sizes[j];
+    bp.doubled = (j < f - 1);
+    const int a = start, e = start + bp.size;
+    auto cls = [&](int q) { return q < a ? 0 : (q < e ? 1 : 2); };  // prefix/batch/rest
+    std::vector<int> final_of(NL, -1);  // label -> qubit whose final output it is
+    for (int q = 0; q < p.n; ++q) final_of[k.final_label[q]] = q;
+    auto bra_label = [&](int L) {
+      int q = final_of[L];
+      if (q >= 0 && cls(q) != 0) return L;   // batch / rest outputs are shared
+      return L + NL;
+    };
+    std::vector<NetTensor> left, right;
+    for (int g = 0; g < p.G; ++g) {
+      bool is_left = false;
+      for (int s = 0; s < p.arity[g]; ++s) is_left |= cls(p.qubits[g][s]) == 0;
+      for (int side = 0; side < (bp.doubled ? 2 : 1); ++side) {
+        if (is_left && side == 1) continue;  // bra of the left part = conj(V)
+        NetTensor t;
+        t.gate = g;
+        t.conj = side;
+        t.time = g;
+        t.col = std::max(p.qubits[g][0], p.arity[g] == 2 ? p.qubits[g][1] : -1);
+        int ar = p.arity[g];
+        t.nlegs = 2 * ar;
+        // legs: outputs then inputs, first listed qubit is the high index bit
+        for (int s = 0; s < ar; ++s) {
+          int wout = ar == 2 ? (s == 0 ? 8 : 4) : 2;
+          int win = ar == 2 ? (s == 0 ? 2 : 1) : 1;
+          int Lo = k.out_label[g][s], Li = k.in_label[g][s];
+          // output leg
+          int qo = final_of[Lo];
+          if (qo >= 0 && cls(qo) == 0) {
+            t.slice[s] = SL_PREFIX;
+            t.sq[s] = qo;
+            t.label[s] = -1;
+          } else {
+            t.label[s] = side ? bra_label(Lo) : Lo;
+          }
+          t.weight[s] = wout;
+          // input leg
+          if (Li < 0) {
+            t.slice[ar + s] = SL_ZERO;
+            t.label[ar + s] = -1;
+          } else {
+            t.label[ar + s] = side ? bra_label(Li) : Li;
+          }
+          t.weight[ar + s] = win;
+        }
+        (is_left ? left : right).push_back(t);
+      }
+    }
+    // label groups
+    std::set<int> left_labels, right_labels;
+    for (auto& t : left)
+      for (int i = 0; i < t.nlegs; ++i)
+        if (t.label[i] >= 0) left_labels.insert(t.label[i]);
+    for (auto& t : right)
+      for (int i = 0; i < t.nlegs; ++i)
+        if (t.label[i] >= 0) right_labels.insert(t.label[i]);
+    std::vector<int> xb_q, xT_q;
+    for (int q = a; q < e; ++q) {
+      int L = k.final_label[q];
+      if (left_labels.count(L)) { bp.xb.push_back(L); xb_q.push_back(q); }
+      else { bp.xT.push_back(L); xT_q.push_back(q); }
+    }
+    if (bp.doubled) {
+      for (int q = e; q < p.n; ++q)
+        if (left_labels.count(k.final_label[q])) {
+          err = "unsupported network: a later qubit's output lies on a gate that touches the prefix";
+          return false;
+        }
+    }
+    for (int L : left_labels)
+      if (L < NL && right_labels.count(L) && final_of[L] < 0) bp.lk.push_back(L);
+    for (int L : bp.lk) bp.lb.push_back(L + NL);
+    std::set<int> keep_left(bp.lk.begin(), bp.lk.end());
+    keep_left.insert(bp.xb.begin(), bp.xb.end());
+    std::set<int> keep_right(bp.lk.begin(), bp.lk.end());
+    keep_right.insert(bp.xT.begin(), bp.xT.end());
+    if (bp.doubled) keep_right.insert(bp.lb.begin(), bp.lb.end());
+    std::string e1;
+    if (!plan_part(left, keep_left, p.hypersamples, p.path_seed * 1315423911ULL + 2 * j + 1, bp.left, e1)) {
+      err = "batch " + std::to_string(j) + " left part: " + e1;
+      return false;
+    }
+    if (!plan_part(right, keep_right, p.hypersamples, p.path_seed * 1315423911ULL + 2 * j + 2, bp.right, e1)) {
+      err = "batch " + std::to_string(j) + " right part: " + e1;
+      return false;
+    }
+    if ((int)bp.lk.size() > 12) {
+      err = "batch " + std::to_string(j) + ": " + std::to_string(bp.lk.size()) +
+            " wires cross between the prefix part and the rest (limit 12)";
+      return false;
+    }
+    // join tables
+    bp.v_row = make_table(bp.xb, bp.left.labels);
+    bp.v_col = make_table(bp.lk, bp.left.labels);
+    bp.t_x = make_table(bp.xT, bp.right.labels);
+    bp.t_k = make_table(bp.lk, bp.right.labels);
+    bp.t_b = make_table(bp.doubled ? bp.lb : std::vector<int>(), bp.right.labels);
+    bp.o_x = make_out_table(bp.xT, xT_q, a);
+    bp.o_b = make_out_table(bp.xb, xb_q, a);
+    double rows = std::ldexp(1.0, (int)bp.xb.size());
+    double K = std::ldexp(1.0, (int)bp.lk.size());
+    double X = std::ldexp(1.0, (int)bp.xT.size());
+    bp.join_flops_per_elem = bp.doubled ? rows * X * (8.0 * K * K + 8.0 * K) : rows * X * 8.0 * K;
+    p.batches.push_back(bp);
+    start = e;
+  }
+  return true;
+}
+
+}  // namespace ptsbe

@@ -1,0 +1,307 @@
+"""GPU parity of the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances: amplitudes 1e-5 L2-relative per element, marginals 1e-6 absolute on
+the normalised conditionals, shots identical except CDF-boundary flips (their
+exact per-draw probability is computed from both marginals), trajectory weights
+1e-6 relative."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import sampling, tn
+from oracle import statevector as sv
+from tests.gpu_helpers import (assert_shot_parity, flip_probability, oracle_shots_sv, oracle_states,
+                               prefix_words, shots_to_ints, to_dev, torch_dev)
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _plan(circuit, bs, **kw):
+    import paper_2604_08467_amd as P
+    return P.Plan(circuit, bs, **kw)
+
+
+def _contract(plan, torch, dev, kraus_d, traj, prefixes, j, amp=False):
+    import paper_2604_08467_amd as P
+    et = to_dev(torch, dev, np.asarray(traj, dtype=np.int32))
+    ep = to_dev(torch, dev, prefix_words(prefixes, plan.n_words))
+    out, tot = plan.contract_batch(j, kraus_d, et, ep, P.OUT_AMPLITUDE if amp else P.OUT_POPULATION)
+    torch.cuda.synchronize()
+    return out.cpu().numpy(), (None if tot is None else tot.cpu().numpy())
+
+
+# ------------------------------------------------------------------ config 1
+def test_config1_amplitudes_populations_and_weights():
+    torch, dev = torch_dev()
+    wl = W.config1()
+    c = wl.circuit
+    _say("config1: plan + PTS")
+    plan = _plan(c, wl.batch_sizes)
+    kr, mult, lq, nd = plan.sample_trajectories(wl.pts_seed, wl.n_traj)
+    E = len(kr)
+    kd = to_dev(torch, dev, kr)
+    psis = oracle_states(c, kr)
+    amp, _ = _contract(plan, torch, dev, kd, range(E), [0] * E, 0, amp=True)
+    pop, tot = _contract(plan, torch, dev, kd, range(E), [0] * E, 0)
+    for i in range(E):
+        ref = psis[i]
+        rel = np.linalg.norm(amp[i] - ref) / np.linalg.norm(ref)
+        assert rel <= 1e-5, (i, rel)
+        pref = np.abs(ref) ** 2
+        assert np.abs(pop[i] - pref).max() <= 1e-6, i
+        Z = np.vdot(ref, ref).real
+        assert abs(tot[i] - Z) <= 1e-6 * Z
+    _say("config1: amplitudes/populations ok")
+
+
+def test_config1_shots_match_oracle_sampler():
+    torch, dev = torch_dev()
+    wl = W.config1()
+    c = wl.circuit
+    plan = _plan(c, wl.batch_sizes)
+    kr, mult, lq, nd = plan.sample_trajectories(wl.pts_seed, wl.n_traj)
+    E, m = len(kr), wl.shots_per_traj
+    kd = to_dev(torch, dev, kr)
+    md = to_dev(torch, dev, np.full(E, m, dtype=np.int64))
+    multd = to_dev(torch, dev, mult)
+    out = plan.sample_shots(kd, md, wl.shot_seed, mult_dev=multd)
+    torch.cuda.synchronize()
+    shots = shots_to_ints(out["shots"].cpu().numpy())
+    straj = out["shot_traj"].cpu().numpy()
+    assert np.array_equal(straj, np.repeat(np.arange(E), m))
+    psis = oracle_states(c, kr)
+    ref, _ = oracle_shots_sv(c, psis, wl.batch_sizes, m, wl.shot_seed)
+    pop, _ = _contract(plan, torch, dev, kd, range(E), [0] * E, 0)
+    mism, expect = 0, 0.0
+    for i in range(E):
+        got = shots[i * m:(i + 1) * m]
+        mism += sum(1 for a, b in zip(got, ref[i]) if a != b)
+        expect += m * flip_probability(pop[i], np.abs(psis[i]) ** 2)
+    _say(f"config1 shots: {mism} mismatches of {E * m}, expected flips {expect:.3g}")
+    assert_shot_parity(mism, expect, E * m)
+    # weights: W_i = mult_i Z_i / sum mult Z (Pauli noise: Z_i = 1 up to gate rounding)
+    Z = np.array([np.vdot(p, p).real for p in psis])
+    wref = sampling.trajectory_weights(Z, mult)
+    np.testing.assert_allclose(out["weights"].cpu().numpy(), wref, rtol=1e-6)
+    np.testing.assert_allclose(out["norms"].cpu().numpy(), Z, rtol=1e-6)
+    assert list(out["elements_per_batch"]) == [E]
+
+
+def test_config1_pooled_shots_tvd():
+    """Pooled shots vs the weighted mean of the per-trajectory oracle distributions."""
+    torch, dev = torch_dev()
+    wl = W.config1()
+    c = wl.circuit
+    plan = _plan(c, wl.batch_sizes)
+    kr, mult, _, _ = plan.sample_trajectories(wl.pts_seed, wl.n_traj)
+    E, m = len(kr), wl.shots_per_traj
+    out = plan.sample_shots(to_dev(torch, dev, kr), to_dev(torch, dev, np.full(E, m, dtype=np.int64)),
+                            wl.shot_seed)
+    shots = np.array(shots_to_ints(out["shots"].cpu().numpy()))
+    pbar = np.mean([np.abs(p) ** 2 for p in oracle_states(c, kr)], axis=0)
+    M = E * m
+    hist = np.bincount(shots, minlength=1024) / M
+    tvd = 0.5 * np.abs(hist - pbar).sum()
+    bound = 0.5 * math.sqrt(1024 / M) + math.sqrt(math.log(1e9) / (2 * M))
+    assert tvd <= bound, (tvd, bound)
+    for q in range(10):
+        p1 = np.mean((shots >> q) & 1)
+        ref = sum(pbar[x] for x in range(1024) if (x >> q) & 1)
+        assert abs(p1 - ref) <= 0.5 * math.sqrt(2 / M) * 2 + math.sqrt(math.log(1e9) / (2 * M))
+
+
+# ------------------------------------------------- multi-batch small circuits
+def _small_cases():
+    rng = np.random.default_rng(77)
+    cases = []
+    c = W.random_brickwork(12, 5, rng, 0.05)
+    cases.append(("bw12", c, [4, 4, 4]))
+    c = W.small_random_circuit(14, 40, rng, [W.depolarizing(0.1), W.amplitude_damping(0.2), W.depolarizing2(0.05)],
+                               site_prob=0.6)
+    cases.append(("rand14_ad", c, [3, 5, 6]))
+    c = W.random_brickwork(16, 6, rng, 0.02, layout="2d")
+    cases.append(("grid16", c, [5, 5, 6]))
+    c = W.random_brickwork(13, 4, rng, 0.05)
+    cases.append(("bw13_uneven", c, [1, 6, 2, 4]))
+    return cases
+
+
+@pytest.mark.parametrize("case", range(4))
+def test_small_multibatch_marginals(case):
+    torch, dev = torch_dev()
+    name, c, bs = _small_cases()[case]
+    _say(f"{name}: marginals b={bs}")
+    plan = _plan(c, bs)
+    kr, mult, _, _ = plan.sample_trajectories(11 + case, 8)
+    kd = to_dev(torch, dev, kr)
+    psis = oracle_states(c, kr)
+    n = c.n_qubits
+    starts = sampling.batch_starts(bs)
+    rng = np.random.default_rng(case)
+    for j, (a, b) in enumerate(zip(starts, bs)):
+        traj = np.sort(rng.integers(0, len(kr), size=12))
+        pre = [int(rng.integers(0, 2 ** a)) if a else 0 for _ in traj]
+        pop, tot = _contract(plan, torch, dev, kd, traj, pre, j)
+        for e, (i, p) in enumerate(zip(traj, pre)):
+            ref = sampling.marginal_from_state(psis[i], n, a, b, p)
+            Z = ref.sum()
+            scale = max(Z, 1e-30)
+            assert np.abs(pop[e] - ref).max() <= 1e-6 * scale + 1e-12, (name, j, e)
+            assert abs(tot[e] - Z) <= 1e-5 * scale + 1e-12
+        if j == len(bs) - 1:
+            amp, _ = _contract(plan, torch, dev, kd, traj, pre, j, amp=True)
+            for e, (i, p) in enumerate(zip(traj, pre)):
+                ref = sampling.amplitudes_from_state(psis[i], n, a, b, p)
+                nr = np.linalg.norm(ref)
+                if nr > 1e-12:
+                    assert np.linalg.norm(amp[e] - ref) / nr <= 1e-5, (name, e)
+
+
+@pytest.mark.parametrize("case", range(4))
+def test_small_multibatch_shots(case):
+    torch, dev = torch_dev()
+    name, c, bs = _small_cases()[case]
+    _say(f"{name}: NBS shots b={bs}")
+    plan = _plan(c, bs)
+    kr, mult, _, _ = plan.sample_trajectories(11 + case, 8)
+    E, m = len(kr), 300
+    kd = to_dev(torch, dev, kr)
+    out = plan.sample_shots(kd, to_dev(torch, dev, np.full(E, m, dtype=np.int64)), 1234 + case,
+                            mult_dev=to_dev(torch, dev, mult))
+    shots = shots_to_ints(out["shots"].cpu().numpy())
+    psis = oracle_states(c, kr)
+    ref, distinct = oracle_shots_sv(c, psis, bs, m, 1234 + case)
+    n = c.n_qubits
+    starts = sampling.batch_starts(bs)
+    mism = 0
+    expect = 0.0
+    for i in range(E):
+        got = shots[i * m:(i + 1) * m]
+        for t in range(m):
+            if got[t] != ref[i][t]:
+                mism += 1
+        # expected flips: every batch of every oracle shot, from the GPU marginals
+        prefixes = {}
+        for t in range(m):
+            for j in range(len(bs)):
+                p = ref[i][t] & ((1 << starts[j]) - 1)
+                prefixes[(j, p)] = prefixes.get((j, p), 0) + 1
+        for (j, p), cnt in prefixes.items():
+            g, _ = _contract(plan, torch, dev, kd, [i], [p], j)
+            expect += cnt * flip_probability(g[0], sampling.marginal_from_state(psis[i], n, starts[j], bs[j], p))
+    _say(f"{name}: {mism} mismatches / {E * m}, expected {expect:.3g}")
+    assert_shot_parity(mism, expect, E * m)
+    Z = np.array([np.vdot(p, p).real for p in psis])
+    np.testing.assert_allclose(out["norms"].cpu().numpy(), Z, rtol=1e-5)
+    np.testing.assert_allclose(out["weights"].cpu().numpy(), sampling.trajectory_weights(Z, mult), rtol=1e-5)
+    if mism == 0:
+        got_distinct = list(out["elements_per_batch"])
+        want = [E] + [sum(d[j] for d in distinct) for j in range(1, len(bs))]
+        assert got_distinct == want
+
+
+# ------------------------------------------------------------------ config 2
+def test_config2_sampled_marginals_vs_tensor_network_oracle():
+    torch, dev = torch_dev()
+    wl = W.config2()
+    c = wl.circuit
+    _say("config2: plan + PTS(64)")
+    plan = _plan(c, wl.batch_sizes)
+    kr, mult, _, _ = plan.sample_trajectories(wl.pts_seed, 64)
+    kd = to_dev(torch, dev, kr)
+    # realistic prefixes: from a short GPU sampling run on trajectories 0..3
+    out = plan.sample_shots(kd[:4].contiguous(), to_dev(torch, dev, np.full(4, 4, dtype=np.int64)), 7)
+    shots = shots_to_ints(out["shots"].cpu().numpy())
+    starts = sampling.batch_starts(wl.batch_sizes)
+    checks = [(0, 0, 0), (1, 0, 0)]
+    for j in range(1, 5):
+        r = (j * 5) % len(shots)
+        checks.append((j, r // 4, shots[r] & ((1 << starts[j]) - 1)))
+    for (j, i, p) in checks:
+        kind = "ket" if j == 4 else "doubled"
+        ref = tn.batch_network_value(c, kr[i], starts[j], 10, p, kind)
+        if kind == "ket":
+            amp, _ = _contract(plan, torch, dev, kd, [i], [p], j, amp=True)
+            rel = np.linalg.norm(amp[0] - ref) / np.linalg.norm(ref)
+            _say(f"config2 j={j} traj={i}: amplitude rel err {rel:.3g}")
+            assert rel <= 1e-5
+            ref = np.abs(ref) ** 2
+        pop, tot = _contract(plan, torch, dev, kd, [i], [p], j)
+        Z = ref.sum()
+        err = np.abs(pop[0] / tot[0] - ref / Z).max()
+        _say(f"config2 j={j} traj={i}: conditional max abs err {err:.3g}, Z rel {abs(tot[0] - Z) / Z:.3g}")
+        assert err <= 1e-6
+        assert abs(tot[0] - Z) <= 1e-5 * Z
+
+
+def test_config2_shots_of_one_trajectory_vs_oracle():
+    torch, dev = torch_dev()
+    wl = W.config2()
+    c = wl.circuit
+    plan = _plan(c, wl.batch_sizes)
+    kr, mult, _, _ = plan.sample_trajectories(wl.pts_seed, 8)
+    i, m = 5, 6
+    kd = to_dev(torch, dev, kr)
+    md = np.zeros(len(kr), dtype=np.int64)
+    md[i] = m
+    out = plan.sample_shots(kd, to_dev(torch, dev, md), wl.shot_seed)
+    got = shots_to_ints(out["shots"].cpu().numpy())
+    starts = sampling.batch_starts(wl.batch_sizes)
+
+    def mfn(j, prefix):
+        return tn.batch_network_value(c, kr[i], starts[j], 10, prefix, "ket" if j == 4 else "doubled")
+
+    ref, _ = sampling.sample_trajectory(
+        lambda j, p: np.abs(mfn(j, p)) ** 2 if j == 4 else mfn(j, p), i, 50, wl.batch_sizes, m, wl.shot_seed)
+    mism = sum(1 for a, b in zip(got, ref) if a != b)
+    _say(f"config2 traj {i}: {mism} mismatches of {m}")
+    assert mism <= 1
+
+
+def test_config2_full_size_properties():
+    """512 trajectories x 1000 shots at full circuit size: deterministic shots,
+    unit Pauli norms, normalised weights, and the chain rule Z(child) = pi_parent(x)."""
+    torch, dev = torch_dev()
+    wl = W.config2()
+    c = wl.circuit
+    plan = _plan(c, wl.batch_sizes)
+    kr, mult, _, _ = plan.sample_trajectories(wl.pts_seed, 512)
+    E, m = len(kr), 1000
+    kd = to_dev(torch, dev, kr)
+    md = to_dev(torch, dev, np.full(E, m, dtype=np.int64))
+    ws = torch.empty(8 << 30, dtype=torch.uint8, device=dev)
+    o1 = plan.sample_shots(kd, md, wl.shot_seed, mult_dev=to_dev(torch, dev, mult), workspace=ws)
+    s1 = o1["shots"].clone()
+    o2 = plan.sample_shots(kd, md, wl.shot_seed, mult_dev=to_dev(torch, dev, mult), workspace=ws)
+    assert torch.equal(s1, o2["shots"])
+    norms = o1["norms"].cpu().numpy()
+    assert np.abs(norms - 1).max() < 2e-4
+    w = o1["weights"].cpu().numpy()
+    assert abs(w.sum() - 1) < 1e-12
+    epb = list(o1["elements_per_batch"])
+    _say(f"config2 512x1000 elements per batch {epb}")
+    assert epb[0] == E and all(epb[j] <= E * m for j in range(5))
+    # chain rule on a few (parent, child) pairs
+    shots = shots_to_ints(s1[:2000].cpu().numpy())
+    starts = sampling.batch_starts(wl.batch_sizes)
+    for j in range(1, 4):
+        traj, pre, chil = [], [], []
+        for r in range(0, 2000, 250):
+            traj.append(r // m)
+            pre.append(shots[r] & ((1 << starts[j]) - 1))
+            chil.append(shots[r] & ((1 << starts[j + 1]) - 1))
+        pop, tot = _contract(plan, torch, dev, kd, traj, pre, j)
+        _, tchild = _contract(plan, torch, dev, kd, traj, chil, j + 1) if j + 1 < 4 else (None, None)
+        if tchild is None:
+            continue
+        for e in range(len(traj)):
+            x = (chil[e] >> starts[j]) & 1023
+            assert abs(tchild[e] - pop[e][x]) <= 1e-4 * pop[e][x] + 1e-30

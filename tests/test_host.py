@@ -1,0 +1,134 @@
+"""CPU tests of the C-ABI library's host side: it loads, exports every declared
+symbol, plans (host-only plans, no GPU calls), pre-samples trajectories exactly
+like the oracle, and rejects bad input with the documented status codes."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import pts as opts_pts
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    import paper_2604_08467_amd as P
+    return P
+
+
+def test_library_exports_every_declared_symbol():
+    import ctypes
+    P = _lib()
+    lib = P.load_library()
+    header = open(os.path.join(ROOT, "include", "ptsbe.h")).read()
+    names = set(re.findall(r"\b(ptsbe_[a-z_]+)\s*\(", header))
+    assert len(names) >= 12
+    for n in sorted(names):
+        assert hasattr(lib, n), n
+        assert ctypes.cast(getattr(lib, n), ctypes.c_void_p).value
+
+
+@pytest.mark.parametrize("make", [W.config1, W.config2])
+def test_host_plan_shapes(make):
+    P = _lib()
+    wl = make()
+    plan = P.Plan(wl.circuit, wl.batch_sizes, hypersamples=4, device=-1)
+    f = len(wl.batch_sizes)
+    n_gate_tensors = wl.circuit.n_gates
+    for j in range(f):
+        bi = plan.batch_info(j)
+        assert bi["start"] == sum(wl.batch_sizes[:j]) and bi["size"] == wl.batch_sizes[j]
+        assert bi["doubled"] == (j < f - 1)
+        # every ket gate is in exactly one part; bra copies only in the right part
+        n_left = bi["n_left_steps"]
+        n_right = bi["n_right_steps"]
+        if bi["doubled"]:
+            assert n_left + n_right // 2 == n_gate_tensors
+        else:
+            assert n_left + n_right == n_gate_tensors
+        if j == 0:
+            assert n_left == 0 and bi["crossing"] == 0
+        # the join output covers exactly the batch qubits
+        assert bi["right_rank"] == (bi["size"] - bi["join_rows_log2"]) + bi["crossing"] * (2 if bi["doubled"] else 1)
+        assert bi["left_rank"] == bi["join_rows_log2"] + bi["crossing"]
+
+
+def test_config2_path_is_the_expected_sweep():
+    """1D depth-6 brickwork: five wires cross between the prefix part and the rest,
+    the per-trajectory tensor is 2^9 x 2^5 x 2^5 and the join costs 8.65 MFLOP."""
+    P = _lib()
+    wl = W.config2()
+    plan = P.Plan(wl.circuit, wl.batch_sizes, hypersamples=4, device=-1)
+    for j in (1, 2, 3):
+        bi = plan.batch_info(j)
+        assert bi["crossing"] == 5 and bi["right_rank"] == 19 and bi["left_rank"] == 6
+        assert bi["join_flops_per_elem"] == 2 * 512 * (8 * 32 * 32 + 8 * 32)
+
+
+@pytest.mark.parametrize("which", ["config1", "config2", "ad_2q"])
+def test_host_pts_equals_oracle(which):
+    P = _lib()
+    if which == "config1":
+        c, seed, n = W.config1().circuit, 1002, 64
+    elif which == "config2":
+        c, seed, n = W.config2().circuit, 2002, 300
+    else:
+        rng = np.random.default_rng(5)
+        c = W.small_random_circuit(5, 12, rng, [W.depolarizing(0.2), W.amplitude_damping(0.3), W.depolarizing2(0.1)])
+        seed, n = 99, 200
+    bs = [c.n_qubits] if c.n_qubits <= 12 else [10] * (c.n_qubits // 10)
+    plan = P.Plan(c, bs, device=-1)
+    kr, mult, lq, nd = plan.sample_trajectories(seed, n)
+    kr2, mult2, lq2, nd2 = opts_pts.presample(c, seed, n)
+    assert nd == nd2
+    np.testing.assert_array_equal(kr, kr2)
+    np.testing.assert_array_equal(mult, mult2)
+    np.testing.assert_allclose(lq, lq2, rtol=0, atol=1e-12)
+
+
+def test_pts_max_draws_limit():
+    P = _lib()
+    c = W.config1().circuit
+    plan = P.Plan(c, [10], device=-1)
+    kr, mult, lq, nd = plan.sample_trajectories(1002, 64, max_draws=20)
+    assert nd == 20 and mult.sum() == 20 and len(kr) <= 20
+
+
+def _expect_status(code, fn):
+    P = _lib()
+    with pytest.raises(P.PtsbeError) as ei:
+        fn()
+    assert ei.value.status == code, str(ei.value)
+
+
+def test_error_codes():
+    P = _lib()
+    c = W.config1().circuit
+    _expect_status(1, lambda: P.Plan(c, [5, 4], device=-1))          # sizes do not sum to n
+    _expect_status(1, lambda: P.Plan(c, [0, 10], device=-1))
+    big = W.Circuit(40)
+    for q in range(39):
+        big.add_gate((q, q + 1), W.CNOT)
+    _expect_status(2, lambda: P.Plan(big, [31, 9], device=-1))       # b > 30
+    bad = W.Circuit(2)
+    g = bad.add_gate((0, 1), W.CNOT)
+    ch = bad.add_channel(W.Channel(np.stack([np.eye(2) * 0.9]), None))  # not trace preserving
+    bad.add_site(g, (0,), ch)
+    _expect_status(1, lambda: P.Plan(bad, [2], device=-1))
+    off = W.Circuit(3)
+    g = off.add_gate((0, 1), W.CNOT)
+    ch = off.add_channel(W.depolarizing(0.1))
+    off.add_site(g, (2,), ch)                                         # site qubit not on the gate
+    _expect_status(1, lambda: P.Plan(off, [3], device=-1))
+    _expect_status(3, lambda: P.Plan(c, [10], device=-1, device_budget_bytes=64))
+    _expect_status(2, lambda: P.Plan(c, [10], device=-1, precision=1))
+
+
+def test_untouched_qubit_gets_identity():
+    P = _lib()
+    c = W.Circuit(4)
+    c.add_gate((0, 1), W.CNOT)
+    plan = P.Plan(c, [2, 2], device=-1)
+    assert plan.n_gates == 3           # two identities added for qubits 2 and 3
