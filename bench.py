@@ -1,0 +1,140 @@
+"""Benchmark of the PTSBE hot path on one MI355X.
+
+Workload: 50-qubit open-chain brickwork, depth 6 (147 Haar SU(4) gates rounded to
+complex64), depolarising p=0.005 on both qubits after every gate (294 noise
+sites), 4096 unique trajectories x 1000 shots, batches of 10 qubits.  One step is
+one full non-degenerate batched sampling pass (all five batches: error injection,
+contraction, FP64 CDFs, inverse-CDF draws, prefix deduplication, trajectory
+weights) over all 4096 trajectories, inputs resident in HBM.  Path finding and
+trajectory pre-sampling happen before the timed region.
+
+Prints one JSON line (metric: sampled shots/s).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP32_MFMA_PEAK_TFLOPS = 157.3
+
+
+def cpu_baseline(wl, kr, budget_s=20.0):
+    """The FP64 oracle, as it stands, on a bounded sample: per-shot batch-wise
+    sampling of trajectory 0 with memoised explicit-network marginals."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import sampling, tn
+
+    c = wl.circuit
+    starts = sampling.batch_starts(wl.batch_sizes)
+    f = len(wl.batch_sizes)
+
+    def mfn(j, p):
+        kind = "ket" if j == f - 1 else "doubled"
+        v = tn.batch_network_value(c, kr[0], starts[j], wl.batch_sizes[j], p, kind)
+        return np.abs(v) ** 2 if kind == "ket" else v
+
+    shots = 0
+    t0 = time.perf_counter()
+    with threadpool_limits(limits=1):
+        m = 1
+        while True:
+            sampling.sample_trajectory(mfn, 0, c.n_qubits, wl.batch_sizes, m, wl.shot_seed)
+            shots += m
+            if time.perf_counter() - t0 > budget_s:
+                break
+    dt = time.perf_counter() - t0
+    return {"value": shots / dt, "unit": "shots/s", "cores": 1, "kind": "oracle",
+            "sample": f"{shots} shot(s) of trajectory 0 (per-shot batch-wise sampling, explicit FP64 "
+                      f"networks, {dt:.1f} s, one thread)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--traj", type=int, default=4096)
+    ap.add_argument("--shots", type=int, default=1000)
+    ap.add_argument("--workspace-gb", type=float, default=64.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "join_traffic.json"))
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the path shards over trajectories across GPUs by design, "
+              "but this build measures a single MI355X", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2604_08467_amd as P
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    wl = W.config2()
+    c = wl.circuit
+    plan = P.Plan(c, wl.batch_sizes, hypersamples=8)
+    kr, mult, _, n_draws = plan.sample_trajectories(wl.pts_seed, args.traj)
+    E = len(kr)
+    kd = torch.from_numpy(kr).to(dev)
+    md = torch.full((E,), args.shots, dtype=torch.int64, device=dev)
+    multd = torch.from_numpy(mult).to(dev)
+    M = E * args.shots
+    ws = torch.empty(int(args.workspace_gb * (1 << 30)), dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream(dev)
+
+    def step():
+        return plan.sample_shots(kd, md, wl.shot_seed, mult_dev=multd, workspace=ws, want_traj=True)
+
+    for _ in range(args.warmup):
+        out = step()
+    torch.cuda.synchronize()
+    plan.profile_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out = step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = plan.profile_read()
+    plan.profile_enable(False)
+    shots_per_s = M * args.steps / dt
+    epb = [int(x) for x in out["elements_per_batch"]]
+
+    join_s = prof["join_ms"] / 1e3
+    achieved = prof["join_flops"] / join_s / 1e12 if join_s > 0 else 0.0
+    traffic = None
+    if os.path.exists(args.traffic_json):
+        try:
+            traffic = json.load(open(args.traffic_json)).get("bytes_per_launch")
+        except Exception:
+            traffic = None
+    roofline = {"bound": "mfma", "achieved": achieved, "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / FP32_MFMA_PEAK_TFLOPS, "traffic": traffic,
+                "kernel": "join (prefix part x per-trajectory part, FP32)",
+                "launches": prof["join_launches"], "kernel_ms_per_step": prof["join_ms"] / args.steps}
+    line = {
+        "metric": "sampled shots/sec", "value": shots_per_s, "unit": "shots/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c64",
+        "data": "synthetic",
+        "config": {"workload": f"50-qubit 1D brickwork depth 6, Haar SU(4) c64, depolarising p=0.005, "
+                               f"{E} trajectories x {args.shots} shots, batches [10]*5, proportional NBS",
+                   "trajectories": E, "shots_per_traj": args.shots, "batch_sizes": wl.batch_sizes,
+                   "pts_draws": int(n_draws), "elements_per_batch": epb,
+                   "unique_bitstrings_last_step": int(torch.unique(out["shots"][:, 0]).numel())},
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(wl, kr)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -169,7 +169,8 @@ ptsbe_status_t run_batch(Plan& p, int j, const uint8_t* d_kraus, int64_t E, Batc
   HIP_TRY(hipMemcpyAsync(first.data(), d_first, (size_t)(E + 1) * 4, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   const int rT = (int)bp.right.labels.size(), rV = (int)bp.left.labels.size();
-  const size_t per_traj = ((size_t)8 << rT) + part_scratch_per_job(bp.right);
+  const bool use_qform = bp.doubled && ptsbe::qform_supported((int)bp.lk.size());
+  const size_t per_traj = ((size_t)8 << rT) * (use_qform ? 2 : 1) + part_scratch_per_job(bp.right);
   const size_t nb = (size_t)1 << bp.size;
   const size_t per_elem = ((size_t)8 << rV) + part_scratch_per_job(bp.left) + (io.sample ? 4 * nb : 0);
   const size_t avail = ar.left();
@@ -178,6 +179,7 @@ ptsbe_status_t run_batch(Plan& p, int j, const uint8_t* d_kraus, int64_t E, Batc
   if (t_cap < 1 || e_cap < 1)
     return fail(PTSBE_ERR_OUT_OF_MEMORY, "workspace too small for one trajectory of batch " + std::to_string(j));
   e_cap = std::min<int64_t>(e_cap, 1 << 22);
+  t_cap = std::min<int64_t>(t_cap, 65535);       // one grid dimension of the MFMA join
   const ptsbe::AbsorbStep* d_left = p.d_steps + p.part_step_off[2 * j];
   const ptsbe::AbsorbStep* d_right = p.d_steps + p.part_step_off[2 * j + 1];
   for (int64_t t0 = 0; t0 < E; t0 += t_cap) {
@@ -189,6 +191,13 @@ ptsbe_status_t run_batch(Plan& p, int j, const uint8_t* d_kraus, int64_t E, Batc
     if (!T) return fail(PTSBE_ERR_OUT_OF_MEMORY, "workspace too small (right part)");
     ptsbe_status_t st = run_part(p, bp.right, d_right, g, t1 - t0, nullptr, (int32_t)t0, nullptr, T, ar, s);
     if (st != PTSBE_OK) return st;
+    float2* Tc = nullptr;
+    if (use_qform) {   // canonical [x][k][k'] layout for the MFMA join
+      Tc = (float2*)ar.take((size_t)(t1 - t0) * ((size_t)8 << rT));
+      if (!Tc) return fail(PTSBE_ERR_OUT_OF_MEMORY, "workspace too small (join layout)");
+      HIP_TRY(ptsbe::launch_permute_T(T, (int64_t)1 << rT, t1 - t0, p.d_tables, p.join_dev[j], (int)bp.xT.size(),
+                                      (int)bp.lk.size(), Tc, s));
+    }
     for (int64_t a0 = e0; a0 < e1; a0 += e_cap) {
       const int64_t a1 = std::min<int64_t>(e1, a0 + e_cap), ne = a1 - a0;
       const size_t mark2 = ar.used;
@@ -217,7 +226,28 @@ ptsbe_status_t run_batch(Plan& p, int j, const uint8_t* d_kraus, int64_t E, Batc
         HIP_TRY(hipEventCreate(&ev.b));
         HIP_TRY(hipEventRecord(ev.a, s));
       }
-      HIP_TRY(ptsbe::launch_join(ja, s));
+      if (use_qform) {
+        ptsbe::QformArgs qa{};
+        qa.V = V; qa.v_stride = (int64_t)1 << rV; qa.v_base = a0;
+        qa.Tc = Tc; qa.traj_base = (int32_t)t0;
+        int64_t tA = t0, tB = t1 - 1;
+        while (tA + 1 < t1 && first[tA + 1] <= a0) ++tA;     // trajectory holding element a0
+        while (tB > tA && first[tB] >= a1) --tB;             // trajectory holding element a1-1
+        int64_t max_rows = 0;
+        for (int64_t t = tA; t <= tB; ++t) {
+          int64_t lo = std::max<int64_t>(first[t], a0), hi = std::min<int64_t>(first[t + 1], a1);
+          max_rows = std::max<int64_t>(max_rows, (hi - lo) << bp.xb.size());
+        }
+        qa.traj0 = (int32_t)tA;
+        qa.first = d_first; qa.e_lo = a0; qa.e_hi = a1;
+        qa.xb_bits = (int)bp.xb.size(); qa.lk_bits = (int)bp.lk.size(); qa.xT_bits = (int)bp.xT.size();
+        qa.b = bp.size; qa.tab = p.d_tables; qa.jd = p.join_dev[j];
+        qa.pop = ja.pop;
+        if (!qa.pop) return fail(PTSBE_ERR_INVALID_ARG, "population output required");
+        HIP_TRY(ptsbe::launch_qform(qa, (int)(tB - tA + 1), (int)max_rows, s));
+      } else {
+        HIP_TRY(ptsbe::launch_join(ja, s));
+      }
       if (p.profile) {
         HIP_TRY(hipEventRecord(ev.b, s));
         evs.push_back(ev);
@@ -250,8 +280,8 @@ ptsbe_status_t collect_events(Plan& p, std::vector<EventPair>& evs) {
     float ms = 0.f;
     HIP_TRY(hipEventElapsedTime(&ms, e.a, e.b));
     p.join_ms += ms;
-    hipEventDestroy(e.a);
-    hipEventDestroy(e.b);
+    (void)hipEventDestroy(e.a);
+    (void)hipEventDestroy(e.b);
   }
   evs.clear();
   return PTSBE_OK;
@@ -497,11 +527,11 @@ ptsbe_status_t ptsbe_plan(const ptsbe_circuit_t* c, const ptsbe_plan_opts_t* o, 
 void ptsbe_plan_destroy(ptsbe_plan_t plan) {
   Plan* p = reinterpret_cast<Plan*>(plan);
   if (!p) return;
-  if (p->d_gates) hipFree(p->d_gates);
-  if (p->d_gate_site_list) hipFree(p->d_gate_site_list);
-  if (p->d_site_ops) hipFree(p->d_site_ops);
-  if (p->d_steps) hipFree(p->d_steps);
-  if (p->d_tables) hipFree(p->d_tables);
+  if (p->d_gates) (void)hipFree(p->d_gates);
+  if (p->d_gate_site_list) (void)hipFree(p->d_gate_site_list);
+  if (p->d_site_ops) (void)hipFree(p->d_site_ops);
+  if (p->d_steps) (void)hipFree(p->d_steps);
+  if (p->d_tables) (void)hipFree(p->d_tables);
   delete p;
 }
 

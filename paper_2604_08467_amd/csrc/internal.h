@@ -143,6 +143,22 @@ struct JoinArgs {
   float2* amp;                           // [n_elems][2^b] (amplitude out) or null
 };
 hipError_t launch_join(const JoinArgs& a, hipStream_t stream);
+struct QformArgs {
+  const float2* V; int64_t v_stride; int64_t v_base;   // V rows of elements [v_base, ...)
+  const float2* Tc;                                     // canonical [traj][x][k][k']
+  int32_t traj_base;                                    // Tc index = traj - traj_base
+  int32_t traj0;                                        // trajectory of grid.y == 0
+  const int32_t* first;                                 // [E+1] first element of each trajectory
+  int64_t e_lo, e_hi;                                   // element range of this launch
+  int xb_bits, lk_bits, xT_bits, b;
+  const int64_t* tab; Plan::JoinDev jd;
+  float* pop;                                           // [elements - v_base][2^b]
+};
+hipError_t launch_permute_T(const float2* T, int64_t t_stride, int64_t n_traj, const int64_t* tab,
+                            const Plan::JoinDev& jd, int xT_bits, int lk_bits, float2* Tc,
+                            hipStream_t stream);
+bool qform_supported(int lk_bits);
+hipError_t launch_qform(const QformArgs& a, int n_traj, int max_rows, hipStream_t stream);
 hipError_t launch_row_totals(const float* pop, int64_t n_elems, int b, double* totals,
                              hipStream_t stream);
 

@@ -243,6 +243,160 @@ __global__ void join_kernel(JoinArgs a) {
   }
 }
 
+// Gather the per-trajectory part T into the canonical layout used by the MFMA
+// join: Tc[x][k][k'] with k' fastest (K = 2^lk_bits), via the plan's tables.
+__global__ void permute_T_kernel(const float2* __restrict__ T, int64_t t_stride, int64_t n_traj,
+                                 const int64_t* __restrict__ tables, Plan::JoinDev jd, int xT_bits, int lk_bits,
+                                 float2* __restrict__ Tc) {
+  const int64_t per = (int64_t)1 << (xT_bits + 2 * lk_bits);
+  const int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (id >= per * n_traj) return;
+  const int64_t t = id / per, r = id % per;
+  const uint32_t K = 1u << lk_bits;
+  const uint32_t kb = (uint32_t)(r & (K - 1)), k = (uint32_t)((r >> lk_bits) & (K - 1));
+  const uint32_t x = (uint32_t)(r >> (2 * lk_bits));
+  const int lo_x = xT_bits < 12 ? xT_bits : 12, lo_k = lk_bits < 12 ? lk_bits : 12;
+  const int64_t off = tab(tables, jd.tx_lo, jd.tx_hi, lo_x, x) + tab(tables, jd.tk_lo, jd.tk_hi, lo_k, k) +
+                      tab(tables, jd.tb_lo, jd.tb_hi, lo_k, kb);
+  Tc[id] = T[t * t_stride + off];
+}
+
+// MFMA join of the doubled network (Sec. II-B marginals):
+//   pi[e][o(x, xb)] = Re sum_{k'} conj(v[k']) sum_k v[k] Tc[t][x][k][k'],  v = V[e] row xb.
+// Rows r = (element, xb) of one trajectory form the M dimension of a complex GEMM
+// Y = V * Tc[x] (K x K); the quadratic form's second contraction is fused in the
+// epilogue.  One workgroup = 4 wavefronts = 64 rows of one trajectory; it loops
+// over a range of x, staging Tc[x] (real and imaginary planes) in LDS.  Complex
+// arithmetic = four real v_mfma_f32_16x16x4f32 products (Yr += Vr Tr - Vi Ti,
+// Yi += Vr Ti + Vi Tr).
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+template <int K>
+__global__ void __launch_bounds__(256) qform_mfma_kernel(QformArgs a) {
+  constexpr int ROWS = 64;
+  constexpr int KS = K / 4;          // k-steps of 4
+  constexpr int NH = K / 16;         // 16-column tiles of k'
+  constexpr int TS = K + 1;          // padded LDS row stride
+  constexpr int PER = K * K / 256;   // Tc entries per thread per block
+  __shared__ float Tr[2][K * TS];
+  __shared__ float Ti[2][K * TS];
+  __shared__ float2 Vs[ROWS][K + 1];
+  const int t = a.traj0 + blockIdx.y;                 // trajectory of this tile
+  const int64_t e_begin = a.first[t] > a.e_lo ? a.first[t] : a.e_lo;
+  const int64_t e_end = a.first[t + 1] < a.e_hi ? a.first[t + 1] : a.e_hi;
+  const int xb_bits = a.xb_bits;
+  const int64_t rows_t = (e_end - e_begin) << xb_bits;
+  const int64_t row0 = (int64_t)blockIdx.x * ROWS;
+  if (row0 >= rows_t) return;
+  const int nx = 1 << a.xT_bits;
+  const int x_per = (nx + gridDim.z - 1) / gridDim.z;
+  const int x_begin = blockIdx.z * x_per;
+  const int x_end = x_begin + x_per < nx ? x_begin + x_per : nx;
+  if (x_begin >= x_end) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lo_b = xb_bits < 12 ? xb_bits : 12, lo_k = a.lk_bits < 12 ? a.lk_bits : 12;
+  // stage the 64 rows of V (zero beyond the trajectory's rows)
+  for (int i = tid; i < ROWS * K; i += 256) {
+    const int rr = i / K, k = i % K;
+    const int64_t row = row0 + rr;
+    float2 v = make_float2(0.f, 0.f);
+    if (row < rows_t) {
+      const int64_t e = e_begin + (row >> xb_bits);
+      const uint32_t xb = (uint32_t)(row & ((1 << xb_bits) - 1));
+      v = a.V[(e - a.v_base) * a.v_stride + tab(a.tab, a.jd.vr_lo, a.jd.vr_hi, lo_b, xb) +
+              tab(a.tab, a.jd.vc_lo, a.jd.vc_hi, lo_k, (uint32_t)k)];
+    }
+    Vs[rr][k] = v;
+  }
+  const float2* Tt = a.Tc + (int64_t)(t - a.traj_base) * ((int64_t)nx * K * K);
+  {
+    const float2* src = Tt + (int64_t)x_begin * K * K;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int idx = tid + 256 * i;
+      const float2 v = src[idx];
+      Tr[0][(idx / K) * TS + idx % K] = v.x;
+      Ti[0][(idx / K) * TS + idx % K] = v.y;
+    }
+  }
+  __syncthreads();
+  // A fragments: lane holds V[row = wave*16 + lane%16][4s + lane/16]
+  float ar[KS], ai[KS];
+  const int arow = wave * 16 + (lane & 15);
+#pragma unroll
+  for (int s = 0; s < KS; ++s) {
+    const float2 v = Vs[arow][4 * s + (lane >> 4)];
+    ar[s] = v.x;
+    ai[s] = v.y;
+  }
+  const int nout = 1 << a.b;
+  const int lo_x = a.xT_bits < 12 ? a.xT_bits : 12;
+  int buf = 0;
+  for (int x = x_begin; x < x_end; ++x) {
+    const bool more = x + 1 < x_end;
+    float2 nxt[PER];
+    if (more) {                                   // next block in flight during the MFMAs
+      const float2* src = Tt + (int64_t)(x + 1) * K * K;
+#pragma unroll
+      for (int i = 0; i < PER; ++i) nxt[i] = src[tid + 256 * i];
+    }
+    float p[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int h = 0; h < NH; ++h) {
+      floatx4 yr = {0.f, 0.f, 0.f, 0.f}, yi = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int s = 0; s < KS; ++s) {
+        const int bi = (4 * s + (lane >> 4)) * TS + 16 * h + (lane & 15);
+        const float br = Tr[buf][bi], bim = Ti[buf][bi];
+        yr = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[s], br, yr, 0, 0, 0);
+        yr = __builtin_amdgcn_mfma_f32_16x16x4f32(-ai[s], bim, yr, 0, 0, 0);
+        yi = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[s], bim, yi, 0, 0, 0);
+        yi = __builtin_amdgcn_mfma_f32_16x16x4f32(ai[s], br, yi, 0, 0, 0);
+      }
+      // epilogue: Re(Y * conj(v)) for the lane's 4 rows and column k'
+      const int kc = 16 * h + (lane & 15);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const float2 v = Vs[wave * 16 + 4 * (lane >> 4) + i][kc];
+        p[i] += yr[i] * v.x + yi[i] * v.y;
+      }
+    }
+    // reduce over the 16 lanes that share lane/16
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      float v = p[i];
+      v += __shfl_xor(v, 1);
+      v += __shfl_xor(v, 2);
+      v += __shfl_xor(v, 4);
+      v += __shfl_xor(v, 8);
+      p[i] = v;
+    }
+    if ((lane & 15) == 0) {
+      const int64_t ox = tab(a.tab, a.jd.ox_lo, a.jd.ox_hi, lo_x, (uint32_t)x);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int64_t row = row0 + wave * 16 + 4 * (lane >> 4) + i;
+        if (row < rows_t) {
+          const int64_t e = e_begin + (row >> xb_bits);
+          const uint32_t xb = (uint32_t)(row & ((1 << xb_bits) - 1));
+          const int64_t o = ox + tab(a.tab, a.jd.ob_lo, a.jd.ob_hi, lo_b, xb);
+          a.pop[(e - a.v_base) * nout + o] = p[i];
+        }
+      }
+    }
+    if (more) {
+#pragma unroll
+      for (int i = 0; i < PER; ++i) {
+        const int idx = tid + 256 * i;
+        Tr[buf ^ 1][(idx / K) * TS + idx % K] = nxt[i].x;
+        Ti[buf ^ 1][(idx / K) * TS + idx % K] = nxt[i].y;
+      }
+    }
+    __syncthreads();
+    buf ^= 1;
+  }
+}
+
 __global__ void row_totals_kernel(const float* pop, int64_t n_elems, int b, double* totals) {
   __shared__ double red[256];
   const int64_t e = blockIdx.x;
@@ -564,6 +718,32 @@ hipError_t launch_join(const JoinArgs& a, hipStream_t stream) {
   const int64_t total = a.n_elems * ((int64_t)1 << (a.xb_bits + a.xT_bits));
   if (total <= 0) return hipSuccess;
   hipLaunchKernelGGL(join_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_permute_T(const float2* T, int64_t t_stride, int64_t n_traj, const int64_t* tab,
+                            const Plan::JoinDev& jd, int xT_bits, int lk_bits, float2* Tc, hipStream_t stream) {
+  const int64_t total = n_traj << (xT_bits + 2 * lk_bits);
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(permute_T_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream, T, t_stride,
+                     n_traj, tab, jd, xT_bits, lk_bits, Tc);
+  return hipGetLastError();
+}
+
+bool qform_supported(int lk_bits) { return lk_bits == 4 || lk_bits == 5; }
+
+hipError_t launch_qform(const QformArgs& a, int n_traj, int max_rows, hipStream_t stream) {
+  if (n_traj <= 0 || max_rows <= 0) return hipSuccess;
+  const int tiles = (max_rows + 63) / 64;
+  const int nx = 1 << a.xT_bits;
+  // split x so that every CU gets work even when rows are few
+  int64_t wg = (int64_t)tiles * n_traj;
+  int zs = 1;
+  while (zs < nx && wg * zs < 4096) zs *= 2;
+  dim3 grid((unsigned)tiles, (unsigned)n_traj, (unsigned)zs);
+  if (a.lk_bits == 4) hipLaunchKernelGGL(qform_mfma_kernel<16>, grid, dim3(256), 0, stream, a);
+  else if (a.lk_bits == 5) hipLaunchKernelGGL(qform_mfma_kernel<32>, grid, dim3(256), 0, stream, a);
+  else return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

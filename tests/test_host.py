@@ -67,17 +67,24 @@ def test_config2_path_is_the_expected_sweep():
         assert bi["join_flops_per_elem"] == 2 * 512 * (8 * 32 * 32 + 8 * 32)
 
 
-@pytest.mark.parametrize("which", ["config1", "config2", "ad_2q"])
+@pytest.mark.parametrize("which", ["config1", "config2", "ad_2q", "exhaust"])
 def test_host_pts_equals_oracle(which):
     P = _lib()
     if which == "config1":
         c, seed, n = W.config1().circuit, 1002, 64
     elif which == "config2":
         c, seed, n = W.config2().circuit, 2002, 300
-    else:
+    elif which == "ad_2q":
         rng = np.random.default_rng(5)
         c = W.small_random_circuit(5, 12, rng, [W.depolarizing(0.2), W.amplitude_damping(0.3), W.depolarizing2(0.1)])
         seed, n = 99, 200
+    else:
+        c = W.Circuit(2)
+        g = c.add_gate((0, 1), W.CNOT)
+        ch = c.add_channel(W.amplitude_damping(0.5))
+        c.add_site(g, (0,), ch)
+        c.add_site(g, (1,), ch)
+        seed, n = 4, 100
     bs = [c.n_qubits] if c.n_qubits <= 12 else [10] * (c.n_qubits // 10)
     plan = P.Plan(c, bs, device=-1)
     kr, mult, lq, nd = plan.sample_trajectories(seed, n)

@@ -317,9 +317,9 @@ def test_pts_site_frequencies():
     c = W.Circuit(1)
     g = c.add_gate((0,), np.eye(2))
     ch = c.add_channel(W.depolarizing(0.3))
-    for _ in range(3):
+    for _ in range(12):
         c.add_site(g, (0,), ch)
-    kr, mult, _, nd = pts.presample(c, seed=5, n_unique=1000, max_draws=20000)
+    kr, mult, _, nd = pts.presample(c, seed=5, n_unique=10 ** 6, max_draws=20000)
     assert nd == 20000 and mult.sum() == 20000
     counts = np.zeros(4)
     for r, m in zip(kr, mult):
@@ -327,3 +327,14 @@ def test_pts_site_frequencies():
     p = np.array([0.7, 0.1, 0.1, 0.1])
     sd = np.sqrt(20000 * p * (1 - p))
     assert np.all(np.abs(counts - 20000 * p) < 5 * sd)
+
+
+def test_pts_stops_when_every_error_set_has_appeared():
+    c = W.Circuit(1)
+    g = c.add_gate((0,), np.eye(2))
+    ch = c.add_channel(W.pauli_channel(W.pauli_x, 0.5))
+    c.add_site(g, (0,), ch)
+    c.add_site(g, (0,), ch)
+    kr, mult, _, nd = pts.presample(c, seed=3, n_unique=10)
+    assert len(kr) == 4 and mult.sum() == nd
+    assert sorted(map(tuple, kr.tolist())) == [(0, 0), (0, 1), (1, 0), (1, 1)]
