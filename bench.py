@@ -64,7 +64,9 @@ def main():
     ap.add_argument("--shots", type=int, default=1000)
     ap.add_argument("--workspace-gb", type=float, default=64.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "join_traffic.json"))
+    ap.add_argument("--traffic-file", default=os.path.join(ROOT, "profiles", "join_traffic.txt"))
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run only a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the path shards over trajectories across GPUs by design, "
@@ -73,6 +75,16 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.copy_calibration:
+        n = 1 << 30
+        src = torch.ones(n, dtype=torch.uint8, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read_per_launch": n, "copy_bytes_written_per_launch": n, "launches": 3}))
+        return
 
     import paper_2604_08467_amd as P
     import workloads as W
@@ -110,11 +122,11 @@ def main():
     join_s = prof["join_ms"] / 1e3
     achieved = prof["join_flops"] / join_s / 1e12 if join_s > 0 else 0.0
     traffic = None
-    if os.path.exists(args.traffic_json):
-        try:
-            traffic = json.load(open(args.traffic_json)).get("bytes_per_launch")
-        except Exception:
-            traffic = None
+    if os.path.exists(args.traffic_file):
+        # "bytes_per_launch: N" written from two rocprofv3 counter runs of this command
+        for ln in open(args.traffic_file):
+            if ln.startswith("bytes_per_launch:"):
+                traffic = float(ln.split(":", 1)[1])
     roofline = {"bound": "mfma", "achieved": achieved, "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / FP32_MFMA_PEAK_TFLOPS, "traffic": traffic,
                 "kernel": "join (prefix part x per-trajectory part, FP32)",

@@ -127,6 +127,8 @@ typedef struct {
   int32_t doubled;              /* 1: ket x bra network (j < f-1), 0: ket only   */
   int32_t n_left_steps;         /* per-element steps (prefix-projected part)     */
   int32_t n_right_steps;        /* per-trajectory steps                          */
+  int32_t n_resume_steps;       /* per-element steps when resuming from the parent
+                                   element's left tensor (sampling loop, j >= 1)  */
   int32_t left_rank, right_rank;/* ranks of the two partial results              */
   int32_t left_peak_rank, right_peak_rank;
   int32_t join_rows_log2;       /* open batch legs carried by the left part      */
@@ -202,9 +204,10 @@ ptsbe_status_t ptsbe_sample_shots(ptsbe_plan_t plan, const uint8_t* d_kraus_idx,
                                   double* d_traj_norm, int64_t* stats_out, void* d_workspace,
                                   size_t workspace_bytes, void* stream);
 
-/* Timing hook for measurement: when enabled, the library records HIP events
- * around every launch of the batch join kernel and accumulates its total time
- * (milliseconds), launch count and algorithmic flops. */
+/* Timing hook for measurement: when enabled, the library records HIP events (on
+ * the launch stream) around every launch of the MFMA join of doubled networks
+ * and accumulates its total time (milliseconds), launch count and algorithmic
+ * flops (2^xb * 2^xT * (8 K^2 + 8 K) per element, K = 2^crossing). */
 ptsbe_status_t ptsbe_profile_enable(ptsbe_plan_t plan, int32_t on);
 ptsbe_status_t ptsbe_profile_read(ptsbe_plan_t plan, double* join_ms, int64_t* join_launches,
                                   double* join_flops, double* sweep_ms, double* sweep_bytes);

@@ -54,7 +54,7 @@ class PlanInfo_t(C.Structure):
 class BatchInfo_t(C.Structure):
     _fields_ = [
         ("start", C.c_int32), ("size", C.c_int32), ("doubled", C.c_int32),
-        ("n_left_steps", C.c_int32), ("n_right_steps", C.c_int32),
+        ("n_left_steps", C.c_int32), ("n_right_steps", C.c_int32), ("n_resume_steps", C.c_int32),
         ("left_rank", C.c_int32), ("right_rank", C.c_int32),
         ("left_peak_rank", C.c_int32), ("right_peak_rank", C.c_int32),
         ("join_rows_log2", C.c_int32), ("crossing", C.c_int32),

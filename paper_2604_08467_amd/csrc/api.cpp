@@ -88,7 +88,7 @@ struct Arena {
   }
 };
 
-ptsbe::GateCtx gate_ctx(const Plan& p, const uint8_t* kraus) {
+ptsbe::GateCtx gate_ctx(const Plan& p, const uint8_t* kraus, const float2* merged) {
   ptsbe::GateCtx g;
   g.gates = p.d_gates;
   g.gate_site_list = p.d_gate_site_list;
@@ -96,8 +96,12 @@ ptsbe::GateCtx gate_ctx(const Plan& p, const uint8_t* kraus) {
   g.kraus = kraus;
   g.S = p.S;
   g.max_kraus = p.max_kraus;
+  g.merged = merged;
+  g.G = p.G;
   return g;
 }
+
+size_t merged_bytes(const Plan& p, int64_t E) { return (size_t)E * p.G * 16 * sizeof(float2); }
 
 bool part_uses_vm(const ptsbe::PartPlan& pp) { return pp.peak <= ptsbe::kVmMaxRank; }
 
@@ -110,23 +114,26 @@ size_t part_scratch_per_job(const ptsbe::PartPlan& pp) {
 // goes to out[job][2^rank].
 ptsbe_status_t run_part(Plan& p, const ptsbe::PartPlan& pp, const ptsbe::AbsorbStep* d_steps,
                         const ptsbe::GateCtx& g, int64_t n_jobs, const int32_t* job_traj, int32_t traj_base,
-                        const uint64_t* job_prefix, float2* out, Arena& ar, hipStream_t s) {
+                        const uint64_t* job_prefix, const ptsbe::InitArgs& init, float2* out, Arena& ar,
+                        hipStream_t s) {
   if (n_jobs <= 0) return PTSBE_OK;
   const int out_rank = (int)pp.labels.size();
   if (pp.steps.empty()) {
-    HIP_TRY(ptsbe::launch_fill_one(out, n_jobs, s));
+    if (init.Vprev) HIP_TRY(ptsbe::launch_init_gather(init, n_jobs, job_prefix, p.NW, out, s));
+    else HIP_TRY(ptsbe::launch_fill_one(out, n_jobs, s));
     return PTSBE_OK;
   }
   if (part_uses_vm(pp)) {
     HIP_TRY(ptsbe::launch_part_vm(d_steps, (int)pp.steps.size(), pp.peak, g, n_jobs, job_traj, traj_base,
-                                  job_prefix, p.NW, out, out_rank, s));
+                                  job_prefix, p.NW, init, out, out_rank, s));
     return PTSBE_OK;
   }
   const size_t mark = ar.used;
   float2* b0 = (float2*)ar.take((size_t)n_jobs * ((size_t)8 << pp.peak));
   float2* b1 = (float2*)ar.take((size_t)n_jobs * ((size_t)8 << pp.peak));
   if (!b0 || !b1) return fail(PTSBE_ERR_OUT_OF_MEMORY, "workspace too small for a sweep");
-  HIP_TRY(ptsbe::launch_fill_one(b0, n_jobs, s));   // rank-0 start: the scalar 1 per job
+  if (init.Vprev) HIP_TRY(ptsbe::launch_init_gather(init, n_jobs, job_prefix, p.NW, b0, s));
+  else HIP_TRY(ptsbe::launch_fill_one(b0, n_jobs, s));   // rank-0 start: the scalar 1 per job
   const float2* A = b0;
   for (size_t i = 0; i < pp.steps.size(); ++i) {
     float2* C = (i + 1 == pp.steps.size()) ? out : (A == b0 ? b1 : b0);
@@ -151,14 +158,20 @@ struct BatchIO {
   double* totals = nullptr;     // [U] FP64 sums (may be null for contract_batch)
   bool sample = false;
   ptsbe::SampleArgs sa{};       // template: per-element arrays at offset 0
+  // prefix-tree reuse: left tensors of all elements kept for the next batch
+  float2* V_out = nullptr;      // [U][2^rank] persistent left tensors of this batch, or null
+  bool resume = false;          // start each element from its parent's left tensor
+  const float2* V_prev = nullptr;
+  int64_t V_prev_stride = 1;
+  const int32_t* parent = nullptr;
 };
 
 struct EventPair { hipEvent_t a, b; };
 
-ptsbe_status_t run_batch(Plan& p, int j, const uint8_t* d_kraus, int64_t E, BatchIO& io, Arena& ar,
-                         hipStream_t s, std::vector<EventPair>& evs) {
+ptsbe_status_t run_batch(Plan& p, int j, const uint8_t* d_kraus, const float2* merged, int64_t E, BatchIO& io,
+                         Arena& ar, hipStream_t s, std::vector<EventPair>& evs) {
   const ptsbe::BatchPlan& bp = p.batches[j];
-  const ptsbe::GateCtx g = gate_ctx(p, d_kraus);
+  const ptsbe::GateCtx g = gate_ctx(p, d_kraus, merged);
   if (io.U <= 0) return PTSBE_OK;
   const size_t mark0 = ar.used;
   // element ranges per trajectory
@@ -168,11 +181,16 @@ ptsbe_status_t run_batch(Plan& p, int j, const uint8_t* d_kraus, int64_t E, Batc
   std::vector<int32_t> first((size_t)E + 1);
   HIP_TRY(hipMemcpyAsync(first.data(), d_first, (size_t)(E + 1) * 4, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
-  const int rT = (int)bp.right.labels.size(), rV = (int)bp.left.labels.size();
-  const bool use_qform = bp.doubled && ptsbe::qform_supported((int)bp.lk.size());
-  const size_t per_traj = ((size_t)8 << rT) * (use_qform ? 2 : 1) + part_scratch_per_job(bp.right);
+  const ptsbe::PartPlan& left = io.resume ? bp.left_resume : bp.left;
+  const int rT = (int)bp.right.labels.size(), rV = (int)left.labels.size();
+  const Plan::JoinDev& jdv = io.resume ? p.join_dev_r[j] : p.join_dev[j];
+  const int lkb = (int)bp.lk.size();
+  const bool use_qform = bp.doubled && ptsbe::qform_supported(lkb);
+  const bool use_ket = !bp.doubled && ptsbe::ketjoin_supported(lkb);
+  const bool use_mfma = use_qform || use_ket;
+  const size_t per_traj = ((size_t)8 << rT) * (use_mfma ? 2 : 1) + part_scratch_per_job(bp.right);
   const size_t nb = (size_t)1 << bp.size;
-  const size_t per_elem = ((size_t)8 << rV) + part_scratch_per_job(bp.left) + (io.sample ? 4 * nb : 0);
+  const size_t per_elem = (io.V_out ? 0 : ((size_t)8 << rV)) + part_scratch_per_job(left) + (io.sample ? 4 * nb : 0);
   const size_t avail = ar.left();
   int64_t t_cap = (int64_t)std::min<size_t>((size_t)E, (avail / 2) / per_traj);
   int64_t e_cap = (int64_t)((avail / 2) / per_elem);
@@ -180,8 +198,8 @@ ptsbe_status_t run_batch(Plan& p, int j, const uint8_t* d_kraus, int64_t E, Batc
     return fail(PTSBE_ERR_OUT_OF_MEMORY, "workspace too small for one trajectory of batch " + std::to_string(j));
   e_cap = std::min<int64_t>(e_cap, 1 << 22);
   t_cap = std::min<int64_t>(t_cap, 65535);       // one grid dimension of the MFMA join
-  const ptsbe::AbsorbStep* d_left = p.d_steps + p.part_step_off[2 * j];
-  const ptsbe::AbsorbStep* d_right = p.d_steps + p.part_step_off[2 * j + 1];
+  const ptsbe::AbsorbStep* d_left = p.d_steps + p.part_step_off[3 * j + (io.resume ? 2 : 0)];
+  const ptsbe::AbsorbStep* d_right = p.d_steps + p.part_step_off[3 * j + 1];
   for (int64_t t0 = 0; t0 < E; t0 += t_cap) {
     const int64_t t1 = std::min<int64_t>(E, t0 + t_cap);
     const int64_t e0 = first[t0], e1 = first[t1];
@@ -189,22 +207,32 @@ ptsbe_status_t run_batch(Plan& p, int j, const uint8_t* d_kraus, int64_t E, Batc
     const size_t mark = ar.used;
     float2* T = (float2*)ar.take((size_t)(t1 - t0) * ((size_t)8 << rT));
     if (!T) return fail(PTSBE_ERR_OUT_OF_MEMORY, "workspace too small (right part)");
-    ptsbe_status_t st = run_part(p, bp.right, d_right, g, t1 - t0, nullptr, (int32_t)t0, nullptr, T, ar, s);
+    ptsbe_status_t st = run_part(p, bp.right, d_right, g, t1 - t0, nullptr, (int32_t)t0, nullptr,
+                                 ptsbe::InitArgs(), T, ar, s);
     if (st != PTSBE_OK) return st;
     float2* Tc = nullptr;
-    if (use_qform) {   // canonical [x][k][k'] layout for the MFMA join
+    if (use_mfma) {   // canonical [x][k][k'] (doubled) or [x][k] (ket) layout for the MFMA joins
       Tc = (float2*)ar.take((size_t)(t1 - t0) * ((size_t)8 << rT));
       if (!Tc) return fail(PTSBE_ERR_OUT_OF_MEMORY, "workspace too small (join layout)");
       HIP_TRY(ptsbe::launch_permute_T(T, (int64_t)1 << rT, t1 - t0, p.d_tables, p.join_dev[j], (int)bp.xT.size(),
-                                      (int)bp.lk.size(), Tc, s));
+                                      lkb, bp.doubled ? lkb : 0, Tc, s));
     }
     for (int64_t a0 = e0; a0 < e1; a0 += e_cap) {
       const int64_t a1 = std::min<int64_t>(e1, a0 + e_cap), ne = a1 - a0;
       const size_t mark2 = ar.used;
-      float2* V = (float2*)ar.take((size_t)ne * ((size_t)8 << rV));
+      float2* V = io.V_out ? io.V_out + a0 * ((int64_t)1 << rV) : (float2*)ar.take((size_t)ne * ((size_t)8 << rV));
       float* pop = io.sample ? (float*)ar.take((size_t)ne * nb * 4) : nullptr;
       if (!V || (io.sample && !pop)) return fail(PTSBE_ERR_OUT_OF_MEMORY, "workspace too small (elements)");
-      st = run_part(p, bp.left, d_left, g, ne, io.elem_traj + a0, 0, io.elem_prefix + a0 * p.NW, V, ar, s);
+      ptsbe::InitArgs init;
+      if (io.resume) {
+        init.Vprev = io.V_prev;
+        init.stride = io.V_prev_stride;
+        init.parent = io.parent + a0;
+        init.r0 = bp.resume_rank0;
+        init.nsl = (int)bp.resume_slice_pos.size();
+        for (int i = 0; i < init.nsl; ++i) { init.pos[i] = bp.resume_slice_pos[i]; init.q[i] = bp.resume_slice_q[i]; }
+      }
+      st = run_part(p, left, d_left, g, ne, io.elem_traj + a0, 0, io.elem_prefix + a0 * p.NW, init, V, ar, s);
       if (st != PTSBE_OK) return st;
       ptsbe::JoinArgs ja{};
       ja.V = V; ja.v_stride = (int64_t)1 << rV;
@@ -212,7 +240,7 @@ ptsbe_status_t run_batch(Plan& p, int j, const uint8_t* d_kraus, int64_t E, Batc
       ja.elem_traj = io.elem_traj + a0; ja.traj_base = (int32_t)t0;
       ja.n_elems = ne;
       ja.xb_bits = (int)bp.xb.size(); ja.lk_bits = (int)bp.lk.size(); ja.xT_bits = (int)bp.xT.size();
-      ja.tab = p.d_tables; ja.jd = p.join_dev[j];
+      ja.tab = p.d_tables; ja.jd = jdv;
       ja.b = bp.size; ja.doubled = bp.doubled ? 1 : 0;
       if (io.sample) {
         ja.pop = pop;
@@ -221,12 +249,13 @@ ptsbe_status_t run_batch(Plan& p, int j, const uint8_t* d_kraus, int64_t E, Batc
         ja.amp = io.amp_out ? io.amp_out + a0 * (int64_t)nb : nullptr;
       }
       EventPair ev{};
-      if (p.profile) {
+      const bool timed = p.profile && use_qform;   // the MFMA join is the measured kernel
+      if (timed) {
         HIP_TRY(hipEventCreate(&ev.a));
         HIP_TRY(hipEventCreate(&ev.b));
         HIP_TRY(hipEventRecord(ev.a, s));
       }
-      if (use_qform) {
+      if (use_mfma) {
         ptsbe::QformArgs qa{};
         qa.V = V; qa.v_stride = (int64_t)1 << rV; qa.v_base = a0;
         qa.Tc = Tc; qa.traj_base = (int32_t)t0;
@@ -241,14 +270,19 @@ ptsbe_status_t run_batch(Plan& p, int j, const uint8_t* d_kraus, int64_t E, Batc
         qa.traj0 = (int32_t)tA;
         qa.first = d_first; qa.e_lo = a0; qa.e_hi = a1;
         qa.xb_bits = (int)bp.xb.size(); qa.lk_bits = (int)bp.lk.size(); qa.xT_bits = (int)bp.xT.size();
-        qa.b = bp.size; qa.tab = p.d_tables; qa.jd = p.join_dev[j];
+        qa.b = bp.size; qa.tab = p.d_tables; qa.jd = jdv;
         qa.pop = ja.pop;
-        if (!qa.pop) return fail(PTSBE_ERR_INVALID_ARG, "population output required");
-        HIP_TRY(ptsbe::launch_qform(qa, (int)(tB - tA + 1), (int)max_rows, s));
+        qa.amp = ja.amp;
+        if (use_qform) {
+          if (!qa.pop) return fail(PTSBE_ERR_INVALID_ARG, "population output required");
+          HIP_TRY(ptsbe::launch_qform(qa, (int)(tB - tA + 1), (int)max_rows, s));
+        } else {
+          HIP_TRY(ptsbe::launch_ketjoin(qa, (int)(tB - tA + 1), (int)max_rows, s));
+        }
       } else {
         HIP_TRY(ptsbe::launch_join(ja, s));
       }
-      if (p.profile) {
+      if (timed) {
         HIP_TRY(hipEventRecord(ev.b, s));
         evs.push_back(ev);
         p.join_launches++;
@@ -482,6 +516,8 @@ ptsbe_status_t ptsbe_plan(const ptsbe_circuit_t* c, const ptsbe_plan_opts_t* o, 
     steps.insert(steps.end(), bp.left.steps.begin(), bp.left.steps.end());
     p->part_step_off.push_back((int64_t)steps.size());
     steps.insert(steps.end(), bp.right.steps.begin(), bp.right.steps.end());
+    p->part_step_off.push_back((int64_t)steps.size());
+    steps.insert(steps.end(), bp.left_resume.steps.begin(), bp.left_resume.steps.end());
     Plan::JoinDev jd{};
     auto put = [&](const ptsbe::SplitTable& t, int64_t& lo, int64_t& hi) {
       lo = (int64_t)tables.size();
@@ -497,6 +533,10 @@ ptsbe_status_t ptsbe_plan(const ptsbe_circuit_t* c, const ptsbe_plan_opts_t* o, 
     put(bp.o_x, jd.ox_lo, jd.ox_hi);
     put(bp.o_b, jd.ob_lo, jd.ob_hi);
     p->join_dev.push_back(jd);
+    Plan::JoinDev jr = jd;   // the resumed left part may order its legs differently
+    put(bp.v_row_r.lo.empty() ? bp.v_row : bp.v_row_r, jr.vr_lo, jr.vr_hi);
+    put(bp.v_col_r.lo.empty() ? bp.v_col : bp.v_col_r, jr.vc_lo, jr.vc_hi);
+    p->join_dev_r.push_back(jr);
   }
   if (steps.empty()) steps.push_back(ptsbe::AbsorbStep{});
   if (site_list.empty()) site_list.push_back(0);
@@ -558,6 +598,7 @@ ptsbe_status_t ptsbe_plan_batch_info(ptsbe_plan_t plan, int32_t j, ptsbe_batch_i
   out->doubled = bp.doubled;
   out->n_left_steps = (int32_t)bp.left.steps.size();
   out->n_right_steps = (int32_t)bp.right.steps.size();
+  out->n_resume_steps = j >= 1 ? (int32_t)bp.left_resume.steps.size() : 0;
   out->left_rank = (int32_t)bp.left.labels.size();
   out->right_rank = (int32_t)bp.right.labels.size();
   out->left_peak_rank = bp.left.peak;
@@ -640,7 +681,8 @@ ptsbe_status_t ptsbe_contract_workspace_size(ptsbe_plan_t plan, int32_t j, int64
   const size_t per_traj = ((size_t)8 << bp.right.labels.size()) + part_scratch_per_job(bp.right);
   const size_t per_elem = ((size_t)8 << bp.left.labels.size()) + part_scratch_per_job(bp.left);
   size_t t = (size_t)std::min<int64_t>(E, 256), e = (size_t)std::min<int64_t>(n_elems, 65536);
-  *bytes = (size_t)(E + 1) * 4 + 2 * (std::max<size_t>(t, 1) * per_traj + std::max<size_t>(e, 1) * per_elem) + (1 << 20);
+  *bytes = merged_bytes(*p, E) + (size_t)(E + 1) * 4 +
+           2 * (std::max<size_t>(t, 1) * per_traj * 2 + std::max<size_t>(e, 1) * per_elem) + (1 << 20);
   return PTSBE_OK;
 }
 
@@ -664,6 +706,13 @@ size_t sample_persistent_bytes(const Plan& p, int64_t E, int64_t M) {
   add((size_t)E * 8);                     // norms
   add(ptsbe::scan_scratch_bytes(cap));
   add(64);                                // counters
+  add((size_t)E * p.G * 16 * 8);          // merged gates
+  int rVmax = 0;
+  for (auto& bp : p.batches) rVmax = std::max<int>(rVmax, (int)bp.left_resume.labels.size());
+  for (int k = 0; k < 2; ++k) {
+    add((size_t)cap * ((size_t)8 << rVmax));   // left tensors
+    add((size_t)cap * 4);                      // parents
+  }
   return b;
 }
 }  // namespace
@@ -673,7 +722,7 @@ ptsbe_status_t ptsbe_sample_workspace_size(ptsbe_plan_t plan, int64_t E, int64_t
   if (!p || !bytes) return fail(PTSBE_ERR_INVALID_ARG, "null argument");
   size_t chunk = 0;
   for (auto& bp : p->batches) {
-    const size_t per_traj = ((size_t)8 << bp.right.labels.size()) + part_scratch_per_job(bp.right);
+    const size_t per_traj = ((size_t)16 << bp.right.labels.size()) + part_scratch_per_job(bp.right);
     const size_t per_elem = ((size_t)8 << bp.left.labels.size()) + part_scratch_per_job(bp.left) +
                             ((size_t)4 << bp.size);
     chunk = std::max(chunk, 2 * (std::min<size_t>(E, 256) * per_traj + 65536 * per_elem));
@@ -711,7 +760,10 @@ ptsbe_status_t ptsbe_contract_batch(ptsbe_plan_t plan, int32_t j, const uint8_t*
   else io.pop_out = (float*)d_out;
   io.totals = out_kind == PTSBE_OUT_POPULATION ? d_elem_total : nullptr;
   std::vector<EventPair> evs;
-  ptsbe_status_t st = run_batch(*p, j, d_kraus_idx, E, io, ar, s, evs);
+  float2* merged = (float2*)ar.take(merged_bytes(*p, E));
+  if (!merged) return fail(PTSBE_ERR_OUT_OF_MEMORY, "workspace too small for the merged gates");
+  HIP_TRY(ptsbe::launch_upv_merge(gate_ctx(*p, d_kraus_idx, nullptr), E, merged, s));
+  ptsbe_status_t st = run_batch(*p, j, d_kraus_idx, merged, E, io, ar, s, evs);
   if (st != PTSBE_OK) return st;
   if (p->profile) {
     HIP_TRY(hipStreamSynchronize(s));
@@ -748,8 +800,14 @@ ptsbe_status_t ptsbe_sample_shots(ptsbe_plan_t plan, const uint8_t* d_kraus_idx,
   Arena ar;
   ar.base = (char*)d_workspace;
   ar.cap = workspace_bytes;
-  struct Elems { int32_t* traj; uint64_t* prefix; int32_t* off; int32_t* cnt; int32_t* ids; } el[2];
+  struct Elems { int32_t* traj; uint64_t* prefix; int32_t* off; int32_t* cnt; int32_t* ids; int32_t* parent; } el[2];
+  // left tensors of every element are kept for one batch (prefix-tree reuse)
+  int rVmax = 0;
+  for (auto& bp : p->batches) rVmax = std::max<int>(rVmax, (int)bp.left_resume.labels.size());
+  float2* Vbuf[2];
+  for (int k = 0; k < 2; ++k) Vbuf[k] = (float2*)ar.take((size_t)cap * ((size_t)8 << rVmax));
   for (int k = 0; k < 2; ++k) {
+    el[k].parent = (int32_t*)ar.take((size_t)cap * 4);
     el[k].traj = (int32_t*)ar.take((size_t)cap * 4);
     el[k].prefix = (uint64_t*)ar.take((size_t)cap * 8 * p->NW);
     el[k].off = (int32_t*)ar.take((size_t)cap * 4);
@@ -764,13 +822,17 @@ ptsbe_status_t ptsbe_sample_shots(ptsbe_plan_t plan, const uint8_t* d_kraus_idx,
   double* norms = (double*)ar.take((size_t)E * 8);
   int32_t* scan_scratch = (int32_t*)ar.take(ptsbe::scan_scratch_bytes(cap));
   int32_t* counters = (int32_t*)ar.take(64);
-  bool ok = shot_x && child_cnt && child_off && totals && d_base && norms && scan_scratch && counters;
-  for (int k = 0; k < 2; ++k) ok = ok && el[k].traj && el[k].prefix && el[k].off && el[k].cnt && el[k].ids;
+  float2* merged = (float2*)ar.take(merged_bytes(*p, E));
+  bool ok = shot_x && child_cnt && child_off && totals && d_base && norms && scan_scratch && counters && merged;
+  for (int k = 0; k < 2; ++k)
+    ok = ok && el[k].traj && el[k].prefix && el[k].off && el[k].cnt && el[k].ids && el[k].parent && Vbuf[k];
   if (!ok) return fail(PTSBE_ERR_OUT_OF_MEMORY, "workspace too small for the shot and element arrays");
   HIP_TRY(hipMemcpyAsync(d_base, base.data(), (size_t)E * 8, hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemsetAsync(counters, 0, 64, s));
   HIP_TRY(ptsbe::launch_init_elements(E, d_shots_per_traj, el[0].traj, el[0].prefix, p->NW, el[0].off, el[0].cnt,
                                       d_base, el[0].ids, d_shot_traj, d_shots, M, s));
+  // error injection: the UPV merge of every trajectory's operators into its gates
+  HIP_TRY(ptsbe::launch_upv_merge(gate_ctx(*p, d_kraus_idx, nullptr), E, merged, s));
   int cur = 0;
   int64_t U = E;
   std::vector<EventPair> evs;
@@ -781,6 +843,14 @@ ptsbe_status_t ptsbe_sample_shots(ptsbe_plan_t plan, const uint8_t* d_kraus_idx,
     BatchIO io;
     io.elem_traj = el[cur].traj;
     io.elem_prefix = el[cur].prefix;
+    io.V_out = Vbuf[j & 1];
+    if (j >= 1) {
+      io.resume = true;
+      io.V_prev = Vbuf[(j - 1) & 1];
+      const auto& pv = p->batches[j - 1];
+      io.V_prev_stride = (int64_t)1 << (j - 1 == 0 ? pv.left.labels.size() : pv.left_resume.labels.size());
+      io.parent = el[cur].parent;
+    }
     io.U = U;
     io.sample = true;
     ptsbe::SampleArgs& sa = io.sa;
@@ -793,7 +863,7 @@ ptsbe_status_t ptsbe_sample_shots(ptsbe_plan_t plan, const uint8_t* d_kraus_idx,
     sa.elem_total = totals;
     sa.child_cnt = (j + 1 < f) ? child_cnt : nullptr;
     sa.bad_flag = counters + 1;
-    ptsbe_status_t st = run_batch(*p, j, d_kraus_idx, E, io, ar, s, evs);
+    ptsbe_status_t st = run_batch(*p, j, d_kraus_idx, merged, E, io, ar, s, evs);
     if (st != PTSBE_OK) return st;
     if (j == 0) {
       // elements of batch 0 are the trajectories themselves: totals = squared norms
@@ -813,6 +883,7 @@ ptsbe_status_t ptsbe_sample_shots(ptsbe_plan_t plan, const uint8_t* d_kraus_idx,
       ca.shot_ids = el[cur].ids; ca.shot_x = shot_x; ca.child_off = child_off;
       ca.out_traj = el[1 - cur].traj; ca.out_prefix = el[1 - cur].prefix;
       ca.out_shot_off = el[1 - cur].off; ca.out_shot_cnt = el[1 - cur].cnt; ca.out_shot_ids = el[1 - cur].ids;
+      ca.out_parent = el[1 - cur].parent;
       HIP_TRY(ptsbe::launch_children(ca, s));
       cur = 1 - cur;
       U = nU;

@@ -33,6 +33,10 @@ struct AbsorbStep {
   int32_t npos[4], nw[4];
   int32_t hm[4], hw[4];
   int32_t sq[kMaxSlices], sw[kMaxSlices];   // prefix-sliced legs: qubit, weight
+  // derived tables (filled by the planner): for every value k of the contracted
+  // legs / n of the new legs, the offset into A / C and the index into B
+  uint32_t koff[16], noff[16];
+  int32_t kB[16], nB[16];
 };
 
 struct PartPlan {
@@ -56,6 +60,15 @@ struct BatchPlan {
   bool doubled = false;
   PartPlan left, right;             // left: per element (ket, prefix projected)
   std::vector<int> lk, lb, xb, xT;  // join label groups
+  std::vector<int> xb_qubits;       // qubit of each xb label
+  std::vector<int> left_gates;      // gates of the left part
+  // resume variant of the left part (j >= 1): starts from the parent element's
+  // left tensor (rank resume_parent_rank) with the legs at resume_slice_pos sliced
+  // to the element's bits of qubits resume_slice_q (initial rank resume_rank0)
+  PartPlan left_resume;
+  int resume_rank0 = 0, resume_parent_rank = 0;
+  std::vector<int> resume_slice_pos, resume_slice_q;
+  SplitTable v_row_r, v_col_r;
   // join tables
   SplitTable v_row, v_col;          // V[e]: rows over xb, cols over lk
   SplitTable t_x, t_k, t_b;         // T[t]: xT, lk, lb
@@ -93,9 +106,10 @@ struct Plan {
   float2* d_site_ops = nullptr;                   // [S][max_kraus][16] embedded K/sqrt(q)
   AbsorbStep* d_steps = nullptr;                  // all parts' steps, concatenated
   int64_t* d_tables = nullptr;                    // all join tables, concatenated
-  std::vector<int64_t> part_step_off;             // per batch: left, right offsets
+  std::vector<int64_t> part_step_off;             // per batch: left, right, resumed-left offsets
   struct JoinDev { int64_t vr_lo, vr_hi, vc_lo, vc_hi, tx_lo, tx_hi, tk_lo, tk_hi, tb_lo, tb_hi, ox_lo, ox_hi, ob_lo, ob_hi; };
   std::vector<JoinDev> join_dev;
+  std::vector<JoinDev> join_dev_r;                // same with the resumed left part's V tables
   int64_t device_bytes = 0;
 
   // measurement
@@ -114,14 +128,33 @@ struct GateCtx {
   const float2* site_ops;
   const uint8_t* kraus;     // [E][S]
   int32_t S, max_kraus;
+  const float2* merged;     // [E][G][16] merged gates of every trajectory
+  int32_t G;
 };
+// UPV merge (error injection) of every (trajectory, gate): merged[t][g] =
+// (prod of the inserted operators of g's sites) . d_g, the shared default when
+// all of g's sites take Kraus index 0.
+hipError_t launch_upv_merge(GateCtx g, int64_t E, float2* merged, hipStream_t stream);
 
+// Initial tensor of a resumed part: the parent element's tensor with some legs
+// sliced to the job's prefix bits (Vprev == null: the scalar 1).
+struct InitArgs {
+  const float2* Vprev = nullptr;
+  int64_t stride = 1;                 // entries per parent tensor
+  const int32_t* parent = nullptr;    // [job] parent index into Vprev
+  int r0 = 0;                         // rank of the initial tensor
+  int nsl = 0;
+  int pos[8] = {0, 0, 0, 0, 0, 0, 0, 0};   // sliced positions in the parent tensor (ascending)
+  int q[8] = {0, 0, 0, 0, 0, 0, 0, 0};     // qubit whose prefix bit fixes each
+};
 // Run all steps of one part in LDS, one workgroup per job.
 // jobs: traj of job = job_traj ? job_traj[job] : job0 + job; prefix words of job.
 hipError_t launch_part_vm(const AbsorbStep* d_steps, int n_steps, int peak, GateCtx g,
                           int64_t n_jobs, const int32_t* job_traj, int32_t traj_base,
-                          const uint64_t* job_prefix, int NW, float2* out, int out_rank,
-                          hipStream_t stream);
+                          const uint64_t* job_prefix, int NW, const InitArgs& init, float2* out,
+                          int out_rank, hipStream_t stream);
+hipError_t launch_init_gather(const InitArgs& init, int64_t n_jobs, const uint64_t* job_prefix, int NW,
+                              float2* out, hipStream_t stream);
 // One absorb step over all jobs in global memory.
 hipError_t launch_absorb_global(const AbsorbStep& st, const AbsorbStep* d_st, GateCtx g,
                                 int64_t n_jobs, const int32_t* job_traj, int32_t traj_base,
@@ -152,13 +185,16 @@ struct QformArgs {
   int64_t e_lo, e_hi;                                   // element range of this launch
   int xb_bits, lk_bits, xT_bits, b;
   const int64_t* tab; Plan::JoinDev jd;
-  float* pop;                                           // [elements - v_base][2^b]
+  float* pop;                                           // [elements - v_base][2^b] or null
+  float2* amp;                                          // ket join only: amplitudes or null
 };
 hipError_t launch_permute_T(const float2* T, int64_t t_stride, int64_t n_traj, const int64_t* tab,
-                            const Plan::JoinDev& jd, int xT_bits, int lk_bits, float2* Tc,
+                            const Plan::JoinDev& jd, int xT_bits, int lk_bits, int lb_bits, float2* Tc,
                             hipStream_t stream);
 bool qform_supported(int lk_bits);
+bool ketjoin_supported(int lk_bits);
 hipError_t launch_qform(const QformArgs& a, int n_traj, int max_rows, hipStream_t stream);
+hipError_t launch_ketjoin(const QformArgs& a, int n_traj, int max_rows, hipStream_t stream);
 hipError_t launch_row_totals(const float* pop, int64_t n_elems, int b, double* totals,
                              hipStream_t stream);
 
@@ -179,6 +215,7 @@ struct SampleArgs {
 hipError_t launch_sample(const SampleArgs& a, hipStream_t stream);
 
 struct ChildArgs {
+  int32_t* out_parent;                   // [children] index of the parent element
   int64_t n_elems; int b; int start; int NW;
   const int32_t* elem_traj; const uint64_t* elem_prefix;
   const int32_t* elem_shot_off; const int32_t* elem_shot_cnt;

@@ -20,6 +20,8 @@
 namespace ptsbe {
 namespace {
 
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
 __device__ inline float2 cmul(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
@@ -31,56 +33,53 @@ __device__ inline uint32_t bit_of_prefix(const uint64_t* pw, int q) {
   return (uint32_t)((pw[q >> 6] >> (q & 63)) & 1ull);
 }
 
-// Load the (merged) gate matrix of `gate` for trajectory `traj` into out[16]
-// (LDS).  Must be called by all threads of the block; uses threads 0..15.
-__device__ void load_gate_block(const GateCtx& g, int gate, int traj, int conj, float2* out) {
+// UPV merge of one (trajectory, gate) into out[16] (per thread, FP32 products).
+__device__ void merge_gate(const GateCtx& g, int gate, int traj, float2* out) {
   const DeviceGate* G = g.gates + gate;
   const int sb = G->site_begin, se = G->site_end;
   const uint8_t* kr = g.kraus + (int64_t)traj * g.S;
   bool dev = false;
   for (int s = sb; s < se; ++s) dev |= kr[g.gate_site_list[s]] != 0;
-  const int tid = threadIdx.x;
   if (!dev) {
-    if (tid < 16) {
-      float2 v = G->def[tid];
-      if (conj) v.y = -v.y;
-      out[tid] = v;
-    }
+    for (int i = 0; i < 16; ++i) out[i] = G->def[i];
     return;
   }
-  if (tid == 0) {
-    const int d = G->arity == 2 ? 4 : 2;
-    float2 m[16], t[16];
-    for (int i = 0; i < 16; ++i) m[i] = G->raw[i];
-    for (int s = sb; s < se; ++s) {
-      int site = g.gate_site_list[s];
-      int k = kr[site];
-      const float2* op = g.site_ops + ((int64_t)site * g.max_kraus + k) * 16;
-      for (int r = 0; r < d; ++r)
-        for (int c = 0; c < d; ++c) {
-          float2 acc = make_float2(0.f, 0.f);
-          for (int x = 0; x < d; ++x) acc = cfma(op[r * d + x], m[x * d + c], acc);
-          t[r * d + c] = acc;
-        }
-      for (int i = 0; i < d * d; ++i) m[i] = t[i];
-    }
-    for (int i = 0; i < 16; ++i) {
-      float2 v = m[i];
-      if (conj) v.y = -v.y;
-      out[i] = v;
-    }
+  const int d = G->arity == 2 ? 4 : 2;
+  float2 m[16], t[16];
+  for (int i = 0; i < 16; ++i) m[i] = G->raw[i];
+  for (int s = sb; s < se; ++s) {
+    const int site = g.gate_site_list[s];
+    const int k = kr[site];
+    const float2* op = g.site_ops + ((int64_t)site * g.max_kraus + k) * 16;
+    for (int r = 0; r < d; ++r)
+      for (int c = 0; c < d; ++c) {
+        float2 acc = make_float2(0.f, 0.f);
+        for (int x = 0; x < d; ++x) acc = cfma(op[r * d + x], m[x * d + c], acc);
+        t[r * d + c] = acc;
+      }
+    for (int i = 0; i < d * d; ++i) m[i] = t[i];
   }
+  for (int i = 0; i < 16; ++i) out[i] = m[i];
 }
 
-struct StepRegs {
-  int rA, rC, nK, nN, nH;
-  uint32_t kbase_mask;
-  int kpos[4], npos[4], hm[4], hw[4];
-  int koff[16], noff[16], kB[16], nB[16];
-  int sbase;
-};
+__global__ void upv_merge_kernel(GateCtx g, int64_t E, float2* __restrict__ merged) {
+  const int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (id >= E * g.G) return;
+  const int traj = (int)(id / g.G), gate = (int)(id % g.G);
+  float2 m[16];
+  merge_gate(g, gate, traj, m);
+  float4* o = reinterpret_cast<float4*>(merged + id * 16);
+  for (int i = 0; i < 8; ++i) o[i] = make_float4(m[2 * i].x, m[2 * i].y, m[2 * i + 1].x, m[2 * i + 1].y);
+}
 
-__device__ inline uint32_t insert_zero_bits(uint32_t m, const int* pos, int n) {
+// Gate entry i (< 16) of (traj, gate), conjugated for bra tensors.
+__device__ inline float2 gate_entry(const GateCtx& g, int gate, int traj, int conj, int i) {
+  float2 v = g.merged[((int64_t)traj * g.G + gate) * 16 + i];
+  if (conj) v.y = -v.y;
+  return v;
+}
+
+__device__ inline uint32_t insert_zero_bits(uint32_t m, const int32_t* pos, int n) {
   for (int i = 0; i < n; ++i) {
     const int p = pos[i];
     const uint32_t lo = m & ((1u << p) - 1u);
@@ -89,83 +88,87 @@ __device__ inline uint32_t insert_zero_bits(uint32_t m, const int* pos, int n) {
   return m;
 }
 
-__device__ inline void prepare_step(const AbsorbStep& st, const uint64_t* prefix, StepRegs& r) {
-  r.rA = st.rA; r.rC = st.rC; r.nK = st.nK; r.nN = st.nN; r.nH = st.nH;
-  for (int i = 0; i < 4; ++i) { r.kpos[i] = st.kpos[i]; r.npos[i] = st.npos[i]; r.hm[i] = st.hm[i]; r.hw[i] = st.hw[i]; }
-  for (int k = 0; k < (1 << st.nK); ++k) {
-    int o = 0, w = 0;
-    for (int i = 0; i < st.nK; ++i)
-      if ((k >> i) & 1) { o += 1 << st.kpos[i]; w += st.kw[i]; }
-    r.koff[k] = o; r.kB[k] = w;
-  }
-  for (int n = 0; n < (1 << st.nN); ++n) {
-    int o = 0, w = 0;
-    for (int i = 0; i < st.nN; ++i)
-      if ((n >> i) & 1) { o += 1 << st.npos[i]; w += st.nw[i]; }
-    r.noff[n] = o; r.nB[n] = w;
-  }
+__device__ inline int slice_base(const AbsorbStep& st, const uint64_t* prefix) {
   int sb = 0;
   for (int i = 0; i < st.nS; ++i) sb += (int)bit_of_prefix(prefix, st.sq[i]) * st.sw[i];
-  r.sbase = sb;
+  return sb;
 }
 
-// out[c] for all n of one kept index m
-__device__ inline void absorb_one(const StepRegs& r, uint32_t m, const float2* A, float2* C,
+// C entries of all n for one kept index m (tables precomputed by the planner)
+__device__ inline void absorb_one(const AbsorbStep& st, int sbase, uint32_t m, const float2* A, float2* C,
                                   const float2* Gm) {
   float2 a[16];
-  const uint32_t abase = insert_zero_bits(m, r.kpos, r.nK);
-  const int nk = 1 << r.nK;
+  const int nK = st.nK, nN = st.nN;
+  const uint32_t abase = insert_zero_bits(m, st.kpos, nK);
+  const int nk = 1 << nK;
   // A always holds the running tensor; before the first step it is the scalar 1
-  for (int k = 0; k < nk; ++k) a[k] = A[abase + r.koff[k]];
-  int hidx = r.sbase;
-  for (int i = 0; i < r.nH; ++i) hidx += (int)((m >> r.hm[i]) & 1u) * r.hw[i];
-  const uint32_t cbase = insert_zero_bits(m, r.npos, r.nN);
-  const int nn = 1 << r.nN;
+  for (int k = 0; k < nk; ++k) a[k] = A[abase + st.koff[k]];
+  int hidx = sbase;
+  for (int i = 0; i < st.nH; ++i) hidx += (int)((m >> st.hm[i]) & 1u) * st.hw[i];
+  const uint32_t cbase = insert_zero_bits(m, st.npos, nN);
+  const int nn = 1 << nN;
   for (int n = 0; n < nn; ++n) {
     float2 acc = make_float2(0.f, 0.f);
-    const int bn = hidx + r.nB[n];
-    for (int k = 0; k < nk; ++k) acc = cfma(a[k], Gm[bn + r.kB[k]], acc);
-    C[cbase + r.noff[n]] = acc;
+    const int bn = hidx + st.nB[n];
+    for (int k = 0; k < nk; ++k) acc = cfma(a[k], Gm[bn + st.kB[k]], acc);
+    C[cbase + st.noff[n]] = acc;
   }
 }
 
 // ------------------------------------------------------------------ LDS sweep
+__device__ inline uint32_t init_offset(const InitArgs& in, uint32_t m, const uint64_t* pw) {
+  for (int i = 0; i < in.nsl; ++i) {
+    const int p = in.pos[i];
+    const uint32_t lo = m & ((1u << p) - 1u);
+    m = ((m >> p) << (p + 1)) | (bit_of_prefix(pw, in.q[i]) << p) | lo;
+  }
+  return m;
+}
+
 __global__ void part_vm_kernel(const AbsorbStep* __restrict__ steps, int n_steps, int buf_elems,
                                GateCtx g, int64_t n_jobs, const int32_t* __restrict__ job_traj,
                                int32_t traj_base, const uint64_t* __restrict__ job_prefix, int NW,
-                               float2* __restrict__ out, int out_rank) {
+                               InitArgs init, float2* __restrict__ out, int out_rank) {
   extern __shared__ float2 lds[];
   float2* bufA = lds;
   float2* bufC = lds + buf_elems;
-  float2* Gm = lds + 2 * buf_elems;
-  uint64_t* pw = reinterpret_cast<uint64_t*>(Gm + 16);
+  float2* Gm = lds + 2 * buf_elems;              // two gate buffers of 16
+  uint64_t* pw = reinterpret_cast<uint64_t*>(Gm + 32);
   const int64_t job = blockIdx.x;
   if (job >= n_jobs) return;
+  const int tid = threadIdx.x;
   const int traj = job_traj ? job_traj[job] : traj_base + (int)job;
-  if (job_prefix) {
-    for (int w = threadIdx.x; w < NW; w += blockDim.x) pw[w] = job_prefix[job * NW + w];
-  } else {
-    for (int w = threadIdx.x; w < NW; w += blockDim.x) pw[w] = 0;
+  for (int w = tid; w < NW; w += blockDim.x) pw[w] = job_prefix ? job_prefix[job * NW + w] : 0ull;
+  if (init.Vprev) {
+    __syncthreads();
+    const float2* src = init.Vprev + (int64_t)init.parent[job] * init.stride;
+    for (uint32_t m = tid; m < (1u << init.r0); m += blockDim.x) bufA[m] = src[init_offset(init, m, pw)];
+  } else if (tid == 0) {
+    bufA[0] = make_float2(1.f, 0.f);
   }
-  if (threadIdx.x == 0) bufA[0] = make_float2(1.f, 0.f);
-  __syncthreads();
+  // the gate of the next step is loaded while the current step computes
+  float2 gnext = make_float2(0.f, 0.f);
+  if (tid < 16 && n_steps > 0) gnext = gate_entry(g, steps[0].gate, traj, steps[0].conj, tid);
   for (int s = 0; s < n_steps; ++s) {
     const AbsorbStep& st = steps[s];
-    load_gate_block(g, st.gate, traj, st.conj, Gm);
-    __syncthreads();
-    StepRegs r;
-    prepare_step(st, pw, r);
-    const uint32_t nm = 1u << (r.rC - r.nN);
-    for (uint32_t m = threadIdx.x; m < nm; m += blockDim.x) absorb_one(r, m, bufA, bufC, Gm);
-    __syncthreads();
+    float2* G = Gm + 16 * (s & 1);
+    if (tid < 16) G[tid] = gnext;
+    if (tid < 16 && s + 1 < n_steps) gnext = gate_entry(g, steps[s + 1].gate, traj, steps[s + 1].conj, tid);
+    __syncthreads();     // gate visible; previous step's C complete
+    const int sb = slice_base(st, pw);
+    const uint32_t nm = 1u << (st.rC - st.nN);
+    for (uint32_t m = tid; m < nm; m += blockDim.x) absorb_one(st, sb, m, bufA, bufC, G);
     float2* t = bufA; bufA = bufC; bufC = t;
   }
+  __syncthreads();
   const int64_t n_out = (int64_t)1 << out_rank;
   float2* o = out + job * n_out;
-  for (int64_t i = threadIdx.x; i < n_out; i += blockDim.x) o[i] = bufA[i];
+  for (int64_t i = tid; i < n_out; i += blockDim.x) o[i] = bufA[i];
 }
 
 // --------------------------------------------------------------- HBM sweep step
+constexpr uint32_t kAbsorbPerBlock = 2048;
+
 __global__ void absorb_global_kernel(const AbsorbStep* __restrict__ st_dev, GateCtx g, int64_t n_jobs,
                                      int64_t blocks_per_job, const int32_t* __restrict__ job_traj,
                                      int32_t traj_base, const uint64_t* __restrict__ job_prefix, int NW,
@@ -178,16 +181,30 @@ __global__ void absorb_global_kernel(const AbsorbStep* __restrict__ st_dev, Gate
   const AbsorbStep& st = *st_dev;
   const int traj = job_traj ? job_traj[job] : traj_base + (int)job;
   if (threadIdx.x < NW) pw[threadIdx.x] = job_prefix ? job_prefix[job * NW + threadIdx.x] : 0ull;
-  load_gate_block(g, st.gate, traj, st.conj, Gm);
+  if (threadIdx.x < 16) Gm[threadIdx.x] = gate_entry(g, st.gate, traj, st.conj, threadIdx.x);
   __syncthreads();
-  StepRegs r;
-  prepare_step(st, pw, r);
-  const uint32_t nm = 1u << (r.rC - r.nN);
-  const uint32_t m = (uint32_t)(chunk * blockDim.x + threadIdx.x);
-  if (m >= nm) return;
+  const int sb = slice_base(st, pw);
+  const uint32_t nm = 1u << (st.rC - st.nN);
   const float2* Aj = A + (job << st.rA);
   float2* Cj = C + (job << st.rC);
-  absorb_one(r, m, Aj, Cj, Gm);
+  // each block covers kAbsorbPerBlock kept indices (the gate load is amortised)
+  const uint32_t m0 = (uint32_t)(chunk * kAbsorbPerBlock);
+  for (uint32_t i = threadIdx.x; i < kAbsorbPerBlock; i += blockDim.x) {
+    const uint32_t m = m0 + i;
+    if (m >= nm) break;
+    absorb_one(st, sb, m, Aj, Cj, Gm);
+  }
+}
+
+__global__ void init_gather_kernel(InitArgs init, int64_t n_jobs, const uint64_t* __restrict__ job_prefix, int NW,
+                                   float2* __restrict__ out) {
+  const int64_t per = (int64_t)1 << init.r0;
+  const int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (id >= per * n_jobs) return;
+  const int64_t job = id / per;
+  const uint32_t m = (uint32_t)(id % per);
+  const uint64_t* pw = job_prefix + job * NW;
+  out[id] = init.Vprev[(int64_t)init.parent[job] * init.stride + init_offset(init, m, pw)];
 }
 
 __global__ void fill_one_kernel(float2* buf, int64_t n) {
@@ -247,18 +264,114 @@ __global__ void join_kernel(JoinArgs a) {
 // join: Tc[x][k][k'] with k' fastest (K = 2^lk_bits), via the plan's tables.
 __global__ void permute_T_kernel(const float2* __restrict__ T, int64_t t_stride, int64_t n_traj,
                                  const int64_t* __restrict__ tables, Plan::JoinDev jd, int xT_bits, int lk_bits,
-                                 float2* __restrict__ Tc) {
-  const int64_t per = (int64_t)1 << (xT_bits + 2 * lk_bits);
+                                 int lb_bits, float2* __restrict__ Tc) {
+  const int64_t per = (int64_t)1 << (xT_bits + lk_bits + lb_bits);
   const int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (id >= per * n_traj) return;
   const int64_t t = id / per, r = id % per;
-  const uint32_t K = 1u << lk_bits;
-  const uint32_t kb = (uint32_t)(r & (K - 1)), k = (uint32_t)((r >> lk_bits) & (K - 1));
-  const uint32_t x = (uint32_t)(r >> (2 * lk_bits));
+  const uint32_t kb = (uint32_t)(r & ((1u << lb_bits) - 1u));
+  const uint32_t k = (uint32_t)((r >> lb_bits) & ((1u << lk_bits) - 1u));
+  const uint32_t x = (uint32_t)(r >> (lb_bits + lk_bits));
   const int lo_x = xT_bits < 12 ? xT_bits : 12, lo_k = lk_bits < 12 ? lk_bits : 12;
+  const int lo_b = lb_bits < 12 ? lb_bits : 12;
   const int64_t off = tab(tables, jd.tx_lo, jd.tx_hi, lo_x, x) + tab(tables, jd.tk_lo, jd.tk_hi, lo_k, k) +
-                      tab(tables, jd.tb_lo, jd.tb_hi, lo_k, kb);
+                      tab(tables, jd.tb_lo, jd.tb_hi, lo_b, kb);
   Tc[id] = T[t * t_stride + off];
+}
+
+// MFMA join of the last (ket-only) batch: amp[e][o(x, xb)] = sum_k V[e][xb][k] Tc[t][x][k]
+// and pi = |amp|^2.  Rows (element, xb) of one trajectory are the M dimension, x
+// the N dimension (tiles of 16), k the reduction (K = 2^crossing).
+template <int K>
+__global__ void __launch_bounds__(256) ketjoin_mfma_kernel(QformArgs a) {
+  constexpr int ROWS = 64;
+  constexpr int KS = K / 4;
+  __shared__ float Tr[K][17], Ti[K][17];
+  __shared__ float2 Vs[ROWS][K + 1];
+  uint32_t bx, by, bz;
+  {
+    const uint32_t nbx = gridDim.x, nby = gridDim.y, total = nbx * nby * gridDim.z;
+    const uint32_t phys = blockIdx.x + nbx * (blockIdx.y + nby * blockIdx.z);
+    const uint32_t xcd = phys % 8u, slot = phys / 8u, q = total / 8u, r = total % 8u;
+    const uint32_t logical = xcd < r ? xcd * (q + 1) + slot : r * (q + 1) + (xcd - r) * q + slot;
+    bx = logical % nbx;
+    by = (logical / nbx) % nby;
+    bz = logical / (nbx * nby);
+  }
+  const int t = a.traj0 + (int)by;
+  const int64_t e_begin = a.first[t] > a.e_lo ? a.first[t] : a.e_lo;
+  const int64_t e_end = a.first[t + 1] < a.e_hi ? a.first[t + 1] : a.e_hi;
+  const int xb_bits = a.xb_bits;
+  const int64_t rows_t = (e_end - e_begin) << xb_bits;
+  const int64_t row0 = (int64_t)bx * ROWS;
+  if (row0 >= rows_t) return;
+  const int nx = 1 << a.xT_bits;
+  const int ntile = (nx + 15) / 16;
+  const int t_per = (ntile + gridDim.z - 1) / gridDim.z;
+  const int tile_begin = (int)bz * t_per;
+  const int tile_end = tile_begin + t_per < ntile ? tile_begin + t_per : ntile;
+  if (tile_begin >= tile_end) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lo_b = xb_bits < 12 ? xb_bits : 12, lo_k = a.lk_bits < 12 ? a.lk_bits : 12;
+  const int lo_x = a.xT_bits < 12 ? a.xT_bits : 12;
+  for (int i = tid; i < ROWS * K; i += 256) {
+    const int rr = i / K, k = i % K;
+    const int64_t row = row0 + rr;
+    float2 v = make_float2(0.f, 0.f);
+    if (row < rows_t) {
+      const int64_t e = e_begin + (row >> xb_bits);
+      const uint32_t xb = (uint32_t)(row & ((1 << xb_bits) - 1));
+      v = a.V[(e - a.v_base) * a.v_stride + tab(a.tab, a.jd.vr_lo, a.jd.vr_hi, lo_b, xb) +
+              tab(a.tab, a.jd.vc_lo, a.jd.vc_hi, lo_k, (uint32_t)k)];
+    }
+    Vs[rr][k] = v;
+  }
+  __syncthreads();
+  float ar[KS], ai[KS];
+  const int arow = wave * 16 + (lane & 15);
+#pragma unroll
+  for (int s = 0; s < KS; ++s) {
+    const float2 v = Vs[arow][4 * s + (lane >> 4)];
+    ar[s] = v.x;
+    ai[s] = v.y;
+  }
+  const float2* Tt = a.Tc + (int64_t)(t - a.traj_base) * ((int64_t)nx * K);
+  const int nout = 1 << a.b;
+  for (int tl = tile_begin; tl < tile_end; ++tl) {
+    const int x0 = tl * 16;
+    for (int i = tid; i < 16 * K; i += 256) {       // Tc[x0 + xi][k] -> Tr[k][xi]
+      const int xi = i / K, k = i % K;
+      const float2 v = x0 + xi < nx ? Tt[(int64_t)(x0 + xi) * K + k] : make_float2(0.f, 0.f);
+      Tr[k][xi] = v.x;
+      Ti[k][xi] = v.y;
+    }
+    __syncthreads();
+    floatx4 yr = {0.f, 0.f, 0.f, 0.f}, yi = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      const float br = Tr[4 * s + (lane >> 4)][lane & 15], bim = Ti[4 * s + (lane >> 4)][lane & 15];
+      yr = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[s], br, yr, 0, 0, 0);
+      yr = __builtin_amdgcn_mfma_f32_16x16x4f32(-ai[s], bim, yr, 0, 0, 0);
+      yi = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[s], bim, yi, 0, 0, 0);
+      yi = __builtin_amdgcn_mfma_f32_16x16x4f32(ai[s], br, yi, 0, 0, 0);
+    }
+    const int x = x0 + (lane & 15);
+    if (x < nx) {
+      const int64_t ox = tab(a.tab, a.jd.ox_lo, a.jd.ox_hi, lo_x, (uint32_t)x);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int64_t row = row0 + wave * 16 + 4 * (lane >> 4) + i;
+        if (row < rows_t) {
+          const int64_t e = e_begin + (row >> xb_bits);
+          const uint32_t xb = (uint32_t)(row & ((1 << xb_bits) - 1));
+          const int64_t o = (e - a.v_base) * nout + ox + tab(a.tab, a.jd.ob_lo, a.jd.ob_hi, lo_b, xb);
+          if (a.pop) a.pop[o] = yr[i] * yr[i] + yi[i] * yi[i];
+          if (a.amp) a.amp[o] = make_float2(yr[i], yi[i]);
+        }
+      }
+    }
+    __syncthreads();
+  }
 }
 
 // MFMA join of the doubled network (Sec. II-B marginals):
@@ -269,7 +382,6 @@ __global__ void permute_T_kernel(const float2* __restrict__ T, int64_t t_stride,
 // over a range of x, staging Tc[x] (real and imaginary planes) in LDS.  Complex
 // arithmetic = four real v_mfma_f32_16x16x4f32 products (Yr += Vr Tr - Vi Ti,
 // Yi += Vr Ti + Vi Tr).
-typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 template <int K>
 __global__ void __launch_bounds__(256) qform_mfma_kernel(QformArgs a) {
@@ -281,16 +393,29 @@ __global__ void __launch_bounds__(256) qform_mfma_kernel(QformArgs a) {
   __shared__ float Tr[2][K * TS];
   __shared__ float Ti[2][K * TS];
   __shared__ float2 Vs[ROWS][K + 1];
-  const int t = a.traj0 + blockIdx.y;                 // trajectory of this tile
+  // Workgroups go round-robin to the 8 XCDs in linear launch order; renumber them
+  // so that consecutive logical tiles (the row tiles of one trajectory, which all
+  // read that trajectory's T) run on the same XCD and share its L2.
+  uint32_t bx, by, bz;
+  {
+    const uint32_t nbx = gridDim.x, nby = gridDim.y, total = nbx * nby * gridDim.z;
+    const uint32_t phys = blockIdx.x + nbx * (blockIdx.y + nby * blockIdx.z);
+    const uint32_t xcd = phys % 8u, slot = phys / 8u, q = total / 8u, r = total % 8u;
+    const uint32_t logical = xcd < r ? xcd * (q + 1) + slot : r * (q + 1) + (xcd - r) * q + slot;
+    bx = logical % nbx;
+    by = (logical / nbx) % nby;
+    bz = logical / (nbx * nby);
+  }
+  const int t = a.traj0 + (int)by;                    // trajectory of this tile
   const int64_t e_begin = a.first[t] > a.e_lo ? a.first[t] : a.e_lo;
   const int64_t e_end = a.first[t + 1] < a.e_hi ? a.first[t + 1] : a.e_hi;
   const int xb_bits = a.xb_bits;
   const int64_t rows_t = (e_end - e_begin) << xb_bits;
-  const int64_t row0 = (int64_t)blockIdx.x * ROWS;
+  const int64_t row0 = (int64_t)bx * ROWS;
   if (row0 >= rows_t) return;
   const int nx = 1 << a.xT_bits;
   const int x_per = (nx + gridDim.z - 1) / gridDim.z;
-  const int x_begin = blockIdx.z * x_per;
+  const int x_begin = (int)bz * x_per;
   const int x_end = x_begin + x_per < nx ? x_begin + x_per : nx;
   if (x_begin >= x_end) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -554,6 +679,7 @@ __global__ void __launch_bounds__(kSampleThreads) children_kernel(ChildArgs a) {
     if (hist[x] == 0) continue;
     const int64_t c = cbase + rank[x];
     a.out_traj[c] = traj;
+    a.out_parent[c] = (int32_t)e;
     a.out_shot_off[c] = off + start[x];
     a.out_shot_cnt[c] = hist[x];
     uint64_t* op = a.out_prefix + c * a.NW;
@@ -684,15 +810,32 @@ __global__ void traj_first_kernel(const int32_t* elem_traj, int64_t U, int64_t E
 }  // namespace
 
 // ---------------------------------------------------------------------- launchers
+hipError_t launch_init_gather(const InitArgs& init, int64_t n_jobs, const uint64_t* job_prefix, int NW,
+                              float2* out, hipStream_t stream) {
+  const int64_t total = n_jobs << init.r0;
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(init_gather_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream, init, n_jobs,
+                     job_prefix, NW, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_part_vm(const AbsorbStep* d_steps, int n_steps, int peak, GateCtx g, int64_t n_jobs,
                           const int32_t* job_traj, int32_t traj_base, const uint64_t* job_prefix, int NW,
-                          float2* out, int out_rank, hipStream_t stream) {
+                          const InitArgs& init, float2* out, int out_rank, hipStream_t stream) {
   if (n_jobs <= 0) return hipSuccess;
   const int buf = 1 << (peak > 0 ? peak : 0);
-  const size_t shmem = (size_t)(2 * buf + 16) * sizeof(float2) + (size_t)NW * sizeof(uint64_t);
+  const size_t shmem = (size_t)(2 * buf + 32) * sizeof(float2) + (size_t)NW * sizeof(uint64_t);
+  // one wavefront per job while the tensor has <= 128 entries
   int threads = buf / 2 < 64 ? 64 : (buf / 2 > 256 ? 256 : buf / 2);
   hipLaunchKernelGGL(part_vm_kernel, dim3((unsigned)n_jobs), dim3(threads), shmem, stream, d_steps, n_steps,
-                     buf, g, n_jobs, job_traj, traj_base, job_prefix, NW, out, out_rank);
+                     buf, g, n_jobs, job_traj, traj_base, job_prefix, NW, init, out, out_rank);
+  return hipGetLastError();
+}
+
+hipError_t launch_upv_merge(GateCtx g, int64_t E, float2* merged, hipStream_t stream) {
+  const int64_t n = E * g.G;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(upv_merge_kernel, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, stream, g, E, merged);
   return hipGetLastError();
 }
 
@@ -702,7 +845,7 @@ hipError_t launch_absorb_global(const AbsorbStep& st, const AbsorbStep* d_st, Ga
   if (n_jobs <= 0) return hipSuccess;
   const int64_t nm = (int64_t)1 << (st.rC - st.nN);
   const int threads = 256;
-  const int64_t bpj = (nm + threads - 1) / threads;
+  const int64_t bpj = (nm + kAbsorbPerBlock - 1) / kAbsorbPerBlock;
   hipLaunchKernelGGL(absorb_global_kernel, dim3((unsigned)(bpj * n_jobs)), dim3(threads), 0, stream, d_st, g,
                      n_jobs, bpj, job_traj, traj_base, job_prefix, NW, A, C);
   return hipGetLastError();
@@ -722,15 +865,17 @@ hipError_t launch_join(const JoinArgs& a, hipStream_t stream) {
 }
 
 hipError_t launch_permute_T(const float2* T, int64_t t_stride, int64_t n_traj, const int64_t* tab,
-                            const Plan::JoinDev& jd, int xT_bits, int lk_bits, float2* Tc, hipStream_t stream) {
-  const int64_t total = n_traj << (xT_bits + 2 * lk_bits);
+                            const Plan::JoinDev& jd, int xT_bits, int lk_bits, int lb_bits, float2* Tc,
+                            hipStream_t stream) {
+  const int64_t total = n_traj << (xT_bits + lk_bits + lb_bits);
   if (total <= 0) return hipSuccess;
   hipLaunchKernelGGL(permute_T_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream, T, t_stride,
-                     n_traj, tab, jd, xT_bits, lk_bits, Tc);
+                     n_traj, tab, jd, xT_bits, lk_bits, lb_bits, Tc);
   return hipGetLastError();
 }
 
 bool qform_supported(int lk_bits) { return lk_bits == 4 || lk_bits == 5; }
+bool ketjoin_supported(int lk_bits) { return lk_bits >= 2 && lk_bits <= 6; }
 
 hipError_t launch_qform(const QformArgs& a, int n_traj, int max_rows, hipStream_t stream) {
   if (n_traj <= 0 || max_rows <= 0) return hipSuccess;
@@ -744,6 +889,25 @@ hipError_t launch_qform(const QformArgs& a, int n_traj, int max_rows, hipStream_
   if (a.lk_bits == 4) hipLaunchKernelGGL(qform_mfma_kernel<16>, grid, dim3(256), 0, stream, a);
   else if (a.lk_bits == 5) hipLaunchKernelGGL(qform_mfma_kernel<32>, grid, dim3(256), 0, stream, a);
   else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_ketjoin(const QformArgs& a, int n_traj, int max_rows, hipStream_t stream) {
+  if (n_traj <= 0 || max_rows <= 0) return hipSuccess;
+  const int tiles = (max_rows + 63) / 64;
+  const int ntile = ((1 << a.xT_bits) + 15) / 16;
+  int64_t wg = (int64_t)tiles * n_traj;
+  int zs = 1;
+  while (zs < ntile && wg * zs < 4096) zs *= 2;
+  dim3 grid((unsigned)tiles, (unsigned)n_traj, (unsigned)zs);
+  switch (a.lk_bits) {
+    case 2: hipLaunchKernelGGL(ketjoin_mfma_kernel<4>, grid, dim3(256), 0, stream, a); break;
+    case 3: hipLaunchKernelGGL(ketjoin_mfma_kernel<8>, grid, dim3(256), 0, stream, a); break;
+    case 4: hipLaunchKernelGGL(ketjoin_mfma_kernel<16>, grid, dim3(256), 0, stream, a); break;
+    case 5: hipLaunchKernelGGL(ketjoin_mfma_kernel<32>, grid, dim3(256), 0, stream, a); break;
+    case 6: hipLaunchKernelGGL(ketjoin_mfma_kernel<64>, grid, dim3(256), 0, stream, a); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

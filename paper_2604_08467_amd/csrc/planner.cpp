@@ -70,14 +70,14 @@ KetNet build_ket(const Plan& p) {
 
 // Simulate absorbing `order` into a running tensor; keep_open labels survive.
 bool simulate(const std::vector<const NetTensor*>& order, const std::set<int>& keep_open,
-              PartPlan& out, std::string& err) {
+              const std::vector<int>& init, PartPlan& out, std::string& err) {
   std::map<int, int> cnt;
   for (const NetTensor* t : order)
     for (int i = 0; i < t->nlegs; ++i)
       if (t->label[i] >= 0) cnt[t->label[i]]++;
-  std::vector<int> cur;
+  std::vector<int> cur = init;
+  out.peak = (int)init.size();
   out.steps.clear();
-  out.peak = 0;
   out.flops = out.bytes = 0;
   for (const NetTensor* t : order) {
     AbsorbStep st{};
@@ -157,7 +157,17 @@ bool simulate(const std::vector<const NetTensor*>& order, const std::set<int>& k
       if (chk != kept) { err = "internal layout error"; return false; }
     }
     st.rC = (int)C.size();
-    if (st.rC > 40 || st.rA > 40) { err = "intermediate too large"; return false; }
+    if (st.rC > 31 || st.rA > 31) { err = "intermediate too large"; return false; }
+    for (int k = 0; k < (1 << st.nK); ++k) {
+      st.koff[k] = 0; st.kB[k] = 0;
+      for (int i = 0; i < st.nK; ++i)
+        if ((k >> i) & 1) { st.koff[k] += 1u << st.kpos[i]; st.kB[k] += st.kw[i]; }
+    }
+    for (int n = 0; n < (1 << st.nN); ++n) {
+      st.noff[n] = 0; st.nB[n] = 0;
+      for (int i = 0; i < st.nN; ++i)
+        if ((n >> i) & 1) { st.noff[n] += 1u << st.npos[i]; st.nB[n] += st.nw[i]; }
+    }
     out.peak = std::max(out.peak, std::max(st.rA, st.rC));
     double m = std::ldexp(1.0, st.rC - st.nN);
     out.flops += 8.0 * m * std::ldexp(1.0, st.nN + st.nK);
@@ -192,12 +202,12 @@ std::vector<const NetTensor*> sorted_order(const std::vector<NetTensor>& ts, int
 // Randomised greedy sweep: repeatedly absorb the tensor that gives the smallest
 // running rank (ties: most contracted legs, then random).
 std::vector<const NetTensor*> greedy_order(const std::vector<NetTensor>& ts, const std::set<int>& keep_open,
-                                           std::mt19937_64& rng) {
+                                           const std::vector<int>& init, std::mt19937_64& rng) {
   std::map<int, int> cnt;
   for (auto& t : ts)
     for (int i = 0; i < t.nlegs; ++i)
       if (t.label[i] >= 0) cnt[t.label[i]]++;
-  std::set<int> cur;
+  std::set<int> cur(init.begin(), init.end());
   std::vector<char> used(ts.size(), 0);
   std::vector<const NetTensor*> order;
   std::uniform_real_distribution<double> U(0.0, 1.0);
@@ -240,12 +250,16 @@ std::vector<const NetTensor*> greedy_order(const std::vector<NetTensor>& ts, con
 }
 
 bool plan_part(const std::vector<NetTensor>& ts, const std::set<int>& keep_open, int hypersamples,
-               uint64_t seed, PartPlan& best, std::string& err) {
+               uint64_t seed, PartPlan& best, std::string& err, const std::vector<int>& init = {}) {
   best = PartPlan();
   best.cost = 1e300;
   if (ts.empty()) {
+    for (int L : init)
+      if (!keep_open.count(L)) { err = "label left open"; return false; }
     best.cost = 0;
     best.order_name = "empty";
+    best.labels = init;
+    best.peak = (int)init.size();
     return true;
   }
   struct Cand { const char* name; int cs, tsg; bool tm; };
@@ -257,7 +271,7 @@ bool plan_part(const std::vector<NetTensor>& ts, const std::set<int>& keep_open,
   for (const Cand& c : cands) {
     PartPlan pp;
     std::string e;
-    if (!simulate(sorted_order(ts, c.cs, c.tsg, c.tm), keep_open, pp, e)) { last_err = e; continue; }
+    if (!simulate(sorted_order(ts, c.cs, c.tsg, c.tm), keep_open, init, pp, e)) { last_err = e; continue; }
     pp.order_name = c.name;
     if (pp.cost < best.cost) best = pp;
     any = true;
@@ -266,7 +280,7 @@ bool plan_part(const std::vector<NetTensor>& ts, const std::set<int>& keep_open,
   for (int h = 0; h < hypersamples; ++h) {
     PartPlan pp;
     std::string e;
-    if (!simulate(greedy_order(ts, keep_open, rng), keep_open, pp, e)) { last_err = e; continue; }
+    if (!simulate(greedy_order(ts, keep_open, init, rng), keep_open, init, pp, e)) { last_err = e; continue; }
     pp.order_name = "greedy";
     if (pp.cost < best.cost) best = pp;
     any = true;
@@ -418,6 +432,41 @@ bool build_batch_plans(Plan& p, std::string& err) {
             " wires cross between the prefix part and the rest (limit 12)";
       return false;
     }
+    // Resume variant of the left part (used by the sampling loop): start from the
+    // parent element's left tensor of batch j-1, whose open batch legs are now
+    // prefix outputs and get sliced to the element's bits, and absorb only the
+    // gates that touch the newly projected qubits.
+    if (j >= 1) {
+      const BatchPlan& pv = p.batches[j - 1];
+      const std::vector<int>& plabels = (j - 1 == 0) ? pv.left.labels : pv.left_resume.labels;
+      std::set<int> pgates(pv.left_gates.begin(), pv.left_gates.end());
+      std::vector<int> init;
+      std::vector<std::pair<int, int>> sl;   // (position in parent tensor, qubit)
+      for (size_t i = 0; i < plabels.size(); ++i) {
+        auto it = std::find(pv.xb.begin(), pv.xb.end(), plabels[i]);
+        if (it != pv.xb.end()) sl.push_back({(int)i, pv.xb_qubits[it - pv.xb.begin()]});
+        else init.push_back(plabels[i]);
+      }
+      std::vector<NetTensor> delta;
+      for (auto& t : left)
+        if (!pgates.count(t.gate)) delta.push_back(t);
+      if (!plan_part(delta, keep_left, p.hypersamples, p.path_seed * 1315423911ULL + 2 * j + 7, bp.left_resume, e1,
+                     init)) {
+        err = "batch " + std::to_string(j) + " resumed left part: " + e1;
+        return false;
+      }
+      bp.resume_rank0 = (int)init.size();
+      bp.resume_parent_rank = (int)plabels.size();
+      for (auto& x : sl) { bp.resume_slice_pos.push_back(x.first); bp.resume_slice_q.push_back(x.second); }
+      if (bp.resume_slice_pos.size() > 8) {
+        err = "batch " + std::to_string(j) + ": too many open batch legs on the prefix part";
+        return false;
+      }
+      bp.v_row_r = make_table(bp.xb, bp.left_resume.labels);
+      bp.v_col_r = make_table(bp.lk, bp.left_resume.labels);
+    }
+    for (auto& t : left) bp.left_gates.push_back(t.gate);
+    bp.xb_qubits = xb_q;
     // join tables
     bp.v_row = make_table(bp.xb, bp.left.labels);
     bp.v_col = make_table(bp.lk, bp.left.labels);
