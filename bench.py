@@ -21,6 +21,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 FP32_MFMA_PEAK_TFLOPS = 157.3
+BF16_MFMA_PEAK_TFLOPS = 2500.0
 
 
 def cpu_baseline(wl, kr, budget_s=20.0):
@@ -64,6 +65,8 @@ def main():
     ap.add_argument("--shots", type=int, default=1000)
     ap.add_argument("--workspace-gb", type=float, default=64.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--precision", choices=["c64", "bf16"], default="c64",
+                    help="bf16: split-precision (bf16 hi+lo) MFMA for the dense join")
     ap.add_argument("--traffic-file", default=os.path.join(ROOT, "profiles", "join_traffic.txt"))
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 1 GiB device copy (reference for HBM byte counters)")
@@ -92,7 +95,7 @@ def main():
     dev = torch.device("cuda:0")
     wl = W.config2()
     c = wl.circuit
-    plan = P.Plan(c, wl.batch_sizes, hypersamples=8)
+    plan = P.Plan(c, wl.batch_sizes, hypersamples=8, precision=1 if args.precision == "bf16" else 0)
     kr, mult, _, n_draws = plan.sample_trajectories(wl.pts_seed, args.traj)
     E = len(kr)
     kd = torch.from_numpy(kr).to(dev)
@@ -127,14 +130,17 @@ def main():
         for ln in open(args.traffic_file):
             if ln.startswith("bytes_per_launch:"):
                 traffic = float(ln.split(":", 1)[1])
-    roofline = {"bound": "mfma", "achieved": achieved, "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / FP32_MFMA_PEAK_TFLOPS, "traffic": traffic,
-                "kernel": "join (prefix part x per-trajectory part, FP32)",
+    peak = FP32_MFMA_PEAK_TFLOPS if args.precision == "c64" else BF16_MFMA_PEAK_TFLOPS
+    roofline = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                "frac": achieved / peak, "traffic": traffic if args.precision == "c64" else None,
+                "kernel": "qform_mfma_kernel<32> (doubled-network join, FP32 MFMA)" if args.precision == "c64"
+                          else "qform_split_bf16_kernel (doubled-network join, bf16x3 MFMA)",
                 "launches": prof["join_launches"], "kernel_ms_per_step": prof["join_ms"] / args.steps}
     line = {
         "metric": "sampled shots/sec", "value": shots_per_s, "unit": "shots/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c64",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "c64" if args.precision == "c64" else "c64+bf16x3",
         "data": "synthetic",
         "config": {"workload": f"50-qubit 1D brickwork depth 6, Haar SU(4) c64, depolarising p=0.005, "
                                f"{E} trajectories x {args.shots} shots, batches [10]*5, proportional NBS",

@@ -275,7 +275,10 @@ ptsbe_status_t run_batch(Plan& p, int j, const uint8_t* d_kraus, const float2* m
         qa.amp = ja.amp;
         if (use_qform) {
           if (!qa.pop) return fail(PTSBE_ERR_INVALID_ARG, "population output required");
-          HIP_TRY(ptsbe::launch_qform(qa, (int)(tB - tA + 1), (int)max_rows, s));
+          if (p.precision == PTSBE_SPLIT_BF16 && ptsbe::qform_split_supported(lkb))
+            HIP_TRY(ptsbe::launch_qform_split(qa, (int)(tB - tA + 1), (int)max_rows, s));
+          else
+            HIP_TRY(ptsbe::launch_qform(qa, (int)(tB - tA + 1), (int)max_rows, s));
         } else {
           HIP_TRY(ptsbe::launch_ketjoin(qa, (int)(tB - tA + 1), (int)max_rows, s));
         }
@@ -339,11 +342,13 @@ ptsbe_status_t ptsbe_plan(const ptsbe_circuit_t* c, const ptsbe_plan_opts_t* o, 
   if (c->n_channels > 0 && (!c->ch_arity || !c->ch_nkraus || !c->ch_kraus))
     return fail(PTSBE_ERR_INVALID_ARG, "bad channel arrays");
   if (o->n_batches < 1 || !o->batch_sizes) return fail(PTSBE_ERR_INVALID_ARG, "no batches");
-  if (o->precision != PTSBE_C64) return fail(PTSBE_ERR_UNSUPPORTED, "only complex64 precision is implemented");
+  if (o->precision != PTSBE_C64 && o->precision != PTSBE_SPLIT_BF16)
+    return fail(PTSBE_ERR_UNSUPPORTED, "precision must be PTSBE_C64 or PTSBE_SPLIT_BF16");
   auto p = new Plan();
   std::unique_ptr<Plan> guard(p);
   p->n = c->n_qubits;
   p->NW = (p->n + 63) / 64;
+  p->precision = o->precision;
   p->device = o->device;
   p->hypersamples = std::max(1, o->hypersamples);
   p->path_seed = o->path_seed;

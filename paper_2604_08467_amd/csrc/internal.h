@@ -86,6 +86,7 @@ struct DeviceGate {
 
 struct Plan {
   int device = 0;
+  int precision = PTSBE_C64;
   int n = 0, G = 0, S = 0, NW = 1, max_kraus = 1;
   std::vector<int> arity;
   std::vector<std::array<int, 2>> qubits;
@@ -193,6 +194,9 @@ hipError_t launch_permute_T(const float2* T, int64_t t_stride, int64_t n_traj, c
                             hipStream_t stream);
 bool qform_supported(int lk_bits);
 bool ketjoin_supported(int lk_bits);
+bool qform_split_supported(int lk_bits);
+// split-precision (bf16 hi + lo, three products, FP32 accumulate) doubled join
+hipError_t launch_qform_split(const QformArgs& a, int n_traj, int max_rows, hipStream_t stream);
 hipError_t launch_qform(const QformArgs& a, int n_traj, int max_rows, hipStream_t stream);
 hipError_t launch_ketjoin(const QformArgs& a, int n_traj, int max_rows, hipStream_t stream);
 hipError_t launch_row_totals(const float* pop, int64_t n_elems, int b, double* totals,

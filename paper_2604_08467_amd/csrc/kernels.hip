@@ -279,6 +279,154 @@ __global__ void permute_T_kernel(const float2* __restrict__ T, int64_t t_stride,
   Tc[id] = T[t * t_stride + off];
 }
 
+// Split-precision variant of the doubled-network join (K = 32): every operand
+// x = hi + lo with hi = bf16(x), lo = bf16(x - hi); each real product is
+// hi*hi + hi*lo + lo*hi on v_mfma_f32_16x16x32_bf16 with FP32 accumulation.
+// The complex GEMM Y = V T is two real GEMMs of reduction length 2K:
+// Yr = [Vr | -Vi] [Tr ; Ti], Yi = [Vr | Vi] [Ti ; Tr].  T blocks are split into
+// four bf16 planes in LDS, stored transposed ([k'][k]) so that a lane's eight
+// consecutive k of one column are one 16-byte read.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+__global__ void __launch_bounds__(256) qform_split_bf16_kernel(QformArgs a) {
+  constexpr int K = 32, ROWS = 64, NH = 2, KP = K + 8;   // KP: padded row of a plane
+  constexpr int PER = K * K / 256;
+  __shared__ __attribute__((aligned(16))) __bf16 Tp[2][4][K][KP];   // planes: r_hi, r_lo, i_hi, i_lo
+  __shared__ float2 Vs[ROWS][K + 1];
+  uint32_t bx, by, bz;
+  {
+    const uint32_t nbx = gridDim.x, nby = gridDim.y, total = nbx * nby * gridDim.z;
+    const uint32_t phys = blockIdx.x + nbx * (blockIdx.y + nby * blockIdx.z);
+    const uint32_t xcd = phys % 8u, slot = phys / 8u, q = total / 8u, r = total % 8u;
+    const uint32_t logical = xcd < r ? xcd * (q + 1) + slot : r * (q + 1) + (xcd - r) * q + slot;
+    bx = logical % nbx;
+    by = (logical / nbx) % nby;
+    bz = logical / (nbx * nby);
+  }
+  const int t = a.traj0 + (int)by;
+  const int64_t e_begin = a.first[t] > a.e_lo ? a.first[t] : a.e_lo;
+  const int64_t e_end = a.first[t + 1] < a.e_hi ? a.first[t + 1] : a.e_hi;
+  const int xb_bits = a.xb_bits;
+  const int64_t rows_t = (e_end - e_begin) << xb_bits;
+  const int64_t row0 = (int64_t)bx * ROWS;
+  if (row0 >= rows_t) return;
+  const int nx = 1 << a.xT_bits;
+  const int x_per = (nx + gridDim.z - 1) / gridDim.z;
+  const int x_begin = (int)bz * x_per;
+  const int x_end = x_begin + x_per < nx ? x_begin + x_per : nx;
+  if (x_begin >= x_end) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lo_b = xb_bits < 12 ? xb_bits : 12, lo_k = a.lk_bits < 12 ? a.lk_bits : 12;
+  for (int i = tid; i < ROWS * K; i += 256) {
+    const int rr = i / K, k = i % K;
+    const int64_t row = row0 + rr;
+    float2 v = make_float2(0.f, 0.f);
+    if (row < rows_t) {
+      const int64_t e = e_begin + (row >> xb_bits);
+      const uint32_t xb = (uint32_t)(row & ((1 << xb_bits) - 1));
+      v = a.V[(e - a.v_base) * a.v_stride + tab(a.tab, a.jd.vr_lo, a.jd.vr_hi, lo_b, xb) +
+              tab(a.tab, a.jd.vc_lo, a.jd.vc_hi, lo_k, (uint32_t)k)];
+    }
+    Vs[rr][k] = v;
+  }
+  const float2* Tt = a.Tc + (int64_t)(t - a.traj_base) * ((int64_t)nx * K * K);
+  auto store_split = [&](int buf, int idx, float2 v) {
+    const int k = idx / K, kp = idx % K;          // Tc index = k * K + kp
+    const __bf16 rh = (__bf16)v.x, ih = (__bf16)v.y;
+    Tp[buf][0][kp][k] = rh;
+    Tp[buf][1][kp][k] = (__bf16)(v.x - (float)rh);
+    Tp[buf][2][kp][k] = ih;
+    Tp[buf][3][kp][k] = (__bf16)(v.y - (float)ih);
+  };
+  {
+    const float2* src = Tt + (int64_t)x_begin * K * K;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) store_split(0, tid + 256 * i, src[tid + 256 * i]);
+  }
+  __syncthreads();
+  // A fragments: lane holds row wave*16 + lane%16, k = 8*(lane/16) + 0..7
+  bf16x8 arh, arl, aih, ail, naih, nail;
+  {
+    const int row = wave * 16 + (lane & 15), kb = 8 * (lane >> 4);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const float2 v = Vs[row][kb + i];
+      const __bf16 rh = (__bf16)v.x, ih = (__bf16)v.y;
+      const __bf16 rl = (__bf16)(v.x - (float)rh), il = (__bf16)(v.y - (float)ih);
+      arh[i] = rh; arl[i] = rl; aih[i] = ih; ail[i] = il;
+      naih[i] = -ih; nail[i] = -il;
+    }
+  }
+  const int nout = 1 << a.b;
+  const int lo_x = a.xT_bits < 12 ? a.xT_bits : 12;
+  int buf = 0;
+  for (int x = x_begin; x < x_end; ++x) {
+    const bool more = x + 1 < x_end;
+    float2 nxt[PER];
+    if (more) {
+      const float2* src = Tt + (int64_t)(x + 1) * K * K;
+#pragma unroll
+      for (int i = 0; i < PER; ++i) nxt[i] = src[tid + 256 * i];
+    }
+    float p[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int h = 0; h < NH; ++h) {
+      const int c = 16 * h + (lane & 15), kb = 8 * (lane >> 4);
+      const bf16x8 brh = *reinterpret_cast<const bf16x8*>(&Tp[buf][0][c][kb]);
+      const bf16x8 brl = *reinterpret_cast<const bf16x8*>(&Tp[buf][1][c][kb]);
+      const bf16x8 bih = *reinterpret_cast<const bf16x8*>(&Tp[buf][2][c][kb]);
+      const bf16x8 bil = *reinterpret_cast<const bf16x8*>(&Tp[buf][3][c][kb]);
+      floatx4 yr = {0.f, 0.f, 0.f, 0.f}, yi = {0.f, 0.f, 0.f, 0.f};
+      yr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arh, brh, yr, 0, 0, 0);
+      yr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arh, brl, yr, 0, 0, 0);
+      yr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arl, brh, yr, 0, 0, 0);
+      yr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(naih, bih, yr, 0, 0, 0);
+      yr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(naih, bil, yr, 0, 0, 0);
+      yr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nail, bih, yr, 0, 0, 0);
+      yi = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arh, bih, yi, 0, 0, 0);
+      yi = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arh, bil, yi, 0, 0, 0);
+      yi = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arl, bih, yi, 0, 0, 0);
+      yi = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aih, brh, yi, 0, 0, 0);
+      yi = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aih, brl, yi, 0, 0, 0);
+      yi = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ail, brh, yi, 0, 0, 0);
+      const int kc = 16 * h + (lane & 15);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const float2 v = Vs[wave * 16 + 4 * (lane >> 4) + i][kc];
+        p[i] += yr[i] * v.x + yi[i] * v.y;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      float v = p[i];
+      v += __shfl_xor(v, 1);
+      v += __shfl_xor(v, 2);
+      v += __shfl_xor(v, 4);
+      v += __shfl_xor(v, 8);
+      p[i] = v;
+    }
+    if ((lane & 15) == 0) {
+      const int64_t ox = tab(a.tab, a.jd.ox_lo, a.jd.ox_hi, lo_x, (uint32_t)x);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int64_t row = row0 + wave * 16 + 4 * (lane >> 4) + i;
+        if (row < rows_t) {
+          const int64_t e = e_begin + (row >> xb_bits);
+          const uint32_t xb = (uint32_t)(row & ((1 << xb_bits) - 1));
+          const int64_t o = ox + tab(a.tab, a.jd.ob_lo, a.jd.ob_hi, lo_b, xb);
+          a.pop[(e - a.v_base) * nout + o] = p[i];
+        }
+      }
+    }
+    if (more) {
+#pragma unroll
+      for (int i = 0; i < PER; ++i) store_split(buf ^ 1, tid + 256 * i, nxt[i]);
+    }
+    __syncthreads();
+    buf ^= 1;
+  }
+}
+
 // MFMA join of the last (ket-only) batch: amp[e][o(x, xb)] = sum_k V[e][xb][k] Tc[t][x][k]
 // and pi = |amp|^2.  Rows (element, xb) of one trajectory are the M dimension, x
 // the N dimension (tiles of 16), k the reduction (K = 2^crossing).
@@ -875,6 +1023,20 @@ hipError_t launch_permute_T(const float2* T, int64_t t_stride, int64_t n_traj, c
 }
 
 bool qform_supported(int lk_bits) { return lk_bits == 4 || lk_bits == 5; }
+bool qform_split_supported(int lk_bits) { return lk_bits == 5; }
+
+hipError_t launch_qform_split(const QformArgs& a, int n_traj, int max_rows, hipStream_t stream) {
+  if (n_traj <= 0 || max_rows <= 0) return hipSuccess;
+  if (a.lk_bits != 5) return hipErrorInvalidValue;
+  const int tiles = (max_rows + 63) / 64;
+  const int nx = 1 << a.xT_bits;
+  int64_t wg = (int64_t)tiles * n_traj;
+  int zs = 1;
+  while (zs < nx && wg * zs < 4096) zs *= 2;
+  dim3 grid((unsigned)tiles, (unsigned)n_traj, (unsigned)zs);
+  hipLaunchKernelGGL(qform_split_bf16_kernel, grid, dim3(256), 0, stream, a);
+  return hipGetLastError();
+}
 bool ketjoin_supported(int lk_bits) { return lk_bits >= 2 && lk_bits <= 6; }
 
 hipError_t launch_qform(const QformArgs& a, int n_traj, int max_rows, hipStream_t stream) {

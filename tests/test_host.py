@@ -130,7 +130,7 @@ def test_error_codes():
     off.add_site(g, (2,), ch)                                         # site qubit not on the gate
     _expect_status(1, lambda: P.Plan(off, [3], device=-1))
     _expect_status(3, lambda: P.Plan(c, [10], device=-1, device_budget_bytes=64))
-    _expect_status(2, lambda: P.Plan(c, [10], device=-1, precision=1))
+    _expect_status(2, lambda: P.Plan(c, [10], device=-1, precision=2))   # split FP16: not built
 
 
 def test_untouched_qubit_gets_identity():
