@@ -207,6 +207,41 @@ ptsbe_status_t ptsbe_sample_shots(ptsbe_plan_t plan, const uint8_t* d_kraus_idx,
                                   double* d_traj_norm, int64_t* stats_out, void* d_workspace,
                                   size_t workspace_bytes, void* stream);
 
+/* Differentiation of trajectory-averaged observables (an addition to the
+ * paper's method; its networks and UPV merge are reused).
+ *   - Rotation gates: gate g with gate_param[g] >= 0 has matrix
+ *     exp(-i theta[gate_param[g]] P / 2), P = X, Y, Z for gate_axis[g] = 0, 1, 2;
+ *     its matrix in the plan's circuit is ignored.  Several gates may share a
+ *     parameter.
+ *   - Observable O = sum_t zz_coef[t] Z_{zz_qubits[2t]} Z_{zz_qubits[2t+1]}.
+ *   - Error sets are fixed; f = sum_i w_i <psi_i|O|psi_i> with psi_i the UPV-merged
+ *     gates (Sec. III-A) applied in circuit order to |0...0> (n_qubits <= 30).
+ *   - Gradient by the adjoint contraction: lambda_N = O psi_N,
+ *     lambda_{k-1} = A_k^dag lambda_k and df/dtheta += 2 w_i Re <lambda_k|(dA_k/dtheta) psi_{k-1}>,
+ *     where dA_k = (inserted operators of gate k) . dU_k/dtheta.  States psi_k are
+ *     checkpointed every checkpoint_every gates in the forward pass and
+ *     recomputed segment by segment in the backward pass (valid for non-unitary
+ *     Kraus operators as well). */
+typedef struct {
+  int32_t n_params;
+  const int32_t* gate_param;    /* [n_gates] (host) parameter index, -1 for fixed */
+  const int32_t* gate_axis;     /* [n_gates] (host) 0 X, 1 Y, 2 Z                  */
+  int32_t n_terms;
+  const int32_t* zz_qubits;     /* [n_terms][2] (host)                             */
+  const double* zz_coef;        /* [n_terms] (host)                                */
+  int32_t checkpoint_every;     /* >= 1                                            */
+} ptsbe_grad_spec_t;
+
+ptsbe_status_t ptsbe_expect_workspace_size(ptsbe_plan_t plan, const ptsbe_grad_spec_t* spec, int64_t E,
+                                           size_t* bytes);
+/*   d_kraus_idx [E][n_sites] uint8, d_weights [E] double w_i, d_theta [n_params] double;
+ *   outputs: d_traj_value [E] <psi_i|O|psi_i> (may be NULL), d_value [1] f,
+ *   d_grad [n_params] df/dtheta (NULL: value only).  Synchronises `stream`. */
+ptsbe_status_t ptsbe_expect_grad(ptsbe_plan_t plan, const ptsbe_grad_spec_t* spec, const uint8_t* d_kraus_idx,
+                                 int64_t E, const double* d_weights, const double* d_theta,
+                                 double* d_traj_value, double* d_value, double* d_grad, void* d_workspace,
+                                 size_t workspace_bytes, void* stream);
+
 /* Timing hook for measurement: when enabled, the library records HIP events (on
  * the launch stream) around every launch of the MFMA join of doubled networks
  * and accumulates its total time (milliseconds), launch count and algorithmic

@@ -14,7 +14,7 @@ import numpy as np
 from . import _lib
 from ._lib import PtsbeError
 
-__all__ = ["Plan", "PtsbeError", "load_library", "OUT_POPULATION", "OUT_AMPLITUDE"]
+__all__ = ["Plan", "PtsbeError", "GradSpec", "ExpectZZ", "load_library", "OUT_POPULATION", "OUT_AMPLITUDE"]
 
 OUT_POPULATION = 0
 OUT_AMPLITUDE = 1
@@ -70,6 +70,20 @@ class _CircuitArrays:
             _ptr(self.ch_nkraus, C.c_int32), _ptr(self.ch_kraus, C.c_double), _ptr(self.ch_prob, C.c_double),
             S, _ptr(self.site_gate, C.c_int32), _ptr(self.site_qubits, C.c_int32),
             _ptr(self.site_channel, C.c_int32))
+
+
+class GradSpec:
+    """Rotation gates and ZZ observable for Plan.expect_grad (ptsbe_grad_spec_t)."""
+
+    def __init__(self, n_params, gate_param, gate_axis, terms, checkpoint_every=16):
+        self.n_params = int(n_params)
+        self.gate_param = np.ascontiguousarray(gate_param, dtype=np.int32)
+        self.gate_axis = np.ascontiguousarray(gate_axis, dtype=np.int32)
+        self.zz_qubits = np.ascontiguousarray([q for (q, _c) in terms] or [(0, 0)], dtype=np.int32).reshape(-1)
+        self.zz_coef = np.ascontiguousarray([cf for (_q, cf) in terms] or [0.0], dtype=np.float64)
+        self.struct = _lib.GradSpec_t(self.n_params, _ptr(self.gate_param, C.c_int32), _ptr(self.gate_axis, C.c_int32),
+                                      len(terms), _ptr(self.zz_qubits, C.c_int32), _ptr(self.zz_coef, C.c_double),
+                                      int(checkpoint_every))
 
 
 class Plan:
@@ -184,6 +198,25 @@ class Plan:
         return {"shots": shots[:M], "shot_traj": None if shot_traj is None else shot_traj[:M],
                 "weights": weights, "norms": norms, "elements_per_batch": stats}
 
+    def expect_grad(self, spec, kraus_dev, weights_dev, theta_dev, want_grad=True, workspace=None, stream=None):
+        """ptsbe_expect_grad: value, per-trajectory values and (optionally) the gradient."""
+        import torch
+        E = kraus_dev.shape[0]
+        dev = kraus_dev.device
+        value = torch.empty(1, dtype=torch.float64, device=dev)
+        traj = torch.empty(E, dtype=torch.float64, device=dev)
+        grad = torch.empty(max(spec.n_params, 1), dtype=torch.float64, device=dev) if want_grad else None
+        if workspace is None:
+            b = C.c_size_t()
+            _lib.check(self._lib.ptsbe_expect_workspace_size(self._h, C.byref(spec.struct), int(E), C.byref(b)))
+            workspace = torch.empty(b.value, dtype=torch.uint8, device=dev)
+        if stream is None:
+            stream = torch.cuda.current_stream(dev).cuda_stream
+        _lib.check(self._lib.ptsbe_expect_grad(
+            self._h, C.byref(spec.struct), _tptr(kraus_dev), int(E), _tptr(weights_dev), _tptr(theta_dev),
+            _tptr(traj), _tptr(value), _tptr(grad), _tptr(workspace), int(workspace.numel()), C.c_void_p(stream)))
+        return {"value": value[0], "traj_values": traj, "grad": None if grad is None else grad[:spec.n_params]}
+
     # -------------------------------------------------------------- measurement
     def profile_enable(self, on=True):
         _lib.check(self._lib.ptsbe_profile_enable(self._h, 1 if on else 0))
@@ -195,3 +228,38 @@ class Plan:
                                                 C.byref(e)))
         return {"join_ms": a.value, "join_launches": b.value, "join_flops": c.value, "sweep_ms": d.value,
                 "sweep_bytes": e.value}
+
+
+def _expect_zz_function():
+    import torch
+
+    class ExpectZZ(torch.autograd.Function):
+        """f(theta) = sum_i w_i <psi_i(theta)|O|psi_i(theta)> through the HIP library;
+        the forward call also runs the adjoint contraction, whose gradient the
+        backward returns (scaled by the incoming gradient)."""
+
+        @staticmethod
+        def forward(ctx, theta, plan, spec, kraus_dev, weights_dev):
+            out = plan.expect_grad(spec, kraus_dev, weights_dev, theta.detach().to(torch.float64).contiguous(),
+                                   want_grad=True)
+            ctx.save_for_backward(out["grad"].to(theta.dtype))
+            return out["value"].to(theta.dtype)
+
+        @staticmethod
+        def backward(ctx, gout):
+            (g,) = ctx.saved_tensors
+            return gout * g, None, None, None, None
+
+    return ExpectZZ
+
+
+class _Lazy:
+    _cls = None
+
+    def __getattr__(self, name):
+        if _Lazy._cls is None:
+            _Lazy._cls = _expect_zz_function()
+        return getattr(_Lazy._cls, name)
+
+
+ExpectZZ = _Lazy()

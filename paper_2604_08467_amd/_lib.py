@@ -15,6 +15,7 @@ EXPORTS = [
     "ptsbe_plan", "ptsbe_plan_query", "ptsbe_plan_batch_info", "ptsbe_plan_destroy", "ptsbe_last_error",
     "ptsbe_sample_trajectories", "ptsbe_contract_workspace_size", "ptsbe_sample_workspace_size",
     "ptsbe_contract_batch", "ptsbe_sample_shots", "ptsbe_profile_enable", "ptsbe_profile_read",
+    "ptsbe_expect_workspace_size", "ptsbe_expect_grad",
 ]
 
 
@@ -63,6 +64,14 @@ class BatchInfo_t(C.Structure):
     ]
 
 
+class GradSpec_t(C.Structure):
+    _fields_ = [
+        ("n_params", C.c_int32), ("gate_param", C.POINTER(C.c_int32)), ("gate_axis", C.POINTER(C.c_int32)),
+        ("n_terms", C.c_int32), ("zz_qubits", C.POINTER(C.c_int32)), ("zz_coef", C.POINTER(C.c_double)),
+        ("checkpoint_every", C.c_int32),
+    ]
+
+
 _lib = None
 
 
@@ -90,6 +99,8 @@ def load():
     lib.ptsbe_profile_enable.argtypes = [P, i32]
     lib.ptsbe_profile_read.argtypes = [P, C.POINTER(C.c_double), C.POINTER(i64), C.POINTER(C.c_double),
                                        C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    lib.ptsbe_expect_workspace_size.argtypes = [P, C.POINTER(GradSpec_t), i64, C.POINTER(sz)]
+    lib.ptsbe_expect_grad.argtypes = [P, C.POINTER(GradSpec_t), P, i64, P, P, P, P, P, P, sz, P]
     for name in EXPORTS:
         f = getattr(lib, name)
         if name not in ("ptsbe_last_error", "ptsbe_plan_destroy"):

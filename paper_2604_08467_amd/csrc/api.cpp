@@ -19,20 +19,7 @@
 using ptsbe::Plan;
 
 namespace {
-
-thread_local std::string g_last_error;
-
-ptsbe_status_t fail(ptsbe_status_t s, const std::string& msg) {
-  g_last_error = msg;
-  return s;
-}
-
-#define HIP_TRY(expr)                                                                  \
-  do {                                                                                 \
-    hipError_t e_ = (expr);                                                            \
-    if (e_ != hipSuccess)                                                              \
-      return fail(PTSBE_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
-  } while (0)
+using ptsbe::fail;
 
 using cd = std::complex<double>;
 
@@ -73,20 +60,19 @@ void matmul(const cd* a, const cd* b, cd* c, int d) {
     }
 }
 
-struct Arena {
-  char* base = nullptr;
-  size_t cap = 0, used = 0;
-  void* take(size_t bytes) {
-    size_t off = (used + 255) & ~(size_t)255;
-    if (off + bytes > cap) return nullptr;
-    used = off + bytes;
-    return base + off;
-  }
-  size_t left() const {
-    size_t off = (used + 255) & ~(size_t)255;
-    return off >= cap ? 0 : cap - off;
-  }
-};
+using ptsbe::Arena;
+
+}  // namespace
+
+namespace ptsbe {
+thread_local std::string g_last_error;
+ptsbe_status_t fail(ptsbe_status_t s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+}  // namespace ptsbe
+
+namespace {
 
 ptsbe::GateCtx gate_ctx(const Plan& p, const uint8_t* kraus, const float2* merged) {
   ptsbe::GateCtx g;
@@ -134,15 +120,24 @@ ptsbe_status_t run_part(Plan& p, const ptsbe::PartPlan& pp, const ptsbe::AbsorbS
   if (!b0 || !b1) return fail(PTSBE_ERR_OUT_OF_MEMORY, "workspace too small for a sweep");
   if (init.Vprev) HIP_TRY(ptsbe::launch_init_gather(init, n_jobs, job_prefix, p.NW, b0, s));
   else HIP_TRY(ptsbe::launch_fill_one(b0, n_jobs, s));   // rank-0 start: the scalar 1 per job
-  const float2* A = b0;
-  for (size_t i = 0; i < pp.steps.size(); ++i) {
-    float2* C = (i + 1 == pp.steps.size()) ? out : (A == b0 ? b1 : b0);
+  float2* A = b0;
+  const size_t nseg = pp.segs.size();
+  for (size_t si = 0; si < nseg; ++si) {
+    const ptsbe::Segment& sg = pp.segs[si];
+    if (sg.fused) {   // a run of in-place steps, one tile pass, in place
+      HIP_TRY(ptsbe::launch_fused(sg, p.d_fused, g, n_jobs, job_traj, traj_base, job_prefix, p.NW, A, s));
+      if (p.profile) p.sweep_bytes += (double)n_jobs * 16.0 * std::ldexp(1.0, sg.r);
+      continue;
+    }
+    const size_t i = (size_t)sg.first;
+    float2* C = (si + 1 == nseg) ? out : (A == b0 ? b1 : b0);
     HIP_TRY(ptsbe::launch_absorb_global(pp.steps[i], d_steps + i, g, n_jobs, job_traj, traj_base, job_prefix,
                                         p.NW, A, C, s));
     A = C;
     if (p.profile) p.sweep_bytes += (double)n_jobs * 8.0 *
                                     (std::ldexp(1.0, pp.steps[i].rA) + std::ldexp(1.0, pp.steps[i].rC));
   }
+  if (A != out) HIP_TRY(ptsbe::launch_copy(A, out, n_jobs << out_rank, s));
   ar.used = mark;
   return PTSBE_OK;
 }
@@ -328,7 +323,7 @@ ptsbe_status_t collect_events(Plan& p, std::vector<EventPair>& evs) {
 
 extern "C" {
 
-const char* ptsbe_last_error(void) { return g_last_error.c_str(); }
+const char* ptsbe_last_error(void) { return ptsbe::g_last_error.c_str(); }
 
 ptsbe_status_t ptsbe_plan(const ptsbe_circuit_t* c, const ptsbe_plan_opts_t* o, ptsbe_plan_t* out) {
   if (!c || !o || !out) return fail(PTSBE_ERR_INVALID_ARG, "null argument");
@@ -357,7 +352,6 @@ ptsbe_status_t ptsbe_plan(const ptsbe_circuit_t* c, const ptsbe_plan_opts_t* o, 
     int b = o->batch_sizes[j];
     if (b < 1) return fail(PTSBE_ERR_INVALID_ARG, "batch size < 1");
     if (b > ptsbe::kMaxBatch) return fail(PTSBE_ERR_UNSUPPORTED, "batch size > 30");
-    if (b > 12) return fail(PTSBE_ERR_UNSUPPORTED, "batch size > 12 not implemented by the sampler yet");
     sum += b;
     p->batch_sizes.push_back(b);
   }
@@ -386,6 +380,7 @@ ptsbe_status_t ptsbe_plan(const ptsbe_circuit_t* c, const ptsbe_plan_opts_t* o, 
     p->qubits.push_back(q);
     p->mats.push_back(m);
   }
+  p->n_user_gates = c->n_gates;
   // untouched qubits get an explicit identity so that every output leg is on a gate
   for (int q = 0; q < p->n; ++q)
     if (!touched[q]) {
@@ -477,6 +472,37 @@ ptsbe_status_t ptsbe_plan(const ptsbe_circuit_t* c, const ptsbe_plan_opts_t* o, 
   // path
   std::string err;
   if (!ptsbe::build_batch_plans(*p, err)) return fail(PTSBE_ERR_UNSUPPORTED, err);
+  // statevector schedule: every gate in circuit order, in place on qubit positions
+  if (p->n <= 30) {
+    for (int g = 0; g < p->G; ++g) {
+      ptsbe::AbsorbStep st{};
+      st.gate = g;
+      st.rA = st.rC = p->n;
+      const int ar = p->arity[g];
+      std::vector<std::pair<int, int>> ins, outs;   // (position, weight)
+      for (int a = 0; a < ar; ++a) {
+        const int q = p->qubits[g][a];
+        outs.push_back({q, ar == 2 ? (a == 0 ? 8 : 4) : 2});
+        ins.push_back({q, ar == 2 ? (a == 0 ? 2 : 1) : 1});
+      }
+      std::sort(ins.begin(), ins.end());
+      std::sort(outs.begin(), outs.end());
+      st.nK = st.nN = ar;
+      for (int i = 0; i < ar; ++i) {
+        st.kpos[i] = ins[i].first; st.kw[i] = ins[i].second;
+        st.npos[i] = outs[i].first; st.nw[i] = outs[i].second;
+      }
+      for (int k = 0; k < (1 << st.nK); ++k) {
+        st.koff[k] = 0; st.kB[k] = 0; st.noff[k] = 0; st.nB[k] = 0;
+        for (int i = 0; i < st.nK; ++i)
+          if ((k >> i) & 1) {
+            st.koff[k] += 1u << st.kpos[i]; st.kB[k] += st.kw[i];
+            st.noff[k] += 1u << st.npos[i]; st.nB[k] += st.nw[i];
+          }
+      }
+      p->sv_steps.push_back(st);
+    }
+  }
   // device constants
   std::vector<ptsbe::DeviceGate> dg(p->G);
   std::vector<int32_t> site_list;
@@ -514,6 +540,9 @@ ptsbe_status_t ptsbe_plan(const ptsbe_circuit_t* c, const ptsbe_plan_opts_t* o, 
     for (int i = 0; i < 16; ++i) dg[g].def[i] = make_float2(0.f, 0.f);
     for (int i = 0; i < d * d; ++i) dg[g].def[i] = make_float2((float)m[i].real(), (float)m[i].imag());
   }
+  for (auto& bp : p->batches)
+    for (ptsbe::PartPlan* pp : {&bp.left, &bp.right, &bp.left_resume})
+      ptsbe::build_segments(pp->steps, pp->segs, p->fused);
   std::vector<ptsbe::AbsorbStep> steps;
   std::vector<int64_t> tables;
   for (auto& bp : p->batches) {
@@ -560,6 +589,16 @@ ptsbe_status_t ptsbe_plan(const ptsbe_circuit_t* c, const ptsbe_plan_opts_t* o, 
   HIP_TRY(hipMalloc(&p->d_site_ops, site_ops.size() * sizeof(float2)));
   HIP_TRY(hipMalloc(&p->d_steps, steps.size() * sizeof(ptsbe::AbsorbStep)));
   HIP_TRY(hipMalloc(&p->d_tables, tables.size() * 8));
+  if (!p->fused.empty()) {
+    HIP_TRY(hipMalloc(&p->d_fused, p->fused.size() * sizeof(ptsbe::FusedStep)));
+    HIP_TRY(hipMemcpy(p->d_fused, p->fused.data(), p->fused.size() * sizeof(ptsbe::FusedStep),
+                      hipMemcpyHostToDevice));
+  }
+  if (!p->sv_steps.empty()) {
+    HIP_TRY(hipMalloc(&p->d_sv_steps, p->sv_steps.size() * sizeof(ptsbe::AbsorbStep)));
+    HIP_TRY(hipMemcpy(p->d_sv_steps, p->sv_steps.data(), p->sv_steps.size() * sizeof(ptsbe::AbsorbStep),
+                      hipMemcpyHostToDevice));
+  }
   HIP_TRY(hipMemcpy(p->d_gates, dg.data(), dg.size() * sizeof(ptsbe::DeviceGate), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(p->d_gate_site_list, site_list.data(), site_list.size() * 4, hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(p->d_site_ops, site_ops.data(), site_ops.size() * sizeof(float2), hipMemcpyHostToDevice));
@@ -577,6 +616,8 @@ void ptsbe_plan_destroy(ptsbe_plan_t plan) {
   if (p->d_site_ops) (void)hipFree(p->d_site_ops);
   if (p->d_steps) (void)hipFree(p->d_steps);
   if (p->d_tables) (void)hipFree(p->d_tables);
+  if (p->d_sv_steps) (void)hipFree(p->d_sv_steps);
+  if (p->d_fused) (void)hipFree(p->d_fused);
   delete p;
 }
 
@@ -785,6 +826,8 @@ ptsbe_status_t ptsbe_sample_shots(ptsbe_plan_t plan, const uint8_t* d_kraus_idx,
   if (!p) return fail(PTSBE_ERR_INVALID_ARG, "null plan");
   if (p->device < 0) return fail(PTSBE_ERR_INVALID_ARG, "plan was built without a device");
   if (mode != PTSBE_MODE_PROPORTIONAL) return fail(PTSBE_ERR_UNSUPPORTED, "only proportional mode is implemented");
+  for (int b : p->batch_sizes)
+    if (b > 12) return fail(PTSBE_ERR_UNSUPPORTED, "the sampler handles batches of at most 12 qubits");
   if (E < 1) return fail(PTSBE_ERR_INVALID_ARG, "E < 1");
   if (!d_kraus_idx || !d_shots_per_traj || !d_shots || !d_workspace)
     return fail(PTSBE_ERR_INVALID_ARG, "null device pointer");

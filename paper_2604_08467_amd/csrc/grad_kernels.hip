@@ -1,0 +1,263 @@
+// HIP kernels of the adjoint contraction (gradients of trajectory-averaged
+// observables with respect to rotation angles).  The ket network is contracted
+// in circuit order into a 2^n statevector per trajectory (qubit q = bit q); the
+// adjoint pass applies the conjugate-transposed merged gates to the observable's
+// seed lambda = O psi and reduces <lambda|(dA/dtheta) psi> gate by gate.
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace ptsbe {
+namespace {
+
+__device__ inline float2 cfma2(float2 a, float2 b, float2 c) {
+  return make_float2(fmaf(a.x, b.x, fmaf(-a.y, b.y, c.x)), fmaf(a.x, b.y, fmaf(a.y, b.x, c.y)));
+}
+
+// M (d x d) = S . B where S is the product of the gate's inserted operators for
+// trajectory traj (later sites on the left) and B a d x d matrix (row-major).
+__device__ void site_product_times(const GateCtx& g, int gate, int traj, const float2* B, float2* out) {
+  const DeviceGate* G = g.gates + gate;
+  const int d = G->arity == 2 ? 4 : 2;
+  float2 m[16], t[16];
+  for (int i = 0; i < 16; ++i) m[i] = i < d * d ? B[i] : make_float2(0.f, 0.f);
+  const uint8_t* kr = g.kraus + (int64_t)traj * g.S;
+  for (int s = G->site_begin; s < G->site_end; ++s) {
+    const int site = g.gate_site_list[s];
+    const float2* op = g.site_ops + ((int64_t)site * g.max_kraus + kr[site]) * 16;
+    for (int r = 0; r < d; ++r)
+      for (int c = 0; c < d; ++c) {
+        float2 acc = make_float2(0.f, 0.f);
+        for (int x = 0; x < d; ++x) acc = cfma2(op[r * d + x], m[x * d + c], acc);
+        t[r * d + c] = acc;
+      }
+    for (int i = 0; i < d * d; ++i) m[i] = t[i];
+  }
+  for (int i = 0; i < 16; ++i) out[i] = m[i];
+}
+
+// Rotation exp(-i theta P / 2) and its theta-derivative (2x2, row-major).
+__device__ void rotation_pair(int axis, double theta, float2* U, float2* dU) {
+  const double c = cos(0.5 * theta), s = sin(0.5 * theta);
+  // U = c I - i s P ; dU = -(s/2) I - i (c/2) P
+  double P[8] = {0, 0, 0, 0, 0, 0, 0, 0};   // interleaved 2x2 complex
+  if (axis == 0) { P[2] = 1; P[4] = 1; }
+  else if (axis == 1) { P[3] = -1; P[5] = 1; }
+  else { P[0] = 1; P[6] = -1; }
+  for (int i = 0; i < 4; ++i) {
+    const double id = (i == 0 || i == 3) ? 1.0 : 0.0;
+    const double pr = P[2 * i], pi = P[2 * i + 1];
+    // -i * (a + i b) = b - i a
+    U[i] = make_float2((float)(c * id + s * pi), (float)(-s * pr));
+    dU[i] = make_float2((float)(-0.5 * s * id + 0.5 * c * pi), (float)(-0.5 * c * pr));
+  }
+}
+
+__global__ void grad_gates_kernel(GradGateArgs a) {
+  const int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (id >= a.E * a.g.G) return;
+  const int traj = (int)(id / a.g.G), gate = (int)(id % a.g.G);
+  const DeviceGate* G = a.g.gates + gate;
+  const int d = G->arity == 2 ? 4 : 2;
+  float2 base[16], m[16];
+  const int prm = a.gate_param[gate];
+  float2 dU[4];
+  if (prm >= 0) {
+    rotation_pair(a.gate_axis[gate], a.theta[prm], base, dU);
+  } else {
+    for (int i = 0; i < 16; ++i) base[i] = G->raw[i];
+  }
+  site_product_times(a.g, gate, traj, base, m);
+  float2* o = a.merged + id * 16;
+  float2* od = a.dagger + id * 16;
+  for (int i = 0; i < 16; ++i) o[i] = m[i];
+  for (int r = 0; r < 16; ++r) od[r] = make_float2(0.f, 0.f);
+  for (int r = 0; r < d; ++r)
+    for (int c = 0; c < d; ++c) {
+      const float2 v = m[c * d + r];
+      od[r * d + c] = make_float2(v.x, -v.y);
+    }
+  const int slot = a.gate_slot[gate];
+  if (slot >= 0) {
+    float2 dm[16];
+    site_product_times(a.g, gate, traj, dU, dm);
+    float2* odm = a.dmerged + ((int64_t)traj * a.n_slots + slot) * 16;
+    for (int i = 0; i < 16; ++i) odm[i] = dm[i];
+  }
+}
+
+__global__ void state_init_kernel(float2* psi, int64_t n_jobs, int n) {
+  const int64_t per = (int64_t)1 << n;
+  const int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (id >= per * n_jobs) return;
+  psi[id] = make_float2((id % per) == 0 ? 1.f : 0.f, 0.f);
+}
+
+__global__ void copy_kernel(const float2* __restrict__ src, float2* __restrict__ dst, int64_t n) {
+  const int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (id < n) dst[id] = src[id];
+}
+
+__device__ inline float zz_value(uint32_t x, const int32_t* zq, const double* zc, int nt) {
+  float o = 0.f;
+  for (int t = 0; t < nt; ++t) {
+    const int za = 1 - 2 * (int)((x >> zq[2 * t]) & 1u);
+    const int zb = 1 - 2 * (int)((x >> zq[2 * t + 1]) & 1u);
+    o += (float)zc[t] * (float)(za * zb);
+  }
+  return o;
+}
+
+// lambda = O psi and value[job] = <psi|O|psi> (FP64 block reduction per job)
+__global__ void __launch_bounds__(256) observable_kernel(const float2* __restrict__ psi, float2* __restrict__ lam,
+                                                        int n, const int32_t* zq, const double* zc, int nt,
+                                                        double* __restrict__ value, int64_t job0) {
+  __shared__ double red[256];
+  const int64_t job = blockIdx.x;
+  const int64_t per = (int64_t)1 << n;
+  const float2* p = psi + job * per;
+  float2* l = lam + job * per;
+  double acc = 0.0;
+  for (int64_t x = threadIdx.x; x < per; x += 256) {
+    const float o = zz_value((uint32_t)x, zq, zc, nt);
+    const float2 v = p[x];
+    l[x] = make_float2(o * v.x, o * v.y);
+    acc += (double)o * ((double)v.x * v.x + (double)v.y * v.y);
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) value[job0 + job] = red[0];
+}
+
+// partial[traj][slot] = 2 w_traj Re sum_{a,b} dA[a][b] M[a][b],
+// M[a][b] = sum_rest conj(lambda[rest, a]) psi[rest, b] over the gate's qubits.
+__global__ void __launch_bounds__(256) grad_reduce_kernel(const float2* __restrict__ lam,
+                                                         const float2* __restrict__ psi, int n, int arity,
+                                                         int q0, int q1, const float2* __restrict__ dmerged,
+                                                         int n_slots, int slot, const double* __restrict__ w,
+                                                         int64_t job0, double* __restrict__ partial) {
+  __shared__ double red[256][2];
+  const int64_t job = blockIdx.x;
+  const int64_t traj = job0 + job;
+  const int64_t per = (int64_t)1 << n;
+  const float2* L = lam + job * per;
+  const float2* P = psi + job * per;
+  const float2* dA = dmerged + (traj * n_slots + slot) * 16;
+  const int d = arity == 2 ? 4 : 2;
+  // positions: for 2q gates index a = 2 x[q0] + x[q1]
+  int pos[2] = {q0, q1};
+  int plo = arity == 2 ? (q0 < q1 ? q0 : q1) : q0;
+  int phi = arity == 2 ? (q0 < q1 ? q1 : q0) : q0;
+  const int64_t nrest = per >> arity;
+  double re = 0.0;
+  for (int64_t m = threadIdx.x; m < nrest; m += 256) {
+    uint32_t base = (uint32_t)m;
+    base = ((base >> plo) << (plo + 1)) | (base & ((1u << plo) - 1u));
+    if (arity == 2) base = ((base >> phi) << (phi + 1)) | (base & ((1u << phi) - 1u));
+    float2 lv[4], pv[4];
+    for (int a = 0; a < d; ++a) {
+      uint32_t off = base;
+      if (arity == 2) {
+        off |= (uint32_t)((a >> 1) & 1) << pos[0];
+        off |= (uint32_t)(a & 1) << pos[1];
+      } else {
+        off |= (uint32_t)(a & 1) << pos[0];
+      }
+      lv[a] = L[off];
+      pv[a] = P[off];
+    }
+    // Re sum_ab dA[a][b] conj(l_a) p_b
+    for (int a = 0; a < d; ++a) {
+      float2 s = make_float2(0.f, 0.f);
+      for (int b = 0; b < d; ++b) s = cfma2(dA[a * d + b], pv[b], s);
+      re += (double)lv[a].x * s.x + (double)lv[a].y * s.y;
+    }
+  }
+  red[threadIdx.x][0] = re;
+  __syncthreads();
+  for (int wd = 128; wd > 0; wd >>= 1) {
+    if ((int)threadIdx.x < wd) red[threadIdx.x][0] += red[threadIdx.x + wd][0];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[traj * n_slots + slot] = 2.0 * w[traj] * red[0][0];
+}
+
+// grad[p] = sum over trajectories and over the slots that use p (fixed order)
+__global__ void grad_sum_kernel(const double* __restrict__ partial, int64_t E, int n_slots,
+                                const int32_t* __restrict__ slot_param, int n_params, double* __restrict__ grad) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n_params) return;
+  double acc = 0.0;
+  for (int64_t t = 0; t < E; ++t)
+    for (int s = 0; s < n_slots; ++s)
+      if (slot_param[s] == p) acc += partial[t * n_slots + s];
+  grad[p] = acc;
+}
+
+__global__ void value_sum_kernel(const double* __restrict__ vals, const double* __restrict__ w, int64_t E,
+                                 double* __restrict__ out) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int64_t t = threadIdx.x; t < E; t += 256) acc += w[t] * vals[t];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int wd = 128; wd > 0; wd >>= 1) {
+    if ((int)threadIdx.x < wd) red[threadIdx.x] += red[threadIdx.x + wd];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = red[0];
+}
+
+}  // namespace
+
+hipError_t launch_grad_gates(const GradGateArgs& a, hipStream_t stream) {
+  const int64_t n = a.E * a.g.G;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(grad_gates_kernel, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, stream, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_state_init(float2* psi, int64_t n_jobs, int n, hipStream_t stream) {
+  const int64_t total = n_jobs << n;
+  hipLaunchKernelGGL(state_init_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream, psi, n_jobs, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(const float2* src, float2* dst, int64_t n, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(copy_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, src, dst, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_observable(const float2* psi, float2* lam, int64_t n_jobs, int n, const int32_t* zq,
+                             const double* zc, int nt, double* value, int64_t job0, hipStream_t stream) {
+  hipLaunchKernelGGL(observable_kernel, dim3((unsigned)n_jobs), dim3(256), 0, stream, psi, lam, n, zq, zc, nt, value,
+                     job0);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_reduce(const float2* lam, const float2* psi, int64_t n_jobs, int n, int arity, int q0, int q1,
+                              const float2* dmerged, int n_slots, int slot, const double* w, int64_t job0,
+                              double* partial, hipStream_t stream) {
+  hipLaunchKernelGGL(grad_reduce_kernel, dim3((unsigned)n_jobs), dim3(256), 0, stream, lam, psi, n, arity, q0, q1,
+                     dmerged, n_slots, slot, w, job0, partial);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_sum(const double* partial, int64_t E, int n_slots, const int32_t* slot_param, int n_params,
+                           double* grad, hipStream_t stream) {
+  hipLaunchKernelGGL(grad_sum_kernel, dim3((unsigned)((n_params + 63) / 64)), dim3(64), 0, stream, partial, E,
+                     n_slots, slot_param, n_params, grad);
+  return hipGetLastError();
+}
+
+hipError_t launch_value_sum(const double* vals, const double* w, int64_t E, double* out, hipStream_t stream) {
+  hipLaunchKernelGGL(value_sum_kernel, dim3(1), dim3(256), 0, stream, vals, w, E, out);
+  return hipGetLastError();
+}
+
+}  // namespace ptsbe

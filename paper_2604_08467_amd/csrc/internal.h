@@ -13,6 +13,33 @@
 
 namespace ptsbe {
 
+// ---------------------------------------------------------------- host helpers
+extern thread_local std::string g_last_error;
+ptsbe_status_t fail(ptsbe_status_t s, const std::string& msg);
+
+#define HIP_TRY(expr)                                                                         \
+  do {                                                                                        \
+    hipError_t e_ = (expr);                                                                   \
+    if (e_ != hipSuccess)                                                                     \
+      return ::ptsbe::fail(PTSBE_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// bump allocator over the caller's workspace (256-byte aligned blocks)
+struct Arena {
+  char* base = nullptr;
+  size_t cap = 0, used = 0;
+  void* take(size_t bytes) {
+    size_t off = (used + 255) & ~(size_t)255;
+    if (off + bytes > cap) return nullptr;
+    used = off + bytes;
+    return base + off;
+  }
+  size_t left() const {
+    size_t off = (used + 255) & ~(size_t)255;
+    return off >= cap ? 0 : cap - off;
+  }
+};
+
 constexpr int kMaxBatch = 30;       // largest b_j accepted
 constexpr int kMaxQubits = 1024;
 constexpr int kVmMaxRank = 11;      // parts whose tensors fit 2^11 c64 run in LDS
@@ -39,8 +66,35 @@ struct AbsorbStep {
   int32_t kB[16], nB[16];
 };
 
+// Local view of an in-place step (same bit positions in and out, rank
+// unchanged) inside a fused tile of the tensor: positions are indices into the
+// tile's position list P; hyper legs read their bit from the tile-local index
+// (h_inP = 1) or from the tile's global base (h_inP = 0, h_pos a global position).
+struct FusedStep {
+  int32_t gate, conj, nK, nN, nH, nS;
+  int32_t kloc[4];
+  uint32_t koff[16], noff[16];
+  int32_t kB[16], nB[16];
+  int32_t h_inP[4], h_pos[4], hw[4];
+  int32_t sq[kMaxSlices], sw[kMaxSlices];
+};
+
+// A run of steps executed by one launch: either one absorb step, or a fused
+// run of in-place steps whose positions lie in P (|P| = np <= kFuseMax).
+constexpr int kFuseMax = 12;
+struct Segment {
+  int first = 0, count = 1;
+  bool fused = false;
+  int np = 0, r = 0;
+  int P[kFuseMax] = {0};
+  int64_t fused_off = 0;            // index of the first FusedStep on the device
+};
+bool build_segments(const std::vector<AbsorbStep>& steps, std::vector<Segment>& segs,
+                    std::vector<FusedStep>& fused);
+
 struct PartPlan {
   std::vector<AbsorbStep> steps;
+  std::vector<Segment> segs;        // launch grouping of the steps (global execution)
   std::vector<int> labels;          // final labels, bit order (bit 0 first)
   int peak = 0;                     // largest rank of any A or C
   double flops = 0, bytes = 0, cost = 0;
@@ -88,6 +142,7 @@ struct Plan {
   int device = 0;
   int precision = PTSBE_C64;
   int n = 0, G = 0, S = 0, NW = 1, max_kraus = 1;
+  int n_user_gates = 0;                           // gates of the caller's circuit (identities follow)
   std::vector<int> arity;
   std::vector<std::array<int, 2>> qubits;
   std::vector<std::array<double, 32>> mats;       // complex128, 4x4 or 2x2 row-major
@@ -112,6 +167,14 @@ struct Plan {
   std::vector<JoinDev> join_dev;
   std::vector<JoinDev> join_dev_r;                // same with the resumed left part's V tables
   int64_t device_bytes = 0;
+
+  // statevector schedule (qubit q = bit q, gates in circuit order, in place)
+  std::vector<AbsorbStep> sv_steps;
+  AbsorbStep* d_sv_steps = nullptr;
+  std::vector<Segment> sv_segs;
+  // fused in-place steps of every part and of the statevector schedule
+  std::vector<FusedStep> fused;
+  FusedStep* d_fused = nullptr;
 
   // measurement
   bool profile = false;
@@ -162,6 +225,10 @@ hipError_t launch_absorb_global(const AbsorbStep& st, const AbsorbStep* d_st, Ga
                                 const uint64_t* job_prefix, int NW, const float2* A,
                                 float2* C, hipStream_t stream);
 hipError_t launch_fill_one(float2* buf, int64_t n, hipStream_t stream);
+// A fused run of in-place steps on every job's tensor (rank seg.r), in place.
+hipError_t launch_fused(const Segment& seg, const FusedStep* d_fs, GateCtx g, int64_t n_jobs,
+                        const int32_t* job_traj, int32_t traj_base, const uint64_t* job_prefix, int NW,
+                        float2* A, hipStream_t stream);
 
 struct JoinArgs {
   const float2* V; int64_t v_stride;     // per element
@@ -247,5 +314,30 @@ hipError_t launch_init_elements(int64_t E, const int64_t* shots_per_traj, int32_
                                 hipStream_t stream);
 hipError_t launch_traj_ranges(const int32_t* elem_traj, int64_t n_elems, int64_t E,
                               int32_t* traj_first, hipStream_t stream);
+
+// ---------------------------------------------------------------- adjoint pass
+struct GradGateArgs {
+  GateCtx g;
+  int64_t E;
+  const int32_t* gate_param;   // [G] parameter index or -1
+  const int32_t* gate_axis;    // [G]
+  const int32_t* gate_slot;    // [G] index among parameterised gates or -1
+  int n_slots;
+  const double* theta;
+  float2* merged;              // [E][G][16] A = S . U
+  float2* dagger;              // [E][G][16] A^dag
+  float2* dmerged;             // [E][n_slots][16] S . dU/dtheta
+};
+hipError_t launch_grad_gates(const GradGateArgs& a, hipStream_t stream);
+hipError_t launch_state_init(float2* psi, int64_t n_jobs, int n, hipStream_t stream);
+hipError_t launch_copy(const float2* src, float2* dst, int64_t n, hipStream_t stream);
+hipError_t launch_observable(const float2* psi, float2* lam, int64_t n_jobs, int n, const int32_t* zq,
+                             const double* zc, int nt, double* value, int64_t job0, hipStream_t stream);
+hipError_t launch_grad_reduce(const float2* lam, const float2* psi, int64_t n_jobs, int n, int arity, int q0,
+                              int q1, const float2* dmerged, int n_slots, int slot, const double* w,
+                              int64_t job0, double* partial, hipStream_t stream);
+hipError_t launch_grad_sum(const double* partial, int64_t E, int n_slots, const int32_t* slot_param,
+                           int n_params, double* grad, hipStream_t stream);
+hipError_t launch_value_sum(const double* vals, const double* w, int64_t E, double* out, hipStream_t stream);
 
 }  // namespace ptsbe

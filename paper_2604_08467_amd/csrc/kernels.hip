@@ -172,7 +172,7 @@ constexpr uint32_t kAbsorbPerBlock = 2048;
 __global__ void absorb_global_kernel(const AbsorbStep* __restrict__ st_dev, GateCtx g, int64_t n_jobs,
                                      int64_t blocks_per_job, const int32_t* __restrict__ job_traj,
                                      int32_t traj_base, const uint64_t* __restrict__ job_prefix, int NW,
-                                     const float2* __restrict__ A, float2* __restrict__ C) {
+                                     const float2* A, float2* C) {   // A == C allowed for in-place steps
   __shared__ float2 Gm[16];
   __shared__ uint64_t pw[16];
   const int64_t job = blockIdx.x / blocks_per_job;
@@ -193,6 +193,83 @@ __global__ void absorb_global_kernel(const AbsorbStep* __restrict__ st_dev, Gate
     const uint32_t m = m0 + i;
     if (m >= nm) break;
     absorb_one(st, sb, m, Aj, Cj, Gm);
+  }
+}
+
+// A fused run of in-place steps: one workgroup per (job, tile); the tile is the
+// 2^np entries whose non-P bits equal the tile index; every step of the run is
+// applied to the tile in LDS before it is written back.
+struct FusedArgs {
+  const FusedStep* fs; int n_fs;
+  int r, np;
+  int P[kFuseMax];
+  int64_t tiles_per_job;
+};
+
+__device__ inline uint32_t deposit_tile(uint32_t t, const int* P, int np, int r) {
+  // spread the bits of t over the positions not in P (ascending)
+  uint32_t out = 0;
+  int pi = 0, bit = 0;
+  for (int q = 0; q < r; ++q) {
+    if (pi < np && P[pi] == q) { ++pi; continue; }
+    out |= ((t >> bit) & 1u) << q;
+    ++bit;
+  }
+  return out;
+}
+
+__global__ void __launch_bounds__(256) fused_inplace_kernel(FusedArgs f, GateCtx g, int64_t n_jobs,
+                                                           const int32_t* __restrict__ job_traj, int32_t traj_base,
+                                                           const uint64_t* __restrict__ job_prefix, int NW,
+                                                           float2* A) {
+  extern __shared__ float2 tile[];
+  float2* Gm = tile + ((int64_t)1 << f.np);
+  __shared__ uint64_t pw[16];
+  const int64_t job = blockIdx.x / f.tiles_per_job;
+  const uint32_t t = (uint32_t)(blockIdx.x % f.tiles_per_job);
+  if (job >= n_jobs) return;
+  const int tid = threadIdx.x;
+  const int traj = job_traj ? job_traj[job] : traj_base + (int)job;
+  if (tid < NW) pw[tid] = job_prefix ? job_prefix[job * NW + tid] : 0ull;
+  const uint32_t base = deposit_tile(t, f.P, f.np, f.r);
+  float2* Aj = A + (job << f.r);
+  const uint32_t nt = 1u << f.np;
+  for (uint32_t l = tid; l < nt; l += blockDim.x) {
+    uint32_t off = base;
+    for (int i = 0; i < f.np; ++i) off |= ((l >> i) & 1u) << f.P[i];
+    tile[l] = Aj[off];
+  }
+  for (int s = 0; s < f.n_fs; ++s) {
+    const FusedStep& st = f.fs[s];
+    if (tid < 16) Gm[16 * (s & 1) + tid] = gate_entry(g, st.gate, traj, st.conj, tid);
+    __syncthreads();
+    const float2* G = Gm + 16 * (s & 1);
+    int sb = 0;
+    for (int i = 0; i < st.nS; ++i) sb += (int)bit_of_prefix(pw, st.sq[i]) * st.sw[i];
+    const uint32_t nm = nt >> st.nK;
+    const int nk = 1 << st.nK, nn = 1 << st.nN;
+    for (uint32_t m = tid; m < nm; m += blockDim.x) {
+      const uint32_t lb = insert_zero_bits(m, st.kloc, st.nK);
+      float2 a[16];
+      for (int k = 0; k < nk; ++k) a[k] = tile[lb + st.koff[k]];
+      int hidx = sb;
+      for (int i = 0; i < st.nH; ++i) {
+        const uint32_t bit = st.h_inP[i] ? (lb >> st.h_pos[i]) & 1u : (base >> st.h_pos[i]) & 1u;
+        hidx += (int)bit * st.hw[i];
+      }
+      for (int n = 0; n < nn; ++n) {
+        float2 acc = make_float2(0.f, 0.f);
+        const int bn = hidx + st.nB[n];
+        for (int k = 0; k < nk; ++k) acc = cfma(a[k], G[bn + st.kB[k]], acc);
+        tile[lb + st.noff[n]] = acc;
+      }
+    }
+    __syncthreads();
+  }
+  for (uint32_t l = tid; l < nt; l += blockDim.x) {
+    uint32_t off = base;
+    for (int i = 0; i < f.np; ++i) off |= ((l >> i) & 1u) << f.P[i];
+    Aj[off] = tile[l];
   }
 }
 
@@ -996,6 +1073,22 @@ hipError_t launch_absorb_global(const AbsorbStep& st, const AbsorbStep* d_st, Ga
   const int64_t bpj = (nm + kAbsorbPerBlock - 1) / kAbsorbPerBlock;
   hipLaunchKernelGGL(absorb_global_kernel, dim3((unsigned)(bpj * n_jobs)), dim3(threads), 0, stream, d_st, g,
                      n_jobs, bpj, job_traj, traj_base, job_prefix, NW, A, C);
+  return hipGetLastError();
+}
+
+hipError_t launch_fused(const Segment& seg, const FusedStep* d_fs, GateCtx g, int64_t n_jobs, const int32_t* job_traj,
+                        int32_t traj_base, const uint64_t* job_prefix, int NW, float2* A, hipStream_t stream) {
+  if (n_jobs <= 0) return hipSuccess;
+  FusedArgs f{};
+  f.fs = d_fs + seg.fused_off;
+  f.n_fs = seg.count;
+  f.r = seg.r;
+  f.np = seg.np;
+  for (int i = 0; i < kFuseMax; ++i) f.P[i] = seg.P[i];
+  f.tiles_per_job = (int64_t)1 << (seg.r - seg.np);
+  const size_t shmem = ((size_t)1 << seg.np) * sizeof(float2) + 32 * sizeof(float2);
+  hipLaunchKernelGGL(fused_inplace_kernel, dim3((unsigned)(f.tiles_per_job * n_jobs)), dim3(256), shmem, stream, f, g,
+                     n_jobs, job_traj, traj_base, job_prefix, NW, A);
   return hipGetLastError();
 }
 

@@ -486,3 +486,98 @@ bool build_batch_plans(Plan& p, std::string& err) {
 }
 
 }  // namespace ptsbe
+
+namespace ptsbe {
+
+// Group a step list into launches: maximal runs of in-place steps (rank and bit
+// positions unchanged) whose positions fit in kFuseMax bits become one fused
+// tile pass; every other step is launched alone.  P is padded with the lowest
+// unused positions so that a tile covers contiguous memory where possible.
+bool build_segments(const std::vector<AbsorbStep>& steps, std::vector<Segment>& segs,
+                    std::vector<FusedStep>& fused) {
+  segs.clear();
+  auto in_place = [](const AbsorbStep& st) {
+    if (st.rA != st.rC || st.nK != st.nN) return false;
+    for (int i = 0; i < st.nK; ++i)
+      if (st.kpos[i] != st.npos[i]) return false;
+    return st.rA > kFuseMax;
+  };
+  size_t i = 0;
+  while (i < steps.size()) {
+    if (!in_place(steps[i])) {
+      Segment sg;
+      sg.first = (int)i;
+      sg.count = 1;
+      segs.push_back(sg);
+      ++i;
+      continue;
+    }
+    std::set<int> P;
+    size_t j = i;
+    const int r = steps[i].rA;
+    while (j < steps.size() && in_place(steps[j]) && steps[j].rA == r) {
+      std::set<int> P2 = P;
+      for (int k = 0; k < steps[j].nK; ++k) P2.insert(steps[j].kpos[k]);
+      if ((int)P2.size() > kFuseMax) break;
+      P = P2;
+      ++j;
+    }
+    if (j - i < 2) {
+      Segment sg;
+      sg.first = (int)i;
+      sg.count = 1;
+      segs.push_back(sg);
+      ++i;
+      continue;
+    }
+    for (int pos = 0; (int)P.size() < kFuseMax && pos < r; ++pos) P.insert(pos);
+    Segment sg;
+    sg.first = (int)i;
+    sg.count = (int)(j - i);
+    sg.fused = true;
+    sg.r = r;
+    sg.np = (int)P.size();
+    std::vector<int> Pv(P.begin(), P.end());
+    for (int k = 0; k < sg.np; ++k) sg.P[k] = Pv[k];
+    sg.fused_off = (int64_t)fused.size();
+    for (size_t s = i; s < j; ++s) {
+      const AbsorbStep& st = steps[s];
+      FusedStep fs{};
+      fs.gate = st.gate; fs.conj = st.conj; fs.nK = st.nK; fs.nN = st.nN; fs.nH = st.nH; fs.nS = st.nS;
+      auto loc = [&](int pos) { return (int)(std::find(Pv.begin(), Pv.end(), pos) - Pv.begin()); };
+      for (int k = 0; k < st.nK; ++k) fs.kloc[k] = loc(st.kpos[k]);
+      for (int k = 0; k < (1 << st.nK); ++k) {
+        fs.koff[k] = 0;
+        fs.kB[k] = st.kB[k];
+        for (int b = 0; b < st.nK; ++b)
+          if ((k >> b) & 1) fs.koff[k] += 1u << loc(st.kpos[b]);
+      }
+      for (int nn = 0; nn < (1 << st.nN); ++nn) {
+        fs.noff[nn] = 0;
+        fs.nB[nn] = st.nB[nn];
+        for (int b = 0; b < st.nN; ++b)
+          if ((nn >> b) & 1) fs.noff[nn] += 1u << loc(st.npos[b]);
+      }
+      // hyper legs: kept index bit hm -> tensor position (kept = all positions but kpos)
+      for (int h = 0; h < st.nH; ++h) {
+        int pos = -1, cnt = -1;
+        for (int q = 0; q < st.rA; ++q) {
+          bool is_k = false;
+          for (int b = 0; b < st.nK; ++b) is_k |= st.kpos[b] == q;
+          if (is_k) continue;
+          if (++cnt == st.hm[h]) { pos = q; break; }
+        }
+        if (P.count(pos)) { fs.h_inP[h] = 1; fs.h_pos[h] = loc(pos); }
+        else { fs.h_inP[h] = 0; fs.h_pos[h] = pos; }
+        fs.hw[h] = st.hw[h];
+      }
+      for (int k = 0; k < st.nS; ++k) { fs.sq[k] = st.sq[k]; fs.sw[k] = st.sw[k]; }
+      fused.push_back(fs);
+    }
+    segs.push_back(sg);
+    i = j;
+  }
+  return true;
+}
+
+}  // namespace ptsbe

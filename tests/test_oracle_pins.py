@@ -338,3 +338,43 @@ def test_pts_stops_when_every_error_set_has_appeared():
     kr, mult, _, nd = pts.presample(c, seed=3, n_unique=10)
     assert len(kr) == 4 and mult.sum() == nd
     assert sorted(map(tuple, kr.tolist())) == [(0, 0), (0, 1), (1, 0), (1, 1)]
+
+
+# ----------------------------------------------------------------- gradients
+def _hea_case(noise, seed=0, n=4, layers=2, E=3):
+    from oracle import gradients as gr
+    rng = np.random.default_rng(seed)
+    angles = rng.uniform(0, 2 * np.pi, size=2 * n * layers)
+    c = W.hea(n, layers, angles, noise)
+    gp, ga = W.rotation_spec(c)
+    kr, mult, _, _ = pts.presample(c, seed + 10, E)
+    w = mult / mult.sum()
+    return gr, c, kr, w, angles, gp, ga, W.zz_chain_terms(n)
+
+
+@pytest.mark.parametrize("noise", ["depol", "ad"])
+def test_adjoint_gradient_equals_parameter_shift(noise):
+    chans = [W.depolarizing(0.2)] if noise == "depol" else [W.depolarizing(0.1), W.amplitude_damping(0.3)]
+    gr, c, kr, w, th, gp, ga, terms = _hea_case(chans)
+    g = gr.adjoint_gradient(c, kr, w, th, gp, ga, terms)
+    for k in range(len(th)):
+        ps = gr.parameter_shift(c, kr, w, th, gp, ga, terms, k)
+        assert abs(g[k] - ps) < 1e-10, (k, g[k], ps)
+
+
+def test_adjoint_gradient_matches_central_difference():
+    gr, c, kr, w, th, gp, ga, terms = _hea_case([W.depolarizing(0.2)], seed=3)
+    g = gr.adjoint_gradient(c, kr, w, th, gp, ga, terms)
+    # f is a + R cos(theta - theta0) in each angle with R <= ||O|| = 3: truncation <= h^2/6 R
+    for k in range(0, len(th), 3):
+        fd = gr.central_difference(c, kr, w, th, gp, ga, terms, k, h=1e-3)
+        assert abs(fd - g[k]) < 1e-5
+
+
+def test_gradient_value_matches_statevector_definition():
+    gr, c, kr, w, th, gp, ga, terms = _hea_case([W.depolarizing(0.2)], seed=4)
+    f = gr.value(c, kr, w, th, gp, ga, terms)
+    psis = [sv.trajectory_state(c, row) for row in kr]      # gates built from the same angles
+    o = gr.zz_diagonal(c.n_qubits, terms)
+    ref = sum(wi * np.real(np.vdot(p, o * p)) for wi, p in zip(w, psis))
+    assert abs(f - ref) < 1e-12

@@ -31,7 +31,8 @@ import numpy as np
 __all__ = [
     "Channel", "Circuit", "Workload", "haar_su4", "depolarizing", "amplitude_damping",
     "pauli_x", "pauli_y", "pauli_z", "brickwork_1d", "config1", "config2", "config3",
-    "config5", "random_brickwork", "small_random_circuit", "grid_layers",
+    "config5", "random_brickwork", "small_random_circuit", "grid_layers", "hea", "rotation_spec",
+    "zz_chain_terms",
 ]
 
 I2 = np.eye(2, dtype=np.complex128)
@@ -306,6 +307,50 @@ def config3(batch_sizes=(25,)) -> Workload:
     return Workload("config3_grid5x5_d8", c, 16384, 256, list(batch_sizes), pts_seed=3002, shot_seed=3003)
 
 
+def hea(n: int, layers: int, angles: np.ndarray, noise: Sequence[Channel]) -> Circuit:
+    """Hardware-efficient ansatz: per layer RY on every qubit, RZ on every qubit,
+    CNOT ladder 0->1 ... n-2->n-1; each listed channel after every gate on each
+    qubit it touches.  Angle of layer L: RY uses 2nL + q, RZ uses 2nL + n + q."""
+    angles = np.asarray(angles, dtype=np.float64)
+    c = Circuit(n)
+    ids = [c.add_channel(ch) for ch in noise]
+    for L in range(layers):
+        for q in range(n):
+            k = 2 * n * L + q
+            g = c.add_gate((q,), ry(angles[k]), param=("ry", k))
+            for cid in ids:
+                c.add_site(g, (q,), cid)
+        for q in range(n):
+            k = 2 * n * L + n + q
+            g = c.add_gate((q,), rz(angles[k]), param=("rz", k))
+            for cid in ids:
+                c.add_site(g, (q,), cid)
+        for q in range(n - 1):
+            g = c.add_gate((q, q + 1), CNOT)
+            for cid in ids:
+                c.add_site(g, (q,), cid)
+                c.add_site(g, (q + 1,), cid)
+    return c
+
+
+def rotation_spec(circuit: Circuit):
+    """(gate_param, gate_axis) arrays: parameter index of every rotation gate (-1
+    for fixed gates) and its axis (0 X, 1 Y, 2 Z)."""
+    axis_of = {"rx": 0, "ry": 1, "rz": 2}
+    gp = np.full(circuit.n_gates, -1, dtype=np.int32)
+    ga = np.zeros(circuit.n_gates, dtype=np.int32)
+    for g, prm in enumerate(circuit.gate_param):
+        if prm is not None:
+            gp[g] = prm[1]
+            ga[g] = axis_of[prm[0]]
+    return gp, ga
+
+
+def zz_chain_terms(n: int):
+    """O = sum_{q=0}^{n-2} Z_q Z_{q+1} as ((q, q+1), coefficient) pairs."""
+    return [((q, q + 1), 1.0) for q in range(n - 1)]
+
+
 def config5_angles() -> np.ndarray:
     rng = np.random.default_rng(5005)
     return rng.uniform(0.0, 2 * np.pi, size=400).astype(np.float32)
@@ -317,20 +362,5 @@ def config5(angles: Optional[np.ndarray] = None) -> Workload:
     qubit; 1024 trajectories.  Angle k of layer L: RY uses 40L + q, RZ 40L + 20 + q."""
     if angles is None:
         angles = config5_angles()
-    angles = np.asarray(angles, dtype=np.float64)
-    c = Circuit(20)
-    dep = c.add_channel(depolarizing(0.01))
-    for L in range(10):
-        for q in range(20):
-            k = 40 * L + q
-            g = c.add_gate((q,), ry(angles[k]), param=("ry", k))
-            c.add_site(g, (q,), dep)
-        for q in range(20):
-            k = 40 * L + 20 + q
-            g = c.add_gate((q,), rz(angles[k]), param=("rz", k))
-            c.add_site(g, (q,), dep)
-        for q in range(19):
-            g = c.add_gate((q, q + 1), CNOT)
-            c.add_site(g, (q,), dep)
-            c.add_site(g, (q + 1,), dep)
+    c = hea(20, 10, angles, [depolarizing(0.01)])
     return Workload("config5_hea_n20", c, 1024, 0, [20], pts_seed=5002, shot_seed=5003)
