@@ -74,6 +74,17 @@ typedef enum {
 enum { PTSBE_C64 = 0, PTSBE_SPLIT_BF16 = 1, PTSBE_SPLIT_F16 = 2 };
 enum { PTSBE_OUT_POPULATION = 0, PTSBE_OUT_AMPLITUDE = 1 };
 enum { PTSBE_MODE_PROPORTIONAL = 0 };
+/* How the per-trajectory network is contracted (plan option "method"):
+ *   NETWORK      the doubled / ket network of each batch along the unified
+ *                sweep path (Sec. III-A); any n, but the path must fit.
+ *   STATEVECTOR  the ket network contracted in circuit order into the full
+ *                2^n statevector of each trajectory (n <= 30), gates applied in
+ *                LDS-resident windows of at most 12 qubits; every batch's
+ *                marginals are then partial sums over that state.  Same
+ *                unified-path property: one gate schedule for all trajectories.
+ *   AUTO         STATEVECTOR when n <= 20, or when the network path does not
+ *                fit and n <= 30; NETWORK otherwise. */
+enum { PTSBE_METHOD_AUTO = 0, PTSBE_METHOD_NETWORK = 1, PTSBE_METHOD_STATEVECTOR = 2 };
 
 typedef struct ptsbe_plan_s* ptsbe_plan_t;
 
@@ -116,12 +127,17 @@ typedef struct {
   int32_t device;               /* HIP device ordinal; -1: host-only plan (path,
                                    query and pre-sampling only, no device calls) */
   size_t device_budget_bytes;   /* 0: no limit; else plan constants must fit     */
+  int32_t method;               /* PTSBE_METHOD_*; STATEVECTOR plans take
+                                   precision PTSBE_C64 only                      */
 } ptsbe_plan_opts_t;
 
 typedef struct {
   int32_t n_qubits, n_gates, n_sites, n_batches, n_words;  /* n_words = ceil(n/64) */
   int32_t max_kraus;            /* largest channel size                          */
   int64_t plan_device_bytes;    /* constants held by the plan                    */
+  int32_t method;               /* PTSBE_METHOD_NETWORK or _STATEVECTOR (chosen)  */
+  int32_t sv_windows;           /* statevector method: launches (state passes) per
+                                   trajectory to apply every gate; else 0        */
 } ptsbe_plan_info_t;
 
 /* Per-batch description of the unified path P^j (host-side cost model). */

@@ -86,19 +86,26 @@ class GradSpec:
                                       int(checkpoint_every))
 
 
+# contraction method of a plan: the sweep over each batch's network, or the
+# statevector of each trajectory (n <= 30); "auto" lets the planner choose
+METHODS = {"auto": 0, "network": 1, "statevector": 2}
+
+
 class Plan:
     """ptsbe_plan: the unified contraction path of every batch (host, once)."""
 
     def __init__(self, circuit, batch_sizes, hypersamples=4, path_seed=0, device=0, precision=0,
-                 device_budget_bytes=0):
+                 device_budget_bytes=0, method="auto"):
         self._lib = _lib.load()
         self.n_qubits = circuit.n_qubits
         self.n_sites = len(circuit.site_gate)
         self.batch_sizes = list(batch_sizes)
         arrs = _CircuitArrays(circuit)
         bs = np.array(self.batch_sizes, dtype=np.int32)
+        if method not in METHODS:
+            raise ValueError(f"method must be one of {sorted(METHODS)}")
         opts = _lib.PlanOpts_t(len(bs), _ptr(bs, C.c_int32), int(hypersamples), int(path_seed), int(precision),
-                               int(device), int(device_budget_bytes))
+                               int(device), int(device_budget_bytes), METHODS[method])
         h = C.c_void_p()
         _lib.check(self._lib.ptsbe_plan(C.byref(arrs.struct), C.byref(opts), C.byref(h)))
         self._h = h
@@ -108,6 +115,8 @@ class Plan:
         self.n_words = info.n_words
         self.n_gates = info.n_gates
         self.plan_device_bytes = info.plan_device_bytes
+        self.method = {v: k for k, v in METHODS.items()}[info.method]
+        self.sv_windows = info.sv_windows
 
     def close(self):
         if getattr(self, "_h", None):

@@ -41,7 +41,7 @@ class PlanOpts_t(C.Structure):
     _fields_ = [
         ("n_batches", C.c_int32), ("batch_sizes", C.POINTER(C.c_int32)), ("hypersamples", C.c_int32),
         ("path_seed", C.c_uint64), ("precision", C.c_int32), ("device", C.c_int32),
-        ("device_budget_bytes", C.c_size_t),
+        ("device_budget_bytes", C.c_size_t), ("method", C.c_int32),
     ]
 
 
@@ -49,6 +49,7 @@ class PlanInfo_t(C.Structure):
     _fields_ = [
         ("n_qubits", C.c_int32), ("n_gates", C.c_int32), ("n_sites", C.c_int32), ("n_batches", C.c_int32),
         ("n_words", C.c_int32), ("max_kraus", C.c_int32), ("plan_device_bytes", C.c_int64),
+        ("method", C.c_int32), ("sv_windows", C.c_int32),
     ]
 
 

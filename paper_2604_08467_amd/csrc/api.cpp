@@ -469,11 +469,28 @@ ptsbe_status_t ptsbe_plan(const ptsbe_circuit_t* c, const ptsbe_plan_opts_t* o, 
     p->gate_sites[g].push_back(s);
   }
   p->S = c->n_sites;
-  // path
+  // contraction method and path
+  if (o->method < PTSBE_METHOD_AUTO || o->method > PTSBE_METHOD_STATEVECTOR)
+    return fail(PTSBE_ERR_INVALID_ARG, "unknown method");
   std::string err;
-  if (!ptsbe::build_batch_plans(*p, err)) return fail(PTSBE_ERR_UNSUPPORTED, err);
+  bool use_sv = o->method == PTSBE_METHOD_STATEVECTOR || (o->method == PTSBE_METHOD_AUTO && p->n <= 20);
+  if (!use_sv) {
+    const bool net_ok = ptsbe::build_batch_plans(*p, err);
+    if (!net_ok) {
+      if (o->method == PTSBE_METHOD_NETWORK || p->n > ptsbe::kSvMaxQubits) return fail(PTSBE_ERR_UNSUPPORTED, err);
+      use_sv = true;
+    }
+  }
+  if (use_sv) {
+    if (p->n > ptsbe::kSvMaxQubits) return fail(PTSBE_ERR_UNSUPPORTED, "the statevector method needs n_qubits <= 30");
+    if (p->precision != PTSBE_C64) return fail(PTSBE_ERR_UNSUPPORTED, "the statevector method runs in complex64 only");
+    for (int b : p->batch_sizes)
+      if (b > 12) return fail(PTSBE_ERR_UNSUPPORTED, "the statevector method samples batches of at most 12 qubits");
+    p->method = PTSBE_METHOD_STATEVECTOR;
+    ptsbe::build_sv_batches(*p);
+  }
   // statevector schedule: every gate in circuit order, in place on qubit positions
-  if (p->n <= 30) {
+  if (p->n <= ptsbe::kSvMaxQubits) {
     for (int g = 0; g < p->G; ++g) {
       ptsbe::AbsorbStep st{};
       st.gate = g;
@@ -543,6 +560,7 @@ ptsbe_status_t ptsbe_plan(const ptsbe_circuit_t* c, const ptsbe_plan_opts_t* o, 
   for (auto& bp : p->batches)
     for (ptsbe::PartPlan* pp : {&bp.left, &bp.right, &bp.left_resume})
       ptsbe::build_segments(pp->steps, pp->segs, p->fused);
+  if (p->method == PTSBE_METHOD_STATEVECTOR) ptsbe::build_sv_schedule(*p);
   std::vector<ptsbe::AbsorbStep> steps;
   std::vector<int64_t> tables;
   for (auto& bp : p->batches) {
@@ -575,7 +593,8 @@ ptsbe_status_t ptsbe_plan(const ptsbe_circuit_t* c, const ptsbe_plan_opts_t* o, 
   if (steps.empty()) steps.push_back(ptsbe::AbsorbStep{});
   if (site_list.empty()) site_list.push_back(0);
   size_t bytes = dg.size() * sizeof(ptsbe::DeviceGate) + site_list.size() * 4 + site_ops.size() * sizeof(float2) +
-                 steps.size() * sizeof(ptsbe::AbsorbStep) + tables.size() * 8;
+                 steps.size() * sizeof(ptsbe::AbsorbStep) + tables.size() * 8 +
+                 p->fused.size() * sizeof(ptsbe::FusedStep);
   p->device_bytes = (int64_t)bytes;
   if (o->device_budget_bytes && bytes > o->device_budget_bytes)
     return fail(PTSBE_ERR_OUT_OF_MEMORY, "plan constants exceed device_budget_bytes");
@@ -631,6 +650,8 @@ ptsbe_status_t ptsbe_plan_query(ptsbe_plan_t plan, ptsbe_plan_info_t* out) {
   out->n_words = p->NW;
   out->max_kraus = p->max_kraus;
   out->plan_device_bytes = p->device_bytes;
+  out->method = p->method;
+  out->sv_windows = p->method == PTSBE_METHOD_STATEVECTOR ? (int32_t)p->sv_segs.size() : 0;
   return PTSBE_OK;
 }
 
@@ -723,6 +744,10 @@ ptsbe_status_t ptsbe_contract_workspace_size(ptsbe_plan_t plan, int32_t j, int64
   Plan* p = reinterpret_cast<Plan*>(plan);
   if (!p || !bytes) return fail(PTSBE_ERR_INVALID_ARG, "null argument");
   if (j < 0 || j >= (int)p->batches.size()) return fail(PTSBE_ERR_INVALID_ARG, "batch index out of range");
+  if (p->method == PTSBE_METHOD_STATEVECTOR) {
+    *bytes = ptsbe::sv_contract_workspace(*p, j, E, n_elems);
+    return PTSBE_OK;
+  }
   const auto& bp = p->batches[j];
   const size_t per_traj = ((size_t)8 << bp.right.labels.size()) + part_scratch_per_job(bp.right);
   const size_t per_elem = ((size_t)8 << bp.left.labels.size()) + part_scratch_per_job(bp.left);
@@ -766,6 +791,10 @@ size_t sample_persistent_bytes(const Plan& p, int64_t E, int64_t M) {
 ptsbe_status_t ptsbe_sample_workspace_size(ptsbe_plan_t plan, int64_t E, int64_t total_shots, size_t* bytes) {
   Plan* p = reinterpret_cast<Plan*>(plan);
   if (!p || !bytes) return fail(PTSBE_ERR_INVALID_ARG, "null argument");
+  if (p->method == PTSBE_METHOD_STATEVECTOR) {
+    *bytes = ptsbe::sv_sample_workspace(*p, E, total_shots);
+    return PTSBE_OK;
+  }
   size_t chunk = 0;
   for (auto& bp : p->batches) {
     const size_t per_traj = ((size_t)16 << bp.right.labels.size()) + part_scratch_per_job(bp.right);
@@ -795,6 +824,9 @@ ptsbe_status_t ptsbe_contract_batch(ptsbe_plan_t plan, int32_t j, const uint8_t*
     return fail(PTSBE_ERR_INVALID_ARG, "bad out_kind");
   HIP_TRY(hipSetDevice(p->device));
   hipStream_t s = (hipStream_t)stream;
+  if (p->method == PTSBE_METHOD_STATEVECTOR)
+    return ptsbe::sv_contract_batch(*p, j, d_kraus_idx, E, d_elem_traj, d_elem_prefix, n_elems, out_kind, d_out,
+                                    d_elem_total, d_workspace, workspace_bytes, s);
   Arena ar;
   ar.base = (char*)d_workspace;
   ar.cap = workspace_bytes;
@@ -833,6 +865,9 @@ ptsbe_status_t ptsbe_sample_shots(ptsbe_plan_t plan, const uint8_t* d_kraus_idx,
     return fail(PTSBE_ERR_INVALID_ARG, "null device pointer");
   HIP_TRY(hipSetDevice(p->device));
   hipStream_t s = (hipStream_t)stream;
+  if (p->method == PTSBE_METHOD_STATEVECTOR)
+    return ptsbe::sv_sample_shots(*p, d_kraus_idx, E, d_mult, d_shots_per_traj, seed, d_shots, d_shot_traj,
+                                  d_traj_weight, d_traj_norm, stats_out, d_workspace, workspace_bytes, s);
   // shot layout: trajectory i owns rows [base_i, base_i + m_i)
   std::vector<int64_t> m(E), base(E);
   HIP_TRY(hipMemcpyAsync(m.data(), d_shots_per_traj, (size_t)E * 8, hipMemcpyDeviceToHost, s));

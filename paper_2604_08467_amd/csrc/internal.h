@@ -42,6 +42,7 @@ struct Arena {
 
 constexpr int kMaxBatch = 30;       // largest b_j accepted
 constexpr int kMaxQubits = 1024;
+constexpr int kSvMaxQubits = 30;   // statevector method and adjoint pass
 constexpr int kVmMaxRank = 11;      // parts whose tensors fit 2^11 c64 run in LDS
 constexpr int kMaxSlices = 4;
 
@@ -171,6 +172,10 @@ struct Plan {
   // statevector schedule (qubit q = bit q, gates in circuit order, in place)
   std::vector<AbsorbStep> sv_steps;
   AbsorbStep* d_sv_steps = nullptr;
+  // statevector method: the same steps regrouped into LDS windows (sv_run holds
+  // them in execution order; every segment of sv_segs is one fused window)
+  int method = PTSBE_METHOD_NETWORK;
+  std::vector<AbsorbStep> sv_run;
   std::vector<Segment> sv_segs;
   // fused in-place steps of every part and of the statevector schedule
   std::vector<FusedStep> fused;
@@ -184,6 +189,14 @@ struct Plan {
 
 // planner.cpp
 bool build_batch_plans(Plan& p, std::string& err);
+// Batch table without network parts (statevector method).
+void build_sv_batches(Plan& p);
+// Gate windows of the statevector method: gates are packed greedily into
+// windows of at most kFuseMax qubits (qubits 0..3 always included, so that the
+// window's tile rows are 128-byte runs), a gate joining a window only when no
+// earlier gate left out of it touches its qubits (so it commutes with all of
+// them).  Fills p.sv_run, p.sv_segs and appends to p.fused.
+void build_sv_schedule(Plan& p);
 
 // kernels.hip: launchers (all asynchronous on `stream`)
 struct GateCtx {
@@ -312,6 +325,9 @@ hipError_t launch_init_elements(int64_t E, const int64_t* shots_per_traj, int32_
                                 int32_t* shot_cnt, int64_t* traj_shot_base, int32_t* shot_ids,
                                 int32_t* shot_traj, uint64_t* shots, int64_t M,
                                 hipStream_t stream);
+// Shot rows only: ids = identity, shots zeroed, row -> trajectory.
+hipError_t launch_init_shots(int64_t M, int64_t E, const int64_t* traj_shot_base, int32_t* shot_ids,
+                             int32_t* shot_traj, uint64_t* shots, int NW, hipStream_t stream);
 hipError_t launch_traj_ranges(const int32_t* elem_traj, int64_t n_elems, int64_t E,
                               int32_t* traj_first, hipStream_t stream);
 
@@ -339,5 +355,39 @@ hipError_t launch_grad_reduce(const float2* lam, const float2* psi, int64_t n_jo
 hipError_t launch_grad_sum(const double* partial, int64_t E, int n_slots, const int32_t* slot_param,
                            int n_params, double* grad, hipStream_t stream);
 hipError_t launch_value_sum(const double* vals, const double* w, int64_t E, double* out, hipStream_t stream);
+
+// ---------------------------------------------------------- statevector method
+// Marginal of batch qubits [start, start + b) of each element (trajectory,
+// prefix bits of qubits < start) from its trajectory's statevector:
+// part[e][s][x] = sum over later-qubit values y in slice s of |psi(y, x, prefix)|^2
+// (FP64 sums), then pop[e][x] = sum_s part[e][s][x] in slice order (FP32 out).
+struct SvMargArgs {
+  const float2* psi;                 // [traj - traj_base][2^n]
+  int n, start, b, NW;
+  int64_t n_elems;
+  const int32_t* elem_traj; int32_t traj_base;
+  const uint64_t* elem_prefix;       // [n_elems][NW] (bits of qubits < start used)
+  int log_split;                     // later-qubit values split into 2^log_split slices
+  double* part;                      // [n_elems][2^log_split][2^b]
+  float* pop;                        // [n_elems][2^b]
+};
+hipError_t launch_sv_marginal(const SvMargArgs& a, hipStream_t stream);
+// Amplitudes of the last batch: amp[e][x] = psi(x, prefix) (no later qubits).
+hipError_t launch_sv_amplitudes(const SvMargArgs& a, float2* amp, hipStream_t stream);
+// Elements of a trajectory range [t0, t0 + count): one element per trajectory.
+// statevector method drivers (sv.cpp)
+ptsbe_status_t sv_evolve(const Plan& p, const GateCtx& g, int64_t t0, int64_t nj, float2* psi, hipStream_t s);
+size_t sv_sample_workspace(const Plan& p, int64_t E, int64_t M);
+size_t sv_contract_workspace(const Plan& p, int j, int64_t E, int64_t n_elems);
+ptsbe_status_t sv_sample_shots(Plan& p, const uint8_t* d_kraus, int64_t E, const int64_t* d_mult,
+                               const int64_t* d_m, uint64_t seed, uint64_t* d_shots, int32_t* d_shot_traj,
+                               double* d_w, double* d_norm, int64_t* stats, void* d_workspace,
+                               size_t workspace_bytes, hipStream_t s);
+ptsbe_status_t sv_contract_batch(Plan& p, int j, const uint8_t* d_kraus, int64_t E, const int32_t* d_elem_traj,
+                                 const uint64_t* d_elem_prefix, int64_t n_elems, int32_t out_kind, void* d_out,
+                                 double* d_elem_total, void* d_workspace, size_t workspace_bytes, hipStream_t s);
+hipError_t launch_init_traj_range(int64_t t0, int64_t count, const int64_t* shots_per_traj,
+                                  const int64_t* traj_shot_base, int32_t* elem_traj, uint64_t* elem_prefix,
+                                  int NW, int32_t* shot_off, int32_t* shot_cnt, hipStream_t stream);
 
 }  // namespace ptsbe

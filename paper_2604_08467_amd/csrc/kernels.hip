@@ -1223,6 +1223,14 @@ hipError_t launch_init_elements(int64_t E, const int64_t* shots_per_traj, int32_
   return hipGetLastError();
 }
 
+hipError_t launch_init_shots(int64_t M, int64_t E, const int64_t* traj_shot_base, int32_t* shot_ids,
+                             int32_t* shot_traj, uint64_t* shots, int NW, hipStream_t stream) {
+  if (M > 0)
+    hipLaunchKernelGGL(init_shots_kernel, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, stream, M, E,
+                       traj_shot_base, shot_ids, shot_traj, shots, NW);
+  return hipGetLastError();
+}
+
 hipError_t launch_traj_ranges(const int32_t* elem_traj, int64_t n_elems, int64_t E, int32_t* traj_first,
                               hipStream_t stream) {
   hipLaunchKernelGGL(traj_first_kernel, dim3((unsigned)((n_elems + 1 + 255) / 256)), dim3(256), 0, stream,

@@ -493,6 +493,46 @@ namespace ptsbe {
 // positions unchanged) whose positions fit in kFuseMax bits become one fused
 // tile pass; every other step is launched alone.  P is padded with the lowest
 // unused positions so that a tile covers contiguous memory where possible.
+namespace {
+// One in-place step re-expressed on the positions of a fused window P (sorted):
+// window-local index bits for its legs, and the bits of hyper legs either inside
+// the window (local) or outside it (taken from the tile's base offset).
+FusedStep make_fused_step(const AbsorbStep& st, const std::vector<int>& Pv) {
+  FusedStep fs{};
+  auto in_P = [&](int pos) { return std::find(Pv.begin(), Pv.end(), pos) != Pv.end(); };
+  fs.gate = st.gate; fs.conj = st.conj; fs.nK = st.nK; fs.nN = st.nN; fs.nH = st.nH; fs.nS = st.nS;
+  auto loc = [&](int pos) { return (int)(std::find(Pv.begin(), Pv.end(), pos) - Pv.begin()); };
+  for (int k = 0; k < st.nK; ++k) fs.kloc[k] = loc(st.kpos[k]);
+  for (int k = 0; k < (1 << st.nK); ++k) {
+    fs.koff[k] = 0;
+    fs.kB[k] = st.kB[k];
+    for (int b = 0; b < st.nK; ++b)
+      if ((k >> b) & 1) fs.koff[k] += 1u << loc(st.kpos[b]);
+  }
+  for (int nn = 0; nn < (1 << st.nN); ++nn) {
+    fs.noff[nn] = 0;
+    fs.nB[nn] = st.nB[nn];
+    for (int b = 0; b < st.nN; ++b)
+      if ((nn >> b) & 1) fs.noff[nn] += 1u << loc(st.npos[b]);
+  }
+  // hyper legs: kept index bit hm -> tensor position (kept = all positions but kpos)
+  for (int h = 0; h < st.nH; ++h) {
+    int pos = -1, cnt = -1;
+    for (int q = 0; q < st.rA; ++q) {
+      bool is_k = false;
+      for (int b = 0; b < st.nK; ++b) is_k |= st.kpos[b] == q;
+      if (is_k) continue;
+      if (++cnt == st.hm[h]) { pos = q; break; }
+    }
+    if (in_P(pos)) { fs.h_inP[h] = 1; fs.h_pos[h] = loc(pos); }
+    else { fs.h_inP[h] = 0; fs.h_pos[h] = pos; }
+    fs.hw[h] = st.hw[h];
+  }
+  for (int k = 0; k < st.nS; ++k) { fs.sq[k] = st.sq[k]; fs.sw[k] = st.sw[k]; }
+  return fs;
+}
+}  // namespace
+
 bool build_segments(const std::vector<AbsorbStep>& steps, std::vector<Segment>& segs,
                     std::vector<FusedStep>& fused) {
   segs.clear();
@@ -540,44 +580,70 @@ bool build_segments(const std::vector<AbsorbStep>& steps, std::vector<Segment>& 
     std::vector<int> Pv(P.begin(), P.end());
     for (int k = 0; k < sg.np; ++k) sg.P[k] = Pv[k];
     sg.fused_off = (int64_t)fused.size();
-    for (size_t s = i; s < j; ++s) {
-      const AbsorbStep& st = steps[s];
-      FusedStep fs{};
-      fs.gate = st.gate; fs.conj = st.conj; fs.nK = st.nK; fs.nN = st.nN; fs.nH = st.nH; fs.nS = st.nS;
-      auto loc = [&](int pos) { return (int)(std::find(Pv.begin(), Pv.end(), pos) - Pv.begin()); };
-      for (int k = 0; k < st.nK; ++k) fs.kloc[k] = loc(st.kpos[k]);
-      for (int k = 0; k < (1 << st.nK); ++k) {
-        fs.koff[k] = 0;
-        fs.kB[k] = st.kB[k];
-        for (int b = 0; b < st.nK; ++b)
-          if ((k >> b) & 1) fs.koff[k] += 1u << loc(st.kpos[b]);
-      }
-      for (int nn = 0; nn < (1 << st.nN); ++nn) {
-        fs.noff[nn] = 0;
-        fs.nB[nn] = st.nB[nn];
-        for (int b = 0; b < st.nN; ++b)
-          if ((nn >> b) & 1) fs.noff[nn] += 1u << loc(st.npos[b]);
-      }
-      // hyper legs: kept index bit hm -> tensor position (kept = all positions but kpos)
-      for (int h = 0; h < st.nH; ++h) {
-        int pos = -1, cnt = -1;
-        for (int q = 0; q < st.rA; ++q) {
-          bool is_k = false;
-          for (int b = 0; b < st.nK; ++b) is_k |= st.kpos[b] == q;
-          if (is_k) continue;
-          if (++cnt == st.hm[h]) { pos = q; break; }
-        }
-        if (P.count(pos)) { fs.h_inP[h] = 1; fs.h_pos[h] = loc(pos); }
-        else { fs.h_inP[h] = 0; fs.h_pos[h] = pos; }
-        fs.hw[h] = st.hw[h];
-      }
-      for (int k = 0; k < st.nS; ++k) { fs.sq[k] = st.sq[k]; fs.sw[k] = st.sw[k]; }
-      fused.push_back(fs);
-    }
+    for (size_t s = i; s < j; ++s) fused.push_back(make_fused_step(steps[s], Pv));
     segs.push_back(sg);
     i = j;
   }
   return true;
+}
+
+void build_sv_batches(Plan& p) {
+  p.batches.clear();
+  int start = 0;
+  const int f = (int)p.batch_sizes.size();
+  for (int j = 0; j < f; ++j) {
+    BatchPlan bp;
+    bp.start = start;
+    bp.size = p.batch_sizes[j];
+    bp.doubled = j < f - 1;
+    p.batches.push_back(bp);
+    start += bp.size;
+  }
+}
+
+void build_sv_schedule(Plan& p) {
+  p.sv_run.clear();
+  p.sv_segs.clear();
+  const int n = p.n;
+  const int low = std::min(4, n);
+  std::vector<int> rest(p.sv_steps.size());
+  for (size_t i = 0; i < rest.size(); ++i) rest[i] = (int)i;
+  while (!rest.empty()) {
+    std::set<int> P, blocked;
+    for (int q = 0; q < low; ++q) P.insert(q);
+    std::vector<int> taken, left_out;
+    for (int g : rest) {
+      const AbsorbStep& st = p.sv_steps[g];
+      bool free = true;
+      for (int k = 0; k < st.nK; ++k) free = free && !blocked.count(st.kpos[k]);
+      std::set<int> P2 = P;
+      for (int k = 0; k < st.nK; ++k) P2.insert(st.kpos[k]);
+      if (free && (int)P2.size() <= std::min(kFuseMax, n)) {
+        P = P2;
+        taken.push_back(g);
+      } else {
+        for (int k = 0; k < st.nK; ++k) blocked.insert(st.kpos[k]);
+        left_out.push_back(g);
+      }
+    }
+    // pad the window with the lowest qubits not yet in it
+    for (int q = 0; (int)P.size() < std::min(kFuseMax, n) && q < n; ++q) P.insert(q);
+    Segment sg;
+    sg.first = (int)p.sv_run.size();
+    sg.count = (int)taken.size();
+    sg.fused = true;
+    sg.r = n;
+    sg.np = (int)P.size();
+    std::vector<int> Pv(P.begin(), P.end());
+    for (int k = 0; k < sg.np; ++k) sg.P[k] = Pv[k];
+    sg.fused_off = (int64_t)p.fused.size();
+    for (int g : taken) {
+      p.sv_run.push_back(p.sv_steps[g]);
+      p.fused.push_back(make_fused_step(p.sv_steps[g], Pv));
+    }
+    p.sv_segs.push_back(sg);
+    rest = left_out;
+  }
 }
 
 }  // namespace ptsbe

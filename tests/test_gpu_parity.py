@@ -38,13 +38,18 @@ def _contract(plan, torch, dev, kraus_d, traj, prefixes, j, amp=False):
     return out.cpu().numpy(), (None if tot is None else tot.cpu().numpy())
 
 
+METHODS = ["network", "statevector"]
+
+
 # ------------------------------------------------------------------ config 1
-def test_config1_amplitudes_populations_and_weights():
+@pytest.mark.parametrize("method", METHODS)
+def test_config1_amplitudes_populations_and_weights(method):
     torch, dev = torch_dev()
     wl = W.config1()
     c = wl.circuit
-    _say("config1: plan + PTS")
-    plan = _plan(c, wl.batch_sizes)
+    _say(f"config1 ({method}): plan + PTS")
+    plan = _plan(c, wl.batch_sizes, method=method)
+    assert plan.method == method
     kr, mult, lq, nd = plan.sample_trajectories(wl.pts_seed, wl.n_traj)
     E = len(kr)
     kd = to_dev(torch, dev, kr)
@@ -62,11 +67,12 @@ def test_config1_amplitudes_populations_and_weights():
     _say("config1: amplitudes/populations ok")
 
 
-def test_config1_shots_match_oracle_sampler():
+@pytest.mark.parametrize("method", METHODS)
+def test_config1_shots_match_oracle_sampler(method):
     torch, dev = torch_dev()
     wl = W.config1()
     c = wl.circuit
-    plan = _plan(c, wl.batch_sizes)
+    plan = _plan(c, wl.batch_sizes, method=method)
     kr, mult, lq, nd = plan.sample_trajectories(wl.pts_seed, wl.n_traj)
     E, m = len(kr), wl.shots_per_traj
     kd = to_dev(torch, dev, kr)
@@ -85,7 +91,7 @@ def test_config1_shots_match_oracle_sampler():
         got = shots[i * m:(i + 1) * m]
         mism += sum(1 for a, b in zip(got, ref[i]) if a != b)
         expect += m * flip_probability(pop[i], np.abs(psis[i]) ** 2)
-    _say(f"config1 shots: {mism} mismatches of {E * m}, expected flips {expect:.3g}")
+    _say(f"config1 ({method}) shots: {mism} mismatches of {E * m}, expected flips {expect:.3g}")
     assert_shot_parity(mism, expect, E * m)
     # weights: W_i = mult_i Z_i / sum mult Z (Pauli noise: Z_i = 1 up to gate rounding)
     Z = np.array([np.vdot(p, p).real for p in psis])
@@ -95,12 +101,13 @@ def test_config1_shots_match_oracle_sampler():
     assert list(out["elements_per_batch"]) == [E]
 
 
-def test_config1_pooled_shots_tvd():
+@pytest.mark.parametrize("method", METHODS)
+def test_config1_pooled_shots_tvd(method):
     """Pooled shots vs the weighted mean of the per-trajectory oracle distributions."""
     torch, dev = torch_dev()
     wl = W.config1()
     c = wl.circuit
-    plan = _plan(c, wl.batch_sizes)
+    plan = _plan(c, wl.batch_sizes, method=method)
     kr, mult, _, _ = plan.sample_trajectories(wl.pts_seed, wl.n_traj)
     E, m = len(kr), wl.shots_per_traj
     out = plan.sample_shots(to_dev(torch, dev, kr), to_dev(torch, dev, np.full(E, m, dtype=np.int64)),
@@ -134,12 +141,13 @@ def _small_cases():
     return cases
 
 
+@pytest.mark.parametrize("method", METHODS)
 @pytest.mark.parametrize("case", range(4))
-def test_small_multibatch_marginals(case):
+def test_small_multibatch_marginals(case, method):
     torch, dev = torch_dev()
     name, c, bs = _small_cases()[case]
-    _say(f"{name}: marginals b={bs}")
-    plan = _plan(c, bs)
+    _say(f"{name} ({method}): marginals b={bs}")
+    plan = _plan(c, bs, method=method)
     kr, mult, _, _ = plan.sample_trajectories(11 + case, 8)
     kd = to_dev(torch, dev, kr)
     psis = oracle_states(c, kr)
@@ -165,12 +173,13 @@ def test_small_multibatch_marginals(case):
                     assert np.linalg.norm(amp[e] - ref) / nr <= 1e-5, (name, e)
 
 
+@pytest.mark.parametrize("method", METHODS)
 @pytest.mark.parametrize("case", range(4))
-def test_small_multibatch_shots(case):
+def test_small_multibatch_shots(case, method):
     torch, dev = torch_dev()
     name, c, bs = _small_cases()[case]
-    _say(f"{name}: NBS shots b={bs}")
-    plan = _plan(c, bs)
+    _say(f"{name} ({method}): NBS shots b={bs}")
+    plan = _plan(c, bs, method=method)
     kr, mult, _, _ = plan.sample_trajectories(11 + case, 8)
     E, m = len(kr), 300
     kd = to_dev(torch, dev, kr)

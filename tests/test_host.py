@@ -34,7 +34,7 @@ def test_library_exports_every_declared_symbol():
 def test_host_plan_shapes(make):
     P = _lib()
     wl = make()
-    plan = P.Plan(wl.circuit, wl.batch_sizes, hypersamples=4, device=-1)
+    plan = P.Plan(wl.circuit, wl.batch_sizes, hypersamples=4, device=-1, method="network")
     f = len(wl.batch_sizes)
     n_gate_tensors = wl.circuit.n_gates
     for j in range(f):
@@ -139,3 +139,35 @@ def test_untouched_qubit_gets_identity():
     c.add_gate((0, 1), W.CNOT)
     plan = P.Plan(c, [2, 2], device=-1)
     assert plan.n_gates == 3           # two identities added for qubits 2 and 3
+
+
+def test_method_selection():
+    """auto: statevector for n <= 20 or when the network sweep does not fit (n <= 30);
+    network otherwise.  Forced methods fail with UNSUPPORTED where they cannot run."""
+    P = _lib()
+    wl1, wl2, wl3 = W.config1(), W.config2(), W.config3((10, 10, 5))
+    assert P.Plan(wl1.circuit, wl1.batch_sizes, device=-1).method == "statevector"
+    assert P.Plan(wl1.circuit, wl1.batch_sizes, device=-1, method="network").method == "network"
+    assert P.Plan(wl2.circuit, wl2.batch_sizes, device=-1).method == "network"
+    p3 = P.Plan(wl3.circuit, wl3.batch_sizes, device=-1)
+    assert p3.method == "statevector"
+    # every gate is applied exactly once; each window of at most 12 qubits holds >= 1 gate
+    assert 1 <= p3.sv_windows <= p3.n_gates
+    assert [p3.batch_info(j)["start"] for j in range(3)] == [0, 10, 20]
+    assert p3.batch_info(0)["n_right_steps"] == 0
+    _expect_status(2, lambda: P.Plan(wl3.circuit, wl3.batch_sizes, device=-1, method="network"))
+    _expect_status(2, lambda: P.Plan(wl3.circuit, wl3.batch_sizes, device=-1, precision=1))   # c64 only
+    _expect_status(2, lambda: P.Plan(wl3.circuit, [25], device=-1, method="statevector"))     # b > 12
+    _expect_status(2, lambda: P.Plan(wl2.circuit, wl2.batch_sizes, device=-1, method="statevector"))  # n > 30
+    with pytest.raises(ValueError):
+        P.Plan(wl1.circuit, wl1.batch_sizes, device=-1, method="dense")
+
+
+def test_statevector_windows_cover_small_circuits_in_one_launch():
+    """A circuit on at most 12 qubits is one LDS window: the whole state stays on chip."""
+    P = _lib()
+    wl1 = W.config1()
+    assert P.Plan(wl1.circuit, wl1.batch_sizes, device=-1).sv_windows == 1
+    c = W.sqrt_grid(4, 4, 8, np.random.default_rng(0))
+    p = P.Plan(c, [6, 6, 4], device=-1)
+    assert p.method == "statevector" and 2 <= p.sv_windows <= 16

@@ -283,19 +283,20 @@ def config2() -> Workload:
     return Workload("config2_n50_d6", c, 4096, 1000, [10] * 5, pts_seed=2002, shot_seed=2003)
 
 
-def config3(batch_sizes=(25,)) -> Workload:
-    """5x5 grid (q = 5r + c), 8 cycles of random sqrt(X)/sqrt(Y)/sqrt(W) on every
-    qubit then a CZ layer (patterns H-even, V-even, H-odd, V-odd); depolarising
-    p=0.01 then amplitude damping gamma=0.02 after every gate on each qubit it
-    touches; 16384 unique trajectories x 256 shots."""
-    rng = np.random.default_rng(3001)
-    c = Circuit(25)
-    dep = c.add_channel(depolarizing(0.01))
-    ad = c.add_channel(amplitude_damping(0.02))
-    pats = grid_layers(5, 5, 25)
+def sqrt_grid(rows: int, cols: int, cycles: int, rng: np.random.Generator, p: float = 0.01,
+              gamma: float = 0.02) -> Circuit:
+    """rows x cols grid (q = cols*r + c): each cycle applies a random sqrt(X)/sqrt(Y)/
+    sqrt(W) to every qubit, then a CZ layer (patterns H-even, V-even, H-odd, V-odd in
+    turn); depolarising p then amplitude damping gamma after every gate on each qubit
+    it touches."""
+    n = rows * cols
+    c = Circuit(n)
+    dep = c.add_channel(depolarizing(p))
+    ad = c.add_channel(amplitude_damping(gamma))
+    pats = grid_layers(rows, cols, n)
     choices = [SQRT_X, SQRT_Y, SQRT_W]
-    for cyc in range(8):
-        for q in range(25):
+    for cyc in range(cycles):
+        for q in range(n):
             g = c.add_gate((q,), choices[int(rng.integers(0, 3))])
             c.add_site(g, (q,), dep)
             c.add_site(g, (q,), ad)
@@ -304,6 +305,14 @@ def config3(batch_sizes=(25,)) -> Workload:
             for q in (a, b):
                 c.add_site(g, (q,), dep)
                 c.add_site(g, (q,), ad)
+    return c
+
+
+def config3(batch_sizes=(25,)) -> Workload:
+    """5x5 grid, 8 cycles of sqrt_grid (depolarising 0.01 + amplitude damping
+    0.02); 16384 unique trajectories x 256 shots."""
+    rng = np.random.default_rng(3001)
+    c = sqrt_grid(5, 5, 8, rng)
     return Workload("config3_grid5x5_d8", c, 16384, 256, list(batch_sizes), pts_seed=3002, shot_seed=3003)
 
 
