@@ -41,11 +41,15 @@ def amplitudes_from_state(psi: np.ndarray, n: int, start: int, b: int, prefix: i
 
 
 def inverse_cdf(pi: np.ndarray, u: float) -> int:
+    """x = min{x : C(x) > u C(last)}; the largest x with pi(x) > 0 if rounding
+    leaves none; 0 when pi is identically zero (a trajectory whose inserted
+    operators annihilate the state: it has weight 0 and all-zero shots)."""
     c = np.cumsum(np.asarray(pi, dtype=np.float64))   # sequential, index order
     hit = np.nonzero(c > u * c[-1])[0]
     if hit.size:
         return int(hit[0])
-    return int(np.nonzero(pi > 0)[0][-1])
+    pos = np.nonzero(np.asarray(pi) > 0)[0]
+    return int(pos[-1]) if pos.size else 0
 
 
 def shot_uniforms(seed: int, traj: int, j: int, n_shots: int) -> np.ndarray:

@@ -378,3 +378,39 @@ def test_gradient_value_matches_statevector_definition():
     o = gr.zz_diagonal(c.n_qubits, terms)
     ref = sum(wi * np.real(np.vdot(p, o * p)) for wi, p in zip(w, psis))
     assert abs(f - ref) < 1e-12
+
+
+def test_annihilated_trajectory_has_weight_zero_and_zero_shots():
+    """Amplitude damping's K1 twice on a qubit with only a diagonal gate between
+    maps every state to 0: Z = 0 exactly, the trajectory weight is 0, the
+    all-zero marginal draws x = 0, and the exact enumeration identity still holds
+    (the term contributes nothing).  K1 = [[0, sqrt(g)], [0, 0]], K1 K1 = 0."""
+    g = 0.3
+    c = W.Circuit(1)
+    ad = c.add_channel(W.amplitude_damping(g))
+    h = np.array([[1, 1], [1, -1]], dtype=np.complex128) / np.sqrt(2)
+    g0 = c.add_gate((0,), h)
+    c.add_site(g0, (0,), ad)
+    g1 = c.add_gate((0,), np.diag([1, 1j]).astype(np.complex128))   # S: diagonal
+    c.add_site(g1, (0,), ad)
+    dead = np.array([1, 1], dtype=np.uint8)
+    psi = sv.trajectory_state(c, dead)
+    assert np.all(psi == 0)
+    Z = np.array([np.vdot(sv.trajectory_state(c, np.array(k, dtype=np.uint8)),
+                          sv.trajectory_state(c, np.array(k, dtype=np.uint8))).real
+                  for k in ([0, 0], [0, 1], [1, 0], [1, 1])])
+    assert Z[3] == 0.0 and np.all(Z[:3] > 0)
+    w = sampling.trajectory_weights(Z, np.ones(4))
+    assert w[3] == 0.0 and abs(w.sum() - 1) < 1e-15
+    pi = sampling.marginal_from_state(psi, 1, 0, 1, 0)
+    for u in (0.0, 0.5, 1 - 2 ** -53):
+        assert sampling.inverse_cdf(pi, u) == 0
+    shots, _ = sampling.sample_trajectory(lambda j, p: pi, 3, 1, [1], 5, 7)
+    assert shots == [0] * 5
+    # exact enumeration: sum_K q(K) |psi_K|^2 = diag rho (textbook channel application)
+    q = {0: 1 - g / 2, 1: g / 2}
+    diag = np.zeros(2)
+    for k in itertools.product((0, 1), repeat=2):
+        st = sv.trajectory_state(c, np.array(k, dtype=np.uint8))
+        diag += q[k[0]] * q[k[1]] * np.abs(st) ** 2
+    np.testing.assert_allclose(diag, sv.density_matrix_diag(c), atol=1e-14)
