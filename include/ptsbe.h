@@ -34,7 +34,10 @@
  *   - Shot draws: u = Philox4x32-10(key = (lo32(seed), hi32(seed) ^ 2*0x9E3779B9),
  *     counter = (trajectory, batch, shot index within trajectory, 0)), top 53
  *     bits; x = min{x : C(x) > u * C(last)} with C the FP64 inclusive prefix sum
- *     of pi_e in index order (the largest x with pi_e(x) > 0 if none).
+ *     of pi_e in index order (the largest x with pi_e(x) > 0 if none; 0 if pi_e
+ *     is identically zero: a trajectory whose inserted operators annihilate the
+ *     state, e.g. amplitude damping's K1 twice on a qubit with only diagonal
+ *     gates between, has Z_i = 0, weight 0 and all-zero shots).
  *
  * Memory ownership
  *   - Host arrays passed in are copied before the call returns.
@@ -68,7 +71,7 @@ typedef enum {
   PTSBE_ERR_UNSUPPORTED = 2,   /* gate arity > 2, batch size > 30, path shape   */
   PTSBE_ERR_OUT_OF_MEMORY = 3, /* workspace or plan budget too small            */
   PTSBE_ERR_DEVICE = 4,        /* HIP runtime error                             */
-  PTSBE_ERR_NUMERIC = 5        /* zero-norm element or non-finite marginal      */
+  PTSBE_ERR_NUMERIC = 5        /* non-finite marginal                           */
 } ptsbe_status_t;
 
 enum { PTSBE_C64 = 0, PTSBE_SPLIT_BF16 = 1, PTSBE_SPLIT_F16 = 2 };
@@ -83,7 +86,8 @@ enum { PTSBE_MODE_PROPORTIONAL = 0 };
  *                marginals are then partial sums over that state.  Same
  *                unified-path property: one gate schedule for all trajectories.
  *   AUTO         STATEVECTOR when n <= 20, or when the network path does not
- *                fit and n <= 30; NETWORK otherwise. */
+ *                fit and n <= 30 (both only if every b_j <= 12); NETWORK
+ *                otherwise. */
 enum { PTSBE_METHOD_AUTO = 0, PTSBE_METHOD_NETWORK = 1, PTSBE_METHOD_STATEVECTOR = 2 };
 
 typedef struct ptsbe_plan_s* ptsbe_plan_t;
@@ -138,6 +142,7 @@ typedef struct {
   int32_t method;               /* PTSBE_METHOD_NETWORK or _STATEVECTOR (chosen)  */
   int32_t sv_windows;           /* statevector method: launches (state passes) per
                                    trajectory to apply every gate; else 0        */
+  int32_t sv_windows_by_size[3];/* the same for windows of 10, 11, 12 qubits     */
 } ptsbe_plan_info_t;
 
 /* Per-batch description of the unified path P^j (host-side cost model). */
@@ -257,6 +262,69 @@ ptsbe_status_t ptsbe_expect_grad(ptsbe_plan_t plan, const ptsbe_grad_spec_t* spe
                                  int64_t E, const double* d_weights, const double* d_theta,
                                  double* d_traj_value, double* d_value, double* d_grad, void* d_workspace,
                                  size_t workspace_bytes, void* stream);
+
+/* ------------------------------------------------------------- ragged sets
+ * Several circuits sampled in the same launches (an addition to the paper's
+ * method, which batches the trajectories of one circuit).  Every job is a
+ * statevector-method plan with its error sets and shot counts; the set cuts the
+ * jobs' trajectories into waves whose states fit the workspace and runs each
+ * wave as one fixed launch sequence with no host round trip: UPV merge per
+ * piece, one persistent gate-window launch per window level (all circuits'
+ * tiles in one grid-stride queue, heaviest circuits first), then per batch
+ * level one persistent marginal, sampling, scan and children launch over the
+ * elements of every circuit, with element counts kept on the device.  With
+ * PTSBE_RAGGED_GRAPH each wave is captured once as a hipGraph and replayed on
+ * later calls with the same arguments.  Kernel boundaries are the dependency
+ * barriers between window and batch levels.
+ *
+ * Ownership: the set owns its graphs; jobs' device arrays and the workspace
+ * are the caller's and must stay untouched between calls that replay graphs.
+ * stream must not be the null stream when PTSBE_RAGGED_GRAPH is set. */
+typedef struct ptsbe_ragged_s* ptsbe_ragged_t;
+enum { PTSBE_RAGGED_GRAPH = 1 };
+
+typedef struct {
+  ptsbe_plan_t plan;              /* statevector-method plan (b_j <= 12)          */
+  const uint8_t* d_kraus_idx;     /* [E][n_sites] uint8 (device)                   */
+  int64_t E;
+  const int64_t* shots_per_traj;  /* [E] m_i (HOST: the shot layout of the waves)  */
+  const int64_t* d_mult;          /* [E] multiplicities (device) or NULL (all 1)   */
+  uint64_t seed;                  /* shot seed (Philox tag 2, counters as in
+                                     ptsbe_sample_shots: same shots bit for bit)   */
+  uint64_t* d_shots;              /* [sum m_i][1] uint64 (device; n <= 30)         */
+  double* d_traj_weight;          /* [E] W_i within the job (device) or NULL       */
+  double* d_traj_norm;            /* [E] Z_i (device) or NULL                      */
+} ptsbe_ragged_job_t;
+
+typedef struct {
+  int32_t n_waves;                /* waves of the last call                        */
+  int32_t graphs_replayed;        /* waves of the last call served by a cached graph */
+  int64_t launches;               /* kernel launches of the last call              */
+  double wall_clock_khz;          /* rate of the completion stamps                 */
+} ptsbe_ragged_info_t;
+
+ptsbe_status_t ptsbe_ragged_create(int32_t device, ptsbe_ragged_t* out);
+void ptsbe_ragged_destroy(ptsbe_ragged_t set);
+ptsbe_status_t ptsbe_ragged_info(ptsbe_ragged_t set, ptsbe_ragged_info_t* out);
+/* Workspace for the jobs: states of at least one wave of the largest job
+ * trajectory plus the per-job arrays; more workspace means fewer waves. */
+ptsbe_status_t ptsbe_ragged_workspace_size(ptsbe_ragged_t set, const ptsbe_ragged_job_t* jobs, int32_t n_jobs,
+                                           size_t* bytes);
+/* Autotuner: for every job's plan, times one full gate-window pass of up to 4
+ * trajectories with windows of 10, 11 and 12 qubits (tiles of 2^10..2^12
+ * amplitudes in LDS) and keeps the fastest per plan for later calls.
+ * best_window (host, [n_jobs], may be NULL) receives the choice; ms_per_traj
+ * (host, [n_jobs][3], may be NULL) the measured times.  Synchronises. */
+ptsbe_status_t ptsbe_ragged_autotune(ptsbe_ragged_t set, const ptsbe_ragged_job_t* jobs, int32_t n_jobs,
+                                     int32_t* best_window, float* ms_per_traj, void* d_workspace,
+                                     size_t workspace_bytes, void* stream);
+/* Sample every job's shots (proportional mode).  d_done_ticks (device uint64
+ * [n_jobs + 1], may be NULL): entry n_jobs receives the wall-clock stamp at the
+ * start, entry i the stamp at which job i's last element was sampled (rate in
+ * ptsbe_ragged_info).  Synchronises `stream` at the end. */
+ptsbe_status_t ptsbe_ragged_sample_shots(ptsbe_ragged_t set, const ptsbe_ragged_job_t* jobs, int32_t n_jobs,
+                                         int32_t flags, uint64_t* d_done_ticks, void* d_workspace,
+                                         size_t workspace_bytes, void* stream);
 
 /* Timing hook for measurement: when enabled, the library records HIP events (on
  * the launch stream) around every launch of the MFMA join of doubled networks

@@ -117,6 +117,12 @@ class Plan:
         self.plan_device_bytes = info.plan_device_bytes
         self.method = {v: k for k, v in METHODS.items()}[info.method]
         self.sv_windows = info.sv_windows
+        self._sv_windows_by_size = list(info.sv_windows_by_size)
+
+    def sv_windows_for(self, window_qubits):
+        """Gate windows (state passes) of the statevector schedule for windows of
+        10, 11 or 12 qubits."""
+        return self._sv_windows_by_size[int(window_qubits) - 10]
 
     def close(self):
         if getattr(self, "_h", None):

@@ -16,6 +16,8 @@ EXPORTS = [
     "ptsbe_sample_trajectories", "ptsbe_contract_workspace_size", "ptsbe_sample_workspace_size",
     "ptsbe_contract_batch", "ptsbe_sample_shots", "ptsbe_profile_enable", "ptsbe_profile_read",
     "ptsbe_expect_workspace_size", "ptsbe_expect_grad",
+    "ptsbe_ragged_create", "ptsbe_ragged_destroy", "ptsbe_ragged_info", "ptsbe_ragged_workspace_size",
+    "ptsbe_ragged_autotune", "ptsbe_ragged_sample_shots",
 ]
 
 
@@ -49,7 +51,7 @@ class PlanInfo_t(C.Structure):
     _fields_ = [
         ("n_qubits", C.c_int32), ("n_gates", C.c_int32), ("n_sites", C.c_int32), ("n_batches", C.c_int32),
         ("n_words", C.c_int32), ("max_kraus", C.c_int32), ("plan_device_bytes", C.c_int64),
-        ("method", C.c_int32), ("sv_windows", C.c_int32),
+        ("method", C.c_int32), ("sv_windows", C.c_int32), ("sv_windows_by_size", C.c_int32 * 3),
     ]
 
 
@@ -104,7 +106,7 @@ def load():
     lib.ptsbe_expect_grad.argtypes = [P, C.POINTER(GradSpec_t), P, i64, P, P, P, P, P, P, sz, P]
     for name in EXPORTS:
         f = getattr(lib, name)
-        if name not in ("ptsbe_last_error", "ptsbe_plan_destroy"):
+        if name not in ("ptsbe_last_error", "ptsbe_plan_destroy", "ptsbe_ragged_destroy"):
             f.restype = C.c_int
     _lib = lib
     return lib

@@ -473,11 +473,13 @@ ptsbe_status_t ptsbe_plan(const ptsbe_circuit_t* c, const ptsbe_plan_opts_t* o, 
   if (o->method < PTSBE_METHOD_AUTO || o->method > PTSBE_METHOD_STATEVECTOR)
     return fail(PTSBE_ERR_INVALID_ARG, "unknown method");
   std::string err;
-  bool use_sv = o->method == PTSBE_METHOD_STATEVECTOR || (o->method == PTSBE_METHOD_AUTO && p->n <= 20);
+  bool sv_fits = p->n <= ptsbe::kSvMaxQubits;   // the statevector sampler takes batches of <= 12 qubits
+  for (int b : p->batch_sizes) sv_fits = sv_fits && b <= 12;
+  bool use_sv = o->method == PTSBE_METHOD_STATEVECTOR || (o->method == PTSBE_METHOD_AUTO && p->n <= 20 && sv_fits);
   if (!use_sv) {
     const bool net_ok = ptsbe::build_batch_plans(*p, err);
     if (!net_ok) {
-      if (o->method == PTSBE_METHOD_NETWORK || p->n > ptsbe::kSvMaxQubits) return fail(PTSBE_ERR_UNSUPPORTED, err);
+      if (o->method == PTSBE_METHOD_NETWORK || !sv_fits) return fail(PTSBE_ERR_UNSUPPORTED, err);
       use_sv = true;
     }
   }
@@ -613,6 +615,20 @@ ptsbe_status_t ptsbe_plan(const ptsbe_circuit_t* c, const ptsbe_plan_opts_t* o, 
     HIP_TRY(hipMemcpy(p->d_fused, p->fused.data(), p->fused.size() * sizeof(ptsbe::FusedStep),
                       hipMemcpyHostToDevice));
   }
+  if (p->method == PTSBE_METHOD_STATEVECTOR) {
+    for (int i = 0; i < 3; ++i) {
+      std::vector<ptsbe::RgWindow> w(p->sv_win[i].size());
+      for (size_t k = 0; k < w.size(); ++k) {
+        const ptsbe::Segment& sg = p->sv_win[i][k];
+        w[k].np = sg.np;
+        w[k].n_fs = sg.count;
+        for (int q = 0; q < ptsbe::kFuseMax; ++q) w[k].P[q] = sg.P[q];
+        w[k].fused_off = sg.fused_off;
+      }
+      HIP_TRY(hipMalloc(&p->d_rg_win[i], std::max<size_t>(1, w.size()) * sizeof(ptsbe::RgWindow)));
+      HIP_TRY(hipMemcpy(p->d_rg_win[i], w.data(), w.size() * sizeof(ptsbe::RgWindow), hipMemcpyHostToDevice));
+    }
+  }
   if (!p->sv_steps.empty()) {
     HIP_TRY(hipMalloc(&p->d_sv_steps, p->sv_steps.size() * sizeof(ptsbe::AbsorbStep)));
     HIP_TRY(hipMemcpy(p->d_sv_steps, p->sv_steps.data(), p->sv_steps.size() * sizeof(ptsbe::AbsorbStep),
@@ -637,6 +653,8 @@ void ptsbe_plan_destroy(ptsbe_plan_t plan) {
   if (p->d_tables) (void)hipFree(p->d_tables);
   if (p->d_sv_steps) (void)hipFree(p->d_sv_steps);
   if (p->d_fused) (void)hipFree(p->d_fused);
+  for (auto* w : p->d_rg_win)
+    if (w) (void)hipFree(w);
   delete p;
 }
 
@@ -652,6 +670,8 @@ ptsbe_status_t ptsbe_plan_query(ptsbe_plan_t plan, ptsbe_plan_info_t* out) {
   out->plan_device_bytes = p->device_bytes;
   out->method = p->method;
   out->sv_windows = p->method == PTSBE_METHOD_STATEVECTOR ? (int32_t)p->sv_segs.size() : 0;
+  for (int i = 0; i < 3; ++i)
+    out->sv_windows_by_size[i] = p->method == PTSBE_METHOD_STATEVECTOR ? (int32_t)p->sv_win[i].size() : 0;
   return PTSBE_OK;
 }
 
@@ -979,7 +999,7 @@ ptsbe_status_t ptsbe_sample_shots(ptsbe_plan_t plan, const uint8_t* d_kraus_idx,
     ptsbe_status_t st = collect_events(*p, evs);
     if (st != PTSBE_OK) return st;
   }
-  if (bad) return fail(PTSBE_ERR_NUMERIC, "an element had a zero or non-finite marginal total");
+  if (bad) return fail(PTSBE_ERR_NUMERIC, "an element had a non-finite marginal total");
   return PTSBE_OK;
 }
 

@@ -1,0 +1,136 @@
+// Device helpers shared by the sweep, statevector and ragged kernels (included
+// by each kernel translation unit; everything here is inline).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace ptsbe {
+namespace {
+
+__device__ inline float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ inline float2 cfma(float2 a, float2 b, float2 c) {
+  return make_float2(fmaf(a.x, b.x, fmaf(-a.y, b.y, c.x)), fmaf(a.x, b.y, fmaf(a.y, b.x, c.y)));
+}
+
+__device__ inline uint32_t bit_of_prefix(const uint64_t* pw, int q) {
+  return (uint32_t)((pw[q >> 6] >> (q & 63)) & 1ull);
+}
+
+// Gate entry i (< 16) of (traj, gate), conjugated for bra tensors.
+__device__ inline float2 gate_entry(const GateCtx& g, int gate, int traj, int conj, int i) {
+  float2 v = g.merged[((int64_t)traj * g.G + gate) * 16 + i];
+  if (conj) v.y = -v.y;
+  return v;
+}
+
+__device__ inline uint32_t insert_zero_bits(uint32_t m, const int32_t* pos, int n) {
+  for (int i = 0; i < n; ++i) {
+    const int p = pos[i];
+    const uint32_t lo = m & ((1u << p) - 1u);
+    m = ((m >> p) << (p + 1)) | lo;
+  }
+  return m;
+}
+
+__device__ inline uint32_t deposit_tile(uint32_t t, const int* P, int np, int r) {
+  // spread the bits of t over the positions not in P (ascending)
+  uint32_t out = 0;
+  int pi = 0, bit = 0;
+  for (int q = 0; q < r; ++q) {
+    if (pi < np && P[pi] == q) { ++pi; continue; }
+    out |= ((t >> bit) & 1u) << q;
+    ++bit;
+  }
+  return out;
+}
+
+// UPV merge of one (trajectory, gate) into out[16] (per thread, FP32 products).
+__device__ void merge_gate(const GateCtx& g, int gate, int traj, float2* out) {
+  const DeviceGate* G = g.gates + gate;
+  const int sb = G->site_begin, se = G->site_end;
+  const uint8_t* kr = g.kraus + (int64_t)traj * g.S;
+  bool dev = false;
+  for (int s = sb; s < se; ++s) dev |= kr[g.gate_site_list[s]] != 0;
+  if (!dev) {
+    for (int i = 0; i < 16; ++i) out[i] = G->def[i];
+    return;
+  }
+  const int d = G->arity == 2 ? 4 : 2;
+  float2 m[16], t[16];
+  for (int i = 0; i < 16; ++i) m[i] = G->raw[i];
+  for (int s = sb; s < se; ++s) {
+    const int site = g.gate_site_list[s];
+    const int k = kr[site];
+    const float2* op = g.site_ops + ((int64_t)site * g.max_kraus + k) * 16;
+    for (int r = 0; r < d; ++r)
+      for (int c = 0; c < d; ++c) {
+        float2 acc = make_float2(0.f, 0.f);
+        for (int x = 0; x < d; ++x) acc = cfma(op[r * d + x], m[x * d + c], acc);
+        t[r * d + c] = acc;
+      }
+    for (int i = 0; i < d * d; ++i) m[i] = t[i];
+  }
+  for (int i = 0; i < 16; ++i) out[i] = m[i];
+}
+
+// One tile pass of a window of in-place steps (positions P, |P| = np, of a rank-r
+// tensor A of one job): the 2^np entries whose other bits equal the tile index t
+// are loaded into LDS, every step is applied there (gate operands of trajectory
+// traj, double-buffered in Gm[32]), and the tile is written back.  pw: the job's
+// prefix words in LDS (for sliced legs).  Ends with a barrier, so the caller may
+// reuse tile and Gm at once.
+__device__ inline void window_tile_pass(const FusedStep* fs, int n_fs, const int* P, int np, int r, uint32_t t,
+                                        float2* Aj, const GateCtx& g, int traj, const uint64_t* pw,
+                                        float2* tile, float2* Gm) {
+  const uint32_t base = deposit_tile(t, P, np, r);
+  const uint32_t nt = 1u << np;
+  for (uint32_t l = threadIdx.x; l < nt; l += blockDim.x) {
+    uint32_t off = base;
+    for (int i = 0; i < np; ++i) off |= ((l >> i) & 1u) << P[i];
+    tile[l] = Aj[off];
+  }
+  for (int s = 0; s < n_fs; ++s) {
+    const FusedStep& st = fs[s];
+    if ((int)threadIdx.x < 16) Gm[16 * (s & 1) + (int)threadIdx.x] = gate_entry(g, st.gate, traj, st.conj, (int)threadIdx.x);
+    __syncthreads();
+    const float2* G = Gm + 16 * (s & 1);
+    int sb = 0;
+    for (int i = 0; i < st.nS; ++i) sb += (int)bit_of_prefix(pw, st.sq[i]) * st.sw[i];
+    const uint32_t nm = nt >> st.nK;
+    const int nk = 1 << st.nK, nn = 1 << st.nN;
+    for (uint32_t m = threadIdx.x; m < nm; m += blockDim.x) {
+      const uint32_t lb = insert_zero_bits(m, st.kloc, st.nK);
+      float2 a[16];
+#pragma unroll
+      for (int k = 0; k < 16; ++k)
+        if (k < nk) a[k] = tile[lb + st.koff[k]];
+      int hidx = sb;
+      for (int i = 0; i < st.nH; ++i) {
+        const uint32_t bit = st.h_inP[i] ? (lb >> st.h_pos[i]) & 1u : (base >> st.h_pos[i]) & 1u;
+        hidx += (int)bit * st.hw[i];
+      }
+      for (int n = 0; n < nn; ++n) {
+        float2 acc = make_float2(0.f, 0.f);
+        const int bn = hidx + st.nB[n];
+#pragma unroll
+        for (int k = 0; k < 16; ++k)
+          if (k < nk) acc = cfma(a[k], G[bn + st.kB[k]], acc);
+        tile[lb + st.noff[n]] = acc;
+      }
+    }
+    __syncthreads();
+  }
+  for (uint32_t l = threadIdx.x; l < nt; l += blockDim.x) {
+    uint32_t off = base;
+    for (int i = 0; i < np; ++i) off |= ((l >> i) & 1u) << P[i];
+    Aj[off] = tile[l];
+  }
+  __syncthreads();
+}
+
+}  // namespace
+}  // namespace ptsbe

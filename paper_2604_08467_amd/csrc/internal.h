@@ -83,6 +83,7 @@ struct FusedStep {
 // A run of steps executed by one launch: either one absorb step, or a fused
 // run of in-place steps whose positions lie in P (|P| = np <= kFuseMax).
 constexpr int kFuseMax = 12;
+constexpr int kSvWindowMin = 10;      // smallest statevector window the autotuner tries
 struct Segment {
   int first = 0, count = 1;
   bool fused = false;
@@ -131,6 +132,8 @@ struct BatchPlan {
   double join_flops_per_elem = 0;
 };
 
+struct RgWindow;
+
 // Per-gate tensor data uploaded at plan time.
 struct DeviceGate {
   float2 def[16];                   // default-branch merged matrix (all sites k=0)
@@ -176,7 +179,11 @@ struct Plan {
   // them in execution order; every segment of sv_segs is one fused window)
   int method = PTSBE_METHOD_NETWORK;
   std::vector<AbsorbStep> sv_run;
-  std::vector<Segment> sv_segs;
+  std::vector<Segment> sv_segs;                   // windows of kFuseMax qubits (the default)
+  // window schedules for every tile size the ragged autotuner may pick:
+  // sv_win[i] holds windows of at most kSvWindowMin + i qubits
+  std::vector<Segment> sv_win[3];
+  RgWindow* d_rg_win[3] = {nullptr, nullptr, nullptr};   // the same windows on the device
   // fused in-place steps of every part and of the statevector schedule
   std::vector<FusedStep> fused;
   FusedStep* d_fused = nullptr;
@@ -195,7 +202,7 @@ void build_sv_batches(Plan& p);
 // windows of at most kFuseMax qubits (qubits 0..3 always included, so that the
 // window's tile rows are 128-byte runs), a gate joining a window only when no
 // earlier gate left out of it touches its qubits (so it commutes with all of
-// them).  Fills p.sv_run, p.sv_segs and appends to p.fused.
+// them).  Fills p.sv_run, p.sv_segs, p.sv_win[*] and appends to p.fused.
 void build_sv_schedule(Plan& p);
 
 // kernels.hip: launchers (all asynchronous on `stream`)
@@ -389,5 +396,57 @@ ptsbe_status_t sv_contract_batch(Plan& p, int j, const uint8_t* d_kraus, int64_t
 hipError_t launch_init_traj_range(int64_t t0, int64_t count, const int64_t* shots_per_traj,
                                   const int64_t* traj_shot_base, int32_t* elem_traj, uint64_t* elem_prefix,
                                   int NW, int32_t* shot_off, int32_t* shot_cnt, hipStream_t stream);
+
+// ------------------------------------------------------------------ ragged sets
+constexpr int kRgMaxBatches = kSvMaxQubits;
+constexpr int kRgThreads = 256;
+struct RgWindow {                    // one gate window of a statevector plan
+  int32_t np, n_fs;
+  int32_t P[kFuseMax];
+  int64_t fused_off;
+};
+struct RgPiece {                     // trajectories [t0, t0 + nj) of one job inside a wave
+  GateCtx g;                         // kraus / merged of the piece (local trajectory index)
+  const RgWindow* win;               // the plan's windows (device)
+  const FusedStep* fused;            // the plan's fused steps (device)
+  float2* psi;                       // [nj][2^n]
+  uint64_t* shots;                   // the job's shot rows (device, one word per row)
+  double* norms;                     // [E] the job's squared norms (workspace)
+  int64_t row0;                      // first wave row of the piece
+  int64_t job_row0;                  // the same row in the job's shot array
+  int64_t part_off;                  // first-batch partial sums: first row
+  uint64_t seed;
+  int32_t job, n, f, n_win;
+  int32_t t0, nj, traj_off;          // job trajectory range, first wave trajectory
+  int32_t log_split0;                // slices per trajectory of the first-batch marginal
+  int32_t start[kRgMaxBatches], b[kRgMaxBatches];
+};
+struct RgWave {                      // device arrays of one wave (all in the workspace)
+  const RgPiece* pieces; int32_t n_pieces;
+  const int32_t* traj_piece;         // [T] piece of every wave trajectory
+  const int64_t* traj_row0;          // [T + 1] first wave row of every trajectory
+  int32_t T; int64_t R;              // trajectories, shot rows
+  int32_t xbits;                     // populations are stored with stride 2^xbits
+  int32_t* el_wt[2]; uint64_t* el_prefix[2]; int32_t* el_off[2]; int32_t* el_cnt[2];
+  int32_t* ids[2]; int32_t* shot_x;
+  int32_t* child_cnt; int32_t* child_off; int32_t* scan_sums;
+  int32_t* counts;                   // [kRgMaxBatches + 1] elements per batch level (device)
+  int64_t cap;                       // element capacity
+  float* pop; double* part;
+  const int64_t* m0_start;           // [n_pieces + 1] first-batch marginal tasks per piece
+  uint64_t* done;                    // [n_jobs + 1] completion stamps or null
+  int32_t* bad_flag;
+  int32_t n_jobs;
+};
+// window level l: entries (piece, first task) of the pieces with more than l windows
+struct RgLevel { const int32_t* piece; const int64_t* start; int32_t n; int64_t tasks; };
+hipError_t launch_rg_start(const RgWave& w, hipStream_t s);
+hipError_t launch_rg_prepare(const RgWave& w, int grid, hipStream_t s);
+hipError_t launch_rg_window(const RgWave& w, const RgLevel& lv, int level, int grid, hipStream_t s);
+hipError_t launch_rg_marginal0(const RgWave& w, int64_t tasks, int grid, hipStream_t s);
+hipError_t launch_rg_marginal(const RgWave& w, int j, int cur, int grid, hipStream_t s);
+hipError_t launch_rg_sample(const RgWave& w, int j, int cur, int grid, hipStream_t s);
+hipError_t launch_rg_scan(const RgWave& w, int j, hipStream_t s);
+hipError_t launch_rg_children(const RgWave& w, int j, int cur, int grid, hipStream_t s);
 
 }  // namespace ptsbe

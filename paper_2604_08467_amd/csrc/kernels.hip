@@ -14,6 +14,7 @@
 //    (prefix, x) of an element's shots become the next batch's elements.
 #include <hip/hip_runtime.h>
 
+#include "device_util.h"
 #include "internal.h"
 #include "philox.h"
 
@@ -22,45 +23,7 @@ namespace {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-__device__ inline float2 cmul(float2 a, float2 b) {
-  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
-__device__ inline float2 cfma(float2 a, float2 b, float2 c) {
-  return make_float2(fmaf(a.x, b.x, fmaf(-a.y, b.y, c.x)), fmaf(a.x, b.y, fmaf(a.y, b.x, c.y)));
-}
 
-__device__ inline uint32_t bit_of_prefix(const uint64_t* pw, int q) {
-  return (uint32_t)((pw[q >> 6] >> (q & 63)) & 1ull);
-}
-
-// UPV merge of one (trajectory, gate) into out[16] (per thread, FP32 products).
-__device__ void merge_gate(const GateCtx& g, int gate, int traj, float2* out) {
-  const DeviceGate* G = g.gates + gate;
-  const int sb = G->site_begin, se = G->site_end;
-  const uint8_t* kr = g.kraus + (int64_t)traj * g.S;
-  bool dev = false;
-  for (int s = sb; s < se; ++s) dev |= kr[g.gate_site_list[s]] != 0;
-  if (!dev) {
-    for (int i = 0; i < 16; ++i) out[i] = G->def[i];
-    return;
-  }
-  const int d = G->arity == 2 ? 4 : 2;
-  float2 m[16], t[16];
-  for (int i = 0; i < 16; ++i) m[i] = G->raw[i];
-  for (int s = sb; s < se; ++s) {
-    const int site = g.gate_site_list[s];
-    const int k = kr[site];
-    const float2* op = g.site_ops + ((int64_t)site * g.max_kraus + k) * 16;
-    for (int r = 0; r < d; ++r)
-      for (int c = 0; c < d; ++c) {
-        float2 acc = make_float2(0.f, 0.f);
-        for (int x = 0; x < d; ++x) acc = cfma(op[r * d + x], m[x * d + c], acc);
-        t[r * d + c] = acc;
-      }
-    for (int i = 0; i < d * d; ++i) m[i] = t[i];
-  }
-  for (int i = 0; i < 16; ++i) out[i] = m[i];
-}
 
 __global__ void upv_merge_kernel(GateCtx g, int64_t E, float2* __restrict__ merged) {
   const int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -72,21 +35,7 @@ __global__ void upv_merge_kernel(GateCtx g, int64_t E, float2* __restrict__ merg
   for (int i = 0; i < 8; ++i) o[i] = make_float4(m[2 * i].x, m[2 * i].y, m[2 * i + 1].x, m[2 * i + 1].y);
 }
 
-// Gate entry i (< 16) of (traj, gate), conjugated for bra tensors.
-__device__ inline float2 gate_entry(const GateCtx& g, int gate, int traj, int conj, int i) {
-  float2 v = g.merged[((int64_t)traj * g.G + gate) * 16 + i];
-  if (conj) v.y = -v.y;
-  return v;
-}
 
-__device__ inline uint32_t insert_zero_bits(uint32_t m, const int32_t* pos, int n) {
-  for (int i = 0; i < n; ++i) {
-    const int p = pos[i];
-    const uint32_t lo = m & ((1u << p) - 1u);
-    m = ((m >> p) << (p + 1)) | lo;
-  }
-  return m;
-}
 
 __device__ inline int slice_base(const AbsorbStep& st, const uint64_t* prefix) {
   int sb = 0;
@@ -97,12 +46,15 @@ __device__ inline int slice_base(const AbsorbStep& st, const uint64_t* prefix) {
 // C entries of all n for one kept index m (tables precomputed by the planner)
 __device__ inline void absorb_one(const AbsorbStep& st, int sbase, uint32_t m, const float2* A, float2* C,
                                   const float2* Gm) {
+  // the 16 slots are unrolled with a predicate so that a[] stays in registers
   float2 a[16];
   const int nK = st.nK, nN = st.nN;
   const uint32_t abase = insert_zero_bits(m, st.kpos, nK);
   const int nk = 1 << nK;
   // A always holds the running tensor; before the first step it is the scalar 1
-  for (int k = 0; k < nk; ++k) a[k] = A[abase + st.koff[k]];
+#pragma unroll
+  for (int k = 0; k < 16; ++k)
+    if (k < nk) a[k] = A[abase + st.koff[k]];
   int hidx = sbase;
   for (int i = 0; i < st.nH; ++i) hidx += (int)((m >> st.hm[i]) & 1u) * st.hw[i];
   const uint32_t cbase = insert_zero_bits(m, st.npos, nN);
@@ -110,7 +62,9 @@ __device__ inline void absorb_one(const AbsorbStep& st, int sbase, uint32_t m, c
   for (int n = 0; n < nn; ++n) {
     float2 acc = make_float2(0.f, 0.f);
     const int bn = hidx + st.nB[n];
-    for (int k = 0; k < nk; ++k) acc = cfma(a[k], Gm[bn + st.kB[k]], acc);
+#pragma unroll
+    for (int k = 0; k < 16; ++k)
+      if (k < nk) acc = cfma(a[k], Gm[bn + st.kB[k]], acc);
     C[cbase + st.noff[n]] = acc;
   }
 }
@@ -206,17 +160,6 @@ struct FusedArgs {
   int64_t tiles_per_job;
 };
 
-__device__ inline uint32_t deposit_tile(uint32_t t, const int* P, int np, int r) {
-  // spread the bits of t over the positions not in P (ascending)
-  uint32_t out = 0;
-  int pi = 0, bit = 0;
-  for (int q = 0; q < r; ++q) {
-    if (pi < np && P[pi] == q) { ++pi; continue; }
-    out |= ((t >> bit) & 1u) << q;
-    ++bit;
-  }
-  return out;
-}
 
 __global__ void __launch_bounds__(256) fused_inplace_kernel(FusedArgs f, GateCtx g, int64_t n_jobs,
                                                            const int32_t* __restrict__ job_traj, int32_t traj_base,
@@ -228,49 +171,9 @@ __global__ void __launch_bounds__(256) fused_inplace_kernel(FusedArgs f, GateCtx
   const int64_t job = blockIdx.x / f.tiles_per_job;
   const uint32_t t = (uint32_t)(blockIdx.x % f.tiles_per_job);
   if (job >= n_jobs) return;
-  const int tid = threadIdx.x;
   const int traj = job_traj ? job_traj[job] : traj_base + (int)job;
-  if (tid < NW) pw[tid] = job_prefix ? job_prefix[job * NW + tid] : 0ull;
-  const uint32_t base = deposit_tile(t, f.P, f.np, f.r);
-  float2* Aj = A + (job << f.r);
-  const uint32_t nt = 1u << f.np;
-  for (uint32_t l = tid; l < nt; l += blockDim.x) {
-    uint32_t off = base;
-    for (int i = 0; i < f.np; ++i) off |= ((l >> i) & 1u) << f.P[i];
-    tile[l] = Aj[off];
-  }
-  for (int s = 0; s < f.n_fs; ++s) {
-    const FusedStep& st = f.fs[s];
-    if (tid < 16) Gm[16 * (s & 1) + tid] = gate_entry(g, st.gate, traj, st.conj, tid);
-    __syncthreads();
-    const float2* G = Gm + 16 * (s & 1);
-    int sb = 0;
-    for (int i = 0; i < st.nS; ++i) sb += (int)bit_of_prefix(pw, st.sq[i]) * st.sw[i];
-    const uint32_t nm = nt >> st.nK;
-    const int nk = 1 << st.nK, nn = 1 << st.nN;
-    for (uint32_t m = tid; m < nm; m += blockDim.x) {
-      const uint32_t lb = insert_zero_bits(m, st.kloc, st.nK);
-      float2 a[16];
-      for (int k = 0; k < nk; ++k) a[k] = tile[lb + st.koff[k]];
-      int hidx = sb;
-      for (int i = 0; i < st.nH; ++i) {
-        const uint32_t bit = st.h_inP[i] ? (lb >> st.h_pos[i]) & 1u : (base >> st.h_pos[i]) & 1u;
-        hidx += (int)bit * st.hw[i];
-      }
-      for (int n = 0; n < nn; ++n) {
-        float2 acc = make_float2(0.f, 0.f);
-        const int bn = hidx + st.nB[n];
-        for (int k = 0; k < nk; ++k) acc = cfma(a[k], G[bn + st.kB[k]], acc);
-        tile[lb + st.noff[n]] = acc;
-      }
-    }
-    __syncthreads();
-  }
-  for (uint32_t l = tid; l < nt; l += blockDim.x) {
-    uint32_t off = base;
-    for (int i = 0; i < f.np; ++i) off |= ((l >> i) & 1u) << f.P[i];
-    Aj[off] = tile[l];
-  }
+  if ((int)threadIdx.x < NW) pw[threadIdx.x] = job_prefix ? job_prefix[job * NW + threadIdx.x] : 0ull;
+  window_tile_pass(f.fs, f.n_fs, f.P, f.np, f.r, t, A + (job << f.r), g, traj, pw, tile, Gm);
 }
 
 __global__ void init_gather_kernel(InitArgs init, int64_t n_jobs, const uint64_t* __restrict__ job_prefix, int NW,
@@ -820,7 +723,9 @@ __global__ void __launch_bounds__(kSampleThreads) sample_kernel(SampleArgs a) {
   const double Z = C[n - 1];
   if (threadIdx.x == 0) {
     a.elem_total[e] = Z;
-    if (!(Z > 0.0) || !isfinite(Z)) atomicExch(a.bad_flag, 1);
+    // Z == 0: the trajectory's inserted operators annihilated the state (weight 0,
+    // all-zero shots); only a non-finite or negative total is an error
+    if (!(Z >= 0.0) || !isfinite(Z)) atomicExch(a.bad_flag, 1);
   }
   const int traj = a.elem_traj[e];
   const int off = a.elem_shot_off[e];

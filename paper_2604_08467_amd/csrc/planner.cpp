@@ -601,13 +601,17 @@ void build_sv_batches(Plan& p) {
   }
 }
 
-void build_sv_schedule(Plan& p) {
-  p.sv_run.clear();
-  p.sv_segs.clear();
+namespace {
+// Windows of at most `wmax` qubits (see build_sv_schedule); appends the fused
+// steps to p.fused and returns the segments.
+std::vector<Segment> sv_windows(Plan& p, int wmax, std::vector<AbsorbStep>* run) {
+  std::vector<Segment> segs;
   const int n = p.n;
+  const int cap = std::min(wmax, n);
   const int low = std::min(4, n);
   std::vector<int> rest(p.sv_steps.size());
   for (size_t i = 0; i < rest.size(); ++i) rest[i] = (int)i;
+  int64_t first = 0;
   while (!rest.empty()) {
     std::set<int> P, blocked;
     for (int q = 0; q < low; ++q) P.insert(q);
@@ -618,7 +622,7 @@ void build_sv_schedule(Plan& p) {
       for (int k = 0; k < st.nK; ++k) free = free && !blocked.count(st.kpos[k]);
       std::set<int> P2 = P;
       for (int k = 0; k < st.nK; ++k) P2.insert(st.kpos[k]);
-      if (free && (int)P2.size() <= std::min(kFuseMax, n)) {
+      if (free && (int)P2.size() <= cap) {
         P = P2;
         taken.push_back(g);
       } else {
@@ -627,9 +631,9 @@ void build_sv_schedule(Plan& p) {
       }
     }
     // pad the window with the lowest qubits not yet in it
-    for (int q = 0; (int)P.size() < std::min(kFuseMax, n) && q < n; ++q) P.insert(q);
+    for (int q = 0; (int)P.size() < cap && q < n; ++q) P.insert(q);
     Segment sg;
-    sg.first = (int)p.sv_run.size();
+    sg.first = (int)first;
     sg.count = (int)taken.size();
     sg.fused = true;
     sg.r = n;
@@ -638,12 +642,21 @@ void build_sv_schedule(Plan& p) {
     for (int k = 0; k < sg.np; ++k) sg.P[k] = Pv[k];
     sg.fused_off = (int64_t)p.fused.size();
     for (int g : taken) {
-      p.sv_run.push_back(p.sv_steps[g]);
+      if (run) run->push_back(p.sv_steps[g]);
       p.fused.push_back(make_fused_step(p.sv_steps[g], Pv));
     }
-    p.sv_segs.push_back(sg);
+    first += (int64_t)taken.size();
+    segs.push_back(sg);
     rest = left_out;
   }
+  return segs;
+}
+}  // namespace
+
+void build_sv_schedule(Plan& p) {
+  p.sv_run.clear();
+  for (int i = 0; i < 3; ++i) p.sv_win[i] = sv_windows(p, kSvWindowMin + i, i == 2 ? &p.sv_run : nullptr);
+  p.sv_segs = p.sv_win[2];
 }
 
 }  // namespace ptsbe

@@ -229,7 +229,7 @@ ptsbe_status_t sv_sample_shots(Plan& p, const uint8_t* d_kraus, int64_t E, const
   int32_t bad = 0;
   HIP_TRY(hipMemcpyAsync(&bad, counters + 1, 4, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
-  if (bad) return fail(PTSBE_ERR_NUMERIC, "an element had a zero or non-finite marginal total");
+  if (bad) return fail(PTSBE_ERR_NUMERIC, "an element had a non-finite marginal total");
   return PTSBE_OK;
 }
 

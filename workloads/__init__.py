@@ -373,3 +373,25 @@ def config5(angles: Optional[np.ndarray] = None) -> Workload:
         angles = config5_angles()
     c = hea(20, 10, angles, [depolarizing(0.01)])
     return Workload("config5_hea_n20", c, 1024, 0, [20], pts_seed=5002, shot_seed=5003)
+
+
+def config4(n_circuits: int = 256, seed: int = 4001):
+    """Ragged mix: n ~ U{12..40}, depth ~ U{4..10}, 1D or 2D brickwork (p = 1/2)
+    of Haar SU(4) with depolarising p=0.005 after every gate, E_c =
+    round(exp(U[ln 32, ln 2048])) unique trajectories and 100 shots each,
+    batches of 10 qubits with the remainder last.  Returns a list of dicts
+    (circuit, n_traj, shots_per_traj, batch_sizes, pts_seed, shot_seed, layout,
+    depth)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(n_circuits):
+        n = int(rng.integers(12, 41))
+        depth = int(rng.integers(4, 11))
+        layout = "2d" if rng.random() < 0.5 else "1d"
+        E = int(round(float(np.exp(rng.uniform(np.log(32), np.log(2048))))))
+        crng = np.random.default_rng([seed, k])
+        c = random_brickwork(n, depth, crng, 0.005, layout).round_to_complex64()
+        bs = [10] * (n // 10) + ([n % 10] if n % 10 else [])
+        out.append({"circuit": c, "n_traj": E, "shots_per_traj": 100, "batch_sizes": bs,
+                    "pts_seed": 4002 + 10 * k, "shot_seed": 4003 + 10 * k, "layout": layout, "depth": depth})
+    return out
