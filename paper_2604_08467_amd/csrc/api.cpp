@@ -844,6 +844,15 @@ ptsbe_status_t ptsbe_contract_batch(ptsbe_plan_t plan, int32_t j, const uint8_t*
     return fail(PTSBE_ERR_INVALID_ARG, "bad out_kind");
   HIP_TRY(hipSetDevice(p->device));
   hipStream_t s = (hipStream_t)stream;
+  {
+    // per-trajectory buffers are indexed through elem_traj: it must be sorted and in range
+    std::vector<int32_t> et((size_t)n_elems);
+    HIP_TRY(hipMemcpyAsync(et.data(), d_elem_traj, (size_t)n_elems * 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int64_t e = 0; e < n_elems; ++e)
+      if (et[e] < 0 || et[e] >= E || (e > 0 && et[e] < et[e - 1]))
+        return fail(PTSBE_ERR_INVALID_ARG, "d_elem_traj must be non-decreasing trajectory ids in [0, E)");
+  }
   if (p->method == PTSBE_METHOD_STATEVECTOR)
     return ptsbe::sv_contract_batch(*p, j, d_kraus_idx, E, d_elem_traj, d_elem_prefix, n_elems, out_kind, d_out,
                                     d_elem_total, d_workspace, workspace_bytes, s);

@@ -376,6 +376,7 @@ struct SvMargArgs {
   const uint64_t* elem_prefix;       // [n_elems][NW] (bits of qubits < start used)
   int log_split;                     // later-qubit values split into 2^log_split slices
   double* part;                      // [n_elems][2^log_split][2^b]
+  int64_t part_rows = 0;             // capacity of part in rows of 2^b (checked at launch)
   float* pop;                        // [n_elems][2^b]
 };
 hipError_t launch_sv_marginal(const SvMargArgs& a, hipStream_t stream);

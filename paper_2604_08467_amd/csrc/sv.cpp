@@ -22,9 +22,13 @@ namespace {
 
 constexpr int64_t kSvElemCap = 16384;     // elements per marginal launch (contract_batch)
 
+// Slices of the later-qubit range per element: enough (element, slice) tasks to
+// fill the chip.  The partial-sum rows n_elems << ls are < kSplitRows whenever
+// ls > 0 (ls grows only while n_elems << (ls - 1) < kSplitRows / 2).
+constexpr int64_t kSplitRows = 4096;
 int pick_log_split(int64_t n_elems, int ybits) {
   int ls = 0;
-  while (ls < ybits && (n_elems << ls) < 2048) ++ls;
+  while (ls < ybits && (n_elems << ls) < kSplitRows / 2) ++ls;
   return ls;
 }
 
@@ -47,7 +51,7 @@ size_t sv_global_bytes(const Plan& p, int64_t E, int64_t M) {
   add((size_t)E * 8 * 2);                          // shot base, norms
   add(64);
   add((size_t)E * p.G * 16 * sizeof(float2));      // merged gates
-  add(((size_t)2048 << max_batch_bits(p)) * 8);     // split partial sums of the first batch
+  add(((size_t)kSplitRows << max_batch_bits(p)) * 8);   // split partial sums of the first batch
   return b + (1 << 20);
 }
 
@@ -73,7 +77,7 @@ size_t sv_contract_workspace(const Plan& p, int j, int64_t E, int64_t n_elems) {
   const int64_t ec = std::min<int64_t>(std::max<int64_t>(n_elems, 1), kSvElemCap);
   const size_t state = (size_t)8 << p.n;
   const int64_t k = std::max<int64_t>(1, std::min<int64_t>(E, (int64_t)(((size_t)16 << 30) / state)));
-  return (size_t)E * p.G * 16 * sizeof(float2) + (size_t)(E + 1) * 4 + (size_t)std::max<int64_t>(ec, 2048) * X * 8 +
+  return (size_t)E * p.G * 16 * sizeof(float2) + (size_t)(E + 1) * 4 + (size_t)std::max<int64_t>(ec, kSplitRows) * X * 8 +
          (size_t)k * state + ((size_t)4 << 20);
 }
 
@@ -111,7 +115,7 @@ ptsbe_status_t sv_sample_shots(Plan& p, const uint8_t* d_kraus, int64_t E, const
   // batch never outnumber max(trajectories, shots) of the chunk)
   const size_t state = (size_t)8 << p.n;
   const size_t per_elem = sv_elem_bytes(p);
-  const size_t fixed = (size_t)2048 * Xmax * 8 + ((size_t)1 << 20);   // first-batch split sums + alignment
+  const size_t fixed = (size_t)kSplitRows * Xmax * 8 + ((size_t)1 << 20);   // first-batch split sums + alignment
   const size_t avail = ar.left() > fixed ? ar.left() - fixed : 0;
   int64_t max_m = 0;
   for (int64_t t = 0; t < E; ++t) max_m = std::max(max_m, m[t]);
@@ -148,7 +152,8 @@ ptsbe_status_t sv_sample_shots(Plan& p, const uint8_t* d_kraus, int64_t E, const
   int32_t* scan_scratch = (int32_t*)ar.take(scan_scratch_bytes(cap));
   int32_t* parents = (int32_t*)ar.take((size_t)cap * 4);
   float* pop = (float*)ar.take((size_t)cap * Xmax * 4);
-  double* part = (double*)ar.take((size_t)std::max<int64_t>(cap, 2048) * Xmax * 8);
+  const int64_t part_rows = std::max<int64_t>(cap, kSplitRows);
+  double* part = (double*)ar.take((size_t)part_rows * Xmax * 8);
   bool ok = child_cnt && child_off && totals && scan_scratch && parents && pop && part;
   for (int k = 0; k < 2; ++k) ok = ok && el[k].traj && el[k].prefix && el[k].off && el[k].cnt;
   if (!ok) return fail(PTSBE_ERR_OUT_OF_MEMORY, "workspace too small for the element arrays");
@@ -188,7 +193,7 @@ ptsbe_status_t sv_sample_shots(Plan& p, const uint8_t* d_kraus, int64_t E, const
       ma.psi = psi; ma.n = p.n; ma.start = bp.start; ma.b = bp.size; ma.NW = p.NW;
       ma.n_elems = U; ma.elem_traj = el[cur].traj; ma.traj_base = (int32_t)t0; ma.elem_prefix = el[cur].prefix;
       ma.log_split = pick_log_split(U, p.n - bp.start - bp.size);
-      ma.part = part; ma.pop = pop;
+      ma.part = part; ma.part_rows = part_rows; ma.pop = pop;
       HIP_TRY(launch_sv_marginal(ma, s));
       SampleArgs sa{};
       sa.pop = pop; sa.b = bp.size; sa.start = bp.start; sa.NW = p.NW;
@@ -246,7 +251,8 @@ ptsbe_status_t sv_contract_batch(Plan& p, int j, const uint8_t* d_kraus, int64_t
   int32_t* d_first = (int32_t*)ar.take((size_t)(E + 1) * 4);
   const int64_t X = (int64_t)1 << bp.size;
   const int64_t ec = std::min<int64_t>(n_elems, kSvElemCap);
-  double* part = (double*)ar.take((size_t)std::max<int64_t>(ec, 2048) * X * 8);
+  const int64_t part_rows = std::max<int64_t>(ec, kSplitRows);
+  double* part = (double*)ar.take((size_t)part_rows * X * 8);
   if (!merged || !d_first || !part) return fail(PTSBE_ERR_OUT_OF_MEMORY, "workspace too small (merged gates, ranges)");
   GateCtx g{};
   g.gates = p.d_gates;
@@ -285,6 +291,7 @@ ptsbe_status_t sv_contract_batch(Plan& p, int j, const uint8_t* d_kraus, int64_t
       } else {
         ma.log_split = pick_log_split(ne, p.n - bp.start - bp.size);
         ma.part = part;
+        ma.part_rows = part_rows;
         ma.pop = (float*)d_out + a0 * X;
         HIP_TRY(launch_sv_marginal(ma, s));
         if (d_elem_total) HIP_TRY(launch_row_totals(ma.pop, ne, bp.size, d_elem_total + a0, s));

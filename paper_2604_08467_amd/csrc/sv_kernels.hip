@@ -113,7 +113,7 @@ __global__ void init_traj_range_kernel(int64_t t0, int64_t count, const int64_t*
 hipError_t launch_sv_marginal(const SvMargArgs& a, hipStream_t stream) {
   if (a.n_elems <= 0) return hipSuccess;
   if (a.b < 1 || a.b > 12 || a.start < 0 || a.start + a.b > a.n || a.log_split < 0 ||
-      a.log_split > a.n - a.start - a.b)
+      a.log_split > a.n - a.start - a.b || (a.n_elems << a.log_split) > a.part_rows)
     return hipErrorInvalidValue;
   const dim3 grid((unsigned)(a.n_elems << a.log_split));
   switch (a.b) {
