@@ -44,6 +44,8 @@ def flip_probability(pi_gpu, pi_ref):
     sum_x |C_gpu(x)/Z_gpu - C_ref(x)/Z_ref| (exact for the strict rule)."""
     cg = np.cumsum(np.asarray(pi_gpu, dtype=np.float64))
     cr = np.cumsum(np.asarray(pi_ref, dtype=np.float64))
+    if cg[-1] == 0 or cr[-1] == 0:          # an annihilated trajectory: every draw gives x = 0
+        return 0.0 if cg[-1] == cr[-1] else 1.0
     return float(np.abs(cg / cg[-1] - cr / cr[-1]).sum())
 
 
