@@ -84,7 +84,7 @@ __device__ void merge_gate(const GateCtx& g, int gate, int traj, float2* out) {
 // prefix words in LDS (for sliced legs).  Ends with a barrier, so the caller may
 // reuse tile and Gm at once.
 __device__ inline void window_tile_pass(const FusedStep* fs, int n_fs, const int* P, int np, int r, uint32_t t,
-                                        float2* Aj, const GateCtx& g, int traj, const uint64_t* pw,
+                                        float2* Aj, const GateCtx& g_, int traj, const uint64_t* pw,
                                         float2* tile, float2* Gm) {
   const uint32_t base = deposit_tile(t, P, np, r);
   const uint32_t nt = 1u << np;
@@ -93,9 +93,53 @@ __device__ inline void window_tile_pass(const FusedStep* fs, int n_fs, const int
     for (int i = 0; i < np; ++i) off |= ((l >> i) & 1u) << P[i];
     tile[l] = Aj[off];
   }
+  __syncthreads();   // the tile is complete before any step reads it
   for (int s = 0; s < n_fs; ++s) {
     const FusedStep& st = fs[s];
-    if ((int)threadIdx.x < 16) Gm[16 * (s & 1) + (int)threadIdx.x] = gate_entry(g, st.gate, traj, st.conj, (int)threadIdx.x);
+    // a plain gate applied in place: no hyper or sliced legs, outputs where the inputs were
+    const bool plain = st.nH == 0 && st.nS == 0 && st.nK == st.nN && st.nK >= 1 && st.nK <= 2 &&
+                       st.noff[1] == st.koff[1] && (st.nK == 1 || (st.noff[2] == st.koff[2] && st.noff[3] == st.koff[3]));
+    if (plain && st.nK == 1) {
+      // one-qubit gate in place: the 2x2 matrix in registers, pairs (lb, lb + o)
+      float2 g[2][2];
+#pragma unroll
+      for (int n = 0; n < 2; ++n)
+#pragma unroll
+        for (int k = 0; k < 2; ++k) g[n][k] = gate_entry(g_, st.gate, traj, st.conj, st.nB[n] + st.kB[k]);
+      const int p = st.kloc[0];
+      const uint32_t o = st.koff[1], lo_mask = (1u << p) - 1u;
+      for (uint32_t m = threadIdx.x; m < (nt >> 1); m += blockDim.x) {
+        const uint32_t lb = ((m & ~lo_mask) << 1) | (m & lo_mask);
+        const float2 a0 = tile[lb], a1 = tile[lb + o];
+        tile[lb] = cfma(g[0][1], a1, cmul(g[0][0], a0));
+        tile[lb + o] = cfma(g[1][1], a1, cmul(g[1][0], a0));
+      }
+      __syncthreads();
+      continue;
+    }
+    if (plain && st.nK == 2) {
+      // two-qubit gate in place: the 4x4 matrix in registers, quads at lb + koff[k]
+      float2 g[4][4];
+#pragma unroll
+      for (int n = 0; n < 4; ++n)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) g[n][k] = gate_entry(g_, st.gate, traj, st.conj, st.nB[n] + st.kB[k]);
+      const int p0 = st.kloc[0], p1 = st.kloc[1];
+      const uint32_t o1 = st.koff[1], o2 = st.koff[2], o3 = st.koff[3];
+      const uint32_t m0 = (1u << p0) - 1u, m1 = (1u << p1) - 1u;
+      for (uint32_t m = threadIdx.x; m < (nt >> 2); m += blockDim.x) {
+        uint32_t lb = ((m & ~m0) << 1) | (m & m0);
+        lb = ((lb & ~m1) << 1) | (lb & m1);
+        const float2 a0 = tile[lb], a1 = tile[lb + o1], a2 = tile[lb + o2], a3 = tile[lb + o3];
+        const uint32_t off[4] = {0u, o1, o2, o3};
+#pragma unroll
+        for (int n = 0; n < 4; ++n)
+          tile[lb + off[n]] = cfma(g[n][3], a3, cfma(g[n][2], a2, cfma(g[n][1], a1, cmul(g[n][0], a0))));
+      }
+      __syncthreads();
+      continue;
+    }
+    if ((int)threadIdx.x < 16) Gm[16 * (s & 1) + (int)threadIdx.x] = gate_entry(g_, st.gate, traj, st.conj, (int)threadIdx.x);
     __syncthreads();
     const float2* G = Gm + 16 * (s & 1);
     int sb = 0;
