@@ -54,48 +54,48 @@ __device__ void rotation_pair(int axis, double theta, float2* U, float2* dU) {
 }
 
 __global__ void grad_gates_kernel(GradGateArgs a) {
-  const int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (id >= a.E * a.g.G) return;
-  const int traj = (int)(id / a.g.G), gate = (int)(id % a.g.G);
-  const DeviceGate* G = a.g.gates + gate;
-  const int d = G->arity == 2 ? 4 : 2;
-  float2 base[16], m[16];
-  const int prm = a.gate_param[gate];
-  float2 dU[4];
-  if (prm >= 0) {
-    rotation_pair(a.gate_axis[gate], a.theta[prm], base, dU);
-  } else {
-    for (int i = 0; i < 16; ++i) base[i] = G->raw[i];
-  }
-  site_product_times(a.g, gate, traj, base, m);
-  float2* o = a.merged + id * 16;
-  float2* od = a.dagger + id * 16;
-  for (int i = 0; i < 16; ++i) o[i] = m[i];
-  for (int r = 0; r < 16; ++r) od[r] = make_float2(0.f, 0.f);
-  for (int r = 0; r < d; ++r)
-    for (int c = 0; c < d; ++c) {
-      const float2 v = m[c * d + r];
-      od[r * d + c] = make_float2(v.x, -v.y);
+  for (int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; id < a.E * a.g.G; id += (int64_t)gridDim.x * blockDim.x) {
+    const int traj = (int)(id / a.g.G), gate = (int)(id % a.g.G);
+    const DeviceGate* G = a.g.gates + gate;
+    const int d = G->arity == 2 ? 4 : 2;
+    float2 base[16], m[16];
+    const int prm = a.gate_param[gate];
+    float2 dU[4];
+    if (prm >= 0) {
+      rotation_pair(a.gate_axis[gate], a.theta[prm], base, dU);
+    } else {
+      for (int i = 0; i < 16; ++i) base[i] = G->raw[i];
     }
-  const int slot = a.gate_slot[gate];
-  if (slot >= 0) {
-    float2 dm[16];
-    site_product_times(a.g, gate, traj, dU, dm);
-    float2* odm = a.dmerged + ((int64_t)traj * a.n_slots + slot) * 16;
-    for (int i = 0; i < 16; ++i) odm[i] = dm[i];
+    site_product_times(a.g, gate, traj, base, m);
+    float2* o = a.merged + id * 16;
+    float2* od = a.dagger + id * 16;
+    for (int i = 0; i < 16; ++i) o[i] = m[i];
+    for (int r = 0; r < 16; ++r) od[r] = make_float2(0.f, 0.f);
+    for (int r = 0; r < d; ++r)
+      for (int c = 0; c < d; ++c) {
+        const float2 v = m[c * d + r];
+        od[r * d + c] = make_float2(v.x, -v.y);
+      }
+    const int slot = a.gate_slot[gate];
+    if (slot >= 0) {
+      float2 dm[16];
+      site_product_times(a.g, gate, traj, dU, dm);
+      float2* odm = a.dmerged + ((int64_t)traj * a.n_slots + slot) * 16;
+      for (int i = 0; i < 16; ++i) odm[i] = dm[i];
+    }
   }
 }
 
 __global__ void state_init_kernel(float2* psi, int64_t n_jobs, int n) {
   const int64_t per = (int64_t)1 << n;
-  const int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (id >= per * n_jobs) return;
-  psi[id] = make_float2((id % per) == 0 ? 1.f : 0.f, 0.f);
+  for (int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; id < per * n_jobs; id += (int64_t)gridDim.x * blockDim.x) {
+    psi[id] = make_float2((id % per) == 0 ? 1.f : 0.f, 0.f);
+  }
 }
 
 __global__ void copy_kernel(const float2* __restrict__ src, float2* __restrict__ dst, int64_t n) {
-  const int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (id < n) dst[id] = src[id];
+  for (int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; id < n; id += (int64_t)gridDim.x * blockDim.x)
+    dst[id] = src[id];
 }
 
 __device__ inline float zz_value(uint32_t x, const int32_t* zq, const double* zc, int nt) {
@@ -217,19 +217,19 @@ __global__ void value_sum_kernel(const double* __restrict__ vals, const double* 
 hipError_t launch_grad_gates(const GradGateArgs& a, hipStream_t stream) {
   const int64_t n = a.E * a.g.G;
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(grad_gates_kernel, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, stream, a);
+  hipLaunchKernelGGL(grad_gates_kernel, dim3(grid_blocks((n + 127) / 128)), dim3(128), 0, stream, a);
   return hipGetLastError();
 }
 
 hipError_t launch_state_init(float2* psi, int64_t n_jobs, int n, hipStream_t stream) {
   const int64_t total = n_jobs << n;
-  hipLaunchKernelGGL(state_init_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream, psi, n_jobs, n);
+  hipLaunchKernelGGL(state_init_kernel, dim3(grid_blocks((total + 255) / 256)), dim3(256), 0, stream, psi, n_jobs, n);
   return hipGetLastError();
 }
 
 hipError_t launch_copy(const float2* src, float2* dst, int64_t n, hipStream_t stream) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(copy_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, src, dst, n);
+  hipLaunchKernelGGL(copy_kernel, dim3(grid_blocks((n + 255) / 256)), dim3(256), 0, stream, src, dst, n);
   return hipGetLastError();
 }
 

@@ -41,6 +41,12 @@ struct Arena {
 };
 
 constexpr int kMaxBatch = 30;       // largest b_j accepted
+// An HSA dispatch counts its work-items in 32 bits: grids stay at most 2^20
+// workgroups and the kernels walk larger ranges with grid- or block-stride loops.
+constexpr int64_t kMaxGridBlocks = (int64_t)1 << 20;
+inline unsigned grid_blocks(int64_t blocks) {
+  return (unsigned)(blocks < 1 ? 1 : (blocks > kMaxGridBlocks ? kMaxGridBlocks : blocks));
+}
 constexpr int kMaxQubits = 1024;
 constexpr int kSvMaxQubits = 30;   // statevector method and adjoint pass
 constexpr int kVmMaxRank = 11;      // parts whose tensors fit 2^11 c64 run in LDS

@@ -26,13 +26,13 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 
 __global__ void upv_merge_kernel(GateCtx g, int64_t E, float2* __restrict__ merged) {
-  const int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (id >= E * g.G) return;
-  const int traj = (int)(id / g.G), gate = (int)(id % g.G);
-  float2 m[16];
-  merge_gate(g, gate, traj, m);
-  float4* o = reinterpret_cast<float4*>(merged + id * 16);
-  for (int i = 0; i < 8; ++i) o[i] = make_float4(m[2 * i].x, m[2 * i].y, m[2 * i + 1].x, m[2 * i + 1].y);
+  for (int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; id < E * g.G; id += (int64_t)gridDim.x * blockDim.x) {
+    const int traj = (int)(id / g.G), gate = (int)(id % g.G);
+    float2 m[16];
+    merge_gate(g, gate, traj, m);
+    float4* o = reinterpret_cast<float4*>(merged + id * 16);
+    for (int i = 0; i < 8; ++i) o[i] = make_float4(m[2 * i].x, m[2 * i].y, m[2 * i + 1].x, m[2 * i + 1].y);
+  }
 }
 
 
@@ -88,9 +88,8 @@ __global__ void part_vm_kernel(const AbsorbStep* __restrict__ steps, int n_steps
   float2* bufC = lds + buf_elems;
   float2* Gm = lds + 2 * buf_elems;              // two gate buffers of 16
   uint64_t* pw = reinterpret_cast<uint64_t*>(Gm + 32);
-  const int64_t job = blockIdx.x;
-  if (job >= n_jobs) return;
   const int tid = threadIdx.x;
+  for (int64_t job = blockIdx.x; job < n_jobs; job += gridDim.x) {
   const int traj = job_traj ? job_traj[job] : traj_base + (int)job;
   for (int w = tid; w < NW; w += blockDim.x) pw[w] = job_prefix ? job_prefix[job * NW + w] : 0ull;
   if (init.Vprev) {
@@ -118,6 +117,8 @@ __global__ void part_vm_kernel(const AbsorbStep* __restrict__ steps, int n_steps
   const int64_t n_out = (int64_t)1 << out_rank;
   float2* o = out + job * n_out;
   for (int64_t i = tid; i < n_out; i += blockDim.x) o[i] = bufA[i];
+  __syncthreads();   // LDS is reused by the next job of this workgroup
+  }
 }
 
 // --------------------------------------------------------------- HBM sweep step
@@ -129,10 +130,10 @@ __global__ void absorb_global_kernel(const AbsorbStep* __restrict__ st_dev, Gate
                                      const float2* A, float2* C) {   // A == C allowed for in-place steps
   __shared__ float2 Gm[16];
   __shared__ uint64_t pw[16];
-  const int64_t job = blockIdx.x / blocks_per_job;
-  const int64_t chunk = blockIdx.x % blocks_per_job;
-  if (job >= n_jobs) return;
   const AbsorbStep& st = *st_dev;
+  for (int64_t bid = blockIdx.x; bid < n_jobs * blocks_per_job; bid += gridDim.x) {
+  const int64_t job = bid / blocks_per_job;
+  const int64_t chunk = bid % blocks_per_job;
   const int traj = job_traj ? job_traj[job] : traj_base + (int)job;
   if (threadIdx.x < NW) pw[threadIdx.x] = job_prefix ? job_prefix[job * NW + threadIdx.x] : 0ull;
   if (threadIdx.x < 16) Gm[threadIdx.x] = gate_entry(g, st.gate, traj, st.conj, threadIdx.x);
@@ -147,6 +148,8 @@ __global__ void absorb_global_kernel(const AbsorbStep* __restrict__ st_dev, Gate
     const uint32_t m = m0 + i;
     if (m >= nm) break;
     absorb_one(st, sb, m, Aj, Cj, Gm);
+  }
+  __syncthreads();   // Gm and pw are rewritten for the next block of this workgroup
   }
 }
 
@@ -168,28 +171,29 @@ __global__ void __launch_bounds__(256) fused_inplace_kernel(FusedArgs f, GateCtx
   extern __shared__ float2 tile[];
   float2* Gm = tile + ((int64_t)1 << f.np);
   __shared__ uint64_t pw[16];
-  const int64_t job = blockIdx.x / f.tiles_per_job;
-  const uint32_t t = (uint32_t)(blockIdx.x % f.tiles_per_job);
-  if (job >= n_jobs) return;
-  const int traj = job_traj ? job_traj[job] : traj_base + (int)job;
-  if ((int)threadIdx.x < NW) pw[threadIdx.x] = job_prefix ? job_prefix[job * NW + threadIdx.x] : 0ull;
-  window_tile_pass(f.fs, f.n_fs, f.P, f.np, f.r, t, A + (job << f.r), g, traj, pw, tile, Gm);
+  for (int64_t bid = blockIdx.x; bid < n_jobs * f.tiles_per_job; bid += gridDim.x) {
+    const int64_t job = bid / f.tiles_per_job;
+    const uint32_t t = (uint32_t)(bid % f.tiles_per_job);
+    const int traj = job_traj ? job_traj[job] : traj_base + (int)job;
+    if ((int)threadIdx.x < NW) pw[threadIdx.x] = job_prefix ? job_prefix[job * NW + threadIdx.x] : 0ull;
+    window_tile_pass(f.fs, f.n_fs, f.P, f.np, f.r, t, A + (job << f.r), g, traj, pw, tile, Gm);   // ends with a barrier
+  }
 }
 
 __global__ void init_gather_kernel(InitArgs init, int64_t n_jobs, const uint64_t* __restrict__ job_prefix, int NW,
                                    float2* __restrict__ out) {
   const int64_t per = (int64_t)1 << init.r0;
-  const int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (id >= per * n_jobs) return;
-  const int64_t job = id / per;
-  const uint32_t m = (uint32_t)(id % per);
-  const uint64_t* pw = job_prefix + job * NW;
-  out[id] = init.Vprev[(int64_t)init.parent[job] * init.stride + init_offset(init, m, pw)];
+  for (int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; id < per * n_jobs; id += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t job = id / per;
+    const uint32_t m = (uint32_t)(id % per);
+    const uint64_t* pw = job_prefix + job * NW;
+    out[id] = init.Vprev[(int64_t)init.parent[job] * init.stride + init_offset(init, m, pw)];
+  }
 }
 
 __global__ void fill_one_kernel(float2* buf, int64_t n) {
-  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i < n) buf[i] = make_float2(1.f, 0.f);
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    buf[i] = make_float2(1.f, 0.f);
 }
 
 // ------------------------------------------------------------------------ join
@@ -201,42 +205,42 @@ __global__ void join_kernel(JoinArgs a) {
   const int64_t rows = (int64_t)1 << a.xb_bits;
   const int64_t nx = (int64_t)1 << a.xT_bits;
   const int64_t total = a.n_elems * rows * nx;
-  const int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (id >= total) return;
-  const uint32_t x = (uint32_t)(id % nx);
-  const uint32_t row = (uint32_t)((id / nx) % rows);
-  const int64_t e = id / (nx * rows);
-  const int lo_x = a.xT_bits < 12 ? a.xT_bits : 12;
-  const int lo_b = a.xb_bits < 12 ? a.xb_bits : 12;
-  const int lo_k = a.lk_bits < 12 ? a.lk_bits : 12;
-  const float2* V = a.V + e * a.v_stride;
-  const float2* T = a.T + (int64_t)(a.elem_traj[e] - a.traj_base) * a.t_stride;
-  const int64_t vr = tab(a.tab, a.jd.vr_lo, a.jd.vr_hi, lo_b, row);
-  const int64_t tx = tab(a.tab, a.jd.tx_lo, a.jd.tx_hi, lo_x, x);
-  const int nk = 1 << a.lk_bits;
-  const int64_t oidx = tab(a.tab, a.jd.ox_lo, a.jd.ox_hi, lo_x, x) + tab(a.tab, a.jd.ob_lo, a.jd.ob_hi, lo_b, row);
-  const int64_t nout = (int64_t)1 << a.b;
-  if (a.doubled) {
-    float acc = 0.f;
-    for (int k2 = 0; k2 < nk; ++k2) {
-      const float2 v2 = V[vr + tab(a.tab, a.jd.vc_lo, a.jd.vc_hi, lo_k, k2)];
-      const int64_t tb = tab(a.tab, a.jd.tb_lo, a.jd.tb_hi, lo_k, k2);
+  for (int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; id < total; id += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t x = (uint32_t)(id % nx);
+    const uint32_t row = (uint32_t)((id / nx) % rows);
+    const int64_t e = id / (nx * rows);
+    const int lo_x = a.xT_bits < 12 ? a.xT_bits : 12;
+    const int lo_b = a.xb_bits < 12 ? a.xb_bits : 12;
+    const int lo_k = a.lk_bits < 12 ? a.lk_bits : 12;
+    const float2* V = a.V + e * a.v_stride;
+    const float2* T = a.T + (int64_t)(a.elem_traj[e] - a.traj_base) * a.t_stride;
+    const int64_t vr = tab(a.tab, a.jd.vr_lo, a.jd.vr_hi, lo_b, row);
+    const int64_t tx = tab(a.tab, a.jd.tx_lo, a.jd.tx_hi, lo_x, x);
+    const int nk = 1 << a.lk_bits;
+    const int64_t oidx = tab(a.tab, a.jd.ox_lo, a.jd.ox_hi, lo_x, x) + tab(a.tab, a.jd.ob_lo, a.jd.ob_hi, lo_b, row);
+    const int64_t nout = (int64_t)1 << a.b;
+    if (a.doubled) {
+      float acc = 0.f;
+      for (int k2 = 0; k2 < nk; ++k2) {
+        const float2 v2 = V[vr + tab(a.tab, a.jd.vc_lo, a.jd.vc_hi, lo_k, k2)];
+        const int64_t tb = tab(a.tab, a.jd.tb_lo, a.jd.tb_hi, lo_k, k2);
+        float2 y = make_float2(0.f, 0.f);
+        for (int k = 0; k < nk; ++k) {
+          const float2 v = V[vr + tab(a.tab, a.jd.vc_lo, a.jd.vc_hi, lo_k, k)];
+          y = cfma(v, T[tx + tab(a.tab, a.jd.tk_lo, a.jd.tk_hi, lo_k, k) + tb], y);
+        }
+        acc += y.x * v2.x + y.y * v2.y;   // Re(y * conj(v2))
+      }
+      a.pop[e * nout + oidx] = acc;
+    } else {
       float2 y = make_float2(0.f, 0.f);
       for (int k = 0; k < nk; ++k) {
         const float2 v = V[vr + tab(a.tab, a.jd.vc_lo, a.jd.vc_hi, lo_k, k)];
-        y = cfma(v, T[tx + tab(a.tab, a.jd.tk_lo, a.jd.tk_hi, lo_k, k) + tb], y);
+        y = cfma(v, T[tx + tab(a.tab, a.jd.tk_lo, a.jd.tk_hi, lo_k, k)], y);
       }
-      acc += y.x * v2.x + y.y * v2.y;   // Re(y * conj(v2))
+      if (a.amp) a.amp[e * nout + oidx] = y;
+      if (a.pop) a.pop[e * nout + oidx] = y.x * y.x + y.y * y.y;
     }
-    a.pop[e * nout + oidx] = acc;
-  } else {
-    float2 y = make_float2(0.f, 0.f);
-    for (int k = 0; k < nk; ++k) {
-      const float2 v = V[vr + tab(a.tab, a.jd.vc_lo, a.jd.vc_hi, lo_k, k)];
-      y = cfma(v, T[tx + tab(a.tab, a.jd.tk_lo, a.jd.tk_hi, lo_k, k)], y);
-    }
-    if (a.amp) a.amp[e * nout + oidx] = y;
-    if (a.pop) a.pop[e * nout + oidx] = y.x * y.x + y.y * y.y;
   }
 }
 
@@ -246,17 +250,17 @@ __global__ void permute_T_kernel(const float2* __restrict__ T, int64_t t_stride,
                                  const int64_t* __restrict__ tables, Plan::JoinDev jd, int xT_bits, int lk_bits,
                                  int lb_bits, float2* __restrict__ Tc) {
   const int64_t per = (int64_t)1 << (xT_bits + lk_bits + lb_bits);
-  const int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (id >= per * n_traj) return;
-  const int64_t t = id / per, r = id % per;
-  const uint32_t kb = (uint32_t)(r & ((1u << lb_bits) - 1u));
-  const uint32_t k = (uint32_t)((r >> lb_bits) & ((1u << lk_bits) - 1u));
-  const uint32_t x = (uint32_t)(r >> (lb_bits + lk_bits));
-  const int lo_x = xT_bits < 12 ? xT_bits : 12, lo_k = lk_bits < 12 ? lk_bits : 12;
-  const int lo_b = lb_bits < 12 ? lb_bits : 12;
-  const int64_t off = tab(tables, jd.tx_lo, jd.tx_hi, lo_x, x) + tab(tables, jd.tk_lo, jd.tk_hi, lo_k, k) +
-                      tab(tables, jd.tb_lo, jd.tb_hi, lo_b, kb);
-  Tc[id] = T[t * t_stride + off];
+  for (int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; id < per * n_traj; id += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t t = id / per, r = id % per;
+    const uint32_t kb = (uint32_t)(r & ((1u << lb_bits) - 1u));
+    const uint32_t k = (uint32_t)((r >> lb_bits) & ((1u << lk_bits) - 1u));
+    const uint32_t x = (uint32_t)(r >> (lb_bits + lk_bits));
+    const int lo_x = xT_bits < 12 ? xT_bits : 12, lo_k = lk_bits < 12 ? lk_bits : 12;
+    const int lo_b = lb_bits < 12 ? lb_bits : 12;
+    const int64_t off = tab(tables, jd.tx_lo, jd.tx_hi, lo_x, x) + tab(tables, jd.tk_lo, jd.tk_hi, lo_k, k) +
+                        tab(tables, jd.tb_lo, jd.tb_hi, lo_b, kb);
+    Tc[id] = T[t * t_stride + off];
+  }
 }
 
 // Split-precision variant of the doubled-network join (K = 32): every operand
@@ -652,8 +656,8 @@ __global__ void __launch_bounds__(256) qform_mfma_kernel(QformArgs a) {
 
 __global__ void row_totals_kernel(const float* pop, int64_t n_elems, int b, double* totals) {
   __shared__ double red[256];
-  const int64_t e = blockIdx.x;
   const int64_t n = (int64_t)1 << b;
+  for (int64_t e = blockIdx.x; e < n_elems; e += gridDim.x) {
   // sequential chunks per thread, then a fixed tree: deterministic
   double s = 0.0;
   const int64_t per = (n + blockDim.x - 1) / blockDim.x;
@@ -666,6 +670,8 @@ __global__ void row_totals_kernel(const float* pop, int64_t n_elems, int b, doub
     __syncthreads();
   }
   if (threadIdx.x == 0) totals[e] = red[0];
+  __syncthreads();
+  }
 }
 
 // --------------------------------------------------------------------- sampling
@@ -702,8 +708,7 @@ __global__ void __launch_bounds__(kSampleThreads) sample_kernel(SampleArgs a) {
   int* hist = reinterpret_cast<int*>(part + kSampleThreads);
   __shared__ int last_pos;
   __shared__ int nchild;
-  const int64_t e = blockIdx.x;
-  if (e >= a.n_elems) return;
+  for (int64_t e = blockIdx.x; e < a.n_elems; e += gridDim.x) {
   const float* pi = a.pop + e * (int64_t)n;
   for (int i = threadIdx.x; i < n; i += kSampleThreads) {
     C[i] = (double)pi[i];
@@ -761,6 +766,8 @@ __global__ void __launch_bounds__(kSampleThreads) sample_kernel(SampleArgs a) {
     __syncthreads();
     if (threadIdx.x == 0) a.child_cnt[e] = nchild;
   }
+  __syncthreads();   // LDS and the shared scalars are reset for the next element
+  }
 }
 
 __global__ void __launch_bounds__(kSampleThreads) children_kernel(ChildArgs a) {
@@ -771,8 +778,7 @@ __global__ void __launch_bounds__(kSampleThreads) children_kernel(ChildArgs a) {
   int* rank = ism + 2 * n;  // exclusive scan of (count > 0)
   __shared__ int part_s[kSampleThreads];
   __shared__ int part_r[kSampleThreads];
-  const int64_t e = blockIdx.x;
-  if (e >= a.n_elems) return;
+  for (int64_t e = blockIdx.x; e < a.n_elems; e += gridDim.x) {
   for (int i = threadIdx.x; i < n; i += kSampleThreads) hist[i] = 0;
   __syncthreads();
   const int off = a.elem_shot_off[e], cnt = a.elem_shot_cnt[e];
@@ -825,6 +831,8 @@ __global__ void __launch_bounds__(kSampleThreads) children_kernel(ChildArgs a) {
     const int x = a.shot_x[row];
     const int pos = atomicAdd(&start[x], 1);
     a.out_shot_ids[off + pos] = row;
+  }
+  __syncthreads();   // LDS is reused by the next element
   }
 }
 
@@ -944,7 +952,7 @@ hipError_t launch_init_gather(const InitArgs& init, int64_t n_jobs, const uint64
                               float2* out, hipStream_t stream) {
   const int64_t total = n_jobs << init.r0;
   if (total <= 0) return hipSuccess;
-  hipLaunchKernelGGL(init_gather_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream, init, n_jobs,
+  hipLaunchKernelGGL(init_gather_kernel, dim3(grid_blocks((total + 255) / 256)), dim3(256), 0, stream, init, n_jobs,
                      job_prefix, NW, out);
   return hipGetLastError();
 }
@@ -957,7 +965,7 @@ hipError_t launch_part_vm(const AbsorbStep* d_steps, int n_steps, int peak, Gate
   const size_t shmem = (size_t)(2 * buf + 32) * sizeof(float2) + (size_t)NW * sizeof(uint64_t);
   // one wavefront per job while the tensor has <= 128 entries
   int threads = buf / 2 < 64 ? 64 : (buf / 2 > 256 ? 256 : buf / 2);
-  hipLaunchKernelGGL(part_vm_kernel, dim3((unsigned)n_jobs), dim3(threads), shmem, stream, d_steps, n_steps,
+  hipLaunchKernelGGL(part_vm_kernel, dim3(grid_blocks(n_jobs)), dim3(threads), shmem, stream, d_steps, n_steps,
                      buf, g, n_jobs, job_traj, traj_base, job_prefix, NW, init, out, out_rank);
   return hipGetLastError();
 }
@@ -965,7 +973,7 @@ hipError_t launch_part_vm(const AbsorbStep* d_steps, int n_steps, int peak, Gate
 hipError_t launch_upv_merge(GateCtx g, int64_t E, float2* merged, hipStream_t stream) {
   const int64_t n = E * g.G;
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(upv_merge_kernel, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, stream, g, E, merged);
+  hipLaunchKernelGGL(upv_merge_kernel, dim3(grid_blocks((n + 127) / 128)), dim3(128), 0, stream, g, E, merged);
   return hipGetLastError();
 }
 
@@ -976,7 +984,7 @@ hipError_t launch_absorb_global(const AbsorbStep& st, const AbsorbStep* d_st, Ga
   const int64_t nm = (int64_t)1 << (st.rC - st.nN);
   const int threads = 256;
   const int64_t bpj = (nm + kAbsorbPerBlock - 1) / kAbsorbPerBlock;
-  hipLaunchKernelGGL(absorb_global_kernel, dim3((unsigned)(bpj * n_jobs)), dim3(threads), 0, stream, d_st, g,
+  hipLaunchKernelGGL(absorb_global_kernel, dim3(grid_blocks(bpj * n_jobs)), dim3(threads), 0, stream, d_st, g,
                      n_jobs, bpj, job_traj, traj_base, job_prefix, NW, A, C);
   return hipGetLastError();
 }
@@ -992,21 +1000,21 @@ hipError_t launch_fused(const Segment& seg, const FusedStep* d_fs, GateCtx g, in
   for (int i = 0; i < kFuseMax; ++i) f.P[i] = seg.P[i];
   f.tiles_per_job = (int64_t)1 << (seg.r - seg.np);
   const size_t shmem = ((size_t)1 << seg.np) * sizeof(float2) + 32 * sizeof(float2);
-  hipLaunchKernelGGL(fused_inplace_kernel, dim3((unsigned)(f.tiles_per_job * n_jobs)), dim3(256), shmem, stream, f, g,
+  hipLaunchKernelGGL(fused_inplace_kernel, dim3(grid_blocks(f.tiles_per_job * n_jobs)), dim3(256), shmem, stream, f, g,
                      n_jobs, job_traj, traj_base, job_prefix, NW, A);
   return hipGetLastError();
 }
 
 hipError_t launch_fill_one(float2* buf, int64_t n, hipStream_t stream) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(fill_one_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, buf, n);
+  hipLaunchKernelGGL(fill_one_kernel, dim3(grid_blocks((n + 255) / 256)), dim3(256), 0, stream, buf, n);
   return hipGetLastError();
 }
 
 hipError_t launch_join(const JoinArgs& a, hipStream_t stream) {
   const int64_t total = a.n_elems * ((int64_t)1 << (a.xb_bits + a.xT_bits));
   if (total <= 0) return hipSuccess;
-  hipLaunchKernelGGL(join_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream, a);
+  hipLaunchKernelGGL(join_kernel, dim3(grid_blocks((total + 255) / 256)), dim3(256), 0, stream, a);
   return hipGetLastError();
 }
 
@@ -1015,7 +1023,7 @@ hipError_t launch_permute_T(const float2* T, int64_t t_stride, int64_t n_traj, c
                             hipStream_t stream) {
   const int64_t total = n_traj << (xT_bits + lk_bits + lb_bits);
   if (total <= 0) return hipSuccess;
-  hipLaunchKernelGGL(permute_T_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream, T, t_stride,
+  hipLaunchKernelGGL(permute_T_kernel, dim3(grid_blocks((total + 255) / 256)), dim3(256), 0, stream, T, t_stride,
                      n_traj, tab, jd, xT_bits, lk_bits, lb_bits, Tc);
   return hipGetLastError();
 }
@@ -1073,7 +1081,7 @@ hipError_t launch_ketjoin(const QformArgs& a, int n_traj, int max_rows, hipStrea
 
 hipError_t launch_row_totals(const float* pop, int64_t n_elems, int b, double* totals, hipStream_t stream) {
   if (n_elems <= 0) return hipSuccess;
-  hipLaunchKernelGGL(row_totals_kernel, dim3((unsigned)n_elems), dim3(256), 0, stream, pop, n_elems, b, totals);
+  hipLaunchKernelGGL(row_totals_kernel, dim3(grid_blocks(n_elems)), dim3(256), 0, stream, pop, n_elems, b, totals);
   return hipGetLastError();
 }
 
@@ -1081,7 +1089,7 @@ hipError_t launch_sample(const SampleArgs& a, hipStream_t stream) {
   if (a.n_elems <= 0) return hipSuccess;
   const int n = 1 << a.b;
   const size_t shmem = (size_t)n * sizeof(double) + kSampleThreads * sizeof(double) + (size_t)n * sizeof(int);
-  hipLaunchKernelGGL(sample_kernel, dim3((unsigned)a.n_elems), dim3(kSampleThreads), shmem, stream, a);
+  hipLaunchKernelGGL(sample_kernel, dim3(grid_blocks(a.n_elems)), dim3(kSampleThreads), shmem, stream, a);
   return hipGetLastError();
 }
 
@@ -1089,7 +1097,7 @@ hipError_t launch_children(const ChildArgs& a, hipStream_t stream) {
   if (a.n_elems <= 0) return hipSuccess;
   const int n = 1 << a.b;
   const size_t shmem = (size_t)3 * n * sizeof(int);
-  hipLaunchKernelGGL(children_kernel, dim3((unsigned)a.n_elems), dim3(kSampleThreads), shmem, stream, a);
+  hipLaunchKernelGGL(children_kernel, dim3(grid_blocks(a.n_elems)), dim3(kSampleThreads), shmem, stream, a);
   return hipGetLastError();
 }
 

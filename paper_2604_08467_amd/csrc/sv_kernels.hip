@@ -24,9 +24,9 @@ __device__ inline const float2* elem_state(const SvMargArgs& a, int64_t e, uint6
 // 2^start (contiguous at the first batch).
 template <int NX>
 __global__ void __launch_bounds__(kSvThreads) sv_marg_wide_kernel(SvMargArgs a) {
-  const int64_t e = (int64_t)(blockIdx.x >> a.log_split);
-  const int64_t sl = (int64_t)(blockIdx.x & ((1u << a.log_split) - 1u));
-  if (e >= a.n_elems) return;
+  for (int64_t bid = blockIdx.x; bid < (a.n_elems << a.log_split); bid += gridDim.x) {
+  const int64_t e = bid >> a.log_split;
+  const int64_t sl = bid & (((int64_t)1 << a.log_split) - 1);
   const int tid = threadIdx.x;
   const int ybits = a.n - a.start - a.b;
   const int64_t ys = (int64_t)1 << (ybits - a.log_split);
@@ -46,15 +46,16 @@ __global__ void __launch_bounds__(kSvThreads) sv_marg_wide_kernel(SvMargArgs a) 
   double* out = a.part + ((e << a.log_split) + sl) * ((int64_t)NX * kSvThreads);
 #pragma unroll
   for (int i = 0; i < NX; ++i) out[tid + kSvThreads * i] = acc[i];
+  }
 }
 
 // 2^b < 256: R = 256 / 2^b threads share a batch value x, striding over y;
 // their partial sums are combined in a fixed order.
 __global__ void __launch_bounds__(kSvThreads) sv_marg_narrow_kernel(SvMargArgs a) {
   __shared__ double red[kSvThreads];
-  const int64_t e = (int64_t)(blockIdx.x >> a.log_split);
-  const int64_t sl = (int64_t)(blockIdx.x & ((1u << a.log_split) - 1u));
-  if (e >= a.n_elems) return;
+  for (int64_t bid = blockIdx.x; bid < (a.n_elems << a.log_split); bid += gridDim.x) {
+  const int64_t e = bid >> a.log_split;
+  const int64_t sl = bid & (((int64_t)1 << a.log_split) - 1);
   const int tid = threadIdx.x;
   const int X = 1 << a.b, R = kSvThreads >> a.b;
   const int x = tid & (X - 1), r = tid >> a.b;
@@ -73,27 +74,31 @@ __global__ void __launch_bounds__(kSvThreads) sv_marg_narrow_kernel(SvMargArgs a
     for (int k = 0; k < R; ++k) t += red[k * X + tid];
     a.part[((e << a.log_split) + sl) * X + tid] = t;
   }
+  __syncthreads();
+  }
 }
 
 __global__ void sv_pop_reduce_kernel(SvMargArgs a) {
-  const int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int64_t X = (int64_t)1 << a.b;
-  if (id >= a.n_elems * X) return;
-  const int64_t e = id >> a.b, x = id & (X - 1);
   const int64_t ns = (int64_t)1 << a.log_split;
-  double t = 0.0;
-  for (int64_t sl = 0; sl < ns; ++sl) t += a.part[((e << a.log_split) + sl) * X + x];
-  a.pop[id] = (float)t;
+  for (int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; id < a.n_elems * X;
+       id += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t e = id >> a.b, x = id & (X - 1);
+    double t = 0.0;
+    for (int64_t sl = 0; sl < ns; ++sl) t += a.part[((e << a.log_split) + sl) * X + x];
+    a.pop[id] = (float)t;
+  }
 }
 
 __global__ void sv_amp_kernel(SvMargArgs a, float2* amp) {
-  const int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int64_t X = (int64_t)1 << a.b;
-  if (id >= a.n_elems * X) return;
-  const int64_t e = id >> a.b, x = id & (X - 1);
-  uint64_t s;
-  const float2* P = elem_state(a, e, s);
-  amp[id] = P[(x << a.start) + (int64_t)s];
+  for (int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; id < a.n_elems * X;
+       id += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t e = id >> a.b, x = id & (X - 1);
+    uint64_t s;
+    const float2* P = elem_state(a, e, s);
+    amp[id] = P[(x << a.start) + (int64_t)s];
+  }
 }
 
 __global__ void init_traj_range_kernel(int64_t t0, int64_t count, const int64_t* m, const int64_t* base,
@@ -115,7 +120,7 @@ hipError_t launch_sv_marginal(const SvMargArgs& a, hipStream_t stream) {
   if (a.b < 1 || a.b > 12 || a.start < 0 || a.start + a.b > a.n || a.log_split < 0 ||
       a.log_split > a.n - a.start - a.b || (a.n_elems << a.log_split) > a.part_rows)
     return hipErrorInvalidValue;
-  const dim3 grid((unsigned)(a.n_elems << a.log_split));
+  const dim3 grid(grid_blocks(a.n_elems << a.log_split));
   switch (a.b) {
     case 8: hipLaunchKernelGGL(sv_marg_wide_kernel<1>, grid, dim3(kSvThreads), 0, stream, a); break;
     case 9: hipLaunchKernelGGL(sv_marg_wide_kernel<2>, grid, dim3(kSvThreads), 0, stream, a); break;
@@ -127,7 +132,7 @@ hipError_t launch_sv_marginal(const SvMargArgs& a, hipStream_t stream) {
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
   const int64_t total = a.n_elems << a.b;
-  hipLaunchKernelGGL(sv_pop_reduce_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream, a);
+  hipLaunchKernelGGL(sv_pop_reduce_kernel, dim3(grid_blocks((total + 255) / 256)), dim3(256), 0, stream, a);
   return hipGetLastError();
 }
 
@@ -135,7 +140,7 @@ hipError_t launch_sv_amplitudes(const SvMargArgs& a, float2* amp, hipStream_t st
   if (a.n_elems <= 0) return hipSuccess;
   if (a.start + a.b != a.n) return hipErrorInvalidValue;
   const int64_t total = a.n_elems << a.b;
-  hipLaunchKernelGGL(sv_amp_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream, a, amp);
+  hipLaunchKernelGGL(sv_amp_kernel, dim3(grid_blocks((total + 255) / 256)), dim3(256), 0, stream, a, amp);
   return hipGetLastError();
 }
 
