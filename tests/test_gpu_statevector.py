@@ -197,9 +197,12 @@ def test_grid25_full_size_properties():
     o2 = plan.sample_shots(kd, md, wl.shot_seed, mult_dev=to_dev(torch, dev, mult), workspace=ws)
     assert torch.equal(s1, o2["shots"])
     w = o1["weights"].cpu().numpy()
-    assert abs(w.sum() - 1) < 1e-12 and np.all(w > 0)
     norms = o1["norms"].cpu().numpy()
-    assert np.all((norms > 0) & (norms <= 1 + 1e-4))
+    assert abs(w.sum() - 1) < 1e-12 and np.all(w >= 0)
+    # annihilated trajectories (amplitude damping's K1 twice around a CZ) have Z = 0 and weight 0
+    assert np.all((norms >= 0) & (norms <= 1 + 1e-4))
+    assert np.array_equal(w == 0, norms == 0)
+    _say(f"grid25: {int(np.sum(norms == 0))} annihilated trajectories of {E}")
     traj = [0, 100, 2000]
     _, tot = _contract(plan, torch, dev, kd, traj, [0, 0, 0], 0)
     np.testing.assert_allclose(tot, norms[traj], rtol=1e-6)
