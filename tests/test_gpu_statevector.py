@@ -200,7 +200,13 @@ def test_grid25_full_size_properties():
     norms = o1["norms"].cpu().numpy()
     assert abs(w.sum() - 1) < 1e-12 and np.all(w >= 0)
     # annihilated trajectories (amplitude damping's K1 twice around a CZ) have Z = 0 and weight 0
-    assert np.all((norms >= 0) & (norms <= 1 + 1e-4))
+    assert np.all(np.isfinite(norms) & (norms >= 0))
+    # Z_i = |psi_i|^2 with inserted operators K/sqrt(q) is unbiased: E_q[Z] = 1 (each
+    # unique trajectory counted with its multiplicity); individual Z_i may exceed 1
+    zbar = np.sum(mult * norms) / np.sum(mult)
+    zsd = np.sqrt(np.sum(mult * (norms - zbar) ** 2) / np.sum(mult)) / np.sqrt(np.sum(mult))
+    _say(f"grid25: weighted mean Z {zbar:.5f} +- {zsd:.5f}")
+    assert abs(zbar - 1) <= 5 * zsd + 1e-3
     assert np.array_equal(w == 0, norms == 0)
     _say(f"grid25: {int(np.sum(norms == 0))} annihilated trajectories of {E}")
     traj = [0, 100, 2000]
