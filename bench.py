@@ -187,20 +187,27 @@ def bench_ragged(args):
                      "shots_per_traj": np.full(len(kr), c["shots_per_traj"], dtype=np.int64),
                      "seed": c["shot_seed"]})
     t_plan = time.perf_counter() - t_plan
+    print(f"ragged: {len(jobs)} plans + PTS in {t_plan:.1f} s", file=sys.stderr, flush=True)
     rs = RaggedSet()
     stream = torch.cuda.Stream(dev)
     with torch.cuda.stream(stream):
         ws = torch.empty(int(args.workspace_gb * (1 << 30)), dtype=torch.uint8, device=dev)
+        t_tune = time.perf_counter()
         best, ms = rs.autotune(jobs, workspace=ws, stream=stream.cuda_stream)
+        print(f"ragged: autotune {time.perf_counter() - t_tune:.1f} s, windows "
+              f"{ {w: int(np.sum(best == w)) for w in (10, 11, 12)} }", file=sys.stderr, flush=True)
         outs = None
-        for _ in range(args.warmup):
+        for k in range(args.warmup):
+            t_w = time.perf_counter()
             outs, lat = rs.sample_shots(jobs, graph=True, workspace=ws, stream=stream.cuda_stream, outputs=outs)
+            print(f"ragged: warmup {k} {time.perf_counter() - t_w:.1f} s, {rs.info()}", file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         lats = []
-        for _ in range(args.steps):
+        for k in range(args.steps):
             outs, lat = rs.sample_shots(jobs, graph=True, workspace=ws, stream=stream.cuda_stream, outputs=outs)
             lats.append(lat)
+            print(f"ragged: step {k} done at {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
     info = rs.info()

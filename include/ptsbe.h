@@ -310,7 +310,7 @@ ptsbe_status_t ptsbe_ragged_info(ptsbe_ragged_t set, ptsbe_ragged_info_t* out);
  * trajectory plus the per-job arrays; more workspace means fewer waves. */
 ptsbe_status_t ptsbe_ragged_workspace_size(ptsbe_ragged_t set, const ptsbe_ragged_job_t* jobs, int32_t n_jobs,
                                            size_t* bytes);
-/* Autotuner: for every job's plan, times one full gate-window pass of up to 4
+/* Autotuner: for every job's plan, times one full gate-window pass of up to 2
  * trajectories with windows of 10, 11 and 12 qubits (tiles of 2^10..2^12
  * amplitudes in LDS) and keeps the fastest per plan for later calls.
  * best_window (host, [n_jobs], may be NULL) receives the choice; ms_per_traj

@@ -169,7 +169,7 @@ ptsbe_status_t ptsbe_ragged_autotune(ptsbe_ragged_t set, const ptsbe_ragged_job_
     if (it != seen.end()) {
       ms = it->second;
     } else {
-      const int64_t nt = std::min<int64_t>(jobs[c].E, 4);
+      const int64_t nt = std::min<int64_t>(jobs[c].E, 2);
       Arena ar;
       ar.base = (char*)d_workspace;
       ar.cap = workspace_bytes;
