@@ -596,8 +596,7 @@ ptsbe_status_t ptsbe_plan(const ptsbe_circuit_t* c, const ptsbe_plan_opts_t* o, 
   if (site_list.empty()) site_list.push_back(0);
   size_t bytes = dg.size() * sizeof(ptsbe::DeviceGate) + site_list.size() * 4 + site_ops.size() * sizeof(float2) +
                  steps.size() * sizeof(ptsbe::AbsorbStep) + tables.size() * 8 +
-                 p->fused.size() * sizeof(ptsbe::FusedStep) + p->reg_phases.size() * sizeof(ptsbe::RegPhase) +
-                 p->reg_ops.size() * sizeof(ptsbe::RegOp);
+                 p->fused.size() * sizeof(ptsbe::FusedStep);
   p->device_bytes = (int64_t)bytes;
   if (o->device_budget_bytes && bytes > o->device_budget_bytes)
     return fail(PTSBE_ERR_OUT_OF_MEMORY, "plan constants exceed device_budget_bytes");
@@ -617,14 +616,6 @@ ptsbe_status_t ptsbe_plan(const ptsbe_circuit_t* c, const ptsbe_plan_opts_t* o, 
                       hipMemcpyHostToDevice));
   }
   if (p->method == PTSBE_METHOD_STATEVECTOR) {
-    if (!p->reg_phases.empty()) {
-      HIP_TRY(hipMalloc(&p->d_reg_phases, p->reg_phases.size() * sizeof(ptsbe::RegPhase)));
-      HIP_TRY(hipMemcpy(p->d_reg_phases, p->reg_phases.data(), p->reg_phases.size() * sizeof(ptsbe::RegPhase),
-                        hipMemcpyHostToDevice));
-      HIP_TRY(hipMalloc(&p->d_reg_ops, std::max<size_t>(1, p->reg_ops.size()) * sizeof(ptsbe::RegOp)));
-      HIP_TRY(hipMemcpy(p->d_reg_ops, p->reg_ops.data(), p->reg_ops.size() * sizeof(ptsbe::RegOp),
-                        hipMemcpyHostToDevice));
-    }
     for (int i = 0; i < 3; ++i) {
       std::vector<ptsbe::RgWindow> w(p->sv_win[i].size());
       for (size_t k = 0; k < w.size(); ++k) {
@@ -633,8 +624,6 @@ ptsbe_status_t ptsbe_plan(const ptsbe_circuit_t* c, const ptsbe_plan_opts_t* o, 
         w[k].n_fs = sg.count;
         for (int q = 0; q < ptsbe::kFuseMax; ++q) w[k].P[q] = sg.P[q];
         w[k].fused_off = sg.fused_off;
-        w[k].phase_off = sg.phase_off;
-        w[k].n_phases = sg.n_phases;
       }
       HIP_TRY(hipMalloc(&p->d_rg_win[i], std::max<size_t>(1, w.size()) * sizeof(ptsbe::RgWindow)));
       HIP_TRY(hipMemcpy(p->d_rg_win[i], w.data(), w.size() * sizeof(ptsbe::RgWindow), hipMemcpyHostToDevice));
@@ -666,8 +655,6 @@ void ptsbe_plan_destroy(ptsbe_plan_t plan) {
   if (p->d_fused) (void)hipFree(p->d_fused);
   for (auto* w : p->d_rg_win)
     if (w) (void)hipFree(w);
-  if (p->d_reg_phases) (void)hipFree(p->d_reg_phases);
-  if (p->d_reg_ops) (void)hipFree(p->d_reg_ops);
   delete p;
 }
 

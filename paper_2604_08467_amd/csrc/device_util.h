@@ -176,113 +176,5 @@ __device__ inline void window_tile_pass(const FusedStep* fs, int n_fs, const int
   __syncthreads();
 }
 
-// ------------------------------------------------- register-blocked windows
-// LDS address of tile entry l: one pad slot every 16 entries, so that threads
-// whose amplitudes are 16 entries apart do not all hit the same banks.
-__device__ inline uint32_t lds_addr(uint32_t l) { return l + (l >> 4); }
-__host__ __device__ constexpr uint32_t padded_tile(uint32_t n) { return n + (n >> 4); }
-
-template <int K>
-__device__ inline void reg_gate1(float2 (&a)[16], const float2 (&g)[2][2]) {
-#pragma unroll
-  for (int i = 0; i < 16; ++i) {
-    if (i & (1 << K)) continue;
-    const int j = i | (1 << K);
-    const float2 x = a[i], y = a[j];
-    a[i] = cfma(g[0][1], y, cmul(g[0][0], x));
-    a[j] = cfma(g[1][1], y, cmul(g[1][0], x));
-  }
-}
-
-template <int KA, int KB>
-__device__ inline void reg_gate2(float2 (&a)[16], const float2 (&g)[4][4]) {
-#pragma unroll
-  for (int i = 0; i < 16; ++i) {
-    if (i & ((1 << KA) | (1 << KB))) continue;
-    const int idx[4] = {i, i | (1 << KA), i | (1 << KB), i | (1 << KA) | (1 << KB)};
-    const float2 x0 = a[idx[0]], x1 = a[idx[1]], x2 = a[idx[2]], x3 = a[idx[3]];
-#pragma unroll
-    for (int n = 0; n < 4; ++n)
-      a[idx[n]] = cfma(g[n][3], x3, cfma(g[n][2], x2, cfma(g[n][1], x1, cmul(g[n][0], x0))));
-  }
-}
-
-// One tile pass of a statevector window executed phase by phase: threads
-// t < 2^(np-4) each hold the 16 amplitudes whose bits outside the phase's
-// register positions R equal t's bits; a phase applies all its gates in
-// registers between one LDS load and one LDS store.  tile holds
-// padded_tile(2^np) entries.  Ends with a barrier.
-__device__ inline void window_tile_pass_reg(const FusedStep* fused, const RegPhase* phases, int n_phases,
-                                            const RegOp* ops, const int* P, int np, int r, uint32_t t, float2* Aj,
-                                            const GateCtx& g_, int traj, float2* tile) {
-  const uint32_t base = deposit_tile(t, P, np, r);
-  const uint32_t nt = 1u << np;
-  for (uint32_t l = threadIdx.x; l < nt; l += blockDim.x) {
-    uint32_t off = base;
-    for (int i = 0; i < np; ++i) off |= ((l >> i) & 1u) << P[i];
-    tile[lds_addr(l)] = Aj[off];
-  }
-  __syncthreads();
-  const bool active = threadIdx.x < (nt >> kRegBits);
-  for (int ph = 0; ph < n_phases; ++ph) {
-    const RegPhase& Ph = phases[ph];
-    if (active) {
-      // the thread's bits, spread over the local positions outside R
-      uint32_t tb = 0;
-      for (int q = 0, bit = 0; q < np; ++q) {
-        if (q == Ph.R[0] || q == Ph.R[1] || q == Ph.R[2] || q == Ph.R[3]) continue;
-        tb |= ((threadIdx.x >> bit) & 1u) << q;
-        ++bit;
-      }
-      const uint32_t r0 = 1u << Ph.R[0], r1 = 1u << Ph.R[1], r2 = 1u << Ph.R[2], r3 = 1u << Ph.R[3];
-      float2 a[16];
-#pragma unroll
-      for (int i = 0; i < 16; ++i)
-        a[i] = tile[lds_addr(tb | ((i & 1) ? r0 : 0u) | ((i & 2) ? r1 : 0u) | ((i & 4) ? r2 : 0u) | ((i & 8) ? r3 : 0u))];
-      for (int o = Ph.op_begin; o < Ph.op_begin + Ph.n_ops; ++o) {
-        const RegOp op = ops[o];
-        const FusedStep& st = fused[op.fs];
-        if (op.kb < 0) {
-          float2 gm[2][2];
-#pragma unroll
-          for (int n = 0; n < 2; ++n)
-#pragma unroll
-            for (int k = 0; k < 2; ++k) gm[n][k] = gate_entry(g_, st.gate, traj, st.conj, st.nB[n] + st.kB[k]);
-          switch (op.ka) {
-            case 0: reg_gate1<0>(a, gm); break;
-            case 1: reg_gate1<1>(a, gm); break;
-            case 2: reg_gate1<2>(a, gm); break;
-            default: reg_gate1<3>(a, gm); break;
-          }
-        } else {
-          float2 gm[4][4];
-#pragma unroll
-          for (int n = 0; n < 4; ++n)
-#pragma unroll
-            for (int k = 0; k < 4; ++k) gm[n][k] = gate_entry(g_, st.gate, traj, st.conj, st.nB[n] + st.kB[k]);
-          switch (op.ka * 4 + op.kb) {
-            case 1: reg_gate2<0, 1>(a, gm); break;
-            case 2: reg_gate2<0, 2>(a, gm); break;
-            case 3: reg_gate2<0, 3>(a, gm); break;
-            case 6: reg_gate2<1, 2>(a, gm); break;
-            case 7: reg_gate2<1, 3>(a, gm); break;
-            default: reg_gate2<2, 3>(a, gm); break;
-          }
-        }
-      }
-#pragma unroll
-      for (int i = 0; i < 16; ++i)
-        tile[lds_addr(tb | ((i & 1) ? r0 : 0u) | ((i & 2) ? r1 : 0u) | ((i & 4) ? r2 : 0u) | ((i & 8) ? r3 : 0u))] = a[i];
-    }
-    __syncthreads();
-  }
-  for (uint32_t l = threadIdx.x; l < nt; l += blockDim.x) {
-    uint32_t off = base;
-    for (int i = 0; i < np; ++i) off |= ((l >> i) & 1u) << P[i];
-    Aj[off] = tile[lds_addr(l)];
-  }
-  __syncthreads();
-}
-
 }  // namespace
 }  // namespace ptsbe

@@ -96,18 +96,7 @@ struct Segment {
   int np = 0, r = 0;
   int P[kFuseMax] = {0};
   int64_t fused_off = 0;            // index of the first FusedStep on the device
-  int64_t phase_off = 0;            // register-blocked plan (statevector windows): phases
-  int n_phases = 0;                 //   [phase_off, phase_off + n_phases), 0: none
 };
-
-// Register-blocked execution of a statevector window: every thread holds 16
-// amplitudes of the tile, those whose local bits outside R[0..3] equal the
-// thread's bits; a phase loads them from LDS, applies its gates (all on qubits
-// in R) in registers and stores them back.
-constexpr int kRegBits = 4;
-struct RegPhase { int32_t R[kRegBits]; int32_t op_begin, n_ops; };
-struct RegOp { int32_t fs;   // absolute index of the gate's FusedStep
-               int32_t ka, kb; };   // register bits of its local qubits (kb = -1 for one qubit)
 bool build_segments(const std::vector<AbsorbStep>& steps, std::vector<Segment>& segs,
                     std::vector<FusedStep>& fused);
 
@@ -201,10 +190,6 @@ struct Plan {
   // sv_win[i] holds windows of at most kSvWindowMin + i qubits
   std::vector<Segment> sv_win[3];
   RgWindow* d_rg_win[3] = {nullptr, nullptr, nullptr};   // the same windows on the device
-  std::vector<RegPhase> reg_phases;               // register-blocked plans of the windows
-  std::vector<RegOp> reg_ops;
-  RegPhase* d_reg_phases = nullptr;
-  RegOp* d_reg_ops = nullptr;
   // fused in-place steps of every part and of the statevector schedule
   std::vector<FusedStep> fused;
   FusedStep* d_fused = nullptr;
@@ -267,12 +252,9 @@ hipError_t launch_absorb_global(const AbsorbStep& st, const AbsorbStep* d_st, Ga
                                 float2* C, hipStream_t stream);
 hipError_t launch_fill_one(float2* buf, int64_t n, hipStream_t stream);
 // A fused run of in-place steps on every job's tensor (rank seg.r), in place.
-// With reg_phases / reg_ops (the plan's device tables) a window that has a
-// register-blocked plan runs phase by phase.
 hipError_t launch_fused(const Segment& seg, const FusedStep* d_fs, GateCtx g, int64_t n_jobs,
                         const int32_t* job_traj, int32_t traj_base, const uint64_t* job_prefix, int NW,
-                        float2* A, hipStream_t stream, const RegPhase* reg_phases = nullptr,
-                        const RegOp* reg_ops = nullptr);
+                        float2* A, hipStream_t stream);
 
 struct JoinArgs {
   const float2* V; int64_t v_stride;     // per element
@@ -429,15 +411,11 @@ struct RgWindow {                    // one gate window of a statevector plan
   int32_t np, n_fs;
   int32_t P[kFuseMax];
   int64_t fused_off;
-  int64_t phase_off;                 // register-blocked plan (n_phases == 0: none)
-  int32_t n_phases, pad;
 };
 struct RgPiece {                     // trajectories [t0, t0 + nj) of one job inside a wave
   GateCtx g;                         // kraus / merged of the piece (local trajectory index)
   const RgWindow* win;               // the plan's windows (device)
   const FusedStep* fused;            // the plan's fused steps (device)
-  const RegPhase* reg_phases;        // the plan's register-blocked window plans (device)
-  const RegOp* reg_ops;
   float2* psi;                       // [nj][2^n]
   uint64_t* shots;                   // the job's shot rows (device, one word per row)
   double* norms;                     // [E] the job's squared norms (workspace)

@@ -14,8 +14,6 @@
 //    (prefix, x) of an element's shots become the next batch's elements.
 #include <hip/hip_runtime.h>
 
-#include <algorithm>
-
 #include "device_util.h"
 #include "internal.h"
 #include "philox.h"
@@ -163,9 +161,6 @@ struct FusedArgs {
   int r, np;
   int P[kFuseMax];
   int64_t tiles_per_job;
-  const FusedStep* fused_base;          // register-blocked plan (n_phases > 0)
-  const RegPhase* phases; int n_phases;
-  const RegOp* ops;
 };
 
 
@@ -174,7 +169,7 @@ __global__ void __launch_bounds__(256) fused_inplace_kernel(FusedArgs f, GateCtx
                                                            const uint64_t* __restrict__ job_prefix, int NW,
                                                            float2* A) {
   extern __shared__ float2 tile[];
-  float2* Gm = tile + padded_tile(1u << f.np);
+  float2* Gm = tile + ((int64_t)1 << f.np);
   __shared__ uint64_t pw[16];
   for (int64_t bid = blockIdx.x; bid < n_jobs * f.tiles_per_job; bid += gridDim.x) {
     const int64_t job = bid / f.tiles_per_job;
@@ -182,18 +177,6 @@ __global__ void __launch_bounds__(256) fused_inplace_kernel(FusedArgs f, GateCtx
     const int traj = job_traj ? job_traj[job] : traj_base + (int)job;
     if ((int)threadIdx.x < NW) pw[threadIdx.x] = job_prefix ? job_prefix[job * NW + threadIdx.x] : 0ull;
     window_tile_pass(f.fs, f.n_fs, f.P, f.np, f.r, t, A + (job << f.r), g, traj, pw, tile, Gm);   // ends with a barrier
-  }
-}
-
-// The same window with a register-blocked plan (statevector windows).
-__global__ void __launch_bounds__(256) fused_reg_kernel(FusedArgs f, GateCtx g, int64_t n_jobs, int32_t traj_base,
-                                                       float2* A) {
-  extern __shared__ float2 tile[];
-  for (int64_t bid = blockIdx.x; bid < n_jobs * f.tiles_per_job; bid += gridDim.x) {
-    const int64_t job = bid / f.tiles_per_job;
-    const uint32_t t = (uint32_t)(bid % f.tiles_per_job);
-    window_tile_pass_reg(f.fused_base, f.phases, f.n_phases, f.ops, f.P, f.np, f.r, t, A + (job << f.r), g,
-                         traj_base + (int)job, tile);   // ends with a barrier
   }
 }
 
@@ -1007,8 +990,7 @@ hipError_t launch_absorb_global(const AbsorbStep& st, const AbsorbStep* d_st, Ga
 }
 
 hipError_t launch_fused(const Segment& seg, const FusedStep* d_fs, GateCtx g, int64_t n_jobs, const int32_t* job_traj,
-                        int32_t traj_base, const uint64_t* job_prefix, int NW, float2* A, hipStream_t stream,
-                        const RegPhase* reg_phases, const RegOp* reg_ops) {
+                        int32_t traj_base, const uint64_t* job_prefix, int NW, float2* A, hipStream_t stream) {
   if (n_jobs <= 0) return hipSuccess;
   FusedArgs f{};
   f.fs = d_fs + seg.fused_off;
@@ -1017,17 +999,7 @@ hipError_t launch_fused(const Segment& seg, const FusedStep* d_fs, GateCtx g, in
   f.np = seg.np;
   for (int i = 0; i < kFuseMax; ++i) f.P[i] = seg.P[i];
   f.tiles_per_job = (int64_t)1 << (seg.r - seg.np);
-  const size_t shmem = (size_t)padded_tile(1u << seg.np) * sizeof(float2) + 32 * sizeof(float2);
-  if (seg.n_phases > 0 && reg_phases && reg_ops && !job_traj && !job_prefix) {
-    f.fused_base = d_fs;
-    f.phases = reg_phases + seg.phase_off;
-    f.n_phases = seg.n_phases;
-    f.ops = reg_ops;
-    const int threads = std::max(64, std::min(256, 1 << (seg.np - kRegBits)));
-    hipLaunchKernelGGL(fused_reg_kernel, dim3(grid_blocks(f.tiles_per_job * n_jobs)), dim3(threads), shmem, stream, f,
-                       g, n_jobs, traj_base, A);
-    return hipGetLastError();
-  }
+  const size_t shmem = ((size_t)1 << seg.np) * sizeof(float2) + 32 * sizeof(float2);
   hipLaunchKernelGGL(fused_inplace_kernel, dim3(grid_blocks(f.tiles_per_job * n_jobs)), dim3(256), shmem, stream, f, g,
                      n_jobs, job_traj, traj_base, job_prefix, NW, A);
   return hipGetLastError();

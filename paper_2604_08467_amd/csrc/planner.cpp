@@ -602,67 +602,6 @@ void build_sv_batches(Plan& p) {
 }
 
 namespace {
-// Register-blocked plan of one statevector window (its FusedSteps are the last
-// sg.count entries of p.fused): gates are packed greedily into phases whose
-// qubits fit kRegBits register positions, a gate joining a phase only when no
-// earlier gate left out of it touches its qubits (so the reordering only swaps
-// commuting gates).  The register set is padded with the highest free local
-// positions, so that threads run over the low positions (contiguous LDS).
-// Windows with fewer than 8 local qubits, or with a step that is not a plain
-// in-place 1- or 2-qubit gate, keep the gate-by-gate pass (n_phases = 0).
-void plan_reg_phases(Plan& p, Segment& sg) {
-  sg.n_phases = 0;
-  if (sg.np < 8) return;
-  std::vector<int> rest;
-  for (int k = 0; k < sg.count; ++k) {
-    const FusedStep& fs = p.fused[sg.fused_off + k];
-    const bool plain = fs.nH == 0 && fs.nS == 0 && fs.nK == fs.nN && fs.nK >= 1 && fs.nK <= 2;
-    if (!plain) return;
-    for (int i = 0; i < (1 << fs.nK); ++i)
-      if (fs.koff[i] != fs.noff[i]) return;
-    rest.push_back(k);
-  }
-  const int64_t phase0 = (int64_t)p.reg_phases.size();
-  while (!rest.empty()) {
-    std::vector<int> R, taken, left_out;
-    std::set<int> blocked;
-    for (int k : rest) {
-      const FusedStep& fs = p.fused[sg.fused_off + k];
-      bool free = true;
-      for (int i = 0; i < fs.nK; ++i) free = free && !blocked.count(fs.kloc[i]);
-      std::vector<int> R2 = R;
-      for (int i = 0; i < fs.nK; ++i)
-        if (std::find(R2.begin(), R2.end(), fs.kloc[i]) == R2.end()) R2.push_back(fs.kloc[i]);
-      if (free && (int)R2.size() <= kRegBits) {
-        R = R2;
-        taken.push_back(k);
-      } else {
-        for (int i = 0; i < fs.nK; ++i) blocked.insert(fs.kloc[i]);
-        left_out.push_back(k);
-      }
-    }
-    for (int q = sg.np - 1; (int)R.size() < kRegBits && q >= 0; --q)
-      if (std::find(R.begin(), R.end(), q) == R.end()) R.push_back(q);
-    std::sort(R.begin(), R.end());
-    RegPhase ph{};
-    for (int i = 0; i < kRegBits; ++i) ph.R[i] = R[i];
-    ph.op_begin = (int32_t)p.reg_ops.size();
-    ph.n_ops = (int32_t)taken.size();
-    for (int k : taken) {
-      const FusedStep& fs = p.fused[sg.fused_off + k];
-      RegOp op{};
-      op.fs = (int32_t)(sg.fused_off + k);
-      op.ka = (int32_t)(std::find(R.begin(), R.end(), fs.kloc[0]) - R.begin());
-      op.kb = fs.nK == 2 ? (int32_t)(std::find(R.begin(), R.end(), fs.kloc[1]) - R.begin()) : -1;
-      p.reg_ops.push_back(op);
-    }
-    p.reg_phases.push_back(ph);
-    rest = left_out;
-  }
-  sg.phase_off = phase0;
-  sg.n_phases = (int)((int64_t)p.reg_phases.size() - phase0);
-}
-
 // Windows of at most `wmax` qubits (see build_sv_schedule); appends the fused
 // steps to p.fused and returns the segments.
 std::vector<Segment> sv_windows(Plan& p, int wmax, std::vector<AbsorbStep>* run) {
@@ -707,7 +646,6 @@ std::vector<Segment> sv_windows(Plan& p, int wmax, std::vector<AbsorbStep>* run)
       p.fused.push_back(make_fused_step(p.sv_steps[g], Pv));
     }
     first += (int64_t)taken.size();
-    plan_reg_phases(p, sg);
     segs.push_back(sg);
     rest = left_out;
   }
@@ -717,8 +655,6 @@ std::vector<Segment> sv_windows(Plan& p, int wmax, std::vector<AbsorbStep>* run)
 
 void build_sv_schedule(Plan& p) {
   p.sv_run.clear();
-  p.reg_phases.clear();
-  p.reg_ops.clear();
   for (int i = 0; i < 3; ++i) p.sv_win[i] = sv_windows(p, kSvWindowMin + i, i == 2 ? &p.sv_run : nullptr);
   p.sv_segs = p.sv_win[2];
 }

@@ -191,8 +191,7 @@ ptsbe_status_t ptsbe_ragged_autotune(ptsbe_ragged_t set, const ptsbe_ragged_job_
           HIP_TRY(hipEventRecord(ev[0], s));
           HIP_TRY(ptsbe::launch_state_init(psi, nt, p.n, s));
           for (const ptsbe::Segment& sg : p.sv_win[w])
-            HIP_TRY(ptsbe::launch_fused(sg, p.d_fused, g, nt, nullptr, 0, nullptr, p.NW, psi, s, p.d_reg_phases,
-                                        p.d_reg_ops));
+            HIP_TRY(ptsbe::launch_fused(sg, p.d_fused, g, nt, nullptr, 0, nullptr, p.NW, psi, s));
           HIP_TRY(hipEventRecord(ev[1], s));
         }
         HIP_TRY(hipEventSynchronize(ev[1]));
@@ -343,8 +342,6 @@ ptsbe_status_t ptsbe_ragged_sample_shots(ptsbe_ragged_t set, const ptsbe_ragged_
       pc.psi = (float2*)wa.take((size_t)ps.nj * ((size_t)8 << p.n));
       pc.win = p.d_rg_win[wc];
       pc.fused = p.d_fused;
-      pc.reg_phases = p.d_reg_phases;
-      pc.reg_ops = p.d_reg_ops;
       pc.shots = jb.d_shots;
       pc.norms = norms[ps.job];
       pc.row0 = row;

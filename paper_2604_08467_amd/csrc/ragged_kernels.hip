@@ -111,7 +111,7 @@ __global__ void __launch_bounds__(kRgThreads) rg_prepare_kernel(RgWave w) {
 __global__ void __launch_bounds__(kRgThreads) rg_window_kernel(RgWave w, RgLevel lv, int level) {
   extern __shared__ float2 lds[];
   float2* tile = lds;
-  float2* Gm = lds + padded_tile(1u << kFuseMax);
+  float2* Gm = lds + (1 << kFuseMax);
   __shared__ uint64_t pw[1];
   if (threadIdx.x == 0) pw[0] = 0ull;
   for (int64_t task = blockIdx.x; task < lv.tasks; task += gridDim.x) {
@@ -122,12 +122,8 @@ __global__ void __launch_bounds__(kRgThreads) rg_window_kernel(RgWave w, RgLevel
     const int64_t local = task - lv.start[e];
     const int64_t traj = local >> tb;
     const uint32_t t = (uint32_t)(local & (((int64_t)1 << tb) - 1));
-    if (wd.n_phases > 0 && pc.reg_phases)
-      window_tile_pass_reg(pc.fused, pc.reg_phases + wd.phase_off, wd.n_phases, pc.reg_ops, wd.P, wd.np, pc.n, t,
-                           pc.psi + (traj << pc.n), pc.g, (int)traj, tile);
-    else
-      window_tile_pass(pc.fused + wd.fused_off, wd.n_fs, wd.P, wd.np, pc.n, t, pc.psi + (traj << pc.n), pc.g,
-                       (int)traj, pw, tile, Gm);
+    window_tile_pass(pc.fused + wd.fused_off, wd.n_fs, wd.P, wd.np, pc.n, t, pc.psi + (traj << pc.n), pc.g,
+                     (int)traj, pw, tile, Gm);
   }
 }
 
@@ -413,7 +409,7 @@ hipError_t launch_rg_prepare(const RgWave& w, int grid, hipStream_t s) {
 
 hipError_t launch_rg_window(const RgWave& w, const RgLevel& lv, int level, int grid, hipStream_t s) {
   if (lv.tasks <= 0) return hipSuccess;
-  const size_t shmem = (size_t)padded_tile(1u << kFuseMax) * sizeof(float2) + 32 * sizeof(float2);
+  const size_t shmem = ((size_t)1 << kFuseMax) * sizeof(float2) + 32 * sizeof(float2);
   hipLaunchKernelGGL(rg_window_kernel, dim3((unsigned)grid), dim3(kRgThreads), shmem, s, w, lv, level);
   return hipGetLastError();
 }

@@ -60,8 +60,7 @@ size_t sv_global_bytes(const Plan& p, int64_t E, int64_t M) {
 ptsbe_status_t sv_evolve(const Plan& p, const GateCtx& g, int64_t t0, int64_t nj, float2* psi, hipStream_t s) {
   HIP_TRY(launch_state_init(psi, nj, p.n, s));
   for (const Segment& sg : p.sv_segs)
-    HIP_TRY(launch_fused(sg, p.d_fused, g, nj, nullptr, (int32_t)t0, nullptr, p.NW, psi, s, p.d_reg_phases,
-                         p.d_reg_ops));
+    HIP_TRY(launch_fused(sg, p.d_fused, g, nj, nullptr, (int32_t)t0, nullptr, p.NW, psi, s));
   return PTSBE_OK;
 }
 
