@@ -108,11 +108,26 @@ __device__ inline void window_tile_pass(const FusedStep* fs, int n_fs, const int
         for (int k = 0; k < 2; ++k) g[n][k] = gate_entry(g_, st.gate, traj, st.conj, st.nB[n] + st.kB[k]);
       const int p = st.kloc[0];
       const uint32_t o = st.koff[1], lo_mask = (1u << p) - 1u;
-      for (uint32_t m = threadIdx.x; m < (nt >> 1); m += blockDim.x) {
-        const uint32_t lb = ((m & ~lo_mask) << 1) | (m & lo_mask);
-        const float2 a0 = tile[lb], a1 = tile[lb + o];
-        tile[lb] = cfma(g[0][1], a1, cmul(g[0][0], a0));
-        tile[lb + o] = cfma(g[1][1], a1, cmul(g[1][0], a0));
+      const bool z00 = g[0][0].x == 0.f && g[0][0].y == 0.f, z01 = g[0][1].x == 0.f && g[0][1].y == 0.f;
+      const bool z10 = g[1][0].x == 0.f && g[1][0].y == 0.f, z11 = g[1][1].x == 0.f && g[1][1].y == 0.f;
+      if ((z00 || z01) && (z10 || z11)) {
+        // monomial (diagonal or anti-diagonal): one product per amplitude
+        // row 0 takes a0 unless g00 == 0 (then a1); row 1 takes a1 unless g11 == 0 (then a0)
+        const bool swap0 = z00, swap1 = z11;
+        const float2 d0 = swap0 ? g[0][1] : g[0][0], d1 = swap1 ? g[1][0] : g[1][1];
+        for (uint32_t m = threadIdx.x; m < (nt >> 1); m += blockDim.x) {
+          const uint32_t lb = ((m & ~lo_mask) << 1) | (m & lo_mask);
+          const float2 a0 = tile[lb], a1 = tile[lb + o];
+          tile[lb] = cmul(d0, swap0 ? a1 : a0);
+          tile[lb + o] = cmul(d1, swap1 ? a0 : a1);
+        }
+      } else {
+        for (uint32_t m = threadIdx.x; m < (nt >> 1); m += blockDim.x) {
+          const uint32_t lb = ((m & ~lo_mask) << 1) | (m & lo_mask);
+          const float2 a0 = tile[lb], a1 = tile[lb + o];
+          tile[lb] = cfma(g[0][1], a1, cmul(g[0][0], a0));
+          tile[lb + o] = cfma(g[1][1], a1, cmul(g[1][0], a0));
+        }
       }
       __syncthreads();
       continue;
@@ -127,14 +142,48 @@ __device__ inline void window_tile_pass(const FusedStep* fs, int n_fs, const int
       const int p0 = st.kloc[0], p1 = st.kloc[1];
       const uint32_t o1 = st.koff[1], o2 = st.koff[2], o3 = st.koff[3];
       const uint32_t m0 = (1u << p0) - 1u, m1 = (1u << p1) - 1u;
-      for (uint32_t m = threadIdx.x; m < (nt >> 2); m += blockDim.x) {
-        uint32_t lb = ((m & ~m0) << 1) | (m & m0);
-        lb = ((lb & ~m1) << 1) | (lb & m1);
-        const float2 a0 = tile[lb], a1 = tile[lb + o1], a2 = tile[lb + o2], a3 = tile[lb + o3];
-        const uint32_t off[4] = {0u, o1, o2, o3};
+      const uint32_t off[4] = {0u, o1, o2, o3};
+      // monomial matrix (at most one nonzero per row: diagonal gates such as CZ
+      // with diagonal Kraus factors, CNOT and Pauli products): one product per amplitude
+      int col[4];
+      bool mono = true;
 #pragma unroll
-        for (int n = 0; n < 4; ++n)
-          tile[lb + off[n]] = cfma(g[n][3], a3, cfma(g[n][2], a2, cfma(g[n][1], a1, cmul(g[n][0], a0))));
+      for (int n = 0; n < 4; ++n) {
+        col[n] = -1;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          if (g[n][k].x != 0.f || g[n][k].y != 0.f) {
+            mono = mono && col[n] < 0;
+            col[n] = k;
+          }
+      }
+      if (mono) {
+        float2 gd[4];
+#pragma unroll
+        for (int n = 0; n < 4; ++n) {
+          const int c = col[n];
+          gd[n] = c == 0 ? g[n][0] : c == 1 ? g[n][1] : c == 2 ? g[n][2] : c == 3 ? g[n][3] : make_float2(0.f, 0.f);
+        }
+        for (uint32_t m = threadIdx.x; m < (nt >> 2); m += blockDim.x) {
+          uint32_t lb = ((m & ~m0) << 1) | (m & m0);
+          lb = ((lb & ~m1) << 1) | (lb & m1);
+          const float2 a0 = tile[lb], a1 = tile[lb + o1], a2 = tile[lb + o2], a3 = tile[lb + o3];
+#pragma unroll
+          for (int n = 0; n < 4; ++n) {
+            const int c = col[n];
+            const float2 x = c == 0 ? a0 : c == 1 ? a1 : c == 2 ? a2 : a3;
+            tile[lb + off[n]] = cmul(gd[n], x);
+          }
+        }
+      } else {
+        for (uint32_t m = threadIdx.x; m < (nt >> 2); m += blockDim.x) {
+          uint32_t lb = ((m & ~m0) << 1) | (m & m0);
+          lb = ((lb & ~m1) << 1) | (lb & m1);
+          const float2 a0 = tile[lb], a1 = tile[lb + o1], a2 = tile[lb + o2], a3 = tile[lb + o3];
+#pragma unroll
+          for (int n = 0; n < 4; ++n)
+            tile[lb + off[n]] = cfma(g[n][3], a3, cfma(g[n][2], a2, cfma(g[n][1], a1, cmul(g[n][0], a0))));
+        }
       }
       __syncthreads();
       continue;
