@@ -449,7 +449,8 @@ struct RgWave {                      // device arrays of one wave (all in the wo
 struct RgLevel { const int32_t* piece; const int64_t* start; int32_t n; int64_t tasks; };
 hipError_t launch_rg_start(const RgWave& w, hipStream_t s);
 hipError_t launch_rg_prepare(const RgWave& w, int grid, hipStream_t s);
-hipError_t launch_rg_window(const RgWave& w, const RgLevel& lv, int level, int grid, hipStream_t s);
+// grid: n_cu times the kernel's occupancy per CU
+hipError_t launch_rg_window(const RgWave& w, const RgLevel& lv, int level, int n_cu, hipStream_t s);
 hipError_t launch_rg_marginal0(const RgWave& w, int64_t tasks, int grid, hipStream_t s);
 hipError_t launch_rg_marginal(const RgWave& w, int j, int cur, int grid, hipStream_t s);
 hipError_t launch_rg_sample(const RgWave& w, int j, int cur, int grid, hipStream_t s);

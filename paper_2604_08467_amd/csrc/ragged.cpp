@@ -444,7 +444,7 @@ ptsbe_status_t ptsbe_ragged_sample_shots(ptsbe_ragged_t set, const ptsbe_ragged_
   const bool replay = use_graph && set->key == key && set->execs.size() == waves.size();
   if (use_graph && !replay) set->drop_graphs();
   int64_t launches = 0;
-  const int g_win = set->n_cu * 4, g_mem = set->n_cu * 8, g_samp = set->n_cu * 2;
+  const int g_mem = set->n_cu * 8, g_samp = set->n_cu * 2;
   for (size_t wi = 0; wi < waves.size(); ++wi) {
     const WaveLaunch& L = wl[wi];
     if (replay) {
@@ -457,7 +457,7 @@ ptsbe_status_t ptsbe_ragged_sample_shots(ptsbe_ragged_t set, const ptsbe_ragged_
     HIP_TRY(ptsbe::launch_rg_prepare(L.w, g_mem, s));
     ++launches;
     for (size_t l = 0; l < L.levels.size(); ++l) {
-      HIP_TRY(ptsbe::launch_rg_window(L.w, L.levels[l], (int)l, g_win, s));
+      HIP_TRY(ptsbe::launch_rg_window(L.w, L.levels[l], (int)l, set->n_cu, s));
       ++launches;
     }
     HIP_TRY(ptsbe::launch_rg_marginal0(L.w, L.m0_tasks, g_mem, s));

@@ -7,6 +7,8 @@
 // (qubit count, batch layout, gate windows, shot rows) comes from its piece.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "device_util.h"
 #include "internal.h"
 #include "philox.h"
@@ -407,10 +409,15 @@ hipError_t launch_rg_prepare(const RgWave& w, int grid, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_rg_window(const RgWave& w, const RgLevel& lv, int level, int grid, hipStream_t s) {
+hipError_t launch_rg_window(const RgWave& w, const RgLevel& lv, int level, int n_cu, hipStream_t s) {
   if (lv.tasks <= 0) return hipSuccess;
   const size_t shmem = ((size_t)1 << kFuseMax) * sizeof(float2) + 32 * sizeof(float2);
-  hipLaunchKernelGGL(rg_window_kernel, dim3((unsigned)grid), dim3(kRgThreads), shmem, s, w, lv, level);
+  // a persistent grid is only as large as what fits on the chip at once
+  int per_cu = 0;
+  hipError_t err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, rg_window_kernel, kRgThreads, shmem);
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL(rg_window_kernel, dim3((unsigned)(n_cu * std::max(per_cu, 1))), dim3(kRgThreads), shmem, s, w,
+                     lv, level);
   return hipGetLastError();
 }
 
