@@ -999,7 +999,7 @@ hipError_t launch_fused(const Segment& seg, const FusedStep* d_fs, GateCtx g, in
   f.np = seg.np;
   for (int i = 0; i < kFuseMax; ++i) f.P[i] = seg.P[i];
   f.tiles_per_job = (int64_t)1 << (seg.r - seg.np);
-  const size_t shmem = ((size_t)1 << seg.np) * sizeof(float2) + 32 * sizeof(float2);
+  const size_t shmem = (((size_t)1 << seg.np) + 16 * kGateChunk) * sizeof(float2);
   hipLaunchKernelGGL(fused_inplace_kernel, dim3(grid_blocks(f.tiles_per_job * n_jobs)), dim3(256), shmem, stream, f, g,
                      n_jobs, job_traj, traj_base, job_prefix, NW, A);
   return hipGetLastError();

@@ -411,7 +411,7 @@ hipError_t launch_rg_prepare(const RgWave& w, int grid, hipStream_t s) {
 
 hipError_t launch_rg_window(const RgWave& w, const RgLevel& lv, int level, int n_cu, hipStream_t s) {
   if (lv.tasks <= 0) return hipSuccess;
-  const size_t shmem = ((size_t)1 << kFuseMax) * sizeof(float2) + 32 * sizeof(float2);
+  const size_t shmem = (((size_t)1 << kFuseMax) + 16 * kGateChunk) * sizeof(float2);
   // a persistent grid is only as large as what fits on the chip at once
   int per_cu = 0;
   hipError_t err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, rg_window_kernel, kRgThreads, shmem);
