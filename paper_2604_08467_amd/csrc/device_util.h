@@ -77,10 +77,14 @@ __device__ void merge_gate(const GateCtx& g, int gate, int traj, float2* out) {
   for (int i = 0; i < 16; ++i) out[i] = m[i];
 }
 
+// Gate matrices of a window are staged in LDS kGateChunk steps at a time (16
+// entries each), so that every step reads its matrix with LDS broadcasts.
+constexpr int kGateChunk = 32;
+
 // One tile pass of a window of in-place steps (positions P, |P| = np, of a rank-r
 // tensor A of one job): the 2^np entries whose other bits equal the tile index t
 // are loaded into LDS, every step is applied there (gate operands of trajectory
-// traj, double-buffered in Gm[32]), and the tile is written back.  pw: the job's
+// traj, staged in Gm[16 * kGateChunk]), and the tile is written back.  pw: the job's
 // prefix words in LDS (for sliced legs).  Ends with a barrier, so the caller may
 // reuse tile and Gm at once.
 __device__ inline void window_tile_pass(const FusedStep* fs, int n_fs, const int* P, int np, int r, uint32_t t,
@@ -96,6 +100,15 @@ __device__ inline void window_tile_pass(const FusedStep* fs, int n_fs, const int
   __syncthreads();   // the tile is complete before any step reads it
   for (int s = 0; s < n_fs; ++s) {
     const FusedStep& st = fs[s];
+    if (s % kGateChunk == 0) {   // every thread is past step s - 1 (it ended with a barrier)
+      const int cnt = (n_fs - s < kGateChunk ? n_fs - s : kGateChunk) * 16;
+      for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
+        const FusedStep& sj = fs[s + i / 16];
+        Gm[i] = gate_entry(g_, sj.gate, traj, sj.conj, i % 16);
+      }
+      __syncthreads();
+    }
+    const float2* G = Gm + 16 * (s % kGateChunk);
     // a plain gate applied in place: no hyper or sliced legs, outputs where the inputs were
     const bool plain = st.nH == 0 && st.nS == 0 && st.nK == st.nN && st.nK >= 1 && st.nK <= 2 &&
                        st.noff[1] == st.koff[1] && (st.nK == 1 || (st.noff[2] == st.koff[2] && st.noff[3] == st.koff[3]));
@@ -105,7 +118,7 @@ __device__ inline void window_tile_pass(const FusedStep* fs, int n_fs, const int
 #pragma unroll
       for (int n = 0; n < 2; ++n)
 #pragma unroll
-        for (int k = 0; k < 2; ++k) g[n][k] = gate_entry(g_, st.gate, traj, st.conj, st.nB[n] + st.kB[k]);
+        for (int k = 0; k < 2; ++k) g[n][k] = G[st.nB[n] + st.kB[k]];
       const int p = st.kloc[0];
       const uint32_t o = st.koff[1], lo_mask = (1u << p) - 1u;
       const bool z00 = g[0][0].x == 0.f && g[0][0].y == 0.f, z01 = g[0][1].x == 0.f && g[0][1].y == 0.f;
@@ -138,7 +151,7 @@ __device__ inline void window_tile_pass(const FusedStep* fs, int n_fs, const int
 #pragma unroll
       for (int n = 0; n < 4; ++n)
 #pragma unroll
-        for (int k = 0; k < 4; ++k) g[n][k] = gate_entry(g_, st.gate, traj, st.conj, st.nB[n] + st.kB[k]);
+        for (int k = 0; k < 4; ++k) g[n][k] = G[st.nB[n] + st.kB[k]];
       const int p0 = st.kloc[0], p1 = st.kloc[1];
       const uint32_t o1 = st.koff[1], o2 = st.koff[2], o3 = st.koff[3];
       const uint32_t m0 = (1u << p0) - 1u, m1 = (1u << p1) - 1u;
@@ -188,9 +201,6 @@ __device__ inline void window_tile_pass(const FusedStep* fs, int n_fs, const int
       __syncthreads();
       continue;
     }
-    if ((int)threadIdx.x < 16) Gm[16 * (s & 1) + (int)threadIdx.x] = gate_entry(g_, st.gate, traj, st.conj, (int)threadIdx.x);
-    __syncthreads();
-    const float2* G = Gm + 16 * (s & 1);
     int sb = 0;
     for (int i = 0; i < st.nS; ++i) sb += (int)bit_of_prefix(pw, st.sq[i]) * st.sw[i];
     const uint32_t nm = nt >> st.nK;
