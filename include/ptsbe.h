@@ -167,6 +167,16 @@ ptsbe_status_t ptsbe_plan(const ptsbe_circuit_t* circuit, const ptsbe_plan_opts_
                           ptsbe_plan_t* out);
 ptsbe_status_t ptsbe_plan_query(ptsbe_plan_t plan, ptsbe_plan_info_t* out);
 ptsbe_status_t ptsbe_plan_batch_info(ptsbe_plan_t plan, int32_t j, ptsbe_batch_info_t* out);
+/* Statevector method: the gate schedule for windows of window_qubits (10, 11 or
+ * 12) qubits, for inspection and tests.  Host outputs (caller-owned; any may be
+ * NULL): gate_order [n_gates] gate indices in execution order (each gate once; a
+ * gate is moved only past gates on disjoint qubits), window_first [n_windows + 1]
+ * offsets into gate_order, window_qubits [n_windows][12] the qubits held in LDS
+ * by each window (-1 padded), n_windows_out.  Arrays must hold n_gates entries
+ * (window_first: n_gates + 1, window_qubits: 12 * n_gates).
+ * PTSBE_ERR_INVALID_ARG for a network-method plan or another window size. */
+ptsbe_status_t ptsbe_plan_sv_schedule(ptsbe_plan_t plan, int32_t window_qubits, int32_t* gate_order,
+                                      int32_t* window_first, int32_t* window_qubits_out, int32_t* n_windows_out);
 void ptsbe_plan_destroy(ptsbe_plan_t plan);
 const char* ptsbe_last_error(void);
 

@@ -135,6 +135,19 @@ class Plan:
         except Exception:
             pass
 
+    def sv_schedule(self, window_qubits=12):
+        """ptsbe_plan_sv_schedule: (gate order, window offsets, window qubit lists)."""
+        G = self.n_gates
+        order = np.zeros(G, dtype=np.int32)
+        first = np.zeros(G + 1, dtype=np.int32)
+        wq = np.full((G, 12), -1, dtype=np.int32)
+        nw = C.c_int32()
+        _lib.check(self._lib.ptsbe_plan_sv_schedule(self._h, int(window_qubits), order.ctypes.data_as(C.c_void_p),
+                                                     first.ctypes.data_as(C.c_void_p), wq.ctypes.data_as(C.c_void_p),
+                                                     C.byref(nw)))
+        k = nw.value
+        return order, first[:k + 1], [list(q[q >= 0]) for q in wq[:k]]
+
     def batch_info(self, j):
         bi = _lib.BatchInfo_t()
         _lib.check(self._lib.ptsbe_plan_batch_info(self._h, int(j), C.byref(bi)))

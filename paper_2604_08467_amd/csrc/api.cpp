@@ -675,6 +675,28 @@ ptsbe_status_t ptsbe_plan_query(ptsbe_plan_t plan, ptsbe_plan_info_t* out) {
   return PTSBE_OK;
 }
 
+ptsbe_status_t ptsbe_plan_sv_schedule(ptsbe_plan_t plan, int32_t window_qubits, int32_t* gate_order,
+                                      int32_t* window_first, int32_t* window_qubits_out, int32_t* n_windows_out) {
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  if (!p) return fail(PTSBE_ERR_INVALID_ARG, "null plan");
+  if (p->method != PTSBE_METHOD_STATEVECTOR) return fail(PTSBE_ERR_INVALID_ARG, "not a statevector-method plan");
+  const int w = window_qubits - ptsbe::kSvWindowMin;
+  if (w < 0 || w > 2) return fail(PTSBE_ERR_INVALID_ARG, "window_qubits must be 10, 11 or 12");
+  const auto& segs = p->sv_win[w];
+  int32_t pos = 0;
+  for (size_t k = 0; k < segs.size(); ++k) {
+    const ptsbe::Segment& sg = segs[k];
+    if (window_first) window_first[k] = pos;
+    for (int i = 0; i < sg.count; ++i, ++pos)
+      if (gate_order) gate_order[pos] = p->fused[sg.fused_off + i].gate;
+    if (window_qubits_out)
+      for (int q = 0; q < ptsbe::kFuseMax; ++q) window_qubits_out[12 * k + q] = q < sg.np ? sg.P[q] : -1;
+  }
+  if (window_first) window_first[segs.size()] = pos;
+  if (n_windows_out) *n_windows_out = (int32_t)segs.size();
+  return PTSBE_OK;
+}
+
 ptsbe_status_t ptsbe_plan_batch_info(ptsbe_plan_t plan, int32_t j, ptsbe_batch_info_t* out) {
   Plan* p = reinterpret_cast<Plan*>(plan);
   if (!p || !out) return fail(PTSBE_ERR_INVALID_ARG, "null argument");

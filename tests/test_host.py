@@ -171,3 +171,34 @@ def test_statevector_windows_cover_small_circuits_in_one_launch():
     c = W.sqrt_grid(4, 4, 8, np.random.default_rng(0))
     p = P.Plan(c, [6, 6, 4], device=-1)
     assert p.method == "statevector" and 2 <= p.sv_windows <= 16
+
+
+@pytest.mark.parametrize("window", [10, 11, 12])
+def test_statevector_schedule_only_reorders_commuting_gates(window):
+    """Every gate appears once; each window's gates act inside its qubit set of at
+    most `window` qubits (qubits 0..3 always held); a gate moves ahead of another
+    only if they share no qubit (so the product of gates is unchanged)."""
+    P = _lib()
+    cases = [W.config3().circuit, W.sqrt_grid(4, 4, 8, np.random.default_rng(0)),
+             W.random_brickwork(20, 6, np.random.default_rng(1), 0.01, layout="2d"),
+             W.small_random_circuit(15, 60, np.random.default_rng(2), [W.depolarizing(0.1)])]
+    for c in cases:
+        n = c.n_qubits
+        bs = [12] * (n // 12) + ([n % 12] if n % 12 else [])
+        plan = P.Plan(c, bs, device=-1, method="statevector")
+        order, first, wq = plan.sv_schedule(window)
+        G = plan.n_gates
+        assert sorted(order.tolist()) == list(range(G))
+        qubits = [tuple(q) for q in c.gate_qubits] + [(q,) for q in range(c.n_qubits)
+                                                      if all(q not in g for g in c.gate_qubits)]
+        for k in range(len(wq)):
+            held = set(wq[k])
+            assert len(held) <= window and set(range(min(4, c.n_qubits))) <= held
+            for g in order[first[k]:first[k + 1]]:
+                assert set(qubits[g]) <= held
+        pos = np.empty(G, dtype=np.int64)
+        pos[order] = np.arange(G)
+        for a in range(G):
+            for b in range(a + 1, G):
+                if set(qubits[a]) & set(qubits[b]):
+                    assert pos[a] < pos[b], (a, b)
