@@ -22,6 +22,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 FP32_MFMA_PEAK_TFLOPS = 157.3
 BF16_MFMA_PEAK_TFLOPS = 2500.0
+# the join kernel version that profiles/join_traffic.txt must name to be used
+JOIN_KERNEL_TAG = "qform_mfma_kernel<32> folded blocks"
 
 
 def cpu_baseline(wl, kr, budget_s=20.0):
@@ -132,15 +134,18 @@ def main():
     achieved = prof["join_flops"] / join_s / 1e12 if join_s > 0 else 0.0
     traffic = None
     if os.path.exists(args.traffic_file):
-        # "bytes_per_launch: N" written from two rocprofv3 counter runs of this command
-        for ln in open(args.traffic_file):
-            if ln.startswith("bytes_per_launch:"):
-                traffic = float(ln.split(":", 1)[1])
+        # "bytes_per_launch: N" written from two rocprofv3 counter runs of this command;
+        # used only when its "kernel:" line names the join kernel as it is now
+        kv = dict(ln.split(":", 1) for ln in open(args.traffic_file) if ":" in ln and not ln.startswith("#"))
+        if kv.get("kernel", "").strip() == JOIN_KERNEL_TAG and "bytes_per_launch" in kv:
+            traffic = float(kv["bytes_per_launch"])
     peak = FP32_MFMA_PEAK_TFLOPS if args.precision == "c64" else BF16_MFMA_PEAK_TFLOPS
     roofline = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                 "frac": achieved / peak, "traffic": traffic if args.precision == "c64" else None,
-                "kernel": "qform_mfma_kernel<32> (doubled-network join, FP32 MFMA)" if args.precision == "c64"
-                          else "qform_split_bf16_kernel (doubled-network join, bf16x3 MFMA)",
+                "kernel": "qform_mfma_kernel<32> (doubled-network join as a folded real quadratic form, FP32 MFMA)"
+                          if args.precision == "c64" else "qform_split_bf16_kernel (doubled-network join, bf16x3 MFMA)",
+                "flops": "folded real quadratic form: 2*256*NB(NB+1)/2 + 4K per row and x (K=32, NB=4: 5248; "
+                         "the plain complex product would be 8320)",
                 "launches": prof["join_launches"], "kernel_ms_per_step": prof["join_ms"] / args.steps}
     line = {
         "metric": "sampled shots/sec", "value": shots_per_s, "unit": "shots/s", "n_gpus": 1,

@@ -159,7 +159,11 @@ typedef struct {
   int32_t crossing;             /* wires joining the left and right parts        */
   double flops_per_traj;        /* algorithmic real flops, per-trajectory part   */
   double flops_per_elem;        /* per element: left sweep + join                */
-  double join_flops_per_elem;   /* join only                                     */
+  double join_flops_per_elem;   /* join only; for a doubled batch on the MFMA
+                                   join (K = 16, 32) the flops of the folded real
+                                   quadratic form: per row and x, 2 per entry of
+                                   its NB(NB+1)/2 blocks of 16 x 16 (NB = 2K/16)
+                                   plus 4K                                       */
   double bytes_per_traj;        /* algorithmic HBM bytes of the per-traj part    */
 } ptsbe_batch_info_t;
 

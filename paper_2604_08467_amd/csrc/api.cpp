@@ -96,6 +96,16 @@ size_t part_scratch_per_job(const ptsbe::PartPlan& pp) {
   return 2 * ((size_t)8 << pp.peak);
 }
 
+// Workspace of one trajectory at batch bp: its right tensor, the join's layout of
+// it (the larger of the folded blocks and the canonical copy) and sweep scratch.
+size_t join_traj_bytes(const ptsbe::BatchPlan& bp) {
+  const int lkb = (int)bp.lk.size();
+  size_t layout = (size_t)8 << bp.right.labels.size();
+  if (bp.doubled && ptsbe::qform_supported(lkb))
+    layout = std::max(layout, ptsbe::qform_fold_bytes((int)bp.xT.size(), lkb));
+  return ((size_t)8 << bp.right.labels.size()) + layout + part_scratch_per_job(bp.right);
+}
+
 // Run one part (left or right) for n_jobs jobs; the result (rank = labels.size())
 // goes to out[job][2^rank].
 ptsbe_status_t run_part(Plan& p, const ptsbe::PartPlan& pp, const ptsbe::AbsorbStep* d_steps,
@@ -183,7 +193,11 @@ ptsbe_status_t run_batch(Plan& p, int j, const uint8_t* d_kraus, const float2* m
   const bool use_qform = bp.doubled && ptsbe::qform_supported(lkb);
   const bool use_ket = !bp.doubled && ptsbe::ketjoin_supported(lkb);
   const bool use_mfma = use_qform || use_ket;
-  const size_t per_traj = ((size_t)8 << rT) * (use_mfma ? 2 : 1) + part_scratch_per_job(bp.right);
+  const bool use_split = use_qform && p.precision == PTSBE_SPLIT_BF16 && ptsbe::qform_split_supported(lkb);
+  const bool use_fold = use_qform && !use_split;
+  const size_t layout_bytes = use_fold ? ptsbe::qform_fold_bytes((int)bp.xT.size(), lkb)
+                                       : (use_mfma ? ((size_t)8 << rT) : 0);
+  const size_t per_traj = ((size_t)8 << rT) + layout_bytes + part_scratch_per_job(bp.right);
   const size_t nb = (size_t)1 << bp.size;
   const size_t per_elem = (io.V_out ? 0 : ((size_t)8 << rV)) + part_scratch_per_job(left) + (io.sample ? 4 * nb : 0);
   const size_t avail = ar.left();
@@ -206,8 +220,14 @@ ptsbe_status_t run_batch(Plan& p, int j, const uint8_t* d_kraus, const float2* m
                                  ptsbe::InitArgs(), T, ar, s);
     if (st != PTSBE_OK) return st;
     float2* Tc = nullptr;
-    if (use_mfma) {   // canonical [x][k][k'] (doubled) or [x][k] (ket) layout for the MFMA joins
-      Tc = (float2*)ar.take((size_t)(t1 - t0) * ((size_t)8 << rT));
+    float4* Uf = nullptr;
+    if (use_fold) {   // folded quadratic-form blocks for the FP32 MFMA doubled join
+      Uf = (float4*)ar.take((size_t)(t1 - t0) * layout_bytes);
+      if (!Uf) return fail(PTSBE_ERR_OUT_OF_MEMORY, "workspace too small (join layout)");
+      HIP_TRY(ptsbe::launch_fold_T(T, (int64_t)1 << rT, t1 - t0, p.d_tables, p.join_dev[j], (int)bp.xT.size(), lkb,
+                                   Uf, s));
+    } else if (use_mfma) {   // canonical [x][k][k'] (split doubled) or [x][k] (ket) layout
+      Tc = (float2*)ar.take((size_t)(t1 - t0) * layout_bytes);
       if (!Tc) return fail(PTSBE_ERR_OUT_OF_MEMORY, "workspace too small (join layout)");
       HIP_TRY(ptsbe::launch_permute_T(T, (int64_t)1 << rT, t1 - t0, p.d_tables, p.join_dev[j], (int)bp.xT.size(),
                                       lkb, bp.doubled ? lkb : 0, Tc, s));
@@ -253,7 +273,7 @@ ptsbe_status_t run_batch(Plan& p, int j, const uint8_t* d_kraus, const float2* m
       if (use_mfma) {
         ptsbe::QformArgs qa{};
         qa.V = V; qa.v_stride = (int64_t)1 << rV; qa.v_base = a0;
-        qa.Tc = Tc; qa.traj_base = (int32_t)t0;
+        qa.Tc = Tc; qa.Uf = Uf; qa.traj_base = (int32_t)t0;
         int64_t tA = t0, tB = t1 - 1;
         while (tA + 1 < t1 && first[tA + 1] <= a0) ++tA;     // trajectory holding element a0
         while (tB > tA && first[tB] >= a1) --tB;             // trajectory holding element a1-1
@@ -270,7 +290,7 @@ ptsbe_status_t run_batch(Plan& p, int j, const uint8_t* d_kraus, const float2* m
         qa.amp = ja.amp;
         if (use_qform) {
           if (!qa.pop) return fail(PTSBE_ERR_INVALID_ARG, "population output required");
-          if (p.precision == PTSBE_SPLIT_BF16 && ptsbe::qform_split_supported(lkb))
+          if (use_split)
             HIP_TRY(ptsbe::launch_qform_split(qa, (int)(tB - tA + 1), (int)max_rows, s));
           else
             HIP_TRY(ptsbe::launch_qform(qa, (int)(tB - tA + 1), (int)max_rows, s));
@@ -791,11 +811,11 @@ ptsbe_status_t ptsbe_contract_workspace_size(ptsbe_plan_t plan, int32_t j, int64
     return PTSBE_OK;
   }
   const auto& bp = p->batches[j];
-  const size_t per_traj = ((size_t)8 << bp.right.labels.size()) + part_scratch_per_job(bp.right);
+  const size_t per_traj = join_traj_bytes(bp);
   const size_t per_elem = ((size_t)8 << bp.left.labels.size()) + part_scratch_per_job(bp.left);
   size_t t = (size_t)std::min<int64_t>(E, 256), e = (size_t)std::min<int64_t>(n_elems, 65536);
   *bytes = merged_bytes(*p, E) + (size_t)(E + 1) * 4 +
-           2 * (std::max<size_t>(t, 1) * per_traj * 2 + std::max<size_t>(e, 1) * per_elem) + (1 << 20);
+           2 * (std::max<size_t>(t, 1) * per_traj + std::max<size_t>(e, 1) * per_elem) + (1 << 20);
   return PTSBE_OK;
 }
 
@@ -839,7 +859,7 @@ ptsbe_status_t ptsbe_sample_workspace_size(ptsbe_plan_t plan, int64_t E, int64_t
   }
   size_t chunk = 0;
   for (auto& bp : p->batches) {
-    const size_t per_traj = ((size_t)16 << bp.right.labels.size()) + part_scratch_per_job(bp.right);
+    const size_t per_traj = join_traj_bytes(bp);
     const size_t per_elem = ((size_t)8 << bp.left.labels.size()) + part_scratch_per_job(bp.left) +
                             ((size_t)4 << bp.size);
     chunk = std::max(chunk, 2 * (std::min<size_t>(E, 256) * per_traj + 65536 * per_elem));

@@ -506,28 +506,92 @@ __global__ void __launch_bounds__(256) ketjoin_mfma_kernel(QformArgs a) {
   }
 }
 
-// MFMA join of the doubled network (Sec. II-B marginals):
-//   pi[e][o(x, xb)] = Re sum_{k'} conj(v[k']) sum_k v[k] Tc[t][x][k][k'],  v = V[e] row xb.
-// Rows r = (element, xb) of one trajectory form the M dimension of a complex GEMM
-// Y = V * Tc[x] (K x K); the quadratic form's second contraction is fused in the
-// epilogue.  One workgroup = 4 wavefronts = 64 rows of one trajectory; it loops
-// over a range of x, staging Tc[x] (real and imaginary planes) in LDS.  Complex
-// arithmetic = four real v_mfma_f32_16x16x4f32 products (Yr += Vr Tr - Vi Ti,
-// Yi += Vr Ti + Vi Tr).
+// MFMA join of the doubled network (Sec. II-B marginals).  The population of
+// element row v (one row of V, K = 2^lk_bits complex entries) at batch value x is
+//   pi = Re sum_{k,k'} v[k] Tc[x][k][k'] conj(v[k']).
+// With w = [Re v ; Im v] (2K reals) and T = Tr + i Ti this is the real quadratic
+// form pi = w^T G w, G = [[Tr, Ti], [-Ti, Tr]].  A quadratic form only depends on
+// the symmetric part of its matrix, so cutting G into 16 x 16 blocks G_IJ
+// (NB = 2K / 16 block rows) gives pi = sum_{I <= J} w_I^T U_IJ w_J with
+// U_II = G_II and U_IJ = G_IJ + G_JI^T for I < J: NB (NB + 1) / 2 block products
+// instead of the NB^2 of the plain complex product (10 instead of 16 for K = 32).
+// The identity is exact; it does not assume that T is Hermitian.
+//
+// fold_T_kernel writes, per trajectory and x, the blocks in the order
+// blk = J (J + 1) / 2 + I (I <= J), each as 64 float4 in MFMA fragment order:
+// float4 number L holds U_IJ[4 s + L / 16][L % 16] for s = 0..3, the B operand
+// of lane L at k-step s of v_mfma_f32_16x16x4f32.
+// One workgroup per (trajectory, x): T[x] is gathered once into LDS through the
+// plan's tables, then the workgroup writes the folded blocks of that x as
+// contiguous float4.
+template <int K>
+__global__ void __launch_bounds__(256) fold_T_kernel(const float2* __restrict__ T, int64_t t_stride, int64_t n_traj,
+                                                      const int64_t* __restrict__ tables, Plan::JoinDev jd,
+                                                      int xT_bits, float4* __restrict__ Uf) {
+  constexpr int NB = K / 8, NBLK = NB * (NB + 1) / 2, F4 = NBLK * 64, KK = K * K, PERT = KK / 256;
+  constexpr int LK = K == 16 ? 4 : 5;
+  static_assert(KK % 256 == 0, "K = 16 or 32");
+  __shared__ float2 Ts[K][K + 1];
+  const int tid = threadIdx.x;
+  const int lo_x = xT_bits < 12 ? xT_bits : 12;
+  int64_t koff[PERT];
+#pragma unroll
+  for (int i = 0; i < PERT; ++i) {
+    const int idx = tid + 256 * i;
+    koff[i] = tab(tables, jd.tk_lo, jd.tk_hi, LK, (uint32_t)(idx / K)) +
+              tab(tables, jd.tb_lo, jd.tb_hi, LK, (uint32_t)(idx % K));
+  }
+  // entry (i, j) of G, i, j in [0, 2K)
+  auto G = [&](int i, int j) -> float {
+    const float2 v = Ts[i & (K - 1)][j & (K - 1)];
+    if (i < K) return j < K ? v.x : v.y;
+    return j < K ? -v.y : v.x;
+  };
+  const int64_t nx = (int64_t)1 << xT_bits;
+  for (int64_t g = blockIdx.x; g < n_traj * nx; g += gridDim.x) {
+    const int64_t t = g >> xT_bits;
+    const uint32_t x = (uint32_t)(g & (nx - 1));
+    const float2* Tx = T + t * t_stride + tab(tables, jd.tx_lo, jd.tx_hi, lo_x, x);
+#pragma unroll
+    for (int i = 0; i < PERT; ++i) {
+      const int idx = tid + 256 * i;
+      Ts[idx / K][idx % K] = Tx[koff[i]];
+    }
+    __syncthreads();
+    float4* out = Uf + g * F4;
+    for (int f = tid; f < F4; f += 256) {
+      const int L = f & 63, blk = f >> 6;
+      int J = 0;
+      while ((J + 1) * (J + 2) / 2 <= blk) ++J;
+      const int I = blk - J * (J + 1) / 2;
+      float u[4];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int i = 16 * I + 4 * s + (L >> 4), j = 16 * J + (L & 15);
+        u[s] = G(i, j) + (I < J ? G(j, i) : 0.f);
+      }
+      out[f] = make_float4(u[0], u[1], u[2], u[3]);
+    }
+    __syncthreads();
+  }
+}
 
+// One workgroup = 4 wavefronts = 64 rows of one trajectory (16 rows per wave);
+// it walks a range of x, double-buffering the folded blocks of x + 1 in LDS
+// while the MFMAs of x run.  For each block column J the products w_I U_IJ
+// (I <= J) accumulate in one 16 x 16 tile, which is then dotted with w_J.
 template <int K>
 __global__ void __launch_bounds__(256) qform_mfma_kernel(QformArgs a) {
   constexpr int ROWS = 64;
-  constexpr int KS = K / 4;          // k-steps of 4
-  constexpr int NH = K / 16;         // 16-column tiles of k'
-  constexpr int TS = K + 1;          // padded LDS row stride
-  constexpr int PER = K * K / 256;   // Tc entries per thread per block
-  __shared__ float Tr[2][K * TS];
-  __shared__ float Ti[2][K * TS];
+  constexpr int NB = K / 8;                    // 16-wide block rows of the 2K reals
+  constexpr int NBLK = NB * (NB + 1) / 2;
+  constexpr int F4 = NBLK * 64;                // float4 per x
+  constexpr int PER = (F4 + 255) / 256;
+  __shared__ float4 Ub[2][F4];
   __shared__ float2 Vs[ROWS][K + 1];
   // Workgroups go round-robin to the 8 XCDs in linear launch order; renumber them
   // so that consecutive logical tiles (the row tiles of one trajectory, which all
-  // read that trajectory's T) run on the same XCD and share its L2.
+  // read that trajectory's blocks) run on the same XCD and share its L2.
   uint32_t bx, by, bz;
   {
     const uint32_t nbx = gridDim.x, nby = gridDim.y, total = nbx * nby * gridDim.z;
@@ -565,58 +629,72 @@ __global__ void __launch_bounds__(256) qform_mfma_kernel(QformArgs a) {
     }
     Vs[rr][k] = v;
   }
-  const float2* Tt = a.Tc + (int64_t)(t - a.traj_base) * ((int64_t)nx * K * K);
+  const float4* Ut = a.Uf + (int64_t)(t - a.traj_base) * ((int64_t)nx * F4);
   {
-    const float2* src = Tt + (int64_t)x_begin * K * K;
-#pragma unroll
-    for (int i = 0; i < PER; ++i) {
-      const int idx = tid + 256 * i;
-      const float2 v = src[idx];
-      Tr[0][(idx / K) * TS + idx % K] = v.x;
-      Ti[0][(idx / K) * TS + idx % K] = v.y;
-    }
+    const float4* src = Ut + (int64_t)x_begin * F4;
+    for (int idx = tid; idx < F4; idx += 256) Ub[0][idx] = src[idx];
   }
   __syncthreads();
-  // A fragments: lane holds V[row = wave*16 + lane%16][4s + lane/16]
-  float ar[KS], ai[KS];
-  const int arow = wave * 16 + (lane & 15);
+  // A fragments: wa[I][s] = w[wave*16 + lane%16][16 I + 4 s + lane/16];
+  // epilogue weights: we[J][i] = w[wave*16 + 4 (lane/16) + i][16 J + lane%16]
+  float wa[NB][4], we[NB][4];
+  {
+    const int arow = wave * 16 + (lane & 15);
 #pragma unroll
-  for (int s = 0; s < KS; ++s) {
-    const float2 v = Vs[arow][4 * s + (lane >> 4)];
-    ar[s] = v.x;
-    ai[s] = v.y;
+    for (int I = 0; I < NB; ++I)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const float2 v = Vs[arow][(16 * I + 4 * s + (lane >> 4)) & (K - 1)];
+        wa[I][s] = 16 * I < K ? v.x : v.y;
+      }
+#pragma unroll
+    for (int J = 0; J < NB; ++J)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const float2 v = Vs[wave * 16 + 4 * (lane >> 4) + i][(16 * J + (lane & 15)) & (K - 1)];
+        we[J][i] = 16 * J < K ? v.x : v.y;
+      }
   }
   const int nout = 1 << a.b;
   const int lo_x = a.xT_bits < 12 ? a.xT_bits : 12;
+  // output offsets of the lane's 4 rows (without the x part), -1 past the rows
+  int64_t obase[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int64_t row = row0 + wave * 16 + 4 * (lane >> 4) + i;
+    obase[i] = -1;
+    if (row < rows_t) {
+      const int64_t e = e_begin + (row >> xb_bits);
+      const uint32_t xb = (uint32_t)(row & ((1 << xb_bits) - 1));
+      obase[i] = (e - a.v_base) * nout + tab(a.tab, a.jd.ob_lo, a.jd.ob_hi, lo_b, xb);
+    }
+  }
   int buf = 0;
   for (int x = x_begin; x < x_end; ++x) {
     const bool more = x + 1 < x_end;
-    float2 nxt[PER];
-    if (more) {                                   // next block in flight during the MFMAs
-      const float2* src = Tt + (int64_t)(x + 1) * K * K;
-#pragma unroll
-      for (int i = 0; i < PER; ++i) nxt[i] = src[tid + 256 * i];
-    }
+    const int64_t ox = tab(a.tab, a.jd.ox_lo, a.jd.ox_hi, lo_x, (uint32_t)x);   // uniform
+    // next blocks in flight during the MFMAs (every lane loads, at clamped in-bounds
+    // indexes; the last x reloads its own blocks, which are not stored)
+    static_assert(PER <= 3, "at most three float4 per thread per x");
+    const float4* src = Ut + (int64_t)(more ? x + 1 : x) * F4;
+    const float4 nx0 = src[tid < F4 ? tid : F4 - 1];
+    const float4 nx1 = src[PER > 1 && tid + 256 < F4 ? tid + 256 : F4 - 1];
+    const float4 nx2 = src[PER > 2 && tid + 512 < F4 ? tid + 512 : F4 - 1];
+    __builtin_amdgcn_sched_barrier(0);            // keep the loads ahead of the MFMAs
     float p[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int h = 0; h < NH; ++h) {
-      floatx4 yr = {0.f, 0.f, 0.f, 0.f}, yi = {0.f, 0.f, 0.f, 0.f};
+    for (int J = 0; J < NB; ++J) {
+      floatx4 y = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int s = 0; s < KS; ++s) {
-        const int bi = (4 * s + (lane >> 4)) * TS + 16 * h + (lane & 15);
-        const float br = Tr[buf][bi], bim = Ti[buf][bi];
-        yr = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[s], br, yr, 0, 0, 0);
-        yr = __builtin_amdgcn_mfma_f32_16x16x4f32(-ai[s], bim, yr, 0, 0, 0);
-        yi = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[s], bim, yi, 0, 0, 0);
-        yi = __builtin_amdgcn_mfma_f32_16x16x4f32(ai[s], br, yi, 0, 0, 0);
+      for (int I = 0; I <= J; ++I) {
+        const float4 bq = Ub[buf][(J * (J + 1) / 2 + I) * 64 + lane];
+        y = __builtin_amdgcn_mfma_f32_16x16x4f32(wa[I][0], bq.x, y, 0, 0, 0);
+        y = __builtin_amdgcn_mfma_f32_16x16x4f32(wa[I][1], bq.y, y, 0, 0, 0);
+        y = __builtin_amdgcn_mfma_f32_16x16x4f32(wa[I][2], bq.z, y, 0, 0, 0);
+        y = __builtin_amdgcn_mfma_f32_16x16x4f32(wa[I][3], bq.w, y, 0, 0, 0);
       }
-      // epilogue: Re(Y * conj(v)) for the lane's 4 rows and column k'
-      const int kc = 16 * h + (lane & 15);
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const float2 v = Vs[wave * 16 + 4 * (lane >> 4) + i][kc];
-        p[i] += yr[i] * v.x + yi[i] * v.y;
-      }
+      for (int i = 0; i < 4; ++i) p[i] += y[i] * we[J][i];
     }
     // reduce over the 16 lanes that share lane/16
 #pragma unroll
@@ -629,25 +707,14 @@ __global__ void __launch_bounds__(256) qform_mfma_kernel(QformArgs a) {
       p[i] = v;
     }
     if ((lane & 15) == 0) {
-      const int64_t ox = tab(a.tab, a.jd.ox_lo, a.jd.ox_hi, lo_x, (uint32_t)x);
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int64_t row = row0 + wave * 16 + 4 * (lane >> 4) + i;
-        if (row < rows_t) {
-          const int64_t e = e_begin + (row >> xb_bits);
-          const uint32_t xb = (uint32_t)(row & ((1 << xb_bits) - 1));
-          const int64_t o = ox + tab(a.tab, a.jd.ob_lo, a.jd.ob_hi, lo_b, xb);
-          a.pop[(e - a.v_base) * nout + o] = p[i];
-        }
-      }
+      for (int i = 0; i < 4; ++i)
+        if (obase[i] >= 0) a.pop[obase[i] + ox] = p[i];
     }
     if (more) {
-#pragma unroll
-      for (int i = 0; i < PER; ++i) {
-        const int idx = tid + 256 * i;
-        Tr[buf ^ 1][(idx / K) * TS + idx % K] = nxt[i].x;
-        Ti[buf ^ 1][(idx / K) * TS + idx % K] = nxt[i].y;
-      }
+      if (tid < F4) Ub[buf ^ 1][tid] = nx0;
+      if (PER > 1 && tid + 256 < F4) Ub[buf ^ 1][tid + 256] = nx1;
+      if (PER > 2 && tid + 512 < F4) Ub[buf ^ 1][tid + 512] = nx2;
     }
     __syncthreads();
     buf ^= 1;
@@ -1044,6 +1111,23 @@ hipError_t launch_qform_split(const QformArgs& a, int n_traj, int max_rows, hipS
   return hipGetLastError();
 }
 bool ketjoin_supported(int lk_bits) { return lk_bits >= 2 && lk_bits <= 6; }
+
+size_t qform_fold_bytes(int xT_bits, int lk_bits) {
+  const size_t nb = (size_t)1 << (lk_bits - 3);
+  return (nb * (nb + 1) / 2) * 1024 << xT_bits;
+}
+
+hipError_t launch_fold_T(const float2* T, int64_t t_stride, int64_t n_traj, const int64_t* tab,
+                         const Plan::JoinDev& jd, int xT_bits, int lk_bits, float4* Uf, hipStream_t stream) {
+  if (n_traj <= 0) return hipSuccess;
+  if (!qform_supported(lk_bits)) return hipErrorInvalidValue;
+  const dim3 grid(grid_blocks(n_traj << xT_bits));
+  if (lk_bits == 4)
+    hipLaunchKernelGGL(fold_T_kernel<16>, grid, dim3(256), 0, stream, T, t_stride, n_traj, tab, jd, xT_bits, Uf);
+  else
+    hipLaunchKernelGGL(fold_T_kernel<32>, grid, dim3(256), 0, stream, T, t_stride, n_traj, tab, jd, xT_bits, Uf);
+  return hipGetLastError();
+}
 
 hipError_t launch_qform(const QformArgs& a, int n_traj, int max_rows, hipStream_t stream) {
   if (n_traj <= 0 || max_rows <= 0) return hipSuccess;
