@@ -128,11 +128,31 @@ ptsbe_status_t run_part(Plan& p, const ptsbe::PartPlan& pp, const ptsbe::AbsorbS
   float2* b0 = (float2*)ar.take((size_t)n_jobs * ((size_t)8 << pp.peak));
   float2* b1 = (float2*)ar.take((size_t)n_jobs * ((size_t)8 << pp.peak));
   if (!b0 || !b1) return fail(PTSBE_ERR_OUT_OF_MEMORY, "workspace too small for a sweep");
-  if (init.Vprev) HIP_TRY(ptsbe::launch_init_gather(init, n_jobs, job_prefix, p.NW, b0, s));
-  else HIP_TRY(ptsbe::launch_fill_one(b0, n_jobs, s));   // rank-0 start: the scalar 1 per job
-  float2* A = b0;
+  // the leading segments whose tensors all fit 2^kVmMaxRank entries run as one
+  // LDS sweep (one launch) instead of one launch per step
   const size_t nseg = pp.segs.size();
-  for (size_t si = 0; si < nseg; ++si) {
+  size_t s0 = 0;
+  int h = 0, hpeak = 0;
+  while (s0 + 1 < nseg) {
+    const ptsbe::Segment& sg = pp.segs[s0];
+    int pk = hpeak;
+    for (int i = sg.first; i < sg.first + sg.count; ++i)
+      pk = std::max(pk, std::max(pp.steps[(size_t)i].rA, pp.steps[(size_t)i].rC));
+    if (pk > ptsbe::kVmMaxRank) break;
+    hpeak = pk;
+    h = sg.first + sg.count;
+    ++s0;
+  }
+  if (h >= 2) {
+    HIP_TRY(ptsbe::launch_part_vm(d_steps, h, hpeak, g, n_jobs, job_traj, traj_base, job_prefix, p.NW, init, b0,
+                                  pp.steps[(size_t)h - 1].rC, s));
+  } else {
+    s0 = 0;
+    if (init.Vprev) HIP_TRY(ptsbe::launch_init_gather(init, n_jobs, job_prefix, p.NW, b0, s));
+    else HIP_TRY(ptsbe::launch_fill_one(b0, n_jobs, s));   // rank-0 start: the scalar 1 per job
+  }
+  float2* A = b0;
+  for (size_t si = s0; si < nseg; ++si) {
     const ptsbe::Segment& sg = pp.segs[si];
     if (sg.fused) {   // a run of in-place steps, one tile pass, in place
       HIP_TRY(ptsbe::launch_fused(sg, p.d_fused, g, n_jobs, job_traj, traj_base, job_prefix, p.NW, A, s));

@@ -79,45 +79,66 @@ __device__ inline uint32_t init_offset(const InitArgs& in, uint32_t m, const uin
   return m;
 }
 
-__global__ void part_vm_kernel(const AbsorbStep* __restrict__ steps, int n_steps, int buf_elems,
-                               GateCtx g, int64_t n_jobs, const int32_t* __restrict__ job_traj,
-                               int32_t traj_base, const uint64_t* __restrict__ job_prefix, int NW,
-                               InitArgs init, float2* __restrict__ out, int out_rank) {
+__global__ void __launch_bounds__(256) part_vm_kernel(const AbsorbStep* __restrict__ steps, int n_steps,
+                                                      int buf_elems, int J, GateCtx g, int64_t n_jobs,
+                                                      const int32_t* __restrict__ job_traj, int32_t traj_base,
+                                                      const uint64_t* __restrict__ job_prefix, int NW,
+                                                      InitArgs init, float2* __restrict__ out, int out_rank) {
+  // J jobs per workgroup run the same step list in lockstep: each step's
+  // descriptor is decoded once for all of them and the threads take
+  // (job, kept index) work items.
   extern __shared__ float2 lds[];
-  float2* bufA = lds;
-  float2* bufC = lds + buf_elems;
-  float2* Gm = lds + 2 * buf_elems;              // two gate buffers of 16
-  uint64_t* pw = reinterpret_cast<uint64_t*>(Gm + 32);
-  const int tid = threadIdx.x;
-  for (int64_t job = blockIdx.x; job < n_jobs; job += gridDim.x) {
-  const int traj = job_traj ? job_traj[job] : traj_base + (int)job;
-  for (int w = tid; w < NW; w += blockDim.x) pw[w] = job_prefix ? job_prefix[job * NW + w] : 0ull;
-  if (init.Vprev) {
+  float2* bufA = lds;                                   // [J][buf_elems]
+  float2* bufC = lds + (size_t)J * buf_elems;           // [J][buf_elems]
+  float2* Gm = lds + 2 * (size_t)J * buf_elems;         // [2][J][16] gates of the step, double-buffered
+  uint64_t* pw = reinterpret_cast<uint64_t*>(Gm + 32 * J);   // [J][NW] prefixes
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int gj = tid >> 4, gi = tid & 15;               // the gate entry this thread loads (gj < J)
+  const int64_t n_groups = (n_jobs + J - 1) / J;
+  for (int64_t grp = blockIdx.x; grp < n_groups; grp += gridDim.x) {
+    const int64_t job0 = grp * J;
+    const int nj = (int)(n_jobs - job0 < J ? n_jobs - job0 : J);
+    for (int i = tid; i < nj * NW; i += nt) pw[i] = job_prefix ? job_prefix[job0 * NW + i] : 0ull;
     __syncthreads();
-    const float2* src = init.Vprev + (int64_t)init.parent[job] * init.stride;
-    for (uint32_t m = tid; m < (1u << init.r0); m += blockDim.x) bufA[m] = src[init_offset(init, m, pw)];
-  } else if (tid == 0) {
-    bufA[0] = make_float2(1.f, 0.f);
-  }
-  // the gate of the next step is loaded while the current step computes
-  float2 gnext = make_float2(0.f, 0.f);
-  if (tid < 16 && n_steps > 0) gnext = gate_entry(g, steps[0].gate, traj, steps[0].conj, tid);
-  for (int s = 0; s < n_steps; ++s) {
-    const AbsorbStep& st = steps[s];
-    float2* G = Gm + 16 * (s & 1);
-    if (tid < 16) G[tid] = gnext;
-    if (tid < 16 && s + 1 < n_steps) gnext = gate_entry(g, steps[s + 1].gate, traj, steps[s + 1].conj, tid);
-    __syncthreads();     // gate visible; previous step's C complete
-    const int sb = slice_base(st, pw);
-    const uint32_t nm = 1u << (st.rC - st.nN);
-    for (uint32_t m = tid; m < nm; m += blockDim.x) absorb_one(st, sb, m, bufA, bufC, G);
-    float2* t = bufA; bufA = bufC; bufC = t;
-  }
-  __syncthreads();
-  const int64_t n_out = (int64_t)1 << out_rank;
-  float2* o = out + job * n_out;
-  for (int64_t i = tid; i < n_out; i += blockDim.x) o[i] = bufA[i];
-  __syncthreads();   // LDS is reused by the next job of this workgroup
+    if (init.Vprev) {
+      const uint32_t n0 = 1u << init.r0;
+      for (int i = tid; i < nj * (int)n0; i += nt) {
+        const int j = i >> init.r0;
+        const uint32_t m = (uint32_t)i & (n0 - 1u);
+        const float2* src = init.Vprev + (int64_t)init.parent[job0 + j] * init.stride;
+        bufA[(size_t)j * buf_elems + m] = src[init_offset(init, m, pw + j * NW)];
+      }
+    } else {
+      for (int j = tid; j < nj; j += nt) bufA[(size_t)j * buf_elems] = make_float2(1.f, 0.f);
+    }
+    // the gate of the next step is loaded while the current step computes
+    const bool gl = gj < nj;
+    const int traj = gl ? (job_traj ? job_traj[job0 + gj] : traj_base + (int)(job0 + gj)) : 0;
+    float2 gnext = make_float2(0.f, 0.f);
+    if (gl && n_steps > 0) gnext = gate_entry(g, steps[0].gate, traj, steps[0].conj, gi);
+    for (int s = 0; s < n_steps; ++s) {
+      const AbsorbStep& st = steps[s];
+      float2* G = Gm + 16 * J * (s & 1);
+      if (gl) G[tid] = gnext;
+      if (gl && s + 1 < n_steps) gnext = gate_entry(g, steps[s + 1].gate, traj, steps[s + 1].conj, gi);
+      __syncthreads();     // gates visible; previous step's C complete
+      const int lnm = st.rC - st.nN;
+      const int items = nj << lnm;
+      for (int i = tid; i < items; i += nt) {
+        const int j = i >> lnm;
+        const uint32_t m = (uint32_t)i & ((1u << lnm) - 1u);
+        absorb_one(st, slice_base(st, pw + j * NW), m, bufA + (size_t)j * buf_elems, bufC + (size_t)j * buf_elems,
+                   G + 16 * j);
+      }
+      float2* t = bufA; bufA = bufC; bufC = t;
+    }
+    __syncthreads();
+    const int64_t n_out = (int64_t)1 << out_rank;
+    for (int64_t i = tid; i < (int64_t)nj * n_out; i += nt) {
+      const int64_t j = i >> out_rank, k = i & (n_out - 1);
+      out[(job0 + j) * n_out + k] = bufA[j * buf_elems + k];
+    }
+    __syncthreads();   // LDS is reused by the next group of this workgroup
   }
 }
 
@@ -1029,11 +1050,13 @@ hipError_t launch_part_vm(const AbsorbStep* d_steps, int n_steps, int peak, Gate
                           const InitArgs& init, float2* out, int out_rank, hipStream_t stream) {
   if (n_jobs <= 0) return hipSuccess;
   const int buf = 1 << (peak > 0 ? peak : 0);
-  const size_t shmem = (size_t)(2 * buf + 32) * sizeof(float2) + (size_t)NW * sizeof(uint64_t);
-  // one wavefront per job while the tensor has <= 128 entries
-  int threads = buf / 2 < 64 ? 64 : (buf / 2 > 256 ? 256 : buf / 2);
-  hipLaunchKernelGGL(part_vm_kernel, dim3(grid_blocks(n_jobs)), dim3(threads), shmem, stream, d_steps, n_steps,
-                     buf, g, n_jobs, job_traj, traj_base, job_prefix, NW, init, out, out_rank);
+  // small tensors: up to 16 jobs share a 256-thread workgroup (<= 16 KB of tensors);
+  // one job per workgroup from 2^10 entries on
+  const int J = buf <= 64 ? 16 : (buf >= 1024 ? 1 : 1024 / buf);
+  const int threads = J > 1 ? 256 : (buf / 2 < 64 ? 64 : (buf / 2 > 256 ? 256 : buf / 2));
+  const size_t shmem = (size_t)(2 * J * buf + 32 * J) * sizeof(float2) + (size_t)J * NW * sizeof(uint64_t);
+  hipLaunchKernelGGL(part_vm_kernel, dim3(grid_blocks((n_jobs + J - 1) / J)), dim3(threads), shmem, stream,
+                     d_steps, n_steps, buf, J, g, n_jobs, job_traj, traj_base, job_prefix, NW, init, out, out_rank);
   return hipGetLastError();
 }
 
