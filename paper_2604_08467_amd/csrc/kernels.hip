@@ -763,164 +763,199 @@ __global__ void row_totals_kernel(const float* pop, int64_t n_elems, int b, doub
 }
 
 // --------------------------------------------------------------------- sampling
-constexpr int kSampleThreads = 256;
-
-// Block-wide inclusive FP64 scan of c[0..n) in LDS (n a power of two <= 4096):
-// each thread scans a contiguous chunk sequentially, chunk totals are scanned
-// by a fixed tree, then added back.
-__device__ void block_scan_f64(double* c, int n, double* part) {
-  const int T = kSampleThreads;
-  const int per = (n + T - 1) / T;
-  const int lo = threadIdx.x * per;
-  const int hi = lo + per < n ? lo + per : n;
-  double s = 0.0;
-  for (int i = lo; i < hi; ++i) { s += c[i]; c[i] = s; }
-  part[threadIdx.x] = s;
-  __syncthreads();
-  for (int off = 1; off < T; off <<= 1) {
-    double v = (int)threadIdx.x >= off ? part[threadIdx.x - off] : 0.0;
-    __syncthreads();
-    part[threadIdx.x] += v;
-    __syncthreads();
-  }
-  const double add = threadIdx.x > 0 ? part[threadIdx.x - 1] : 0.0;
-  for (int i = lo; i < hi; ++i) c[i] += add;
-  __syncthreads();
+// Sampling and non-degenerate batching run one wavefront per element, with no
+// workgroup-wide scans: lane L owns the contiguous chunk [L per, (L+1) per) of
+// the 2^b values.
+//
+// The CDF (Sec. II-B inverse-CDF draw) in FP64: a lane sums its chunk in index
+// order (s_L), a fixed shuffle tree gives the exclusive prefix exc_L of the
+// chunk sums, and C(x) = exc_L + (sum of the chunk's values up to x, in index
+// order).  cend_L = exc_L + s_L is C at the chunk's end, computed by the same
+// operations, so the lane found by a search over cend always contains the
+// first x with C(x) > target.  Z = C(2^b - 1).
+__device__ inline void chunk_of(int n, int lane, int& c0, int& c1) {
+  const int per = n >= 64 ? n >> 6 : 1;
+  c0 = lane * per;
+  c1 = c0 + per < n ? c0 + per : n;
+  if (c0 > n) c0 = n;
 }
 
-__global__ void __launch_bounds__(kSampleThreads) sample_kernel(SampleArgs a) {
-  extern __shared__ double sm[];
+__global__ void __launch_bounds__(64) sample_kernel(SampleArgs a) {
+  extern __shared__ int hist[];           // [2^b] shot counts per x (child counts only)
+  __shared__ double cend[64], exc[64];
   const int n = 1 << a.b;
-  double* C = sm;
-  double* part = sm + n;
-  int* hist = reinterpret_cast<int*>(part + kSampleThreads);
-  __shared__ int last_pos;
-  __shared__ int nchild;
+  const int lane = threadIdx.x;
+  const int nl = n < 64 ? n : 64;         // lanes with a non-empty chunk
+  int c0, c1;
+  chunk_of(n, lane, c0, c1);
   for (int64_t e = blockIdx.x; e < a.n_elems; e += gridDim.x) {
-  const float* pi = a.pop + e * (int64_t)n;
-  for (int i = threadIdx.x; i < n; i += kSampleThreads) {
-    C[i] = (double)pi[i];
-    hist[i] = 0;
-  }
-  if (threadIdx.x == 0) { last_pos = -1; nchild = 0; }
-  __syncthreads();
-  // largest x with pi(x) > 0
-  {
+    const float* pi = a.pop + e * (int64_t)n;
+    const int off = a.elem_shot_off[e];
+    const int cnt = a.elem_shot_cnt[e];
+    const bool want_hist = a.child_cnt && cnt > 1;
+    if (want_hist)
+      for (int x = c0; x < c1; ++x) hist[x] = 0;
+    double s = 0.0;
     int lp = -1;
-    for (int i = threadIdx.x; i < n; i += kSampleThreads)
-      if (C[i] > 0.0) lp = i;
-    atomicMax(&last_pos, lp);
-  }
-  __syncthreads();
-  block_scan_f64(C, n, part);
-  const double Z = C[n - 1];
-  if (threadIdx.x == 0) {
-    a.elem_total[e] = Z;
-    // Z == 0: the trajectory's inserted operators annihilated the state (weight 0,
-    // all-zero shots); only a non-finite or negative total is an error
-    if (!(Z >= 0.0) || !isfinite(Z)) atomicExch(a.bad_flag, 1);
-  }
-  const int traj = a.elem_traj[e];
-  const int off = a.elem_shot_off[e];
-  const int cnt = a.elem_shot_cnt[e];
-  const int64_t tbase = a.traj_shot_base[traj];
-  for (int i = threadIdx.x; i < cnt; i += kSampleThreads) {
-    const int row = a.shot_ids[off + i];
-    const uint32_t t = (uint32_t)(row - tbase);
-    const double u = philox_uniform(a.seed, 2u, (uint32_t)traj, (uint32_t)a.j, t, 0u);
-    const double target = u * Z;
-    // first x with C[x] > target
-    int lo = 0, hi = n;   // invariant: answer in [lo, hi]
-    while (lo < hi) {
-      int mid = (lo + hi) >> 1;
-      if (C[mid] > target) hi = mid; else lo = mid + 1;
+    if (((c1 - c0) & 3) == 0) {
+      for (int x = c0; x < c1; x += 4) {
+        const float4 v = *reinterpret_cast<const float4*>(pi + x);
+        s += (double)v.x; s += (double)v.y; s += (double)v.z; s += (double)v.w;
+        if (v.x > 0.f) lp = x;
+        if (v.y > 0.f) lp = x + 1;
+        if (v.z > 0.f) lp = x + 2;
+        if (v.w > 0.f) lp = x + 3;
+      }
+    } else {
+      for (int x = c0; x < c1; ++x) {
+        const float v = pi[x];
+        s += (double)v;
+        if (v > 0.f) lp = x;
+      }
     }
-    int x = lo < n ? lo : last_pos;
-    if (x < 0) x = 0;
-    a.shot_x[row] = x;
-    // write the batch bits at qubits [start, start + b)
-    uint64_t* w = a.shots + (int64_t)row * a.NW;
-    const int q0 = a.start;
-    const int wi = q0 >> 6, sh = q0 & 63;
-    w[wi] |= (uint64_t)x << sh;
-    if (sh + a.b > 64) w[wi + 1] |= (uint64_t)x >> (64 - sh);
-    if (a.child_cnt) atomicAdd(&hist[x], 1);
-  }
-  if (a.child_cnt) {
+    double incl = s;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const double t = __shfl_up(incl, d);
+      if (lane >= d) incl += t;
+    }
+    double ex = __shfl_up(incl, 1);
+    if (lane == 0) ex = 0.0;
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) {
+      const int o = __shfl_xor(lp, d);
+      lp = o > lp ? o : lp;
+    }
+    const int last_pos = lp;                   // largest x with pi(x) > 0, or -1
+    exc[lane] = ex;
+    cend[lane] = ex + s;
     __syncthreads();
-    int c = 0;
-    for (int i = threadIdx.x; i < n; i += kSampleThreads) c += hist[i] > 0;
-    atomicAdd(&nchild, c);
-    __syncthreads();
-    if (threadIdx.x == 0) a.child_cnt[e] = nchild;
-  }
-  __syncthreads();   // LDS and the shared scalars are reset for the next element
+    const double Z = cend[nl - 1];
+    if (lane == 0) {
+      a.elem_total[e] = Z;
+      // Z == 0: the trajectory's inserted operators annihilated the state (weight 0,
+      // all-zero shots); only a non-finite or negative total is an error
+      if (!(Z >= 0.0) || !isfinite(Z)) atomicExch(a.bad_flag, 1);
+    }
+    const int traj = a.elem_traj[e];
+    const int64_t tbase = a.traj_shot_base[traj];
+    for (int i = lane; i < cnt; i += 64) {
+      const int row = a.shot_ids[off + i];
+      const uint32_t t = (uint32_t)(row - tbase);
+      const double u = philox_uniform(a.seed, 2u, (uint32_t)traj, (uint32_t)a.j, t, 0u);
+      const double target = u * Z;
+      int lo = 0, hi = nl;                      // first lane with cend > target
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (cend[mid] > target) hi = mid; else lo = mid + 1;
+      }
+      int x = last_pos;
+      if (lo < nl) {
+        int b0, b1;
+        chunk_of(n, lo, b0, b1);
+        const double el = exc[lo];
+        double sx = 0.0;
+        for (int k = b0; k < b1; ++k) {
+          sx += (double)pi[k];
+          if (el + sx > target) { x = k; break; }
+        }
+      }
+      if (x < 0) x = 0;
+      a.shot_x[row] = x;
+      // write the batch bits at qubits [start, start + b)
+      uint64_t* w = a.shots + (int64_t)row * a.NW;
+      const int q0 = a.start;
+      const int wi = q0 >> 6, sh = q0 & 63;
+      w[wi] |= (uint64_t)x << sh;
+      if (sh + a.b > 64) w[wi + 1] |= (uint64_t)x >> (64 - sh);
+      if (want_hist) atomicAdd(&hist[x], 1);
+    }
+    if (a.child_cnt) {
+      int c = cnt > 0 ? 1 : 0;
+      if (want_hist) {
+        __syncthreads();
+        c = 0;
+        for (int x = c0; x < c1; ++x) c += hist[x] > 0;
+#pragma unroll
+        for (int d = 32; d > 0; d >>= 1) c += __shfl_xor(c, d);
+      }
+      if (lane == 0) a.child_cnt[e] = c;
+    }
+    __syncthreads();   // LDS is reused by the next element
   }
 }
 
-__global__ void __launch_bounds__(kSampleThreads) children_kernel(ChildArgs a) {
+__global__ void __launch_bounds__(64) children_kernel(ChildArgs a) {
   extern __shared__ int ism[];
   const int n = 1 << a.b;
   int* hist = ism;          // counts per x
-  int* start = ism + n;     // exclusive scan of counts
+  int* start = ism + n;     // exclusive scan of counts (then the scatter cursor)
   int* rank = ism + 2 * n;  // exclusive scan of (count > 0)
-  __shared__ int part_s[kSampleThreads];
-  __shared__ int part_r[kSampleThreads];
+  const int lane = threadIdx.x;
+  int c0, c1;
+  chunk_of(n, lane, c0, c1);
   for (int64_t e = blockIdx.x; e < a.n_elems; e += gridDim.x) {
-  for (int i = threadIdx.x; i < n; i += kSampleThreads) hist[i] = 0;
-  __syncthreads();
-  const int off = a.elem_shot_off[e], cnt = a.elem_shot_cnt[e];
-  for (int i = threadIdx.x; i < cnt; i += kSampleThreads) atomicAdd(&hist[a.shot_x[a.shot_ids[off + i]]], 1);
-  __syncthreads();
-  // exclusive scans of hist and of (hist > 0), chunked per thread
-  const int per = (n + kSampleThreads - 1) / kSampleThreads;
-  const int lo = threadIdx.x * per, hi = lo + per < n ? lo + per : n;
-  int s = 0, r = 0;
-  for (int i = lo; i < hi; ++i) { s += hist[i]; r += hist[i] > 0; }
-  part_s[threadIdx.x] = s;
-  part_r[threadIdx.x] = r;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int as = 0, ar = 0;
-    for (int t = 0; t < kSampleThreads; ++t) {
-      int ts = part_s[t], tr = part_r[t];
-      part_s[t] = as; part_r[t] = ar;
-      as += ts; ar += tr;
-    }
-  }
-  __syncthreads();
-  s = part_s[threadIdx.x];
-  r = part_r[threadIdx.x];
-  for (int i = lo; i < hi; ++i) {
-    start[i] = s; rank[i] = r;
-    s += hist[i]; r += hist[i] > 0;
-  }
-  __syncthreads();
-  const int traj = a.elem_traj[e];
-  const int64_t cbase = a.child_off[e];
-  const uint64_t* pp = a.elem_prefix + e * a.NW;
-  for (int x = threadIdx.x; x < n; x += kSampleThreads) {
-    if (hist[x] == 0) continue;
-    const int64_t c = cbase + rank[x];
-    a.out_traj[c] = traj;
-    a.out_parent[c] = (int32_t)e;
-    a.out_shot_off[c] = off + start[x];
-    a.out_shot_cnt[c] = hist[x];
-    uint64_t* op = a.out_prefix + c * a.NW;
-    for (int w = 0; w < a.NW; ++w) op[w] = pp[w];
+    const int off = a.elem_shot_off[e], cnt = a.elem_shot_cnt[e];
+    if (cnt <= 0) continue;               // uniform over the wavefront
+    const int traj = a.elem_traj[e];
+    const int64_t cbase = a.child_off[e];
+    const uint64_t* pp = a.elem_prefix + e * a.NW;
     const int wi = a.start >> 6, sh = a.start & 63;
-    op[wi] |= (uint64_t)x << sh;
-    if (sh + a.b > 64) op[wi + 1] |= (uint64_t)x >> (64 - sh);
-  }
-  __syncthreads();
-  // scatter shot ids into the children's ranges (order within a child is free)
-  for (int i = threadIdx.x; i < cnt; i += kSampleThreads) {
-    const int row = a.shot_ids[off + i];
-    const int x = a.shot_x[row];
-    const int pos = atomicAdd(&start[x], 1);
-    a.out_shot_ids[off + pos] = row;
-  }
-  __syncthreads();   // LDS is reused by the next element
+    if (cnt == 1) {                       // one shot: one child
+      if (lane == 0) {
+        const int row = a.shot_ids[off];
+        const int x = a.shot_x[row];
+        a.out_traj[cbase] = traj;
+        a.out_parent[cbase] = (int32_t)e;
+        a.out_shot_off[cbase] = off;
+        a.out_shot_cnt[cbase] = 1;
+        uint64_t* op = a.out_prefix + cbase * a.NW;
+        for (int w = 0; w < a.NW; ++w) op[w] = pp[w];
+        op[wi] |= (uint64_t)x << sh;
+        if (sh + a.b > 64) op[wi + 1] |= (uint64_t)x >> (64 - sh);
+        a.out_shot_ids[off] = row;
+      }
+      continue;
+    }
+    for (int x = c0; x < c1; ++x) hist[x] = 0;
+    __syncthreads();
+    for (int i = lane; i < cnt; i += 64) atomicAdd(&hist[a.shot_x[a.shot_ids[off + i]]], 1);
+    __syncthreads();
+    // exclusive scans of hist and of (hist > 0) over the lanes' chunks
+    int ls = 0, lr = 0;
+    for (int x = c0; x < c1; ++x) { ls += hist[x]; lr += hist[x] > 0; }
+    int is = ls, ir = lr;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int ts = __shfl_up(is, d), tr = __shfl_up(ir, d);
+      if (lane >= d) { is += ts; ir += tr; }
+    }
+    int sacc = is - ls, racc = ir - lr;
+    for (int x = c0; x < c1; ++x) {
+      const int h = hist[x];
+      start[x] = sacc; rank[x] = racc;
+      if (h > 0) {
+        const int64_t c = cbase + racc;
+        a.out_traj[c] = traj;
+        a.out_parent[c] = (int32_t)e;
+        a.out_shot_off[c] = off + sacc;
+        a.out_shot_cnt[c] = h;
+        uint64_t* op = a.out_prefix + c * a.NW;
+        for (int w = 0; w < a.NW; ++w) op[w] = pp[w];
+        op[wi] |= (uint64_t)x << sh;
+        if (sh + a.b > 64) op[wi + 1] |= (uint64_t)x >> (64 - sh);
+      }
+      sacc += h; racc += h > 0;
+    }
+    __syncthreads();
+    // scatter shot ids into the children's ranges (order within a child is free)
+    for (int i = lane; i < cnt; i += 64) {
+      const int row = a.shot_ids[off + i];
+      const int x = a.shot_x[row];
+      const int pos = atomicAdd(&start[x], 1);
+      a.out_shot_ids[off + pos] = row;
+    }
+    __syncthreads();   // LDS is reused by the next element
   }
 }
 
@@ -1195,8 +1230,8 @@ hipError_t launch_row_totals(const float* pop, int64_t n_elems, int b, double* t
 hipError_t launch_sample(const SampleArgs& a, hipStream_t stream) {
   if (a.n_elems <= 0) return hipSuccess;
   const int n = 1 << a.b;
-  const size_t shmem = (size_t)n * sizeof(double) + kSampleThreads * sizeof(double) + (size_t)n * sizeof(int);
-  hipLaunchKernelGGL(sample_kernel, dim3(grid_blocks(a.n_elems)), dim3(kSampleThreads), shmem, stream, a);
+  const size_t shmem = (size_t)n * sizeof(int);
+  hipLaunchKernelGGL(sample_kernel, dim3(grid_blocks(a.n_elems)), dim3(64), shmem, stream, a);
   return hipGetLastError();
 }
 
@@ -1204,7 +1239,7 @@ hipError_t launch_children(const ChildArgs& a, hipStream_t stream) {
   if (a.n_elems <= 0) return hipSuccess;
   const int n = 1 << a.b;
   const size_t shmem = (size_t)3 * n * sizeof(int);
-  hipLaunchKernelGGL(children_kernel, dim3(grid_blocks(a.n_elems)), dim3(kSampleThreads), shmem, stream, a);
+  hipLaunchKernelGGL(children_kernel, dim3(grid_blocks(a.n_elems)), dim3(64), shmem, stream, a);
   return hipGetLastError();
 }
 
