@@ -23,7 +23,7 @@ HBM_PEAK_GBS = 8000.0
 FP32_MFMA_PEAK_TFLOPS = 157.3
 BF16_MFMA_PEAK_TFLOPS = 2500.0
 # the join kernel version that profiles/join_traffic.txt must name to be used
-JOIN_KERNEL_TAG = "qform_mfma_kernel<32> folded blocks"
+JOIN_KERNEL_TAG = "qform_mfma_kernel<32,4> bilinear slots"
 
 
 def cpu_baseline(wl, kr, budget_s=20.0):
@@ -142,9 +142,10 @@ def main():
     peak = FP32_MFMA_PEAK_TFLOPS if args.precision == "c64" else BF16_MFMA_PEAK_TFLOPS
     roofline = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                 "frac": achieved / peak, "traffic": traffic if args.precision == "c64" else None,
-                "kernel": "qform_mfma_kernel<32> (doubled-network join as a folded real quadratic form, FP32 MFMA)"
-                          if args.precision == "c64" else "qform_split_bf16_kernel (doubled-network join, bf16x3 MFMA)",
-                "flops": "folded real quadratic form: 2*256*NB(NB+1)/2 + 4K per row and x (K=32, NB=4: 5248; "
+                "kernel": "qform_mfma_kernel<32,4> (doubled-network join as a real GEMM over K^2 folded slots, "
+                          "FP32 MFMA)" if args.precision == "c64"
+                          else "qform_split_bf16_kernel (doubled-network join, bf16x3 MFMA)",
+                "flops": "real bilinear form over K^2 folded slots: 2K^2 per row and x (K=32: 2048; "
                          "the plain complex product would be 8320)",
                 "launches": prof["join_launches"], "kernel_ms_per_step": prof["join_ms"] / args.steps}
     line = {

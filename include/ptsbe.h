@@ -160,10 +160,9 @@ typedef struct {
   double flops_per_traj;        /* algorithmic real flops, per-trajectory part   */
   double flops_per_elem;        /* per element: left sweep + join                */
   double join_flops_per_elem;   /* join only; for a doubled batch on the MFMA
-                                   join (K = 16, 32) the flops of the folded real
-                                   quadratic form: per row and x, 2 per entry of
-                                   its NB(NB+1)/2 blocks of 16 x 16 (NB = 2K/16)
-                                   plus 4K                                       */
+                                   join (K = 16, 32) the flops of the real
+                                   bilinear form over K^2 folded slots: 2 K^2 per
+                                   row and x                                     */
   double bytes_per_traj;        /* algorithmic HBM bytes of the per-traj part    */
 } ptsbe_batch_info_t;
 

@@ -102,7 +102,7 @@ size_t join_traj_bytes(const ptsbe::BatchPlan& bp) {
   const int lkb = (int)bp.lk.size();
   size_t layout = (size_t)8 << bp.right.labels.size();
   if (bp.doubled && ptsbe::qform_supported(lkb))
-    layout = std::max(layout, ptsbe::qform_fold_bytes((int)bp.xT.size(), lkb));
+    layout = std::max(layout, ptsbe::qform_theta_bytes((int)bp.xT.size(), lkb));
   return ((size_t)8 << bp.right.labels.size()) + layout + part_scratch_per_job(bp.right);
 }
 
@@ -215,7 +215,7 @@ ptsbe_status_t run_batch(Plan& p, int j, const uint8_t* d_kraus, const float2* m
   const bool use_mfma = use_qform || use_ket;
   const bool use_split = use_qform && p.precision == PTSBE_SPLIT_BF16 && ptsbe::qform_split_supported(lkb);
   const bool use_fold = use_qform && !use_split;
-  const size_t layout_bytes = use_fold ? ptsbe::qform_fold_bytes((int)bp.xT.size(), lkb)
+  const size_t layout_bytes = use_fold ? ptsbe::qform_theta_bytes((int)bp.xT.size(), lkb)
                                        : (use_mfma ? ((size_t)8 << rT) : 0);
   const size_t per_traj = ((size_t)8 << rT) + layout_bytes + part_scratch_per_job(bp.right);
   const size_t nb = (size_t)1 << bp.size;
@@ -240,12 +240,12 @@ ptsbe_status_t run_batch(Plan& p, int j, const uint8_t* d_kraus, const float2* m
                                  ptsbe::InitArgs(), T, ar, s);
     if (st != PTSBE_OK) return st;
     float2* Tc = nullptr;
-    float4* Uf = nullptr;
-    if (use_fold) {   // folded quadratic-form blocks for the FP32 MFMA doubled join
-      Uf = (float4*)ar.take((size_t)(t1 - t0) * layout_bytes);
-      if (!Uf) return fail(PTSBE_ERR_OUT_OF_MEMORY, "workspace too small (join layout)");
-      HIP_TRY(ptsbe::launch_fold_T(T, (int64_t)1 << rT, t1 - t0, p.d_tables, p.join_dev[j], (int)bp.xT.size(), lkb,
-                                   Uf, s));
+    float* Th = nullptr;
+    if (use_fold) {   // Theta (folded bilinear-form coefficients) for the FP32 MFMA doubled join
+      Th = (float*)ar.take((size_t)(t1 - t0) * layout_bytes);
+      if (!Th) return fail(PTSBE_ERR_OUT_OF_MEMORY, "workspace too small (join layout)");
+      HIP_TRY(ptsbe::launch_theta_T(T, (int64_t)1 << rT, t1 - t0, p.d_tables, p.join_dev[j], (int)bp.xT.size(),
+                                    lkb, Th, s));
     } else if (use_mfma) {   // canonical [x][k][k'] (split doubled) or [x][k] (ket) layout
       Tc = (float2*)ar.take((size_t)(t1 - t0) * layout_bytes);
       if (!Tc) return fail(PTSBE_ERR_OUT_OF_MEMORY, "workspace too small (join layout)");
@@ -293,7 +293,7 @@ ptsbe_status_t run_batch(Plan& p, int j, const uint8_t* d_kraus, const float2* m
       if (use_mfma) {
         ptsbe::QformArgs qa{};
         qa.V = V; qa.v_stride = (int64_t)1 << rV; qa.v_base = a0;
-        qa.Tc = Tc; qa.Uf = Uf; qa.traj_base = (int32_t)t0;
+        qa.Tc = Tc; qa.Th = Th; qa.traj_base = (int32_t)t0;
         int64_t tA = t0, tB = t1 - 1;
         while (tA + 1 < t1 && first[tA + 1] <= a0) ++tA;     // trajectory holding element a0
         while (tB > tA && first[tB] >= a1) --tB;             // trajectory holding element a1-1

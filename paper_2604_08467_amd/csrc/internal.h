@@ -273,7 +273,7 @@ hipError_t launch_join(const JoinArgs& a, hipStream_t stream);
 struct QformArgs {
   const float2* V; int64_t v_stride; int64_t v_base;   // V rows of elements [v_base, ...)
   const float2* Tc;                                     // canonical [traj][x][k][k'] (split join, ket join)
-  const float4* Uf;                                     // folded blocks [traj][x][blk][64] (FP32 doubled join)
+  const float* Th;                                      // Theta [traj][x][K^2] (FP32 doubled join)
   int32_t traj_base;                                    // Tc index = traj - traj_base
   int32_t traj0;                                        // trajectory of grid.y == 0
   const int32_t* first;                                 // [E+1] first element of each trajectory
@@ -287,10 +287,10 @@ hipError_t launch_permute_T(const float2* T, int64_t t_stride, int64_t n_traj, c
                             const Plan::JoinDev& jd, int xT_bits, int lk_bits, int lb_bits, float2* Tc,
                             hipStream_t stream);
 bool qform_supported(int lk_bits);
-// folded block layout of the doubled join (FP32 MFMA path): bytes per trajectory
-size_t qform_fold_bytes(int xT_bits, int lk_bits);
-hipError_t launch_fold_T(const float2* T, int64_t t_stride, int64_t n_traj, const int64_t* tab,
-                         const Plan::JoinDev& jd, int xT_bits, int lk_bits, float4* Uf, hipStream_t stream);
+// Theta layout of the doubled join (FP32 MFMA path): bytes per trajectory
+size_t qform_theta_bytes(int xT_bits, int lk_bits);
+hipError_t launch_theta_T(const float2* T, int64_t t_stride, int64_t n_traj, const int64_t* tab,
+                          const Plan::JoinDev& jd, int xT_bits, int lk_bits, float* Th, hipStream_t stream);
 bool ketjoin_supported(int lk_bits);
 bool qform_split_supported(int lk_bits);
 // split-precision (bf16 hi + lo, three products, FP32 accumulate) doubled join

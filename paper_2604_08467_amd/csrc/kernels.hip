@@ -527,29 +527,27 @@ __global__ void __launch_bounds__(256) ketjoin_mfma_kernel(QformArgs a) {
   }
 }
 
-// MFMA join of the doubled network (Sec. II-B marginals).  The population of
-// element row v (one row of V, K = 2^lk_bits complex entries) at batch value x is
-//   pi = Re sum_{k,k'} v[k] Tc[x][k][k'] conj(v[k']).
-// With w = [Re v ; Im v] (2K reals) and T = Tr + i Ti this is the real quadratic
-// form pi = w^T G w, G = [[Tr, Ti], [-Ti, Tr]].  A quadratic form only depends on
-// the symmetric part of its matrix, so cutting G into 16 x 16 blocks G_IJ
-// (NB = 2K / 16 block rows) gives pi = sum_{I <= J} w_I^T U_IJ w_J with
-// U_II = G_II and U_IJ = G_IJ + G_JI^T for I < J: NB (NB + 1) / 2 block products
-// instead of the NB^2 of the plain complex product (10 instead of 16 for K = 32).
-// The identity is exact; it does not assume that T is Hermitian.
+// MFMA join of the doubled network (Sec. II-B marginals) as one real GEMM.  For
+// an element row v (K = 2^lk_bits complex entries) and T = Tc[x] (K x K,
+// rows k, columns k'), the population pi = Re sum_{a,b} v_a T_ab conj(v_b) is
+// a real bilinear form in the products v_a conj(v_b).  Folding each unordered
+// pair {a, b} (Re(v_a conj v_b) is symmetric, Im antisymmetric) leaves exactly
+// K^2 terms, one per slot f = a K + b:
+//   a == b:  M_f = |v_a|^2,              Theta_f = Re T_aa
+//   a <  b:  M_f = Re(v_a conj v_b),     Theta_f = Re T_ab + Re T_ba
+//   a >  b:  M_f = Im(v_b conj v_a),     Theta_f = Im T_ab - Im T_ba
+// and pi = sum_f M_f(v) Theta_f(T) exactly (T need not be Hermitian).  The
+// populations of a tile of rows and a tile of x values are the real product
+// M Theta with inner dimension K^2: 2 K^2 flops per row and x, against 8 K^2
+// for the complex product followed by the second contraction.
 //
-// fold_T_kernel writes, per trajectory and x, the blocks in the order
-// blk = J (J + 1) / 2 + I (I <= J), each as 64 float4 in MFMA fragment order:
-// float4 number L holds U_IJ[4 s + L / 16][L % 16] for s = 0..3, the B operand
-// of lane L at k-step s of v_mfma_f32_16x16x4f32.
-// One workgroup per (trajectory, x): T[x] is gathered once into LDS through the
-// plan's tables, then the workgroup writes the folded blocks of that x as
-// contiguous float4.
+// theta_T_kernel: one workgroup per (trajectory, x) gathers T[x] into LDS through
+// the plan's tables and writes Theta[traj][x][f] (f contiguous).
 template <int K>
-__global__ void __launch_bounds__(256) fold_T_kernel(const float2* __restrict__ T, int64_t t_stride, int64_t n_traj,
-                                                      const int64_t* __restrict__ tables, Plan::JoinDev jd,
-                                                      int xT_bits, float4* __restrict__ Uf) {
-  constexpr int NB = K / 8, NBLK = NB * (NB + 1) / 2, F4 = NBLK * 64, KK = K * K, PERT = KK / 256;
+__global__ void __launch_bounds__(256) theta_T_kernel(const float2* __restrict__ T, int64_t t_stride, int64_t n_traj,
+                                                       const int64_t* __restrict__ tables, Plan::JoinDev jd,
+                                                       int xT_bits, float* __restrict__ Th) {
+  constexpr int KK = K * K, PERT = KK / 256;
   constexpr int LK = K == 16 ? 4 : 5;
   static_assert(KK % 256 == 0, "K = 16 or 32");
   __shared__ float2 Ts[K][K + 1];
@@ -562,12 +560,6 @@ __global__ void __launch_bounds__(256) fold_T_kernel(const float2* __restrict__ 
     koff[i] = tab(tables, jd.tk_lo, jd.tk_hi, LK, (uint32_t)(idx / K)) +
               tab(tables, jd.tb_lo, jd.tb_hi, LK, (uint32_t)(idx % K));
   }
-  // entry (i, j) of G, i, j in [0, 2K)
-  auto G = [&](int i, int j) -> float {
-    const float2 v = Ts[i & (K - 1)][j & (K - 1)];
-    if (i < K) return j < K ? v.x : v.y;
-    return j < K ? -v.y : v.x;
-  };
   const int64_t nx = (int64_t)1 << xT_bits;
   for (int64_t g = blockIdx.x; g < n_traj * nx; g += gridDim.x) {
     const int64_t t = g >> xT_bits;
@@ -579,49 +571,47 @@ __global__ void __launch_bounds__(256) fold_T_kernel(const float2* __restrict__ 
       Ts[idx / K][idx % K] = Tx[koff[i]];
     }
     __syncthreads();
-    float4* out = Uf + g * F4;
-    for (int f = tid; f < F4; f += 256) {
-      const int L = f & 63, blk = f >> 6;
-      int J = 0;
-      while ((J + 1) * (J + 2) / 2 <= blk) ++J;
-      const int I = blk - J * (J + 1) / 2;
-      float u[4];
+    float* out = Th + g * KK;
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const int i = 16 * I + 4 * s + (L >> 4), j = 16 * J + (L & 15);
-        u[s] = G(i, j) + (I < J ? G(j, i) : 0.f);
-      }
-      out[f] = make_float4(u[0], u[1], u[2], u[3]);
+    for (int i = 0; i < PERT; ++i) {
+      const int f = tid + 256 * i;
+      const int a = f / K, b = f % K;
+      float th;
+      if (a == b) th = Ts[a][a].x;
+      else if (a < b) th = Ts[a][b].x + Ts[b][a].x;
+      else th = Ts[a][b].y - Ts[b][a].y;
+      out[f] = th;
     }
     __syncthreads();
   }
 }
 
-// One workgroup = 4 wavefronts = 64 rows of one trajectory (16 rows per wave);
-// it walks a range of x, double-buffering the folded blocks of x + 1 in LDS
-// while the MFMAs of x run.  For each block column J the products w_I U_IJ
-// (I <= J) accumulate in one 16 x 16 tile, which is then dotted with w_J.
-template <int K>
+// One workgroup = 4 wavefronts = 64 rows of one trajectory (16 per wave) x a tile
+// of XT = 16 NC values of x.  The inner dimension runs in chunks of 32 slots:
+// Theta[x][chunk] is staged in LDS in MFMA fragment order (double-buffered, the
+// next chunk in flight during the MFMAs), and each lane builds its A operand
+// M_f(row) on the fly from the row's V entries (for K = 32 the chunk fixes a and
+// the lane's b runs over 8 values it keeps in registers).  Output: v_mfma
+// accumulators hold pi[row][x] directly.
+template <int K, int NC>
 __global__ void __launch_bounds__(256) qform_mfma_kernel(QformArgs a) {
-  constexpr int ROWS = 64;
-  constexpr int NB = K / 8;                    // 16-wide block rows of the 2K reals
-  constexpr int NBLK = NB * (NB + 1) / 2;
-  constexpr int F4 = NBLK * 64;                // float4 per x
-  constexpr int PER = (F4 + 255) / 256;
-  __shared__ float4 Ub[2][F4];
+  constexpr int ROWS = 64, KK = K * K, KC = 32, NS = KC / 4, XT = 16 * NC, NCH = KK / KC, KB = K / 4;
+  constexpr int F4C = KC * XT / 4;              // float4 of Theta per chunk
+  static_assert(F4C <= 512, "two float4 per thread at most");
+  __shared__ float Thl[2][KC * XT];
   __shared__ float2 Vs[ROWS][K + 1];
   // Workgroups go round-robin to the 8 XCDs in linear launch order; renumber them
-  // so that consecutive logical tiles (the row tiles of one trajectory, which all
-  // read that trajectory's blocks) run on the same XCD and share its L2.
+  // so that consecutive logical tiles (the x tiles, then the row tiles of one
+  // trajectory, which share its Theta and V) run on the same XCD and share its L2.
   uint32_t bx, by, bz;
   {
-    const uint32_t nbx = gridDim.x, nby = gridDim.y, total = nbx * nby * gridDim.z;
+    const uint32_t nbx = gridDim.x, nby = gridDim.y, nbz = gridDim.z, total = nbx * nby * nbz;
     const uint32_t phys = blockIdx.x + nbx * (blockIdx.y + nby * blockIdx.z);
     const uint32_t xcd = phys % 8u, slot = phys / 8u, q = total / 8u, r = total % 8u;
     const uint32_t logical = xcd < r ? xcd * (q + 1) + slot : r * (q + 1) + (xcd - r) * q + slot;
-    bx = logical % nbx;
-    by = (logical / nbx) % nby;
-    bz = logical / (nbx * nby);
+    bz = logical % nbz;
+    bx = (logical / nbz) % nbx;
+    by = logical / (nbz * nbx);
   }
   const int t = a.traj0 + (int)by;                    // trajectory of this tile
   const int64_t e_begin = a.first[t] > a.e_lo ? a.first[t] : a.e_lo;
@@ -631,10 +621,9 @@ __global__ void __launch_bounds__(256) qform_mfma_kernel(QformArgs a) {
   const int64_t row0 = (int64_t)bx * ROWS;
   if (row0 >= rows_t) return;
   const int nx = 1 << a.xT_bits;
-  const int x_per = (nx + gridDim.z - 1) / gridDim.z;
-  const int x_begin = (int)bz * x_per;
-  const int x_end = x_begin + x_per < nx ? x_begin + x_per : nx;
-  if (x_begin >= x_end) return;
+  const int x0 = (int)bz * XT;
+  if (x0 >= nx) return;
+  const int xv = nx - x0 < XT ? nx - x0 : XT;         // valid x of this tile
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lo_b = xb_bits < 12 ? xb_bits : 12, lo_k = a.lk_bits < 12 ? a.lk_bits : 12;
   // stage the 64 rows of V (zero beyond the trajectory's rows)
@@ -650,39 +639,38 @@ __global__ void __launch_bounds__(256) qform_mfma_kernel(QformArgs a) {
     }
     Vs[rr][k] = v;
   }
-  const float4* Ut = a.Uf + (int64_t)(t - a.traj_base) * ((int64_t)nx * F4);
+  // Theta chunk loader: float4 number idx holds slots 4s..4s+3 of the chunk at
+  // x = x0 + idx % XT (s = idx / XT); in LDS slot 4s + q of x = x0 + 16c + j sits
+  // at ((s * 64 + 16 q + j) * NC + c), the B operand of lane 16 q + j at k-step s.
+  const float* Tt = a.Th + ((int64_t)(t - a.traj_base) * nx + x0) * KK;
+  const int i0 = tid, i1 = tid + 256;
+  const bool h0 = i0 < F4C, h1 = i1 < F4C;
+  const int xl0 = i0 % XT, s0 = (i0 / XT) % NS, xl1 = i1 % XT, s1 = (i1 / XT) % NS;
+  const bool v0 = h0 && xl0 < xv, v1 = h1 && xl1 < xv;
+  auto ld = [&](int ch, int xl, int s, bool ok) -> float4 {
+    return ok ? *reinterpret_cast<const float4*>(Tt + (int64_t)xl * KK + ch * KC + 4 * s)
+              : make_float4(0.f, 0.f, 0.f, 0.f);
+  };
+  auto st = [&](float* d, int xl, int s, float4 v) {
+    float* p = d + (s * 64 + (xl & 15)) * NC + (xl >> 4);
+    p[0] = v.x; p[16 * NC] = v.y; p[32 * NC] = v.z; p[48 * NC] = v.w;
+  };
   {
-    const float4* src = Ut + (int64_t)x_begin * F4;
-    for (int idx = tid; idx < F4; idx += 256) Ub[0][idx] = src[idx];
+    const float4 r0 = ld(0, xl0, s0, v0), r1 = ld(0, xl1, s1, v1);
+    if (h0) st(Thl[0], xl0, s0, r0);
+    if (h1) st(Thl[0], xl1, s1, r1);
   }
   __syncthreads();
-  // A fragments: wa[I][s] = w[wave*16 + lane%16][16 I + 4 s + lane/16];
-  // epilogue weights: we[J][i] = w[wave*16 + 4 (lane/16) + i][16 J + lane%16]
-  float wa[NB][4], we[NB][4];
-  {
-    const int arow = wave * 16 + (lane & 15);
+  // per lane: row rl, slot offset q; vb[i] = v[rl][4 i + q]
+  const int rl = wave * 16 + (lane & 15), q = lane >> 4;
+  float2 vb[KB];
 #pragma unroll
-    for (int I = 0; I < NB; ++I)
-#pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const float2 v = Vs[arow][(16 * I + 4 * s + (lane >> 4)) & (K - 1)];
-        wa[I][s] = 16 * I < K ? v.x : v.y;
-      }
-#pragma unroll
-    for (int J = 0; J < NB; ++J)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const float2 v = Vs[wave * 16 + 4 * (lane >> 4) + i][(16 * J + (lane & 15)) & (K - 1)];
-        we[J][i] = 16 * J < K ? v.x : v.y;
-      }
-  }
+  for (int i = 0; i < KB; ++i) vb[i] = Vs[rl][4 * i + q];
   const int nout = 1 << a.b;
-  const int lo_x = a.xT_bits < 12 ? a.xT_bits : 12;
-  // output offsets of the lane's 4 rows (without the x part), -1 past the rows
   int64_t obase[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    const int64_t row = row0 + wave * 16 + 4 * (lane >> 4) + i;
+    const int64_t row = row0 + wave * 16 + 4 * q + i;
     obase[i] = -1;
     if (row < rows_t) {
       const int64_t e = e_begin + (row >> xb_bits);
@@ -690,55 +678,58 @@ __global__ void __launch_bounds__(256) qform_mfma_kernel(QformArgs a) {
       obase[i] = (e - a.v_base) * nout + tab(a.tab, a.jd.ob_lo, a.jd.ob_hi, lo_b, xb);
     }
   }
-  int buf = 0;
-  for (int x = x_begin; x < x_end; ++x) {
-    const bool more = x + 1 < x_end;
-    const int64_t ox = tab(a.tab, a.jd.ox_lo, a.jd.ox_hi, lo_x, (uint32_t)x);   // uniform
-    // next blocks in flight during the MFMAs (every lane loads, at clamped in-bounds
-    // indexes; the last x reloads its own blocks, which are not stored)
-    static_assert(PER <= 3, "at most three float4 per thread per x");
-    const float4* src = Ut + (int64_t)(more ? x + 1 : x) * F4;
-    const float4 nx0 = src[tid < F4 ? tid : F4 - 1];
-    const float4 nx1 = src[PER > 1 && tid + 256 < F4 ? tid + 256 : F4 - 1];
-    const float4 nx2 = src[PER > 2 && tid + 512 < F4 ? tid + 512 : F4 - 1];
-    __builtin_amdgcn_sched_barrier(0);            // keep the loads ahead of the MFMAs
-    float p[4] = {0.f, 0.f, 0.f, 0.f};
+  floatx4 acc[NC];
 #pragma unroll
-    for (int J = 0; J < NB; ++J) {
-      floatx4 y = {0.f, 0.f, 0.f, 0.f};
+  for (int c = 0; c < NC; ++c) acc[c] = floatx4{0.f, 0.f, 0.f, 0.f};
+  for (int ch = 0; ch < NCH; ++ch) {
+    const int buf = ch & 1;
+    const bool more = ch + 1 < NCH;
+    const int cn = more ? ch + 1 : ch;            // the last chunk reloads itself (not stored)
+    const float4 r0 = ld(cn, xl0, s0, v0), r1 = ld(cn, xl1, s1, v1);
+    __builtin_amdgcn_sched_barrier(0);          // keep the loads ahead of the MFMAs
+    const float* B = Thl[buf];
 #pragma unroll
-      for (int I = 0; I <= J; ++I) {
-        const float4 bq = Ub[buf][(J * (J + 1) / 2 + I) * 64 + lane];
-        y = __builtin_amdgcn_mfma_f32_16x16x4f32(wa[I][0], bq.x, y, 0, 0, 0);
-        y = __builtin_amdgcn_mfma_f32_16x16x4f32(wa[I][1], bq.y, y, 0, 0, 0);
-        y = __builtin_amdgcn_mfma_f32_16x16x4f32(wa[I][2], bq.z, y, 0, 0, 0);
-        y = __builtin_amdgcn_mfma_f32_16x16x4f32(wa[I][3], bq.w, y, 0, 0, 0);
+    for (int s = 0; s < NS; ++s) {
+      const int kstep = ch * NS + s;
+      const int av = (4 * kstep) / K;               // the slot's a: uniform
+      const int ib = s % KB;                         // kstep % KB: static
+      const int b = 4 * ib + q;
+      const float2 va = Vs[rl][av];
+      const float2 w = vb[ib];
+      const float R = va.x * w.x + va.y * w.y;       // Re(v_a conj v_b)
+      const float I = w.y * va.x - w.x * va.y;       // Im(v_b conj v_a)
+      const float m = av <= b ? R : I;
+      if constexpr (NC == 4) {
+        const float4 bq = *reinterpret_cast<const float4*>(B + (s * 64 + lane) * 4);
+        acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(m, bq.x, acc[0], 0, 0, 0);
+        acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(m, bq.y, acc[1], 0, 0, 0);
+        acc[2] = __builtin_amdgcn_mfma_f32_16x16x4f32(m, bq.z, acc[2], 0, 0, 0);
+        acc[3] = __builtin_amdgcn_mfma_f32_16x16x4f32(m, bq.w, acc[3], 0, 0, 0);
+      } else if constexpr (NC == 2) {
+        const float2 bq = *reinterpret_cast<const float2*>(B + (s * 64 + lane) * 2);
+        acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(m, bq.x, acc[0], 0, 0, 0);
+        acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(m, bq.y, acc[1], 0, 0, 0);
+      } else {
+        acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(m, B[s * 64 + lane], acc[0], 0, 0, 0);
       }
-#pragma unroll
-      for (int i = 0; i < 4; ++i) p[i] += y[i] * we[J][i];
-    }
-    // reduce over the 16 lanes that share lane/16
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      float v = p[i];
-      v += __shfl_xor(v, 1);
-      v += __shfl_xor(v, 2);
-      v += __shfl_xor(v, 4);
-      v += __shfl_xor(v, 8);
-      p[i] = v;
-    }
-    if ((lane & 15) == 0) {
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-        if (obase[i] >= 0) a.pop[obase[i] + ox] = p[i];
     }
     if (more) {
-      if (tid < F4) Ub[buf ^ 1][tid] = nx0;
-      if (PER > 1 && tid + 256 < F4) Ub[buf ^ 1][tid + 256] = nx1;
-      if (PER > 2 && tid + 512 < F4) Ub[buf ^ 1][tid + 512] = nx2;
+      if (h0) st(Thl[buf ^ 1], xl0, s0, r0);
+      if (h1) st(Thl[buf ^ 1], xl1, s1, r1);
     }
     __syncthreads();
-    buf ^= 1;
+  }
+  // acc[c][i] = pi[row wave*16 + 4 q + i][x0 + 16 c + lane % 16]
+  const int lo_x = a.xT_bits < 12 ? a.xT_bits : 12;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const int xl = 16 * c + (lane & 15);
+    if (xl < xv) {
+      const int64_t ox = tab(a.tab, a.jd.ox_lo, a.jd.ox_hi, lo_x, (uint32_t)(x0 + xl));
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (obase[i] >= 0) a.pop[obase[i] + ox] = acc[c][i];
+    }
   }
 }
 
@@ -1170,20 +1161,17 @@ hipError_t launch_qform_split(const QformArgs& a, int n_traj, int max_rows, hipS
 }
 bool ketjoin_supported(int lk_bits) { return lk_bits >= 2 && lk_bits <= 6; }
 
-size_t qform_fold_bytes(int xT_bits, int lk_bits) {
-  const size_t nb = (size_t)1 << (lk_bits - 3);
-  return (nb * (nb + 1) / 2) * 1024 << xT_bits;
-}
+size_t qform_theta_bytes(int xT_bits, int lk_bits) { return (size_t)4 << (xT_bits + 2 * lk_bits); }
 
-hipError_t launch_fold_T(const float2* T, int64_t t_stride, int64_t n_traj, const int64_t* tab,
-                         const Plan::JoinDev& jd, int xT_bits, int lk_bits, float4* Uf, hipStream_t stream) {
+hipError_t launch_theta_T(const float2* T, int64_t t_stride, int64_t n_traj, const int64_t* tab,
+                          const Plan::JoinDev& jd, int xT_bits, int lk_bits, float* Th, hipStream_t stream) {
   if (n_traj <= 0) return hipSuccess;
   if (!qform_supported(lk_bits)) return hipErrorInvalidValue;
   const dim3 grid(grid_blocks(n_traj << xT_bits));
   if (lk_bits == 4)
-    hipLaunchKernelGGL(fold_T_kernel<16>, grid, dim3(256), 0, stream, T, t_stride, n_traj, tab, jd, xT_bits, Uf);
+    hipLaunchKernelGGL(theta_T_kernel<16>, grid, dim3(256), 0, stream, T, t_stride, n_traj, tab, jd, xT_bits, Th);
   else
-    hipLaunchKernelGGL(fold_T_kernel<32>, grid, dim3(256), 0, stream, T, t_stride, n_traj, tab, jd, xT_bits, Uf);
+    hipLaunchKernelGGL(theta_T_kernel<32>, grid, dim3(256), 0, stream, T, t_stride, n_traj, tab, jd, xT_bits, Th);
   return hipGetLastError();
 }
 
@@ -1191,14 +1179,18 @@ hipError_t launch_qform(const QformArgs& a, int n_traj, int max_rows, hipStream_
   if (n_traj <= 0 || max_rows <= 0) return hipSuccess;
   const int tiles = (max_rows + 63) / 64;
   const int nx = 1 << a.xT_bits;
-  // split x so that every CU gets work even when rows are few
-  int64_t wg = (int64_t)tiles * n_traj;
-  int zs = 1;
-  while (zs < nx && wg * zs < 4096) zs *= 2;
-  dim3 grid((unsigned)tiles, (unsigned)n_traj, (unsigned)zs);
-  if (a.lk_bits == 4) hipLaunchKernelGGL(qform_mfma_kernel<16>, grid, dim3(256), 0, stream, a);
-  else if (a.lk_bits == 5) hipLaunchKernelGGL(qform_mfma_kernel<32>, grid, dim3(256), 0, stream, a);
-  else return hipErrorInvalidValue;
+  const int nc = nx >= 64 ? 4 : (nx >= 32 ? 2 : 1);
+  const int xtiles = (nx + 16 * nc - 1) / (16 * nc);
+  dim3 grid((unsigned)tiles, (unsigned)n_traj, (unsigned)xtiles);
+#define PTSBE_QFORM(KV, NCV) hipLaunchKernelGGL((qform_mfma_kernel<KV, NCV>), grid, dim3(256), 0, stream, a)
+  if (a.lk_bits == 4) {
+    if (nc == 4) PTSBE_QFORM(16, 4); else if (nc == 2) PTSBE_QFORM(16, 2); else PTSBE_QFORM(16, 1);
+  } else if (a.lk_bits == 5) {
+    if (nc == 4) PTSBE_QFORM(32, 4); else if (nc == 2) PTSBE_QFORM(32, 2); else PTSBE_QFORM(32, 1);
+  } else {
+    return hipErrorInvalidValue;
+  }
+#undef PTSBE_QFORM
   return hipGetLastError();
 }
 

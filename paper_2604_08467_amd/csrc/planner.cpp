@@ -479,11 +479,9 @@ bool build_batch_plans(Plan& p, std::string& err) {
     double K = std::ldexp(1.0, (int)bp.lk.size());
     double X = std::ldexp(1.0, (int)bp.xT.size());
     if (bp.doubled && qform_supported((int)bp.lk.size())) {
-      // MFMA join: the folded real quadratic form, 2 flops per entry of its
-      // NB (NB + 1) / 2 blocks of 16 x 16 (NB = 2K / 16) and 2 per term of the
-      // closing dot over the 2K reals, per row and x
-      const double nb = 2.0 * K / 16.0;
-      bp.join_flops_per_elem = rows * X * (2.0 * 256.0 * nb * (nb + 1.0) / 2.0 + 4.0 * K);
+      // MFMA join: the real bilinear form over K^2 folded slots, 2 flops per
+      // slot, per row and x
+      bp.join_flops_per_elem = rows * X * 2.0 * K * K;
     } else {
       bp.join_flops_per_elem = bp.doubled ? rows * X * (8.0 * K * K + 8.0 * K) : rows * X * 8.0 * K;
     }

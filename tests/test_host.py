@@ -57,16 +57,16 @@ def test_host_plan_shapes(make):
 
 def test_config2_path_is_the_expected_sweep():
     """1D depth-6 brickwork: five wires cross between the prefix part and the rest,
-    the per-trajectory tensor is 2^9 x 2^5 x 2^5 and the join, evaluated as the
-    folded real quadratic form (10 blocks of 16 x 16 for K = 32), costs 5.37 MFLOP
-    per element (the plain complex product would cost 8.52)."""
+    the per-trajectory tensor is 2^9 x 2^5 x 2^5 and the join, evaluated as a real
+    bilinear form over K^2 = 1024 folded slots, costs 2.10 MFLOP per element (the
+    plain complex product would cost 8.52)."""
     P = _lib()
     wl = W.config2()
     plan = P.Plan(wl.circuit, wl.batch_sizes, hypersamples=4, device=-1)
     for j in (1, 2, 3):
         bi = plan.batch_info(j)
         assert bi["crossing"] == 5 and bi["right_rank"] == 19 and bi["left_rank"] == 6
-        assert bi["join_flops_per_elem"] == 2 * 512 * (2 * 256 * 10 + 4 * 32)
+        assert bi["join_flops_per_elem"] == 2 * 512 * 2 * 32 * 32
 
 
 @pytest.mark.parametrize("which", ["config1", "config2", "ad_2q", "exhaust"])
