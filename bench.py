@@ -128,6 +128,8 @@ def main():
     prof = plan.profile_read()
     plan.profile_enable(False)
     shots_per_s = M * args.steps / dt
+    print(f"right-part sweep steps in HBM: {prof['sweep_bytes'] / args.steps / 1e9:.2f} GB per step (algorithmic)",
+          file=sys.stderr)
     epb = [int(x) for x in out["elements_per_batch"]]
 
     join_s = prof["join_ms"] / 1e3

@@ -164,12 +164,23 @@ typedef struct {
                                    bilinear form over K^2 folded slots: 2 K^2 per
                                    row and x                                     */
   double bytes_per_traj;        /* algorithmic HBM bytes of the per-traj part    */
+  int32_t n_right_launches;     /* launches of the per-trajectory part: fused
+                                   in-place runs + single steps in HBM (0 when it
+                                   runs as one LDS sweep)                        */
+  int32_t n_right_fused_steps;  /* per-trajectory steps inside fused in-place runs */
+  int32_t right_longest_run;    /* steps of the longest fused run                */
 } ptsbe_batch_info_t;
 
 ptsbe_status_t ptsbe_plan(const ptsbe_circuit_t* circuit, const ptsbe_plan_opts_t* opts,
                           ptsbe_plan_t* out);
 ptsbe_status_t ptsbe_plan_query(ptsbe_plan_t plan, ptsbe_plan_info_t* out);
 ptsbe_status_t ptsbe_plan_batch_info(ptsbe_plan_t plan, int32_t j, ptsbe_batch_info_t* out);
+/* The noise sites whose Kraus choices enter the per-trajectory part of batch j:
+ * two trajectories that agree on these sites have the same per-trajectory tensor
+ * at batch j (network method).  sites (host, caller-owned, may be NULL): the
+ * ascending site ids, room for the circuit's site count; *n_sites_out: their
+ * number.  PTSBE_ERR_INVALID_ARG for a statevector plan or j out of range. */
+ptsbe_status_t ptsbe_plan_right_sites(ptsbe_plan_t plan, int32_t j, int32_t* sites, int32_t* n_sites_out);
 /* Statevector method: the gate schedule for windows of window_qubits (10, 11 or
  * 12) qubits, for inspection and tests.  Host outputs (caller-owned; any may be
  * NULL): gate_order [n_gates] gate indices in execution order (each gate once; a

@@ -135,6 +135,13 @@ class Plan:
         except Exception:
             pass
 
+    def right_sites(self, j):
+        """ptsbe_plan_right_sites: sites whose Kraus choices enter batch j's per-trajectory part."""
+        buf = np.zeros(max(self.n_sites, 1), dtype=np.int32)
+        n = C.c_int32()
+        _lib.check(self._lib.ptsbe_plan_right_sites(self._h, int(j), buf.ctypes.data_as(C.c_void_p), C.byref(n)))
+        return buf[:n.value].copy()
+
     def sv_schedule(self, window_qubits=12):
         """ptsbe_plan_sv_schedule: (gate order, window offsets, window qubit lists)."""
         G = self.n_gates

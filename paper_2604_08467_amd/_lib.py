@@ -17,7 +17,7 @@ EXPORTS = [
     "ptsbe_contract_batch", "ptsbe_sample_shots", "ptsbe_profile_enable", "ptsbe_profile_read",
     "ptsbe_expect_workspace_size", "ptsbe_expect_grad",
     "ptsbe_ragged_create", "ptsbe_ragged_destroy", "ptsbe_ragged_info", "ptsbe_ragged_workspace_size",
-    "ptsbe_ragged_autotune", "ptsbe_ragged_sample_shots", "ptsbe_plan_sv_schedule",
+    "ptsbe_ragged_autotune", "ptsbe_ragged_sample_shots", "ptsbe_plan_sv_schedule", "ptsbe_plan_right_sites",
 ]
 
 
@@ -64,6 +64,7 @@ class BatchInfo_t(C.Structure):
         ("join_rows_log2", C.c_int32), ("crossing", C.c_int32),
         ("flops_per_traj", C.c_double), ("flops_per_elem", C.c_double),
         ("join_flops_per_elem", C.c_double), ("bytes_per_traj", C.c_double),
+        ("n_right_launches", C.c_int32), ("n_right_fused_steps", C.c_int32), ("right_longest_run", C.c_int32),
     ]
 
 
@@ -93,6 +94,7 @@ def load():
     lib.ptsbe_plan_query.argtypes = [P, C.POINTER(PlanInfo_t)]
     lib.ptsbe_plan_batch_info.argtypes = [P, i32, C.POINTER(BatchInfo_t)]
     lib.ptsbe_plan_sv_schedule.argtypes = [P, i32, P, P, P, C.POINTER(i32)]
+    lib.ptsbe_plan_right_sites.argtypes = [P, i32, P, C.POINTER(i32)]
     lib.ptsbe_plan_destroy.argtypes = [P]
     lib.ptsbe_plan_destroy.restype = None
     lib.ptsbe_sample_trajectories.argtypes = [P, u64, i64, i64, P, P, P, C.POINTER(i64), C.POINTER(i64)]

@@ -143,15 +143,20 @@ ptsbe_status_t run_part(Plan& p, const ptsbe::PartPlan& pp, const ptsbe::AbsorbS
     h = sg.first + sg.count;
     ++s0;
   }
+  if (h < 2) s0 = 0;
+  // the last rank-changing step writes the output; in-place runs after it work on
+  // the output directly (no final copy)
+  size_t last_nf = nseg;
+  for (size_t si = s0; si < nseg; ++si)
+    if (!pp.segs[si].fused) last_nf = si;
+  float2* A = last_nf == nseg ? out : b0;
   if (h >= 2) {
-    HIP_TRY(ptsbe::launch_part_vm(d_steps, h, hpeak, g, n_jobs, job_traj, traj_base, job_prefix, p.NW, init, b0,
+    HIP_TRY(ptsbe::launch_part_vm(d_steps, h, hpeak, g, n_jobs, job_traj, traj_base, job_prefix, p.NW, init, A,
                                   pp.steps[(size_t)h - 1].rC, s));
   } else {
-    s0 = 0;
-    if (init.Vprev) HIP_TRY(ptsbe::launch_init_gather(init, n_jobs, job_prefix, p.NW, b0, s));
-    else HIP_TRY(ptsbe::launch_fill_one(b0, n_jobs, s));   // rank-0 start: the scalar 1 per job
+    if (init.Vprev) HIP_TRY(ptsbe::launch_init_gather(init, n_jobs, job_prefix, p.NW, A, s));
+    else HIP_TRY(ptsbe::launch_fill_one(A, n_jobs, s));   // rank-0 start: the scalar 1 per job
   }
-  float2* A = b0;
   for (size_t si = s0; si < nseg; ++si) {
     const ptsbe::Segment& sg = pp.segs[si];
     if (sg.fused) {   // a run of in-place steps, one tile pass, in place
@@ -160,7 +165,7 @@ ptsbe_status_t run_part(Plan& p, const ptsbe::PartPlan& pp, const ptsbe::AbsorbS
       continue;
     }
     const size_t i = (size_t)sg.first;
-    float2* C = (si + 1 == nseg) ? out : (A == b0 ? b1 : b0);
+    float2* C = (si == last_nf) ? out : (A == b0 ? b1 : b0);
     HIP_TRY(ptsbe::launch_absorb_global(pp.steps[i], d_steps + i, g, n_jobs, job_traj, traj_base, job_prefix,
                                         p.NW, A, C, s));
     A = C;
@@ -189,7 +194,22 @@ struct BatchIO {
   const float2* V_prev = nullptr;
   int64_t V_prev_stride = 1;
   const int32_t* parent = nullptr;
+  // host copy of the trajectories' Kraus indices [E][S]: trajectories that agree
+  // on the sites of a batch's per-trajectory part share its tensor (null: no sharing)
+  const uint8_t* h_kraus = nullptr;
 };
+
+// The noise sites whose Kraus choices enter the per-trajectory part of a batch.
+std::vector<int32_t> right_sites(const Plan& p, const ptsbe::BatchPlan& bp) {
+  std::vector<char> on((size_t)p.site_gate.size(), 0);
+  for (const ptsbe::AbsorbStep& st : bp.right.steps)
+    if (st.gate >= 0 && st.gate < p.n_user_gates)
+      for (int s : p.gate_sites[(size_t)st.gate]) on[(size_t)s] = 1;
+  std::vector<int32_t> out;
+  for (size_t s = 0; s < on.size(); ++s)
+    if (on[s]) out.push_back((int32_t)s);
+  return out;
+}
 
 struct EventPair { hipEvent_t a, b; };
 
@@ -229,27 +249,58 @@ ptsbe_status_t run_batch(Plan& p, int j, const uint8_t* d_kraus, const float2* m
   t_cap = std::min<int64_t>(t_cap, 65535);       // one grid dimension of the MFMA join
   const ptsbe::AbsorbStep* d_left = p.d_steps + p.part_step_off[3 * j + (io.resume ? 2 : 0)];
   const ptsbe::AbsorbStep* d_right = p.d_steps + p.part_step_off[3 * j + 1];
+  const std::vector<int32_t> rsites = io.h_kraus ? right_sites(p, bp) : std::vector<int32_t>();
+  const int64_t S = (int64_t)p.site_gate.size();
+  std::vector<std::vector<int32_t>> keep;         // host sources of async uploads
   for (int64_t t0 = 0; t0 < E; t0 += t_cap) {
     const int64_t t1 = std::min<int64_t>(E, t0 + t_cap);
     const int64_t e0 = first[t0], e1 = first[t1];
     if (e1 <= e0) continue;                       // no elements for these trajectories
     const size_t mark = ar.used;
-    float2* T = (float2*)ar.take((size_t)(t1 - t0) * ((size_t)8 << rT));
+    // one per-trajectory tensor per distinct Kraus pattern on the part's sites
+    int64_t n_rt = t1 - t0;
+    const int32_t* d_rjob = nullptr;              // trajectory of each right job (null: t0 + job)
+    const int32_t* d_slot = nullptr;              // right job of each trajectory (null: t - t0)
+    if (io.h_kraus && n_rt > 1) {
+      std::unordered_map<std::string, int32_t> seen;
+      std::vector<int32_t> reps, slot((size_t)n_rt);
+      std::string key(rsites.size(), '\0');
+      for (int64_t t = t0; t < t1; ++t) {
+        const uint8_t* kr = io.h_kraus + t * S;
+        for (size_t i = 0; i < rsites.size(); ++i) key[i] = (char)kr[rsites[i]];
+        auto it = seen.emplace(key, (int32_t)reps.size());
+        if (it.second) reps.push_back((int32_t)t);
+        slot[(size_t)(t - t0)] = it.first->second;
+      }
+      if ((int64_t)reps.size() < n_rt) {
+        n_rt = (int64_t)reps.size();
+        int32_t* dr = (int32_t*)ar.take(reps.size() * 4);
+        int32_t* ds = (int32_t*)ar.take(slot.size() * 4);
+        if (!dr || !ds) return fail(PTSBE_ERR_OUT_OF_MEMORY, "workspace too small (trajectory sharing)");
+        keep.push_back(std::move(reps));
+        HIP_TRY(hipMemcpyAsync(dr, keep.back().data(), keep.back().size() * 4, hipMemcpyHostToDevice, s));
+        keep.push_back(std::move(slot));
+        HIP_TRY(hipMemcpyAsync(ds, keep.back().data(), keep.back().size() * 4, hipMemcpyHostToDevice, s));
+        d_rjob = dr;
+        d_slot = ds;
+      }
+    }
+    float2* T = (float2*)ar.take((size_t)n_rt * ((size_t)8 << rT));
     if (!T) return fail(PTSBE_ERR_OUT_OF_MEMORY, "workspace too small (right part)");
-    ptsbe_status_t st = run_part(p, bp.right, d_right, g, t1 - t0, nullptr, (int32_t)t0, nullptr,
+    ptsbe_status_t st = run_part(p, bp.right, d_right, g, n_rt, d_rjob, (int32_t)t0, nullptr,
                                  ptsbe::InitArgs(), T, ar, s);
     if (st != PTSBE_OK) return st;
     float2* Tc = nullptr;
     float* Th = nullptr;
     if (use_fold) {   // Theta (folded bilinear-form coefficients) for the FP32 MFMA doubled join
-      Th = (float*)ar.take((size_t)(t1 - t0) * layout_bytes);
+      Th = (float*)ar.take((size_t)n_rt * layout_bytes);
       if (!Th) return fail(PTSBE_ERR_OUT_OF_MEMORY, "workspace too small (join layout)");
-      HIP_TRY(ptsbe::launch_theta_T(T, (int64_t)1 << rT, t1 - t0, p.d_tables, p.join_dev[j], (int)bp.xT.size(),
+      HIP_TRY(ptsbe::launch_theta_T(T, (int64_t)1 << rT, n_rt, p.d_tables, p.join_dev[j], (int)bp.xT.size(),
                                     lkb, Th, s));
     } else if (use_mfma) {   // canonical [x][k][k'] (split doubled) or [x][k] (ket) layout
-      Tc = (float2*)ar.take((size_t)(t1 - t0) * layout_bytes);
+      Tc = (float2*)ar.take((size_t)n_rt * layout_bytes);
       if (!Tc) return fail(PTSBE_ERR_OUT_OF_MEMORY, "workspace too small (join layout)");
-      HIP_TRY(ptsbe::launch_permute_T(T, (int64_t)1 << rT, t1 - t0, p.d_tables, p.join_dev[j], (int)bp.xT.size(),
+      HIP_TRY(ptsbe::launch_permute_T(T, (int64_t)1 << rT, n_rt, p.d_tables, p.join_dev[j], (int)bp.xT.size(),
                                       lkb, bp.doubled ? lkb : 0, Tc, s));
     }
     for (int64_t a0 = e0; a0 < e1; a0 += e_cap) {
@@ -272,7 +323,7 @@ ptsbe_status_t run_batch(Plan& p, int j, const uint8_t* d_kraus, const float2* m
       ptsbe::JoinArgs ja{};
       ja.V = V; ja.v_stride = (int64_t)1 << rV;
       ja.T = T; ja.t_stride = (int64_t)1 << rT;
-      ja.elem_traj = io.elem_traj + a0; ja.traj_base = (int32_t)t0;
+      ja.elem_traj = io.elem_traj + a0; ja.traj_base = (int32_t)t0; ja.tslot = d_slot;
       ja.n_elems = ne;
       ja.xb_bits = (int)bp.xb.size(); ja.lk_bits = (int)bp.lk.size(); ja.xT_bits = (int)bp.xT.size();
       ja.tab = p.d_tables; ja.jd = jdv;
@@ -293,7 +344,7 @@ ptsbe_status_t run_batch(Plan& p, int j, const uint8_t* d_kraus, const float2* m
       if (use_mfma) {
         ptsbe::QformArgs qa{};
         qa.V = V; qa.v_stride = (int64_t)1 << rV; qa.v_base = a0;
-        qa.Tc = Tc; qa.Th = Th; qa.traj_base = (int32_t)t0;
+        qa.Tc = Tc; qa.Th = Th; qa.traj_base = (int32_t)t0; qa.tslot = d_slot;
         int64_t tA = t0, tB = t1 - 1;
         while (tA + 1 < t1 && first[tA + 1] <= a0) ++tA;     // trajectory holding element a0
         while (tB > tA && first[tB] >= a1) --tB;             // trajectory holding element a1-1
@@ -343,6 +394,7 @@ ptsbe_status_t run_batch(Plan& p, int j, const uint8_t* d_kraus, const float2* m
     }
     ar.used = mark;
   }
+  if (!keep.empty()) HIP_TRY(hipStreamSynchronize(s));   // the uploads' host sources end here
   ar.used = mark0;
   return PTSBE_OK;
 }
@@ -737,6 +789,18 @@ ptsbe_status_t ptsbe_plan_sv_schedule(ptsbe_plan_t plan, int32_t window_qubits, 
   return PTSBE_OK;
 }
 
+
+ptsbe_status_t ptsbe_plan_right_sites(ptsbe_plan_t plan, int32_t j, int32_t* sites, int32_t* n_sites_out) {
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  if (!p) return fail(PTSBE_ERR_INVALID_ARG, "null plan");
+  if (p->method == PTSBE_METHOD_STATEVECTOR) return fail(PTSBE_ERR_INVALID_ARG, "statevector-method plan");
+  if (j < 0 || j >= (int)p->batches.size()) return fail(PTSBE_ERR_INVALID_ARG, "batch index out of range");
+  const std::vector<int32_t> v = right_sites(*p, p->batches[(size_t)j]);
+  if (sites) std::copy(v.begin(), v.end(), sites);
+  if (n_sites_out) *n_sites_out = (int32_t)v.size();
+  return PTSBE_OK;
+}
+
 ptsbe_status_t ptsbe_plan_batch_info(ptsbe_plan_t plan, int32_t j, ptsbe_batch_info_t* out) {
   Plan* p = reinterpret_cast<Plan*>(plan);
   if (!p || !out) return fail(PTSBE_ERR_INVALID_ARG, "null argument");
@@ -758,6 +822,17 @@ ptsbe_status_t ptsbe_plan_batch_info(ptsbe_plan_t plan, int32_t j, ptsbe_batch_i
   out->flops_per_elem = bp.left.flops + bp.join_flops_per_elem;
   out->join_flops_per_elem = bp.join_flops_per_elem;
   out->bytes_per_traj = bp.right.bytes;
+  out->n_right_launches = 0;
+  out->n_right_fused_steps = 0;
+  out->right_longest_run = 0;
+  if (!part_uses_vm(bp.right))
+    for (const ptsbe::Segment& sg : bp.right.segs) {
+      ++out->n_right_launches;
+      if (sg.fused) {
+        out->n_right_fused_steps += sg.count;
+        out->right_longest_run = std::max(out->right_longest_run, sg.count);
+      }
+    }
   return PTSBE_OK;
 }
 
@@ -921,7 +996,13 @@ ptsbe_status_t ptsbe_contract_batch(ptsbe_plan_t plan, int32_t j, const uint8_t*
   Arena ar;
   ar.base = (char*)d_workspace;
   ar.cap = workspace_bytes;
+  std::vector<uint8_t> h_kraus((size_t)E * p->site_gate.size());
+  if (!h_kraus.empty()) {
+    HIP_TRY(hipMemcpyAsync(h_kraus.data(), d_kraus_idx, h_kraus.size(), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+  }
   BatchIO io;
+  io.h_kraus = h_kraus.empty() ? nullptr : h_kraus.data();
   io.elem_traj = d_elem_traj;
   io.elem_prefix = d_elem_prefix;
   io.U = n_elems;
@@ -962,6 +1043,11 @@ ptsbe_status_t ptsbe_sample_shots(ptsbe_plan_t plan, const uint8_t* d_kraus_idx,
   // shot layout: trajectory i owns rows [base_i, base_i + m_i)
   std::vector<int64_t> m(E), base(E);
   HIP_TRY(hipMemcpyAsync(m.data(), d_shots_per_traj, (size_t)E * 8, hipMemcpyDeviceToHost, s));
+  // host copy of the Kraus indices: trajectories that agree on the sites of a
+  // batch's per-trajectory part share that part's tensor
+  std::vector<uint8_t> h_kraus((size_t)E * p->site_gate.size());
+  if (!h_kraus.empty())
+    HIP_TRY(hipMemcpyAsync(h_kraus.data(), d_kraus_idx, h_kraus.size(), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   int64_t M = 0;
   for (int64_t i = 0; i < E; ++i) {
@@ -1015,6 +1101,7 @@ ptsbe_status_t ptsbe_sample_shots(ptsbe_plan_t plan, const uint8_t* d_kraus_idx,
     if (stats_out) stats_out[j] = U;
     const auto& bp = p->batches[j];
     BatchIO io;
+    io.h_kraus = h_kraus.empty() ? nullptr : h_kraus.data();
     io.elem_traj = el[cur].traj;
     io.elem_prefix = el[cur].prefix;
     io.V_out = Vbuf[j & 1];

@@ -258,8 +258,9 @@ hipError_t launch_fused(const Segment& seg, const FusedStep* d_fs, GateCtx g, in
 
 struct JoinArgs {
   const float2* V; int64_t v_stride;     // per element
-  const float2* T; int64_t t_stride;     // per trajectory (indexed traj - traj_base)
+  const float2* T; int64_t t_stride;     // per trajectory (indexed traj - traj_base, or its slot)
   const int32_t* elem_traj; int32_t traj_base;
+  const int32_t* tslot;                  // slot of T of each trajectory (traj - traj_base), or null
   int64_t n_elems;
   int xb_bits, lk_bits, xT_bits;
   const int64_t* tab;                    // plan table base
@@ -274,7 +275,8 @@ struct QformArgs {
   const float2* V; int64_t v_stride; int64_t v_base;   // V rows of elements [v_base, ...)
   const float2* Tc;                                     // canonical [traj][x][k][k'] (split join, ket join)
   const float* Th;                                      // Theta [traj][x][K^2] (FP32 doubled join)
-  int32_t traj_base;                                    // Tc index = traj - traj_base
+  int32_t traj_base;                                    // Tc index = traj - traj_base (or its slot)
+  const int32_t* tslot;                                 // slot of each trajectory's Tc / Theta, or null
   int32_t traj0;                                        // trajectory of grid.y == 0
   const int32_t* first;                                 // [E+1] first element of each trajectory
   int64_t e_lo, e_hi;                                   // element range of this launch

@@ -234,7 +234,8 @@ __global__ void join_kernel(JoinArgs a) {
     const int lo_b = a.xb_bits < 12 ? a.xb_bits : 12;
     const int lo_k = a.lk_bits < 12 ? a.lk_bits : 12;
     const float2* V = a.V + e * a.v_stride;
-    const float2* T = a.T + (int64_t)(a.elem_traj[e] - a.traj_base) * a.t_stride;
+    const int32_t ti = a.elem_traj[e] - a.traj_base;
+    const float2* T = a.T + (int64_t)(a.tslot ? a.tslot[ti] : ti) * a.t_stride;
     const int64_t vr = tab(a.tab, a.jd.vr_lo, a.jd.vr_hi, lo_b, row);
     const int64_t tx = tab(a.tab, a.jd.tx_lo, a.jd.tx_hi, lo_x, x);
     const int nk = 1 << a.lk_bits;
@@ -334,7 +335,8 @@ __global__ void __launch_bounds__(256) qform_split_bf16_kernel(QformArgs a) {
     }
     Vs[rr][k] = v;
   }
-  const float2* Tt = a.Tc + (int64_t)(t - a.traj_base) * ((int64_t)nx * K * K);
+  const int32_t ts = a.tslot ? a.tslot[t - a.traj_base] : t - a.traj_base;
+  const float2* Tt = a.Tc + (int64_t)ts * ((int64_t)nx * K * K);
   auto store_split = [&](int buf, int idx, float2 v) {
     const int k = idx / K, kp = idx % K;          // Tc index = k * K + kp
     const __bf16 rh = (__bf16)v.x, ih = (__bf16)v.y;
@@ -488,7 +490,8 @@ __global__ void __launch_bounds__(256) ketjoin_mfma_kernel(QformArgs a) {
     ar[s] = v.x;
     ai[s] = v.y;
   }
-  const float2* Tt = a.Tc + (int64_t)(t - a.traj_base) * ((int64_t)nx * K);
+  const int32_t ts = a.tslot ? a.tslot[t - a.traj_base] : t - a.traj_base;
+  const float2* Tt = a.Tc + (int64_t)ts * ((int64_t)nx * K);
   const int nout = 1 << a.b;
   for (int tl = tile_begin; tl < tile_end; ++tl) {
     const int x0 = tl * 16;
@@ -642,7 +645,8 @@ __global__ void __launch_bounds__(256) qform_mfma_kernel(QformArgs a) {
   // Theta chunk loader: float4 number idx holds slots 4s..4s+3 of the chunk at
   // x = x0 + idx % XT (s = idx / XT); in LDS slot 4s + q of x = x0 + 16c + j sits
   // at ((s * 64 + 16 q + j) * NC + c), the B operand of lane 16 q + j at k-step s.
-  const float* Tt = a.Th + ((int64_t)(t - a.traj_base) * nx + x0) * KK;
+  const int32_t ts = a.tslot ? a.tslot[t - a.traj_base] : t - a.traj_base;
+  const float* Tt = a.Th + ((int64_t)ts * nx + x0) * KK;
   const int i0 = tid, i1 = tid + 256;
   const bool h0 = i0 < F4C, h1 = i1 < F4C;
   const int xl0 = i0 % XT, s0 = (i0 / XT) % NS, xl1 = i1 % XT, s1 = (i1 / XT) % NS;
