@@ -176,6 +176,46 @@ def test_small_multibatch_marginals(case, method):
                     assert np.linalg.norm(amp[e] - ref) / nr <= 1e-5, (name, e)
 
 
+@pytest.mark.parametrize("case", [0, 1])
+def test_right_part_sharing(case):
+    """Trajectories that agree on the Kraus choices of a batch's per-trajectory part
+    share its tensor: variants of each trajectory that change one site outside
+    (shared right tensor, different left part) or inside (own right tensor) that set
+    must each still give their own oracle marginals."""
+    torch, dev = torch_dev()
+    name, c, bs = _small_cases()[case]
+    plan = _plan(c, bs, method="network")
+    base, _, _, _ = plan.sample_trajectories(31 + case, 6)
+    rng = np.random.default_rng(500 + case)
+    n_kraus = [c.channels[ch].kraus.shape[0] for ch in c.site_channel]
+    n, starts = c.n_qubits, sampling.batch_starts(bs)
+    for j in range(1, len(bs)):
+        inside = set(plan.right_sites(j).tolist())
+        outside = [s for s in range(len(n_kraus)) if s not in inside and n_kraus[s] > 1]
+        inside = [s for s in inside if n_kraus[s] > 1]
+        rows = []
+        for kr in base:
+            rows.append(kr.copy())
+            for pool in (outside, inside):
+                if pool:
+                    v = kr.copy()
+                    s = int(rng.choice(pool))
+                    v[s] = (v[s] + 1 + int(rng.integers(0, n_kraus[s] - 1))) % n_kraus[s]
+                    rows.append(v)
+        kr_all = np.stack(rows).astype(np.uint8)
+        assert len(outside) > 0 and len(inside) > 0, (name, j)
+        _say(f"{name}: batch {j}, {len(kr_all)} trajectories, {len(inside)} right-part sites")
+        psis = oracle_states(c, kr_all)
+        a, b = starts[j], bs[j]
+        traj = np.arange(len(kr_all))
+        pre = [int(rng.integers(0, 2 ** a)) for _ in traj]
+        pop, tot = _contract(plan, torch, dev, to_dev(torch, dev, kr_all), traj, pre, j)
+        for e, (i, p) in enumerate(zip(traj, pre)):
+            ref = sampling.marginal_from_state(psis[i], n, a, b, p)
+            Z = ref.sum()
+            assert np.abs(pop[e] - ref).max() <= 1e-6 * max(Z, 1e-30) + 1e-12, (name, j, e)
+
+
 @pytest.mark.parametrize("method", METHODS)
 @pytest.mark.parametrize("case", range(4))
 def test_small_multibatch_shots(case, method):
