@@ -146,7 +146,8 @@ def main():
                 "frac": achieved / peak, "traffic": traffic if args.precision == "c64" else None,
                 "kernel": "qform_mfma_kernel<32,4> (doubled-network join as a real GEMM over K^2 folded slots, "
                           "FP32 MFMA)" if args.precision == "c64"
-                          else "qform_split_bf16_kernel (doubled-network join, bf16x3 MFMA)",
+                          else "qform_split_kernel<32,4> (doubled-network join as the K^2-slot GEMM, bf16 hi+lo "
+                               "operands, three products on bf16 MFMA, FP32 accumulate)",
                 "flops": "real bilinear form over K^2 folded slots: 2K^2 per row and x (K=32: 2048; "
                          "the plain complex product would be 8320)",
                 "launches": prof["join_launches"], "kernel_ms_per_step": prof["join_ms"] / args.steps}

@@ -234,7 +234,7 @@ ptsbe_status_t run_batch(Plan& p, int j, const uint8_t* d_kraus, const float2* m
   const bool use_ket = !bp.doubled && ptsbe::ketjoin_supported(lkb);
   const bool use_mfma = use_qform || use_ket;
   const bool use_split = use_qform && p.precision == PTSBE_SPLIT_BF16 && ptsbe::qform_split_supported(lkb);
-  const bool use_fold = use_qform && !use_split;
+  const bool use_fold = use_qform;               // Theta layout (FP32, or bf16 hi + lo planes)
   const size_t layout_bytes = use_fold ? ptsbe::qform_theta_bytes((int)bp.xT.size(), lkb)
                                        : (use_mfma ? ((size_t)8 << rT) : 0);
   const size_t per_traj = ((size_t)8 << rT) + layout_bytes + part_scratch_per_job(bp.right);
@@ -296,7 +296,7 @@ ptsbe_status_t run_batch(Plan& p, int j, const uint8_t* d_kraus, const float2* m
       Th = (float*)ar.take((size_t)n_rt * layout_bytes);
       if (!Th) return fail(PTSBE_ERR_OUT_OF_MEMORY, "workspace too small (join layout)");
       HIP_TRY(ptsbe::launch_theta_T(T, (int64_t)1 << rT, n_rt, p.d_tables, p.join_dev[j], (int)bp.xT.size(),
-                                    lkb, Th, s));
+                                    lkb, Th, use_split ? 1 : 0, s));
     } else if (use_mfma) {   // canonical [x][k][k'] (split doubled) or [x][k] (ket) layout
       Tc = (float2*)ar.take((size_t)n_rt * layout_bytes);
       if (!Tc) return fail(PTSBE_ERR_OUT_OF_MEMORY, "workspace too small (join layout)");
@@ -345,6 +345,7 @@ ptsbe_status_t run_batch(Plan& p, int j, const uint8_t* d_kraus, const float2* m
         ptsbe::QformArgs qa{};
         qa.V = V; qa.v_stride = (int64_t)1 << rV; qa.v_base = a0;
         qa.Tc = Tc; qa.Th = Th; qa.traj_base = (int32_t)t0; qa.tslot = d_slot;
+        qa.th_plane = n_rt * ((int64_t)1 << ((int)bp.xT.size() + 2 * lkb));
         int64_t tA = t0, tB = t1 - 1;
         while (tA + 1 < t1 && first[tA + 1] <= a0) ++tA;     // trajectory holding element a0
         while (tB > tA && first[tB] >= a1) --tB;             // trajectory holding element a1-1

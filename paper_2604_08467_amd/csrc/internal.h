@@ -274,7 +274,8 @@ hipError_t launch_join(const JoinArgs& a, hipStream_t stream);
 struct QformArgs {
   const float2* V; int64_t v_stride; int64_t v_base;   // V rows of elements [v_base, ...)
   const float2* Tc;                                     // canonical [traj][x][k][k'] (split join, ket join)
-  const float* Th;                                      // Theta [traj][x][K^2] (FP32 doubled join)
+  const float* Th;                                      // Theta [traj][x][K^2] (FP32), or its bf16 hi plane
+  int64_t th_plane;                                     // split join: bf16 elements from the hi to the lo plane
   int32_t traj_base;                                    // Tc index = traj - traj_base (or its slot)
   const int32_t* tslot;                                 // slot of each trajectory's Tc / Theta, or null
   int32_t traj0;                                        // trajectory of grid.y == 0
@@ -292,10 +293,11 @@ bool qform_supported(int lk_bits);
 // Theta layout of the doubled join (FP32 MFMA path): bytes per trajectory
 size_t qform_theta_bytes(int xT_bits, int lk_bits);
 hipError_t launch_theta_T(const float2* T, int64_t t_stride, int64_t n_traj, const int64_t* tab,
-                          const Plan::JoinDev& jd, int xT_bits, int lk_bits, float* Th, hipStream_t stream);
+                          const Plan::JoinDev& jd, int xT_bits, int lk_bits, float* Th, int split,
+                          hipStream_t stream);
 bool ketjoin_supported(int lk_bits);
 bool qform_split_supported(int lk_bits);
-// split-precision (bf16 hi + lo, three products, FP32 accumulate) doubled join
+// split-precision slot GEMM (bf16 hi + lo, three products, FP32 accumulate) of the doubled join
 hipError_t launch_qform_split(const QformArgs& a, int n_traj, int max_rows, hipStream_t stream);
 hipError_t launch_qform(const QformArgs& a, int n_traj, int max_rows, hipStream_t stream);
 hipError_t launch_ketjoin(const QformArgs& a, int n_traj, int max_rows, hipStream_t stream);

@@ -285,154 +285,7 @@ __global__ void permute_T_kernel(const float2* __restrict__ T, int64_t t_stride,
   }
 }
 
-// Split-precision variant of the doubled-network join (K = 32): every operand
-// x = hi + lo with hi = bf16(x), lo = bf16(x - hi); each real product is
-// hi*hi + hi*lo + lo*hi on v_mfma_f32_16x16x32_bf16 with FP32 accumulation.
-// The complex GEMM Y = V T is two real GEMMs of reduction length 2K:
-// Yr = [Vr | -Vi] [Tr ; Ti], Yi = [Vr | Vi] [Ti ; Tr].  T blocks are split into
-// four bf16 planes in LDS, stored transposed ([k'][k]) so that a lane's eight
-// consecutive k of one column are one 16-byte read.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-
-__global__ void __launch_bounds__(256) qform_split_bf16_kernel(QformArgs a) {
-  constexpr int K = 32, ROWS = 64, NH = 2, KP = K + 8;   // KP: padded row of a plane
-  constexpr int PER = K * K / 256;
-  __shared__ __attribute__((aligned(16))) __bf16 Tp[2][4][K][KP];   // planes: r_hi, r_lo, i_hi, i_lo
-  __shared__ float2 Vs[ROWS][K + 1];
-  uint32_t bx, by, bz;
-  {
-    const uint32_t nbx = gridDim.x, nby = gridDim.y, total = nbx * nby * gridDim.z;
-    const uint32_t phys = blockIdx.x + nbx * (blockIdx.y + nby * blockIdx.z);
-    const uint32_t xcd = phys % 8u, slot = phys / 8u, q = total / 8u, r = total % 8u;
-    const uint32_t logical = xcd < r ? xcd * (q + 1) + slot : r * (q + 1) + (xcd - r) * q + slot;
-    bx = logical % nbx;
-    by = (logical / nbx) % nby;
-    bz = logical / (nbx * nby);
-  }
-  const int t = a.traj0 + (int)by;
-  const int64_t e_begin = a.first[t] > a.e_lo ? a.first[t] : a.e_lo;
-  const int64_t e_end = a.first[t + 1] < a.e_hi ? a.first[t + 1] : a.e_hi;
-  const int xb_bits = a.xb_bits;
-  const int64_t rows_t = (e_end - e_begin) << xb_bits;
-  const int64_t row0 = (int64_t)bx * ROWS;
-  if (row0 >= rows_t) return;
-  const int nx = 1 << a.xT_bits;
-  const int x_per = (nx + gridDim.z - 1) / gridDim.z;
-  const int x_begin = (int)bz * x_per;
-  const int x_end = x_begin + x_per < nx ? x_begin + x_per : nx;
-  if (x_begin >= x_end) return;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int lo_b = xb_bits < 12 ? xb_bits : 12, lo_k = a.lk_bits < 12 ? a.lk_bits : 12;
-  for (int i = tid; i < ROWS * K; i += 256) {
-    const int rr = i / K, k = i % K;
-    const int64_t row = row0 + rr;
-    float2 v = make_float2(0.f, 0.f);
-    if (row < rows_t) {
-      const int64_t e = e_begin + (row >> xb_bits);
-      const uint32_t xb = (uint32_t)(row & ((1 << xb_bits) - 1));
-      v = a.V[(e - a.v_base) * a.v_stride + tab(a.tab, a.jd.vr_lo, a.jd.vr_hi, lo_b, xb) +
-              tab(a.tab, a.jd.vc_lo, a.jd.vc_hi, lo_k, (uint32_t)k)];
-    }
-    Vs[rr][k] = v;
-  }
-  const int32_t ts = a.tslot ? a.tslot[t - a.traj_base] : t - a.traj_base;
-  const float2* Tt = a.Tc + (int64_t)ts * ((int64_t)nx * K * K);
-  auto store_split = [&](int buf, int idx, float2 v) {
-    const int k = idx / K, kp = idx % K;          // Tc index = k * K + kp
-    const __bf16 rh = (__bf16)v.x, ih = (__bf16)v.y;
-    Tp[buf][0][kp][k] = rh;
-    Tp[buf][1][kp][k] = (__bf16)(v.x - (float)rh);
-    Tp[buf][2][kp][k] = ih;
-    Tp[buf][3][kp][k] = (__bf16)(v.y - (float)ih);
-  };
-  {
-    const float2* src = Tt + (int64_t)x_begin * K * K;
-#pragma unroll
-    for (int i = 0; i < PER; ++i) store_split(0, tid + 256 * i, src[tid + 256 * i]);
-  }
-  __syncthreads();
-  // A fragments: lane holds row wave*16 + lane%16, k = 8*(lane/16) + 0..7
-  bf16x8 arh, arl, aih, ail, naih, nail;
-  {
-    const int row = wave * 16 + (lane & 15), kb = 8 * (lane >> 4);
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const float2 v = Vs[row][kb + i];
-      const __bf16 rh = (__bf16)v.x, ih = (__bf16)v.y;
-      const __bf16 rl = (__bf16)(v.x - (float)rh), il = (__bf16)(v.y - (float)ih);
-      arh[i] = rh; arl[i] = rl; aih[i] = ih; ail[i] = il;
-      naih[i] = -ih; nail[i] = -il;
-    }
-  }
-  const int nout = 1 << a.b;
-  const int lo_x = a.xT_bits < 12 ? a.xT_bits : 12;
-  int buf = 0;
-  for (int x = x_begin; x < x_end; ++x) {
-    const bool more = x + 1 < x_end;
-    float2 nxt[PER];
-    if (more) {
-      const float2* src = Tt + (int64_t)(x + 1) * K * K;
-#pragma unroll
-      for (int i = 0; i < PER; ++i) nxt[i] = src[tid + 256 * i];
-    }
-    float p[4] = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int h = 0; h < NH; ++h) {
-      const int c = 16 * h + (lane & 15), kb = 8 * (lane >> 4);
-      const bf16x8 brh = *reinterpret_cast<const bf16x8*>(&Tp[buf][0][c][kb]);
-      const bf16x8 brl = *reinterpret_cast<const bf16x8*>(&Tp[buf][1][c][kb]);
-      const bf16x8 bih = *reinterpret_cast<const bf16x8*>(&Tp[buf][2][c][kb]);
-      const bf16x8 bil = *reinterpret_cast<const bf16x8*>(&Tp[buf][3][c][kb]);
-      floatx4 yr = {0.f, 0.f, 0.f, 0.f}, yi = {0.f, 0.f, 0.f, 0.f};
-      yr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arh, brh, yr, 0, 0, 0);
-      yr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arh, brl, yr, 0, 0, 0);
-      yr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arl, brh, yr, 0, 0, 0);
-      yr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(naih, bih, yr, 0, 0, 0);
-      yr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(naih, bil, yr, 0, 0, 0);
-      yr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nail, bih, yr, 0, 0, 0);
-      yi = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arh, bih, yi, 0, 0, 0);
-      yi = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arh, bil, yi, 0, 0, 0);
-      yi = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arl, bih, yi, 0, 0, 0);
-      yi = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aih, brh, yi, 0, 0, 0);
-      yi = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aih, brl, yi, 0, 0, 0);
-      yi = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ail, brh, yi, 0, 0, 0);
-      const int kc = 16 * h + (lane & 15);
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const float2 v = Vs[wave * 16 + 4 * (lane >> 4) + i][kc];
-        p[i] += yr[i] * v.x + yi[i] * v.y;
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      float v = p[i];
-      v += __shfl_xor(v, 1);
-      v += __shfl_xor(v, 2);
-      v += __shfl_xor(v, 4);
-      v += __shfl_xor(v, 8);
-      p[i] = v;
-    }
-    if ((lane & 15) == 0) {
-      const int64_t ox = tab(a.tab, a.jd.ox_lo, a.jd.ox_hi, lo_x, (uint32_t)x);
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int64_t row = row0 + wave * 16 + 4 * (lane >> 4) + i;
-        if (row < rows_t) {
-          const int64_t e = e_begin + (row >> xb_bits);
-          const uint32_t xb = (uint32_t)(row & ((1 << xb_bits) - 1));
-          const int64_t o = ox + tab(a.tab, a.jd.ob_lo, a.jd.ob_hi, lo_b, xb);
-          a.pop[(e - a.v_base) * nout + o] = p[i];
-        }
-      }
-    }
-    if (more) {
-#pragma unroll
-      for (int i = 0; i < PER; ++i) store_split(buf ^ 1, tid + 256 * i, nxt[i]);
-    }
-    __syncthreads();
-    buf ^= 1;
-  }
-}
 
 // MFMA join of the last (ket-only) batch: amp[e][o(x, xb)] = sum_k V[e][xb][k] Tc[t][x][k]
 // and pi = |amp|^2.  Rows (element, xb) of one trajectory are the M dimension, x
@@ -546,10 +399,13 @@ __global__ void __launch_bounds__(256) ketjoin_mfma_kernel(QformArgs a) {
 //
 // theta_T_kernel: one workgroup per (trajectory, x) gathers T[x] into LDS through
 // the plan's tables and writes Theta[traj][x][f] (f contiguous).
+//
+// With split != 0 the kernel writes Theta as two bf16 planes (hi = bf16(theta),
+// lo = bf16(theta - hi)), hi at Th and lo at Th + n_traj 2^xT K^2 / 2 floats.
 template <int K>
 __global__ void __launch_bounds__(256) theta_T_kernel(const float2* __restrict__ T, int64_t t_stride, int64_t n_traj,
                                                        const int64_t* __restrict__ tables, Plan::JoinDev jd,
-                                                       int xT_bits, float* __restrict__ Th) {
+                                                       int xT_bits, float* __restrict__ Th, int split) {
   constexpr int KK = K * K, PERT = KK / 256;
   constexpr int LK = K == 16 ? 4 : 5;
   static_assert(KK % 256 == 0, "K = 16 or 32");
@@ -575,6 +431,8 @@ __global__ void __launch_bounds__(256) theta_T_kernel(const float2* __restrict__
     }
     __syncthreads();
     float* out = Th + g * KK;
+    __bf16* hi = reinterpret_cast<__bf16*>(Th) + g * KK;
+    __bf16* lo = reinterpret_cast<__bf16*>(Th) + (n_traj * nx + g) * KK;
 #pragma unroll
     for (int i = 0; i < PERT; ++i) {
       const int f = tid + 256 * i;
@@ -583,7 +441,13 @@ __global__ void __launch_bounds__(256) theta_T_kernel(const float2* __restrict__
       if (a == b) th = Ts[a][a].x;
       else if (a < b) th = Ts[a][b].x + Ts[b][a].x;
       else th = Ts[a][b].y - Ts[b][a].y;
-      out[f] = th;
+      if (split) {
+        const __bf16 h = (__bf16)th;
+        hi[f] = h;
+        lo[f] = (__bf16)(th - (float)h);
+      } else {
+        out[f] = th;
+      }
     }
     __syncthreads();
   }
@@ -724,6 +588,158 @@ __global__ void __launch_bounds__(256) qform_mfma_kernel(QformArgs a) {
     __syncthreads();
   }
   // acc[c][i] = pi[row wave*16 + 4 q + i][x0 + 16 c + lane % 16]
+  const int lo_x = a.xT_bits < 12 ? a.xT_bits : 12;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const int xl = 16 * c + (lane & 15);
+    if (xl < xv) {
+      const int64_t ox = tab(a.tab, a.jd.ox_lo, a.jd.ox_hi, lo_x, (uint32_t)(x0 + xl));
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (obase[i] >= 0) a.pop[obase[i] + ox] = acc[c][i];
+    }
+  }
+}
+
+// Split-precision slot GEMM: M and Theta as hi + lo bf16 (hi = bf16(x),
+// lo = bf16(x - hi)), three products hi*hi + hi*lo + lo*hi per tile on
+// v_mfma_f32_16x16x32_bf16, FP32 accumulation.  One MFMA k-step covers 32 slots:
+// lane 16 q + j takes slots 8q..8q+7 of the step, for row j (A) or for x = 16c + j
+// (B).  Theta planes are staged in LDS two k-steps at a time (double-buffered).
+template <int K, int NC>
+__global__ void __launch_bounds__(256) qform_split_kernel(QformArgs a) {
+  constexpr int ROWS = 64, KK = K * K, XT = 16 * NC, NST = KK / 32, KS = 2, NCH = NST / KS;
+  constexpr int U16 = KS * 2 * XT * 4;            // 16-byte units of Theta per chunk
+  static_assert(NCH >= 1 && NST % KS == 0, "chunking");
+  __shared__ bf16x8 Tb[2][KS][2][NC][64];          // [buf][k-step][plane][c][lane]
+  __shared__ float2 Vs[ROWS][K + 1];
+  uint32_t bx, by, bz;
+  {
+    const uint32_t nbx = gridDim.x, nby = gridDim.y, nbz = gridDim.z, total = nbx * nby * nbz;
+    const uint32_t phys = blockIdx.x + nbx * (blockIdx.y + nby * blockIdx.z);
+    const uint32_t xcd = phys % 8u, slot = phys / 8u, q = total / 8u, r = total % 8u;
+    const uint32_t logical = xcd < r ? xcd * (q + 1) + slot : r * (q + 1) + (xcd - r) * q + slot;
+    bz = logical % nbz;
+    bx = (logical / nbz) % nbx;
+    by = logical / (nbz * nbx);
+  }
+  const int t = a.traj0 + (int)by;
+  const int64_t e_begin = a.first[t] > a.e_lo ? a.first[t] : a.e_lo;
+  const int64_t e_end = a.first[t + 1] < a.e_hi ? a.first[t + 1] : a.e_hi;
+  const int xb_bits = a.xb_bits;
+  const int64_t rows_t = (e_end - e_begin) << xb_bits;
+  const int64_t row0 = (int64_t)bx * ROWS;
+  if (row0 >= rows_t) return;
+  const int nx = 1 << a.xT_bits;
+  const int x0 = (int)bz * XT;
+  if (x0 >= nx) return;
+  const int xv = nx - x0 < XT ? nx - x0 : XT;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lo_b = xb_bits < 12 ? xb_bits : 12, lo_k = a.lk_bits < 12 ? a.lk_bits : 12;
+  for (int i = tid; i < ROWS * K; i += 256) {
+    const int rr = i / K, k = i % K;
+    const int64_t row = row0 + rr;
+    float2 v = make_float2(0.f, 0.f);
+    if (row < rows_t) {
+      const int64_t e = e_begin + (row >> xb_bits);
+      const uint32_t xb = (uint32_t)(row & ((1 << xb_bits) - 1));
+      v = a.V[(e - a.v_base) * a.v_stride + tab(a.tab, a.jd.vr_lo, a.jd.vr_hi, lo_b, xb) +
+              tab(a.tab, a.jd.vc_lo, a.jd.vc_hi, lo_k, (uint32_t)k)];
+    }
+    Vs[rr][k] = v;
+  }
+  // Theta planes: hi at a.Th (bf16), lo n_all = (#slots of the launch's trajectories) later
+  const int32_t ts = a.tslot ? a.tslot[t - a.traj_base] : t - a.traj_base;
+  const __bf16* Hp = reinterpret_cast<const __bf16*>(a.Th) + ((int64_t)ts * nx + x0) * KK;
+  const int64_t plane = a.th_plane;                   // elements between the hi and lo planes
+  // chunk loader: 16-byte unit u = (plane, k-step, x, q) with q fastest; every lane
+  // loads (rows past the tile's x read row x0, in bounds) and masks when storing
+  auto ld = [&](int ch, int u) -> bf16x8 {
+    const int q = u & 3, xl = (u >> 2) % XT, ks = (u / (4 * XT)) % KS, pl = u / (4 * XT * KS);
+    const int xr = xl < xv ? xl : 0;
+    return *reinterpret_cast<const bf16x8*>(Hp + pl * plane + (int64_t)xr * KK + (ch * KS + ks) * 32 + 8 * q);
+  };
+  auto st = [&](int buf, int u, bf16x8 v) {
+    const int q = u & 3, xl = (u >> 2) % XT, ks = (u / (4 * XT)) % KS, pl = u / (4 * XT * KS);
+    if (xl >= xv) v = bf16x8{};
+    Tb[buf][ks][pl][xl >> 4][16 * q + (xl & 15)] = v;
+  };
+  constexpr int PU = (U16 + 255) / 256;
+  static_assert(PU <= 4, "four units per thread at most");
+  bf16x8 r[4];
+#pragma unroll
+  for (int i = 0; i < PU; ++i) {
+    const int u = tid + 256 * i;
+    r[i] = ld(0, u < U16 ? u : U16 - 1);
+  }
+#pragma unroll
+  for (int i = 0; i < PU; ++i)
+    if (tid + 256 * i < U16) st(0, tid + 256 * i, r[i]);
+  __syncthreads();
+  // lane: row rl, slot group q (slots 8q..8q+7 of each k-step)
+  const int rl = wave * 16 + (lane & 15), q = lane >> 4;
+  constexpr int BQ = K == 32 ? 1 : 2;                // K = 16: a k-step spans two values of a
+  float2 vb[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) vb[i] = Vs[rl][(8 * (q % (4 / BQ)) + i) & (K - 1)];
+  const int nout = 1 << a.b;
+  int64_t obase[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int64_t row = row0 + wave * 16 + 4 * q + i;
+    obase[i] = -1;
+    if (row < rows_t) {
+      const int64_t e = e_begin + (row >> xb_bits);
+      const uint32_t xb = (uint32_t)(row & ((1 << xb_bits) - 1));
+      obase[i] = (e - a.v_base) * nout + tab(a.tab, a.jd.ob_lo, a.jd.ob_hi, lo_b, xb);
+    }
+  }
+  floatx4 acc[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) acc[c] = floatx4{0.f, 0.f, 0.f, 0.f};
+  for (int ch = 0; ch < NCH; ++ch) {
+    const int buf = ch & 1;
+    const bool more = ch + 1 < NCH;
+    const int cn = more ? ch + 1 : ch;
+#pragma unroll
+    for (int i = 0; i < PU; ++i) {
+      const int u = tid + 256 * i;
+      r[i] = ld(cn, u < U16 ? u : U16 - 1);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int kstep = ch * KS + ks;
+      // slot f = 32 kstep + 8 q + i = a K + b
+      const int av = (32 * kstep + 8 * q) / K;
+      const int b0 = (32 * kstep + 8 * q) % K;
+      const float2 va = Vs[rl][av];
+      bf16x8 ah, al;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const float2 w = vb[i];
+        const float R = va.x * w.x + va.y * w.y;       // Re(v_a conj v_b)
+        const float I = w.y * va.x - w.x * va.y;       // Im(v_b conj v_a)
+        const float m = av <= b0 + i ? R : I;
+        const __bf16 h = (__bf16)m;
+        ah[i] = h;
+        al[i] = (__bf16)(m - (float)h);
+      }
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        const bf16x8 bh = Tb[buf][ks][0][c][lane], bl = Tb[buf][ks][1][c][lane];
+        acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc[c], 0, 0, 0);
+        acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc[c], 0, 0, 0);
+        acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc[c], 0, 0, 0);
+      }
+    }
+    if (more) {
+#pragma unroll
+      for (int i = 0; i < PU; ++i)
+        if (tid + 256 * i < U16) st(buf ^ 1, tid + 256 * i, r[i]);
+    }
+    __syncthreads();
+  }
   const int lo_x = a.xT_bits < 12 ? a.xT_bits : 12;
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
@@ -1149,18 +1165,24 @@ hipError_t launch_permute_T(const float2* T, int64_t t_stride, int64_t n_traj, c
 }
 
 bool qform_supported(int lk_bits) { return lk_bits == 4 || lk_bits == 5; }
-bool qform_split_supported(int lk_bits) { return lk_bits == 5; }
+bool qform_split_supported(int lk_bits) { return lk_bits == 4 || lk_bits == 5; }
 
 hipError_t launch_qform_split(const QformArgs& a, int n_traj, int max_rows, hipStream_t stream) {
   if (n_traj <= 0 || max_rows <= 0) return hipSuccess;
-  if (a.lk_bits != 5) return hipErrorInvalidValue;
   const int tiles = (max_rows + 63) / 64;
   const int nx = 1 << a.xT_bits;
-  int64_t wg = (int64_t)tiles * n_traj;
-  int zs = 1;
-  while (zs < nx && wg * zs < 4096) zs *= 2;
-  dim3 grid((unsigned)tiles, (unsigned)n_traj, (unsigned)zs);
-  hipLaunchKernelGGL(qform_split_bf16_kernel, grid, dim3(256), 0, stream, a);
+  const int nc = nx >= 64 ? 4 : (nx >= 32 ? 2 : 1);
+  const int xtiles = (nx + 16 * nc - 1) / (16 * nc);
+  dim3 grid((unsigned)tiles, (unsigned)n_traj, (unsigned)xtiles);
+#define PTSBE_QSPLIT(KV, NCV) hipLaunchKernelGGL((qform_split_kernel<KV, NCV>), grid, dim3(256), 0, stream, a)
+  if (a.lk_bits == 4) {
+    if (nc == 4) PTSBE_QSPLIT(16, 4); else if (nc == 2) PTSBE_QSPLIT(16, 2); else PTSBE_QSPLIT(16, 1);
+  } else if (a.lk_bits == 5) {
+    if (nc == 4) PTSBE_QSPLIT(32, 4); else if (nc == 2) PTSBE_QSPLIT(32, 2); else PTSBE_QSPLIT(32, 1);
+  } else {
+    return hipErrorInvalidValue;
+  }
+#undef PTSBE_QSPLIT
   return hipGetLastError();
 }
 bool ketjoin_supported(int lk_bits) { return lk_bits >= 2 && lk_bits <= 6; }
@@ -1168,14 +1190,17 @@ bool ketjoin_supported(int lk_bits) { return lk_bits >= 2 && lk_bits <= 6; }
 size_t qform_theta_bytes(int xT_bits, int lk_bits) { return (size_t)4 << (xT_bits + 2 * lk_bits); }
 
 hipError_t launch_theta_T(const float2* T, int64_t t_stride, int64_t n_traj, const int64_t* tab,
-                          const Plan::JoinDev& jd, int xT_bits, int lk_bits, float* Th, hipStream_t stream) {
+                          const Plan::JoinDev& jd, int xT_bits, int lk_bits, float* Th, int split,
+                          hipStream_t stream) {
   if (n_traj <= 0) return hipSuccess;
   if (!qform_supported(lk_bits)) return hipErrorInvalidValue;
   const dim3 grid(grid_blocks(n_traj << xT_bits));
   if (lk_bits == 4)
-    hipLaunchKernelGGL(theta_T_kernel<16>, grid, dim3(256), 0, stream, T, t_stride, n_traj, tab, jd, xT_bits, Th);
+    hipLaunchKernelGGL(theta_T_kernel<16>, grid, dim3(256), 0, stream, T, t_stride, n_traj, tab, jd, xT_bits, Th,
+                       split);
   else
-    hipLaunchKernelGGL(theta_T_kernel<32>, grid, dim3(256), 0, stream, T, t_stride, n_traj, tab, jd, xT_bits, Th);
+    hipLaunchKernelGGL(theta_T_kernel<32>, grid, dim3(256), 0, stream, T, t_stride, n_traj, tab, jd, xT_bits, Th,
+                       split);
   return hipGetLastError();
 }
 
