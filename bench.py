@@ -67,8 +67,8 @@ def main():
     ap.add_argument("--shots", type=int, default=1000)
     ap.add_argument("--workspace-gb", type=float, default=64.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--precision", choices=["c64", "bf16"], default="c64",
-                    help="bf16: split-precision (bf16 hi+lo) MFMA for the dense join")
+    ap.add_argument("--precision", choices=["c64", "bf16", "f16"], default="c64",
+                    help="bf16 / f16: split-precision (16-bit hi+lo, three products) MFMA for the dense join")
     ap.add_argument("--traffic-file", default=os.path.join(ROOT, "profiles", "join_traffic.txt"))
     ap.add_argument("--workload", choices=["brickwork50", "ragged"], default="brickwork50",
                     help="ragged: the ragged mix of circuits as one graph-captured ragged set")
@@ -103,7 +103,7 @@ def main():
     dev = torch.device("cuda:0")
     wl = W.config2()
     c = wl.circuit
-    plan = P.Plan(c, wl.batch_sizes, hypersamples=8, precision=1 if args.precision == "bf16" else 0)
+    plan = P.Plan(c, wl.batch_sizes, hypersamples=8, precision={"c64": 0, "bf16": 1, "f16": 2}[args.precision])
     kr, mult, _, n_draws = plan.sample_trajectories(wl.pts_seed, args.traj)
     E = len(kr)
     kd = torch.from_numpy(kr).to(dev)
@@ -141,13 +141,13 @@ def main():
         kv = dict(ln.split(":", 1) for ln in open(args.traffic_file) if ":" in ln and not ln.startswith("#"))
         if kv.get("kernel", "").strip() == JOIN_KERNEL_TAG and "bytes_per_launch" in kv:
             traffic = float(kv["bytes_per_launch"])
-    peak = FP32_MFMA_PEAK_TFLOPS if args.precision == "c64" else BF16_MFMA_PEAK_TFLOPS
+    peak = FP32_MFMA_PEAK_TFLOPS if args.precision == "c64" else BF16_MFMA_PEAK_TFLOPS   # fp16 dense = bf16 dense
     roofline = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                 "frac": achieved / peak, "traffic": traffic if args.precision == "c64" else None,
                 "kernel": "qform_mfma_kernel<32,4> (doubled-network join as a real GEMM over K^2 folded slots, "
                           "FP32 MFMA)" if args.precision == "c64"
-                          else "qform_split_kernel<32,4> (doubled-network join as the K^2-slot GEMM, bf16 hi+lo "
-                               "operands, three products on bf16 MFMA, FP32 accumulate)",
+                          else f"qform_split_kernel<32,4> (doubled-network join as the K^2-slot GEMM, {args.precision} "
+                               "hi+lo operands, three products on 16-bit MFMA, FP32 accumulate)",
                 "flops": "real bilinear form over K^2 folded slots: 2K^2 per row and x (K=32: 2048; "
                          "the plain complex product would be 8320)",
                 "launches": prof["join_launches"], "kernel_ms_per_step": prof["join_ms"] / args.steps}
@@ -155,7 +155,7 @@ def main():
         "metric": "sampled shots/sec", "value": shots_per_s, "unit": "shots/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "c64" if args.precision == "c64" else "c64+bf16x3",
+        "dtype": {"c64": "c64", "bf16": "c64+bf16x3", "f16": "c64+f16x3"}[args.precision],
         "data": "synthetic",
         "config": {"workload": f"50-qubit 1D brickwork depth 6, Haar SU(4) c64, depolarising p=0.005, "
                                f"{E} trajectories x {args.shots} shots, batches [10]*5, proportional NBS",

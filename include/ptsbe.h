@@ -124,10 +124,13 @@ typedef struct {
   const int32_t* batch_sizes;   /* [n_batches], each 1..30, sum == n_qubits     */
   int32_t hypersamples;         /* randomised path-search restarts (>= 1)        */
   uint64_t path_seed;
-  int32_t precision;            /* PTSBE_C64, or PTSBE_SPLIT_BF16: the dense join
-                                   of doubled networks (32 crossing-wire values)
-                                   runs as bf16 hi+lo three-product MFMA with
-                                   FP32 accumulation; everything else stays c64 */
+  int32_t precision;            /* PTSBE_C64, PTSBE_SPLIT_BF16 or PTSBE_SPLIT_F16:
+                                   the dense join of doubled networks (16 or 32
+                                   crossing-wire values) runs with hi+lo 16-bit
+                                   operands, three products on bf16 / fp16 MFMA
+                                   with FP32 accumulation (fp16: power-of-two
+                                   scaling per row and per x); everything else
+                                   stays c64 */
   int32_t device;               /* HIP device ordinal; -1: host-only plan (path,
                                    query and pre-sampling only, no device calls) */
   size_t device_budget_bytes;   /* 0: no limit; else plan constants must fit     */

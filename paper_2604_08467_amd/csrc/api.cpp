@@ -233,7 +233,8 @@ ptsbe_status_t run_batch(Plan& p, int j, const uint8_t* d_kraus, const float2* m
   const bool use_qform = bp.doubled && ptsbe::qform_supported(lkb);
   const bool use_ket = !bp.doubled && ptsbe::ketjoin_supported(lkb);
   const bool use_mfma = use_qform || use_ket;
-  const bool use_split = use_qform && p.precision == PTSBE_SPLIT_BF16 && ptsbe::qform_split_supported(lkb);
+  const bool use_split = use_qform && p.precision != PTSBE_C64 && ptsbe::qform_split_supported(lkb);
+  const int split_kind = !use_split ? 0 : (p.precision == PTSBE_SPLIT_F16 ? 2 : 1);
   const bool use_fold = use_qform;               // Theta layout (FP32, or bf16 hi + lo planes)
   const size_t layout_bytes = use_fold ? ptsbe::qform_theta_bytes((int)bp.xT.size(), lkb)
                                        : (use_mfma ? ((size_t)8 << rT) : 0);
@@ -296,7 +297,7 @@ ptsbe_status_t run_batch(Plan& p, int j, const uint8_t* d_kraus, const float2* m
       Th = (float*)ar.take((size_t)n_rt * layout_bytes);
       if (!Th) return fail(PTSBE_ERR_OUT_OF_MEMORY, "workspace too small (join layout)");
       HIP_TRY(ptsbe::launch_theta_T(T, (int64_t)1 << rT, n_rt, p.d_tables, p.join_dev[j], (int)bp.xT.size(),
-                                    lkb, Th, use_split ? 1 : 0, s));
+                                    lkb, Th, split_kind, s));
     } else if (use_mfma) {   // canonical [x][k][k'] (split doubled) or [x][k] (ket) layout
       Tc = (float2*)ar.take((size_t)n_rt * layout_bytes);
       if (!Tc) return fail(PTSBE_ERR_OUT_OF_MEMORY, "workspace too small (join layout)");
@@ -346,6 +347,8 @@ ptsbe_status_t run_batch(Plan& p, int j, const uint8_t* d_kraus, const float2* m
         qa.V = V; qa.v_stride = (int64_t)1 << rV; qa.v_base = a0;
         qa.Tc = Tc; qa.Th = Th; qa.traj_base = (int32_t)t0; qa.tslot = d_slot;
         qa.th_plane = n_rt * ((int64_t)1 << ((int)bp.xT.size() + 2 * lkb));
+        qa.th_scale = Th ? reinterpret_cast<const int32_t*>(reinterpret_cast<const uint16_t*>(Th) + 2 * qa.th_plane)
+                         : nullptr;
         int64_t tA = t0, tB = t1 - 1;
         while (tA + 1 < t1 && first[tA + 1] <= a0) ++tA;     // trajectory holding element a0
         while (tB > tA && first[tB] >= a1) --tB;             // trajectory holding element a1-1
@@ -363,7 +366,7 @@ ptsbe_status_t run_batch(Plan& p, int j, const uint8_t* d_kraus, const float2* m
         if (use_qform) {
           if (!qa.pop) return fail(PTSBE_ERR_INVALID_ARG, "population output required");
           if (use_split)
-            HIP_TRY(ptsbe::launch_qform_split(qa, (int)(tB - tA + 1), (int)max_rows, s));
+            HIP_TRY(ptsbe::launch_qform_split(qa, (int)(tB - tA + 1), (int)max_rows, split_kind == 2, s));
           else
             HIP_TRY(ptsbe::launch_qform(qa, (int)(tB - tA + 1), (int)max_rows, s));
         } else {
@@ -430,8 +433,8 @@ ptsbe_status_t ptsbe_plan(const ptsbe_circuit_t* c, const ptsbe_plan_opts_t* o, 
   if (c->n_channels > 0 && (!c->ch_arity || !c->ch_nkraus || !c->ch_kraus))
     return fail(PTSBE_ERR_INVALID_ARG, "bad channel arrays");
   if (o->n_batches < 1 || !o->batch_sizes) return fail(PTSBE_ERR_INVALID_ARG, "no batches");
-  if (o->precision != PTSBE_C64 && o->precision != PTSBE_SPLIT_BF16)
-    return fail(PTSBE_ERR_UNSUPPORTED, "precision must be PTSBE_C64 or PTSBE_SPLIT_BF16");
+  if (o->precision != PTSBE_C64 && o->precision != PTSBE_SPLIT_BF16 && o->precision != PTSBE_SPLIT_F16)
+    return fail(PTSBE_ERR_INVALID_ARG, "precision must be PTSBE_C64, PTSBE_SPLIT_BF16 or PTSBE_SPLIT_F16");
   auto p = new Plan();
   std::unique_ptr<Plan> guard(p);
   p->n = c->n_qubits;

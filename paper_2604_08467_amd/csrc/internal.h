@@ -275,7 +275,8 @@ struct QformArgs {
   const float2* V; int64_t v_stride; int64_t v_base;   // V rows of elements [v_base, ...)
   const float2* Tc;                                     // canonical [traj][x][k][k'] (split join, ket join)
   const float* Th;                                      // Theta [traj][x][K^2] (FP32), or its bf16 hi plane
-  int64_t th_plane;                                     // split join: bf16 elements from the hi to the lo plane
+  int64_t th_plane;                                     // split join: 16-bit elements from the hi to the lo plane
+  const int32_t* th_scale;                              // fp16 split: Theta exponent per (trajectory slot, x)
   int32_t traj_base;                                    // Tc index = traj - traj_base (or its slot)
   const int32_t* tslot;                                 // slot of each trajectory's Tc / Theta, or null
   int32_t traj0;                                        // trajectory of grid.y == 0
@@ -298,7 +299,7 @@ hipError_t launch_theta_T(const float2* T, int64_t t_stride, int64_t n_traj, con
 bool ketjoin_supported(int lk_bits);
 bool qform_split_supported(int lk_bits);
 // split-precision slot GEMM (bf16 hi + lo, three products, FP32 accumulate) of the doubled join
-hipError_t launch_qform_split(const QformArgs& a, int n_traj, int max_rows, hipStream_t stream);
+hipError_t launch_qform_split(const QformArgs& a, int n_traj, int max_rows, bool f16, hipStream_t stream);
 hipError_t launch_qform(const QformArgs& a, int n_traj, int max_rows, hipStream_t stream);
 hipError_t launch_ketjoin(const QformArgs& a, int n_traj, int max_rows, hipStream_t stream);
 hipError_t launch_row_totals(const float* pop, int64_t n_elems, int b, double* totals,

@@ -400,8 +400,17 @@ __global__ void __launch_bounds__(256) ketjoin_mfma_kernel(QformArgs a) {
 // theta_T_kernel: one workgroup per (trajectory, x) gathers T[x] into LDS through
 // the plan's tables and writes Theta[traj][x][f] (f contiguous).
 //
-// With split != 0 the kernel writes Theta as two bf16 planes (hi = bf16(theta),
-// lo = bf16(theta - hi)), hi at Th and lo at Th + n_traj 2^xT K^2 / 2 floats.
+// With split != 0 the kernel writes Theta as two 16-bit planes, hi = h(theta) and
+// lo = h(theta - hi), hi at Th and the lo plane n_traj 2^xT K^2 elements later:
+// split 1: bf16; split 2: fp16 of theta 2^s with s chosen per (trajectory, x) so
+// that max |theta| 2^s lies in [1/2, 1) (s stored as int32 after the lo plane).
+template <typename H>
+__device__ inline void put_split(H* hi, H* lo, int f, float v) {
+  const H h = (H)v;
+  hi[f] = h;
+  lo[f] = (H)(v - (float)h);
+}
+
 template <int K>
 __global__ void __launch_bounds__(256) theta_T_kernel(const float2* __restrict__ T, int64_t t_stride, int64_t n_traj,
                                                        const int64_t* __restrict__ tables, Plan::JoinDev jd,
@@ -410,6 +419,7 @@ __global__ void __launch_bounds__(256) theta_T_kernel(const float2* __restrict__
   constexpr int LK = K == 16 ? 4 : 5;
   static_assert(KK % 256 == 0, "K = 16 or 32");
   __shared__ float2 Ts[K][K + 1];
+  __shared__ float red[4];
   const int tid = threadIdx.x;
   const int lo_x = xT_bits < 12 ? xT_bits : 12;
   int64_t koff[PERT];
@@ -430,24 +440,39 @@ __global__ void __launch_bounds__(256) theta_T_kernel(const float2* __restrict__
       Ts[idx / K][idx % K] = Tx[koff[i]];
     }
     __syncthreads();
-    float* out = Th + g * KK;
-    __bf16* hi = reinterpret_cast<__bf16*>(Th) + g * KK;
-    __bf16* lo = reinterpret_cast<__bf16*>(Th) + (n_traj * nx + g) * KK;
+    float th[PERT];
+    float mx = 0.f;
 #pragma unroll
     for (int i = 0; i < PERT; ++i) {
       const int f = tid + 256 * i;
       const int a = f / K, b = f % K;
-      float th;
-      if (a == b) th = Ts[a][a].x;
-      else if (a < b) th = Ts[a][b].x + Ts[b][a].x;
-      else th = Ts[a][b].y - Ts[b][a].y;
-      if (split) {
-        const __bf16 h = (__bf16)th;
-        hi[f] = h;
-        lo[f] = (__bf16)(th - (float)h);
-      } else {
-        out[f] = th;
-      }
+      if (a == b) th[i] = Ts[a][a].x;
+      else if (a < b) th[i] = Ts[a][b].x + Ts[b][a].x;
+      else th[i] = Ts[a][b].y - Ts[b][a].y;
+      mx = fmaxf(mx, fabsf(th[i]));
+    }
+    if (split == 0) {
+      float* out = Th + g * KK;
+#pragma unroll
+      for (int i = 0; i < PERT; ++i) out[tid + 256 * i] = th[i];
+    } else if (split == 1) {
+      __bf16* hi = reinterpret_cast<__bf16*>(Th) + g * KK;
+      __bf16* lo = reinterpret_cast<__bf16*>(Th) + (n_traj * nx + g) * KK;
+#pragma unroll
+      for (int i = 0; i < PERT; ++i) put_split(hi, lo, tid + 256 * i, th[i]);
+    } else {
+#pragma unroll
+      for (int d = 32; d > 0; d >>= 1) mx = fmaxf(mx, __shfl_xor(mx, d));
+      if ((tid & 63) == 0) red[tid >> 6] = mx;
+      __syncthreads();
+      mx = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+      int ex = 0;
+      if (mx > 0.f) frexpf(mx, &ex);
+      _Float16* hi = reinterpret_cast<_Float16*>(Th) + g * KK;
+      _Float16* lo = reinterpret_cast<_Float16*>(Th) + (n_traj * nx + g) * KK;
+#pragma unroll
+      for (int i = 0; i < PERT; ++i) put_split(hi, lo, tid + 256 * i, ldexpf(th[i], -ex));
+      if (tid == 0) reinterpret_cast<int32_t*>(reinterpret_cast<_Float16*>(Th) + 2 * n_traj * nx * KK)[g] = -ex;
     }
     __syncthreads();
   }
@@ -601,13 +626,29 @@ __global__ void __launch_bounds__(256) qform_mfma_kernel(QformArgs a) {
   }
 }
 
-// Split-precision slot GEMM: M and Theta as hi + lo bf16 (hi = bf16(x),
-// lo = bf16(x - hi)), three products hi*hi + hi*lo + lo*hi per tile on
-// v_mfma_f32_16x16x32_bf16, FP32 accumulation.  One MFMA k-step covers 32 slots:
-// lane 16 q + j takes slots 8q..8q+7 of the step, for row j (A) or for x = 16c + j
-// (B).  Theta planes are staged in LDS two k-steps at a time (double-buffered).
-template <int K, int NC>
+// Split-precision slot GEMM: M and Theta as hi + lo 16-bit values (hi = h(x),
+// lo = h(x - hi)), three products hi*hi + hi*lo + lo*hi per tile on
+// v_mfma_f32_16x16x32_bf16 / _f16, FP32 accumulation.  One MFMA k-step covers 32
+// slots: lane 16 q + j takes slots 8q..8q+7 of the step, for row j (A) or for
+// x = 16c + j (B).  Theta planes are staged in LDS two k-steps at a time
+// (double-buffered).  fp16 (F16): each row's M is scaled by 2^e_r with max |v|^2
+// 2^e_r in [1/2, 1) (|M_f| <= max |v|^2), Theta by its stored 2^e_x, and the FP32
+// result is multiplied by 2^-(e_r + e_x) (exact).
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+template <bool F16> struct Split16;
+template <> struct Split16<false> {
+  typedef __bf16 E; typedef bf16x8 V;
+  static __device__ floatx4 mfma(V x, V y, floatx4 c) { return __builtin_amdgcn_mfma_f32_16x16x32_bf16(x, y, c, 0, 0, 0); }
+};
+template <> struct Split16<true> {
+  typedef _Float16 E; typedef f16x8 V;
+  static __device__ floatx4 mfma(V x, V y, floatx4 c) { return __builtin_amdgcn_mfma_f32_16x16x32_f16(x, y, c, 0, 0, 0); }
+};
+
+template <int K, int NC, bool F16>
 __global__ void __launch_bounds__(256) qform_split_kernel(QformArgs a) {
+  typedef typename Split16<F16>::E E;
+  typedef typename Split16<F16>::V bf16x8;
   constexpr int ROWS = 64, KK = K * K, XT = 16 * NC, NST = KK / 32, KS = 2, NCH = NST / KS;
   constexpr int U16 = KS * 2 * XT * 4;            // 16-byte units of Theta per chunk
   static_assert(NCH >= 1 && NST % KS == 0, "chunking");
@@ -650,7 +691,7 @@ __global__ void __launch_bounds__(256) qform_split_kernel(QformArgs a) {
   }
   // Theta planes: hi at a.Th (bf16), lo n_all = (#slots of the launch's trajectories) later
   const int32_t ts = a.tslot ? a.tslot[t - a.traj_base] : t - a.traj_base;
-  const __bf16* Hp = reinterpret_cast<const __bf16*>(a.Th) + ((int64_t)ts * nx + x0) * KK;
+  const E* Hp = reinterpret_cast<const E*>(a.Th) + ((int64_t)ts * nx + x0) * KK;
   const int64_t plane = a.th_plane;                   // elements between the hi and lo planes
   // chunk loader: 16-byte unit u = (plane, k-step, x, q) with q fastest; every lane
   // loads (rows past the tile's x read row x0, in bounds) and masks when storing
@@ -682,6 +723,24 @@ __global__ void __launch_bounds__(256) qform_split_kernel(QformArgs a) {
   float2 vb[8];
 #pragma unroll
   for (int i = 0; i < 8; ++i) vb[i] = Vs[rl][(8 * (q % (4 / BQ)) + i) & (K - 1)];
+  // fp16: row scale 2^er from max |v|^2 over the row (lanes 16 q + j, q = 0..3, share row j)
+  int er = 0;
+  float rsc = 1.f;
+  if constexpr (F16) {
+    float mr = 0.f;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) mr = fmaxf(mr, vb[i].x * vb[i].x + vb[i].y * vb[i].y);
+    if (K == 32) {                                    // K = 16: 8 (q % 2) + i covers the row already
+      mr = fmaxf(mr, __shfl_xor(mr, 16));
+      mr = fmaxf(mr, __shfl_xor(mr, 32));
+    } else {
+      mr = fmaxf(mr, __shfl_xor(mr, 16));
+    }
+    int ex = 0;
+    if (mr > 0.f) frexpf(mr, &ex);
+    er = -ex;
+    rsc = ldexpf(1.f, er);
+  }
   const int nout = 1 << a.b;
   int64_t obase[4];
 #pragma unroll
@@ -720,17 +779,17 @@ __global__ void __launch_bounds__(256) qform_split_kernel(QformArgs a) {
         const float2 w = vb[i];
         const float R = va.x * w.x + va.y * w.y;       // Re(v_a conj v_b)
         const float I = w.y * va.x - w.x * va.y;       // Im(v_b conj v_a)
-        const float m = av <= b0 + i ? R : I;
-        const __bf16 h = (__bf16)m;
+        const float m = (av <= b0 + i ? R : I) * rsc;
+        const E h = (E)m;
         ah[i] = h;
-        al[i] = (__bf16)(m - (float)h);
+        al[i] = (E)(m - (float)h);
       }
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
         const bf16x8 bh = Tb[buf][ks][0][c][lane], bl = Tb[buf][ks][1][c][lane];
-        acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc[c], 0, 0, 0);
-        acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc[c], 0, 0, 0);
-        acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc[c], 0, 0, 0);
+        acc[c] = Split16<F16>::mfma(ah, bh, acc[c]);
+        acc[c] = Split16<F16>::mfma(ah, bl, acc[c]);
+        acc[c] = Split16<F16>::mfma(al, bh, acc[c]);
       }
     }
     if (more) {
@@ -741,14 +800,22 @@ __global__ void __launch_bounds__(256) qform_split_kernel(QformArgs a) {
     __syncthreads();
   }
   const int lo_x = a.xT_bits < 12 ? a.xT_bits : 12;
+  // fp16: the output rows' scales (row 4 q + i of the wave is held by lane 4 q + i)
+  int eo[4] = {0, 0, 0, 0};
+  if constexpr (F16) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) eo[i] = __shfl(er, 4 * q + i);
+  }
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
     const int xl = 16 * c + (lane & 15);
     if (xl < xv) {
       const int64_t ox = tab(a.tab, a.jd.ox_lo, a.jd.ox_hi, lo_x, (uint32_t)(x0 + xl));
+      int exs = 0;
+      if constexpr (F16) exs = a.th_scale[(int64_t)ts * nx + x0 + xl];
 #pragma unroll
       for (int i = 0; i < 4; ++i)
-        if (obase[i] >= 0) a.pop[obase[i] + ox] = acc[c][i];
+        if (obase[i] >= 0) a.pop[obase[i] + ox] = F16 ? ldexpf(acc[c][i], -(eo[i] + exs)) : acc[c][i];
     }
   }
 }
@@ -1167,14 +1234,18 @@ hipError_t launch_permute_T(const float2* T, int64_t t_stride, int64_t n_traj, c
 bool qform_supported(int lk_bits) { return lk_bits == 4 || lk_bits == 5; }
 bool qform_split_supported(int lk_bits) { return lk_bits == 4 || lk_bits == 5; }
 
-hipError_t launch_qform_split(const QformArgs& a, int n_traj, int max_rows, hipStream_t stream) {
+hipError_t launch_qform_split(const QformArgs& a, int n_traj, int max_rows, bool f16, hipStream_t stream) {
   if (n_traj <= 0 || max_rows <= 0) return hipSuccess;
   const int tiles = (max_rows + 63) / 64;
   const int nx = 1 << a.xT_bits;
   const int nc = nx >= 64 ? 4 : (nx >= 32 ? 2 : 1);
   const int xtiles = (nx + 16 * nc - 1) / (16 * nc);
   dim3 grid((unsigned)tiles, (unsigned)n_traj, (unsigned)xtiles);
-#define PTSBE_QSPLIT(KV, NCV) hipLaunchKernelGGL((qform_split_kernel<KV, NCV>), grid, dim3(256), 0, stream, a)
+#define PTSBE_QSPLIT(KV, NCV)                                                                         \
+  do {                                                                                                \
+    if (f16) hipLaunchKernelGGL((qform_split_kernel<KV, NCV, true>), grid, dim3(256), 0, stream, a);  \
+    else hipLaunchKernelGGL((qform_split_kernel<KV, NCV, false>), grid, dim3(256), 0, stream, a);     \
+  } while (0)
   if (a.lk_bits == 4) {
     if (nc == 4) PTSBE_QSPLIT(16, 4); else if (nc == 2) PTSBE_QSPLIT(16, 2); else PTSBE_QSPLIT(16, 1);
   } else if (a.lk_bits == 5) {
@@ -1187,7 +1258,9 @@ hipError_t launch_qform_split(const QformArgs& a, int n_traj, int max_rows, hipS
 }
 bool ketjoin_supported(int lk_bits) { return lk_bits >= 2 && lk_bits <= 6; }
 
-size_t qform_theta_bytes(int xT_bits, int lk_bits) { return (size_t)4 << (xT_bits + 2 * lk_bits); }
+size_t qform_theta_bytes(int xT_bits, int lk_bits) {
+  return ((size_t)4 << (xT_bits + 2 * lk_bits)) + ((size_t)4 << xT_bits);   // + fp16 split scales
+}
 
 hipError_t launch_theta_T(const float2* T, int64_t t_stride, int64_t n_traj, const int64_t* tab,
                           const Plan::JoinDev& jd, int xT_bits, int lk_bits, float* Th, int split,

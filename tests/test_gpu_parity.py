@@ -360,15 +360,18 @@ def test_config2_full_size_properties():
 
 
 # ------------------------------------------------------- split precision (BF16)
-def test_config2_split_bf16_error_vs_fp64():
-    """The BF16 split-precision join against the FP64 explicit-network oracle on
-    sampled elements, and against the complex64 path on every element of a batch.
-    The error is stated (printed); the bound checked is a sanity bound."""
+@pytest.mark.parametrize("prec", [1, 2], ids=["bf16", "f16"])
+def test_config2_split_bf16_error_vs_fp64(prec):
+    """The split-precision join (bf16, or fp16 with power-of-two scaling) against
+    the FP64 explicit-network oracle on sampled elements, and against the complex64
+    path on every element of a batch.  The error is stated (printed); the bound
+    checked is a sanity bound."""
     torch, dev = torch_dev()
     wl = W.config2()
     c = wl.circuit
     plan64 = _plan(c, wl.batch_sizes)
-    plan16 = _plan(c, wl.batch_sizes, precision=1)
+    plan16 = _plan(c, wl.batch_sizes, precision=prec)
+    tag = "split-bf16" if prec == 1 else "split-f16"
     kr, mult, _, _ = plan64.sample_trajectories(wl.pts_seed, 32)
     kd = to_dev(torch, dev, kr)
     out = plan64.sample_shots(kd, to_dev(torch, dev, np.full(len(kr), 40, dtype=np.int64)), 3)
@@ -382,7 +385,7 @@ def test_config2_split_bf16_error_vs_fp64():
         pop, tot = _contract(plan16, torch, dev, kd, [i], [p], j)
         err = np.abs(pop[0] / tot[0] - ref / ref.sum()).max()
         worst_fp64 = max(worst_fp64, err)
-        _say(f"split-bf16 j={j}: conditional max abs error vs FP64 {err:.3g}")
+        _say(f"{tag} j={j}: conditional max abs error vs FP64 {err:.3g}")
     assert worst_fp64 < 1e-4
     # every element of batch 2 for all 32 trajectories: split vs complex64
     traj = np.repeat(np.arange(len(kr)), 40)
@@ -390,5 +393,5 @@ def test_config2_split_bf16_error_vs_fp64():
     p64, t64 = _contract(plan64, torch, dev, kd, traj, pre, 2)
     p16, t16 = _contract(plan16, torch, dev, kd, traj, pre, 2)
     d = np.abs(p16 / t16[:, None] - p64 / t64[:, None]).max()
-    _say(f"split-bf16 vs complex64, batch 2, {len(traj)} elements: max abs conditional difference {d:.3g}")
+    _say(f"{tag} vs complex64, batch 2, {len(traj)} elements: max abs conditional difference {d:.3g}")
     assert d < 1e-4
