@@ -723,6 +723,10 @@ ptsbe_status_t ptsbe_plan(const ptsbe_circuit_t* c, const ptsbe_plan_opts_t* o, 
       }
       HIP_TRY(hipMalloc(&p->d_rg_win[i], std::max<size_t>(1, w.size()) * sizeof(ptsbe::RgWindow)));
       HIP_TRY(hipMemcpy(p->d_rg_win[i], w.data(), w.size() * sizeof(ptsbe::RgWindow), hipMemcpyHostToDevice));
+      const auto& cl = p->sv_cl[i];
+      HIP_TRY(hipMalloc(&p->d_sv_cl[i], std::max<size_t>(1, cl.size()) * sizeof(ptsbe::ClusterDesc)));
+      if (!cl.empty())
+        HIP_TRY(hipMemcpy(p->d_sv_cl[i], cl.data(), cl.size() * sizeof(ptsbe::ClusterDesc), hipMemcpyHostToDevice));
     }
   }
   if (!p->sv_steps.empty()) {
@@ -751,6 +755,8 @@ void ptsbe_plan_destroy(ptsbe_plan_t plan) {
   if (p->d_fused) (void)hipFree(p->d_fused);
   for (auto* w : p->d_rg_win)
     if (w) (void)hipFree(w);
+  for (auto* c : p->d_sv_cl)
+    if (c) (void)hipFree(c);
   delete p;
 }
 

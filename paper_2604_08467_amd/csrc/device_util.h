@@ -80,27 +80,171 @@ __device__ void merge_gate(const GateCtx& g, int gate, int traj, float2* out) {
 // Gate matrices of a window are staged in LDS kGateChunk steps at a time (16
 // entries each), so that every step reads its matrix with LDS broadcasts.
 constexpr int kGateChunk = 32;
+static_assert(kGateChunk == kGateChunkHost, "the planner splits gate clusters at the same chunk boundary");
+typedef float floatx4_t __attribute__((ext_vector_type(4)));
+
+// Product U = G_L ... G_1 of a gate cluster (L plain steps fs[0..L) on the 4
+// tile positions cp = fs[0].cl_pos), a 16 x 16 matrix on the cluster's 4 bits
+// (bit i of a cluster state = tile bit cp[i]; bits no member touches act as
+// identity), built in LDS by 256 threads (one entry each) from the gate matrices
+// G (16 per step).  Ua / Ub: 256 entries each.  Returns the buffer holding U.
+__device__ inline float2* build_cluster(const FusedStep* fs, int L, const float2* G, float2* Ua, float2* Ub) {
+  const int tid = threadIdx.x;
+  int cp[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) cp[i] = fs[0].cl_pos[i];
+  {
+    const int r = tid >> 4, c = tid & 15;
+    Ua[tid] = make_float2(r == c ? 1.f : 0.f, 0.f);
+  }
+  __syncthreads();
+  for (int m = 0; m < L; ++m) {           // U <- G_m U
+    const FusedStep& st = fs[m];
+    const float2* Gm = G + 16 * m;
+    int cb0 = 0, cb1 = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      if (cp[i] == st.kloc[0]) cb0 = i;
+      if (st.nK == 2 && cp[i] == st.kloc[1]) cb1 = i;
+    }
+    const int r = tid >> 4, c = tid & 15;
+    float2 acc = make_float2(0.f, 0.f);
+    if (st.nK == 1) {
+      const int n = (r >> cb0) & 1;
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        const int rk = (r & ~(1 << cb0)) | (k << cb0);
+        acc = cfma(Gm[st.nB[n] + st.kB[k]], Ua[rk * 16 + c], acc);
+      }
+    } else {
+      const int n = ((r >> cb0) & 1) | (((r >> cb1) & 1) << 1);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int rk = (r & ~((1 << cb0) | (1 << cb1))) | ((k & 1) << cb0) | ((k >> 1) << cb1);
+        acc = cfma(Gm[st.nB[n] + st.kB[k]], Ua[rk * 16 + c], acc);
+      }
+    }
+    Ub[tid] = acc;
+    __syncthreads();
+    float2* t = Ua; Ua = Ub; Ub = t;
+  }
+  return Ua;
+}
+
+// Apply a gate cluster's matrix U (16 x 16, row-major, built beforehand; in
+// global memory) to the tile: [Yr; Yi] = [[Ur, -Ui], [Ui, Ur]] [Xr; Xi] on
+// v_mfma_f32_16x16x4f32, 32 x 32 times 32 x 2^(np-4) (tile columns = the other
+// np - 4 bits), each wavefront on its own quarter of the columns, so that it
+// reads and then overwrites only its own entries.  Needs blockDim.x == 256 and
+// np >= 10.  Ends with a barrier.
+__device__ inline void apply_cluster(const int* cl_pos, const float2* __restrict__ U, int np, float2* tile) {
+  const int tid = threadIdx.x;
+  int cp[4], cs[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) cp[i] = cs[i] = cl_pos[i];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)              // ascending copy, for the column deposit
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      if (cs[k] > cs[k + 1]) { const int t = cs[k]; cs[k] = cs[k + 1]; cs[k + 1] = t; }
+  // A fragments: lane holds A[16 rt + lane % 16][4 s + lane / 16]; columns 4s+q and 4(s-4)+q coincide
+  const int lane = tid & 63, wave = tid >> 6, q = lane >> 4, j = lane & 15;
+  float2 u4[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) u4[s] = U[j * 16 + 4 * s + q];
+  float af[2][8];
+#pragma unroll
+  for (int s = 0; s < 8; ++s) {
+    const float2 u = u4[s & 3];
+    af[0][s] = s < 4 ? u.x : -u.y;        // [Ur, -Ui]
+    af[1][s] = s < 4 ? u.y : u.x;         // [Ui,  Ur]
+  }
+  auto soff = [&](int v) -> uint32_t {
+    return ((uint32_t)(v & 1) << cp[0]) | ((uint32_t)((v >> 1) & 1) << cp[1]) |
+           ((uint32_t)((v >> 2) & 1) << cp[2]) | ((uint32_t)((v >> 3) & 1) << cp[3]);
+  };
+  auto colbase = [&](uint32_t col) -> uint32_t {   // insert zero bits at the cluster positions
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const uint32_t lo = col & ((1u << cs[i]) - 1u);
+      col = ((col >> cs[i]) << (cs[i] + 1)) | lo;
+    }
+    return col;
+  };
+  const int ncol = 1 << (np - 4), per_wave = ncol >> 2, nct = per_wave >> 4;
+  floatx4_t acc[2][4];
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct) {
+    acc[0][ct] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+    acc[1][ct] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+    if (ct < nct) {
+      const uint32_t cb = colbase((uint32_t)(wave * per_wave + 16 * ct + j));
+#pragma unroll
+      for (int s = 0; s < 8; ++s) {
+        const float2 x = tile[cb + soff((4 * s + q) & 15)];
+        const float b = s < 4 ? x.x : x.y;
+        acc[0][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[0][s], b, acc[0][ct], 0, 0, 0);
+        acc[1][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[1][s], b, acc[1][ct], 0, 0, 0);
+      }
+    }
+  }
+  // D[16 rt + 4 q + i][col]: state 4 q + i, real part from rt = 0, imaginary from rt = 1
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct)
+    if (ct < nct) {
+      const uint32_t cb = colbase((uint32_t)(wave * per_wave + 16 * ct + j));
+#pragma unroll
+      for (int i = 0; i < 4; ++i) tile[cb + soff(4 * q + i)] = make_float2(acc[0][ct][i], acc[1][ct][i]);
+    }
+  __syncthreads();
+}
 
 // One tile pass of a window of in-place steps (positions P, |P| = np, of a rank-r
 // tensor A of one job): the 2^np entries whose other bits equal the tile index t
 // are loaded into LDS, every step is applied there (gate operands of trajectory
 // traj, staged in Gm[16 * kGateChunk]), and the tile is written back.  pw: the job's
-// prefix words in LDS (for sliced legs).  Ends with a barrier, so the caller may
+// prefix words in LDS (for sliced legs); Ucl: the job's gate-cluster matrices,
+// used when CLUSTERS (else the steps of a cluster run one by one); gates_ready:
+// Gm already holds the first kGateChunk gates of these steps for traj (the
+// previous pass of this workgroup had the same steps and trajectory and at most
+// kGateChunk of them).  blockDim.x == 256.  Ends with a barrier, so the caller may
 // reuse tile and Gm at once.
+// Offsets of a tile's entries l = threadIdx.x + 256 i (blockDim.x == 256): the
+// tile-local bits 0..7 come from the thread, bits 8.. from i.
+__device__ inline uint32_t tile_lo_offset(const int* P, int np) {
+  uint32_t off = 0;
+  const uint32_t l = threadIdx.x;
+  for (int b = 0; b < np && b < 8; ++b) off |= ((l >> b) & 1u) << P[b];
+  return off;
+}
+__device__ inline uint32_t tile_hi_offset(const int* P, int np, uint32_t i) {
+  uint32_t off = 0;
+  for (int b = 8; b < np; ++b) off |= ((i >> (b - 8)) & 1u) << P[b];
+  return off;
+}
+
+template <bool CLUSTERS = false>
 __device__ inline void window_tile_pass(const FusedStep* fs, int n_fs, const int* P, int np, int r, uint32_t t,
                                         float2* Aj, const GateCtx& g_, int traj, const uint64_t* pw,
-                                        float2* tile, float2* Gm) {
+                                        float2* tile, float2* Gm, const float2* Ucl, bool gates_ready = false) {
   const uint32_t base = deposit_tile(t, P, np, r);
   const uint32_t nt = 1u << np;
-  for (uint32_t l = threadIdx.x; l < nt; l += blockDim.x) {
-    uint32_t off = base;
-    for (int i = 0; i < np; ++i) off |= ((l >> i) & 1u) << P[i];
-    tile[l] = Aj[off];
+  constexpr int kPer = (1 << kFuseMax) / 256;      // entries per thread at most
+  const uint32_t lo = base | tile_lo_offset(P, np);
+  {
+    // all of the thread's loads in flight before the first LDS write
+    float2 v[kPer];
+#pragma unroll
+    for (int i = 0; i < kPer; ++i)
+      if (threadIdx.x + 256u * i < nt) v[i] = Aj[lo | tile_hi_offset(P, np, (uint32_t)i)];
+#pragma unroll
+    for (int i = 0; i < kPer; ++i)
+      if (threadIdx.x + 256u * i < nt) tile[threadIdx.x + 256u * i] = v[i];
   }
   __syncthreads();   // the tile is complete before any step reads it
   for (int s = 0; s < n_fs; ++s) {
     const FusedStep& st = fs[s];
-    if (s % kGateChunk == 0) {   // every thread is past step s - 1 (it ended with a barrier)
+    if (s % kGateChunk == 0 && !(s == 0 && gates_ready)) {   // every thread is past step s - 1 (barrier)
       const int cnt = (n_fs - s < kGateChunk ? n_fs - s : kGateChunk) * 16;
       for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
         const FusedStep& sj = fs[s + i / 16];
@@ -109,6 +253,11 @@ __device__ inline void window_tile_pass(const FusedStep* fs, int n_fs, const int
       __syncthreads();
     }
     const float2* G = Gm + 16 * (s % kGateChunk);
+    if (CLUSTERS && st.cl_len > 0) {   // a gate cluster on MFMA, matrix built beforehand (ends with a barrier)
+      apply_cluster(st.cl_pos, Ucl + 256 * st.cl_id, np, tile);
+      s += st.cl_len - 1;        // the cluster lies inside one staged chunk
+      continue;
+    }
     // a plain gate applied in place: no hyper or sliced legs, outputs where the inputs were
     const bool plain = st.nH == 0 && st.nS == 0 && st.nK == st.nN && st.nK >= 1 && st.nK <= 2 &&
                        st.noff[1] == st.koff[1] && (st.nK == 1 || (st.noff[2] == st.koff[2] && st.noff[3] == st.koff[3]));
@@ -227,11 +376,9 @@ __device__ inline void window_tile_pass(const FusedStep* fs, int n_fs, const int
     }
     __syncthreads();
   }
-  for (uint32_t l = threadIdx.x; l < nt; l += blockDim.x) {
-    uint32_t off = base;
-    for (int i = 0; i < np; ++i) off |= ((l >> i) & 1u) << P[i];
-    Aj[off] = tile[l];
-  }
+#pragma unroll
+  for (int i = 0; i < kPer; ++i)
+    if (threadIdx.x + 256u * i < nt) Aj[lo | tile_hi_offset(P, np, (uint32_t)i)] = tile[threadIdx.x + 256u * i];
   __syncthreads();
 }
 

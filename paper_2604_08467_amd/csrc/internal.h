@@ -84,11 +84,25 @@ struct FusedStep {
   int32_t kB[16], nB[16];
   int32_t h_inP[4], h_pos[4], hw[4];
   int32_t sq[kMaxSlices], sw[kMaxSlices];
+  // gate cluster (statevector windows): on the first step of a cluster, cl_len > 0
+  // consecutive plain steps act on the 4 distinct tile-local positions cl_pos and
+  // are applied together as one 16 x 16 matrix on MFMA (matrix cl_id of the
+  // window set's cluster table, built per trajectory beforehand); 0 elsewhere
+  int32_t cl_len, cl_id;
+  int32_t cl_pos[4];
+};
+
+// A gate cluster of a statevector window set: steps [first, first + len) of the
+// plan's fused-step list on the tile-local positions pos.
+struct ClusterDesc {
+  int32_t first, len;
+  int32_t pos[4];
 };
 
 // A run of steps executed by one launch: either one absorb step, or a fused
 // run of in-place steps whose positions lie in P (|P| = np <= kFuseMax).
 constexpr int kFuseMax = 12;
+constexpr int kGateChunkHost = 32;    // gate matrices staged per window pass (device: kGateChunk)
 constexpr int kSvWindowMin = 10;      // smallest statevector window the autotuner tries
 struct Segment {
   int first = 0, count = 1;
@@ -190,6 +204,8 @@ struct Plan {
   // sv_win[i] holds windows of at most kSvWindowMin + i qubits
   std::vector<Segment> sv_win[3];
   RgWindow* d_rg_win[3] = {nullptr, nullptr, nullptr};   // the same windows on the device
+  std::vector<ClusterDesc> sv_cl[3];              // gate clusters of each window set
+  ClusterDesc* d_sv_cl[3] = {nullptr, nullptr, nullptr};
   // fused in-place steps of every part and of the statevector schedule
   std::vector<FusedStep> fused;
   FusedStep* d_fused = nullptr;
@@ -254,7 +270,12 @@ hipError_t launch_fill_one(float2* buf, int64_t n, hipStream_t stream);
 // A fused run of in-place steps on every job's tensor (rank seg.r), in place.
 hipError_t launch_fused(const Segment& seg, const FusedStep* d_fs, GateCtx g, int64_t n_jobs,
                         const int32_t* job_traj, int32_t traj_base, const uint64_t* job_prefix, int NW,
-                        float2* A, hipStream_t stream);
+                        float2* A, hipStream_t stream,
+                        const float2* Ucl = nullptr, int n_cl = 0);
+// Gate-cluster matrices of a window set for n_jobs trajectories: Ucl[job][c][16 x 16]
+// = the product of cluster c's gates (merged operands of the job's trajectory).
+hipError_t launch_cluster_build(const ClusterDesc* d_cl, int n_cl, const FusedStep* d_fused, GateCtx g, int64_t n_jobs,
+                                const int32_t* job_traj, int32_t traj_base, float2* Ucl, hipStream_t stream);
 
 struct JoinArgs {
   const float2* V; int64_t v_stride;     // per element
@@ -400,7 +421,8 @@ hipError_t launch_sv_marginal(const SvMargArgs& a, hipStream_t stream);
 hipError_t launch_sv_amplitudes(const SvMargArgs& a, float2* amp, hipStream_t stream);
 // Elements of a trajectory range [t0, t0 + count): one element per trajectory.
 // statevector method drivers (sv.cpp)
-ptsbe_status_t sv_evolve(const Plan& p, const GateCtx& g, int64_t t0, int64_t nj, float2* psi, hipStream_t s);
+ptsbe_status_t sv_evolve(const Plan& p, const GateCtx& g, int64_t t0, int64_t nj, float2* psi, float2* Ucl,
+                         hipStream_t s);
 size_t sv_sample_workspace(const Plan& p, int64_t E, int64_t M);
 size_t sv_contract_workspace(const Plan& p, int j, int64_t E, int64_t n_elems);
 ptsbe_status_t sv_sample_shots(Plan& p, const uint8_t* d_kraus, int64_t E, const int64_t* d_mult,

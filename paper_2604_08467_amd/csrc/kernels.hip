@@ -14,6 +14,8 @@
 //    (prefix, x) of an element's shots become the next batch's elements.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "device_util.h"
 #include "internal.h"
 #include "philox.h"
@@ -182,9 +184,34 @@ struct FusedArgs {
   int r, np;
   int P[kFuseMax];
   int64_t tiles_per_job;
+  const float2* Ucl; int n_cl;    // gate-cluster matrices [job][n_cl][256], or null
 };
 
 
+// Gate-cluster matrices, one workgroup per (job, cluster): the members' merged
+// gate matrices of the job's trajectory are staged in LDS and multiplied up.
+__global__ void __launch_bounds__(256) cluster_build_kernel(const ClusterDesc* __restrict__ cl, int n_cl,
+                                                           const FusedStep* __restrict__ fused, GateCtx g,
+                                                           int64_t n_jobs, const int32_t* __restrict__ job_traj,
+                                                           int32_t traj_base, float2* __restrict__ Ucl) {
+  __shared__ float2 Gm[16 * kGateChunk];
+  __shared__ float2 Ua[256], Ub[256];
+  for (int64_t bid = blockIdx.x; bid < n_jobs * n_cl; bid += gridDim.x) {
+    const int64_t job = bid / n_cl;
+    const int c = (int)(bid % n_cl);
+    const int traj = job_traj ? job_traj[job] : traj_base + (int)job;
+    const ClusterDesc& cd = cl[c];
+    const FusedStep* fs = fused + cd.first;
+    for (int i = threadIdx.x; i < 16 * cd.len; i += blockDim.x)
+      Gm[i] = gate_entry(g, fs[i / 16].gate, traj, fs[i / 16].conj, i % 16);
+    __syncthreads();
+    const float2* U = build_cluster(fs, cd.len, Gm, Ua, Ub);
+    Ucl[bid * 256 + threadIdx.x] = U[threadIdx.x];
+    __syncthreads();   // Gm, Ua, Ub are reused by the next (job, cluster) of this workgroup
+  }
+}
+
+template <bool CLUSTERS>
 __global__ void __launch_bounds__(256) fused_inplace_kernel(FusedArgs f, GateCtx g, int64_t n_jobs,
                                                            const int32_t* __restrict__ job_traj, int32_t traj_base,
                                                            const uint64_t* __restrict__ job_prefix, int NW,
@@ -192,12 +219,21 @@ __global__ void __launch_bounds__(256) fused_inplace_kernel(FusedArgs f, GateCtx
   extern __shared__ float2 tile[];
   float2* Gm = tile + ((int64_t)1 << f.np);
   __shared__ uint64_t pw[16];
-  for (int64_t bid = blockIdx.x; bid < n_jobs * f.tiles_per_job; bid += gridDim.x) {
+  // each workgroup takes a contiguous range of (job, tile) pairs, so that
+  // consecutive tiles of one job reuse the staged gate matrices
+  const int64_t total = n_jobs * f.tiles_per_job;
+  const int64_t per = (total + gridDim.x - 1) / gridDim.x;
+  const int64_t b0 = (int64_t)blockIdx.x * per, b1 = b0 + per < total ? b0 + per : total;
+  int last_traj = -1;
+  for (int64_t bid = b0; bid < b1; ++bid) {
     const int64_t job = bid / f.tiles_per_job;
     const uint32_t t = (uint32_t)(bid % f.tiles_per_job);
     const int traj = job_traj ? job_traj[job] : traj_base + (int)job;
     if ((int)threadIdx.x < NW) pw[threadIdx.x] = job_prefix ? job_prefix[job * NW + threadIdx.x] : 0ull;
-    window_tile_pass(f.fs, f.n_fs, f.P, f.np, f.r, t, A + (job << f.r), g, traj, pw, tile, Gm);   // ends with a barrier
+    const bool ready = traj == last_traj && f.n_fs <= kGateChunk;
+    window_tile_pass<CLUSTERS>(f.fs, f.n_fs, f.P, f.np, f.r, t, A + (job << f.r), g, traj, pw, tile, Gm,
+                               CLUSTERS ? f.Ucl + job * (int64_t)f.n_cl * 256 : nullptr, ready);   // ends with a barrier
+    last_traj = traj;
   }
 }
 
@@ -1193,9 +1229,12 @@ hipError_t launch_absorb_global(const AbsorbStep& st, const AbsorbStep* d_st, Ga
 }
 
 hipError_t launch_fused(const Segment& seg, const FusedStep* d_fs, GateCtx g, int64_t n_jobs, const int32_t* job_traj,
-                        int32_t traj_base, const uint64_t* job_prefix, int NW, float2* A, hipStream_t stream) {
+                        int32_t traj_base, const uint64_t* job_prefix, int NW, float2* A, hipStream_t stream,
+                        const float2* Ucl, int n_cl) {
   if (n_jobs <= 0) return hipSuccess;
   FusedArgs f{};
+  f.Ucl = seg.np >= 10 ? Ucl : nullptr;
+  f.n_cl = n_cl;
   f.fs = d_fs + seg.fused_off;
   f.n_fs = seg.count;
   f.r = seg.r;
@@ -1203,8 +1242,23 @@ hipError_t launch_fused(const Segment& seg, const FusedStep* d_fs, GateCtx g, in
   for (int i = 0; i < kFuseMax; ++i) f.P[i] = seg.P[i];
   f.tiles_per_job = (int64_t)1 << (seg.r - seg.np);
   const size_t shmem = (((size_t)1 << seg.np) + 16 * kGateChunk) * sizeof(float2);
-  hipLaunchKernelGGL(fused_inplace_kernel, dim3(grid_blocks(f.tiles_per_job * n_jobs)), dim3(256), shmem, stream, f, g,
-                     n_jobs, job_traj, traj_base, job_prefix, NW, A);
+  // a few workgroups per CU, each walking a contiguous range of tiles
+  const int64_t total = f.tiles_per_job * n_jobs;
+  const dim3 grid((unsigned)std::min<int64_t>(total, 8192));
+  if (f.Ucl)
+    hipLaunchKernelGGL(fused_inplace_kernel<true>, grid, dim3(256), shmem, stream, f, g, n_jobs, job_traj, traj_base,
+                       job_prefix, NW, A);
+  else
+    hipLaunchKernelGGL(fused_inplace_kernel<false>, grid, dim3(256), shmem, stream, f, g, n_jobs, job_traj, traj_base,
+                       job_prefix, NW, A);
+  return hipGetLastError();
+}
+
+hipError_t launch_cluster_build(const ClusterDesc* d_cl, int n_cl, const FusedStep* d_fused, GateCtx g, int64_t n_jobs,
+                                const int32_t* job_traj, int32_t traj_base, float2* Ucl, hipStream_t stream) {
+  if (n_jobs <= 0 || n_cl <= 0) return hipSuccess;
+  hipLaunchKernelGGL(cluster_build_kernel, dim3(grid_blocks(n_jobs * n_cl)), dim3(256), 0, stream, d_cl, n_cl, d_fused,
+                     g, n_jobs, job_traj, traj_base, Ucl);
   return hipGetLastError();
 }
 

@@ -610,7 +610,72 @@ void build_sv_batches(Plan& p) {
 namespace {
 // Windows of at most `wmax` qubits (see build_sv_schedule); appends the fused
 // steps to p.fused and returns the segments.
-std::vector<Segment> sv_windows(Plan& p, int wmax, std::vector<AbsorbStep>* run) {
+// A step the window pass applies in place as a plain 1- or 2-qubit gate.
+bool plain_step(const AbsorbStep& st) {
+  if (st.nH != 0 || st.nS != 0 || st.nK != st.nN || st.nK < 1 || st.nK > 2) return false;
+  for (int k = 0; k < (1 << st.nK); ++k)
+    if (st.noff[k] != st.koff[k]) return false;
+  return true;
+}
+
+// Relative VALU cost of one step in the window pass (a dense two-qubit gate = 1);
+// a 16 x 16 cluster on MFMA costs about 1.6 plus its build.
+double step_cost(const Plan& p, const AbsorbStep& st) {
+  bool mono = true;
+  if (st.gate >= 0 && st.gate < (int)p.mats.size()) {
+    const int d = 1 << p.arity[(size_t)st.gate];
+    for (int r = 0; r < d; ++r) {
+      int nz = 0;
+      for (int c = 0; c < d; ++c) {
+        const double re = p.mats[(size_t)st.gate][2 * (r * d + c)], im = p.mats[(size_t)st.gate][2 * (r * d + c) + 1];
+        nz += (re != 0.0 || im != 0.0);
+      }
+      mono = mono && nz <= 1;
+    }
+  }
+  if (mono) return 0.3;
+  return st.nK == 1 ? 0.5 : 1.0;
+}
+constexpr double kClusterMinCost = 3.0;
+
+// Regroup a window's steps (in a valid execution order) into clusters of steps on
+// at most 4 qubits: a step joins the current group unless a step it must follow
+// (one on a shared qubit) was left out, so the new order only moves steps past
+// steps on disjoint qubits.  groups: (start, length) in the new order.
+void cluster_order(const Plan& p, const std::vector<int>& steps, std::vector<int>& order,
+                   std::vector<std::pair<int, int>>& groups) {
+  std::vector<char> used(steps.size(), 0);
+  order.clear();
+  groups.clear();
+  while (order.size() < steps.size()) {
+    std::set<int> Q, blocked;
+    const int start = (int)order.size();
+    bool closed = false;
+    for (size_t i = 0; i < steps.size(); ++i) {
+      if (used[i]) continue;
+      const AbsorbStep& st = p.sv_steps[(size_t)steps[i]];
+      const bool first = (int)order.size() == start;   // the first unused step: nothing blocks it
+      bool ok = !closed;
+      std::set<int> Q2 = Q;
+      for (int k = 0; k < st.nK; ++k) {
+        ok = ok && !blocked.count(st.kpos[k]);
+        Q2.insert(st.kpos[k]);
+      }
+      if (!first) ok = ok && plain_step(st) && Q2.size() <= 4;
+      if (ok) {
+        used[i] = 1;
+        order.push_back(steps[i]);
+        Q = Q2;
+        if (first && !plain_step(st)) closed = true;   // a step the cluster pass cannot take stands alone
+      } else {
+        for (int k = 0; k < st.nK; ++k) blocked.insert(st.kpos[k]);
+      }
+    }
+    groups.push_back({start, (int)order.size() - start});
+  }
+}
+
+std::vector<Segment> sv_windows(Plan& p, int wmax, std::vector<AbsorbStep>* run, std::vector<ClusterDesc>& cls) {
   std::vector<Segment> segs;
   const int n = p.n;
   const int cap = std::min(wmax, n);
@@ -647,10 +712,45 @@ std::vector<Segment> sv_windows(Plan& p, int wmax, std::vector<AbsorbStep>* run)
     std::vector<int> Pv(P.begin(), P.end());
     for (int k = 0; k < sg.np; ++k) sg.P[k] = Pv[k];
     sg.fused_off = (int64_t)p.fused.size();
-    for (int g : taken) {
+    std::vector<int> order;
+    std::vector<std::pair<int, int>> groups;
+    cluster_order(p, taken, order, groups);
+    for (int g : order) {
       if (run) run->push_back(p.sv_steps[g]);
       p.fused.push_back(make_fused_step(p.sv_steps[g], Pv));
     }
+    // clusters worth the MFMA pass (windows of >= 10 positions: 4 wavefronts of
+    // column tiles), split where the 32-step gate staging restarts
+    if (sg.np >= 10)
+      for (const auto& gr : groups) {
+        int s0 = gr.first;
+        const int end = gr.first + gr.second;
+        while (s0 < end) {
+          const int s1 = std::min(end, (s0 / kGateChunkHost + 1) * kGateChunkHost);
+          double cost = 0.0;
+          std::set<int> Q;
+          for (int s = s0; s < s1; ++s) {
+            const AbsorbStep& st = p.sv_steps[(size_t)order[(size_t)s]];
+            cost += step_cost(p, st);
+            for (int k = 0; k < st.nK; ++k) Q.insert(st.kpos[k]);
+          }
+          if (s1 - s0 >= 2 && cost >= kClusterMinCost) {
+            FusedStep& f = p.fused[(size_t)sg.fused_off + (size_t)s0];
+            f.cl_len = s1 - s0;
+            f.cl_id = (int32_t)cls.size();
+            std::vector<int> loc;
+            for (int q : Q) loc.push_back((int)(std::find(Pv.begin(), Pv.end(), q) - Pv.begin()));
+            for (int l = 0; (int)loc.size() < 4 && l < sg.np; ++l)      // pad with other tile positions
+              if (std::find(loc.begin(), loc.end(), l) == loc.end()) loc.push_back(l);
+            ClusterDesc cd{};
+            cd.first = (int32_t)(sg.fused_off + s0);
+            cd.len = s1 - s0;
+            for (int i = 0; i < 4; ++i) cd.pos[i] = f.cl_pos[i] = loc[(size_t)i];
+            cls.push_back(cd);
+          }
+          s0 = s1;
+        }
+      }
     first += (int64_t)taken.size();
     segs.push_back(sg);
     rest = left_out;
@@ -661,7 +761,10 @@ std::vector<Segment> sv_windows(Plan& p, int wmax, std::vector<AbsorbStep>* run)
 
 void build_sv_schedule(Plan& p) {
   p.sv_run.clear();
-  for (int i = 0; i < 3; ++i) p.sv_win[i] = sv_windows(p, kSvWindowMin + i, i == 2 ? &p.sv_run : nullptr);
+  for (int i = 0; i < 3; ++i) {
+    p.sv_cl[i].clear();
+    p.sv_win[i] = sv_windows(p, kSvWindowMin + i, i == 2 ? &p.sv_run : nullptr, p.sv_cl[i]);
+  }
   p.sv_segs = p.sv_win[2];
 }
 

@@ -116,7 +116,13 @@ __global__ void __launch_bounds__(kRgThreads) rg_window_kernel(RgWave w, RgLevel
   float2* Gm = lds + (1 << kFuseMax);
   __shared__ uint64_t pw[1];
   if (threadIdx.x == 0) pw[0] = 0ull;
-  for (int64_t task = blockIdx.x; task < lv.tasks; task += gridDim.x) {
+  // contiguous task ranges per workgroup: consecutive tiles of one trajectory
+  // reuse the staged gate matrices
+  const int64_t per = (lv.tasks + gridDim.x - 1) / gridDim.x;
+  const int64_t b0 = (int64_t)blockIdx.x * per, b1 = b0 + per < lv.tasks ? b0 + per : lv.tasks;
+  const RgPiece* last_pc = nullptr;
+  int64_t last_traj = -1;
+  for (int64_t task = b0; task < b1; ++task) {
     const int e = find_le(lv.start, lv.n, task);
     const RgPiece& pc = w.pieces[lv.piece[e]];
     const RgWindow& wd = pc.win[level];
@@ -124,8 +130,11 @@ __global__ void __launch_bounds__(kRgThreads) rg_window_kernel(RgWave w, RgLevel
     const int64_t local = task - lv.start[e];
     const int64_t traj = local >> tb;
     const uint32_t t = (uint32_t)(local & (((int64_t)1 << tb) - 1));
+    const bool ready = &pc == last_pc && traj == last_traj && wd.n_fs <= kGateChunk;
     window_tile_pass(pc.fused + wd.fused_off, wd.n_fs, wd.P, wd.np, pc.n, t, pc.psi + (traj << pc.n), pc.g,
-                     (int)traj, pw, tile, Gm);
+                     (int)traj, pw, tile, Gm, nullptr, ready);
+    last_pc = &pc;
+    last_traj = traj;
   }
 }
 

@@ -57,15 +57,28 @@ size_t sv_global_bytes(const Plan& p, int64_t E, int64_t M) {
 
 }  // namespace
 
-ptsbe_status_t sv_evolve(const Plan& p, const GateCtx& g, int64_t t0, int64_t nj, float2* psi, hipStream_t s) {
+// Device bytes of one trajectory's state and its gate-cluster matrices.
+static size_t sv_traj_bytes(const Plan& p) { return ((size_t)8 << p.n) + p.sv_cl[2].size() * 256 * sizeof(float2) + 512; }
+
+ptsbe_status_t sv_evolve(const Plan& p, const GateCtx& g, int64_t t0, int64_t nj, float2* psi, float2* Ucl,
+                         hipStream_t s) {
   HIP_TRY(launch_state_init(psi, nj, p.n, s));
+  const int n_cl = Ucl ? (int)p.sv_cl[2].size() : 0;
+  if (n_cl > 0) HIP_TRY(launch_cluster_build(p.d_sv_cl[2], n_cl, p.d_fused, g, nj, nullptr, (int32_t)t0, Ucl, s));
   for (const Segment& sg : p.sv_segs)
-    HIP_TRY(launch_fused(sg, p.d_fused, g, nj, nullptr, (int32_t)t0, nullptr, p.NW, psi, s));
+    HIP_TRY(launch_fused(sg, p.d_fused, g, nj, nullptr, (int32_t)t0, nullptr, p.NW, psi, s, n_cl > 0 ? Ucl : nullptr,
+                         n_cl));
   return PTSBE_OK;
 }
 
+// Gate-cluster matrices of nj trajectories (null when the windows have none).
+static float2* take_clusters(const Plan& p, Arena& ar, int64_t nj) {
+  const size_t n_cl = p.sv_cl[2].size();
+  return n_cl ? (float2*)ar.take((size_t)nj * n_cl * 256 * sizeof(float2)) : nullptr;
+}
+
 size_t sv_sample_workspace(const Plan& p, int64_t E, int64_t M) {
-  const size_t state = (size_t)8 << p.n;
+  const size_t state = sv_traj_bytes(p);
   const int64_t avg_m = E > 0 ? (M + E - 1) / E : 0;
   const size_t per_traj = state + (size_t)(avg_m + 1) * sv_elem_bytes(p);
   const int64_t k = std::max<int64_t>(1, std::min<int64_t>(E, (int64_t)(((size_t)16 << 30) / per_traj)));
@@ -75,7 +88,7 @@ size_t sv_sample_workspace(const Plan& p, int64_t E, int64_t M) {
 size_t sv_contract_workspace(const Plan& p, int j, int64_t E, int64_t n_elems) {
   const size_t X = (size_t)1 << p.batches[j].size;
   const int64_t ec = std::min<int64_t>(std::max<int64_t>(n_elems, 1), kSvElemCap);
-  const size_t state = (size_t)8 << p.n;
+  const size_t state = sv_traj_bytes(p);
   const int64_t k = std::max<int64_t>(1, std::min<int64_t>(E, (int64_t)(((size_t)16 << 30) / state)));
   return (size_t)E * p.G * 16 * sizeof(float2) + (size_t)(E + 1) * 4 + (size_t)std::max<int64_t>(ec, kSplitRows) * X * 8 +
          (size_t)k * state + ((size_t)4 << 20);
@@ -113,7 +126,7 @@ ptsbe_status_t sv_sample_shots(Plan& p, const uint8_t* d_kraus, int64_t E, const
     return fail(PTSBE_ERR_OUT_OF_MEMORY, "workspace too small for the shot arrays and merged gates");
   // chunks of trajectories: at most NJ states and CE elements (elements of a
   // batch never outnumber max(trajectories, shots) of the chunk)
-  const size_t state = (size_t)8 << p.n;
+  const size_t state = (size_t)8 << p.n, tb = sv_traj_bytes(p);
   const size_t per_elem = sv_elem_bytes(p);
   const size_t fixed = (size_t)kSplitRows * Xmax * 8 + ((size_t)1 << 20);   // first-batch split sums + alignment
   const size_t avail = ar.left() > fixed ? ar.left() - fixed : 0;
@@ -122,8 +135,8 @@ ptsbe_status_t sv_sample_shots(Plan& p, const uint8_t* d_kraus, int64_t E, const
   int64_t CE = std::min<int64_t>(std::max<int64_t>(E, M), (int64_t)(avail / 2 / per_elem));
   CE = std::max<int64_t>(CE, max_m + 1);
   const size_t elem_bytes = (size_t)CE * per_elem + scan_scratch_bytes(CE);
-  if (elem_bytes + state > avail) return fail(PTSBE_ERR_OUT_OF_MEMORY, "workspace too small for one trajectory's state");
-  const int64_t NJ = std::min<int64_t>({(int64_t)((avail - elem_bytes) / state), 65535, CE});
+  if (elem_bytes + tb > avail) return fail(PTSBE_ERR_OUT_OF_MEMORY, "workspace too small for one trajectory's state");
+  const int64_t NJ = std::min<int64_t>({(int64_t)((avail - elem_bytes) / tb), 65535, CE});
   std::vector<int64_t> cuts = {0};
   {
     int64_t nj = 0, mc = 0;
@@ -180,9 +193,11 @@ ptsbe_status_t sv_sample_shots(Plan& p, const uint8_t* d_kraus, int64_t E, const
     const int64_t t0 = cuts[c], t1 = cuts[c + 1], nj = t1 - t0;
     ar.used = mark;
     float2* psi = (float2*)ar.take((size_t)nj * state);
-    if (!psi) return fail(PTSBE_ERR_OUT_OF_MEMORY, "workspace too small for the chunk's states");
+    float2* Ucl = take_clusters(p, ar, nj);
+    if (!psi || (!Ucl && !p.sv_cl[2].empty()))
+      return fail(PTSBE_ERR_OUT_OF_MEMORY, "workspace too small for the chunk's states");
     HIP_TRY(launch_init_traj_range(t0, nj, d_m, d_base, el[0].traj, el[0].prefix, p.NW, el[0].off, el[0].cnt, s));
-    ptsbe_status_t st = sv_evolve(p, g, t0, nj, psi, s);
+    ptsbe_status_t st = sv_evolve(p, g, t0, nj, psi, Ucl, s);
     if (st != PTSBE_OK) return st;
     int cur = 0;
     int64_t U = nj;
@@ -269,16 +284,19 @@ ptsbe_status_t sv_contract_batch(Plan& p, int j, const uint8_t* d_kraus, int64_t
   HIP_TRY(hipMemcpyAsync(first.data(), d_first, (size_t)(E + 1) * 4, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   const size_t state = (size_t)8 << p.n;
-  const int64_t nj_cap = std::min<int64_t>((int64_t)(ar.left() / state), 65535);
+  const int64_t nj_cap = std::min<int64_t>((int64_t)(ar.left() / sv_traj_bytes(p)), 65535);
   if (nj_cap < 1) return fail(PTSBE_ERR_OUT_OF_MEMORY, "workspace too small for one trajectory's state");
   float2* psi = (float2*)ar.take((size_t)nj_cap * state);
+  float2* Ucl = take_clusters(p, ar, nj_cap);
+  if (!psi || (!Ucl && !p.sv_cl[2].empty()))
+    return fail(PTSBE_ERR_OUT_OF_MEMORY, "workspace too small for one trajectory's state");
   int64_t t0 = 0;
   while (t0 < E) {
     while (t0 < E && first[t0 + 1] == first[t0]) ++t0;   // skip trajectories without elements
     if (t0 >= E) break;
     const int64_t t1 = std::min<int64_t>(E, t0 + nj_cap);
     const int64_t e0 = first[t0], e1 = first[t1];
-    ptsbe_status_t st = sv_evolve(p, g, t0, t1 - t0, psi, s);
+    ptsbe_status_t st = sv_evolve(p, g, t0, t1 - t0, psi, Ucl, s);
     if (st != PTSBE_OK) return st;
     for (int64_t a0 = e0; a0 < e1; a0 += kSvElemCap) {
       const int64_t ne = std::min<int64_t>(kSvElemCap, e1 - a0);
