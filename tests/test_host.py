@@ -204,3 +204,39 @@ def test_statevector_schedule_only_reorders_commuting_gates(window):
             for b in range(a + 1, G):
                 if set(qubits[a]) & set(qubits[b]):
                     assert pos[a] < pos[b], (a, b)
+
+
+def test_public_header_is_c99():
+    """include/ptsbe.h is a plain C header (no C++ or torch types at the boundary)."""
+    import shutil
+    import subprocess
+    import tempfile
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    with tempfile.TemporaryDirectory() as d:
+        src = os.path.join(d, "h.c")
+        with open(src, "w") as f:
+            f.write('#include "ptsbe.h"\nint main(void) { return 0; }\n')
+        r = subprocess.run([cc, "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror", "-fsyntax-only",
+                            "-I", os.path.join(root, "include"), src], capture_output=True, text=True)
+        assert r.returncode == 0, r.stderr
+
+
+def test_right_sites_of_the_brickwork_batches():
+    """The sites entering a batch's per-trajectory part are sorted, in range, and on
+    the 1D brickwork shrink from batch to batch (the traced region moves right)."""
+    P = _lib()
+    wl = W.config2()
+    plan = P.Plan(wl.circuit, wl.batch_sizes, hypersamples=4, device=-1)
+    S = len(wl.circuit.site_gate)
+    prev = None
+    for j in range(len(wl.batch_sizes)):
+        s = plan.right_sites(j)
+        assert np.all(np.diff(s) > 0) and (len(s) == 0 or (s[0] >= 0 and s[-1] < S))
+        if prev is not None:
+            assert set(s.tolist()) <= set(prev.tolist()) and len(s) < len(prev)
+        prev = s
+    with pytest.raises(P.PtsbeError):
+        plan.right_sites(len(wl.batch_sizes))
