@@ -23,7 +23,7 @@ HBM_PEAK_GBS = 8000.0
 FP32_MFMA_PEAK_TFLOPS = 157.3
 BF16_MFMA_PEAK_TFLOPS = 2500.0
 # the join kernel version that profiles/join_traffic.txt must name to be used
-JOIN_KERNEL_TAG = "qform_mfma_kernel<32,4> bilinear slots"
+JOIN_KERNEL_TAG = "qform_mfma_kernel<32,8> bilinear slots"
 
 
 def cpu_baseline(wl, kr, budget_s=20.0):
@@ -144,7 +144,7 @@ def main():
     peak = FP32_MFMA_PEAK_TFLOPS if args.precision == "c64" else BF16_MFMA_PEAK_TFLOPS   # fp16 dense = bf16 dense
     roofline = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                 "frac": achieved / peak, "traffic": traffic if args.precision == "c64" else None,
-                "kernel": "qform_mfma_kernel<32,4> (doubled-network join as a real GEMM over K^2 folded slots, "
+                "kernel": "qform_mfma_kernel<32,8> (doubled-network join as a real GEMM over K^2 folded slots, "
                           "FP32 MFMA)" if args.precision == "c64"
                           else f"qform_split_kernel<32,4> (doubled-network join as the K^2-slot GEMM, {args.precision} "
                                "hi+lo operands, three products on 16-bit MFMA, FP32 accumulate)",

@@ -525,7 +525,8 @@ template <int K, int NC>
 __global__ void __launch_bounds__(256) qform_mfma_kernel(QformArgs a) {
   constexpr int ROWS = 64, KK = K * K, KC = 32, NS = KC / 4, XT = 16 * NC, NCH = KK / KC, KB = K / 4;
   constexpr int F4C = KC * XT / 4;              // float4 of Theta per chunk
-  static_assert(F4C <= 512, "two float4 per thread at most");
+  constexpr int PL = (F4C + 255) / 256;          // float4 per thread per chunk
+  static_assert(PL <= 4, "four float4 per thread at most");
   __shared__ float Thl[2][KC * XT];
   __shared__ float2 Vs[ROWS][K + 1];
   // Workgroups go round-robin to the 8 XCDs in linear launch order; renumber them
@@ -572,10 +573,16 @@ __global__ void __launch_bounds__(256) qform_mfma_kernel(QformArgs a) {
   // at ((s * 64 + 16 q + j) * NC + c), the B operand of lane 16 q + j at k-step s.
   const int32_t ts = a.tslot ? a.tslot[t - a.traj_base] : t - a.traj_base;
   const float* Tt = a.Th + ((int64_t)ts * nx + x0) * KK;
-  const int i0 = tid, i1 = tid + 256;
-  const bool h0 = i0 < F4C, h1 = i1 < F4C;
-  const int xl0 = i0 % XT, s0 = (i0 / XT) % NS, xl1 = i1 % XT, s1 = (i1 / XT) % NS;
-  const bool v0 = h0 && xl0 < xv, v1 = h1 && xl1 < xv;
+  int xlq[PL], sq[PL];
+  bool hq[PL], vq[PL];
+#pragma unroll
+  for (int i = 0; i < PL; ++i) {
+    const int idx = tid + 256 * i;
+    hq[i] = idx < F4C;
+    xlq[i] = idx % XT;
+    sq[i] = (idx / XT) % NS;
+    vq[i] = hq[i] && xlq[i] < xv;
+  }
   auto ld = [&](int ch, int xl, int s, bool ok) -> float4 {
     return ok ? *reinterpret_cast<const float4*>(Tt + (int64_t)xl * KK + ch * KC + 4 * s)
               : make_float4(0.f, 0.f, 0.f, 0.f);
@@ -584,11 +591,12 @@ __global__ void __launch_bounds__(256) qform_mfma_kernel(QformArgs a) {
     float* p = d + (s * 64 + (xl & 15)) * NC + (xl >> 4);
     p[0] = v.x; p[16 * NC] = v.y; p[32 * NC] = v.z; p[48 * NC] = v.w;
   };
-  {
-    const float4 r0 = ld(0, xl0, s0, v0), r1 = ld(0, xl1, s1, v1);
-    if (h0) st(Thl[0], xl0, s0, r0);
-    if (h1) st(Thl[0], xl1, s1, r1);
-  }
+  float4 rq[PL];
+#pragma unroll
+  for (int i = 0; i < PL; ++i) rq[i] = ld(0, xlq[i], sq[i], vq[i]);
+#pragma unroll
+  for (int i = 0; i < PL; ++i)
+    if (hq[i]) st(Thl[0], xlq[i], sq[i], rq[i]);
   __syncthreads();
   // per lane: row rl, slot offset q; vb[i] = v[rl][4 i + q]
   const int rl = wave * 16 + (lane & 15), q = lane >> 4;
@@ -614,7 +622,8 @@ __global__ void __launch_bounds__(256) qform_mfma_kernel(QformArgs a) {
     const int buf = ch & 1;
     const bool more = ch + 1 < NCH;
     const int cn = more ? ch + 1 : ch;            // the last chunk reloads itself (not stored)
-    const float4 r0 = ld(cn, xl0, s0, v0), r1 = ld(cn, xl1, s1, v1);
+#pragma unroll
+    for (int i = 0; i < PL; ++i) rq[i] = ld(cn, xlq[i], sq[i], vq[i]);
     __builtin_amdgcn_sched_barrier(0);          // keep the loads ahead of the MFMAs
     const float* B = Thl[buf];
 #pragma unroll
@@ -628,7 +637,18 @@ __global__ void __launch_bounds__(256) qform_mfma_kernel(QformArgs a) {
       const float R = va.x * w.x + va.y * w.y;       // Re(v_a conj v_b)
       const float I = w.y * va.x - w.x * va.y;       // Im(v_b conj v_a)
       const float m = av <= b ? R : I;
-      if constexpr (NC == 4) {
+      if constexpr (NC == 8) {
+        const float4 bq = *reinterpret_cast<const float4*>(B + (s * 64 + lane) * 8);
+        const float4 bp = *reinterpret_cast<const float4*>(B + (s * 64 + lane) * 8 + 4);
+        acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(m, bq.x, acc[0], 0, 0, 0);
+        acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(m, bq.y, acc[1], 0, 0, 0);
+        acc[2] = __builtin_amdgcn_mfma_f32_16x16x4f32(m, bq.z, acc[2], 0, 0, 0);
+        acc[3] = __builtin_amdgcn_mfma_f32_16x16x4f32(m, bq.w, acc[3], 0, 0, 0);
+        acc[4] = __builtin_amdgcn_mfma_f32_16x16x4f32(m, bp.x, acc[4], 0, 0, 0);
+        acc[5] = __builtin_amdgcn_mfma_f32_16x16x4f32(m, bp.y, acc[5], 0, 0, 0);
+        acc[6] = __builtin_amdgcn_mfma_f32_16x16x4f32(m, bp.z, acc[6], 0, 0, 0);
+        acc[7] = __builtin_amdgcn_mfma_f32_16x16x4f32(m, bp.w, acc[7], 0, 0, 0);
+      } else if constexpr (NC == 4) {
         const float4 bq = *reinterpret_cast<const float4*>(B + (s * 64 + lane) * 4);
         acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(m, bq.x, acc[0], 0, 0, 0);
         acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(m, bq.y, acc[1], 0, 0, 0);
@@ -643,8 +663,9 @@ __global__ void __launch_bounds__(256) qform_mfma_kernel(QformArgs a) {
       }
     }
     if (more) {
-      if (h0) st(Thl[buf ^ 1], xl0, s0, r0);
-      if (h1) st(Thl[buf ^ 1], xl1, s1, r1);
+#pragma unroll
+      for (int i = 0; i < PL; ++i)
+        if (hq[i]) st(Thl[buf ^ 1], xlq[i], sq[i], rq[i]);
     }
     __syncthreads();
   }
@@ -1335,14 +1356,16 @@ hipError_t launch_qform(const QformArgs& a, int n_traj, int max_rows, hipStream_
   if (n_traj <= 0 || max_rows <= 0) return hipSuccess;
   const int tiles = (max_rows + 63) / 64;
   const int nx = 1 << a.xT_bits;
-  const int nc = nx >= 64 ? 4 : (nx >= 32 ? 2 : 1);
+  const int nc = nx >= 128 ? 8 : (nx >= 64 ? 4 : (nx >= 32 ? 2 : 1));
   const int xtiles = (nx + 16 * nc - 1) / (16 * nc);
   dim3 grid((unsigned)tiles, (unsigned)n_traj, (unsigned)xtiles);
 #define PTSBE_QFORM(KV, NCV) hipLaunchKernelGGL((qform_mfma_kernel<KV, NCV>), grid, dim3(256), 0, stream, a)
   if (a.lk_bits == 4) {
-    if (nc == 4) PTSBE_QFORM(16, 4); else if (nc == 2) PTSBE_QFORM(16, 2); else PTSBE_QFORM(16, 1);
+    if (nc == 8) PTSBE_QFORM(16, 8); else if (nc == 4) PTSBE_QFORM(16, 4); else if (nc == 2) PTSBE_QFORM(16, 2);
+    else PTSBE_QFORM(16, 1);
   } else if (a.lk_bits == 5) {
-    if (nc == 4) PTSBE_QFORM(32, 4); else if (nc == 2) PTSBE_QFORM(32, 2); else PTSBE_QFORM(32, 1);
+    if (nc == 8) PTSBE_QFORM(32, 8); else if (nc == 4) PTSBE_QFORM(32, 4); else if (nc == 2) PTSBE_QFORM(32, 2);
+    else PTSBE_QFORM(32, 1);
   } else {
     return hipErrorInvalidValue;
   }
