@@ -253,6 +253,13 @@ ptsbe_status_t run_batch(Plan& p, int j, const uint8_t* d_kraus, const float2* m
   const std::vector<int32_t> rsites = io.h_kraus ? right_sites(p, bp) : std::vector<int32_t>();
   const int64_t S = (int64_t)p.site_gate.size();
   std::vector<std::vector<int32_t>> keep;         // host sources of async uploads
+  struct SyncOnExit {                             // on every return (errors included), the
+    hipStream_t s;                                // uploads from `keep` finish before it is freed
+    const std::vector<std::vector<int32_t>>& k;
+    ~SyncOnExit() {
+      if (!k.empty()) (void)hipStreamSynchronize(s);
+    }
+  } sync_on_exit{s, keep};
   for (int64_t t0 = 0; t0 < E; t0 += t_cap) {
     const int64_t t1 = std::min<int64_t>(E, t0 + t_cap);
     const int64_t e0 = first[t0], e1 = first[t1];
@@ -398,7 +405,6 @@ ptsbe_status_t run_batch(Plan& p, int j, const uint8_t* d_kraus, const float2* m
     }
     ar.used = mark;
   }
-  if (!keep.empty()) HIP_TRY(hipStreamSynchronize(s));   // the uploads' host sources end here
   ar.used = mark0;
   return PTSBE_OK;
 }
