@@ -1,0 +1,151 @@
+"""Edge cases of the shot sampler and the batch contraction through the C ABI.
+
+Trajectories with zero shots between trajectories with shots (they still carry a
+norm and a weight but make no elements of later batches), a call whose
+trajectories all have zero shots, a single trajectory, the largest batch the
+sampler takes (12 qubits, first and last position), and a contraction of no
+elements.  Shots are compared with the FP64 oracle sampler under the same
+Philox counters; the expected CDF-boundary flips come from the first batch's
+marginals (Sec. II-B draws, Eq. for the trajectory weights)."""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import sampling
+from tests.gpu_helpers import (assert_shot_parity, flip_probability, oracle_states, prefix_words, shots_to_ints,
+                               to_dev, torch_dev)
+
+pytestmark = pytest.mark.gpu
+
+METHODS = ["network", "statevector"]
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _check_shots(torch, dev, plan, circ, bs, kr, mult, ms, seed, tag):
+    """Sample with per-trajectory shot counts ms; check row layout, shots, norms and weights."""
+    import paper_2604_08467_amd as P
+    E = len(kr)
+    kd = to_dev(torch, dev, kr)
+    out = plan.sample_shots(kd, to_dev(torch, dev, ms), seed, mult_dev=to_dev(torch, dev, mult))
+    torch.cuda.synchronize()
+    M = int(np.sum(ms))
+    assert out["shots"].shape[0] == M
+    assert np.array_equal(out["shot_traj"].cpu().numpy(), np.repeat(np.arange(E, dtype=np.int32), ms))
+    got = shots_to_ints(out["shots"].cpu().numpy())
+    psis = oracle_states(circ, kr)
+    Z = np.array([np.vdot(p, p).real for p in psis])
+    np.testing.assert_allclose(out["norms"].cpu().numpy(), Z, rtol=1e-5)
+    np.testing.assert_allclose(out["weights"].cpu().numpy(), sampling.trajectory_weights(Z, mult), rtol=1e-5)
+    # batch 0 is reached by every trajectory, later batches only by those with shots
+    assert int(out["elements_per_batch"][0]) == E
+    n, starts = circ.n_qubits, sampling.batch_starts(bs)
+    et = to_dev(torch, dev, np.arange(E, dtype=np.int32))
+    ep = to_dev(torch, dev, prefix_words([0] * E, plan.n_words))
+    pop0, _ = plan.contract_batch(0, kd, et, ep, P.OUT_POPULATION)
+    pop0 = pop0.cpu().numpy()
+    mism, expect, row = 0, 0.0, 0
+    for i, psi in enumerate(psis):
+        m = int(ms[i])
+        if m == 0:
+            continue
+
+        def mfn(j, prefix, psi=psi):
+            return sampling.marginal_from_state(psi, n, starts[j], bs[j], prefix)
+
+        ref, _ = sampling.sample_trajectory(mfn, i, n, bs, m, seed)
+        mism += sum(1 for a, b in zip(got[row:row + m], ref) if a != b)
+        row += m
+        expect += m * flip_probability(pop0[i], mfn(0, 0))
+    _say(f"{tag}: {mism} of {M} shots differ from the oracle (expected first-batch flips {expect:.3g})")
+    assert_shot_parity(mism, expect, max(M, 1))
+    return out
+
+
+@pytest.mark.parametrize("method", METHODS)
+def test_zero_shot_trajectories_between_others(method):
+    import paper_2604_08467_amd as P
+    torch, dev = torch_dev()
+    rng = np.random.default_rng(61)
+    circ = W.random_brickwork(12, 6, rng, 0.03)
+    bs = [5, 4, 3]
+    plan = P.Plan(circ, bs, method=method)
+    kr, mult, _, _ = plan.sample_trajectories(62, 24)
+    E = len(kr)
+    ms = np.random.default_rng(63).integers(1, 60, size=E).astype(np.int64)
+    ms[::3] = 0                                  # every third trajectory draws nothing
+    ms[-1] = 0                                   # ... and the last one
+    out = _check_shots(torch, dev, plan, circ, bs, kr, mult, ms, 64, f"zero-shot mix ({method}, E={E})")
+    # a later batch holds at most one element per shot and none for the zero-shot trajectories
+    nz = int(np.count_nonzero(ms))
+    assert all(nz <= int(u) <= int(np.sum(ms)) for u in out["elements_per_batch"][1:])
+
+
+@pytest.mark.parametrize("method", METHODS)
+def test_all_trajectories_without_shots(method):
+    """No shot rows at all: norms and weights are still produced."""
+    import paper_2604_08467_amd as P
+    torch, dev = torch_dev()
+    rng = np.random.default_rng(71)
+    circ = W.random_brickwork(10, 5, rng, 0.03)
+    bs = [6, 4]
+    plan = P.Plan(circ, bs, method=method)
+    kr, mult, _, _ = plan.sample_trajectories(72, 10)
+    ms = np.zeros(len(kr), dtype=np.int64)
+    out = _check_shots(torch, dev, plan, circ, bs, kr, mult, ms, 73, f"no shots ({method})")
+    assert out["shots"].shape[0] == 0
+    assert int(out["elements_per_batch"][1]) == 0
+
+
+@pytest.mark.parametrize("method", METHODS)
+def test_single_trajectory(method):
+    import paper_2604_08467_amd as P
+    torch, dev = torch_dev()
+    rng = np.random.default_rng(81)
+    circ = W.small_random_circuit(9, 40, rng, [W.depolarizing(0.1), W.amplitude_damping(0.2)])
+    bs = [4, 5]
+    plan = P.Plan(circ, bs, method=method)
+    kr, mult, _, _ = plan.sample_trajectories(82, 1)
+    assert len(kr) == 1
+    out = _check_shots(torch, dev, plan, circ, bs, kr[:1], mult[:1], np.array([700], dtype=np.int64), 83,
+                       f"single trajectory ({method})")
+    if out["norms"].cpu().numpy()[0] > 0:       # a lone trajectory of non-zero norm carries all the weight
+        np.testing.assert_allclose(out["weights"].cpu().numpy(), [1.0], rtol=1e-12)
+
+
+@pytest.mark.parametrize("method", METHODS)
+@pytest.mark.parametrize("bs", [[12, 2], [2, 12]], ids=["12_first", "12_last"])
+def test_largest_batch(method, bs):
+    """12-qubit batches (the sampler's limit) as the doubled first batch and as the
+    amplitude-joined last batch."""
+    import paper_2604_08467_amd as P
+    torch, dev = torch_dev()
+    rng = np.random.default_rng(91)
+    circ = W.random_brickwork(14, 5, rng, 0.02)
+    plan = P.Plan(circ, bs, method=method)
+    kr, mult, _, _ = plan.sample_trajectories(92, 6)
+    ms = np.full(len(kr), 150, dtype=np.int64)
+    _check_shots(torch, dev, plan, circ, bs, kr, mult, ms, 93, f"batches {bs} ({method}, E={len(kr)})")
+
+
+@pytest.mark.parametrize("method", METHODS)
+def test_contract_no_elements(method):
+    """A contraction of zero elements succeeds and writes nothing."""
+    import paper_2604_08467_amd as P
+    torch, dev = torch_dev()
+    wl = W.config1()
+    plan = P.Plan(wl.circuit, wl.batch_sizes, method=method)
+    kr, _, _, _ = plan.sample_trajectories(wl.pts_seed, 4)
+    kd = to_dev(torch, dev, kr)
+    et = torch.empty(0, dtype=torch.int32, device=dev)
+    ep = torch.empty((0, plan.n_words), dtype=torch.int64, device=dev)
+    for kind in (P.OUT_POPULATION, P.OUT_AMPLITUDE):
+        out, tot = plan.contract_batch(0, kd, et, ep, kind)
+        torch.cuda.synchronize()
+        assert out.shape[0] == 0
+        assert tot is None or tot.shape[0] == 0
