@@ -15,7 +15,8 @@ index order (the largest x with pi(x) > 0 if rounding leaves no such x).
 
 Sec. III-B (NBS, proportional mode): the same shots are produced while the
 marginal is contracted once per distinct (trajectory, prefix); the oracle
-memoises marginals per prefix, which changes no result.
+memoises marginals per prefix, which changes no result.  Non-proportional mode
+with exhaustive final-batch sampling: nonproportional_trajectory.
 """
 import numpy as np
 
@@ -92,3 +93,53 @@ def trajectory_weights(Z: np.ndarray, mult: np.ndarray) -> np.ndarray:
     trajectory built from rescaled inserted operators (= 1 for Pauli channels)."""
     r = np.asarray(Z, dtype=np.float64) * np.asarray(mult, dtype=np.float64)
     return r / r.sum()
+
+
+def extra_uniforms(seed: int, traj: int, j: int, t0: int, count: int) -> np.ndarray:
+    """Uniforms of the non-proportional draws: tag 3, counter (trajectory, j, t, 0)."""
+    t = np.arange(t0, t0 + count, dtype=np.uint64)
+    return philox.uniform(seed, philox.TAG_EXTRA, np.full_like(t, traj), np.full_like(t, j), t, 0)
+
+
+def nonproportional_trajectory(marginal_fn, traj: int, n_qubits: int, batch_sizes, draws: int, seed: int,
+                               threshold: float):
+    """Non-proportional NBS with exhaustive final-batch sampling (Sec. III-B).
+
+    Non-final batches: every distinct prefix of the trajectory takes `draws`
+    draws from its conditional marginal; the distinct outcomes x, in increasing
+    order, extend it to the prefixes of the next batch.  Prefixes are visited in
+    the order they were made (parent by parent, outcomes ascending), i.e.
+    lexicographically with the first batch most significant; the r-th prefix of
+    batch j draws with the counters t = r * draws + d, d < draws (tag 3).
+    Final batch: for every prefix, every x whose conditional probability
+    P(x | prefix) = pi(x) / sum(pi) is strictly above `threshold` gives one row
+    (full bitstring, P(x | prefix), p(prefix) = sum(pi) / Z), in prefix order
+    then x ascending; a prefix of zero weight gives no rows.
+    Returns (rows, number of prefixes per batch)."""
+    starts = batch_starts(batch_sizes)
+    f = len(batch_sizes)
+    Z = float(np.sum(marginal_fn(0, 0)))          # the trajectory's squared norm
+    prefixes = [0]
+    counts = []
+    for j in range(f - 1):
+        counts.append(len(prefixes))
+        nxt = []
+        for r, prefix in enumerate(prefixes):
+            pi = marginal_fn(j, prefix)
+            us = extra_uniforms(seed, traj, j, r * draws, draws)
+            xs = sorted({inverse_cdf(pi, float(u)) for u in us})
+            nxt.extend(prefix | (x << starts[j]) for x in xs)
+        prefixes = nxt
+    counts.append(len(prefixes))
+    rows = []
+    for prefix in prefixes:
+        pi = np.asarray(marginal_fn(f - 1, prefix), dtype=np.float64)
+        Ze = float(np.sum(pi))
+        if not Ze > 0.0:
+            continue
+        p_prefix = Ze / Z
+        for x in range(len(pi)):
+            pc = float(pi[x]) / Ze
+            if pc > threshold:
+                rows.append((prefix | (x << starts[f - 1]), pc, p_prefix))
+    return rows, counts

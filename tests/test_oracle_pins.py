@@ -414,3 +414,91 @@ def test_annihilated_trajectory_has_weight_zero_and_zero_shots():
         st = sv.trajectory_state(c, np.array(k, dtype=np.uint8))
         diag += q[k[0]] * q[k[1]] * np.abs(st) ** 2
     np.testing.assert_allclose(diag, sv.density_matrix_diag(c), atol=1e-14)
+
+
+# ----------------------------------------------- non-proportional NBS, exhaustive final batch
+def _sv_marginals(psi, n, bs):
+    starts = sampling.batch_starts(bs)
+    return lambda j, prefix: sampling.marginal_from_state(psi, n, starts[j], bs[j], prefix)
+
+
+def test_nonproportional_ghz_closed_form():
+    """GHZ on 4 qubits, batches [2, 2]: the first batch gives 00 or 11 with 1/2 each,
+    and each fixes the last batch, so the exhaustive rows are (0000, 1, 1/2) and
+    (1111, 1, 1/2); the strict threshold drops them at 1."""
+    n = 4
+    gates = [((0,), W.HADAMARD)] + [((q, q + 1), W.CNOT) for q in range(n - 1)]
+    mfn = _sv_marginals(sv.ideal_state(_circuit(n, gates)), n, [2, 2])
+    rows, counts = sampling.nonproportional_trajectory(mfn, 0, n, [2, 2], 64, 11, 0.5)
+    assert counts == [1, 2]                      # both outcomes of 64 draws (miss probability 2^-63)
+    assert [r[0] for r in rows] == [0b0000, 0b1111]
+    for _, pc, pp in rows:
+        assert abs(pc - 1) < 1e-14 and abs(pp - 0.5) < 1e-14
+    rows1, _ = sampling.nonproportional_trajectory(mfn, 0, n, [2, 2], 1, 11, 0.5)
+    assert len(rows1) == 1 and rows1[0][0] in (0b0000, 0b1111)
+    assert sampling.nonproportional_trajectory(mfn, 0, n, [2, 2], 64, 11, 1.0)[0] == []
+
+
+def test_nonproportional_rows_follow_the_chain_rule():
+    """Every row's P(x | prefix) p(prefix) is the bitstring's probability |psi|^2 / Z
+    (Sec. II-B chain rule), each reached prefix lists each of its bitstrings once at
+    threshold -1, and every prefix whose conditionals at each level are >= 0.05 is
+    reached by 200 draws (miss probability below 1e-4 per prefix)."""
+    rng = np.random.default_rng(64)
+    n, bs = 6, [2, 2, 2]
+    psi = sv.ideal_state(W.random_brickwork(n, 4, rng, 0.0))
+    p = np.abs(psi) ** 2 / np.vdot(psi, psi).real
+    mfn = _sv_marginals(psi, n, bs)
+    rows, counts = sampling.nonproportional_trajectory(mfn, 5, n, bs, 200, 12, -1.0)
+    assert len(rows) == counts[-1] * 4
+    bits = [r[0] for r in rows]
+    assert len(set(bits)) == len(bits)
+    for b, pc, pp in rows:
+        assert abs(pc * pp - p[b]) < 1e-13, b
+    reached = {b & 0xF for b in bits}
+    assert counts == [1, len({b & 0x3 for b in bits}), len(reached)]
+    p1 = np.array([p[[x for x in range(64) if x & 3 == a]].sum() for a in range(4)])
+    p2 = np.array([p[[x for x in range(64) if x & 15 == a]].sum() for a in range(16)])
+    for a in range(16):
+        if p1[a & 3] >= 0.05 and p2[a] / p1[a & 3] >= 0.05:
+            assert a in reached, a
+    # thresholded rows are the subset with P(x | prefix) > threshold
+    thr = 0.3
+    rows_t, _ = sampling.nonproportional_trajectory(mfn, 5, n, bs, 200, 12, thr)
+    assert rows_t == [r for r in rows if r[1] > thr]
+
+
+def test_nonproportional_draws_follow_the_conditional():
+    """One draw per prefix: over many trajectory ids (independent counters) the first
+    batch's outcome follows the closed-form product-state marginal within the TVD
+    bound, and every prefix has exactly one child."""
+    n, bs = 4, [2, 2]
+    th = [0.7, 2.1, 1.0, 0.4]
+    psi = sv.ideal_state(_circuit(n, [((q,), W.ry(t)) for q, t in enumerate(th)]))
+    pq = [np.sin(t / 2) ** 2 for t in th]
+    want = np.array([(pq[0] if x & 1 else 1 - pq[0]) * (pq[1] if x & 2 else 1 - pq[1]) for x in range(4)])
+    mfn = _sv_marginals(psi, n, bs)
+    N = 4000
+    hist = np.zeros(4)
+    for t in range(N):
+        rows, counts = sampling.nonproportional_trajectory(mfn, t, n, bs, 1, 21, -1.0)
+        assert counts == [1, 1] and len(rows) == 4
+        assert len({r[0] & 3 for r in rows}) == 1
+        hist[rows[0][0] & 3] += 1
+    assert sampling.nonproportional_trajectory(mfn, 0, n, bs, 1, 21, 2.0)[0] == []   # threshold above 1
+    tvd = 0.5 * np.abs(hist / N - want).sum()
+    assert tvd <= 0.5 * math.sqrt(4 / N) + math.sqrt(math.log(1e9) / (2 * N)), tvd
+
+
+def test_nonproportional_children_bound_and_zero_weight():
+    """A prefix has at most min(draws, 2^b) children; a trajectory of zero norm
+    (amplitude damping's K1 twice) gives no rows."""
+    rng = np.random.default_rng(65)
+    n, bs = 6, [3, 2, 1]
+    psi = sv.ideal_state(W.random_brickwork(n, 3, rng, 0.0))
+    mfn = _sv_marginals(psi, n, bs)
+    for k in (1, 3, 20):
+        _, counts = sampling.nonproportional_trajectory(mfn, 2, n, bs, k, 13, 0.0)
+        assert counts[1] <= min(k, 8) and counts[2] <= counts[1] * min(k, 4)
+    zero = lambda j, prefix: np.zeros(2 ** bs[j])
+    assert sampling.nonproportional_trajectory(zero, 0, n, bs, 4, 13, -1.0)[0] == []
