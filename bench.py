@@ -70,7 +70,10 @@ def main():
     ap.add_argument("--precision", choices=["c64", "bf16", "f16"], default="c64",
                     help="bf16 / f16: split-precision (16-bit hi+lo, three products) MFMA for the dense join")
     ap.add_argument("--traffic-file", default=os.path.join(ROOT, "profiles", "join_traffic.txt"))
-    ap.add_argument("--workload", choices=["brickwork50", "ragged"], default="brickwork50",
+    ap.add_argument("--final-batch", type=int, default=20, help="exhaustive workload: final batch size")
+    ap.add_argument("--threshold", type=float, default=1e-6, help="exhaustive workload: P(x | prefix) threshold")
+    ap.add_argument("--draws", type=int, default=1, help="exhaustive workload: draws per prefix")
+    ap.add_argument("--workload", choices=["brickwork50", "ragged", "exhaustive"], default="brickwork50",
                     help="ragged: the ragged mix of circuits as one graph-captured ragged set")
     ap.add_argument("--ragged-max-qubits", type=int, default=26)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -86,6 +89,9 @@ def main():
 
     if args.workload == "ragged":
         bench_ragged(args)
+        return
+    if args.workload == "exhaustive":
+        bench_exhaustive(args)
         return
     if args.copy_calibration:
         n = 1 << 30
@@ -166,6 +172,72 @@ def main():
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(wl, kr)
+    print(json.dumps(line), flush=True)
+
+
+def bench_exhaustive(args):
+    """Non-proportional NBS with exhaustive final-batch sampling on the 50-qubit
+    brickwork: batches [10, 10, 10, b_f] (b_f = --final-batch), --draws per prefix,
+    every x with P(x | prefix) > --threshold returned with its probabilities.
+    One step = one ptsbe_sample_exhaustive call; value = rows (distinct labelled
+    bitstrings) per second."""
+    import torch
+
+    import paper_2604_08467_amd as P
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    wl = W.config2()
+    bf = args.final_batch
+    bs = [10, 10, 10, bf] if bf <= 20 else [10, 40 - bf, bf]
+    assert sum(bs) == 50
+    plan = P.Plan(wl.circuit, bs, hypersamples=8, method="network")
+    E_req = args.traj if args.traj != 4096 else 512
+    kr, mult, _, _ = plan.sample_trajectories(wl.pts_seed, E_req)
+    E = len(kr)
+    kd = torch.from_numpy(kr).to(dev)
+    multd = torch.from_numpy(mult).to(dev)
+    max_elems = E * args.draws ** (len(bs) - 1)
+    cap = max_elems << bf
+    outs = {"bits": torch.empty((cap, plan.n_words), dtype=torch.int64, device=dev),
+            "row_traj": torch.empty(cap, dtype=torch.int32, device=dev),
+            "p_cond": torch.empty(cap, dtype=torch.float64, device=dev),
+            "p_prefix": torch.empty(cap, dtype=torch.float64, device=dev)}
+    ws = torch.empty(int(args.workspace_gb * (1 << 30)), dtype=torch.uint8, device=dev)
+    print(f"exhaustive: E={E}, batches {bs}, capacity {cap} rows, workspace {args.workspace_gb} GB",
+          file=sys.stderr, flush=True)
+
+    def step():
+        return plan.sample_exhaustive(kd, args.draws, wl.shot_seed, args.threshold, max_elems=max_elems,
+                                      capacity=cap, mult_dev=multd, workspace=ws, outputs=outs)
+
+    for k in range(args.warmup):
+        out = step()
+        torch.cuda.synchronize()
+        print(f"exhaustive: warmup {k} done, {out['n_rows']} rows", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        out = step()
+        torch.cuda.synchronize()
+        print(f"exhaustive: step {k} done at {time.perf_counter() - t0:.2f} s", file=sys.stderr, flush=True)
+    dt = time.perf_counter() - t0
+    rows = out["n_rows"]
+    # the row writer's algorithmic bytes: populations read (4 B per value of x) and the
+    # rows written (8 B bits + 4 B trajectory + 8 B P(x|prefix) + 8 B p(prefix))
+    n_final = int(out["elements_per_batch"][-1])
+    line = {
+        "metric": "distinct labelled bitstrings/sec (exhaustive non-proportional NBS)", "value": rows * args.steps / dt,
+        "unit": "bitstrings/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "c64", "data": "synthetic",
+        "config": {"workload": f"50-qubit 1D brickwork depth 6, Haar SU(4) c64, depolarising p=0.005, {E} "
+                               f"trajectories, batches {bs}, {args.draws} draw(s) per prefix, exhaustive final "
+                               f"batch above P(x|prefix) > {args.threshold}",
+                   "trajectories": E, "batch_sizes": bs, "rows": rows, "final_elements": n_final,
+                   "elements_per_batch": [int(x) for x in out["elements_per_batch"]],
+                   "population_values_scanned": n_final << bf,
+                   "row_bytes_written": rows * 28},
+    }
     print(json.dumps(line), flush=True)
 
 

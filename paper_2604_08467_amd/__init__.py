@@ -233,6 +233,53 @@ class Plan:
         return {"shots": shots[:M], "shot_traj": None if shot_traj is None else shot_traj[:M],
                 "weights": weights, "norms": norms, "elements_per_batch": stats}
 
+    def exhaustive_workspace_size(self, E, draws, max_elems):
+        b = C.c_size_t()
+        _lib.check(self._lib.ptsbe_exhaustive_workspace_size(self._h, int(E), int(draws), int(max_elems),
+                                                             C.byref(b)))
+        return b.value
+
+    def sample_exhaustive(self, kraus_dev, draws, seed, threshold, max_elems=None, capacity=None, mult_dev=None,
+                          workspace=None, stream=None, outputs=None):
+        """ptsbe_sample_exhaustive (non-proportional NBS, exhaustive final batch); returns a dict
+        of device tensors trimmed to the rows found (n_rows may exceed capacity: then the call
+        raises PtsbeError with status OUT_OF_MEMORY and `needed_rows` set on it)."""
+        import torch
+        E = kraus_dev.shape[0]
+        dev = kraus_dev.device
+        if max_elems is None:
+            max_elems = E * int(draws) ** max(len(self.batch_sizes) - 1, 0)
+        if capacity is None:
+            capacity = min(max_elems << self.batch_sizes[-1], 1 << 24)
+        if outputs is None:
+            outputs = {"bits": torch.empty((max(capacity, 1), self.n_words), dtype=torch.int64, device=dev),
+                       "row_traj": torch.empty(max(capacity, 1), dtype=torch.int32, device=dev),
+                       "p_cond": torch.empty(max(capacity, 1), dtype=torch.float64, device=dev),
+                       "p_prefix": torch.empty(max(capacity, 1), dtype=torch.float64, device=dev)}
+        weights = torch.empty(E, dtype=torch.float64, device=dev)
+        norms = torch.empty(E, dtype=torch.float64, device=dev)
+        stats = np.zeros(len(self.batch_sizes), dtype=np.int64)
+        n_rows = C.c_int64(0)
+        if workspace is None:
+            workspace = torch.empty(self.exhaustive_workspace_size(E, draws, max_elems), dtype=torch.uint8,
+                                    device=dev)
+        if stream is None:
+            stream = torch.cuda.current_stream(dev).cuda_stream
+        st = self._lib.ptsbe_sample_exhaustive(
+            self._h, _tptr(kraus_dev), int(E), _tptr(mult_dev), int(draws), int(max_elems), int(seed),
+            float(threshold), _tptr(outputs["bits"]), _tptr(outputs.get("row_traj")), _tptr(outputs.get("p_cond")),
+            _tptr(outputs.get("p_prefix")), int(capacity), C.byref(n_rows), _tptr(weights), _tptr(norms),
+            stats.ctypes.data_as(C.c_void_p), _tptr(workspace), int(workspace.numel()), C.c_void_p(stream))
+        try:
+            _lib.check(st)
+        except _lib.PtsbeError as e:
+            e.needed_rows = n_rows.value
+            raise
+        M = n_rows.value
+        out = {k: (None if v is None else v[:M]) for k, v in outputs.items()}
+        out.update({"n_rows": M, "weights": weights, "norms": norms, "elements_per_batch": stats})
+        return out
+
     def expect_grad(self, spec, kraus_dev, weights_dev, theta_dev, want_grad=True, workspace=None, stream=None):
         """ptsbe_expect_grad: value, per-trajectory values and (optionally) the gradient."""
         import torch

@@ -197,6 +197,11 @@ struct BatchIO {
   // host copy of the trajectories' Kraus indices [E][S]: trajectories that agree
   // on the sites of a batch's per-trajectory part share its tensor (null: no sharing)
   const uint8_t* h_kraus = nullptr;
+  // exhaustive final-batch sampling: rows appended per element chunk (null: off)
+  struct Exhaustive {
+    ptsbe::ExhArgs tmpl{};      // threshold, traj_norm, outputs, capacity
+    int64_t rows = 0;           // rows found so far (host)
+  }* exh = nullptr;
 };
 
 // The noise sites whose Kraus choices enter the per-trajectory part of a batch.
@@ -212,6 +217,41 @@ std::vector<int32_t> right_sites(const Plan& p, const ptsbe::BatchPlan& bp) {
 }
 
 struct EventPair { hipEvent_t a, b; };
+
+// Exhaustive final-batch sampling of one element chunk (Sec. III-B): FP64 totals,
+// rows per (element, tile), their scan, and the ordered row writes.  The row
+// count is read back so that the next chunk's rows follow these.
+ptsbe_status_t exhaustive_chunk(const ptsbe::BatchPlan& bp, BatchIO& io, const float* pop, int64_t a0, int64_t ne,
+                                int tile_bits, Arena& ar, hipStream_t s) {
+  const size_t mark = ar.used;
+  const int64_t n_units = ne << tile_bits;
+  double* tot = (double*)ar.take((size_t)ne * 8);
+  int32_t* cnt = (int32_t*)ar.take((size_t)n_units * 4);
+  int32_t* off = (int32_t*)ar.take((size_t)n_units * 4);
+  int32_t* scratch = (int32_t*)ar.take(ptsbe::scan_scratch_bytes(n_units));
+  int32_t* total = (int32_t*)ar.take(64);
+  if (!tot || !cnt || !off || !scratch || !total)
+    return fail(PTSBE_ERR_OUT_OF_MEMORY, "workspace too small (exhaustive rows)");
+  HIP_TRY(ptsbe::launch_row_totals(pop, ne, bp.size, tot, s));
+  ptsbe::ExhArgs a = io.exh->tmpl;
+  if (a.totals_out) HIP_TRY(hipMemcpyAsync(a.totals_out + a0, tot, (size_t)ne * 8, hipMemcpyDeviceToDevice, s));
+  a.pop = pop; a.b = bp.size; a.start = bp.start;
+  a.n_elems = ne;
+  a.elem_traj = io.elem_traj + a0;
+  a.elem_prefix = io.elem_prefix + a0 * a.NW;
+  a.elem_total = tot;
+  a.tile_cnt = cnt; a.tile_off = off; a.tile_bits = tile_bits;
+  a.row_base = io.exh->rows;
+  HIP_TRY(ptsbe::launch_exh_count(a, s));
+  HIP_TRY(ptsbe::launch_scan_i32(cnt, off, n_units, total, scratch, s));
+  int32_t found = 0;
+  HIP_TRY(hipMemcpyAsync(&found, total, 4, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (found > 0 && a.row_base < a.capacity) HIP_TRY(ptsbe::launch_exh_write(a, s));
+  io.exh->rows += found;
+  ar.used = mark;
+  return PTSBE_OK;
+}
 
 ptsbe_status_t run_batch(Plan& p, int j, const uint8_t* d_kraus, const float2* merged, int64_t E, BatchIO& io,
                          Arena& ar, hipStream_t s, std::vector<EventPair>& evs) {
@@ -240,13 +280,17 @@ ptsbe_status_t run_batch(Plan& p, int j, const uint8_t* d_kraus, const float2* m
                                        : (use_mfma ? ((size_t)8 << rT) : 0);
   const size_t per_traj = ((size_t)8 << rT) + layout_bytes + part_scratch_per_job(bp.right);
   const size_t nb = (size_t)1 << bp.size;
-  const size_t per_elem = (io.V_out ? 0 : ((size_t)8 << rV)) + part_scratch_per_job(left) + (io.sample ? 4 * nb : 0);
+  const bool chunk_pop = io.sample || io.exh;     // populations live per element chunk
+  const int exh_tile_bits = bp.size > 12 ? bp.size - 12 : 0;
+  const size_t per_elem = (io.V_out ? 0 : ((size_t)8 << rV)) + part_scratch_per_job(left) +
+                          (chunk_pop ? 4 * nb : 0) + (io.exh ? 16 + ((size_t)12 << exh_tile_bits) : 0);
   const size_t avail = ar.left();
   int64_t t_cap = (int64_t)std::min<size_t>((size_t)E, (avail / 2) / per_traj);
   int64_t e_cap = (int64_t)((avail / 2) / per_elem);
   if (t_cap < 1 || e_cap < 1)
     return fail(PTSBE_ERR_OUT_OF_MEMORY, "workspace too small for one trajectory of batch " + std::to_string(j));
   e_cap = std::min<int64_t>(e_cap, 1 << 22);
+  if (io.exh) e_cap = std::min<int64_t>(e_cap, std::max<int64_t>(1, (((int64_t)1 << 31) - 1) >> bp.size));
   t_cap = std::min<int64_t>(t_cap, 65535);       // one grid dimension of the MFMA join
   const ptsbe::AbsorbStep* d_left = p.d_steps + p.part_step_off[3 * j + (io.resume ? 2 : 0)];
   const ptsbe::AbsorbStep* d_right = p.d_steps + p.part_step_off[3 * j + 1];
@@ -315,8 +359,8 @@ ptsbe_status_t run_batch(Plan& p, int j, const uint8_t* d_kraus, const float2* m
       const int64_t a1 = std::min<int64_t>(e1, a0 + e_cap), ne = a1 - a0;
       const size_t mark2 = ar.used;
       float2* V = io.V_out ? io.V_out + a0 * ((int64_t)1 << rV) : (float2*)ar.take((size_t)ne * ((size_t)8 << rV));
-      float* pop = io.sample ? (float*)ar.take((size_t)ne * nb * 4) : nullptr;
-      if (!V || (io.sample && !pop)) return fail(PTSBE_ERR_OUT_OF_MEMORY, "workspace too small (elements)");
+      float* pop = chunk_pop ? (float*)ar.take((size_t)ne * nb * 4) : nullptr;
+      if (!V || (chunk_pop && !pop)) return fail(PTSBE_ERR_OUT_OF_MEMORY, "workspace too small (elements)");
       ptsbe::InitArgs init;
       if (io.resume) {
         init.Vprev = io.V_prev;
@@ -336,7 +380,7 @@ ptsbe_status_t run_batch(Plan& p, int j, const uint8_t* d_kraus, const float2* m
       ja.xb_bits = (int)bp.xb.size(); ja.lk_bits = (int)bp.lk.size(); ja.xT_bits = (int)bp.xT.size();
       ja.tab = p.d_tables; ja.jd = jdv;
       ja.b = bp.size; ja.doubled = bp.doubled ? 1 : 0;
-      if (io.sample) {
+      if (chunk_pop) {
         ja.pop = pop;
       } else {
         ja.pop = io.pop_out ? io.pop_out + a0 * (int64_t)nb : nullptr;
@@ -398,6 +442,9 @@ ptsbe_status_t run_batch(Plan& p, int j, const uint8_t* d_kraus, const float2* m
         sa.elem_total = io.sa.elem_total + a0;
         sa.child_cnt = io.sa.child_cnt ? io.sa.child_cnt + a0 : nullptr;
         HIP_TRY(ptsbe::launch_sample(sa, s));
+      } else if (io.exh) {
+        st = exhaustive_chunk(bp, io, pop, a0, ne, exh_tile_bits, ar, s);
+        if (st != PTSBE_OK) return st;
       } else if (io.totals && ja.pop) {
         HIP_TRY(ptsbe::launch_row_totals(ja.pop, ne, bp.size, io.totals + a0, s));
       }
@@ -1174,6 +1221,200 @@ ptsbe_status_t ptsbe_sample_shots(ptsbe_plan_t plan, const uint8_t* d_kraus_idx,
     if (st != PTSBE_OK) return st;
   }
   if (bad) return fail(PTSBE_ERR_NUMERIC, "an element had a non-finite marginal total");
+  return PTSBE_OK;
+}
+
+namespace {
+// Persistent arrays of ptsbe_sample_exhaustive, in the order they are taken.
+struct ExhLayout {
+  int32_t* traj[2]; uint64_t* prefix[2]; int32_t* off[2]; int32_t* cnt[2]; int32_t* ids[2]; int32_t* parent[2];
+  float2* V[2];
+  int32_t *shot_x, *child_cnt, *child_off, *scan_scratch, *counters;
+  double *totals, *norms;
+  int64_t* base;
+  float2* merged;
+};
+
+bool take_exh_layout(const Plan& p, int64_t E, int64_t cap, int32_t draws, Arena& ar, ExhLayout& L) {
+  int rVmax = 0;
+  for (auto& bp : p.batches) rVmax = std::max<int>(rVmax, (int)bp.left_resume.labels.size());
+  const size_t rows = (size_t)cap * (size_t)draws;
+  bool ok = true;
+  auto take = [&](size_t bytes) {   // every array is taken, so a probe arena measures the whole layout
+    void* q = ar.take(bytes);
+    ok = ok && q != nullptr;
+    return q;
+  };
+  for (int k = 0; k < 2; ++k) {
+    L.traj[k] = (int32_t*)take((size_t)cap * 4);
+    L.prefix[k] = (uint64_t*)take((size_t)cap * 8 * p.NW);
+    L.off[k] = (int32_t*)take((size_t)cap * 4);
+    L.cnt[k] = (int32_t*)take((size_t)cap * 4);
+    L.ids[k] = (int32_t*)take(rows * 4);
+    L.parent[k] = (int32_t*)take((size_t)cap * 4);
+    L.V[k] = (float2*)take((size_t)cap * ((size_t)8 << rVmax));
+  }
+  L.shot_x = (int32_t*)take(rows * 4);
+  L.child_cnt = (int32_t*)take((size_t)cap * 4);
+  L.child_off = (int32_t*)take((size_t)cap * 4);
+  L.scan_scratch = (int32_t*)take(ptsbe::scan_scratch_bytes(cap));
+  L.counters = (int32_t*)take(64);
+  L.totals = (double*)take((size_t)cap * 8);
+  L.norms = (double*)take((size_t)E * 8);
+  L.base = (int64_t*)take((size_t)E * 8);
+  L.merged = (float2*)take(merged_bytes(p, E));
+  return ok;
+}
+}  // namespace
+
+ptsbe_status_t ptsbe_exhaustive_workspace_size(ptsbe_plan_t plan, int64_t E, int32_t draws, int64_t max_elems,
+                                               size_t* bytes) {
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  if (!p || !bytes) return fail(PTSBE_ERR_INVALID_ARG, "null argument");
+  if (E < 1 || draws < 1) return fail(PTSBE_ERR_INVALID_ARG, "E < 1 or draws < 1");
+  const int64_t cap = std::max<int64_t>(E, max_elems);
+  Arena probe;                       // an arena without memory measures the layout
+  probe.base = nullptr;
+  probe.cap = ~(size_t)0 >> 1;
+  ExhLayout L;
+  take_exh_layout(*p, E, cap, draws, probe, L);
+  size_t chunk = 0;
+  for (auto& bp : p->batches) {
+    const size_t per_traj = join_traj_bytes(bp);
+    const size_t tb = bp.size > 12 ? (size_t)1 << (bp.size - 12) : 1;
+    const size_t per_elem = ((size_t)8 << bp.left.labels.size()) + part_scratch_per_job(bp.left) +
+                            ((size_t)4 << bp.size) + 16 + 12 * tb;
+    // trajectories and elements per chunk: up to 256 / 65536, within about 8 GiB each
+    const size_t nt = std::max<size_t>(1, std::min<size_t>(std::min<size_t>(E, 256), ((size_t)8 << 30) / per_traj));
+    const size_t ne = std::max<size_t>(1, std::min<size_t>(std::min<size_t>(cap, 65536), ((size_t)8 << 30) / per_elem));
+    chunk = std::max(chunk, 2 * (nt * per_traj + ne * per_elem));
+  }
+  *bytes = probe.used + (size_t)(E + 1) * 4 + chunk + (1 << 20);
+  return PTSBE_OK;
+}
+
+ptsbe_status_t ptsbe_sample_exhaustive(ptsbe_plan_t plan, const uint8_t* d_kraus_idx, int64_t E,
+                                       const int64_t* d_mult, int32_t draws, int64_t max_elems, uint64_t seed,
+                                       double threshold, uint64_t* d_bits, int32_t* d_row_traj, double* d_p_cond,
+                                       double* d_p_prefix, int64_t capacity, int64_t* n_rows_out,
+                                       double* d_traj_weight, double* d_traj_norm, int64_t* stats_out,
+                                       void* d_workspace, size_t workspace_bytes, void* stream) {
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  if (!p) return fail(PTSBE_ERR_INVALID_ARG, "null plan");
+  if (p->device < 0) return fail(PTSBE_ERR_INVALID_ARG, "plan was built without a device");
+  if (p->method == PTSBE_METHOD_STATEVECTOR)
+    return fail(PTSBE_ERR_UNSUPPORTED, "exhaustive sampling runs on network-method plans");
+  const int f = (int)p->batches.size();
+  for (int j = 0; j + 1 < f; ++j)
+    if (p->batches[j].size > 12) return fail(PTSBE_ERR_UNSUPPORTED, "non-final batches of at most 12 qubits");
+  if (E < 1 || draws < 1 || capacity < 0) return fail(PTSBE_ERR_INVALID_ARG, "E < 1, draws < 1 or capacity < 0");
+  if (std::isnan(threshold)) return fail(PTSBE_ERR_INVALID_ARG, "threshold is NaN");
+  if (!d_kraus_idx || !d_workspace || !n_rows_out || (capacity > 0 && !d_bits))
+    return fail(PTSBE_ERR_INVALID_ARG, "null pointer");
+  const int64_t cap = std::max<int64_t>(E, max_elems);
+  if (cap * (int64_t)draws >= ((int64_t)1 << 31)) return fail(PTSBE_ERR_UNSUPPORTED, "max_elems * draws >= 2^31");
+  *n_rows_out = 0;
+  HIP_TRY(hipSetDevice(p->device));
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<uint8_t> h_kraus((size_t)E * p->site_gate.size());
+  if (!h_kraus.empty()) {
+    HIP_TRY(hipMemcpyAsync(h_kraus.data(), d_kraus_idx, h_kraus.size(), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+  }
+  Arena ar;
+  ar.base = (char*)d_workspace;
+  ar.cap = workspace_bytes;
+  ExhLayout L;
+  if (!take_exh_layout(*p, E, cap, draws, ar, L))
+    return fail(PTSBE_ERR_OUT_OF_MEMORY, "workspace too small for the element arrays");
+  HIP_TRY(hipMemsetAsync(L.counters, 0, 64, s));
+  HIP_TRY(ptsbe::launch_np_init(E, L.traj[0], L.prefix[0], p->NW, s));
+  HIP_TRY(ptsbe::launch_upv_merge(gate_ctx(*p, d_kraus_idx, nullptr), E, L.merged, s));
+  BatchIO::Exhaustive exh;
+  exh.tmpl.NW = p->NW;
+  exh.tmpl.traj_norm = f > 1 ? L.norms : nullptr;      // one batch: p(prefix) = 1
+  exh.tmpl.threshold = threshold;
+  exh.tmpl.capacity = capacity;
+  exh.tmpl.bits = d_bits; exh.tmpl.row_traj = d_row_traj; exh.tmpl.p_cond = d_p_cond; exh.tmpl.p_prefix = d_p_prefix;
+  exh.tmpl.totals_out = f > 1 ? nullptr : L.norms;    // one batch: its totals are the norms
+  int cur = 0;
+  int64_t U = E;
+  std::vector<EventPair> evs;
+  for (int j = 0; j < f; ++j) {
+    if (stats_out) stats_out[j] = U;
+    const auto& bp = p->batches[j];
+    const bool last = j + 1 == f;
+    BatchIO io;
+    io.h_kraus = h_kraus.empty() ? nullptr : h_kraus.data();
+    io.elem_traj = L.traj[cur];
+    io.elem_prefix = L.prefix[cur];
+    io.V_out = L.V[j & 1];
+    if (j >= 1) {
+      io.resume = true;
+      io.V_prev = L.V[(j - 1) & 1];
+      const auto& pv = p->batches[j - 1];
+      io.V_prev_stride = (int64_t)1 << (j - 1 == 0 ? pv.left.labels.size() : pv.left_resume.labels.size());
+      io.parent = L.parent[cur];
+    }
+    io.U = U;
+    if (!last) {
+      HIP_TRY(ptsbe::launch_np_rows(U, draws, L.traj[cur], L.off[cur], L.cnt[cur], L.ids[cur], L.base, s));
+      io.sample = true;
+      ptsbe::SampleArgs& sa = io.sa;
+      sa.b = bp.size; sa.start = bp.start; sa.NW = p->NW;
+      sa.elem_shot_off = L.off[cur]; sa.elem_shot_cnt = L.cnt[cur];
+      sa.shot_ids = L.ids[cur];
+      sa.traj_shot_base = L.base;
+      sa.seed = seed; sa.j = j; sa.tag = 3u;
+      sa.shots = nullptr; sa.shot_x = L.shot_x;
+      sa.elem_total = L.totals;
+      sa.child_cnt = L.child_cnt;
+      sa.bad_flag = L.counters + 1;
+    } else {
+      io.exh = &exh;
+    }
+    ptsbe_status_t st = run_batch(*p, j, d_kraus_idx, L.merged, E, io, ar, s, evs);
+    if (st != PTSBE_OK) return st;
+    if (j == 0 && !last) HIP_TRY(hipMemcpyAsync(L.norms, L.totals, (size_t)E * 8, hipMemcpyDeviceToDevice, s));
+    if (j == 0 && (d_traj_weight || d_traj_norm)) {
+      ptsbe::WeightArgs wa{L.norms, d_mult, E, d_traj_weight, d_traj_norm};
+      HIP_TRY(ptsbe::launch_weights(wa, s));
+    }
+    if (!last) {
+      HIP_TRY(ptsbe::launch_scan_i32(L.child_cnt, L.child_off, U, L.counters, L.scan_scratch, s));
+      int32_t nU = 0;
+      HIP_TRY(hipMemcpyAsync(&nU, L.counters, 4, hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      if (nU > cap) return fail(PTSBE_ERR_OUT_OF_MEMORY, "batch " + std::to_string(j + 1) + " has " +
+                                                          std::to_string(nU) + " elements, more than max_elems");
+      ptsbe::ChildArgs ca{};
+      ca.n_elems = U; ca.b = bp.size; ca.start = bp.start; ca.NW = p->NW;
+      ca.elem_traj = L.traj[cur]; ca.elem_prefix = L.prefix[cur];
+      ca.elem_shot_off = L.off[cur]; ca.elem_shot_cnt = L.cnt[cur];
+      ca.shot_ids = L.ids[cur]; ca.shot_x = L.shot_x; ca.child_off = L.child_off;
+      ca.out_traj = L.traj[1 - cur]; ca.out_prefix = L.prefix[1 - cur];
+      ca.out_shot_off = L.off[1 - cur]; ca.out_shot_cnt = L.cnt[1 - cur]; ca.out_shot_ids = L.ids[1 - cur];
+      ca.out_parent = L.parent[1 - cur];
+      HIP_TRY(ptsbe::launch_children(ca, s));
+      cur = 1 - cur;
+      U = nU;
+    }
+  }
+  if (f == 1 && (d_traj_weight || d_traj_norm)) {   // the norms came from the final batch's totals
+    ptsbe::WeightArgs wa{L.norms, d_mult, E, d_traj_weight, d_traj_norm};
+    HIP_TRY(ptsbe::launch_weights(wa, s));
+  }
+  int32_t bad = 0;
+  HIP_TRY(hipMemcpyAsync(&bad, L.counters + 1, 4, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (p->profile) {
+    ptsbe_status_t st = collect_events(*p, evs);
+    if (st != PTSBE_OK) return st;
+  }
+  *n_rows_out = exh.rows;
+  if (bad) return fail(PTSBE_ERR_NUMERIC, "an element had a non-finite marginal total");
+  if (exh.rows > capacity)
+    return fail(PTSBE_ERR_OUT_OF_MEMORY, std::to_string(exh.rows) + " rows found, capacity " + std::to_string(capacity));
   return PTSBE_OK;
 }
 

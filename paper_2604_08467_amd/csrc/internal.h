@@ -339,8 +339,38 @@ struct SampleArgs {
   double* elem_total;                    // [n_elems]
   int32_t* child_cnt;                    // [n_elems] or null
   int32_t* bad_flag;                     // set to 1 on a zero / non-finite total
+  uint32_t tag = 2u;                     // Philox stream: 2 shot draws, 3 non-proportional draws
 };
 hipError_t launch_sample(const SampleArgs& a, hipStream_t stream);
+
+// Non-proportional NBS (Sec. III-B): element e of a non-final batch takes
+// `draws` fresh draws on the rows [e * draws, (e + 1) * draws); traj_base[t] is
+// the first row of trajectory t's elements, so a draw's Philox counter is the
+// element's rank within its trajectory times `draws` plus the draw index.
+hipError_t launch_np_init(int64_t E, int32_t* elem_traj, uint64_t* elem_prefix, int NW, hipStream_t stream);
+hipError_t launch_np_rows(int64_t n_elems, int draws, const int32_t* elem_traj, int32_t* shot_off,
+                          int32_t* shot_cnt, int32_t* shot_ids, int64_t* traj_base, hipStream_t stream);
+
+// Exhaustive final-batch sampling (Sec. III-B): one row for every x whose
+// conditional P(x | prefix) = pop(x) / Z_e is strictly above the threshold, in
+// element order then x ascending.  Work unit: (element, tile of kExhTile values).
+constexpr int kExhTile = 4096;
+struct ExhArgs {
+  const float* pop; int b; int start; int NW;
+  int64_t n_elems;
+  const int32_t* elem_traj; const uint64_t* elem_prefix;
+  const double* elem_total;              // [n_elems] Z_e
+  const double* traj_norm;               // [E] squared norm of each trajectory
+  double threshold;
+  int32_t* tile_cnt;                     // [n_elems << tile_bits] rows per tile
+  const int32_t* tile_off;               // exclusive scan of tile_cnt
+  int tile_bits;                         // log2 tiles per element
+  int64_t row_base, capacity;            // rows at or beyond capacity are not written
+  double* totals_out;                    // [n_elems] copy of Z_e (null: none)
+  uint64_t* bits; int32_t* row_traj; double* p_cond; double* p_prefix;   // any of the last three may be null
+};
+hipError_t launch_exh_count(const ExhArgs& a, hipStream_t stream);
+hipError_t launch_exh_write(const ExhArgs& a, hipStream_t stream);
 
 struct ChildArgs {
   int32_t* out_parent;                   // [children] index of the parent element

@@ -977,7 +977,7 @@ __global__ void __launch_bounds__(64) sample_kernel(SampleArgs a) {
     for (int i = lane; i < cnt; i += 64) {
       const int row = a.shot_ids[off + i];
       const uint32_t t = (uint32_t)(row - tbase);
-      const double u = philox_uniform(a.seed, 2u, (uint32_t)traj, (uint32_t)a.j, t, 0u);
+      const double u = philox_uniform(a.seed, a.tag, (uint32_t)traj, (uint32_t)a.j, t, 0u);
       const double target = u * Z;
       int lo = 0, hi = nl;                      // first lane with cend > target
       while (lo < hi) {
@@ -997,12 +997,13 @@ __global__ void __launch_bounds__(64) sample_kernel(SampleArgs a) {
       }
       if (x < 0) x = 0;
       a.shot_x[row] = x;
-      // write the batch bits at qubits [start, start + b)
-      uint64_t* w = a.shots + (int64_t)row * a.NW;
-      const int q0 = a.start;
-      const int wi = q0 >> 6, sh = q0 & 63;
-      w[wi] |= (uint64_t)x << sh;
-      if (sh + a.b > 64) w[wi + 1] |= (uint64_t)x >> (64 - sh);
+      if (a.shots) {   // write the batch bits at qubits [start, start + b)
+        uint64_t* w = a.shots + (int64_t)row * a.NW;
+        const int q0 = a.start;
+        const int wi = q0 >> 6, sh = q0 & 63;
+        w[wi] |= (uint64_t)x << sh;
+        if (sh + a.b > 64) w[wi + 1] |= (uint64_t)x >> (64 - sh);
+      }
       if (want_hist) atomicAdd(&hist[x], 1);
     }
     if (a.child_cnt) {
@@ -1091,6 +1092,107 @@ __global__ void __launch_bounds__(64) children_kernel(ChildArgs a) {
       a.out_shot_ids[off + pos] = row;
     }
     __syncthreads();   // LDS is reused by the next element
+  }
+}
+
+// ------------------------------------------- non-proportional NBS (Sec. III-B)
+__global__ void np_init_kernel(int64_t E, int32_t* elem_traj, uint64_t* elem_prefix, int NW) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < E; e += (int64_t)gridDim.x * blockDim.x) {
+    elem_traj[e] = (int32_t)e;
+    for (int w = 0; w < NW; ++w) elem_prefix[e * NW + w] = 0ull;
+  }
+}
+
+__global__ void np_rows_kernel(int64_t n_elems, int draws, const int32_t* elem_traj, int32_t* off, int32_t* cnt,
+                               int32_t* ids, int64_t* traj_base) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n_elems;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r0 = e * draws;
+    off[e] = (int32_t)r0;
+    cnt[e] = draws;
+    for (int d = 0; d < draws; ++d) ids[r0 + d] = (int32_t)(r0 + d);
+    if (e == 0 || elem_traj[e] != elem_traj[e - 1]) traj_base[elem_traj[e]] = r0;
+  }
+}
+
+// Thread t of a tile owns the values [t per, (t + 1) per) of the tile; the
+// threshold decision is the same expression in both kernels.
+__device__ inline bool exh_pass(float v, double Z, double thr) { return Z > 0.0 && (double)v / Z > thr; }
+
+__global__ void __launch_bounds__(256) exh_count_kernel(ExhArgs a) {
+  __shared__ int red[256];
+  const int64_t X = (int64_t)1 << a.b;
+  const int tileX = X < kExhTile ? (int)X : kExhTile;
+  const int per = tileX >= 256 ? tileX >> 8 : 1;
+  const int64_t n_units = a.n_elems << a.tile_bits;
+  for (int64_t u = blockIdx.x; u < n_units; u += gridDim.x) {
+    const int64_t e = u >> a.tile_bits;
+    const int64_t x0 = (u & (((int64_t)1 << a.tile_bits) - 1)) * tileX;
+    const double Z = a.elem_total[e];
+    const float* pi = a.pop + e * X + x0;
+    int c = 0;
+    const int lo = threadIdx.x * per;
+    if (lo < tileX)
+      for (int i = lo; i < lo + per; ++i) c += exh_pass(pi[i], Z, a.threshold);
+    red[threadIdx.x] = c;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) a.tile_cnt[u] = red[0];
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(256) exh_write_kernel(ExhArgs a) {
+  __shared__ int scan[256];
+  const int64_t X = (int64_t)1 << a.b;
+  const int tileX = X < kExhTile ? (int)X : kExhTile;
+  const int per = tileX >= 256 ? tileX >> 8 : 1;
+  const int64_t n_units = a.n_elems << a.tile_bits;
+  const int tid = threadIdx.x;
+  const int wi = a.start >> 6, sh = a.start & 63;
+  for (int64_t u = blockIdx.x; u < n_units; u += gridDim.x) {
+    const int64_t e = u >> a.tile_bits;
+    const int64_t x0 = (u & (((int64_t)1 << a.tile_bits) - 1)) * tileX;
+    const double Z = a.elem_total[e];
+    const float* pi = a.pop + e * X + x0;
+    const int lo = tid * per;
+    const bool mine = lo < tileX;
+    int c = 0;
+    if (mine)
+      for (int i = lo; i < lo + per; ++i) c += exh_pass(pi[i], Z, a.threshold);
+    // exclusive scan of the threads' counts (Hillis-Steele in LDS)
+    scan[tid] = c;
+    __syncthreads();
+    for (int d = 1; d < 256; d <<= 1) {
+      const int t = tid >= d ? scan[tid - d] : 0;
+      __syncthreads();
+      scan[tid] += t;
+      __syncthreads();
+    }
+    int64_t row = a.row_base + a.tile_off[u] + scan[tid] - c;
+    __syncthreads();   // scan[] is rewritten by the next unit
+    if (!mine || c == 0) continue;
+    const int traj = a.elem_traj[e];
+    const uint64_t* pp = a.elem_prefix + e * a.NW;
+    const double pref = a.traj_norm ? Z / a.traj_norm[traj] : 1.0;
+    for (int i = lo; i < lo + per; ++i) {
+      const float v = pi[i];
+      if (!exh_pass(v, Z, a.threshold)) continue;
+      if (row < a.capacity) {
+        const uint64_t x = (uint64_t)(x0 + i);
+        uint64_t* w = a.bits + row * a.NW;
+        for (int k = 0; k < a.NW; ++k) w[k] = pp[k];
+        w[wi] |= x << sh;
+        if (sh + a.b > 64) w[wi + 1] |= x >> (64 - sh);
+        if (a.row_traj) a.row_traj[row] = traj;
+        if (a.p_cond) a.p_cond[row] = (double)v / Z;
+        if (a.p_prefix) a.p_prefix[row] = pref;
+      }
+      ++row;
+    }
   }
 }
 
@@ -1411,6 +1513,36 @@ hipError_t launch_children(const ChildArgs& a, hipStream_t stream) {
   const int n = 1 << a.b;
   const size_t shmem = (size_t)3 * n * sizeof(int);
   hipLaunchKernelGGL(children_kernel, dim3(grid_blocks(a.n_elems)), dim3(64), shmem, stream, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_np_init(int64_t E, int32_t* elem_traj, uint64_t* elem_prefix, int NW, hipStream_t stream) {
+  if (E <= 0) return hipSuccess;
+  hipLaunchKernelGGL(np_init_kernel, dim3(grid_blocks((E + 255) / 256)), dim3(256), 0, stream, E, elem_traj,
+                     elem_prefix, NW);
+  return hipGetLastError();
+}
+
+hipError_t launch_np_rows(int64_t n_elems, int draws, const int32_t* elem_traj, int32_t* shot_off,
+                          int32_t* shot_cnt, int32_t* shot_ids, int64_t* traj_base, hipStream_t stream) {
+  if (n_elems <= 0) return hipSuccess;
+  if (draws < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(np_rows_kernel, dim3(grid_blocks((n_elems + 255) / 256)), dim3(256), 0, stream, n_elems, draws,
+                     elem_traj, shot_off, shot_cnt, shot_ids, traj_base);
+  return hipGetLastError();
+}
+
+hipError_t launch_exh_count(const ExhArgs& a, hipStream_t stream) {
+  if (a.n_elems <= 0) return hipSuccess;
+  if (a.b < 0 || a.b > kMaxBatch || a.tile_bits != (a.b > 12 ? a.b - 12 : 0)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(exh_count_kernel, dim3(grid_blocks(a.n_elems << a.tile_bits)), dim3(256), 0, stream, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_exh_write(const ExhArgs& a, hipStream_t stream) {
+  if (a.n_elems <= 0) return hipSuccess;
+  if (a.b < 0 || a.b > kMaxBatch || a.tile_bits != (a.b > 12 ? a.b - 12 : 0) || !a.bits) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(exh_write_kernel, dim3(grid_blocks(a.n_elems << a.tile_bits)), dim3(256), 0, stream, a);
   return hipGetLastError();
 }
 

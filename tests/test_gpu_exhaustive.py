@@ -1,0 +1,146 @@
+"""Non-proportional NBS with exhaustive final-batch sampling (Sec. III-B) through
+the C ABI, against the FP64 oracle.
+
+Draws at the non-final batches use the same Philox counters on both sides, so
+the sets of prefixes must be identical (a CDF-boundary flip would change one;
+at these sizes its probability is far below 1e-3 for the whole test).  Rows are
+compared bit for bit except values of x whose oracle conditional lies within
+1e-6 of the threshold (FP32 populations decide those); conditionals and prefix
+probabilities within 1e-6 absolute, trajectory norms and weights 1e-5 relative."""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import sampling
+from tests.gpu_helpers import oracle_states, shots_to_ints, to_dev, torch_dev
+
+pytestmark = pytest.mark.gpu
+
+BAND = 1e-6
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _oracle_rows(circ, bs, kr, draws, seed, thr):
+    n, starts = circ.n_qubits, sampling.batch_starts(bs)
+    rows, counts = [], np.zeros(len(bs), dtype=np.int64)
+    psis = oracle_states(circ, kr)
+    for i, psi in enumerate(psis):
+        def mfn(j, prefix, psi=psi):
+            return sampling.marginal_from_state(psi, n, starts[j], bs[j], prefix)
+        r, c = sampling.nonproportional_trajectory(mfn, i, n, bs, draws, seed, thr)
+        rows.extend((i,) + tuple(x) for x in r)
+        counts += np.array(c)
+    return rows, counts, psis
+
+
+def _compare(out, ref_rows, ref_counts, bs, thr, tag):
+    got_bits = shots_to_ints(out["bits"].cpu().numpy())
+    got_traj = out["row_traj"].cpu().numpy()
+    got_pc = out["p_cond"].cpu().numpy()
+    got_pp = out["p_prefix"].cpu().numpy()
+    assert list(out["elements_per_batch"]) == list(ref_counts), (tag, out["elements_per_batch"], ref_counts)
+    got = {(int(t), b): (pc, pp) for t, b, pc, pp in zip(got_traj, got_bits, got_pc, got_pp)}
+    ref = {(t, b): (pc, pp) for t, b, pc, pp in ref_rows}
+    assert len(got) == len(got_bits)                      # no row twice
+    only_got = [k for k in got if k not in ref]
+    only_ref = [k for k in ref if k not in got]
+    for k in only_got:
+        assert abs(got[k][0] - thr) <= BAND, (tag, "extra row", k, got[k])
+    for k in only_ref:
+        assert abs(ref[k][0] - thr) <= BAND, (tag, "missing row", k, ref[k])
+    err_pc = max((abs(got[k][0] - ref[k][0]) for k in got if k in ref), default=0.0)
+    err_pp = max((abs(got[k][1] - ref[k][1]) for k in got if k in ref), default=0.0)
+    _say(f"{tag}: {len(got_bits)} rows (oracle {len(ref_rows)}), {len(only_got)}+{len(only_ref)} in the "
+         f"threshold band; max |dP(x|prefix)| {err_pc:.2e}, max |dp(prefix)| {err_pp:.2e}")
+    assert err_pc <= 1e-6 and err_pp <= 1e-6
+    # row order: trajectory, then prefix (first batch most significant), then x
+    keys = [(int(t),) + tuple((b >> s) & ((1 << w) - 1) for s, w in zip(sampling.batch_starts(bs), bs))
+            for t, b in zip(got_traj, got_bits)]
+    assert keys == sorted(keys)
+
+
+@pytest.mark.parametrize("bs,draws,thr", [([4, 4, 4], 3, 1e-3), ([5, 7], 5, 0.0), ([3, 3, 3, 3], 2, 2e-3)],
+                         ids=["4-4-4_k3", "5-7_k5", "3x4_k2"])
+def test_exhaustive_matches_oracle(bs, draws, thr):
+    import paper_2604_08467_amd as P
+    torch, dev = torch_dev()
+    rng = np.random.default_rng(301)
+    circ = W.random_brickwork(sum(bs), 5, rng, 0.02)
+    plan = P.Plan(circ, bs, method="network")
+    kr, mult, _, _ = plan.sample_trajectories(302, 12)
+    out = plan.sample_exhaustive(to_dev(torch, dev, kr), draws, 303, thr, mult_dev=to_dev(torch, dev, mult))
+    torch.cuda.synchronize()
+    ref_rows, ref_counts, psis = _oracle_rows(circ, bs, kr, draws, 303, thr)
+    _compare(out, ref_rows, ref_counts, bs, thr, f"batches {bs}, draws {draws}, threshold {thr}")
+    Z = np.array([np.vdot(p, p).real for p in psis])
+    np.testing.assert_allclose(out["norms"].cpu().numpy(), Z, rtol=1e-5)
+    np.testing.assert_allclose(out["weights"].cpu().numpy(), sampling.trajectory_weights(Z, mult), rtol=1e-5)
+
+
+def test_exhaustive_single_batch():
+    """One batch: every trajectory's rows are its x with |psi(x)|^2 / Z above the threshold,
+    p(prefix) = 1; the norms come from the batch's own totals."""
+    import paper_2604_08467_amd as P
+    torch, dev = torch_dev()
+    wl = W.config1()
+    plan = P.Plan(wl.circuit, wl.batch_sizes, method="network")
+    kr, mult, _, _ = plan.sample_trajectories(wl.pts_seed, 16)
+    thr = 2e-3
+    out = plan.sample_exhaustive(to_dev(torch, dev, kr), 1, 5, thr, mult_dev=to_dev(torch, dev, mult))
+    ref_rows, ref_counts, psis = _oracle_rows(wl.circuit, wl.batch_sizes, kr, 1, 5, thr)
+    _compare(out, ref_rows, ref_counts, wl.batch_sizes, thr, "single batch")
+    assert np.all(out["p_prefix"].cpu().numpy() == 1.0)
+    Z = np.array([np.vdot(p, p).real for p in psis])
+    np.testing.assert_allclose(out["norms"].cpu().numpy(), Z, rtol=1e-5)
+    np.testing.assert_allclose(out["weights"].cpu().numpy(), sampling.trajectory_weights(Z, mult), rtol=1e-5)
+
+
+def test_exhaustive_large_final_batch():
+    """A 16-qubit final batch (16 tiles of 4096 values per element) after a 4-qubit batch."""
+    import paper_2604_08467_amd as P
+    torch, dev = torch_dev()
+    rng = np.random.default_rng(311)
+    circ = W.random_brickwork(20, 4, rng, 0.02)
+    bs = [4, 16]
+    plan = P.Plan(circ, bs, method="network")
+    kr, mult, _, _ = plan.sample_trajectories(312, 3)
+    thr = 1e-5
+    out = plan.sample_exhaustive(to_dev(torch, dev, kr), 2, 313, thr)
+    ref_rows, ref_counts, _ = _oracle_rows(circ, bs, kr, 2, 313, thr)
+    _compare(out, ref_rows, ref_counts, bs, thr, "final batch of 16 qubits")
+    # every prefix's rows at threshold 0 would sum to 1; above it they sum to at most 1
+    pc = out["p_cond"].cpu().numpy()
+    assert pc.max() <= 1.0 + 1e-6
+
+
+def test_exhaustive_capacity_overflow_keeps_the_first_rows():
+    import paper_2604_08467_amd as P
+    torch, dev = torch_dev()
+    rng = np.random.default_rng(321)
+    circ = W.random_brickwork(12, 5, rng, 0.02)
+    bs = [4, 8]
+    plan = P.Plan(circ, bs, method="network")
+    kr, _, _, _ = plan.sample_trajectories(322, 6)
+    kd = to_dev(torch, dev, kr)
+    full = plan.sample_exhaustive(kd, 3, 323, 1e-4)
+    n = full["n_rows"]
+    assert n > 10
+    with pytest.raises(P.PtsbeError) as ei:
+        plan.sample_exhaustive(kd, 3, 323, 1e-4, capacity=n // 2)
+    assert ei.value.needed_rows == n
+    part = {k: torch.empty((n // 2,) + tuple(v.shape[1:]), dtype=v.dtype, device=dev)
+            for k, v in full.items() if k in ("bits", "row_traj", "p_cond", "p_prefix")}
+    with pytest.raises(P.PtsbeError):
+        plan.sample_exhaustive(kd, 3, 323, 1e-4, capacity=n // 2, outputs=part)
+    torch.cuda.synchronize()
+    assert torch.equal(part["bits"], full["bits"][:n // 2])
+    assert torch.equal(part["row_traj"], full["row_traj"][:n // 2])
+    # more elements than max_elems is an error, not an overrun
+    with pytest.raises(P.PtsbeError):
+        plan.sample_exhaustive(kd, 3, 323, 1e-4, max_elems=len(kr))
