@@ -295,6 +295,8 @@ ptsbe_status_t run_batch(Plan& p, int j, const uint8_t* d_kraus, const float2* m
   const ptsbe::AbsorbStep* d_left = p.d_steps + p.part_step_off[3 * j + (io.resume ? 2 : 0)];
   const ptsbe::AbsorbStep* d_right = p.d_steps + p.part_step_off[3 * j + 1];
   const std::vector<int32_t> rsites = io.h_kraus ? right_sites(p, bp) : std::vector<int32_t>();
+  ptsbe::GemvTiling gtile{};
+  const bool gemv_tiled = !bp.doubled && bp.xb.size() <= 1 && ptsbe::make_gemv_tiling(bp, gtile);
   const int64_t S = (int64_t)p.site_gate.size();
   std::vector<std::vector<int32_t>> keep;         // host sources of async uploads
   struct SyncOnExit {                             // on every return (errors included), the
@@ -342,9 +344,15 @@ ptsbe_status_t run_batch(Plan& p, int j, const uint8_t* d_kraus, const float2* m
     ptsbe_status_t st = run_part(p, bp.right, d_right, g, n_rt, d_rjob, (int32_t)t0, nullptr,
                                  ptsbe::InitArgs(), T, ar, s);
     if (st != PTSBE_OK) return st;
+    // last batch with at most two elements per trajectory: a GEMV on T's own layout
+    // (T read once per element) beats the canonical copy plus the MFMA join
+    const bool gemv = !bp.doubled && ptsbe::ketjoin_gemv_supported((int)bp.xb.size(), lkb, (int)bp.xT.size()) &&
+                      e1 - e0 <= 2 * (t1 - t0);
     float2* Tc = nullptr;
     float* Th = nullptr;
-    if (use_fold) {   // Theta (folded bilinear-form coefficients) for the FP32 MFMA doubled join
+    if (gemv) {
+      // T is read in place
+    } else if (use_fold) {   // Theta (folded bilinear-form coefficients) for the FP32 MFMA doubled join
       Th = (float*)ar.take((size_t)n_rt * layout_bytes);
       if (!Th) return fail(PTSBE_ERR_OUT_OF_MEMORY, "workspace too small (join layout)");
       HIP_TRY(ptsbe::launch_theta_T(T, (int64_t)1 << rT, n_rt, p.d_tables, p.join_dev[j], (int)bp.xT.size(),
@@ -393,7 +401,10 @@ ptsbe_status_t run_batch(Plan& p, int j, const uint8_t* d_kraus, const float2* m
         HIP_TRY(hipEventCreate(&ev.b));
         HIP_TRY(hipEventRecord(ev.a, s));
       }
-      if (use_mfma) {
+      if (gemv) {
+        if (gemv_tiled) HIP_TRY(ptsbe::launch_ketjoin_gemv_tiled(ja, gtile, s));
+        else HIP_TRY(ptsbe::launch_ketjoin_gemv(ja, s));
+      } else if (use_mfma) {
         ptsbe::QformArgs qa{};
         qa.V = V; qa.v_stride = (int64_t)1 << rV; qa.v_base = a0;
         qa.Tc = Tc; qa.Th = Th; qa.traj_base = (int32_t)t0; qa.tslot = d_slot;

@@ -292,6 +292,26 @@ struct JoinArgs {
   float2* amp;                           // [n_elems][2^b] (amplitude out) or null
 };
 hipError_t launch_join(const JoinArgs& a, hipStream_t stream);
+// Last-batch join as an HBM-bound GEMV on the right part's own layout (no
+// canonical copy): for elements of at most 4 rows and at least 256 values of x.
+inline bool ketjoin_gemv_supported(int xb_bits, int lk_bits, int xT_bits) {
+  return xb_bits <= 2 && lk_bits <= 6 && xT_bits >= 8;
+}
+hipError_t launch_ketjoin_gemv(const JoinArgs& a, hipStream_t stream);
+// Tiling of the GEMV join over x when T's x bits are scattered (xT >= 12): a
+// workgroup takes 4096 values of x spanned by 12 tile bits, chosen as the x bits
+// of smallest offset in T (reads) together with those of smallest offset in the
+// output (writes); the remaining x bits enumerate the tiles.
+struct GemvTiling {
+  int64_t t_off[12];     // T offset of tile bit s, s in read order (ascending T offset)
+  int32_t w_of[12];      // write-order index of tile bit s
+  int64_t o_off[12];     // output offset of tile bit q, q in write order (ascending output offset)
+  int64_t o_read[12];    // output offset of tile bit s, s in read order
+  int32_t n_hi;          // x bits outside the tile
+  int64_t t_hi[32], o_hi[32];
+};
+bool make_gemv_tiling(const BatchPlan& bp, GemvTiling& g);
+hipError_t launch_ketjoin_gemv_tiled(const JoinArgs& a, const GemvTiling& g, hipStream_t stream);
 struct QformArgs {
   const float2* V; int64_t v_stride; int64_t v_base;   // V rows of elements [v_base, ...)
   const float2* Tc;                                     // canonical [traj][x][k][k'] (split join, ket join)

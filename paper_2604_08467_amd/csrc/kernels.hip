@@ -302,6 +302,150 @@ __global__ void join_kernel(JoinArgs a) {
   }
 }
 
+// Last-batch join when every element has at most four rows (2^xb <= 4) and its
+// trajectory few elements: amp[e][o(x, r)] = sum_k V[e][r][k] T[t][x][k] with T
+// read in the right part's own layout through the plan's tables, so T crosses
+// HBM once per element and needs no canonical copy (an HBM-bound GEMV: 1 flop
+// per byte of T).  A workgroup takes 256 consecutive x of one element; the
+// element's V rows and the k offsets of T are staged in LDS.
+template <int ROWS>
+__global__ void __launch_bounds__(256) ketjoin_gemv_kernel(JoinArgs a) {
+  __shared__ float2 Vs[ROWS][64];
+  __shared__ int64_t tk[64];
+  const int nk = 1 << a.lk_bits;
+  const int64_t tiles = (int64_t)1 << (a.xT_bits - 8);
+  const int lo_x = a.xT_bits < 12 ? a.xT_bits : 12;
+  const int lo_b = a.xb_bits < 12 ? a.xb_bits : 12;
+  const int lo_k = a.lk_bits < 12 ? a.lk_bits : 12;
+  const int tid = threadIdx.x;
+  if (tid < nk) tk[tid] = tab(a.tab, a.jd.tk_lo, a.jd.tk_hi, lo_k, (uint32_t)tid);
+  const int64_t nout = (int64_t)1 << a.b;
+  for (int64_t bid = blockIdx.x; bid < a.n_elems * tiles; bid += gridDim.x) {
+    const int64_t e = bid >> (a.xT_bits - 8);
+    const uint32_t x = (uint32_t)(((bid & (tiles - 1)) << 8) + tid);
+    __syncthreads();                       // the previous element's Vs is no longer read
+    if (tid < ROWS * nk) {
+      const int r = tid / nk, k = tid % nk;
+      Vs[r][k] = a.V[e * a.v_stride + tab(a.tab, a.jd.vr_lo, a.jd.vr_hi, lo_b, (uint32_t)r) +
+                     tab(a.tab, a.jd.vc_lo, a.jd.vc_hi, lo_k, (uint32_t)k)];
+    }
+    __syncthreads();
+    const int32_t ti = a.elem_traj[e] - a.traj_base;
+    const float2* T = a.T + (int64_t)(a.tslot ? a.tslot[ti] : ti) * a.t_stride +
+                      tab(a.tab, a.jd.tx_lo, a.jd.tx_hi, lo_x, x);
+    float2 acc[ROWS];
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) acc[r] = make_float2(0.f, 0.f);
+#pragma unroll 8
+    for (int k = 0; k < nk; ++k) {
+      const float2 t = T[tk[k]];
+#pragma unroll
+      for (int r = 0; r < ROWS; ++r) acc[r] = cfma(Vs[r][k], t, acc[r]);
+    }
+    const int64_t ox = tab(a.tab, a.jd.ox_lo, a.jd.ox_hi, lo_x, x);
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+      const int64_t o = e * nout + ox + tab(a.tab, a.jd.ob_lo, a.jd.ob_hi, lo_b, (uint32_t)r);
+      if (a.amp) a.amp[o] = acc[r];
+      if (a.pop) a.pop[o] = acc[r].x * acc[r].x + acc[r].y * acc[r].y;
+    }
+  }
+}
+
+// The same GEMV over tiles of 4096 values of x (GemvTiling): thread t reads the
+// 16 values i = t + 256 j of the tile (i's bits are the tile bits in order of
+// their T offsets, so a wavefront's reads are contiguous runs), accumulates all
+// k in registers, and the populations pass through LDS to be written in order
+// of their output offsets.
+template <int ROWS>
+__global__ void __launch_bounds__(256) ketjoin_gemv_tiled_kernel(JoinArgs a, GemvTiling g) {
+  __shared__ float2 Vs[ROWS][64];
+  __shared__ int64_t tk[64];
+  __shared__ float outs[ROWS][4096];
+  const int nk = 1 << a.lk_bits;
+  const int lo_b = a.xb_bits < 12 ? a.xb_bits : 12;
+  const int lo_k = a.lk_bits < 12 ? a.lk_bits : 12;
+  const int tid = threadIdx.x;
+  if (tid < nk) tk[tid] = tab(a.tab, a.jd.tk_lo, a.jd.tk_hi, lo_k, (uint32_t)tid);
+  int64_t t_lo = 0, or_lo = 0, w_lo = 0;
+  int l_lo = 0;
+#pragma unroll
+  for (int s = 0; s < 8; ++s)
+    if ((tid >> s) & 1) {
+      t_lo += g.t_off[s];
+      or_lo += g.o_read[s];
+      l_lo += 1 << g.w_of[s];
+      w_lo += g.o_off[s];
+    }
+  const int64_t nout = (int64_t)1 << a.b;
+  const int64_t tiles = (int64_t)1 << g.n_hi;
+  int64_t obr[ROWS];
+#pragma unroll
+  for (int r = 0; r < ROWS; ++r) obr[r] = tab(a.tab, a.jd.ob_lo, a.jd.ob_hi, lo_b, (uint32_t)r);
+  for (int64_t bid = blockIdx.x; bid < a.n_elems * tiles; bid += gridDim.x) {
+    const int64_t e = bid >> g.n_hi;
+    const int64_t tile = bid & (tiles - 1);
+    int64_t tbase = 0, obase = 0;
+    for (int h = 0; h < g.n_hi; ++h)
+      if ((tile >> h) & 1) { tbase += g.t_hi[h]; obase += g.o_hi[h]; }
+    __syncthreads();                       // Vs and outs of the previous tile are no longer read
+    if (tid < ROWS * nk) {
+      const int r = tid / nk, k = tid % nk;
+      Vs[r][k] = a.V[e * a.v_stride + tab(a.tab, a.jd.vr_lo, a.jd.vr_hi, lo_b, (uint32_t)r) +
+                     tab(a.tab, a.jd.vc_lo, a.jd.vc_hi, lo_k, (uint32_t)k)];
+    }
+    __syncthreads();
+    const int32_t ti = a.elem_traj[e] - a.traj_base;
+    const float2* T = a.T + (int64_t)(a.tslot ? a.tslot[ti] : ti) * a.t_stride + tbase + t_lo;
+    float2 acc[16][ROWS];
+#pragma unroll
+    for (int j = 0; j < 16; ++j)
+#pragma unroll
+      for (int r = 0; r < ROWS; ++r) acc[j][r] = make_float2(0.f, 0.f);
+    for (int k = 0; k < nk; ++k) {
+      const float2* Tk = T + tk[k];
+      float2 v[ROWS];
+#pragma unroll
+      for (int r = 0; r < ROWS; ++r) v[r] = Vs[r][k];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        int64_t hj = 0;
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+          if ((j >> s) & 1) hj += g.t_off[8 + s];
+        const float2 t = Tk[hj];
+#pragma unroll
+        for (int r = 0; r < ROWS; ++r) acc[j][r] = cfma(v[r], t, acc[j][r]);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      int li = l_lo;
+      int64_t orj = or_lo;
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+        if ((j >> s) & 1) { li += 1 << g.w_of[8 + s]; orj += g.o_read[8 + s]; }
+#pragma unroll
+      for (int r = 0; r < ROWS; ++r) {
+        outs[r][li] = acc[j][r].x * acc[j][r].x + acc[j][r].y * acc[j][r].y;
+        if (a.amp) a.amp[e * nout + obase + orj + obr[r]] = acc[j][r];
+      }
+    }
+    __syncthreads();
+    if (a.pop) {
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        int64_t oj = w_lo;
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+          if ((j >> s) & 1) oj += g.o_off[8 + s];
+#pragma unroll
+        for (int r = 0; r < ROWS; ++r) a.pop[e * nout + obase + oj + obr[r]] = outs[r][tid + 256 * j];
+      }
+    }
+  }
+}
+
 // Gather the per-trajectory part T into the canonical layout used by the MFMA
 // join: Tc[x][k][k'] with k' fastest (K = 2^lk_bits), via the plan's tables.
 __global__ void permute_T_kernel(const float2* __restrict__ T, int64_t t_stride, int64_t n_traj,
@@ -1395,6 +1539,28 @@ hipError_t launch_join(const JoinArgs& a, hipStream_t stream) {
   const int64_t total = a.n_elems * ((int64_t)1 << (a.xb_bits + a.xT_bits));
   if (total <= 0) return hipSuccess;
   hipLaunchKernelGGL(join_kernel, dim3(grid_blocks((total + 255) / 256)), dim3(256), 0, stream, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_ketjoin_gemv(const JoinArgs& a, hipStream_t stream) {
+  if (a.n_elems <= 0) return hipSuccess;
+  if (!ketjoin_gemv_supported(a.xb_bits, a.lk_bits, a.xT_bits) || a.doubled) return hipErrorInvalidValue;
+  const dim3 grid(grid_blocks(a.n_elems << (a.xT_bits - 8)));
+  switch (a.xb_bits) {
+    case 0: hipLaunchKernelGGL(ketjoin_gemv_kernel<1>, grid, dim3(256), 0, stream, a); break;
+    case 1: hipLaunchKernelGGL(ketjoin_gemv_kernel<2>, grid, dim3(256), 0, stream, a); break;
+    default: hipLaunchKernelGGL(ketjoin_gemv_kernel<4>, grid, dim3(256), 0, stream, a); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_ketjoin_gemv_tiled(const JoinArgs& a, const GemvTiling& g, hipStream_t stream) {
+  if (a.n_elems <= 0) return hipSuccess;
+  if (a.doubled || a.xb_bits > 1 || a.lk_bits > 6 || a.xT_bits < 12 || g.n_hi != a.xT_bits - 12 || g.n_hi > 32)
+    return hipErrorInvalidValue;
+  const dim3 grid(grid_blocks(a.n_elems << g.n_hi));
+  if (a.xb_bits == 0) hipLaunchKernelGGL(ketjoin_gemv_tiled_kernel<1>, grid, dim3(256), 0, stream, a, g);
+  else hipLaunchKernelGGL(ketjoin_gemv_tiled_kernel<2>, grid, dim3(256), 0, stream, a, g);
   return hipGetLastError();
 }
 

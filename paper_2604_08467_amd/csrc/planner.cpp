@@ -768,4 +768,47 @@ void build_sv_schedule(Plan& p) {
   p.sv_segs = p.sv_win[2];
 }
 
+
+bool make_gemv_tiling(const BatchPlan& bp, GemvTiling& g) {
+  const int nx = (int)bp.xT.size();
+  if (nx < 12 || nx - 12 > 32) return false;
+  auto off = [](const SplitTable& t, int i) -> int64_t {
+    return i < t.lo_bits ? t.lo[(size_t)1 << i] : t.hi[(size_t)1 << (i - t.lo_bits)];
+  };
+  std::vector<int64_t> to((size_t)nx), oo((size_t)nx);
+  for (int i = 0; i < nx; ++i) {
+    to[(size_t)i] = off(bp.t_x, i);
+    oo[(size_t)i] = off(bp.o_x, i);
+  }
+  std::vector<int> by_t((size_t)nx), by_o((size_t)nx);
+  std::iota(by_t.begin(), by_t.end(), 0);
+  std::iota(by_o.begin(), by_o.end(), 0);
+  std::sort(by_t.begin(), by_t.end(), [&](int a, int b) { return to[(size_t)a] < to[(size_t)b]; });
+  std::sort(by_o.begin(), by_o.end(), [&](int a, int b) { return oo[(size_t)a] < oo[(size_t)b]; });
+  // tile bits: the 6 x bits of smallest T offset, the 6 of smallest output offset
+  // among the rest, then further bits by T offset until there are 12
+  std::vector<char> in((size_t)nx, 0);
+  int n_in = 0;
+  for (int q = 0; q < 6; ++q) { in[(size_t)by_t[(size_t)q]] = 1; ++n_in; }
+  for (int q = 0, c = 0; q < nx && c < 6; ++q)
+    if (!in[(size_t)by_o[(size_t)q]]) { in[(size_t)by_o[(size_t)q]] = 1; ++n_in; ++c; }
+  for (int q = 0; q < nx && n_in < 12; ++q)
+    if (!in[(size_t)by_t[(size_t)q]]) { in[(size_t)by_t[(size_t)q]] = 1; ++n_in; }
+  std::vector<int> rd, wr, hi;
+  for (int i : by_t) if (in[(size_t)i]) rd.push_back(i); else hi.push_back(i);
+  for (int i : by_o) if (in[(size_t)i]) wr.push_back(i);
+  for (int s = 0; s < 12; ++s) {
+    g.t_off[s] = to[(size_t)rd[(size_t)s]];
+    g.o_read[s] = oo[(size_t)rd[(size_t)s]];
+    g.w_of[s] = (int32_t)(std::find(wr.begin(), wr.end(), rd[(size_t)s]) - wr.begin());
+    g.o_off[s] = oo[(size_t)wr[(size_t)s]];
+  }
+  g.n_hi = (int32_t)hi.size();
+  for (size_t h = 0; h < hi.size(); ++h) {
+    g.t_hi[h] = to[(size_t)hi[h]];
+    g.o_hi[h] = oo[(size_t)hi[h]];
+  }
+  return true;
+}
+
 }  // namespace ptsbe
