@@ -23,6 +23,7 @@ HBM_PEAK_GBS = 8000.0
 FP32_MFMA_PEAK_TFLOPS = 157.3
 BF16_MFMA_PEAK_TFLOPS = 2500.0
 # the join kernel version that profiles/join_traffic.txt must name to be used
+SWEEP_KERNEL_TAG = "absorb_global_kernel single HBM sweep steps"
 JOIN_KERNEL_TAG = "qform_mfma_kernel<32,8> bilinear slots"
 
 
@@ -134,8 +135,9 @@ def main():
     prof = plan.profile_read()
     plan.profile_enable(False)
     shots_per_s = M * args.steps / dt
-    print(f"right-part sweep steps in HBM: {prof['sweep_bytes'] / args.steps / 1e9:.2f} GB per step (algorithmic)",
-          file=sys.stderr)
+    sw = plan.profile_read_sweeps()
+    print(f"right-part sweeps, algorithmic bytes per step: single HBM steps {sw['step_bytes'] / args.steps / 1e9:.2f} "
+          f"GB, fused in-place runs {sw['fused_bytes'] / args.steps / 1e9:.2f} GB", file=sys.stderr)
     epb = [int(x) for x in out["elements_per_batch"]]
 
     join_s = prof["join_ms"] / 1e3
@@ -222,6 +224,22 @@ def bench_exhaustive(args):
         print(f"exhaustive: step {k} done at {time.perf_counter() - t0:.2f} s", file=sys.stderr, flush=True)
     dt = time.perf_counter() - t0
     rows = out["n_rows"]
+    # one more step with HIP events (recorded by the library on its launch stream)
+    # around every single sweep step in HBM, the dominant kernel of this workload
+    plan.profile_enable(2)
+    step()
+    torch.cuda.synchronize()
+    sw = plan.profile_read_sweeps()
+    plan.profile_enable(0)
+    achieved = sw["step_bytes"] / (sw["step_ms"] / 1e3) / 1e9 if sw["step_ms"] > 0 else 0.0
+    traffic = None
+    tf = os.path.join(ROOT, "profiles", "absorb_global_traffic_exhaustive_n50.txt")
+    if os.path.exists(tf) and bf == 20 and E == 512 and args.draws == 1:
+        # HBM bytes per launch from two rocprofv3 counter runs of this workload, used only
+        # while the file's "kernel:" line names the sweep-step kernel as it is now
+        kv = dict(ln.split(":", 1) for ln in open(tf) if ":" in ln and not ln.startswith("#"))
+        if kv.get("kernel", "").strip() == SWEEP_KERNEL_TAG and "bytes_per_launch" in kv:
+            traffic = float(kv["bytes_per_launch"])
     # the row writer's algorithmic bytes: populations read (4 B per value of x) and the
     # rows written (8 B bits + 4 B trajectory + 8 B P(x|prefix) + 8 B p(prefix))
     n_final = int(out["elements_per_batch"][-1])
@@ -237,6 +255,12 @@ def bench_exhaustive(args):
                    "elements_per_batch": [int(x) for x in out["elements_per_batch"]],
                    "population_values_scanned": n_final << bf,
                    "row_bytes_written": rows * 28},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "absorb_global_kernel (single sweep steps of the per-trajectory part in HBM: each "
+                               "job's input and output tensor once, 8 (2^rA + 2^rC) bytes)",
+                     "launches": sw["step_launches"], "avg_us": sw["step_ms"] * 1e3 / max(sw["step_launches"], 1),
+                     "bytes_per_step": sw["step_bytes"], "kernel_ms_per_step": sw["step_ms"]},
     }
     print(json.dumps(line), flush=True)
 

@@ -387,13 +387,23 @@ ptsbe_status_t ptsbe_ragged_sample_shots(ptsbe_ragged_t set, const ptsbe_ragged_
                                          int32_t flags, uint64_t* d_done_ticks, void* d_workspace,
                                          size_t workspace_bytes, void* stream);
 
-/* Timing hook for measurement: when enabled, the library records HIP events (on
+/* Timing hook for measurement.  Level 1: the library records HIP events (on
  * the launch stream) around every launch of the MFMA join of doubled networks
  * and accumulates its total time (milliseconds), launch count and algorithmic
- * flops (2^xb * 2^xT * (8 K^2 + 8 K) per element, K = 2^crossing). */
+ * flops (the real bilinear form over K^2 folded slots: 2^xb * 2^xT * 2 K^2 per
+ * element, K = 2^crossing), and the algorithmic bytes of the per-trajectory
+ * sweeps.  Level 2 adds events around every single sweep step in HBM
+ * (ptsbe_profile_read_sweeps).  Level 0 turns recording off; every call resets
+ * the counters.  Events are read when a sampling or contraction call returns. */
 ptsbe_status_t ptsbe_profile_enable(ptsbe_plan_t plan, int32_t on);
 ptsbe_status_t ptsbe_profile_read(ptsbe_plan_t plan, double* join_ms, int64_t* join_launches,
                                   double* join_flops, double* sweep_ms, double* sweep_bytes);
+/* Single sweep steps in HBM (one launch per absorbed gate of a part too large
+ * for LDS): total event time (level 2 only), launches, and algorithmic bytes
+ * (each job's input and output tensor once: 8 (2^rA + 2^rC)); fused_bytes: the
+ * in-place tile runs (each job's tensor read and written once per run). */
+ptsbe_status_t ptsbe_profile_read_sweeps(ptsbe_plan_t plan, double* step_ms, int64_t* step_launches,
+                                         double* step_bytes, double* fused_bytes);
 
 #ifdef __cplusplus
 }

@@ -301,7 +301,14 @@ class Plan:
 
     # -------------------------------------------------------------- measurement
     def profile_enable(self, on=True):
-        _lib.check(self._lib.ptsbe_profile_enable(self._h, 1 if on else 0))
+        """on: False/0 off, True/1 join timing, 2 join and single HBM sweep-step timing."""
+        _lib.check(self._lib.ptsbe_profile_enable(self._h, int(on)))
+
+    def profile_read_sweeps(self):
+        ms, b, fb = C.c_double(), C.c_double(), C.c_double()
+        n = C.c_int64()
+        _lib.check(self._lib.ptsbe_profile_read_sweeps(self._h, C.byref(ms), C.byref(n), C.byref(b), C.byref(fb)))
+        return {"step_ms": ms.value, "step_launches": n.value, "step_bytes": b.value, "fused_bytes": fb.value}
 
     def profile_read(self):
         a, c, d, e = C.c_double(), C.c_double(), C.c_double(), C.c_double()

@@ -18,7 +18,7 @@ EXPORTS = [
     "ptsbe_expect_workspace_size", "ptsbe_expect_grad",
     "ptsbe_ragged_create", "ptsbe_ragged_destroy", "ptsbe_ragged_info", "ptsbe_ragged_workspace_size",
     "ptsbe_ragged_autotune", "ptsbe_ragged_sample_shots", "ptsbe_plan_sv_schedule", "ptsbe_plan_right_sites",
-    "ptsbe_exhaustive_workspace_size", "ptsbe_sample_exhaustive",
+    "ptsbe_exhaustive_workspace_size", "ptsbe_sample_exhaustive", "ptsbe_profile_read_sweeps",
 ]
 
 
@@ -107,6 +107,8 @@ def load():
     lib.ptsbe_sample_exhaustive.argtypes = [P, P, i64, P, i32, i64, u64, C.c_double, P, P, P, P, i64,
                                             C.POINTER(i64), P, P, P, P, sz, P]
     lib.ptsbe_profile_enable.argtypes = [P, i32]
+    lib.ptsbe_profile_read_sweeps.argtypes = [P, C.POINTER(C.c_double), C.POINTER(i64), C.POINTER(C.c_double),
+                                              C.POINTER(C.c_double)]
     lib.ptsbe_profile_read.argtypes = [P, C.POINTER(C.c_double), C.POINTER(i64), C.POINTER(C.c_double),
                                        C.POINTER(C.c_double), C.POINTER(C.c_double)]
     lib.ptsbe_expect_workspace_size.argtypes = [P, C.POINTER(GradSpec_t), i64, C.POINTER(sz)]

@@ -161,13 +161,24 @@ ptsbe_status_t run_part(Plan& p, const ptsbe::PartPlan& pp, const ptsbe::AbsorbS
     const ptsbe::Segment& sg = pp.segs[si];
     if (sg.fused) {   // a run of in-place steps, one tile pass, in place
       HIP_TRY(ptsbe::launch_fused(sg, p.d_fused, g, n_jobs, job_traj, traj_base, job_prefix, p.NW, A, s));
-      if (p.profile) p.sweep_bytes += (double)n_jobs * 16.0 * std::ldexp(1.0, sg.r);
+      if (p.profile) p.fused_bytes += (double)n_jobs * 16.0 * std::ldexp(1.0, sg.r);
       continue;
     }
     const size_t i = (size_t)sg.first;
     float2* C = (si == last_nf) ? out : (A == b0 ? b1 : b0);
+    std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+    if (p.profile >= 2) {
+      HIP_TRY(hipEventCreate(&ev.first));
+      HIP_TRY(hipEventCreate(&ev.second));
+      HIP_TRY(hipEventRecord(ev.first, s));
+    }
     HIP_TRY(ptsbe::launch_absorb_global(pp.steps[i], d_steps + i, g, n_jobs, job_traj, traj_base, job_prefix,
                                         p.NW, A, C, s));
+    if (p.profile >= 2) {
+      HIP_TRY(hipEventRecord(ev.second, s));
+      p.sweep_evs.push_back(ev);
+      ++p.sweep_launches;
+    }
     A = C;
     if (p.profile) p.sweep_bytes += (double)n_jobs * 8.0 *
                                     (std::ldexp(1.0, pp.steps[i].rA) + std::ldexp(1.0, pp.steps[i].rC));
@@ -476,6 +487,14 @@ ptsbe_status_t collect_events(Plan& p, std::vector<EventPair>& evs) {
     (void)hipEventDestroy(e.b);
   }
   evs.clear();
+  for (auto& e : p.sweep_evs) {
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, e.first, e.second));
+    p.sweep_ms += ms;
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
+  p.sweep_evs.clear();
   return PTSBE_OK;
 }
 
@@ -810,6 +829,10 @@ ptsbe_status_t ptsbe_plan(const ptsbe_circuit_t* c, const ptsbe_plan_opts_t* o, 
 void ptsbe_plan_destroy(ptsbe_plan_t plan) {
   Plan* p = reinterpret_cast<Plan*>(plan);
   if (!p) return;
+  for (auto& e : p->sweep_evs) {   // events of a profiled call that returned early
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
   if (p->d_gates) (void)hipFree(p->d_gates);
   if (p->d_gate_site_list) (void)hipFree(p->d_gate_site_list);
   if (p->d_site_ops) (void)hipFree(p->d_site_ops);
@@ -1432,9 +1455,26 @@ ptsbe_status_t ptsbe_sample_exhaustive(ptsbe_plan_t plan, const uint8_t* d_kraus
 ptsbe_status_t ptsbe_profile_enable(ptsbe_plan_t plan, int32_t on) {
   Plan* p = reinterpret_cast<Plan*>(plan);
   if (!p) return fail(PTSBE_ERR_INVALID_ARG, "null plan");
-  p->profile = on != 0;
-  p->join_ms = p->sweep_ms = p->join_flops = p->sweep_bytes = 0;
-  p->join_launches = 0;
+  if (on < 0 || on > 2) return fail(PTSBE_ERR_INVALID_ARG, "profile level must be 0, 1 or 2");
+  for (auto& e : p->sweep_evs) {
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
+  p->sweep_evs.clear();
+  p->profile = on;
+  p->join_ms = p->sweep_ms = p->join_flops = p->sweep_bytes = p->fused_bytes = 0;
+  p->join_launches = p->sweep_launches = 0;
+  return PTSBE_OK;
+}
+
+ptsbe_status_t ptsbe_profile_read_sweeps(ptsbe_plan_t plan, double* step_ms, int64_t* step_launches,
+                                         double* step_bytes, double* fused_bytes) {
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  if (!p) return fail(PTSBE_ERR_INVALID_ARG, "null plan");
+  if (step_ms) *step_ms = p->sweep_ms;
+  if (step_launches) *step_launches = p->sweep_launches;
+  if (step_bytes) *step_bytes = p->sweep_bytes;
+  if (fused_bytes) *fused_bytes = p->fused_bytes;
   return PTSBE_OK;
 }
 

@@ -211,9 +211,10 @@ struct Plan {
   FusedStep* d_fused = nullptr;
 
   // measurement
-  bool profile = false;
-  double join_ms = 0, sweep_ms = 0, join_flops = 0, sweep_bytes = 0;
-  int64_t join_launches = 0;
+  int profile = 0;                                // 1: time the MFMA join; 2: also single HBM sweep steps
+  double join_ms = 0, sweep_ms = 0, join_flops = 0, sweep_bytes = 0, fused_bytes = 0;
+  int64_t join_launches = 0, sweep_launches = 0;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> sweep_evs;   // recorded, not yet read
 };
 
 // planner.cpp
