@@ -16,7 +16,7 @@ index order (the largest x with pi(x) > 0 if rounding leaves no such x).
 Sec. III-B (NBS, proportional mode): the same shots are produced while the
 marginal is contracted once per distinct (trajectory, prefix); the oracle
 memoises marginals per prefix, which changes no result.  Non-proportional mode
-with exhaustive final-batch sampling: nonproportional_trajectory.
+with exhaustive or direct final-batch sampling: nonproportional_trajectory.
 """
 import numpy as np
 
@@ -102,7 +102,7 @@ def extra_uniforms(seed: int, traj: int, j: int, t0: int, count: int) -> np.ndar
 
 
 def nonproportional_trajectory(marginal_fn, traj: int, n_qubits: int, batch_sizes, draws: int, seed: int,
-                               threshold: float):
+                               threshold: float, final_draws: int = 0):
     """Non-proportional NBS with exhaustive final-batch sampling (Sec. III-B).
 
     Non-final batches: every distinct prefix of the trajectory takes `draws`
@@ -115,6 +115,10 @@ def nonproportional_trajectory(marginal_fn, traj: int, n_qubits: int, batch_size
     P(x | prefix) = pi(x) / sum(pi) is strictly above `threshold` gives one row
     (full bitstring, P(x | prefix), p(prefix) = sum(pi) / Z), in prefix order
     then x ascending; a prefix of zero weight gives no rows.
+    final_draws > 0 selects direct final-batch sampling instead: the r-th prefix
+    takes final_draws draws (counters r * final_draws + d, tag 3), one row per
+    draw in draw order (repeats kept); a prefix of zero weight draws x = 0 with
+    P(x | prefix) = p(prefix) = 0.
     Returns (rows, number of prefixes per batch)."""
     starts = batch_starts(batch_sizes)
     f = len(batch_sizes)
@@ -132,6 +136,15 @@ def nonproportional_trajectory(marginal_fn, traj: int, n_qubits: int, batch_size
         prefixes = nxt
     counts.append(len(prefixes))
     rows = []
+    if final_draws > 0:
+        for r, prefix in enumerate(prefixes):
+            pi = np.asarray(marginal_fn(f - 1, prefix), dtype=np.float64)
+            Ze = float(np.sum(pi))
+            for u in extra_uniforms(seed, traj, f - 1, r * final_draws, final_draws):
+                x = inverse_cdf(pi, float(u))
+                pc, pp = (float(pi[x]) / Ze, Ze / Z) if Ze > 0.0 else (0.0, 0.0)
+                rows.append((prefix | (x << starts[f - 1]), pc, pp))
+        return rows, counts
     for prefix in prefixes:
         pi = np.asarray(marginal_fn(f - 1, prefix), dtype=np.float64)
         Ze = float(np.sum(pi))

@@ -502,3 +502,35 @@ def test_nonproportional_children_bound_and_zero_weight():
         assert counts[1] <= min(k, 8) and counts[2] <= counts[1] * min(k, 4)
     zero = lambda j, prefix: np.zeros(2 ** bs[j])
     assert sampling.nonproportional_trajectory(zero, 0, n, bs, 4, 13, -1.0)[0] == []
+
+
+def test_nonproportional_direct_final_batch():
+    """Direct final-batch sampling: GHZ rows repeat the prefix's forced completion with
+    P = 1; on a random circuit every row obeys the chain rule; on a product state the
+    final draws of one prefix follow the closed-form conditional within the TVD bound."""
+    n = 4
+    gates = [((0,), W.HADAMARD)] + [((q, q + 1), W.CNOT) for q in range(n - 1)]
+    mfn = _sv_marginals(sv.ideal_state(_circuit(n, gates)), n, [2, 2])
+    rows, counts = sampling.nonproportional_trajectory(mfn, 0, n, [2, 2], 64, 11, 0.0, final_draws=5)
+    assert counts == [1, 2] and len(rows) == 10
+    assert [r[0] for r in rows] == [0b0000] * 5 + [0b1111] * 5
+    assert all(abs(pc - 1) < 1e-14 and abs(pp - 0.5) < 1e-14 for _, pc, pp in rows)
+    rng = np.random.default_rng(66)
+    n, bs = 6, [2, 2, 2]
+    psi = sv.ideal_state(W.random_brickwork(n, 4, rng, 0.0))
+    p = np.abs(psi) ** 2 / np.vdot(psi, psi).real
+    rows, counts = sampling.nonproportional_trajectory(_sv_marginals(psi, n, bs), 1, n, bs, 3, 14, 0.0,
+                                                       final_draws=7)
+    assert len(rows) == 7 * counts[-1]
+    for b, pc, pp in rows:
+        assert abs(pc * pp - p[b]) < 1e-13 and pc > 0
+    th = [0.9, 1.7, 2.4]
+    psi = sv.ideal_state(_circuit(3, [((q,), W.ry(t)) for q, t in enumerate(th)]))
+    pq = [np.sin(t / 2) ** 2 for t in th]
+    want = np.array([(pq[1] if x & 1 else 1 - pq[1]) * (pq[2] if x & 2 else 1 - pq[2]) for x in range(4)])
+    N = 4000
+    rows, counts = sampling.nonproportional_trajectory(_sv_marginals(psi, 3, [1, 2]), 0, 3, [1, 2], 1, 15, 0.0,
+                                                       final_draws=N)
+    assert counts == [1, 1]
+    hist = np.bincount([r[0] >> 1 for r in rows], minlength=4) / N
+    assert 0.5 * np.abs(hist - want).sum() <= 0.5 * math.sqrt(4 / N) + math.sqrt(math.log(1e9) / (2 * N))
