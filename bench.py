@@ -23,7 +23,7 @@ HBM_PEAK_GBS = 8000.0
 FP32_MFMA_PEAK_TFLOPS = 157.3
 BF16_MFMA_PEAK_TFLOPS = 2500.0
 # the join kernel version that profiles/join_traffic.txt must name to be used
-SWEEP_KERNEL_TAG = "absorb_global_kernel single HBM sweep steps"
+SWEEP_KERNEL_TAG = "absorb_global_kernel<NK> single HBM sweep steps, 4 kept indices per thread"
 JOIN_KERNEL_TAG = "qform_mfma_kernel<32,8> bilinear slots"
 
 
@@ -133,9 +133,9 @@ def main():
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     prof = plan.profile_read()
+    sw = plan.profile_read_sweeps()
     plan.profile_enable(False)
     shots_per_s = M * args.steps / dt
-    sw = plan.profile_read_sweeps()
     print(f"right-part sweeps, algorithmic bytes per step: single HBM steps {sw['step_bytes'] / args.steps / 1e9:.2f} "
           f"GB, fused in-place runs {sw['fused_bytes'] / args.steps / 1e9:.2f} GB", file=sys.stderr)
     epb = [int(x) for x in out["elements_per_batch"]]

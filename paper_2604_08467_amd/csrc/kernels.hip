@@ -71,6 +71,41 @@ __device__ inline void absorb_one(const AbsorbStep& st, int sbase, uint32_t m, c
   }
 }
 
+// U kept indices m[u] at once (m[u] < nm for u < nu): every A load of the U
+// indices is issued before the first product, so a thread keeps U * 2^nK loads
+// in flight (the steps in HBM are bound by memory latency otherwise).  NK is an
+// upper bound of 2^nK.
+template <int NK, int U>
+__device__ inline void absorb_multi(const AbsorbStep& st, int sbase, const uint32_t* m, int nu, const float2* A,
+                                    float2* C, const float2* Gm) {
+  float2 a[U][NK];
+  const int nK = st.nK, nN = st.nN;
+  const int nk = 1 << nK;
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const uint32_t abase = insert_zero_bits(m[u], st.kpos, nK);
+#pragma unroll
+    for (int k = 0; k < NK; ++k)
+      if (u < nu && k < nk) a[u][k] = A[abase + st.koff[k]];
+  }
+  const int nn = 1 << nN;
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    if (u >= nu) break;
+    int hidx = sbase;
+    for (int i = 0; i < st.nH; ++i) hidx += (int)((m[u] >> st.hm[i]) & 1u) * st.hw[i];
+    const uint32_t cbase = insert_zero_bits(m[u], st.npos, nN);
+    for (int n = 0; n < nn; ++n) {
+      float2 acc = make_float2(0.f, 0.f);
+      const int bn = hidx + st.nB[n];
+#pragma unroll
+      for (int k = 0; k < NK; ++k)
+        if (k < nk) acc = cfma(a[u][k], Gm[bn + st.kB[k]], acc);
+      C[cbase + st.noff[n]] = acc;
+    }
+  }
+}
+
 // ------------------------------------------------------------------ LDS sweep
 __device__ inline uint32_t init_offset(const InitArgs& in, uint32_t m, const uint64_t* pw) {
   for (int i = 0; i < in.nsl; ++i) {
@@ -147,6 +182,7 @@ __global__ void __launch_bounds__(256) part_vm_kernel(const AbsorbStep* __restri
 // --------------------------------------------------------------- HBM sweep step
 constexpr uint32_t kAbsorbPerBlock = 2048;
 
+template <int NK>
 __global__ void absorb_global_kernel(const AbsorbStep* __restrict__ st_dev, GateCtx g, int64_t n_jobs,
                                      int64_t blocks_per_job, const int32_t* __restrict__ job_traj,
                                      int32_t traj_base, const uint64_t* __restrict__ job_prefix, int NW,
@@ -165,12 +201,27 @@ __global__ void absorb_global_kernel(const AbsorbStep* __restrict__ st_dev, Gate
   const uint32_t nm = 1u << (st.rC - st.nN);
   const float2* Aj = A + (job << st.rA);
   float2* Cj = C + (job << st.rC);
-  // each block covers kAbsorbPerBlock kept indices (the gate load is amortised)
+  // each block covers kAbsorbPerBlock kept indices (the gate load is amortised);
+  // a thread takes 4 of them at a time, blockDim.x apart (coalesced per u)
   const uint32_t m0 = (uint32_t)(chunk * kAbsorbPerBlock);
-  for (uint32_t i = threadIdx.x; i < kAbsorbPerBlock; i += blockDim.x) {
-    const uint32_t m = m0 + i;
-    if (m >= nm) break;
-    absorb_one(st, sb, m, Aj, Cj, Gm);
+  if (NK > 4) {
+    for (uint32_t i = threadIdx.x; i < kAbsorbPerBlock; i += blockDim.x) {
+      const uint32_t m = m0 + i;
+      if (m >= nm) break;
+      absorb_one(st, sb, m, Aj, Cj, Gm);
+    }
+  } else {
+    for (uint32_t i0 = 0; i0 < kAbsorbPerBlock; i0 += 4 * blockDim.x) {
+      uint32_t m[4];
+      int nu = 0;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        m[u] = m0 + i0 + threadIdx.x + u * blockDim.x;
+        nu += m[u] < nm && i0 + threadIdx.x + u * blockDim.x < kAbsorbPerBlock;
+      }
+      if (nu == 0) break;
+      absorb_multi<NK, 4>(st, sb, m, nu, Aj, Cj, Gm);
+    }
   }
   __syncthreads();   // Gm and pw are rewritten for the next block of this workgroup
   }
@@ -1490,8 +1541,16 @@ hipError_t launch_absorb_global(const AbsorbStep& st, const AbsorbStep* d_st, Ga
   const int64_t nm = (int64_t)1 << (st.rC - st.nN);
   const int threads = 256;
   const int64_t bpj = (nm + kAbsorbPerBlock - 1) / kAbsorbPerBlock;
-  hipLaunchKernelGGL(absorb_global_kernel, dim3(grid_blocks(bpj * n_jobs)), dim3(threads), 0, stream, d_st, g,
-                     n_jobs, bpj, job_traj, traj_base, job_prefix, NW, A, C);
+  const dim3 grid(grid_blocks(bpj * n_jobs));
+  if (st.nK <= 1)
+    hipLaunchKernelGGL(absorb_global_kernel<2>, grid, dim3(threads), 0, stream, d_st, g, n_jobs, bpj, job_traj,
+                       traj_base, job_prefix, NW, A, C);
+  else if (st.nK == 2)
+    hipLaunchKernelGGL(absorb_global_kernel<4>, grid, dim3(threads), 0, stream, d_st, g, n_jobs, bpj, job_traj,
+                       traj_base, job_prefix, NW, A, C);
+  else
+    hipLaunchKernelGGL(absorb_global_kernel<16>, grid, dim3(threads), 0, stream, d_st, g, n_jobs, bpj, job_traj,
+                       traj_base, job_prefix, NW, A, C);
   return hipGetLastError();
 }
 
