@@ -181,7 +181,7 @@ def bench_exhaustive(args):
     """Non-proportional NBS with exhaustive final-batch sampling on the 50-qubit
     brickwork: batches [10, 10, 10, b_f] (b_f = --final-batch), --draws per prefix,
     every x with P(x | prefix) > --threshold returned with its probabilities.
-    One step = one ptsbe_sample_exhaustive call; value = rows (distinct labelled
+    One step = one ptsbe_sample_nonproportional call (exhaustive final batch); value = rows (distinct labelled
     bitstrings) per second."""
     import torch
 
@@ -210,7 +210,7 @@ def bench_exhaustive(args):
           file=sys.stderr, flush=True)
 
     def step():
-        return plan.sample_exhaustive(kd, args.draws, wl.shot_seed, args.threshold, max_elems=max_elems,
+        return plan.sample_nonproportional(kd, args.draws, wl.shot_seed, args.threshold, max_elems=max_elems,
                                       capacity=cap, mult_dev=multd, workspace=ws, outputs=outs)
 
     for k in range(args.warmup):

@@ -255,18 +255,23 @@ ptsbe_status_t ptsbe_sample_shots(ptsbe_plan_t plan, const uint8_t* d_kraus_idx,
                                   double* d_traj_norm, int64_t* stats_out, void* d_workspace,
                                   size_t workspace_bytes, void* stream);
 
-/* Non-degenerate batched sampling, non-proportional mode with exhaustive
- * final-batch sampling (Sec. III-B).  Network-method plans only.
+/* Non-degenerate batched sampling, non-proportional mode (Sec. III-B), with
+ * exhaustive or direct final-batch sampling.  Network-method plans only.
  *   Non-final batches: every distinct (trajectory, prefix) element takes
  *   `draws` draws from its conditional marginal (Philox tag 3, counter
  *   (trajectory, j, r * draws + d, 0) for the element of rank r among its
  *   trajectory's elements, r counted in the order below); its distinct outcomes
  *   become the next batch's elements.  Elements are ordered by trajectory, then
  *   lexicographically by (s_1, s_2, ...), the first batch most significant.
- *   Final batch (any size up to 30 qubits; the others at most 12): for every
- *   element of total Z_e > 0, one row per x with P(x | prefix) = pi_e(x) / Z_e
- *   strictly above `threshold` (FP64 quotient of the FP32 population and the
- *   FP64 total), in element order then x ascending.
+ *   Final batch, final_draws == 0 (exhaustive; any size up to 30 qubits, the
+ *   other batches at most 12): for every element of total Z_e > 0, one row per
+ *   x with P(x | prefix) = pi_e(x) / Z_e strictly above `threshold` (FP64
+ *   quotient of the FP32 population and the FP64 total), in element order then
+ *   x ascending.
+ *   Final batch, final_draws > 0 (direct; last batch of at most 12 qubits,
+ *   threshold unused): element e takes final_draws draws (counters as above with
+ *   j = f - 1), rows [e * final_draws, (e + 1) * final_draws) in draw order,
+ *   repeats kept; an element of total 0 draws x = 0 with P = p(prefix) = 0.
  *   draws            >= 1
  *   max_elems        bound on the elements of any batch (sizes the workspace;
  *                    exceeding it returns PTSBE_ERR_OUT_OF_MEMORY)
@@ -275,19 +280,20 @@ ptsbe_status_t ptsbe_sample_shots(ptsbe_plan_t plan, const uint8_t* d_kraus_idx,
  *   d_p_cond         [capacity] double P(x | prefix) (may be NULL)
  *   d_p_prefix       [capacity] double p(prefix) = Z_e / Z_i (may be NULL)
  *   n_rows_out       host: the number of rows found; when it exceeds capacity
- *                    only the first `capacity` rows are written and the call
- *                    returns PTSBE_ERR_OUT_OF_MEMORY (call again with more room)
+ *                    the call returns PTSBE_ERR_OUT_OF_MEMORY (call again with
+ *                    more room): exhaustive mode writes the first `capacity`
+ *                    rows, direct mode none
  *   d_traj_weight, d_traj_norm, stats_out: as for ptsbe_sample_shots.
  * Synchronises `stream` once per batch and once per final-batch element chunk. */
-ptsbe_status_t ptsbe_exhaustive_workspace_size(ptsbe_plan_t plan, int64_t E, int32_t draws, int64_t max_elems,
-                                               size_t* bytes);
-ptsbe_status_t ptsbe_sample_exhaustive(ptsbe_plan_t plan, const uint8_t* d_kraus_idx, int64_t E,
-                                       const int64_t* d_mult, int32_t draws, int64_t max_elems, uint64_t seed,
-                                       double threshold, uint64_t* d_bits, int32_t* d_row_traj,
-                                       double* d_p_cond, double* d_p_prefix, int64_t capacity,
-                                       int64_t* n_rows_out, double* d_traj_weight, double* d_traj_norm,
-                                       int64_t* stats_out, void* d_workspace, size_t workspace_bytes,
-                                       void* stream);
+ptsbe_status_t ptsbe_nonproportional_workspace_size(ptsbe_plan_t plan, int64_t E, int32_t draws,
+                                                    int32_t final_draws, int64_t max_elems, size_t* bytes);
+ptsbe_status_t ptsbe_sample_nonproportional(ptsbe_plan_t plan, const uint8_t* d_kraus_idx, int64_t E,
+                                            const int64_t* d_mult, int32_t draws, int32_t final_draws,
+                                            int64_t max_elems, uint64_t seed, double threshold,
+                                            uint64_t* d_bits, int32_t* d_row_traj, double* d_p_cond,
+                                            double* d_p_prefix, int64_t capacity, int64_t* n_rows_out,
+                                            double* d_traj_weight, double* d_traj_norm, int64_t* stats_out,
+                                            void* d_workspace, size_t workspace_bytes, void* stream);
 
 /* Differentiation of trajectory-averaged observables (an addition to the
  * paper's method; its networks and UPV merge are reused).

@@ -233,24 +233,25 @@ class Plan:
         return {"shots": shots[:M], "shot_traj": None if shot_traj is None else shot_traj[:M],
                 "weights": weights, "norms": norms, "elements_per_batch": stats}
 
-    def exhaustive_workspace_size(self, E, draws, max_elems):
+    def nonproportional_workspace_size(self, E, draws, max_elems, final_draws=0):
         b = C.c_size_t()
-        _lib.check(self._lib.ptsbe_exhaustive_workspace_size(self._h, int(E), int(draws), int(max_elems),
-                                                             C.byref(b)))
+        _lib.check(self._lib.ptsbe_nonproportional_workspace_size(self._h, int(E), int(draws), int(final_draws),
+                                                                  int(max_elems), C.byref(b)))
         return b.value
 
-    def sample_exhaustive(self, kraus_dev, draws, seed, threshold, max_elems=None, capacity=None, mult_dev=None,
-                          workspace=None, stream=None, outputs=None):
-        """ptsbe_sample_exhaustive (non-proportional NBS, exhaustive final batch); returns a dict
-        of device tensors trimmed to the rows found (n_rows may exceed capacity: then the call
-        raises PtsbeError with status OUT_OF_MEMORY and `needed_rows` set on it)."""
+    def sample_nonproportional(self, kraus_dev, draws, seed, threshold=0.0, final_draws=0, max_elems=None,
+                               capacity=None, mult_dev=None, workspace=None, stream=None, outputs=None):
+        """ptsbe_sample_nonproportional (non-proportional NBS; exhaustive final batch when
+        final_draws == 0, direct draws otherwise); returns a dict of device tensors trimmed to
+        the rows found.  When the rows exceed capacity it raises PtsbeError (status
+        OUT_OF_MEMORY) with `needed_rows` set."""
         import torch
         E = kraus_dev.shape[0]
         dev = kraus_dev.device
         if max_elems is None:
             max_elems = E * int(draws) ** max(len(self.batch_sizes) - 1, 0)
         if capacity is None:
-            capacity = min(max_elems << self.batch_sizes[-1], 1 << 24)
+            capacity = max_elems * final_draws if final_draws > 0 else min(max_elems << self.batch_sizes[-1], 1 << 24)
         if outputs is None:
             outputs = {"bits": torch.empty((max(capacity, 1), self.n_words), dtype=torch.int64, device=dev),
                        "row_traj": torch.empty(max(capacity, 1), dtype=torch.int32, device=dev),
@@ -261,15 +262,16 @@ class Plan:
         stats = np.zeros(len(self.batch_sizes), dtype=np.int64)
         n_rows = C.c_int64(0)
         if workspace is None:
-            workspace = torch.empty(self.exhaustive_workspace_size(E, draws, max_elems), dtype=torch.uint8,
-                                    device=dev)
+            workspace = torch.empty(self.nonproportional_workspace_size(E, draws, max_elems, final_draws),
+                                    dtype=torch.uint8, device=dev)
         if stream is None:
             stream = torch.cuda.current_stream(dev).cuda_stream
-        st = self._lib.ptsbe_sample_exhaustive(
-            self._h, _tptr(kraus_dev), int(E), _tptr(mult_dev), int(draws), int(max_elems), int(seed),
-            float(threshold), _tptr(outputs["bits"]), _tptr(outputs.get("row_traj")), _tptr(outputs.get("p_cond")),
-            _tptr(outputs.get("p_prefix")), int(capacity), C.byref(n_rows), _tptr(weights), _tptr(norms),
-            stats.ctypes.data_as(C.c_void_p), _tptr(workspace), int(workspace.numel()), C.c_void_p(stream))
+        st = self._lib.ptsbe_sample_nonproportional(
+            self._h, _tptr(kraus_dev), int(E), _tptr(mult_dev), int(draws), int(final_draws), int(max_elems),
+            int(seed), float(threshold), _tptr(outputs["bits"]), _tptr(outputs.get("row_traj")),
+            _tptr(outputs.get("p_cond")), _tptr(outputs.get("p_prefix")), int(capacity), C.byref(n_rows),
+            _tptr(weights), _tptr(norms), stats.ctypes.data_as(C.c_void_p), _tptr(workspace),
+            int(workspace.numel()), C.c_void_p(stream))
         try:
             _lib.check(st)
         except _lib.PtsbeError as e:

@@ -18,7 +18,7 @@ EXPORTS = [
     "ptsbe_expect_workspace_size", "ptsbe_expect_grad",
     "ptsbe_ragged_create", "ptsbe_ragged_destroy", "ptsbe_ragged_info", "ptsbe_ragged_workspace_size",
     "ptsbe_ragged_autotune", "ptsbe_ragged_sample_shots", "ptsbe_plan_sv_schedule", "ptsbe_plan_right_sites",
-    "ptsbe_exhaustive_workspace_size", "ptsbe_sample_exhaustive", "ptsbe_profile_read_sweeps",
+    "ptsbe_nonproportional_workspace_size", "ptsbe_sample_nonproportional", "ptsbe_profile_read_sweeps",
 ]
 
 
@@ -103,9 +103,9 @@ def load():
     lib.ptsbe_sample_workspace_size.argtypes = [P, i64, i64, C.POINTER(sz)]
     lib.ptsbe_contract_batch.argtypes = [P, i32, P, i64, P, P, i64, i32, P, P, P, sz, P]
     lib.ptsbe_sample_shots.argtypes = [P, P, i64, P, P, i32, u64, P, P, P, P, P, P, sz, P]
-    lib.ptsbe_exhaustive_workspace_size.argtypes = [P, i64, i32, i64, C.POINTER(sz)]
-    lib.ptsbe_sample_exhaustive.argtypes = [P, P, i64, P, i32, i64, u64, C.c_double, P, P, P, P, i64,
-                                            C.POINTER(i64), P, P, P, P, sz, P]
+    lib.ptsbe_nonproportional_workspace_size.argtypes = [P, i64, i32, i32, i64, C.POINTER(sz)]
+    lib.ptsbe_sample_nonproportional.argtypes = [P, P, i64, P, i32, i32, i64, u64, C.c_double, P, P, P, P, i64,
+                                                 C.POINTER(i64), P, P, P, P, sz, P]
     lib.ptsbe_profile_enable.argtypes = [P, i32]
     lib.ptsbe_profile_read_sweeps.argtypes = [P, C.POINTER(C.c_double), C.POINTER(i64), C.POINTER(C.c_double),
                                               C.POINTER(C.c_double)]

@@ -1259,7 +1259,7 @@ ptsbe_status_t ptsbe_sample_shots(ptsbe_plan_t plan, const uint8_t* d_kraus_idx,
 }
 
 namespace {
-// Persistent arrays of ptsbe_sample_exhaustive, in the order they are taken.
+// Persistent arrays of ptsbe_sample_nonproportional, in the order they are taken.
 struct ExhLayout {
   int32_t* traj[2]; uint64_t* prefix[2]; int32_t* off[2]; int32_t* cnt[2]; int32_t* ids[2]; int32_t* parent[2];
   float2* V[2];
@@ -1301,17 +1301,17 @@ bool take_exh_layout(const Plan& p, int64_t E, int64_t cap, int32_t draws, Arena
 }
 }  // namespace
 
-ptsbe_status_t ptsbe_exhaustive_workspace_size(ptsbe_plan_t plan, int64_t E, int32_t draws, int64_t max_elems,
-                                               size_t* bytes) {
+ptsbe_status_t ptsbe_nonproportional_workspace_size(ptsbe_plan_t plan, int64_t E, int32_t draws, int32_t final_draws,
+                                                    int64_t max_elems, size_t* bytes) {
   Plan* p = reinterpret_cast<Plan*>(plan);
   if (!p || !bytes) return fail(PTSBE_ERR_INVALID_ARG, "null argument");
-  if (E < 1 || draws < 1) return fail(PTSBE_ERR_INVALID_ARG, "E < 1 or draws < 1");
+  if (E < 1 || draws < 1 || final_draws < 0) return fail(PTSBE_ERR_INVALID_ARG, "E < 1, draws < 1 or final_draws < 0");
   const int64_t cap = std::max<int64_t>(E, max_elems);
   Arena probe;                       // an arena without memory measures the layout
   probe.base = nullptr;
   probe.cap = ~(size_t)0 >> 1;
   ExhLayout L;
-  take_exh_layout(*p, E, cap, draws, probe, L);
+  take_exh_layout(*p, E, cap, std::max(draws, final_draws), probe, L);
   size_t chunk = 0;
   for (auto& bp : p->batches) {
     const size_t per_traj = join_traj_bytes(bp);
@@ -1327,12 +1327,13 @@ ptsbe_status_t ptsbe_exhaustive_workspace_size(ptsbe_plan_t plan, int64_t E, int
   return PTSBE_OK;
 }
 
-ptsbe_status_t ptsbe_sample_exhaustive(ptsbe_plan_t plan, const uint8_t* d_kraus_idx, int64_t E,
-                                       const int64_t* d_mult, int32_t draws, int64_t max_elems, uint64_t seed,
-                                       double threshold, uint64_t* d_bits, int32_t* d_row_traj, double* d_p_cond,
-                                       double* d_p_prefix, int64_t capacity, int64_t* n_rows_out,
-                                       double* d_traj_weight, double* d_traj_norm, int64_t* stats_out,
-                                       void* d_workspace, size_t workspace_bytes, void* stream) {
+ptsbe_status_t ptsbe_sample_nonproportional(ptsbe_plan_t plan, const uint8_t* d_kraus_idx, int64_t E,
+                                            const int64_t* d_mult, int32_t draws, int32_t final_draws,
+                                            int64_t max_elems, uint64_t seed, double threshold, uint64_t* d_bits,
+                                            int32_t* d_row_traj, double* d_p_cond, double* d_p_prefix,
+                                            int64_t capacity, int64_t* n_rows_out, double* d_traj_weight,
+                                            double* d_traj_norm, int64_t* stats_out, void* d_workspace,
+                                            size_t workspace_bytes, void* stream) {
   Plan* p = reinterpret_cast<Plan*>(plan);
   if (!p) return fail(PTSBE_ERR_INVALID_ARG, "null plan");
   if (p->device < 0) return fail(PTSBE_ERR_INVALID_ARG, "plan was built without a device");
@@ -1341,12 +1342,17 @@ ptsbe_status_t ptsbe_sample_exhaustive(ptsbe_plan_t plan, const uint8_t* d_kraus
   const int f = (int)p->batches.size();
   for (int j = 0; j + 1 < f; ++j)
     if (p->batches[j].size > 12) return fail(PTSBE_ERR_UNSUPPORTED, "non-final batches of at most 12 qubits");
-  if (E < 1 || draws < 1 || capacity < 0) return fail(PTSBE_ERR_INVALID_ARG, "E < 1, draws < 1 or capacity < 0");
+  if (E < 1 || draws < 1 || final_draws < 0 || capacity < 0)
+    return fail(PTSBE_ERR_INVALID_ARG, "E < 1, draws < 1, final_draws < 0 or capacity < 0");
   if (std::isnan(threshold)) return fail(PTSBE_ERR_INVALID_ARG, "threshold is NaN");
+  if (final_draws > 0 && p->batches.back().size > 12)
+    return fail(PTSBE_ERR_UNSUPPORTED, "direct final-batch sampling takes a last batch of at most 12 qubits");
+  const int32_t rows_per_elem = std::max(draws, final_draws);
   if (!d_kraus_idx || !d_workspace || !n_rows_out || (capacity > 0 && !d_bits))
     return fail(PTSBE_ERR_INVALID_ARG, "null pointer");
   const int64_t cap = std::max<int64_t>(E, max_elems);
-  if (cap * (int64_t)draws >= ((int64_t)1 << 31)) return fail(PTSBE_ERR_UNSUPPORTED, "max_elems * draws >= 2^31");
+  if (cap * (int64_t)rows_per_elem >= ((int64_t)1 << 31))
+    return fail(PTSBE_ERR_UNSUPPORTED, "max_elems * max(draws, final_draws) >= 2^31");
   *n_rows_out = 0;
   HIP_TRY(hipSetDevice(p->device));
   hipStream_t s = (hipStream_t)stream;
@@ -1359,7 +1365,7 @@ ptsbe_status_t ptsbe_sample_exhaustive(ptsbe_plan_t plan, const uint8_t* d_kraus
   ar.base = (char*)d_workspace;
   ar.cap = workspace_bytes;
   ExhLayout L;
-  if (!take_exh_layout(*p, E, cap, draws, ar, L))
+  if (!take_exh_layout(*p, E, cap, rows_per_elem, ar, L))
     return fail(PTSBE_ERR_OUT_OF_MEMORY, "workspace too small for the element arrays");
   HIP_TRY(hipMemsetAsync(L.counters, 0, 64, s));
   HIP_TRY(ptsbe::launch_np_init(E, L.traj[0], L.prefix[0], p->NW, s));
@@ -1370,7 +1376,8 @@ ptsbe_status_t ptsbe_sample_exhaustive(ptsbe_plan_t plan, const uint8_t* d_kraus
   exh.tmpl.threshold = threshold;
   exh.tmpl.capacity = capacity;
   exh.tmpl.bits = d_bits; exh.tmpl.row_traj = d_row_traj; exh.tmpl.p_cond = d_p_cond; exh.tmpl.p_prefix = d_p_prefix;
-  exh.tmpl.totals_out = f > 1 ? nullptr : L.norms;    // one batch: its totals are the norms
+  exh.tmpl.totals_out = f > 1 ? nullptr : L.norms;    // one batch: its totals are the norms (copied in
+                                                      // stream order before the weights read them)
   int cur = 0;
   int64_t U = E;
   std::vector<EventPair> evs;
@@ -1404,12 +1411,34 @@ ptsbe_status_t ptsbe_sample_exhaustive(ptsbe_plan_t plan, const uint8_t* d_kraus
       sa.elem_total = L.totals;
       sa.child_cnt = L.child_cnt;
       sa.bad_flag = L.counters + 1;
+    } else if (final_draws > 0) {   // direct sampling: final_draws rows per element
+      const int64_t rows = U * (int64_t)final_draws;
+      *n_rows_out = rows;
+      if (rows > capacity)
+        return fail(PTSBE_ERR_OUT_OF_MEMORY, std::to_string(rows) + " rows, capacity " + std::to_string(capacity));
+      HIP_TRY(ptsbe::launch_np_rows(U, final_draws, L.traj[cur], L.off[cur], L.cnt[cur], L.ids[cur], L.base, s));
+      HIP_TRY(ptsbe::launch_np_direct_rows(U, final_draws, L.traj[cur], L.prefix[cur], p->NW, d_bits, d_row_traj, s));
+      io.sample = true;
+      ptsbe::SampleArgs& sa = io.sa;
+      sa.b = bp.size; sa.start = bp.start; sa.NW = p->NW;
+      sa.elem_shot_off = L.off[cur]; sa.elem_shot_cnt = L.cnt[cur];
+      sa.shot_ids = L.ids[cur];
+      sa.traj_shot_base = L.base;
+      sa.seed = seed; sa.j = j; sa.tag = 3u;
+      sa.shots = d_bits; sa.shot_x = L.shot_x; sa.p_cond = d_p_cond;
+      sa.elem_total = L.totals;
+      sa.child_cnt = nullptr;
+      sa.bad_flag = L.counters + 1;
     } else {
       io.exh = &exh;
     }
     ptsbe_status_t st = run_batch(*p, j, d_kraus_idx, L.merged, E, io, ar, s, evs);
     if (st != PTSBE_OK) return st;
-    if (j == 0 && !last) HIP_TRY(hipMemcpyAsync(L.norms, L.totals, (size_t)E * 8, hipMemcpyDeviceToDevice, s));
+    if (j == 0 && (!last || final_draws > 0))
+      HIP_TRY(hipMemcpyAsync(L.norms, L.totals, (size_t)E * 8, hipMemcpyDeviceToDevice, s));
+    if (last && final_draws > 0)
+      HIP_TRY(ptsbe::launch_np_direct_prefix_p(U, final_draws, L.traj[cur], L.totals, f > 1 ? L.norms : nullptr,
+                                               d_p_prefix, s));
     if (j == 0 && (d_traj_weight || d_traj_norm)) {
       ptsbe::WeightArgs wa{L.norms, d_mult, E, d_traj_weight, d_traj_norm};
       HIP_TRY(ptsbe::launch_weights(wa, s));
@@ -1434,10 +1463,6 @@ ptsbe_status_t ptsbe_sample_exhaustive(ptsbe_plan_t plan, const uint8_t* d_kraus
       U = nU;
     }
   }
-  if (f == 1 && (d_traj_weight || d_traj_norm)) {   // the norms came from the final batch's totals
-    ptsbe::WeightArgs wa{L.norms, d_mult, E, d_traj_weight, d_traj_norm};
-    HIP_TRY(ptsbe::launch_weights(wa, s));
-  }
   int32_t bad = 0;
   HIP_TRY(hipMemcpyAsync(&bad, L.counters + 1, 4, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
@@ -1445,7 +1470,7 @@ ptsbe_status_t ptsbe_sample_exhaustive(ptsbe_plan_t plan, const uint8_t* d_kraus
     ptsbe_status_t st = collect_events(*p, evs);
     if (st != PTSBE_OK) return st;
   }
-  *n_rows_out = exh.rows;
+  if (final_draws == 0) *n_rows_out = exh.rows;
   if (bad) return fail(PTSBE_ERR_NUMERIC, "an element had a non-finite marginal total");
   if (exh.rows > capacity)
     return fail(PTSBE_ERR_OUT_OF_MEMORY, std::to_string(exh.rows) + " rows found, capacity " + std::to_string(capacity));

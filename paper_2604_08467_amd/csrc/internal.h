@@ -361,6 +361,7 @@ struct SampleArgs {
   int32_t* child_cnt;                    // [n_elems] or null
   int32_t* bad_flag;                     // set to 1 on a zero / non-finite total
   uint32_t tag = 2u;                     // Philox stream: 2 shot draws, 3 non-proportional draws
+  double* p_cond = nullptr;              // [rows] P(x | prefix) of each draw (direct final batch), or null
 };
 hipError_t launch_sample(const SampleArgs& a, hipStream_t stream);
 
@@ -369,6 +370,13 @@ hipError_t launch_sample(const SampleArgs& a, hipStream_t stream);
 // the first row of trajectory t's elements, so a draw's Philox counter is the
 // element's rank within its trajectory times `draws` plus the draw index.
 hipError_t launch_np_init(int64_t E, int32_t* elem_traj, uint64_t* elem_prefix, int NW, hipStream_t stream);
+// Direct final-batch sampling: rows [e * draws, (e + 1) * draws) start as element
+// e's prefix bits (the draw ORs its batch bits in) with its trajectory; after the
+// draws, p(prefix) = Z_e / Z_t (1 without traj_norm; 0 for Z_e = 0).
+hipError_t launch_np_direct_rows(int64_t n_elems, int draws, const int32_t* elem_traj, const uint64_t* elem_prefix,
+                                 int NW, uint64_t* bits, int32_t* row_traj, hipStream_t stream);
+hipError_t launch_np_direct_prefix_p(int64_t n_elems, int draws, const int32_t* elem_traj, const double* elem_total,
+                                     const double* traj_norm, double* p_prefix, hipStream_t stream);
 hipError_t launch_np_rows(int64_t n_elems, int draws, const int32_t* elem_traj, int32_t* shot_off,
                           int32_t* shot_cnt, int32_t* shot_ids, int64_t* traj_base, hipStream_t stream);
 

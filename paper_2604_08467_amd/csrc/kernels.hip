@@ -1192,6 +1192,7 @@ __global__ void __launch_bounds__(64) sample_kernel(SampleArgs a) {
       }
       if (x < 0) x = 0;
       a.shot_x[row] = x;
+      if (a.p_cond) a.p_cond[row] = Z > 0.0 ? (double)pi[x] / Z : 0.0;
       if (a.shots) {   // write the batch bits at qubits [start, start + b)
         uint64_t* w = a.shots + (int64_t)row * a.NW;
         const int q0 = a.start;
@@ -1295,6 +1296,26 @@ __global__ void np_init_kernel(int64_t E, int32_t* elem_traj, uint64_t* elem_pre
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < E; e += (int64_t)gridDim.x * blockDim.x) {
     elem_traj[e] = (int32_t)e;
     for (int w = 0; w < NW; ++w) elem_prefix[e * NW + w] = 0ull;
+  }
+}
+
+__global__ void np_direct_rows_kernel(int64_t n_elems, int draws, const int32_t* elem_traj,
+                                      const uint64_t* elem_prefix, int NW, uint64_t* bits, int32_t* row_traj) {
+  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n_elems * draws;
+       r += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t e = r / draws;
+    for (int w = 0; w < NW; ++w) bits[r * NW + w] = elem_prefix[e * NW + w];
+    if (row_traj) row_traj[r] = elem_traj[e];
+  }
+}
+
+__global__ void np_direct_prefix_p_kernel(int64_t n_elems, int draws, const int32_t* elem_traj,
+                                          const double* elem_total, const double* traj_norm, double* p_prefix) {
+  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n_elems * draws;
+       r += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t e = r / draws;
+    const double Z = elem_total[e];
+    p_prefix[r] = Z > 0.0 ? (traj_norm ? Z / traj_norm[elem_traj[e]] : 1.0) : 0.0;
   }
 }
 
@@ -1745,6 +1766,22 @@ hipError_t launch_np_init(int64_t E, int32_t* elem_traj, uint64_t* elem_prefix, 
   if (E <= 0) return hipSuccess;
   hipLaunchKernelGGL(np_init_kernel, dim3(grid_blocks((E + 255) / 256)), dim3(256), 0, stream, E, elem_traj,
                      elem_prefix, NW);
+  return hipGetLastError();
+}
+
+hipError_t launch_np_direct_rows(int64_t n_elems, int draws, const int32_t* elem_traj, const uint64_t* elem_prefix,
+                                 int NW, uint64_t* bits, int32_t* row_traj, hipStream_t stream) {
+  if (n_elems <= 0) return hipSuccess;
+  hipLaunchKernelGGL(np_direct_rows_kernel, dim3(grid_blocks((n_elems * draws + 255) / 256)), dim3(256), 0, stream,
+                     n_elems, draws, elem_traj, elem_prefix, NW, bits, row_traj);
+  return hipGetLastError();
+}
+
+hipError_t launch_np_direct_prefix_p(int64_t n_elems, int draws, const int32_t* elem_traj, const double* elem_total,
+                                     const double* traj_norm, double* p_prefix, hipStream_t stream) {
+  if (n_elems <= 0 || !p_prefix) return hipSuccess;
+  hipLaunchKernelGGL(np_direct_prefix_p_kernel, dim3(grid_blocks((n_elems * draws + 255) / 256)), dim3(256), 0,
+                     stream, n_elems, draws, elem_traj, elem_total, traj_norm, p_prefix);
   return hipGetLastError();
 }
 

@@ -1,5 +1,5 @@
-"""Non-proportional NBS with exhaustive final-batch sampling (Sec. III-B) through
-the C ABI, against the FP64 oracle.
+"""Non-proportional NBS (Sec. III-B) through the C ABI, against the FP64 oracle:
+exhaustive final-batch sampling, and direct final-batch draws.
 
 Draws at the non-final batches use the same Philox counters on both sides, so
 the sets of prefixes must be identical (a CDF-boundary flip would change one;
@@ -74,7 +74,7 @@ def test_exhaustive_matches_oracle(bs, draws, thr):
     circ = W.random_brickwork(sum(bs), 5, rng, 0.02)
     plan = P.Plan(circ, bs, method="network")
     kr, mult, _, _ = plan.sample_trajectories(302, 12)
-    out = plan.sample_exhaustive(to_dev(torch, dev, kr), draws, 303, thr, mult_dev=to_dev(torch, dev, mult))
+    out = plan.sample_nonproportional(to_dev(torch, dev, kr), draws, 303, thr, mult_dev=to_dev(torch, dev, mult))
     torch.cuda.synchronize()
     ref_rows, ref_counts, psis = _oracle_rows(circ, bs, kr, draws, 303, thr)
     _compare(out, ref_rows, ref_counts, bs, thr, f"batches {bs}, draws {draws}, threshold {thr}")
@@ -92,7 +92,7 @@ def test_exhaustive_single_batch():
     plan = P.Plan(wl.circuit, wl.batch_sizes, method="network")
     kr, mult, _, _ = plan.sample_trajectories(wl.pts_seed, 16)
     thr = 2e-3
-    out = plan.sample_exhaustive(to_dev(torch, dev, kr), 1, 5, thr, mult_dev=to_dev(torch, dev, mult))
+    out = plan.sample_nonproportional(to_dev(torch, dev, kr), 1, 5, thr, mult_dev=to_dev(torch, dev, mult))
     ref_rows, ref_counts, psis = _oracle_rows(wl.circuit, wl.batch_sizes, kr, 1, 5, thr)
     _compare(out, ref_rows, ref_counts, wl.batch_sizes, thr, "single batch")
     assert np.all(out["p_prefix"].cpu().numpy() == 1.0)
@@ -111,7 +111,7 @@ def test_exhaustive_large_final_batch():
     plan = P.Plan(circ, bs, method="network")
     kr, mult, _, _ = plan.sample_trajectories(312, 3)
     thr = 1e-5
-    out = plan.sample_exhaustive(to_dev(torch, dev, kr), 2, 313, thr)
+    out = plan.sample_nonproportional(to_dev(torch, dev, kr), 2, 313, thr)
     ref_rows, ref_counts, _ = _oracle_rows(circ, bs, kr, 2, 313, thr)
     _compare(out, ref_rows, ref_counts, bs, thr, "final batch of 16 qubits")
     # every prefix's rows at threshold 0 would sum to 1; above it they sum to at most 1
@@ -128,19 +128,61 @@ def test_exhaustive_capacity_overflow_keeps_the_first_rows():
     plan = P.Plan(circ, bs, method="network")
     kr, _, _, _ = plan.sample_trajectories(322, 6)
     kd = to_dev(torch, dev, kr)
-    full = plan.sample_exhaustive(kd, 3, 323, 1e-4)
+    full = plan.sample_nonproportional(kd, 3, 323, 1e-4)
     n = full["n_rows"]
     assert n > 10
     with pytest.raises(P.PtsbeError) as ei:
-        plan.sample_exhaustive(kd, 3, 323, 1e-4, capacity=n // 2)
+        plan.sample_nonproportional(kd, 3, 323, 1e-4, capacity=n // 2)
     assert ei.value.needed_rows == n
     part = {k: torch.empty((n // 2,) + tuple(v.shape[1:]), dtype=v.dtype, device=dev)
             for k, v in full.items() if k in ("bits", "row_traj", "p_cond", "p_prefix")}
     with pytest.raises(P.PtsbeError):
-        plan.sample_exhaustive(kd, 3, 323, 1e-4, capacity=n // 2, outputs=part)
+        plan.sample_nonproportional(kd, 3, 323, 1e-4, capacity=n // 2, outputs=part)
     torch.cuda.synchronize()
     assert torch.equal(part["bits"], full["bits"][:n // 2])
     assert torch.equal(part["row_traj"], full["row_traj"][:n // 2])
     # more elements than max_elems is an error, not an overrun
     with pytest.raises(P.PtsbeError):
-        plan.sample_exhaustive(kd, 3, 323, 1e-4, max_elems=len(kr))
+        plan.sample_nonproportional(kd, 3, 323, 1e-4, max_elems=len(kr))
+
+
+@pytest.mark.parametrize("bs,draws,fd", [([4, 4, 4], 2, 50), ([6, 6], 3, 200), ([10], 1, 500)],
+                         ids=["4-4-4_k2_f50", "6-6_k3_f200", "10_f500"])
+def test_direct_final_batch_matches_oracle(bs, draws, fd):
+    """Direct final-batch draws: identical element counts, rows in the same order with
+    identical bitstrings except CDF-boundary flips of the final draws (at most 0.1 % of the
+    rows), P(x | prefix) and p(prefix) of identical rows within 1e-6."""
+    import paper_2604_08467_amd as P
+    torch, dev = torch_dev()
+    rng = np.random.default_rng(331)
+    circ = W.random_brickwork(sum(bs), 5, rng, 0.02)
+    plan = P.Plan(circ, bs, method="network")
+    kr, mult, _, _ = plan.sample_trajectories(332, 10)
+    out = plan.sample_nonproportional(to_dev(torch, dev, kr), draws, 333, final_draws=fd,
+                                      mult_dev=to_dev(torch, dev, mult))
+    n, starts = circ.n_qubits, sampling.batch_starts(bs)
+    ref_rows, ref_counts = [], np.zeros(len(bs), dtype=np.int64)
+    psis = oracle_states(circ, kr)
+    for i, psi in enumerate(psis):
+        def mfn(j, prefix, psi=psi):
+            return sampling.marginal_from_state(psi, n, starts[j], bs[j], prefix)
+        r, c = sampling.nonproportional_trajectory(mfn, i, n, bs, draws, 333, 0.0, final_draws=fd)
+        ref_rows.extend((i,) + tuple(x) for x in r)
+        ref_counts += np.array(c)
+    assert list(out["elements_per_batch"]) == list(ref_counts)
+    assert out["n_rows"] == len(ref_rows) == int(ref_counts[-1]) * fd
+    bits = shots_to_ints(out["bits"].cpu().numpy())
+    traj = out["row_traj"].cpu().numpy()
+    pc = out["p_cond"].cpu().numpy()
+    pp = out["p_prefix"].cpu().numpy()
+    same = [k for k in range(len(ref_rows)) if bits[k] == ref_rows[k][1]]
+    assert np.array_equal(traj, np.array([r[0] for r in ref_rows]))
+    err_pc = max(abs(pc[k] - ref_rows[k][2]) for k in same)
+    err_pp = max(abs(pp[k] - ref_rows[k][3]) for k in same)
+    _say(f"direct {bs} draws {draws} final {fd}: {len(ref_rows) - len(same)} of {len(ref_rows)} rows differ; "
+         f"max |dP(x|prefix)| {err_pc:.2e}, max |dp(prefix)| {err_pp:.2e}")
+    assert len(ref_rows) - len(same) <= 0.001 * len(ref_rows) + 1
+    assert err_pc <= 1e-6 and err_pp <= 1e-6
+    Z = np.array([np.vdot(p, p).real for p in psis])
+    np.testing.assert_allclose(out["norms"].cpu().numpy(), Z, rtol=1e-5)
+    np.testing.assert_allclose(out["weights"].cpu().numpy(), sampling.trajectory_weights(Z, mult), rtol=1e-5)

@@ -242,18 +242,20 @@ def test_right_sites_of_the_brickwork_batches():
         plan.right_sites(len(wl.batch_sizes))
 
 
-def test_exhaustive_workspace_size_grows_with_elements_and_draws():
+def test_nonproportional_workspace_size_grows_with_elements_and_draws():
     """The exhaustive sampler's workspace covers its element arrays (two generations,
     draws rows per element) and a final-batch chunk; it grows with max_elems and draws."""
     P = _lib()
     rng = np.random.default_rng(5)
     c = W.random_brickwork(20, 4, rng, 0.01)
     plan = P.Plan(c, [4, 16], device=-1, method="network")
-    a = plan.exhaustive_workspace_size(8, 2, 16)
-    b = plan.exhaustive_workspace_size(8, 2, 4096)
-    d = plan.exhaustive_workspace_size(8, 64, 4096)
+    a = plan.nonproportional_workspace_size(8, 2, 16)
+    b = plan.nonproportional_workspace_size(8, 2, 4096)
+    d = plan.nonproportional_workspace_size(8, 64, 4096)
     assert 0 < a < b < d
     # a final batch of 16 qubits: at least one element's population (2^16 floats) fits
     assert a > 4 << 16
     with pytest.raises(P.PtsbeError):
-        plan.exhaustive_workspace_size(8, 0, 16)
+        plan.nonproportional_workspace_size(8, 0, 16)
+    # direct final-batch draws: rows per element grow with final_draws beyond draws
+    assert plan.nonproportional_workspace_size(8, 2, 4096, final_draws=1000) > b
