@@ -256,7 +256,9 @@ ptsbe_status_t ptsbe_sample_shots(ptsbe_plan_t plan, const uint8_t* d_kraus_idx,
                                   size_t workspace_bytes, void* stream);
 
 /* Non-degenerate batched sampling, non-proportional mode (Sec. III-B), with
- * exhaustive or direct final-batch sampling.  Network-method plans only.
+ * exhaustive or direct final-batch sampling.  Statevector-method plans take
+ * batches of at most 12 qubits (the last one included) and run trajectories in
+ * chunks whose states fit the workspace; rows do not depend on the chunking.
  *   Non-final batches: every distinct (trajectory, prefix) element takes
  *   `draws` draws from its conditional marginal (Philox tag 3, counter
  *   (trajectory, j, r * draws + d, 0) for the element of rank r among its
@@ -282,7 +284,7 @@ ptsbe_status_t ptsbe_sample_shots(ptsbe_plan_t plan, const uint8_t* d_kraus_idx,
  *   n_rows_out       host: the number of rows found; when it exceeds capacity
  *                    the call returns PTSBE_ERR_OUT_OF_MEMORY (call again with
  *                    more room): exhaustive mode writes the first `capacity`
- *                    rows, direct mode none
+ *                    rows, direct mode at most a leading part of them
  *   d_traj_weight, d_traj_norm, stats_out: as for ptsbe_sample_shots.
  * Synchronises `stream` once per batch and once per final-batch element chunk. */
 ptsbe_status_t ptsbe_nonproportional_workspace_size(ptsbe_plan_t plan, int64_t E, int32_t draws,

@@ -1307,6 +1307,10 @@ ptsbe_status_t ptsbe_nonproportional_workspace_size(ptsbe_plan_t plan, int64_t E
   if (!p || !bytes) return fail(PTSBE_ERR_INVALID_ARG, "null argument");
   if (E < 1 || draws < 1 || final_draws < 0) return fail(PTSBE_ERR_INVALID_ARG, "E < 1, draws < 1 or final_draws < 0");
   const int64_t cap = std::max<int64_t>(E, max_elems);
+  if (p->method == PTSBE_METHOD_STATEVECTOR) {
+    *bytes = ptsbe::sv_np_workspace(*p, E, cap, std::max(draws, final_draws));
+    return PTSBE_OK;
+  }
   Arena probe;                       // an arena without memory measures the layout
   probe.base = nullptr;
   probe.cap = ~(size_t)0 >> 1;
@@ -1337,8 +1341,6 @@ ptsbe_status_t ptsbe_sample_nonproportional(ptsbe_plan_t plan, const uint8_t* d_
   Plan* p = reinterpret_cast<Plan*>(plan);
   if (!p) return fail(PTSBE_ERR_INVALID_ARG, "null plan");
   if (p->device < 0) return fail(PTSBE_ERR_INVALID_ARG, "plan was built without a device");
-  if (p->method == PTSBE_METHOD_STATEVECTOR)
-    return fail(PTSBE_ERR_UNSUPPORTED, "exhaustive sampling runs on network-method plans");
   const int f = (int)p->batches.size();
   for (int j = 0; j + 1 < f; ++j)
     if (p->batches[j].size > 12) return fail(PTSBE_ERR_UNSUPPORTED, "non-final batches of at most 12 qubits");
@@ -1356,6 +1358,13 @@ ptsbe_status_t ptsbe_sample_nonproportional(ptsbe_plan_t plan, const uint8_t* d_
   *n_rows_out = 0;
   HIP_TRY(hipSetDevice(p->device));
   hipStream_t s = (hipStream_t)stream;
+  if (p->method == PTSBE_METHOD_STATEVECTOR) {
+    if (p->batches.back().size > 12)
+      return fail(PTSBE_ERR_UNSUPPORTED, "the statevector method samples batches of at most 12 qubits");
+    return ptsbe::sv_sample_nonproportional(*p, d_kraus_idx, E, d_mult, draws, final_draws, cap, seed, threshold,
+                                            d_bits, d_row_traj, d_p_cond, d_p_prefix, capacity, n_rows_out,
+                                            d_traj_weight, d_traj_norm, stats_out, d_workspace, workspace_bytes, s);
+  }
   std::vector<uint8_t> h_kraus((size_t)E * p->site_gate.size());
   if (!h_kraus.empty()) {
     HIP_TRY(hipMemcpyAsync(h_kraus.data(), d_kraus_idx, h_kraus.size(), hipMemcpyDeviceToHost, s));
@@ -1368,7 +1377,7 @@ ptsbe_status_t ptsbe_sample_nonproportional(ptsbe_plan_t plan, const uint8_t* d_
   if (!take_exh_layout(*p, E, cap, rows_per_elem, ar, L))
     return fail(PTSBE_ERR_OUT_OF_MEMORY, "workspace too small for the element arrays");
   HIP_TRY(hipMemsetAsync(L.counters, 0, 64, s));
-  HIP_TRY(ptsbe::launch_np_init(E, L.traj[0], L.prefix[0], p->NW, s));
+  HIP_TRY(ptsbe::launch_np_init(E, 0, L.traj[0], L.prefix[0], p->NW, s));
   HIP_TRY(ptsbe::launch_upv_merge(gate_ctx(*p, d_kraus_idx, nullptr), E, L.merged, s));
   BatchIO::Exhaustive exh;
   exh.tmpl.NW = p->NW;

@@ -369,7 +369,9 @@ hipError_t launch_sample(const SampleArgs& a, hipStream_t stream);
 // `draws` fresh draws on the rows [e * draws, (e + 1) * draws); traj_base[t] is
 // the first row of trajectory t's elements, so a draw's Philox counter is the
 // element's rank within its trajectory times `draws` plus the draw index.
-hipError_t launch_np_init(int64_t E, int32_t* elem_traj, uint64_t* elem_prefix, int NW, hipStream_t stream);
+// Elements of a trajectory range [t0, t0 + count): one per trajectory, empty prefix.
+hipError_t launch_np_init(int64_t count, int64_t t0, int32_t* elem_traj, uint64_t* elem_prefix, int NW,
+                          hipStream_t stream);
 // Direct final-batch sampling: rows [e * draws, (e + 1) * draws) start as element
 // e's prefix bits (the draw ORs its batch bits in) with its trajectory; after the
 // draws, p(prefix) = Z_e / Z_t (1 without traj_norm; 0 for Z_e = 0).
@@ -483,6 +485,13 @@ hipError_t launch_sv_amplitudes(const SvMargArgs& a, float2* amp, hipStream_t st
 ptsbe_status_t sv_evolve(const Plan& p, const GateCtx& g, int64_t t0, int64_t nj, float2* psi, float2* Ucl,
                          hipStream_t s);
 size_t sv_sample_workspace(const Plan& p, int64_t E, int64_t M);
+size_t sv_np_workspace(const Plan& p, int64_t E, int64_t cap, int32_t rows_per_elem);
+ptsbe_status_t sv_sample_nonproportional(Plan& p, const uint8_t* d_kraus, int64_t E, const int64_t* d_mult,
+                                         int32_t draws, int32_t final_draws, int64_t cap, uint64_t seed,
+                                         double threshold, uint64_t* d_bits, int32_t* d_row_traj, double* d_p_cond,
+                                         double* d_p_prefix, int64_t capacity, int64_t* n_rows_out, double* d_w,
+                                         double* d_norm, int64_t* stats, void* d_workspace, size_t workspace_bytes,
+                                         hipStream_t s);
 size_t sv_contract_workspace(const Plan& p, int j, int64_t E, int64_t n_elems);
 ptsbe_status_t sv_sample_shots(Plan& p, const uint8_t* d_kraus, int64_t E, const int64_t* d_mult,
                                const int64_t* d_m, uint64_t seed, uint64_t* d_shots, int32_t* d_shot_traj,

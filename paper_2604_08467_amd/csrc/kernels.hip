@@ -1292,9 +1292,9 @@ __global__ void __launch_bounds__(64) children_kernel(ChildArgs a) {
 }
 
 // ------------------------------------------- non-proportional NBS (Sec. III-B)
-__global__ void np_init_kernel(int64_t E, int32_t* elem_traj, uint64_t* elem_prefix, int NW) {
+__global__ void np_init_kernel(int64_t E, int64_t t0, int32_t* elem_traj, uint64_t* elem_prefix, int NW) {
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < E; e += (int64_t)gridDim.x * blockDim.x) {
-    elem_traj[e] = (int32_t)e;
+    elem_traj[e] = (int32_t)(t0 + e);
     for (int w = 0; w < NW; ++w) elem_prefix[e * NW + w] = 0ull;
   }
 }
@@ -1762,9 +1762,10 @@ hipError_t launch_children(const ChildArgs& a, hipStream_t stream) {
   return hipGetLastError();
 }
 
-hipError_t launch_np_init(int64_t E, int32_t* elem_traj, uint64_t* elem_prefix, int NW, hipStream_t stream) {
+hipError_t launch_np_init(int64_t E, int64_t t0, int32_t* elem_traj, uint64_t* elem_prefix, int NW,
+                          hipStream_t stream) {
   if (E <= 0) return hipSuccess;
-  hipLaunchKernelGGL(np_init_kernel, dim3(grid_blocks((E + 255) / 256)), dim3(256), 0, stream, E, elem_traj,
+  hipLaunchKernelGGL(np_init_kernel, dim3(grid_blocks((E + 255) / 256)), dim3(256), 0, stream, E, t0, elem_traj,
                      elem_prefix, NW);
   return hipGetLastError();
 }

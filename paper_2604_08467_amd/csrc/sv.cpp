@@ -321,4 +321,203 @@ ptsbe_status_t sv_contract_batch(Plan& p, int j, const uint8_t* d_kraus, int64_t
   return PTSBE_OK;
 }
 
+
+// ------------------------------------------------ non-proportional NBS (Sec. III-B)
+// The statevector form of the non-proportional mode: the same draws, element
+// order, Philox counters and final-batch rows as the network method, with every
+// marginal taken from the trajectory's state.  Trajectories run in chunks whose
+// states fit the workspace; a trajectory's elements stay in its chunk, so draw
+// rows (and their counters) are chunk-local and results do not depend on chunking.
+namespace {
+struct SvNpLayout {
+  float2* merged; double* norms; int64_t* base; int32_t* counters; double* part;
+  int32_t* traj[2]; uint64_t* prefix[2]; int32_t* off[2]; int32_t* cnt[2]; int32_t* ids[2];
+  int32_t *shot_x, *child_cnt, *child_off, *parents, *scan_scratch, *tile_cnt, *tile_off, *exh_scan, *exh_total;
+  double* totals; float* pop;
+};
+
+bool take_sv_np(const Plan& p, int64_t E, int64_t cap, int32_t R, Arena& ar, SvNpLayout& L) {
+  const size_t Xmax = (size_t)1 << max_batch_bits(p);
+  const size_t rows = (size_t)cap * (size_t)R;
+  bool ok = true;
+  auto take = [&](size_t bytes) {   // every array is taken, so a probe arena measures the whole layout
+    void* q = ar.take(bytes);
+    ok = ok && q != nullptr;
+    return q;
+  };
+  L.merged = (float2*)take((size_t)E * p.G * 16 * sizeof(float2));
+  L.norms = (double*)take((size_t)E * 8);
+  L.base = (int64_t*)take((size_t)E * 8);
+  L.counters = (int32_t*)take(64);
+  L.part = (double*)take((size_t)std::max<int64_t>(cap, kSplitRows) * Xmax * 8);
+  for (int k = 0; k < 2; ++k) {
+    L.traj[k] = (int32_t*)take((size_t)cap * 4);
+    L.prefix[k] = (uint64_t*)take((size_t)cap * 8 * p.NW);
+    L.off[k] = (int32_t*)take((size_t)cap * 4);
+    L.cnt[k] = (int32_t*)take((size_t)cap * 4);
+    L.ids[k] = (int32_t*)take(rows * 4);
+  }
+  L.shot_x = (int32_t*)take(rows * 4);
+  L.child_cnt = (int32_t*)take((size_t)cap * 4);
+  L.child_off = (int32_t*)take((size_t)cap * 4);
+  L.parents = (int32_t*)take((size_t)cap * 4);
+  L.scan_scratch = (int32_t*)take(scan_scratch_bytes(cap));
+  L.tile_cnt = (int32_t*)take((size_t)cap * 4);
+  L.tile_off = (int32_t*)take((size_t)cap * 4);
+  L.exh_scan = (int32_t*)take(scan_scratch_bytes(cap));
+  L.exh_total = (int32_t*)take(64);
+  L.totals = (double*)take((size_t)cap * 8);
+  L.pop = (float*)take((size_t)cap * Xmax * 4);
+  return ok;
+}
+}  // namespace
+
+size_t sv_np_workspace(const Plan& p, int64_t E, int64_t cap, int32_t rows_per_elem) {
+  Arena probe;                       // an arena without memory measures the layout
+  probe.base = nullptr;
+  probe.cap = ~(size_t)0 >> 1;
+  SvNpLayout L;
+  take_sv_np(p, E, cap, rows_per_elem, probe, L);
+  const size_t state = sv_traj_bytes(p);
+  const int64_t k = std::max<int64_t>(1, std::min<int64_t>(E, (int64_t)(((size_t)16 << 30) / state)));
+  return probe.used + (size_t)k * state + ((size_t)4 << 20);
+}
+
+ptsbe_status_t sv_sample_nonproportional(Plan& p, const uint8_t* d_kraus, int64_t E, const int64_t* d_mult,
+                                         int32_t draws, int32_t final_draws, int64_t cap, uint64_t seed,
+                                         double threshold, uint64_t* d_bits, int32_t* d_row_traj, double* d_p_cond,
+                                         double* d_p_prefix, int64_t capacity, int64_t* n_rows_out, double* d_w,
+                                         double* d_norm, int64_t* stats, void* d_workspace, size_t workspace_bytes,
+                                         hipStream_t s) {
+  const int32_t R = std::max(draws, final_draws);
+  Arena ar;
+  ar.base = (char*)d_workspace;
+  ar.cap = workspace_bytes;
+  SvNpLayout L;
+  if (!take_sv_np(p, E, cap, R, ar, L))
+    return fail(PTSBE_ERR_OUT_OF_MEMORY, "workspace too small for the element arrays");
+  const size_t state = sv_traj_bytes(p);
+  const int64_t NJ = std::min<int64_t>({(int64_t)(ar.left() / (state + 256)), 65535, E});
+  if (NJ < 1) return fail(PTSBE_ERR_OUT_OF_MEMORY, "workspace too small for one trajectory's state");
+  const int64_t part_rows = std::max<int64_t>(cap, kSplitRows);
+  HIP_TRY(hipMemsetAsync(L.counters, 0, 64, s));
+  GateCtx g{};
+  g.gates = p.d_gates;
+  g.gate_site_list = p.d_gate_site_list;
+  g.site_ops = p.d_site_ops;
+  g.kraus = d_kraus;
+  g.S = p.S;
+  g.max_kraus = p.max_kraus;
+  g.G = p.G;
+  HIP_TRY(launch_upv_merge(g, E, L.merged, s));
+  g.merged = L.merged;
+  const int f = (int)p.batches.size();
+  if (stats)
+    for (int j = 0; j < f; ++j) stats[j] = 0;
+  int64_t rows = 0;             // rows found so far
+  bool room = true;             // direct mode: every chunk so far fitted the capacity
+  const size_t mark = ar.used;
+  for (int64_t t0 = 0; t0 < E; t0 += NJ) {
+    const int64_t nj = std::min<int64_t>(NJ, E - t0);
+    ar.used = mark;
+    float2* psi = (float2*)ar.take((size_t)nj * state);
+    float2* Ucl = take_clusters(p, ar, nj);
+    if (!psi || (!Ucl && !p.sv_cl[2].empty()))
+      return fail(PTSBE_ERR_OUT_OF_MEMORY, "workspace too small for the chunk's states");
+    HIP_TRY(launch_np_init(nj, t0, L.traj[0], L.prefix[0], p.NW, s));
+    ptsbe_status_t st = sv_evolve(p, g, t0, nj, psi, Ucl, s);
+    if (st != PTSBE_OK) return st;
+    int cur = 0;
+    int64_t U = nj;
+    for (int j = 0; j < f; ++j) {
+      const BatchPlan& bp = p.batches[j];
+      const bool last = j + 1 == f;
+      if (stats) stats[j] += U;
+      SvMargArgs ma{};
+      ma.psi = psi; ma.n = p.n; ma.start = bp.start; ma.b = bp.size; ma.NW = p.NW;
+      ma.n_elems = U; ma.elem_traj = L.traj[cur]; ma.traj_base = (int32_t)t0; ma.elem_prefix = L.prefix[cur];
+      ma.log_split = pick_log_split(U, p.n - bp.start - bp.size);
+      ma.part = L.part; ma.part_rows = part_rows; ma.pop = L.pop;
+      HIP_TRY(launch_sv_marginal(ma, s));
+      if (last && final_draws == 0) {   // exhaustive final batch
+        HIP_TRY(launch_row_totals(L.pop, U, bp.size, L.totals, s));
+        if (j == 0) HIP_TRY(hipMemcpyAsync(L.norms + t0, L.totals, (size_t)nj * 8, hipMemcpyDeviceToDevice, s));
+        ExhArgs a{};
+        a.pop = L.pop; a.b = bp.size; a.start = bp.start; a.NW = p.NW;
+        a.n_elems = U; a.elem_traj = L.traj[cur]; a.elem_prefix = L.prefix[cur];
+        a.elem_total = L.totals; a.traj_norm = f > 1 ? L.norms : nullptr;
+        a.threshold = threshold;
+        a.tile_cnt = L.tile_cnt; a.tile_off = L.tile_off; a.tile_bits = 0;   // b <= 12: one tile per element
+        a.row_base = rows; a.capacity = capacity;
+        a.bits = d_bits; a.row_traj = d_row_traj; a.p_cond = d_p_cond; a.p_prefix = d_p_prefix;
+        HIP_TRY(launch_exh_count(a, s));
+        HIP_TRY(launch_scan_i32(L.tile_cnt, L.tile_off, U, L.exh_total, L.exh_scan, s));
+        int32_t found = 0;
+        HIP_TRY(hipMemcpyAsync(&found, L.exh_total, 4, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (found > 0 && rows < capacity) HIP_TRY(launch_exh_write(a, s));
+        rows += found;
+        break;
+      }
+      const int32_t Rj = last ? final_draws : draws;
+      HIP_TRY(launch_np_rows(U, Rj, L.traj[cur], L.off[cur], L.cnt[cur], L.ids[cur], L.base, s));
+      const bool write = last && room && rows + U * Rj <= capacity;
+      if (last && !write) room = false;
+      if (write)
+        HIP_TRY(launch_np_direct_rows(U, Rj, L.traj[cur], L.prefix[cur], p.NW, d_bits + rows * p.NW,
+                                      d_row_traj ? d_row_traj + rows : nullptr, s));
+      SampleArgs sa{};
+      sa.pop = L.pop; sa.b = bp.size; sa.start = bp.start; sa.NW = p.NW;
+      sa.n_elems = U; sa.elem_traj = L.traj[cur];
+      sa.elem_shot_off = L.off[cur]; sa.elem_shot_cnt = L.cnt[cur];
+      sa.shot_ids = L.ids[cur]; sa.traj_shot_base = L.base;
+      sa.seed = seed; sa.j = j; sa.tag = 3u;
+      sa.shots = write ? d_bits + rows * p.NW : nullptr;
+      sa.p_cond = write && d_p_cond ? d_p_cond + rows : nullptr;
+      sa.shot_x = L.shot_x;
+      sa.elem_total = L.totals;
+      sa.child_cnt = last ? nullptr : L.child_cnt;
+      sa.bad_flag = L.counters + 1;
+      HIP_TRY(launch_sample(sa, s));
+      if (j == 0) HIP_TRY(hipMemcpyAsync(L.norms + t0, L.totals, (size_t)nj * 8, hipMemcpyDeviceToDevice, s));
+      if (last) {
+        if (write)
+          HIP_TRY(launch_np_direct_prefix_p(U, Rj, L.traj[cur], L.totals, f > 1 ? L.norms : nullptr,
+                                            d_p_prefix ? d_p_prefix + rows : nullptr, s));
+        rows += U * Rj;
+        break;
+      }
+      HIP_TRY(launch_scan_i32(L.child_cnt, L.child_off, U, L.counters, L.scan_scratch, s));
+      int32_t nU = 0;
+      HIP_TRY(hipMemcpyAsync(&nU, L.counters, 4, hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      if (nU > cap)
+        return fail(PTSBE_ERR_OUT_OF_MEMORY, "batch " + std::to_string(j + 1) + " has more elements than max_elems");
+      ChildArgs ca{};
+      ca.n_elems = U; ca.b = bp.size; ca.start = bp.start; ca.NW = p.NW;
+      ca.elem_traj = L.traj[cur]; ca.elem_prefix = L.prefix[cur];
+      ca.elem_shot_off = L.off[cur]; ca.elem_shot_cnt = L.cnt[cur];
+      ca.shot_ids = L.ids[cur]; ca.shot_x = L.shot_x; ca.child_off = L.child_off;
+      ca.out_traj = L.traj[1 - cur]; ca.out_prefix = L.prefix[1 - cur];
+      ca.out_shot_off = L.off[1 - cur]; ca.out_shot_cnt = L.cnt[1 - cur]; ca.out_shot_ids = L.ids[1 - cur];
+      ca.out_parent = L.parents;   // not needed by this method (no left tensors to resume from)
+      HIP_TRY(launch_children(ca, s));
+      cur = 1 - cur;
+      U = nU;
+    }
+  }
+  if (d_w || d_norm) {
+    WeightArgs wa{L.norms, d_mult, E, d_w, d_norm};
+    HIP_TRY(launch_weights(wa, s));
+  }
+  int32_t bad = 0;
+  HIP_TRY(hipMemcpyAsync(&bad, L.counters + 1, 4, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  *n_rows_out = rows;
+  if (bad) return fail(PTSBE_ERR_NUMERIC, "an element had a non-finite marginal total");
+  if (rows > capacity)
+    return fail(PTSBE_ERR_OUT_OF_MEMORY, std::to_string(rows) + " rows found, capacity " + std::to_string(capacity));
+  return PTSBE_OK;
+}
+
 }  // namespace ptsbe

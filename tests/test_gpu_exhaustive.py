@@ -65,19 +65,20 @@ def _compare(out, ref_rows, ref_counts, bs, thr, tag):
     assert keys == sorted(keys)
 
 
+@pytest.mark.parametrize("method", ["network", "statevector"])
 @pytest.mark.parametrize("bs,draws,thr", [([4, 4, 4], 3, 1e-3), ([5, 7], 5, 0.0), ([3, 3, 3, 3], 2, 2e-3)],
                          ids=["4-4-4_k3", "5-7_k5", "3x4_k2"])
-def test_exhaustive_matches_oracle(bs, draws, thr):
+def test_exhaustive_matches_oracle(bs, draws, thr, method):
     import paper_2604_08467_amd as P
     torch, dev = torch_dev()
     rng = np.random.default_rng(301)
     circ = W.random_brickwork(sum(bs), 5, rng, 0.02)
-    plan = P.Plan(circ, bs, method="network")
+    plan = P.Plan(circ, bs, method=method)
     kr, mult, _, _ = plan.sample_trajectories(302, 12)
     out = plan.sample_nonproportional(to_dev(torch, dev, kr), draws, 303, thr, mult_dev=to_dev(torch, dev, mult))
     torch.cuda.synchronize()
     ref_rows, ref_counts, psis = _oracle_rows(circ, bs, kr, draws, 303, thr)
-    _compare(out, ref_rows, ref_counts, bs, thr, f"batches {bs}, draws {draws}, threshold {thr}")
+    _compare(out, ref_rows, ref_counts, bs, thr, f"{method}: batches {bs}, draws {draws}, threshold {thr}")
     Z = np.array([np.vdot(p, p).real for p in psis])
     np.testing.assert_allclose(out["norms"].cpu().numpy(), Z, rtol=1e-5)
     np.testing.assert_allclose(out["weights"].cpu().numpy(), sampling.trajectory_weights(Z, mult), rtol=1e-5)
@@ -146,9 +147,10 @@ def test_exhaustive_capacity_overflow_keeps_the_first_rows():
         plan.sample_nonproportional(kd, 3, 323, 1e-4, max_elems=len(kr))
 
 
+@pytest.mark.parametrize("method", ["network", "statevector"])
 @pytest.mark.parametrize("bs,draws,fd", [([4, 4, 4], 2, 50), ([6, 6], 3, 200), ([10], 1, 500)],
                          ids=["4-4-4_k2_f50", "6-6_k3_f200", "10_f500"])
-def test_direct_final_batch_matches_oracle(bs, draws, fd):
+def test_direct_final_batch_matches_oracle(bs, draws, fd, method):
     """Direct final-batch draws: identical element counts, rows in the same order with
     identical bitstrings except CDF-boundary flips of the final draws (at most 0.1 % of the
     rows), P(x | prefix) and p(prefix) of identical rows within 1e-6."""
@@ -156,7 +158,7 @@ def test_direct_final_batch_matches_oracle(bs, draws, fd):
     torch, dev = torch_dev()
     rng = np.random.default_rng(331)
     circ = W.random_brickwork(sum(bs), 5, rng, 0.02)
-    plan = P.Plan(circ, bs, method="network")
+    plan = P.Plan(circ, bs, method=method)
     kr, mult, _, _ = plan.sample_trajectories(332, 10)
     out = plan.sample_nonproportional(to_dev(torch, dev, kr), draws, 333, final_draws=fd,
                                       mult_dev=to_dev(torch, dev, mult))
@@ -179,10 +181,54 @@ def test_direct_final_batch_matches_oracle(bs, draws, fd):
     assert np.array_equal(traj, np.array([r[0] for r in ref_rows]))
     err_pc = max(abs(pc[k] - ref_rows[k][2]) for k in same)
     err_pp = max(abs(pp[k] - ref_rows[k][3]) for k in same)
-    _say(f"direct {bs} draws {draws} final {fd}: {len(ref_rows) - len(same)} of {len(ref_rows)} rows differ; "
+    _say(f"{method}: direct {bs} draws {draws} final {fd}: {len(ref_rows) - len(same)} of {len(ref_rows)} rows differ; "
          f"max |dP(x|prefix)| {err_pc:.2e}, max |dp(prefix)| {err_pp:.2e}")
     assert len(ref_rows) - len(same) <= 0.001 * len(ref_rows) + 1
     assert err_pc <= 1e-6 and err_pp <= 1e-6
     Z = np.array([np.vdot(p, p).real for p in psis])
     np.testing.assert_allclose(out["norms"].cpu().numpy(), Z, rtol=1e-5)
     np.testing.assert_allclose(out["weights"].cpu().numpy(), sampling.trajectory_weights(Z, mult), rtol=1e-5)
+
+
+@pytest.mark.parametrize("method", ["network", "statevector"])
+def test_exhaustive_grid_with_amplitude_damping(method):
+    """A 3x4 grid of sqrt-gates and CZ with depolarising and amplitude damping (non-unit
+    norms, importance weights), batches [4, 4, 4], two draws per prefix."""
+    import paper_2604_08467_amd as P
+    torch, dev = torch_dev()
+    rng = np.random.default_rng(341)
+    circ = W.sqrt_grid(3, 4, 5, rng, p=0.05, gamma=0.1)
+    bs = [4, 4, 4]
+    plan = P.Plan(circ, bs, method=method)
+    kr, mult, _, _ = plan.sample_trajectories(342, 16)
+    thr = 5e-4
+    out = plan.sample_nonproportional(to_dev(torch, dev, kr), 2, 343, thr, mult_dev=to_dev(torch, dev, mult))
+    ref_rows, ref_counts, psis = _oracle_rows(circ, bs, kr, 2, 343, thr)
+    _compare(out, ref_rows, ref_counts, bs, thr, f"{method}: 3x4 grid with amplitude damping")
+    Z = np.array([np.vdot(p, p).real for p in psis])
+    np.testing.assert_allclose(out["norms"].cpu().numpy(), Z, rtol=1e-5)
+    np.testing.assert_allclose(out["weights"].cpu().numpy(), sampling.trajectory_weights(Z, mult), rtol=1e-5)
+
+
+def test_statevector_chunking_does_not_change_rows():
+    """A workspace that holds only a few states at a time gives the same rows."""
+    import paper_2604_08467_amd as P
+    torch, dev = torch_dev()
+    rng = np.random.default_rng(351)
+    circ = W.random_brickwork(14, 5, rng, 0.03, layout="2d")
+    bs = [5, 5, 4]
+    plan = P.Plan(circ, bs, method="statevector")
+    kr, _, _, _ = plan.sample_trajectories(352, 40)
+    kd = to_dev(torch, dev, kr)
+    full = plan.sample_nonproportional(kd, 2, 353, 1e-3)
+    E = len(kr)
+    need = plan.nonproportional_workspace_size(E, 2, E * 4)
+    small = need - (4 << 20) - (E - 3) * (8 << 14)      # room for a few states at a time
+    ws = torch.empty(small, dtype=torch.uint8, device=dev)
+    part = plan.sample_nonproportional(kd, 2, 353, 1e-3, workspace=ws)
+    _say(f"chunked: {part['n_rows']} rows, unchunked {full['n_rows']}")
+    assert part["n_rows"] == full["n_rows"]
+    assert torch.equal(part["bits"], full["bits"]) and torch.equal(part["p_cond"], full["p_cond"])
+    a = plan.sample_nonproportional(kd, 2, 353, final_draws=25)
+    b = plan.sample_nonproportional(kd, 2, 353, final_draws=25, workspace=ws)
+    assert torch.equal(a["bits"], b["bits"]) and torch.equal(a["p_prefix"], b["p_prefix"])

@@ -259,3 +259,7 @@ def test_nonproportional_workspace_size_grows_with_elements_and_draws():
         plan.nonproportional_workspace_size(8, 0, 16)
     # direct final-batch draws: rows per element grow with final_draws beyond draws
     assert plan.nonproportional_workspace_size(8, 2, 4096, final_draws=1000) > b
+    # statevector plans: element arrays plus at least one state
+    sv = P.Plan(W.random_brickwork(12, 4, rng, 0.01), [4, 4, 4], device=-1, method="statevector")
+    a, b = sv.nonproportional_workspace_size(8, 2, 16), sv.nonproportional_workspace_size(8, 2, 4096)
+    assert (8 << 12) < a < b
