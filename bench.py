@@ -74,7 +74,7 @@ def main():
     ap.add_argument("--final-batch", type=int, default=20, help="exhaustive workload: final batch size")
     ap.add_argument("--threshold", type=float, default=1e-6, help="exhaustive workload: P(x | prefix) threshold")
     ap.add_argument("--draws", type=int, default=1, help="exhaustive workload: draws per prefix")
-    ap.add_argument("--workload", choices=["brickwork50", "ragged", "exhaustive"], default="brickwork50",
+    ap.add_argument("--workload", choices=["brickwork50", "ragged", "exhaustive", "batch-sweep"], default="brickwork50",
                     help="ragged: the ragged mix of circuits as one graph-captured ragged set")
     ap.add_argument("--ragged-max-qubits", type=int, default=26)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -93,6 +93,9 @@ def main():
         return
     if args.workload == "exhaustive":
         bench_exhaustive(args)
+        return
+    if args.workload == "batch-sweep":
+        bench_batch_sweep(args)
         return
     if args.copy_calibration:
         n = 1 << 30
@@ -261,6 +264,76 @@ def bench_exhaustive(args):
                                "job's input and output tensor once, 8 (2^rA + 2^rC) bytes)",
                      "launches": sw["step_launches"], "avg_us": sw["step_ms"] * 1e3 / max(sw["step_launches"], 1),
                      "bytes_per_step": sw["step_bytes"], "kernel_ms_per_step": sw["step_ms"]},
+    }
+    print(json.dumps(line), flush=True)
+
+
+def bench_batch_sweep(args):
+    """Contraction time of the final batch against its size b (Sec. V-B), and the
+    host path-finding time of each plan: a 100-qubit 1D brickwork of 594 Haar SU(4)
+    gates (depth 12, depolarising p=0.005), batches [10, ..., remainder, b].  For each b
+    the plan is built (timed on the host), 4 trajectories are drawn, and the final
+    batch is contracted for them (one element each, empty prefix), timed with events
+    on the launch stream after one untimed call."""
+    import numpy as np
+    import torch
+
+    import paper_2604_08467_amd as P
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(5001)
+    circ = W.random_brickwork(100, 12, rng, 0.005).round_to_complex64()
+    n_traj = 4
+    ws = torch.empty(int(args.workspace_gb * (1 << 30)), dtype=torch.uint8, device=dev)
+    table = []
+    for b in (8, 10, 12, 14, 16, 18, 20):
+        rest = 100 - b
+        bs = [10] * (rest // 10) + ([rest % 10] if rest % 10 else []) + [b]
+        t0 = time.perf_counter()
+        plan = P.Plan(circ, bs, hypersamples=8, method="network")
+        t_plan = time.perf_counter() - t0
+        kr, _, _, _ = plan.sample_trajectories(5002, n_traj)
+        E = len(kr)
+        kd = torch.from_numpy(kr).to(dev)
+        et = torch.arange(E, dtype=torch.int32, device=dev)
+        ep = torch.zeros((E, plan.n_words), dtype=torch.int64, device=dev)
+        j = len(bs) - 1
+        plan.contract_batch(j, kd, et, ep, P.OUT_POPULATION, workspace=ws)
+        torch.cuda.synchronize()
+        reps = 3
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(reps):
+            pop, tot = plan.contract_batch(j, kd, et, ep, P.OUT_POPULATION, workspace=ws)
+        ev1.record()
+        torch.cuda.synchronize()
+        call_ms = ev0.elapsed_time(ev1) / reps
+        # trajectories that agree on the Kraus choices of the per-trajectory part share its tensor
+        sites = plan.right_sites(j)
+        distinct = len({tuple(kr[t, sites]) for t in range(E)})
+        bi = plan.batch_info(j)
+        row = {"b": b, "batches": bs, "plan_s": round(t_plan, 3), "call_ms": round(call_ms, 3),
+               "distinct_right_parts": distinct, "ms_per_right_part": round(call_ms / distinct, 3),
+               "right_rank": bi["right_rank"], "crossing": bi["crossing"],
+               "alg_bytes_per_right_part": bi["bytes_per_traj"], "alg_flops_per_elem": bi["flops_per_elem"]}
+        table.append(row)
+        print(f"batch-sweep: b={b} plan {t_plan:.2f} s, {E} trajectories ({distinct} distinct right parts) in "
+              f"{call_ms:.2f} ms", file=sys.stderr, flush=True)
+        del plan, pop, tot
+    last = table[-1]
+    rate = last["alg_bytes_per_right_part"] / (last["ms_per_right_part"] / 1e3) / 1e9
+    line = {
+        "metric": "final-batch contraction time per distinct per-trajectory part at the largest batch size",
+        "value": last["ms_per_right_part"], "unit": "ms", "n_gpus": 1, "steps": 3, "warmup": 1,
+        "ms_per_step": last["call_ms"], "higher_is_better": False, "scaling": "strong",
+        "vs_baseline": None, "dtype": "c64", "data": "synthetic",
+        "config": {"workload": "100-qubit 1D brickwork depth 12 (594 Haar SU(4) gates, c64), depolarising "
+                               "p=0.005, final batch of b qubits after batches of 10", "table": table},
+        "roofline": {"bound": "hbm", "achieved": rate, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": rate / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "whole final-batch contraction (algorithmic sweep bytes of the distinct "
+                               "per-trajectory parts over the call time; join and left parts included in the time)"},
     }
     print(json.dumps(line), flush=True)
 
