@@ -1076,11 +1076,20 @@ __global__ void row_totals_kernel(const float* pop, int64_t n_elems, int b, doub
   __shared__ double red[256];
   const int64_t n = (int64_t)1 << b;
   for (int64_t e = blockIdx.x; e < n_elems; e += gridDim.x) {
-  // sequential chunks per thread, then a fixed tree: deterministic
-  double s = 0.0;
-  const int64_t per = (n + blockDim.x - 1) / blockDim.x;
-  const int64_t lo = threadIdx.x * per, hi = lo + per < n ? lo + per : n;
-  for (int64_t i = lo; i < hi; ++i) s += (double)pop[e * n + i];
+  // thread t sums the float4 groups t, t + 256, ... (coalesced) into four FP64
+  // accumulators (independent add chains), combined in a fixed order, then a fixed
+  // tree: deterministic
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  if ((n & 3) == 0 && (reinterpret_cast<uintptr_t>(pop) & 15) == 0) {   // 16-byte aligned rows
+    const float4* p4 = reinterpret_cast<const float4*>(pop + e * n);
+    for (int64_t i = threadIdx.x; i < (n >> 2); i += blockDim.x) {
+      const float4 v = p4[i];
+      s0 += (double)v.x; s1 += (double)v.y; s2 += (double)v.z; s3 += (double)v.w;
+    }
+  } else {
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) s0 += (double)pop[e * n + i];
+  }
+  const double s = (s0 + s1) + (s2 + s3);
   red[threadIdx.x] = s;
   __syncthreads();
   for (int w = blockDim.x / 2; w > 0; w >>= 1) {
@@ -1347,9 +1356,10 @@ __global__ void __launch_bounds__(256) exh_count_kernel(ExhArgs a) {
     const double Z = a.elem_total[e];
     const float* pi = a.pop + e * X + x0;
     int c = 0;
-    const int lo = threadIdx.x * per;
-    if (lo < tileX)
-      for (int i = lo; i < lo + per; ++i) c += exh_pass(pi[i], Z, a.threshold);
+    for (int i = 0; i < per; ++i) {   // x = 256 i + t: coalesced
+      const int x = 256 * i + (int)threadIdx.x;
+      if (x < tileX) c += exh_pass(pi[x], Z, a.threshold);
+    }
     red[threadIdx.x] = c;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
@@ -1362,52 +1372,56 @@ __global__ void __launch_bounds__(256) exh_count_kernel(ExhArgs a) {
 }
 
 __global__ void __launch_bounds__(256) exh_write_kernel(ExhArgs a) {
-  __shared__ int scan[256];
+  // Rows of a tile in x order: round i covers x = 256 i + t; within a round the
+  // four wavefronts hold consecutive x ranges, and a lane's place among them is
+  // the popcount of the passing lanes below it (ballot).  Consecutive lanes write
+  // consecutive rows.
+  __shared__ int wcnt[kExhTile / 256][4];
   const int64_t X = (int64_t)1 << a.b;
   const int tileX = X < kExhTile ? (int)X : kExhTile;
   const int per = tileX >= 256 ? tileX >> 8 : 1;
   const int64_t n_units = a.n_elems << a.tile_bits;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
   const int wi = a.start >> 6, sh = a.start & 63;
   for (int64_t u = blockIdx.x; u < n_units; u += gridDim.x) {
     const int64_t e = u >> a.tile_bits;
     const int64_t x0 = (u & (((int64_t)1 << a.tile_bits) - 1)) * tileX;
     const double Z = a.elem_total[e];
     const float* pi = a.pop + e * X + x0;
-    const int lo = tid * per;
-    const bool mine = lo < tileX;
-    int c = 0;
-    if (mine)
-      for (int i = lo; i < lo + per; ++i) c += exh_pass(pi[i], Z, a.threshold);
-    // exclusive scan of the threads' counts (Hillis-Steele in LDS)
-    scan[tid] = c;
-    __syncthreads();
-    for (int d = 1; d < 256; d <<= 1) {
-      const int t = tid >= d ? scan[tid - d] : 0;
-      __syncthreads();
-      scan[tid] += t;
-      __syncthreads();
+    __syncthreads();   // wcnt of the previous unit is no longer read
+    for (int i = 0; i < per; ++i) {
+      const int x = 256 * i + tid;
+      const bool pass = x < tileX && exh_pass(pi[x], Z, a.threshold);
+      const uint64_t m = __ballot(pass);
+      if (lane == 0) wcnt[i][wv] = __popcll(m);
     }
-    int64_t row = a.row_base + a.tile_off[u] + scan[tid] - c;
-    __syncthreads();   // scan[] is rewritten by the next unit
-    if (!mine || c == 0) continue;
+    __syncthreads();
     const int traj = a.elem_traj[e];
     const uint64_t* pp = a.elem_prefix + e * a.NW;
     const double pref = a.traj_norm ? Z / a.traj_norm[traj] : 1.0;
-    for (int i = lo; i < lo + per; ++i) {
-      const float v = pi[i];
-      if (!exh_pass(v, Z, a.threshold)) continue;
-      if (row < a.capacity) {
-        const uint64_t x = (uint64_t)(x0 + i);
-        uint64_t* w = a.bits + row * a.NW;
-        for (int k = 0; k < a.NW; ++k) w[k] = pp[k];
-        w[wi] |= x << sh;
-        if (sh + a.b > 64) w[wi + 1] |= x >> (64 - sh);
-        if (a.row_traj) a.row_traj[row] = traj;
-        if (a.p_cond) a.p_cond[row] = (double)v / Z;
-        if (a.p_prefix) a.p_prefix[row] = pref;
+    int64_t row = a.row_base + a.tile_off[u];
+    for (int i = 0; i < per; ++i) {
+      const int x = 256 * i + tid;
+      const float v = x < tileX ? pi[x] : 0.f;
+      const bool pass = x < tileX && exh_pass(v, Z, a.threshold);
+      const uint64_t m = __ballot(pass);
+      int before = 0;
+      for (int w = 0; w < wv; ++w) before += wcnt[i][w];
+      if (pass) {
+        const int64_t r = row + before + __popcll(m & below);
+        if (r < a.capacity) {
+          const uint64_t xv = (uint64_t)(x0 + x);
+          uint64_t* w = a.bits + r * a.NW;
+          for (int k = 0; k < a.NW; ++k) w[k] = pp[k];
+          w[wi] |= xv << sh;
+          if (sh + a.b > 64) w[wi + 1] |= xv >> (64 - sh);
+          if (a.row_traj) a.row_traj[r] = traj;
+          if (a.p_cond) a.p_cond[r] = (double)v / Z;
+          if (a.p_prefix) a.p_prefix[r] = pref;
+        }
       }
-      ++row;
+      row += wcnt[i][0] + wcnt[i][1] + wcnt[i][2] + wcnt[i][3];
     }
   }
 }
