@@ -184,6 +184,21 @@ ptsbe_status_t ptsbe_plan_batch_info(ptsbe_plan_t plan, int32_t j, ptsbe_batch_i
  * ascending site ids, room for the circuit's site count; *n_sites_out: their
  * number.  PTSBE_ERR_INVALID_ARG for a statevector plan or j out of range. */
 ptsbe_status_t ptsbe_plan_right_sites(ptsbe_plan_t plan, int32_t j, int32_t* sites, int32_t* n_sites_out);
+
+/* Tiling of the last-batch GEMV join over x (plan introspection, network method):
+ * for a ket-only batch j whose per-trajectory part carries at least 12 bits of x,
+ * the 12 tile bits' offsets in that part's tensor T (read order, ascending) and in
+ * the population output (write order, ascending), the write-order index of each
+ * read-order bit, and the T and output offsets of the x bits outside the tile;
+ * also every x bit's own offsets in T and in the output, so that a caller can
+ * check that the tiles cover each x once.  PTSBE_ERR_UNSUPPORTED when the batch
+ * takes no tiling (doubled batch, fewer than 12 bits, more than 2 rows).
+ *   t_read[12], o_read[12], o_write[12] int64; w_of[12] int32;
+ *   t_hi[32], o_hi[32] int64, n_hi: bits outside the tile;
+ *   x_t[32], x_o[32] int64, n_x: every x bit (host buffers, caller-owned). */
+ptsbe_status_t ptsbe_plan_join_tiling(ptsbe_plan_t plan, int32_t j, int64_t* t_read, int64_t* o_read,
+                                      int32_t* w_of, int64_t* o_write, int64_t* t_hi, int64_t* o_hi,
+                                      int32_t* n_hi, int64_t* x_t, int64_t* x_o, int32_t* n_x);
 /* Statevector method: the gate schedule for windows of window_qubits (10, 11 or
  * 12) qubits, for inspection and tests.  Host outputs (caller-owned; any may be
  * NULL): gate_order [n_gates] gate indices in execution order (each gate once; a

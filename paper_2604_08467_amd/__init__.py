@@ -135,6 +135,21 @@ class Plan:
         except Exception:
             pass
 
+    def join_tiling(self, j):
+        """ptsbe_plan_join_tiling: the GEMV join's tiling of batch j over x (dict of arrays)."""
+        a = {k: np.zeros(n, dtype=np.int64) for k, n in
+             (("t_read", 12), ("o_read", 12), ("o_write", 12), ("t_hi", 32), ("o_hi", 32), ("x_t", 32), ("x_o", 32))}
+        w = np.zeros(12, dtype=np.int32)
+        nh, nx = C.c_int32(), C.c_int32()
+        ptr = lambda v: v.ctypes.data_as(C.c_void_p)
+        _lib.check(self._lib.ptsbe_plan_join_tiling(self._h, int(j), ptr(a["t_read"]), ptr(a["o_read"]), ptr(w),
+                                                    ptr(a["o_write"]), ptr(a["t_hi"]), ptr(a["o_hi"]), C.byref(nh),
+                                                    ptr(a["x_t"]), ptr(a["x_o"]), C.byref(nx)))
+        a["w_of"] = w
+        a["t_hi"], a["o_hi"] = a["t_hi"][:nh.value], a["o_hi"][:nh.value]
+        a["x_t"], a["x_o"] = a["x_t"][:nx.value], a["x_o"][:nx.value]
+        return a
+
     def right_sites(self, j):
         """ptsbe_plan_right_sites: sites whose Kraus choices enter batch j's per-trajectory part."""
         buf = np.zeros(max(self.n_sites, 1), dtype=np.int32)

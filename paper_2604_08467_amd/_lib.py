@@ -19,6 +19,7 @@ EXPORTS = [
     "ptsbe_ragged_create", "ptsbe_ragged_destroy", "ptsbe_ragged_info", "ptsbe_ragged_workspace_size",
     "ptsbe_ragged_autotune", "ptsbe_ragged_sample_shots", "ptsbe_plan_sv_schedule", "ptsbe_plan_right_sites",
     "ptsbe_nonproportional_workspace_size", "ptsbe_sample_nonproportional", "ptsbe_profile_read_sweeps",
+    "ptsbe_plan_join_tiling",
 ]
 
 
@@ -96,6 +97,7 @@ def load():
     lib.ptsbe_plan_batch_info.argtypes = [P, i32, C.POINTER(BatchInfo_t)]
     lib.ptsbe_plan_sv_schedule.argtypes = [P, i32, P, P, P, C.POINTER(i32)]
     lib.ptsbe_plan_right_sites.argtypes = [P, i32, P, C.POINTER(i32)]
+    lib.ptsbe_plan_join_tiling.argtypes = [P, i32, P, P, P, P, P, P, C.POINTER(i32), P, P, C.POINTER(i32)]
     lib.ptsbe_plan_destroy.argtypes = [P]
     lib.ptsbe_plan_destroy.restype = None
     lib.ptsbe_sample_trajectories.argtypes = [P, u64, i64, i64, P, P, P, C.POINTER(i64), C.POINTER(i64)]

@@ -898,6 +898,42 @@ ptsbe_status_t ptsbe_plan_right_sites(ptsbe_plan_t plan, int32_t j, int32_t* sit
   return PTSBE_OK;
 }
 
+ptsbe_status_t ptsbe_plan_join_tiling(ptsbe_plan_t plan, int32_t j, int64_t* t_read, int64_t* o_read,
+                                      int32_t* w_of, int64_t* o_write, int64_t* t_hi, int64_t* o_hi,
+                                      int32_t* n_hi, int64_t* x_t, int64_t* x_o, int32_t* n_x) {
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  if (!p) return fail(PTSBE_ERR_INVALID_ARG, "null plan");
+  if (p->method == PTSBE_METHOD_STATEVECTOR) return fail(PTSBE_ERR_INVALID_ARG, "statevector-method plan");
+  if (j < 0 || j >= (int)p->batches.size()) return fail(PTSBE_ERR_INVALID_ARG, "batch index out of range");
+  if (!t_read || !o_read || !w_of || !o_write || !t_hi || !o_hi || !n_hi || !x_t || !x_o || !n_x)
+    return fail(PTSBE_ERR_INVALID_ARG, "null argument");
+  const ptsbe::BatchPlan& bp = p->batches[(size_t)j];
+  ptsbe::GemvTiling g{};
+  if (bp.doubled || bp.xb.size() > 1 || !ptsbe::make_gemv_tiling(bp, g))
+    return fail(PTSBE_ERR_UNSUPPORTED, "batch takes no GEMV tiling");
+  for (int s = 0; s < 12; ++s) {
+    t_read[s] = g.t_off[s];
+    o_read[s] = g.o_read[s];
+    w_of[s] = g.w_of[s];
+    o_write[s] = g.o_off[s];
+  }
+  *n_hi = g.n_hi;
+  for (int h = 0; h < g.n_hi; ++h) {
+    t_hi[h] = g.t_hi[h];
+    o_hi[h] = g.o_hi[h];
+  }
+  const int nx = (int)bp.xT.size();
+  auto off = [](const ptsbe::SplitTable& t, int i) -> int64_t {
+    return i < t.lo_bits ? t.lo[(size_t)1 << i] : t.hi[(size_t)1 << (i - t.lo_bits)];
+  };
+  for (int i = 0; i < nx; ++i) {
+    x_t[i] = off(bp.t_x, i);
+    x_o[i] = off(bp.o_x, i);
+  }
+  *n_x = nx;
+  return PTSBE_OK;
+}
+
 ptsbe_status_t ptsbe_plan_batch_info(ptsbe_plan_t plan, int32_t j, ptsbe_batch_info_t* out) {
   Plan* p = reinterpret_cast<Plan*>(plan);
   if (!p || !out) return fail(PTSBE_ERR_INVALID_ARG, "null argument");

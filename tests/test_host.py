@@ -263,3 +263,56 @@ def test_nonproportional_workspace_size_grows_with_elements_and_draws():
     sv = P.Plan(W.random_brickwork(12, 4, rng, 0.01), [4, 4, 4], device=-1, method="statevector")
     a, b = sv.nonproportional_workspace_size(8, 2, 16), sv.nonproportional_workspace_size(8, 2, 4096)
     assert (8 << 12) < a < b
+
+
+@pytest.mark.parametrize("bs", [[10, 10, 10, 20], [4, 16], [10, 10, 10, 10, 10]])
+def test_gemv_join_tiling_covers_each_x_once(bs):
+    """The tiled GEMV join (last batch, <= 2 rows): replaying its index arithmetic on the
+    host, every value of x is read once at its own offset in T and written once at its
+    own output offset, reads are contiguous over the 6 lowest T offsets and writes over
+    the lowest output offsets."""
+    P = _lib()
+    wl = W.config2() if sum(bs) == 50 else None
+    circ = wl.circuit if wl else W.random_brickwork(sum(bs), 4, np.random.default_rng(311), 0.02)
+    plan = P.Plan(circ, bs, hypersamples=8, device=-1, method="network")
+    j = len(bs) - 1
+    if plan.batch_info(j)["size"] < 12:
+        with pytest.raises(P.PtsbeError):
+            plan.join_tiling(j)
+        return
+    g = plan.join_tiling(j)
+    x_t, x_o = [int(v) for v in g["x_t"]], [int(v) for v in g["x_o"]]
+    nx = len(x_t)
+    assert all(v > 0 and v & (v - 1) == 0 for v in x_t + x_o)
+    assert sorted(list(g["t_read"]) + list(g["t_hi"])) == sorted(x_t)
+    assert sorted(list(g["o_read"]) + list(g["o_hi"])) == sorted(x_o)
+    assert list(g["t_read"]) == sorted(g["t_read"]) and list(g["o_write"]) == sorted(g["o_write"])
+    assert sorted(g["w_of"]) == list(range(12))
+    assert all(g["o_write"][g["w_of"][s]] == g["o_read"][s] for s in range(12))
+    assert list(g["t_read"][:6]) == sorted(x_t)[:6]          # contiguous read runs
+    # every x is read once and written once (small tilings replayed in full)
+    if nx <= 16:
+        t2x = {}
+        for x in range(1 << nx):
+            t2x[sum(x_t[i] for i in range(nx) if x >> i & 1)] = x
+        o_of = lambda x: sum(x_o[i] for i in range(nx) if x >> i & 1)
+        seen_r, seen_w = set(), set()
+        for tile in range(1 << len(g["t_hi"])):
+            tb = sum(int(g["t_hi"][h]) for h in range(len(g["t_hi"])) if tile >> h & 1)
+            ob = sum(int(g["o_hi"][h]) for h in range(len(g["o_hi"])) if tile >> h & 1)
+            lds = {}
+            for i in range(4096):      # read-order index: thread t = i & 255, j = i >> 8
+                toff = tb + sum(int(g["t_read"][s]) for s in range(12) if i >> s & 1)
+                x = t2x[toff]
+                assert x not in seen_r
+                seen_r.add(x)
+                li = sum(1 << int(g["w_of"][s]) for s in range(12) if i >> s & 1)
+                assert li not in lds
+                lds[li] = x
+                assert ob + sum(int(g["o_read"][s]) for s in range(12) if i >> s & 1) == o_of(x)
+            for w in range(4096):      # write-order index
+                off = ob + sum(int(g["o_write"][q]) for q in range(12) if w >> q & 1)
+                assert off == o_of(lds[w])
+                assert off not in seen_w
+                seen_w.add(off)
+        assert len(seen_r) == len(seen_w) == 1 << nx
