@@ -82,7 +82,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the path shards over trajectories across GPUs by design, "
-              "but this build measures a single MI355X", file=sys.stderr)
+              "but this benchmark measures a single MI355X", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -111,7 +111,7 @@ def main():
     import workloads as W
 
     dev = torch.device("cuda:0")
-    wl = W.config2()
+    wl = W.brickwork50_d6()
     c = wl.circuit
     plan = P.Plan(c, wl.batch_sizes, hypersamples=8, precision={"c64": 0, "bf16": 1, "f16": 2}[args.precision])
     kr, mult, _, n_draws = plan.sample_trajectories(wl.pts_seed, args.traj)
@@ -192,7 +192,7 @@ def bench_exhaustive(args):
     import workloads as W
 
     dev = torch.device("cuda:0")
-    wl = W.config2()
+    wl = W.brickwork50_d6()
     bf = args.final_batch
     bs = [10, 10, 10, bf] if bf <= 20 else [10, 40 - bf, bf]
     assert sum(bs) == 50
@@ -351,7 +351,7 @@ def bench_ragged(args):
     from paper_2604_08467_amd.ragged import RaggedSet
 
     dev = torch.device("cuda:0")
-    mix = W.config4()
+    mix = W.ragged_mix()
     jobs, excluded = [], []
     t_plan = time.perf_counter()
     for k, c in enumerate(mix):

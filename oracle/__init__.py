@@ -19,7 +19,8 @@ III-B of the paper):
 * ``sampling``     - batch-wise conditional marginals and the per-shot sampler
                      (Sec. II-B), NBS bookkeeping (Sec. III-B), trajectory weights
 
-Every function names the passage it follows.  Parity status of each function is
-listed in the design doc; the Philox generator's cross-implementation parity is
-unpinned (no published known-answer vectors are available here).
+Every function names the passage it follows and is pinned by the CPU tests of
+the oracle against closed forms, invariants or brute force; the Philox
+generator's cross-implementation parity is unpinned (no published known-answer
+vectors are available here).
 """

@@ -2,7 +2,7 @@
 
 Sec. II-B: the n qubits are split into batches B_1..B_f; a shot is drawn batch by
 batch, the bits already drawn (s_1..s_{j-1}) being projected into the network
-before the marginal of batch j is contracted.  Readings (listed in the design doc):
+before the marginal of batch j is contracted.  Readings of the paper used here:
 batches are contiguous ascending qubit ranges; the marginal of batch j given the
 prefix p is
 

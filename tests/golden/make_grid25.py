@@ -28,7 +28,7 @@ N_TRAJ, N_SHOTS = 2, 16
 
 
 def main():
-    wl = W.config3((10, 10, 5))
+    wl = W.grid5x5_d8((10, 10, 5))
     c = wl.circuit
     n, bs = c.n_qubits, list(wl.batch_sizes)
     starts = sampling.batch_starts(bs)

@@ -138,7 +138,7 @@ def test_contract_no_elements(method):
     """A contraction of zero elements succeeds and writes nothing."""
     import paper_2604_08467_amd as P
     torch, dev = torch_dev()
-    wl = W.config1()
+    wl = W.chain10_d8()
     plan = P.Plan(wl.circuit, wl.batch_sizes, method=method)
     kr, _, _, _ = plan.sample_trajectories(wl.pts_seed, 4)
     kd = to_dev(torch, dev, kr)

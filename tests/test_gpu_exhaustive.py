@@ -89,7 +89,7 @@ def test_exhaustive_single_batch():
     p(prefix) = 1; the norms come from the batch's own totals."""
     import paper_2604_08467_amd as P
     torch, dev = torch_dev()
-    wl = W.config1()
+    wl = W.chain10_d8()
     plan = P.Plan(wl.circuit, wl.batch_sizes, method="network")
     kr, mult, _, _ = plan.sample_trajectories(wl.pts_seed, 16)
     thr = 2e-3

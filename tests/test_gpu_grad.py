@@ -82,19 +82,19 @@ def test_autograd_function_and_gradcheck():
                                     eps=1e-2, atol=2e-3, rtol=1e-2)
 
 
-def test_config5_full_size_gradient():
+def test_hea20_l10_full_size_gradient():
     """20-qubit HEA, 10 layers, 400 angles, 1024 trajectories on the GPU; the FP64
     adjoint gradient of trajectory 0 alone (weight 1) is the reference."""
     torch, dev = torch_dev()
     import paper_2604_08467_amd as P
-    wl = W.config5()
+    wl = W.hea20_l10()
     c = wl.circuit
-    theta = W.config5_angles().astype(np.float64)
+    theta = W.hea20_angles().astype(np.float64)
     gp, ga = W.rotation_spec(c)
     terms = W.zz_chain_terms(20)
     plan = P.Plan(c, [20])
     kr, mult, _, _ = plan.sample_trajectories(wl.pts_seed, wl.n_traj)
-    _say(f"config5: {len(kr)} trajectories")
+    _say(f"hea20_l10: {len(kr)} trajectories")
     spec = P.GradSpec(400, gp, ga, terms, checkpoint_every=24)
     kd = to_dev(torch, dev, kr)
     w = mult / mult.sum()
@@ -102,7 +102,7 @@ def test_config5_full_size_gradient():
     t = time.perf_counter()
     out = plan.expect_grad(spec, kd, to_dev(torch, dev, w), to_dev(torch, dev, theta))
     torch.cuda.synchronize()
-    _say(f"config5: value {out['value'].item():.6f}, forward+adjoint {time.perf_counter() - t:.2f} s")
+    _say(f"hea20_l10: value {out['value'].item():.6f}, forward+adjoint {time.perf_counter() - t:.2f} s")
     g_all = out["grad"].cpu().numpy()
     assert np.all(np.isfinite(g_all))
     # trajectory 0 alone
@@ -113,6 +113,6 @@ def test_config5_full_size_gradient():
     g_ref = gr.adjoint_gradient(c, kr[:1], np.ones(1), theta, gp, ga, terms)
     f_ref = gr.value(c, kr[:1], np.ones(1), theta, gp, ga, terms)
     rel = np.linalg.norm(g1 - g_ref) / np.linalg.norm(g_ref)
-    _say(f"config5 trajectory 0: f {out1['value'].item():.6f} ref {f_ref:.6f}, grad rel-L2 {rel:.3g}")
+    _say(f"hea20_l10 trajectory 0: f {out1['value'].item():.6f} ref {f_ref:.6f}, grad rel-L2 {rel:.3g}")
     assert abs(out1["value"].item() - f_ref) <= 1e-4 * max(1.0, abs(f_ref))
     assert rel <= 1e-4

@@ -43,11 +43,11 @@ METHODS = ["network", "statevector"]
 
 # ------------------------------------------------------------------ config 1
 @pytest.mark.parametrize("method", METHODS)
-def test_config1_amplitudes_populations_and_weights(method):
+def test_chain10_d8_amplitudes_populations_and_weights(method):
     torch, dev = torch_dev()
-    wl = W.config1()
+    wl = W.chain10_d8()
     c = wl.circuit
-    _say(f"config1 ({method}): plan + PTS")
+    _say(f"chain10_d8 ({method}): plan + PTS")
     plan = _plan(c, wl.batch_sizes, method=method)
     assert plan.method == method
     kr, mult, lq, nd = plan.sample_trajectories(wl.pts_seed, wl.n_traj)
@@ -64,13 +64,13 @@ def test_config1_amplitudes_populations_and_weights(method):
         assert np.abs(pop[i] - pref).max() <= 1e-6, i
         Z = np.vdot(ref, ref).real
         assert abs(tot[i] - Z) <= 1e-6 * Z
-    _say("config1: amplitudes/populations ok")
+    _say("chain10_d8: amplitudes/populations ok")
 
 
 @pytest.mark.parametrize("method", METHODS)
-def test_config1_shots_match_oracle_sampler(method):
+def test_chain10_d8_shots_match_oracle_sampler(method):
     torch, dev = torch_dev()
-    wl = W.config1()
+    wl = W.chain10_d8()
     c = wl.circuit
     plan = _plan(c, wl.batch_sizes, method=method)
     kr, mult, lq, nd = plan.sample_trajectories(wl.pts_seed, wl.n_traj)
@@ -91,7 +91,7 @@ def test_config1_shots_match_oracle_sampler(method):
         got = shots[i * m:(i + 1) * m]
         mism += sum(1 for a, b in zip(got, ref[i]) if a != b)
         expect += m * flip_probability(pop[i], np.abs(psis[i]) ** 2)
-    _say(f"config1 ({method}) shots: {mism} mismatches of {E * m}, expected flips {expect:.3g}")
+    _say(f"chain10_d8 ({method}) shots: {mism} mismatches of {E * m}, expected flips {expect:.3g}")
     assert_shot_parity(mism, expect, E * m)
     # weights: W_i = mult_i Z_i / sum mult Z (Pauli noise: Z_i = 1 up to gate rounding)
     Z = np.array([np.vdot(p, p).real for p in psis])
@@ -102,10 +102,10 @@ def test_config1_shots_match_oracle_sampler(method):
 
 
 @pytest.mark.parametrize("method", METHODS)
-def test_config1_pooled_shots_tvd(method):
+def test_chain10_d8_pooled_shots_tvd(method):
     """Pooled shots vs the weighted mean of the per-trajectory oracle distributions."""
     torch, dev = torch_dev()
-    wl = W.config1()
+    wl = W.chain10_d8()
     c = wl.circuit
     plan = _plan(c, wl.batch_sizes, method=method)
     kr, mult, _, _ = plan.sample_trajectories(wl.pts_seed, wl.n_traj)
@@ -261,11 +261,11 @@ def test_small_multibatch_shots(case, method):
 
 
 # ------------------------------------------------------------------ config 2
-def test_config2_sampled_marginals_vs_tensor_network_oracle():
+def test_brickwork50_d6_sampled_marginals_vs_tensor_network_oracle():
     torch, dev = torch_dev()
-    wl = W.config2()
+    wl = W.brickwork50_d6()
     c = wl.circuit
-    _say("config2: plan + PTS(64)")
+    _say("brickwork50_d6: plan + PTS(64)")
     plan = _plan(c, wl.batch_sizes)
     kr, mult, _, _ = plan.sample_trajectories(wl.pts_seed, 64)
     kd = to_dev(torch, dev, kr)
@@ -283,20 +283,20 @@ def test_config2_sampled_marginals_vs_tensor_network_oracle():
         if kind == "ket":
             amp, _ = _contract(plan, torch, dev, kd, [i], [p], j, amp=True)
             rel = np.linalg.norm(amp[0] - ref) / np.linalg.norm(ref)
-            _say(f"config2 j={j} traj={i}: amplitude rel err {rel:.3g}")
+            _say(f"brickwork50_d6 j={j} traj={i}: amplitude rel err {rel:.3g}")
             assert rel <= 1e-5
             ref = np.abs(ref) ** 2
         pop, tot = _contract(plan, torch, dev, kd, [i], [p], j)
         Z = ref.sum()
         err = np.abs(pop[0] / tot[0] - ref / Z).max()
-        _say(f"config2 j={j} traj={i}: conditional max abs err {err:.3g}, Z rel {abs(tot[0] - Z) / Z:.3g}")
+        _say(f"brickwork50_d6 j={j} traj={i}: conditional max abs err {err:.3g}, Z rel {abs(tot[0] - Z) / Z:.3g}")
         assert err <= 1e-6
         assert abs(tot[0] - Z) <= 1e-5 * Z
 
 
-def test_config2_shots_of_one_trajectory_vs_oracle():
+def test_brickwork50_d6_shots_of_one_trajectory_vs_oracle():
     torch, dev = torch_dev()
-    wl = W.config2()
+    wl = W.brickwork50_d6()
     c = wl.circuit
     plan = _plan(c, wl.batch_sizes)
     kr, mult, _, _ = plan.sample_trajectories(wl.pts_seed, 8)
@@ -314,15 +314,15 @@ def test_config2_shots_of_one_trajectory_vs_oracle():
     ref, _ = sampling.sample_trajectory(
         lambda j, p: np.abs(mfn(j, p)) ** 2 if j == 4 else mfn(j, p), i, 50, wl.batch_sizes, m, wl.shot_seed)
     mism = sum(1 for a, b in zip(got, ref) if a != b)
-    _say(f"config2 traj {i}: {mism} mismatches of {m}")
+    _say(f"brickwork50_d6 traj {i}: {mism} mismatches of {m}")
     assert mism <= 1
 
 
-def test_config2_full_size_properties():
+def test_brickwork50_d6_full_size_properties():
     """512 trajectories x 1000 shots at full circuit size: deterministic shots,
     unit Pauli norms, normalised weights, and the chain rule Z(child) = pi_parent(x)."""
     torch, dev = torch_dev()
-    wl = W.config2()
+    wl = W.brickwork50_d6()
     c = wl.circuit
     plan = _plan(c, wl.batch_sizes)
     kr, mult, _, _ = plan.sample_trajectories(wl.pts_seed, 512)
@@ -339,7 +339,7 @@ def test_config2_full_size_properties():
     w = o1["weights"].cpu().numpy()
     assert abs(w.sum() - 1) < 1e-12
     epb = list(o1["elements_per_batch"])
-    _say(f"config2 512x1000 elements per batch {epb}")
+    _say(f"brickwork50_d6 512x1000 elements per batch {epb}")
     assert epb[0] == E and all(epb[j] <= E * m for j in range(5))
     # chain rule on a few (parent, child) pairs
     shots = shots_to_ints(s1[:2000].cpu().numpy())
@@ -361,13 +361,13 @@ def test_config2_full_size_properties():
 
 # ------------------------------------------------------- split precision (BF16)
 @pytest.mark.parametrize("prec", [1, 2], ids=["bf16", "f16"])
-def test_config2_split_bf16_error_vs_fp64(prec):
+def test_brickwork50_d6_split_bf16_error_vs_fp64(prec):
     """The split-precision join (bf16, or fp16 with power-of-two scaling) against
     the FP64 explicit-network oracle on sampled elements, and against the complex64
     path on every element of a batch.  The error is stated (printed); the bound
     checked is a sanity bound."""
     torch, dev = torch_dev()
-    wl = W.config2()
+    wl = W.brickwork50_d6()
     c = wl.circuit
     plan64 = _plan(c, wl.batch_sizes)
     plan16 = _plan(c, wl.batch_sizes, precision=prec)

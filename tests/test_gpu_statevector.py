@@ -147,7 +147,7 @@ def test_grid25_against_stored_oracle_values():
     import paper_2604_08467_amd as P
     with open(GOLDEN) as f:
         gold = json.load(f)
-    wl = W.config3(tuple(gold["batch_sizes"]))
+    wl = W.grid5x5_d8(tuple(gold["batch_sizes"]))
     c = wl.circuit
     plan = P.Plan(c, wl.batch_sizes)
     assert plan.method == "statevector"
@@ -180,7 +180,7 @@ def test_grid25_full_size_properties():
     self-normalised weights, per-element totals consistent with contract_batch."""
     torch, dev = torch_dev()
     import paper_2604_08467_amd as P
-    wl = W.config3((10, 10, 5))
+    wl = W.grid5x5_d8((10, 10, 5))
     plan = P.Plan(wl.circuit, wl.batch_sizes)
     kr, mult, _, _ = plan.sample_trajectories(wl.pts_seed, 2048)
     E, m = len(kr), wl.shots_per_traj

@@ -30,7 +30,7 @@ def test_library_exports_every_declared_symbol():
         assert ctypes.cast(getattr(lib, n), ctypes.c_void_p).value
 
 
-@pytest.mark.parametrize("make", [W.config1, W.config2])
+@pytest.mark.parametrize("make", [W.chain10_d8, W.brickwork50_d6])
 def test_host_plan_shapes(make):
     P = _lib()
     wl = make()
@@ -55,13 +55,13 @@ def test_host_plan_shapes(make):
         assert bi["left_rank"] == bi["join_rows_log2"] + bi["crossing"]
 
 
-def test_config2_path_is_the_expected_sweep():
+def test_brickwork50_d6_path_is_the_expected_sweep():
     """1D depth-6 brickwork: five wires cross between the prefix part and the rest,
     the per-trajectory tensor is 2^9 x 2^5 x 2^5 and the join, evaluated as a real
     bilinear form over K^2 = 1024 folded slots, costs 2.10 MFLOP per element (the
     plain complex product would cost 8.52)."""
     P = _lib()
-    wl = W.config2()
+    wl = W.brickwork50_d6()
     plan = P.Plan(wl.circuit, wl.batch_sizes, hypersamples=4, device=-1)
     for j in (1, 2, 3):
         bi = plan.batch_info(j)
@@ -69,13 +69,13 @@ def test_config2_path_is_the_expected_sweep():
         assert bi["join_flops_per_elem"] == 2 * 512 * 2 * 32 * 32
 
 
-@pytest.mark.parametrize("which", ["config1", "config2", "ad_2q", "exhaust"])
+@pytest.mark.parametrize("which", ["chain10_d8", "brickwork50_d6", "ad_2q", "exhaust"])
 def test_host_pts_equals_oracle(which):
     P = _lib()
-    if which == "config1":
-        c, seed, n = W.config1().circuit, 1002, 64
-    elif which == "config2":
-        c, seed, n = W.config2().circuit, 2002, 300
+    if which == "chain10_d8":
+        c, seed, n = W.chain10_d8().circuit, 1002, 64
+    elif which == "brickwork50_d6":
+        c, seed, n = W.brickwork50_d6().circuit, 2002, 300
     elif which == "ad_2q":
         rng = np.random.default_rng(5)
         c = W.small_random_circuit(5, 12, rng, [W.depolarizing(0.2), W.amplitude_damping(0.3), W.depolarizing2(0.1)])
@@ -99,7 +99,7 @@ def test_host_pts_equals_oracle(which):
 
 def test_pts_max_draws_limit():
     P = _lib()
-    c = W.config1().circuit
+    c = W.chain10_d8().circuit
     plan = P.Plan(c, [10], device=-1)
     kr, mult, lq, nd = plan.sample_trajectories(1002, 64, max_draws=20)
     assert nd == 20 and mult.sum() == 20 and len(kr) <= 20
@@ -114,7 +114,7 @@ def _expect_status(code, fn):
 
 def test_error_codes():
     P = _lib()
-    c = W.config1().circuit
+    c = W.chain10_d8().circuit
     _expect_status(1, lambda: P.Plan(c, [5, 4], device=-1))          # sizes do not sum to n
     _expect_status(1, lambda: P.Plan(c, [0, 10], device=-1))
     big = W.Circuit(40)
@@ -147,7 +147,7 @@ def test_method_selection():
     """auto: statevector for n <= 20 or when the network sweep does not fit (n <= 30);
     network otherwise.  Forced methods fail with UNSUPPORTED where they cannot run."""
     P = _lib()
-    wl1, wl2, wl3 = W.config1(), W.config2(), W.config3((10, 10, 5))
+    wl1, wl2, wl3 = W.chain10_d8(), W.brickwork50_d6(), W.grid5x5_d8((10, 10, 5))
     assert P.Plan(wl1.circuit, wl1.batch_sizes, device=-1).method == "statevector"
     assert P.Plan(wl1.circuit, wl1.batch_sizes, device=-1, method="network").method == "network"
     assert P.Plan(wl2.circuit, wl2.batch_sizes, device=-1).method == "network"
@@ -168,7 +168,7 @@ def test_method_selection():
 def test_statevector_windows_cover_small_circuits_in_one_launch():
     """A circuit on at most 12 qubits is one LDS window: the whole state stays on chip."""
     P = _lib()
-    wl1 = W.config1()
+    wl1 = W.chain10_d8()
     assert P.Plan(wl1.circuit, wl1.batch_sizes, device=-1).sv_windows == 1
     c = W.sqrt_grid(4, 4, 8, np.random.default_rng(0))
     p = P.Plan(c, [6, 6, 4], device=-1)
@@ -181,7 +181,7 @@ def test_statevector_schedule_only_reorders_commuting_gates(window):
     most `window` qubits (qubits 0..3 always held); a gate moves ahead of another
     only if they share no qubit (so the product of gates is unchanged)."""
     P = _lib()
-    cases = [W.config3().circuit, W.sqrt_grid(4, 4, 8, np.random.default_rng(0)),
+    cases = [W.grid5x5_d8().circuit, W.sqrt_grid(4, 4, 8, np.random.default_rng(0)),
              W.random_brickwork(20, 6, np.random.default_rng(1), 0.01, layout="2d"),
              W.small_random_circuit(15, 60, np.random.default_rng(2), [W.depolarizing(0.1)])]
     for c in cases:
@@ -228,7 +228,7 @@ def test_right_sites_of_the_brickwork_batches():
     """The sites entering a batch's per-trajectory part are sorted, in range, and on
     the 1D brickwork shrink from batch to batch (the traced region moves right)."""
     P = _lib()
-    wl = W.config2()
+    wl = W.brickwork50_d6()
     plan = P.Plan(wl.circuit, wl.batch_sizes, hypersamples=4, device=-1)
     S = len(wl.circuit.site_gate)
     prev = None
@@ -272,7 +272,7 @@ def test_gemv_join_tiling_covers_each_x_once(bs):
     own output offset, reads are contiguous over the 6 lowest T offsets and writes over
     the lowest output offsets."""
     P = _lib()
-    wl = W.config2() if sum(bs) == 50 else None
+    wl = W.brickwork50_d6() if sum(bs) == 50 else None
     circ = wl.circuit if wl else W.random_brickwork(sum(bs), 4, np.random.default_rng(311), 0.02)
     plan = P.Plan(circ, bs, hypersamples=8, device=-1, method="network")
     j = len(bs) - 1

@@ -299,7 +299,7 @@ def test_philox_uniform_chi_square_and_streams():
 
 
 def test_pts_properties():
-    c = W.config1().circuit
+    c = W.chain10_d8().circuit
     kr, mult, logq, nd = pts.presample(c, seed=1002, n_unique=64)
     assert kr.shape == (64, 72)
     assert len({r.tobytes() for r in kr}) == 64

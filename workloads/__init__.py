@@ -19,7 +19,9 @@ Conventions (shared by every consumer):
   proposal is ``tr(K^dag K)/d``.
 
 The workload recipes follow the paper's random-circuit family (Sec. IV-B) at the
-sizes of the five benchmark configurations documented in the design doc.
+sizes of the five benchmark configurations: a 10-qubit chain, a 50-qubit chain, a
+5x5 grid with amplitude damping, a ragged mix of 256 circuits and a 20-qubit
+rotation-layer circuit for gradients.
 """
 from __future__ import annotations
 
@@ -30,8 +32,8 @@ import numpy as np
 
 __all__ = [
     "Channel", "Circuit", "Workload", "haar_su4", "depolarizing", "amplitude_damping",
-    "pauli_x", "pauli_y", "pauli_z", "brickwork_1d", "config1", "config2", "config3",
-    "config5", "random_brickwork", "small_random_circuit", "grid_layers", "hea", "rotation_spec",
+    "pauli_x", "pauli_y", "pauli_z", "brickwork_1d", "chain10_d8", "brickwork50_d6", "grid5x5_d8",
+    "hea20_l10", "random_brickwork", "small_random_circuit", "grid_layers", "hea", "rotation_spec",
     "zz_chain_terms",
 ]
 
@@ -264,23 +266,23 @@ def small_random_circuit(n: int, n_gates: int, rng: np.random.Generator,
     return c
 
 
-# ----------------------------------------------------------------------- configs
-def config1() -> Workload:
+# ------------------------------------------------------------- benchmark workloads
+def chain10_d8() -> Workload:
     """10-qubit open chain, 8 brickwork layers of Haar SU(4) (complex64-rounded),
     depolarising p=0.01 on both qubits after each gate, 64 unique trajectories x
     100 shots, one batch of 10 qubits."""
     rng = np.random.default_rng(1001)
     c = random_brickwork(10, 8, rng, 0.01).round_to_complex64()
-    return Workload("config1_n10_d8", c, 64, 100, [10], pts_seed=1002, shot_seed=1003)
+    return Workload("chain10_d8", c, 64, 100, [10], pts_seed=1002, shot_seed=1003)
 
 
-def config2() -> Workload:
+def brickwork50_d6() -> Workload:
     """50-qubit open chain, 6 brickwork layers of Haar SU(4) (complex64-rounded),
     depolarising p=0.005 per qubit after each gate, 4096 unique trajectories x
     1000 shots, batches of 10 qubits."""
     rng = np.random.default_rng(2001)
     c = random_brickwork(50, 6, rng, 0.005).round_to_complex64()
-    return Workload("config2_n50_d6", c, 4096, 1000, [10] * 5, pts_seed=2002, shot_seed=2003)
+    return Workload("brickwork50_d6", c, 4096, 1000, [10] * 5, pts_seed=2002, shot_seed=2003)
 
 
 def sqrt_grid(rows: int, cols: int, cycles: int, rng: np.random.Generator, p: float = 0.01,
@@ -308,12 +310,12 @@ def sqrt_grid(rows: int, cols: int, cycles: int, rng: np.random.Generator, p: fl
     return c
 
 
-def config3(batch_sizes=(25,)) -> Workload:
+def grid5x5_d8(batch_sizes=(25,)) -> Workload:
     """5x5 grid, 8 cycles of sqrt_grid (depolarising 0.01 + amplitude damping
     0.02); 16384 unique trajectories x 256 shots."""
     rng = np.random.default_rng(3001)
     c = sqrt_grid(5, 5, 8, rng)
-    return Workload("config3_grid5x5_d8", c, 16384, 256, list(batch_sizes), pts_seed=3002, shot_seed=3003)
+    return Workload("grid5x5_d8", c, 16384, 256, list(batch_sizes), pts_seed=3002, shot_seed=3003)
 
 
 def hea(n: int, layers: int, angles: np.ndarray, noise: Sequence[Channel]) -> Circuit:
@@ -360,22 +362,22 @@ def zz_chain_terms(n: int):
     return [((q, q + 1), 1.0) for q in range(n - 1)]
 
 
-def config5_angles() -> np.ndarray:
+def hea20_angles() -> np.ndarray:
     rng = np.random.default_rng(5005)
     return rng.uniform(0.0, 2 * np.pi, size=400).astype(np.float32)
 
 
-def config5(angles: Optional[np.ndarray] = None) -> Workload:
+def hea20_l10(angles: Optional[np.ndarray] = None) -> Workload:
     """20-qubit hardware-efficient ansatz: 10 layers of RY on all, RZ on all, CNOT
     ladder 0->1 ... 18->19; depolarising p=0.01 after each gate on each touched
     qubit; 1024 trajectories.  Angle k of layer L: RY uses 40L + q, RZ 40L + 20 + q."""
     if angles is None:
-        angles = config5_angles()
+        angles = hea20_angles()
     c = hea(20, 10, angles, [depolarizing(0.01)])
-    return Workload("config5_hea_n20", c, 1024, 0, [20], pts_seed=5002, shot_seed=5003)
+    return Workload("hea20_l10", c, 1024, 0, [20], pts_seed=5002, shot_seed=5003)
 
 
-def config4(n_circuits: int = 256, seed: int = 4001):
+def ragged_mix(n_circuits: int = 256, seed: int = 4001):
     """Ragged mix: n ~ U{12..40}, depth ~ U{4..10}, 1D or 2D brickwork (p = 1/2)
     of Haar SU(4) with depolarising p=0.005 after every gate, E_c =
     round(exp(U[ln 32, ln 2048])) unique trajectories and 100 shots each,
