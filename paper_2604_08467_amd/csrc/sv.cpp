@@ -442,21 +442,27 @@ ptsbe_status_t sv_sample_nonproportional(Plan& p, const uint8_t* d_kraus, int64_
       if (last && final_draws == 0) {   // exhaustive final batch
         HIP_TRY(launch_row_totals(L.pop, U, bp.size, L.totals, s));
         if (j == 0) HIP_TRY(hipMemcpyAsync(L.norms + t0, L.totals, (size_t)nj * 8, hipMemcpyDeviceToDevice, s));
-        ExhArgs a{};
-        a.pop = L.pop; a.b = bp.size; a.start = bp.start; a.NW = p.NW;
-        a.n_elems = U; a.elem_traj = L.traj[cur]; a.elem_prefix = L.prefix[cur];
-        a.elem_total = L.totals; a.traj_norm = f > 1 ? L.norms : nullptr;
-        a.threshold = threshold;
-        a.tile_cnt = L.tile_cnt; a.tile_off = L.tile_off; a.tile_bits = 0;   // b <= 12: one tile per element
-        a.row_base = rows; a.capacity = capacity;
-        a.bits = d_bits; a.row_traj = d_row_traj; a.p_cond = d_p_cond; a.p_prefix = d_p_prefix;
-        HIP_TRY(launch_exh_count(a, s));
-        HIP_TRY(launch_scan_i32(L.tile_cnt, L.tile_off, U, L.exh_total, L.exh_scan, s));
-        int32_t found = 0;
-        HIP_TRY(hipMemcpyAsync(&found, L.exh_total, 4, hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
-        if (found > 0 && rows < capacity) HIP_TRY(launch_exh_write(a, s));
-        rows += found;
+        // element ranges whose rows stay below 2^31 (the row scan is int32)
+        const int64_t X = (int64_t)1 << bp.size;
+        const int64_t sub = std::max<int64_t>(1, (((int64_t)1 << 31) - 1) / X);
+        for (int64_t a0 = 0; a0 < U; a0 += sub) {
+          const int64_t ne = std::min<int64_t>(sub, U - a0);
+          ExhArgs a{};
+          a.pop = L.pop + a0 * X; a.b = bp.size; a.start = bp.start; a.NW = p.NW;
+          a.n_elems = ne; a.elem_traj = L.traj[cur] + a0; a.elem_prefix = L.prefix[cur] + a0 * p.NW;
+          a.elem_total = L.totals + a0; a.traj_norm = f > 1 ? L.norms : nullptr;
+          a.threshold = threshold;
+          a.tile_cnt = L.tile_cnt; a.tile_off = L.tile_off; a.tile_bits = 0;   // b <= 12: one tile per element
+          a.row_base = rows; a.capacity = capacity;
+          a.bits = d_bits; a.row_traj = d_row_traj; a.p_cond = d_p_cond; a.p_prefix = d_p_prefix;
+          HIP_TRY(launch_exh_count(a, s));
+          HIP_TRY(launch_scan_i32(L.tile_cnt, L.tile_off, ne, L.exh_total, L.exh_scan, s));
+          int32_t found = 0;
+          HIP_TRY(hipMemcpyAsync(&found, L.exh_total, 4, hipMemcpyDeviceToHost, s));
+          HIP_TRY(hipStreamSynchronize(s));
+          if (found > 0 && rows < capacity) HIP_TRY(launch_exh_write(a, s));
+          rows += found;
+        }
         break;
       }
       const int32_t Rj = last ? final_draws : draws;
