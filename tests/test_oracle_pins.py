@@ -502,6 +502,9 @@ def test_nonproportional_children_bound_and_zero_weight():
         assert counts[1] <= min(k, 8) and counts[2] <= counts[1] * min(k, 4)
     zero = lambda j, prefix: np.zeros(2 ** bs[j])
     assert sampling.nonproportional_trajectory(zero, 0, n, bs, 4, 13, -1.0)[0] == []
+    # direct final draws from a zero-weight trajectory: x = 0 rows with P = p(prefix) = 0
+    rows, counts = sampling.nonproportional_trajectory(zero, 0, n, bs, 4, 13, 0.0, final_draws=3)
+    assert counts == [1, 1, 1] and rows == [(0, 0.0, 0.0)] * 3
 
 
 def test_nonproportional_direct_final_batch():
