@@ -5,7 +5,9 @@ marshals arguments.  PyTorch provides device memory and the stream.
 
     plan = Plan(circuit, batch_sizes=[10] * 5)
     kraus, mult, log_q, n_draws = plan.sample_trajectories(seed, n_unique)
-    out = plan.sample_shots(kraus_dev, shots_per_traj_dev, seed=...)
+    out = plan.sample_shots(kraus_dev, shots_per_traj_dev, seed=...)          # proportional NBS
+    rows = plan.sample_nonproportional(kraus_dev, draws=1, seed=..., threshold=1e-6)   # exhaustive
+    rows = plan.sample_nonproportional(kraus_dev, draws=1, seed=..., final_draws=100)  # direct
 """
 import ctypes as C
 
