@@ -290,6 +290,7 @@ def test_gemv_join_tiling_covers_each_x_once(bs):
     assert sorted(g["w_of"]) == list(range(12))
     assert all(g["o_write"][g["w_of"][s]] == g["o_read"][s] for s in range(12))
     assert list(g["t_read"][:6]) == sorted(x_t)[:6]          # contiguous read runs
+    assert set(sorted(x_o)[:6]) <= set(int(v) for v in g["o_write"])   # contiguous write runs
     # every x is read once and written once (small tilings replayed in full)
     if nx <= 16:
         t2x = {}
