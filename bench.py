@@ -27,36 +27,114 @@ SWEEP_KERNEL_TAG = "absorb_global_kernel<NK> single HBM sweep steps, 4 kept indi
 JOIN_KERNEL_TAG = "qform_mfma_kernel<32,8> bilinear slots"
 
 
-def cpu_baseline(wl, kr, budget_s=20.0):
-    """The FP64 oracle, as it stands, on a bounded sample: per-shot batch-wise
-    sampling of trajectory 0 with memoised explicit-network marginals."""
+def _oracle_shots_worker(circuit, kraus_row, traj, batch_sizes, seed, budget_s):
+    """One worker of the CPU baseline: per-shot batch-wise sampling of one
+    trajectory with memoised explicit-network FP64 marginals, until budget_s."""
     import numpy as np
     from threadpoolctl import threadpool_limits
 
     from oracle import sampling, tn
 
-    c = wl.circuit
-    starts = sampling.batch_starts(wl.batch_sizes)
-    f = len(wl.batch_sizes)
+    starts = sampling.batch_starts(batch_sizes)
+    f = len(batch_sizes)
+
+    memo = {}    # marginals persist across calls: the call for m shots contracts only what shot m - 1 adds
 
     def mfn(j, p):
-        kind = "ket" if j == f - 1 else "doubled"
-        v = tn.batch_network_value(c, kr[0], starts[j], wl.batch_sizes[j], p, kind)
-        return np.abs(v) ** 2 if kind == "ket" else v
+        if (j, p) not in memo:
+            kind = "ket" if j == f - 1 else "doubled"
+            v = tn.batch_network_value(circuit, kraus_row, starts[j], batch_sizes[j], p, kind)
+            memo[(j, p)] = np.abs(v) ** 2 if kind == "ket" else v
+        return memo[(j, p)]
 
-    shots = 0
+    m = 0
     t0 = time.perf_counter()
     with threadpool_limits(limits=1):
-        m = 1
-        while True:
-            sampling.sample_trajectory(mfn, 0, c.n_qubits, wl.batch_sizes, m, wl.shot_seed)
-            shots += m
-            if time.perf_counter() - t0 > budget_s:
-                break
+        while time.perf_counter() - t0 < budget_s:
+            m += 1
+            sampling.sample_trajectory(mfn, traj, circuit.n_qubits, batch_sizes, m, seed)
+    return m, time.perf_counter() - t0
+
+
+def _oracle_value_worker(circuit, kraus_row, start, b, prefix, kind):
+    from threadpoolctl import threadpool_limits
+
+    from oracle import tn
+    with threadpool_limits(limits=1):
+        return tn.batch_network_value(circuit, kraus_row, start, b, prefix, kind)
+
+
+def _pool(n):
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    return cf.ProcessPoolExecutor(max_workers=n, mp_context=mp.get_context("spawn"))
+
+
+def host_cores():
+    return max(1, len(os.sched_getaffinity(0)))
+
+
+def cpu_baseline(wl, kr, budget_s=20.0):
+    """The FP64 oracle, as it stands, on a bounded sample, one worker process per
+    host core: worker w samples shots of trajectory w (per-shot batch-wise
+    sampling with memoised explicit-network marginals) for budget_s seconds."""
+    n = min(host_cores(), len(kr))
+    t0 = time.perf_counter()
+    with _pool(n) as pool:
+        futs = [pool.submit(_oracle_shots_worker, wl.circuit, kr[w], w, wl.batch_sizes, wl.shot_seed, budget_s)
+                for w in range(n)]
+        res = [f.result() for f in futs]
     dt = time.perf_counter() - t0
-    return {"value": shots / dt, "unit": "shots/s", "cores": 1, "kind": "oracle",
-            "sample": f"{shots} shot(s) of trajectory 0 (per-shot batch-wise sampling, explicit FP64 "
-                      f"networks, {dt:.1f} s, one thread)"}
+    shots = sum(r[0] for r in res)
+    return {"value": shots / dt, "unit": "shots/s", "cores": n, "kind": "oracle",
+            "sample": f"{shots} shots of trajectories 0..{n - 1} (one worker process per core, per-shot "
+                      f"batch-wise sampling with memoised explicit FP64 networks, {dt:.1f} s wall)"}
+
+
+def error_vs_fp64(plan, wl, kr, kd, shots_dev, n_pick=8):
+    """The run's own error against FP64: conditionals P(x | prefix) of the elements
+    that n_pick of the step's shots passed through (every batch), from the GPU path
+    (ptsbe_contract_batch on the same plan) and from the explicit FP64 network."""
+    import numpy as np
+    import torch
+
+    import paper_2604_08467_amd as P
+    from oracle import sampling
+
+    c = wl.circuit
+    bs = wl.batch_sizes
+    starts = sampling.batch_starts(bs)
+    f = len(bs)
+    m = shots_dev.shape[0] // len(kr)
+    rows = [int(r) for r in np.linspace(0, shots_dev.shape[0] - 1, n_pick).astype(np.int64)]
+    sh = shots_dev[rows].cpu().numpy().view(np.uint64)
+    picks = []
+    for k, r in enumerate(rows):
+        v = sum(int(sh[k, w]) << (64 * w) for w in range(sh.shape[1]))
+        for j in range(f):
+            picks.append((r // m, j, v & ((1 << starts[j]) - 1)))
+    dev = kd.device
+    with _pool(min(host_cores(), len(picks))) as pool:
+        futs = [pool.submit(_oracle_value_worker, c, kr[t], starts[j], bs[j], p, "ket" if j == f - 1 else "doubled")
+                for (t, j, p) in picks]
+        gpu = []
+        for (t, j, p) in picks:
+            et = torch.tensor([t], dtype=torch.int32, device=dev)
+            pw = np.array([[(p >> (64 * w)) & 0xFFFFFFFFFFFFFFFF for w in range(plan.n_words)]], dtype=np.uint64)
+            ep = torch.from_numpy(pw.view(np.int64)).to(dev)
+            pop, tot = plan.contract_batch(j, kd, et, ep, P.OUT_POPULATION)
+            gpu.append((pop[0].double().cpu().numpy(), float(tot[0].item())))
+        refs = [fu.result() for fu in futs]
+    worst = {"doubled": 0.0, "ket": 0.0}
+    for (t, j, p), (g, gt), ref in zip(picks, gpu, refs):
+        kind = "ket" if j == f - 1 else "doubled"
+        pr = np.abs(ref) ** 2 if kind == "ket" else np.asarray(ref)
+        worst[kind] = max(worst[kind], float(np.abs(g / gt - pr / pr.sum()).max()))
+    return {"max_abs_conditional_error": max(worst.values()),
+            "doubled_batches": worst["doubled"], "last_batch": worst["ket"],
+            "elements": len(picks), "reference": "explicit FP64 network of each element (oracle), "
+                                                 "same complex64-rounded gates",
+            "sample": f"the prefixes of {n_pick} of the step's shots, spread over its trajectories, at every batch"}
 
 
 def main():
@@ -176,6 +254,9 @@ def main():
         "roofline": roofline,
     }
     if not args.no_cpu_baseline:
+        print("bench: error vs FP64 on sampled elements", file=sys.stderr, flush=True)
+        line["error_vs_fp64"] = error_vs_fp64(plan, wl, kr, kd, out["shots"])
+        print("bench: CPU oracle baseline", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(wl, kr)
     print(json.dumps(line), flush=True)
 

@@ -234,6 +234,19 @@ ptsbe_status_t ptsbe_contract_workspace_size(ptsbe_plan_t plan, int32_t j, int64
 ptsbe_status_t ptsbe_sample_workspace_size(ptsbe_plan_t plan, int64_t E, int64_t total_shots,
                                            size_t* bytes);
 
+/* Trajectory chunking of a network-method plan (host only, no device work): the
+ * per-trajectory tensors of a batch are built for a chunk of trajectories at a
+ * time, the chunk sized so that they take at most half of the workspace left
+ * after the call's persistent arrays.  For call 0 (ptsbe_contract_batch with E
+ * trajectories and count elements) or call 1 (ptsbe_sample_shots with E
+ * trajectories and count shots in total) and workspace_bytes of workspace,
+ * traj_per_chunk[j] (host, [n_batches], caller-owned) receives the number of
+ * trajectories per chunk at batch j, or 0 when not even one fits (the call
+ * would return PTSBE_ERR_OUT_OF_MEMORY).  Chunking never changes results.
+ * PTSBE_ERR_INVALID_ARG for a statevector-method plan or a bad call kind. */
+ptsbe_status_t ptsbe_plan_chunking(ptsbe_plan_t plan, int32_t call, int64_t E, int64_t count,
+                                   size_t workspace_bytes, int64_t* traj_per_chunk);
+
 /* Batch-wise contraction of batch j (Sec. II-B) for n_elems elements.
  *   d_kraus_idx   [E][n_sites] uint8 error sets (device)
  *   d_elem_traj   [n_elems] int32 trajectory of each element, non-decreasing

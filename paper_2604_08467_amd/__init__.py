@@ -201,6 +201,14 @@ class Plan:
         _lib.check(self._lib.ptsbe_sample_workspace_size(self._h, int(E), int(total_shots), C.byref(b)))
         return b.value
 
+    def chunking(self, call, E, count, workspace_bytes):
+        """ptsbe_plan_chunking: trajectories per chunk at every batch for a workspace of
+        workspace_bytes; call "contract" (count = elements) or "sample" (count = shots)."""
+        out = np.zeros(len(self.batch_sizes), dtype=np.int64)
+        _lib.check(self._lib.ptsbe_plan_chunking(self._h, {"contract": 0, "sample": 1}[call], int(E), int(count),
+                                                 int(workspace_bytes), out.ctypes.data_as(C.c_void_p)))
+        return out
+
     def contract_batch(self, j, kraus_dev, elem_traj_dev, elem_prefix_dev, out_kind=OUT_POPULATION,
                        workspace=None, stream=None):
         """ptsbe_contract_batch on torch device tensors; returns (out, totals)."""

@@ -264,6 +264,35 @@ ptsbe_status_t exhaustive_chunk(const ptsbe::BatchPlan& bp, BatchIO& io, const f
   return PTSBE_OK;
 }
 
+// Bytes of the join's layout of one per-trajectory tensor: Theta (the doubled
+// join's folded slot coefficients) or the canonical copy of the MFMA ket join.
+size_t join_layout_bytes(const ptsbe::BatchPlan& bp) {
+  const int lkb = (int)bp.lk.size();
+  if (bp.doubled && ptsbe::qform_supported(lkb)) return ptsbe::qform_theta_bytes((int)bp.xT.size(), lkb);
+  if (!bp.doubled && ptsbe::ketjoin_supported(lkb)) return (size_t)8 << bp.right.labels.size();
+  return 0;
+}
+
+// Trajectories and elements per chunk of one batch when `avail` workspace bytes are
+// left: half for the per-trajectory tensors (with their join layout and sweep
+// scratch), half for the per-element tensors and populations.
+struct ChunkCaps { int64_t t_cap = 0, e_cap = 0; };
+ChunkCaps chunk_caps(const ptsbe::BatchPlan& bp, const ptsbe::PartPlan& left, int64_t E, bool own_V,
+                     bool chunk_pop, bool exh, size_t avail) {
+  const size_t per_traj = ((size_t)8 << bp.right.labels.size()) + join_layout_bytes(bp) +
+                          part_scratch_per_job(bp.right);
+  const int exh_tile_bits = bp.size > 12 ? bp.size - 12 : 0;
+  const size_t per_elem = (own_V ? ((size_t)8 << left.labels.size()) : 0) + part_scratch_per_job(left) +
+                          (chunk_pop ? ((size_t)4 << bp.size) : 0) + (exh ? 16 + ((size_t)12 << exh_tile_bits) : 0);
+  ChunkCaps c;
+  c.t_cap = (int64_t)std::min<size_t>((size_t)E, (avail / 2) / per_traj);
+  c.e_cap = (int64_t)((avail / 2) / per_elem);
+  c.e_cap = std::min<int64_t>(c.e_cap, 1 << 22);
+  if (exh) c.e_cap = std::min<int64_t>(c.e_cap, std::max<int64_t>(1, (((int64_t)1 << 31) - 1) >> bp.size));
+  c.t_cap = std::min<int64_t>(c.t_cap, 65535);   // one grid dimension of the MFMA join
+  return c;
+}
+
 ptsbe_status_t run_batch(Plan& p, int j, const uint8_t* d_kraus, const float2* merged, int64_t E, BatchIO& io,
                          Arena& ar, hipStream_t s, std::vector<EventPair>& evs) {
   const ptsbe::BatchPlan& bp = p.batches[j];
@@ -287,22 +316,14 @@ ptsbe_status_t run_batch(Plan& p, int j, const uint8_t* d_kraus, const float2* m
   const bool use_split = use_qform && p.precision != PTSBE_C64 && ptsbe::qform_split_supported(lkb);
   const int split_kind = !use_split ? 0 : (p.precision == PTSBE_SPLIT_F16 ? 2 : 1);
   const bool use_fold = use_qform;               // Theta layout (FP32, or bf16 hi + lo planes)
-  const size_t layout_bytes = use_fold ? ptsbe::qform_theta_bytes((int)bp.xT.size(), lkb)
-                                       : (use_mfma ? ((size_t)8 << rT) : 0);
-  const size_t per_traj = ((size_t)8 << rT) + layout_bytes + part_scratch_per_job(bp.right);
+  const size_t layout_bytes = join_layout_bytes(bp);
   const size_t nb = (size_t)1 << bp.size;
   const bool chunk_pop = io.sample || io.exh;     // populations live per element chunk
   const int exh_tile_bits = bp.size > 12 ? bp.size - 12 : 0;
-  const size_t per_elem = (io.V_out ? 0 : ((size_t)8 << rV)) + part_scratch_per_job(left) +
-                          (chunk_pop ? 4 * nb : 0) + (io.exh ? 16 + ((size_t)12 << exh_tile_bits) : 0);
-  const size_t avail = ar.left();
-  int64_t t_cap = (int64_t)std::min<size_t>((size_t)E, (avail / 2) / per_traj);
-  int64_t e_cap = (int64_t)((avail / 2) / per_elem);
-  if (t_cap < 1 || e_cap < 1)
+  const ChunkCaps caps = chunk_caps(bp, left, E, !io.V_out, chunk_pop, io.exh != nullptr, ar.left());
+  if (caps.t_cap < 1 || caps.e_cap < 1)
     return fail(PTSBE_ERR_OUT_OF_MEMORY, "workspace too small for one trajectory of batch " + std::to_string(j));
-  e_cap = std::min<int64_t>(e_cap, 1 << 22);
-  if (io.exh) e_cap = std::min<int64_t>(e_cap, std::max<int64_t>(1, (((int64_t)1 << 31) - 1) >> bp.size));
-  t_cap = std::min<int64_t>(t_cap, 65535);       // one grid dimension of the MFMA join
+  const int64_t t_cap = caps.t_cap, e_cap = caps.e_cap;
   const ptsbe::AbsorbStep* d_left = p.d_steps + p.part_step_off[3 * j + (io.resume ? 2 : 0)];
   const ptsbe::AbsorbStep* d_right = p.d_steps + p.part_step_off[3 * j + 1];
   const std::vector<int32_t> rsites = io.h_kraus ? right_sites(p, bp) : std::vector<int32_t>();
@@ -1048,6 +1069,51 @@ ptsbe_status_t ptsbe_contract_workspace_size(ptsbe_plan_t plan, int32_t j, int64
 }
 
 namespace {
+// Persistent arrays of ptsbe_sample_shots (network method), in the order they are
+// taken from the workspace: element and shot arrays of two generations, the left
+// tensors of every element (prefix-tree reuse), scan scratch, counters and the
+// merged gates.
+struct SampleLayout {
+  struct Elems { int32_t* traj; uint64_t* prefix; int32_t* off; int32_t* cnt; int32_t* ids; int32_t* parent; } el[2];
+  float2* Vbuf[2];
+  int32_t *shot_x, *child_cnt, *child_off, *scan_scratch, *counters;
+  double *totals, *norms;
+  int64_t* base;
+  float2* merged;
+};
+
+bool take_sample_layout(const Plan& p, int64_t E, int64_t M, Arena& ar, SampleLayout& L) {
+  const int64_t cap = std::max<int64_t>(E, M);
+  int rVmax = 0;
+  for (auto& bp : p.batches) rVmax = std::max<int>(rVmax, (int)bp.left_resume.labels.size());
+  for (int k = 0; k < 2; ++k) L.Vbuf[k] = (float2*)ar.take((size_t)cap * ((size_t)8 << rVmax));
+  for (int k = 0; k < 2; ++k) {
+    L.el[k].parent = (int32_t*)ar.take((size_t)cap * 4);
+    L.el[k].traj = (int32_t*)ar.take((size_t)cap * 4);
+    L.el[k].prefix = (uint64_t*)ar.take((size_t)cap * 8 * p.NW);
+    L.el[k].off = (int32_t*)ar.take((size_t)cap * 4);
+    L.el[k].cnt = (int32_t*)ar.take((size_t)cap * 4);
+    L.el[k].ids = (int32_t*)ar.take((size_t)std::max<int64_t>(M, 1) * 4);
+  }
+  L.shot_x = (int32_t*)ar.take((size_t)std::max<int64_t>(M, 1) * 4);
+  L.child_cnt = (int32_t*)ar.take((size_t)cap * 4);
+  L.child_off = (int32_t*)ar.take((size_t)cap * 4);
+  L.totals = (double*)ar.take((size_t)cap * 8);
+  L.base = (int64_t*)ar.take((size_t)E * 8);
+  L.norms = (double*)ar.take((size_t)E * 8);
+  L.scan_scratch = (int32_t*)ar.take(ptsbe::scan_scratch_bytes(cap));
+  L.counters = (int32_t*)ar.take(64);
+  L.merged = (float2*)ar.take(merged_bytes(p, E));
+  bool ok = L.shot_x && L.child_cnt && L.child_off && L.totals && L.base && L.norms && L.scan_scratch &&
+            L.counters && L.merged;
+  for (int k = 0; k < 2; ++k)
+    ok = ok && L.el[k].traj && L.el[k].prefix && L.el[k].off && L.el[k].cnt && L.el[k].ids && L.el[k].parent &&
+         L.Vbuf[k];
+  return ok;
+}
+}  // namespace
+
+namespace {
 size_t sample_persistent_bytes(const Plan& p, int64_t E, int64_t M) {
   const int64_t cap = std::max<int64_t>(E, M);
   size_t b = 0;
@@ -1093,6 +1159,34 @@ ptsbe_status_t ptsbe_sample_workspace_size(ptsbe_plan_t plan, int64_t E, int64_t
     chunk = std::max(chunk, 2 * (std::min<size_t>(E, 256) * per_traj + 65536 * per_elem));
   }
   *bytes = sample_persistent_bytes(*p, E, total_shots) + (size_t)(E + 1) * 4 + chunk + (1 << 20);
+  return PTSBE_OK;
+}
+
+ptsbe_status_t ptsbe_plan_chunking(ptsbe_plan_t plan, int32_t call, int64_t E, int64_t count,
+                                   size_t workspace_bytes, int64_t* traj_per_chunk) {
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  if (!p || !traj_per_chunk) return fail(PTSBE_ERR_INVALID_ARG, "null argument");
+  if (p->method != PTSBE_METHOD_NETWORK) return fail(PTSBE_ERR_INVALID_ARG, "chunking applies to network-method plans");
+  if (call != 0 && call != 1) return fail(PTSBE_ERR_INVALID_ARG, "call must be 0 (contract) or 1 (sample)");
+  if (E < 1 || count < 0) return fail(PTSBE_ERR_INVALID_ARG, "bad counts");
+  Arena probe;                       // an arena without memory measures the layout
+  probe.base = nullptr;
+  probe.cap = ~(size_t)0 >> 1;
+  if (call == 1) {
+    SampleLayout L;
+    take_sample_layout(*p, E, count, probe, L);
+  } else {
+    probe.take(merged_bytes(*p, E));
+  }
+  probe.take((size_t)(E + 1) * 4);   // trajectory ranges, taken first by every batch
+  const size_t off = (probe.used + 255) & ~(size_t)255;
+  const size_t avail = off >= workspace_bytes ? 0 : workspace_bytes - off;
+  for (size_t j = 0; j < p->batches.size(); ++j) {
+    const auto& bp = p->batches[j];
+    const bool resume = call == 1 && j >= 1;
+    const ChunkCaps c = chunk_caps(bp, resume ? bp.left_resume : bp.left, E, call == 0, call == 1, false, avail);
+    traj_per_chunk[j] = (c.t_cap < 1 || c.e_cap < 1) ? 0 : c.t_cap;
+  }
   return PTSBE_OK;
 }
 
@@ -1189,37 +1283,19 @@ ptsbe_status_t ptsbe_sample_shots(ptsbe_plan_t plan, const uint8_t* d_kraus_idx,
     M += m[i];
   }
   if (M >= ((int64_t)1 << 31)) return fail(PTSBE_ERR_UNSUPPORTED, "more than 2^31 shots");
-  const int64_t cap = std::max<int64_t>(E, M);
   Arena ar;
   ar.base = (char*)d_workspace;
   ar.cap = workspace_bytes;
-  struct Elems { int32_t* traj; uint64_t* prefix; int32_t* off; int32_t* cnt; int32_t* ids; int32_t* parent; } el[2];
-  // left tensors of every element are kept for one batch (prefix-tree reuse)
-  int rVmax = 0;
-  for (auto& bp : p->batches) rVmax = std::max<int>(rVmax, (int)bp.left_resume.labels.size());
-  float2* Vbuf[2];
-  for (int k = 0; k < 2; ++k) Vbuf[k] = (float2*)ar.take((size_t)cap * ((size_t)8 << rVmax));
-  for (int k = 0; k < 2; ++k) {
-    el[k].parent = (int32_t*)ar.take((size_t)cap * 4);
-    el[k].traj = (int32_t*)ar.take((size_t)cap * 4);
-    el[k].prefix = (uint64_t*)ar.take((size_t)cap * 8 * p->NW);
-    el[k].off = (int32_t*)ar.take((size_t)cap * 4);
-    el[k].cnt = (int32_t*)ar.take((size_t)cap * 4);
-    el[k].ids = (int32_t*)ar.take((size_t)std::max<int64_t>(M, 1) * 4);
-  }
-  int32_t* shot_x = (int32_t*)ar.take((size_t)std::max<int64_t>(M, 1) * 4);
-  int32_t* child_cnt = (int32_t*)ar.take((size_t)cap * 4);
-  int32_t* child_off = (int32_t*)ar.take((size_t)cap * 4);
-  double* totals = (double*)ar.take((size_t)cap * 8);
-  int64_t* d_base = (int64_t*)ar.take((size_t)E * 8);
-  double* norms = (double*)ar.take((size_t)E * 8);
-  int32_t* scan_scratch = (int32_t*)ar.take(ptsbe::scan_scratch_bytes(cap));
-  int32_t* counters = (int32_t*)ar.take(64);
-  float2* merged = (float2*)ar.take(merged_bytes(*p, E));
-  bool ok = shot_x && child_cnt && child_off && totals && d_base && norms && scan_scratch && counters && merged;
-  for (int k = 0; k < 2; ++k)
-    ok = ok && el[k].traj && el[k].prefix && el[k].off && el[k].cnt && el[k].ids && el[k].parent && Vbuf[k];
-  if (!ok) return fail(PTSBE_ERR_OUT_OF_MEMORY, "workspace too small for the shot and element arrays");
+  SampleLayout L;
+  if (!take_sample_layout(*p, E, M, ar, L))
+    return fail(PTSBE_ERR_OUT_OF_MEMORY, "workspace too small for the shot and element arrays");
+  auto& el = L.el;
+  float2** Vbuf = L.Vbuf;
+  int32_t *shot_x = L.shot_x, *child_cnt = L.child_cnt, *child_off = L.child_off;
+  int32_t *scan_scratch = L.scan_scratch, *counters = L.counters;
+  double *totals = L.totals, *norms = L.norms;
+  int64_t* d_base = L.base;
+  float2* merged = L.merged;
   HIP_TRY(hipMemcpyAsync(d_base, base.data(), (size_t)E * 8, hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemsetAsync(counters, 0, 64, s));
   HIP_TRY(ptsbe::launch_init_elements(E, d_shots_per_traj, el[0].traj, el[0].prefix, p->NW, el[0].off, el[0].cnt,

@@ -72,3 +72,49 @@ def oracle_shots_sv(circuit, psis, batch_sizes, m, seed):
         out.append(shots)
         memos.append(distinct)
     return out, memos
+
+
+# ------------------------------------------------------- oracle in worker processes
+# The FP64 oracle is slow on full-size circuits; the GPU tests run it in spawned
+# worker processes (numpy only, one BLAS thread each), never in the process that
+# holds the GPU.
+_LIMITS = None
+
+
+def _one_blas_thread():
+    global _LIMITS
+    from threadpoolctl import threadpool_limits
+    _LIMITS = threadpool_limits(limits=1)
+
+
+def oracle_pool(workers=None):
+    """A process pool (spawn start method) for oracle work, sized to the host's cores."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    import os
+    n = workers or max(1, min(16, len(os.sched_getaffinity(0))))
+    return cf.ProcessPoolExecutor(max_workers=n, mp_context=mp.get_context("spawn"), initializer=_one_blas_thread)
+
+
+def sv_trajectory_job(circuit, kraus_row, traj, batch_sizes, m, seed):
+    """Oracle work for one trajectory: its statevector, its m shots from the
+    per-shot batch-wise sampler, and every marginal the sampler used
+    ({(j, prefix): pi}), plus its squared norm."""
+    psi = sv.trajectory_state(circuit, kraus_row)
+    n = circuit.n_qubits
+    starts = sampling.batch_starts(batch_sizes)
+    used = {}
+
+    def mfn(j, prefix):
+        pi = sampling.marginal_from_state(psi, n, starts[j], batch_sizes[j], prefix)
+        used[(j, prefix)] = pi
+        return pi
+
+    shots, _ = sampling.sample_trajectory(mfn, traj, n, batch_sizes, m, seed)
+    return shots, used, float(np.vdot(psi, psi).real)
+
+
+def tn_value_job(circuit, kraus_row, start, b, prefix, kind):
+    """Oracle work for one element: the explicit-network value of one batch."""
+    from oracle import tn
+    return tn.batch_network_value(circuit, kraus_row, start, b, prefix, kind)

@@ -317,3 +317,25 @@ def test_gemv_join_tiling_covers_each_x_once(bs):
                 assert off not in seen_w
                 seen_w.add(off)
         assert len(seen_r) == len(seen_w) == 1 << nx
+
+
+def test_chunking_query_grows_with_the_workspace():
+    """ptsbe_plan_chunking: trajectories per chunk never decrease with more workspace,
+    reach E when the workspace is large, are 0 when the persistent arrays do not
+    fit, and the query rejects statevector plans."""
+    P = _lib()
+    c = W.random_brickwork(20, 6, np.random.default_rng(2024), 0.005)
+    plan = P.Plan(c, [8, 8, 4], device=-1, method="network")
+    for call, count in (("sample", 64000), ("contract", 20000)):
+        prev = None
+        for ws in [1 << 16, 1 << 22, 1 << 26, 1 << 28, 1 << 30, 1 << 34]:
+            caps = plan.chunking(call, 64, count, ws)
+            if prev is not None:
+                assert np.all(caps >= prev)
+            prev = caps
+        assert np.all(plan.chunking(call, 64, count, 1 << 34) == 64)
+        assert np.all(plan.chunking(call, 64, count, 1 << 12) == 0)
+    sv = P.Plan(W.random_brickwork(12, 4, np.random.default_rng(1), 0.01), [4, 4, 4], device=-1,
+                method="statevector")
+    with pytest.raises(P.PtsbeError):
+        sv.chunking("sample", 8, 100, 1 << 30)
