@@ -98,20 +98,24 @@ def oracle_pool(workers=None):
 
 def sv_trajectory_job(circuit, kraus_row, traj, batch_sizes, m, seed):
     """Oracle work for one trajectory: its statevector, its m shots from the
-    per-shot batch-wise sampler, and every marginal the sampler used
-    ({(j, prefix): pi}), plus its squared norm."""
+    per-shot batch-wise sampler, every marginal the sampler used
+    ({(j, prefix): pi}), its squared norm, and the last batch's amplitudes of
+    every prefix the sampler reached there ({prefix: amplitudes})."""
     psi = sv.trajectory_state(circuit, kraus_row)
     n = circuit.n_qubits
     starts = sampling.batch_starts(batch_sizes)
-    used = {}
+    f = len(batch_sizes)
+    used, amps = {}, {}
 
     def mfn(j, prefix):
         pi = sampling.marginal_from_state(psi, n, starts[j], batch_sizes[j], prefix)
         used[(j, prefix)] = pi
+        if j == f - 1:
+            amps[prefix] = sampling.amplitudes_from_state(psi, n, starts[j], batch_sizes[j], prefix)
         return pi
 
     shots, _ = sampling.sample_trajectory(mfn, traj, n, batch_sizes, m, seed)
-    return shots, used, float(np.vdot(psi, psi).real)
+    return shots, used, float(np.vdot(psi, psi).real), amps
 
 
 def tn_value_job(circuit, kraus_row, start, b, prefix, kind):

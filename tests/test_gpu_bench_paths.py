@@ -8,7 +8,9 @@ tests put every one of those paths against the FP64 oracle (Sec. II-B for the
 batch-wise marginals, Sec. III-B for the shots):
 
 * a 20-qubit depth-6 chain with batches [8, 8, 4]: every marginal the oracle's
-  per-shot sampler uses, element by element, and all 64 x 1000 shots under the
+  per-shot sampler uses, element by element (doubled batches: 1e-6 on the
+  conditional; the last batch, contracted to amplitudes: 1e-5 L2-relative on the
+  amplitudes and 1e-6 on the joint marginal), and all 64 x 1000 shots under the
   CDF-boundary flip bound, with a workspace that forces trajectory chunks;
 * the 50-qubit benchmark circuit: 112 distinct batch-1 prefixes of one trajectory
   (224 join rows, four row tiles), plus a trajectory sharing its per-trajectory
@@ -47,13 +49,13 @@ def _smallest_workspace(plan, call, E, count, j, want):
     return hi
 
 
-def _contract(plan, torch, dev, kd, traj, prefixes, j, ws=None):
+def _contract(plan, torch, dev, kd, traj, prefixes, j, ws=None, amp=False):
     import paper_2604_08467_amd as P
     et = to_dev(torch, dev, np.asarray(traj, dtype=np.int32))
     ep = to_dev(torch, dev, prefix_words(prefixes, plan.n_words))
-    pop, tot = plan.contract_batch(j, kd, et, ep, P.OUT_POPULATION, workspace=ws)
+    pop, tot = plan.contract_batch(j, kd, et, ep, P.OUT_AMPLITUDE if amp else P.OUT_POPULATION, workspace=ws)
     torch.cuda.synchronize()
-    return pop.cpu().numpy(), tot.cpu().numpy()
+    return pop.cpu().numpy(), (None if tot is None else tot.cpu().numpy())
 
 
 def test_chain20_k32_join_chunks_and_shared_tensors_vs_statevector_oracle():
@@ -95,6 +97,7 @@ def test_chain20_k32_join_chunks_and_shared_tensors_vs_statevector_oracle():
     ref_shots = [r[0] for r in res]
     used = [r[1] for r in res]
     Z = np.array([r[2] for r in res])
+    last_amps = [r[3] for r in res]
     np.testing.assert_allclose(out["norms"].cpu().numpy(), Z, rtol=1e-6)
 
     # every marginal the oracle used, element by element, batch by batch
@@ -118,17 +121,30 @@ def test_chain20_k32_join_chunks_and_shared_tensors_vs_statevector_oracle():
             _say(f"chain20: batch 1, {len(traj)} elements, {per.min()}..{per.max()} per trajectory, "
                  f"{caps_c[1]} trajectories per chunk")
         pop, tot = _contract(plan, torch, dev, kd, traj, pre, j, ws_c)
+        last = j == len(bs) - 1
+        amp = _contract(plan, torch, dev, kd, traj, pre, j, ws_c, amp=True)[0] if last else None
         del ws_c
-        worst = 0.0
+        worst, worst_joint, worst_amp = 0.0, 0.0, 0.0
         for e, (i, p) in enumerate(zip(traj, pre)):
             ref = used[i][(j, p)]
             Ze = ref.sum()
             err = np.abs(pop[e] - ref).max() / max(Ze, 1e-30)
             worst = max(worst, err)
-            assert err <= 1e-6, (j, i, p, err)
+            if last:
+                # the last batch is contracted to amplitudes (Sec. II-B): 1e-5 L2-relative on
+                # the element's amplitudes, 1e-6 absolute on its joint marginal p(prefix) P(x | prefix)
+                ra = last_amps[i][p]
+                rel = np.linalg.norm(amp[e] - ra) / np.linalg.norm(ra)
+                joint = err * Ze / Z[i]
+                worst_amp, worst_joint = max(worst_amp, rel), max(worst_joint, joint)
+                assert rel <= 1e-5, (j, i, p, rel)
+                assert joint <= 1e-6, (j, i, p, joint)
+            else:
+                assert err <= 1e-6, (j, i, p, err)
             assert abs(tot[e] - Ze) <= 1e-5 * Ze + 1e-30, (j, i, p)
             gpu_marg[(i, j, p)] = pop[e]
-        _say(f"chain20: batch {j}, {len(traj)} elements, worst conditional error {worst:.3g}")
+        _say(f"chain20: batch {j}, {len(traj)} elements, worst conditional error {worst:.3g}"
+             + (f", worst amplitude L2-rel {worst_amp:.3g}, worst joint marginal {worst_joint:.3g}" if last else ""))
 
     # all shots against the oracle's per-shot sampler, under the flip bound
     mism, expect = 0, 0.0
