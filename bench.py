@@ -152,8 +152,14 @@ def main():
     ap.add_argument("--final-batch", type=int, default=20, help="exhaustive workload: final batch size")
     ap.add_argument("--threshold", type=float, default=1e-6, help="exhaustive workload: P(x | prefix) threshold")
     ap.add_argument("--draws", type=int, default=1, help="exhaustive workload: draws per prefix")
-    ap.add_argument("--workload", choices=["brickwork50", "ragged", "exhaustive", "batch-sweep"], default="brickwork50",
-                    help="ragged: the ragged mix of circuits as one graph-captured ragged set")
+    ap.add_argument("--points", default="50x200,50x400,100x600",
+                    help="exhaustive-paper workload: n x g points of the paper's random-circuit family")
+    ap.add_argument("--final-batches", default="20,24,28", help="exhaustive-paper workload: b_f values")
+    ap.add_argument("--workload", choices=["brickwork50", "ragged", "exhaustive", "batch-sweep", "grid5x5",
+                                           "exhaustive-paper"],
+                    default="brickwork50",
+                    help="ragged: the ragged mix of circuits as one graph-captured ragged set; grid5x5: the 25-qubit "
+                         "grid with amplitude damping, 16384 x 256 (statevector method, --precision c64|bf16|f16)")
     ap.add_argument("--ragged-max-qubits", type=int, default=26)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 1 GiB device copy (reference for HBM byte counters)")
@@ -174,6 +180,12 @@ def main():
         return
     if args.workload == "batch-sweep":
         bench_batch_sweep(args)
+        return
+    if args.workload == "grid5x5":
+        bench_grid(args)
+        return
+    if args.workload == "exhaustive-paper":
+        bench_exhaustive_paper(args)
         return
     if args.copy_calibration:
         n = 1 << 30
@@ -345,6 +357,220 @@ def bench_exhaustive(args):
                                "job's input and output tensor once, 8 (2^rA + 2^rC) bytes)",
                      "launches": sw["step_launches"], "avg_us": sw["step_ms"] * 1e3 / max(sw["step_launches"], 1),
                      "bytes_per_step": sw["step_bytes"], "kernel_ms_per_step": sw["step_ms"]},
+    }
+    print(json.dumps(line), flush=True)
+
+
+def _oracle_grid_worker(circuit, kraus_row, budget_s):
+    """One worker of the grid's CPU baseline: the FP64 oracle statevector of one
+    trajectory, gate by gate, until budget_s; returns (gates applied, seconds)."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import statevector as sv
+    from oracle import upv
+    n = circuit.n_qubits
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        mats = upv.merged_gates(circuit, kraus_row)
+        psi = sv.zero_state(n)
+        g = 0
+        while g < len(mats) and time.perf_counter() - t0 < budget_s:
+            psi = sv.apply_gate(psi, n, mats[g], circuit.gate_qubits[g])
+            g += 1
+        return g, time.perf_counter() - t0
+
+
+def grid_error_vs_fp64(plan, torch, dev):
+    """Marginals of the stored FP64 oracle trajectories (tests/golden/grid25_sv.json,
+    written by tests/golden/make_grid25.py from the oracle) against the GPU path on
+    the same plan: max joint-marginal error per unit trajectory norm and max
+    conditional error, over every stored batch marginal."""
+    import numpy as np
+
+    import paper_2604_08467_amd as P
+    with open(os.path.join(ROOT, "tests", "golden", "grid25_sv.json")) as f:
+        gold = json.load(f)
+    kr = np.array([t["kraus"] for t in gold["trajectories"]], dtype=np.uint8)
+    kd = torch.from_numpy(kr).to(dev)
+    worst_j, worst_c, n = 0.0, 0.0, 0
+    for i, rec in enumerate(gold["trajectories"]):
+        for mg in rec["marginals"]:
+            ref = np.array(mg["pi"])
+            et = torch.tensor([i], dtype=torch.int32, device=dev)
+            ep = torch.tensor([[mg["prefix"]]], dtype=torch.int64, device=dev)
+            pop, tot = plan.contract_batch(mg["j"], kd, et, ep, P.OUT_POPULATION)
+            g = pop[0].double().cpu().numpy()
+            worst_j = max(worst_j, float(np.abs(g - ref).max() / rec["Z"]))
+            worst_c = max(worst_c, float(np.abs(g / float(tot[0].item()) - ref / ref.sum()).max()))
+            n += 1
+    return {"max_abs_joint_marginal_error": worst_j, "max_abs_conditional_error": worst_c, "marginals": n,
+            "reference": "stored FP64 oracle statevector marginals (tests/golden/grid25_sv.json): "
+                         f"{len(kr)} trajectories x {len(gold['batch_sizes'])} batches"}
+
+
+def bench_grid(args):
+    """The 25-qubit 5x5 grid (depth 8: random sqrt(X)/sqrt(Y)/sqrt(W) layers and CZ
+    layers; depolarising 0.01 then amplitude damping 0.02 after every gate, 720
+    noise sites), batches [10, 10, 5], 16384 trajectories x 256 shots, statevector
+    method (one gate schedule of 12-qubit LDS windows shared by every trajectory).
+    --precision bf16 / f16 runs the gate clusters of the windows with hi + lo 16-bit
+    operands on MFMA.  One step = one ptsbe_sample_shots call over every trajectory."""
+    import numpy as np
+    import torch
+
+    import paper_2604_08467_amd as P
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    wl = W.grid5x5_d8((10, 10, 5))
+    prec = {"c64": 0, "bf16": 1, "f16": 2}[args.precision]
+    plan = P.Plan(wl.circuit, wl.batch_sizes, precision=prec)
+    E_req = args.traj if args.traj != 4096 else wl.n_traj
+    m = args.shots if args.shots != 1000 else wl.shots_per_traj
+    kr, mult, _, n_draws = plan.sample_trajectories(wl.pts_seed, E_req)
+    E = len(kr)
+    kd = torch.from_numpy(kr).to(dev)
+    md = torch.full((E,), m, dtype=torch.int64, device=dev)
+    multd = torch.from_numpy(mult).to(dev)
+    ws = torch.empty(int(args.workspace_gb * (1 << 30)), dtype=torch.uint8, device=dev)
+    print(f"grid5x5: E={E} x {m} shots, precision {args.precision}, {plan.sv_windows} windows, "
+          f"{plan.sv_clusters} clusters ({plan.sv_cluster_steps} of {plan.n_gates} gates)", file=sys.stderr, flush=True)
+
+    def step():
+        return plan.sample_shots(kd, md, wl.shot_seed, mult_dev=multd, workspace=ws)
+
+    for k in range(args.warmup):
+        t_w = time.perf_counter()
+        out = step()
+        torch.cuda.synchronize()
+        print(f"grid5x5: warmup {k} {time.perf_counter() - t_w:.2f} s", file=sys.stderr, flush=True)
+    plan.profile_enable(1)
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        out = step()
+        torch.cuda.synchronize()
+        print(f"grid5x5: step {k} done at {time.perf_counter() - t0:.2f} s", file=sys.stderr, flush=True)
+    dt = time.perf_counter() - t0
+    win = plan.profile_read_windows()
+    plan.profile_enable(0)
+    M = E * m
+    achieved = win["bytes"] / (win["ms"] / 1e3) / 1e9 if win["ms"] > 0 else 0.0
+    line = {
+        "metric": "sampled shots/sec", "value": M * args.steps / dt, "unit": "shots/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"c64": "c64", "bf16": "c64+bf16x3", "f16": "c64+f16x3"}[args.precision], "data": "synthetic",
+        "config": {"workload": f"5x5 grid depth 8 (sqrt(X)/sqrt(Y)/sqrt(W) + CZ layers), depolarising 0.01 + "
+                               f"amplitude damping 0.02, {E} trajectories x {m} shots, batches [10, 10, 5], "
+                               f"statevector method, proportional NBS",
+                   "trajectories": E, "shots_per_traj": m, "batch_sizes": list(wl.batch_sizes),
+                   "pts_draws": int(n_draws), "precision": args.precision,
+                   "windows": plan.sv_windows, "clusters": plan.sv_clusters,
+                   "elements_per_batch": [int(x) for x in out["elements_per_batch"]]},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "sv_window_kernel (gate windows: every 2^12-amplitude tile read and written once "
+                               "per window, gates and clusters applied in LDS)",
+                     "launches": win["launches"], "avg_us": win["ms"] * 1e3 / max(win["launches"], 1),
+                     "bytes_per_step": win["bytes"] / args.steps, "kernel_ms_per_step": win["ms"] / args.steps},
+    }
+    if not args.no_cpu_baseline:
+        print("grid5x5: error vs FP64 on the stored oracle marginals", file=sys.stderr, flush=True)
+        line["error_vs_fp64"] = grid_error_vs_fp64(plan, torch, dev)
+        print("grid5x5: CPU oracle baseline", file=sys.stderr, flush=True)
+        cores = min(host_cores(), E)
+        budget = 20.0
+        t_c = time.perf_counter()
+        with _pool(cores) as pool:
+            res = [f.result() for f in [pool.submit(_oracle_grid_worker, wl.circuit, kr[w], budget)
+                                        for w in range(cores)]]
+        wall = time.perf_counter() - t_c
+        G = plan.n_gates
+        per_traj_s = float(np.mean([t * G / max(g, 1) for g, t in res]))
+        line["cpu_baseline"] = {
+            "value": cores * m / per_traj_s, "unit": "shots/s", "cores": cores, "kind": "oracle",
+            "sample": f"FP64 oracle statevector of trajectories 0..{cores - 1}, one worker process per core, "
+                      f"{budget:.0f} s each ({min(g for g, _ in res)}..{max(g for g, _ in res)} of {G} gates "
+                      f"applied; {wall:.1f} s wall); time per trajectory extrapolated linearly to all {G} gates, "
+                      f"{m} shots per trajectory (marginals and draws not counted)"}
+    print(json.dumps(line), flush=True)
+
+
+def bench_exhaustive_paper(args):
+    """Non-proportional NBS with exhaustive final-batch sampling in the paper's own
+    regime (Sec. IV-B, V-A): random circuits of its family (H, X, Y, Z, T, Rx and
+    nearest-neighbour CX, CY, CZ, CH, CRx, 20 % two-qubit gates, a Pauli error after
+    every single-qubit gate and two-qubit depolarising after every two-qubit gate,
+    p ~ U[0.02, 0.2]; one seeded instance per point, complex64), non-final batches
+    of 10 qubits with one draw each, final batch b_f, every x with
+    P(x | prefix) > --threshold returned.  Per point: host path finding (timed,
+    outside the loop), then --steps timed calls over --traj trajectories.  value =
+    distinct labelled bitstrings per second over all points."""
+    import numpy as np
+    import torch
+
+    import paper_2604_08467_amd as P
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    E_req = args.traj if args.traj != 4096 else 16
+    ws = torch.empty(int(args.workspace_gb * (1 << 30)), dtype=torch.uint8, device=dev)
+    points = [tuple(int(v) for v in pt.split("x")) for pt in args.points.split(",")]
+    bfs = [int(v) for v in args.final_batches.split(",")]
+    table, tot_rows, tot_s = [], 0, 0.0
+    for (n, g) in points:
+        circ = W.paper_random_circuit(n, g, np.random.default_rng(7000 + n + g)).round_to_complex64()
+        for bf in bfs:
+            rest = n - bf
+            bs = [10] * (rest // 10) + ([rest % 10] if rest % 10 else []) + [bf]
+            row = {"n": n, "g": g, "b_f": bf, "batches": bs}
+            try:
+                t_p = time.perf_counter()
+                plan = P.Plan(circ, bs, hypersamples=8, method="network")
+                row["plan_s"] = round(time.perf_counter() - t_p, 3)
+                kr, mult, _, _ = plan.sample_trajectories(7100 + n + g, E_req)
+                E = len(kr)
+                kd = torch.from_numpy(kr).to(dev)
+                multd = torch.from_numpy(mult).to(dev)
+                # strict P(x | prefix) > threshold: at most 1 / threshold rows per final element
+                per_elem = min(1 << bf, int(np.ceil(1.0 / args.threshold)) if args.threshold > 0 else 1 << bf)
+                cap = E * per_elem
+                outs = {"bits": torch.empty((cap, plan.n_words), dtype=torch.int64, device=dev),
+                        "row_traj": torch.empty(cap, dtype=torch.int32, device=dev),
+                        "p_cond": torch.empty(cap, dtype=torch.float64, device=dev),
+                        "p_prefix": torch.empty(cap, dtype=torch.float64, device=dev)}
+
+                def step():
+                    return plan.sample_nonproportional(kd, 1, 7200 + n + g, args.threshold, max_elems=E,
+                                                       capacity=cap, mult_dev=multd, workspace=ws, outputs=outs)
+
+                out = step()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(args.steps):
+                    out = step()
+                torch.cuda.synchronize()
+                dt = (time.perf_counter() - t0) / args.steps
+                bi = plan.batch_info(len(bs) - 1)
+                row.update({"trajectories": E, "rows": int(out["n_rows"]), "call_ms": round(dt * 1e3, 3),
+                            "bitstrings_per_s": out["n_rows"] / dt, "final_right_rank": bi["right_rank"],
+                            "final_crossing": bi["crossing"],
+                            "final_contraction_ms_per_traj": round(dt * 1e3 / E, 3)})
+                tot_rows += int(out["n_rows"])
+                tot_s += dt
+                del plan, outs, out
+            except Exception as e:      # a point beyond this build's limits is reported, not fatal
+                row["error"] = str(e)[:160]
+            table.append(row)
+            print(f"exhaustive-paper: {row}", file=sys.stderr, flush=True)
+    line = {
+        "metric": "distinct labelled bitstrings/sec (exhaustive non-proportional NBS)",
+        "value": tot_rows / tot_s if tot_s > 0 else 0.0, "unit": "bitstrings/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": 1, "ms_per_step": tot_s * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "c64", "data": "synthetic",
+        "config": {"workload": f"paper random-circuit family (Sec. IV-B), points {args.points}, b = 10 with one "
+                               f"draw per non-final batch, b_f in {args.final_batches}, threshold {args.threshold}, "
+                               f"{E_req} trajectories per point", "table": table},
     }
     print(json.dumps(line), flush=True)
 

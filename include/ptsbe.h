@@ -125,17 +125,19 @@ typedef struct {
   int32_t hypersamples;         /* randomised path-search restarts (>= 1)        */
   uint64_t path_seed;
   int32_t precision;            /* PTSBE_C64, PTSBE_SPLIT_BF16 or PTSBE_SPLIT_F16:
-                                   the dense join of doubled networks (16 or 32
-                                   crossing-wire values) runs with hi+lo 16-bit
+                                   the dense contractions run with hi+lo 16-bit
                                    operands, three products on bf16 / fp16 MFMA
-                                   with FP32 accumulation (fp16: power-of-two
-                                   scaling per row and per x); everything else
-                                   stays c64 */
+                                   with FP32 accumulation: network method, the
+                                   join of doubled networks (16 or 32 crossing-
+                                   wire values; fp16: power-of-two scaling per
+                                   row and per x); statevector method, the gate
+                                   clusters of its windows (fp16: power-of-two
+                                   scaling per column).  Everything else stays
+                                   c64, FP64 for sums, CDFs and weights */
   int32_t device;               /* HIP device ordinal; -1: host-only plan (path,
                                    query and pre-sampling only, no device calls) */
   size_t device_budget_bytes;   /* 0: no limit; else plan constants must fit     */
-  int32_t method;               /* PTSBE_METHOD_*; STATEVECTOR plans take
-                                   precision PTSBE_C64 only                      */
+  int32_t method;               /* PTSBE_METHOD_*                                 */
 } ptsbe_plan_opts_t;
 
 typedef struct {
@@ -146,6 +148,10 @@ typedef struct {
   int32_t sv_windows;           /* statevector method: launches (state passes) per
                                    trajectory to apply every gate; else 0        */
   int32_t sv_windows_by_size[3];/* the same for windows of 10, 11, 12 qubits     */
+  int32_t sv_clusters;          /* statevector method: gate clusters (16 x 16
+                                   matrices applied on MFMA) in those windows    */
+  int32_t sv_cluster_steps;     /* gates applied inside those clusters           */
+  int32_t precision;            /* the plan's precision option                    */
 } ptsbe_plan_info_t;
 
 /* Per-batch description of the unified path P^j (host-side cost model). */
@@ -440,6 +446,11 @@ ptsbe_status_t ptsbe_profile_read(ptsbe_plan_t plan, double* join_ms, int64_t* j
  * in-place tile runs (each job's tensor read and written once per run). */
 ptsbe_status_t ptsbe_profile_read_sweeps(ptsbe_plan_t plan, double* step_ms, int64_t* step_launches,
                                          double* step_bytes, double* fused_bytes);
+/* Statevector-method gate windows (any level >= 1): total event time of the
+ * window launches (events recorded on the launch stream), launches, and
+ * algorithmic bytes (every trajectory state of the launch read and written once:
+ * 16 * 2^n bytes per trajectory and window). */
+ptsbe_status_t ptsbe_profile_read_windows(ptsbe_plan_t plan, double* ms, int64_t* launches, double* bytes);
 
 #ifdef __cplusplus
 }

@@ -120,6 +120,9 @@ class Plan:
         self.method = {v: k for k, v in METHODS.items()}[info.method]
         self.sv_windows = info.sv_windows
         self._sv_windows_by_size = list(info.sv_windows_by_size)
+        self.sv_clusters = info.sv_clusters
+        self.sv_cluster_steps = info.sv_cluster_steps
+        self.precision = info.precision
 
     def sv_windows_for(self, window_qubits):
         """Gate windows (state passes) of the statevector schedule for windows of
@@ -330,6 +333,12 @@ class Plan:
     def profile_enable(self, on=True):
         """on: False/0 off, True/1 join timing, 2 join and single HBM sweep-step timing."""
         _lib.check(self._lib.ptsbe_profile_enable(self._h, int(on)))
+
+    def profile_read_windows(self):
+        """ptsbe_profile_read_windows: statevector gate windows (ms, launches, algorithmic bytes)."""
+        ms, n, b = C.c_double(), C.c_int64(), C.c_double()
+        _lib.check(self._lib.ptsbe_profile_read_windows(self._h, C.byref(ms), C.byref(n), C.byref(b)))
+        return {"ms": ms.value, "launches": n.value, "bytes": b.value}
 
     def profile_read_sweeps(self):
         ms, b, fb = C.c_double(), C.c_double(), C.c_double()

@@ -20,6 +20,7 @@ EXPORTS = [
     "ptsbe_ragged_autotune", "ptsbe_ragged_sample_shots", "ptsbe_plan_sv_schedule", "ptsbe_plan_right_sites",
     "ptsbe_nonproportional_workspace_size", "ptsbe_sample_nonproportional", "ptsbe_profile_read_sweeps",
     "ptsbe_plan_join_tiling", "ptsbe_plan_chunking",
+    "ptsbe_profile_read_windows",
 ]
 
 
@@ -54,6 +55,7 @@ class PlanInfo_t(C.Structure):
         ("n_qubits", C.c_int32), ("n_gates", C.c_int32), ("n_sites", C.c_int32), ("n_batches", C.c_int32),
         ("n_words", C.c_int32), ("max_kraus", C.c_int32), ("plan_device_bytes", C.c_int64),
         ("method", C.c_int32), ("sv_windows", C.c_int32), ("sv_windows_by_size", C.c_int32 * 3),
+        ("sv_clusters", C.c_int32), ("sv_cluster_steps", C.c_int32), ("precision", C.c_int32),
     ]
 
 
@@ -110,6 +112,7 @@ def load():
     lib.ptsbe_sample_nonproportional.argtypes = [P, P, i64, P, i32, i32, i64, u64, C.c_double, P, P, P, P, i64,
                                                  C.POINTER(i64), P, P, P, P, sz, P]
     lib.ptsbe_profile_enable.argtypes = [P, i32]
+    lib.ptsbe_profile_read_windows.argtypes = [P, C.POINTER(C.c_double), C.POINTER(i64), C.POINTER(C.c_double)]
     lib.ptsbe_profile_read_sweeps.argtypes = [P, C.POINTER(C.c_double), C.POINTER(i64), C.POINTER(C.c_double),
                                               C.POINTER(C.c_double)]
     lib.ptsbe_profile_read.argtypes = [P, C.POINTER(C.c_double), C.POINTER(i64), C.POINTER(C.c_double),

@@ -685,7 +685,6 @@ ptsbe_status_t ptsbe_plan(const ptsbe_circuit_t* c, const ptsbe_plan_opts_t* o, 
   }
   if (use_sv) {
     if (p->n > ptsbe::kSvMaxQubits) return fail(PTSBE_ERR_UNSUPPORTED, "the statevector method needs n_qubits <= 30");
-    if (p->precision != PTSBE_C64) return fail(PTSBE_ERR_UNSUPPORTED, "the statevector method runs in complex64 only");
     for (int b : p->batch_sizes)
       if (b > 12) return fail(PTSBE_ERR_UNSUPPORTED, "the statevector method samples batches of at most 12 qubits");
     p->method = PTSBE_METHOD_STATEVECTOR;
@@ -762,7 +761,10 @@ ptsbe_status_t ptsbe_plan(const ptsbe_circuit_t* c, const ptsbe_plan_opts_t* o, 
   for (auto& bp : p->batches)
     for (ptsbe::PartPlan* pp : {&bp.left, &bp.right, &bp.left_resume})
       ptsbe::build_segments(pp->steps, pp->segs, p->fused);
-  if (p->method == PTSBE_METHOD_STATEVECTOR) ptsbe::build_sv_schedule(*p);
+  if (p->method == PTSBE_METHOD_STATEVECTOR) {
+    ptsbe::build_sv_schedule(*p);
+    ptsbe::build_sv_ops(*p);
+  }
   std::vector<ptsbe::AbsorbStep> steps;
   std::vector<int64_t> tables;
   for (auto& bp : p->batches) {
@@ -827,6 +829,11 @@ ptsbe_status_t ptsbe_plan(const ptsbe_circuit_t* c, const ptsbe_plan_opts_t* o, 
       }
       HIP_TRY(hipMalloc(&p->d_rg_win[i], std::max<size_t>(1, w.size()) * sizeof(ptsbe::RgWindow)));
       HIP_TRY(hipMemcpy(p->d_rg_win[i], w.data(), w.size() * sizeof(ptsbe::RgWindow), hipMemcpyHostToDevice));
+      const auto& so = p->sv_ops[i];
+      if (!so.empty()) {
+        HIP_TRY(hipMalloc(&p->d_sv_ops[i], so.size() * sizeof(ptsbe::SvOp)));
+        HIP_TRY(hipMemcpy(p->d_sv_ops[i], so.data(), so.size() * sizeof(ptsbe::SvOp), hipMemcpyHostToDevice));
+      }
       const auto& cl = p->sv_cl[i];
       HIP_TRY(hipMalloc(&p->d_sv_cl[i], std::max<size_t>(1, cl.size()) * sizeof(ptsbe::ClusterDesc)));
       if (!cl.empty())
@@ -854,6 +861,10 @@ void ptsbe_plan_destroy(ptsbe_plan_t plan) {
     (void)hipEventDestroy(e.first);
     (void)hipEventDestroy(e.second);
   }
+  for (auto& e : p->win_evs) {
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
   if (p->d_gates) (void)hipFree(p->d_gates);
   if (p->d_gate_site_list) (void)hipFree(p->d_gate_site_list);
   if (p->d_site_ops) (void)hipFree(p->d_site_ops);
@@ -865,6 +876,8 @@ void ptsbe_plan_destroy(ptsbe_plan_t plan) {
     if (w) (void)hipFree(w);
   for (auto* c : p->d_sv_cl)
     if (c) (void)hipFree(c);
+  for (auto* o : p->d_sv_ops)
+    if (o) (void)hipFree(o);
   delete p;
 }
 
@@ -882,6 +895,14 @@ ptsbe_status_t ptsbe_plan_query(ptsbe_plan_t plan, ptsbe_plan_info_t* out) {
   out->sv_windows = p->method == PTSBE_METHOD_STATEVECTOR ? (int32_t)p->sv_segs.size() : 0;
   for (int i = 0; i < 3; ++i)
     out->sv_windows_by_size[i] = p->method == PTSBE_METHOD_STATEVECTOR ? (int32_t)p->sv_win[i].size() : 0;
+  out->sv_clusters = 0;
+  out->sv_cluster_steps = 0;
+  if (p->method == PTSBE_METHOD_STATEVECTOR)
+    for (const auto& cd : p->sv_cl[2]) {
+      ++out->sv_clusters;
+      out->sv_cluster_steps += cd.len;
+    }
+  out->precision = p->precision;
   return PTSBE_OK;
 }
 
@@ -1607,9 +1628,25 @@ ptsbe_status_t ptsbe_profile_enable(ptsbe_plan_t plan, int32_t on) {
     (void)hipEventDestroy(e.second);
   }
   p->sweep_evs.clear();
+  for (auto& e : p->win_evs) {
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
+  p->win_evs.clear();
   p->profile = on;
   p->join_ms = p->sweep_ms = p->join_flops = p->sweep_bytes = p->fused_bytes = 0;
   p->join_launches = p->sweep_launches = 0;
+  p->win_ms = p->win_bytes = 0;
+  p->win_launches = 0;
+  return PTSBE_OK;
+}
+
+ptsbe_status_t ptsbe_profile_read_windows(ptsbe_plan_t plan, double* ms, int64_t* launches, double* bytes) {
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  if (!p) return fail(PTSBE_ERR_INVALID_ARG, "null plan");
+  if (ms) *ms = p->win_ms;
+  if (launches) *launches = p->win_launches;
+  if (bytes) *bytes = p->win_bytes;
   return PTSBE_OK;
 }
 

@@ -99,6 +99,28 @@ struct ClusterDesc {
   int32_t pos[4];
 };
 
+// Compact op of a statevector gate window, read by the window kernel through the
+// scalar cache: a plain one- or two-qubit gate applied in place on the LDS tile,
+// or a gate cluster (a 16 x 16 matrix on four tile positions, applied on MFMA).
+enum { kSvOpGate1 = 1, kSvOpGate2 = 2, kSvOpCluster = 3 };
+struct SvOp {
+  int8_t kind;
+  int8_t p0, p1;            // gate: tile positions of local index bits 0 and 1
+  int8_t conj;              // gate: use the complex conjugate of the merged matrix
+  int8_t cpos[4];           // cluster: tile position of cluster-local bit i
+  int32_t gate;             // gate: index into the trajectory's merged gates
+  int32_t slot;             // gate: staged matrix slot; cluster: index within the window
+  int8_t idx[16];           // gate: local entry (n, k), n * d + k, is merged entry idx[n * d + k]
+};
+static_assert(sizeof(SvOp) == 32, "SvOp is read as eight dwords");
+// One window of a statevector schedule in compact form: ops [op_off, op_off + n_ops)
+// on the tile positions P (|P| = np, P[0] == 0), n_plain staged gate matrices and
+// the window set's clusters [cl_first, cl_first + n_cl).
+struct SvWin {
+  int32_t op_off, n_ops, n_plain, cl_first, n_cl, np;
+  int32_t P[12];
+};
+
 // A run of steps executed by one launch: either one absorb step, or a fused
 // run of in-place steps whose positions lie in P (|P| = np <= kFuseMax).
 constexpr int kFuseMax = 12;
@@ -206,6 +228,11 @@ struct Plan {
   RgWindow* d_rg_win[3] = {nullptr, nullptr, nullptr};   // the same windows on the device
   std::vector<ClusterDesc> sv_cl[3];              // gate clusters of each window set
   ClusterDesc* d_sv_cl[3] = {nullptr, nullptr, nullptr};
+  // the same windows as compact ops (empty when a window holds a step that is not
+  // a plain in-place gate: then the generic fused pass runs it)
+  std::vector<SvWin> sv_wins[3];
+  std::vector<SvOp> sv_ops[3];
+  SvOp* d_sv_ops[3] = {nullptr, nullptr, nullptr};
   // fused in-place steps of every part and of the statevector schedule
   std::vector<FusedStep> fused;
   FusedStep* d_fused = nullptr;
@@ -215,7 +242,13 @@ struct Plan {
   double join_ms = 0, sweep_ms = 0, join_flops = 0, sweep_bytes = 0, fused_bytes = 0;
   int64_t join_launches = 0, sweep_launches = 0;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> sweep_evs;   // recorded, not yet read
+  // statevector gate windows (any profile level): event time, launches, algorithmic bytes
+  double win_ms = 0, win_bytes = 0;
+  int64_t win_launches = 0;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> win_evs;     // recorded, not yet read
 };
+// Reads and destroys the recorded window events (the stream has been synchronised).
+ptsbe_status_t collect_window_events(Plan& p);
 
 // planner.cpp
 bool build_batch_plans(Plan& p, std::string& err);
@@ -227,6 +260,9 @@ void build_sv_batches(Plan& p);
 // earlier gate left out of it touches its qubits (so it commutes with all of
 // them).  Fills p.sv_run, p.sv_segs, p.sv_win[*] and appends to p.fused.
 void build_sv_schedule(Plan& p);
+// Compact ops of every statevector window set (p.sv_wins, p.sv_ops), from the
+// fused steps and clusters that build_sv_schedule made.
+void build_sv_ops(Plan& p);
 
 // kernels.hip: launchers (all asynchronous on `stream`)
 struct GateCtx {
@@ -451,6 +487,18 @@ struct GradGateArgs {
 };
 hipError_t launch_grad_gates(const GradGateArgs& a, hipStream_t stream);
 hipError_t launch_state_init(float2* psi, int64_t n_jobs, int n, hipStream_t stream);
+// One statevector gate window on the n-qubit states of n_jobs trajectories
+// (trajectory traj_base + job), in place: every 2^np tile is loaded into LDS,
+// the window's ops are applied there and the tile is written back.  Gate
+// matrices come from merged ([E][G][16]); cluster matrices from
+// Ucl[job][n_cl_total][256].  precision: PTSBE_C64 (FP32 MFMA for clusters) or
+// PTSBE_SPLIT_BF16 / _F16 (clusters with hi + lo 16-bit operands, three products,
+// FP32 accumulation).
+hipError_t launch_sv_window(const SvWin& w, const SvOp* d_ops, const float2* merged, int G, const float2* Ucl,
+                            int n_cl_total, int64_t n_jobs, int32_t traj_base, float2* psi, int n, int precision,
+                            hipStream_t stream);
+// LDS bytes the window kernel needs for a window (0 if it cannot take it).
+size_t sv_window_lds_bytes(const SvWin& w);
 hipError_t launch_copy(const float2* src, float2* dst, int64_t n, hipStream_t stream);
 hipError_t launch_observable(const float2* psi, float2* lam, int64_t n_jobs, int n, const int32_t* zq,
                              const double* zc, int nt, double* value, int64_t job0, hipStream_t stream);
@@ -482,7 +530,7 @@ hipError_t launch_sv_marginal(const SvMargArgs& a, hipStream_t stream);
 hipError_t launch_sv_amplitudes(const SvMargArgs& a, float2* amp, hipStream_t stream);
 // Elements of a trajectory range [t0, t0 + count): one element per trajectory.
 // statevector method drivers (sv.cpp)
-ptsbe_status_t sv_evolve(const Plan& p, const GateCtx& g, int64_t t0, int64_t nj, float2* psi, float2* Ucl,
+ptsbe_status_t sv_evolve(Plan& p, const GateCtx& g, int64_t t0, int64_t nj, float2* psi, float2* Ucl,
                          hipStream_t s);
 size_t sv_sample_workspace(const Plan& p, int64_t E, int64_t M);
 size_t sv_np_workspace(const Plan& p, int64_t E, int64_t cap, int32_t rows_per_elem);

@@ -768,6 +768,62 @@ void build_sv_schedule(Plan& p) {
   p.sv_segs = p.sv_win[2];
 }
 
+void build_sv_ops(Plan& p) {
+  for (int i = 0; i < 3; ++i) {
+    std::vector<SvWin>& wins = p.sv_wins[i];
+    std::vector<SvOp>& ops = p.sv_ops[i];
+    wins.clear();
+    ops.clear();
+    bool ok = true;
+    for (const Segment& sg : p.sv_win[i]) {
+      SvWin w{};
+      w.op_off = (int32_t)ops.size();
+      w.np = sg.np;
+      for (int k = 0; k < kFuseMax; ++k) w.P[k] = sg.P[k];
+      ok = ok && sg.np >= 1 && sg.P[0] == 0;
+      int cl_lo = -1, cl_hi = -1;
+      for (int s = 0; s < sg.count && ok;) {
+        const FusedStep& f = p.fused[(size_t)(sg.fused_off + s)];
+        SvOp op{};
+        if (f.cl_len > 0) {
+          op.kind = kSvOpCluster;
+          for (int k = 0; k < 4; ++k) op.cpos[k] = (int8_t)f.cl_pos[k];
+          op.slot = f.cl_id;            // made window-relative below
+          cl_lo = cl_lo < 0 ? f.cl_id : std::min(cl_lo, f.cl_id);
+          cl_hi = std::max(cl_hi, f.cl_id);
+          s += f.cl_len;
+        } else {
+          const bool plain = f.nH == 0 && f.nS == 0 && f.nK == f.nN && f.nK >= 1 && f.nK <= 2 &&
+                             f.noff[1] == f.koff[1] && (f.nK == 1 || (f.noff[2] == f.koff[2] && f.noff[3] == f.koff[3]));
+          if (!plain) { ok = false; break; }
+          op.kind = f.nK == 1 ? kSvOpGate1 : kSvOpGate2;
+          op.p0 = (int8_t)f.kloc[0];
+          op.p1 = (int8_t)(f.nK == 2 ? f.kloc[1] : 0);
+          op.conj = (int8_t)f.conj;
+          op.gate = f.gate;
+          op.slot = w.n_plain++;
+          const int d = 1 << f.nK;
+          for (int n = 0; n < d; ++n)
+            for (int k = 0; k < d; ++k) op.idx[n * d + k] = (int8_t)(f.nB[n] + f.kB[k]);
+          ++s;
+        }
+        ops.push_back(op);
+      }
+      if (!ok) break;
+      w.n_ops = (int32_t)ops.size() - w.op_off;
+      w.cl_first = cl_lo < 0 ? 0 : cl_lo;
+      w.n_cl = cl_lo < 0 ? 0 : cl_hi - cl_lo + 1;
+      for (int k = w.op_off; k < (int)ops.size(); ++k)
+        if (ops[(size_t)k].kind == kSvOpCluster) ops[(size_t)k].slot -= w.cl_first;
+      wins.push_back(w);
+    }
+    if (!ok) {
+      wins.clear();
+      ops.clear();
+    }
+  }
+}
+
 
 bool make_gemv_tiling(const BatchPlan& bp, GemvTiling& g) {
   const int nx = (int)bp.xT.size();

@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <string>
 #include <vector>
 
@@ -60,14 +61,47 @@ size_t sv_global_bytes(const Plan& p, int64_t E, int64_t M) {
 // Device bytes of one trajectory's state and its gate-cluster matrices.
 static size_t sv_traj_bytes(const Plan& p) { return ((size_t)8 << p.n) + p.sv_cl[2].size() * 256 * sizeof(float2) + 512; }
 
-ptsbe_status_t sv_evolve(const Plan& p, const GateCtx& g, int64_t t0, int64_t nj, float2* psi, float2* Ucl,
+ptsbe_status_t collect_window_events(Plan& p) {
+  for (auto& e : p.win_evs) {
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, e.first, e.second));
+    p.win_ms += ms;
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
+  p.win_evs.clear();
+  return PTSBE_OK;
+}
+
+ptsbe_status_t sv_evolve(Plan& p, const GateCtx& g, int64_t t0, int64_t nj, float2* psi, float2* Ucl,
                          hipStream_t s) {
   HIP_TRY(launch_state_init(psi, nj, p.n, s));
   const int n_cl = Ucl ? (int)p.sv_cl[2].size() : 0;
   if (n_cl > 0) HIP_TRY(launch_cluster_build(p.d_sv_cl[2], n_cl, p.d_fused, g, nj, nullptr, (int32_t)t0, Ucl, s));
-  for (const Segment& sg : p.sv_segs)
+  const bool compact = p.sv_wins[2].size() == p.sv_segs.size() && p.d_sv_ops[2];
+  for (size_t k = 0; k < p.sv_segs.size(); ++k) {
+    const Segment& sg = p.sv_segs[k];
+    if (compact && sv_window_lds_bytes(p.sv_wins[2][k]) != 0 && sv_window_lds_bytes(p.sv_wins[2][k]) <= 64 * 1024) {
+      std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+      if (p.profile) {
+        HIP_TRY(hipEventCreate(&ev.first));
+        HIP_TRY(hipEventCreate(&ev.second));
+        HIP_TRY(hipEventRecord(ev.first, s));
+      }
+      HIP_TRY(launch_sv_window(p.sv_wins[2][k], p.d_sv_ops[2], g.merged, p.G, Ucl, n_cl, nj, (int32_t)t0, psi, p.n,
+                               p.precision, s));
+      if (p.profile) {
+        HIP_TRY(hipEventRecord(ev.second, s));
+        p.win_evs.push_back(ev);
+        ++p.win_launches;
+        p.win_bytes += (double)nj * 16.0 * std::ldexp(1.0, p.n);   // every state read and written once
+      }
+      continue;
+    }
+    // windows of fewer than 10 qubits (small circuits) take the generic fused pass
     HIP_TRY(launch_fused(sg, p.d_fused, g, nj, nullptr, (int32_t)t0, nullptr, p.NW, psi, s, n_cl > 0 ? Ucl : nullptr,
                          n_cl));
+  }
   return PTSBE_OK;
 }
 
@@ -249,6 +283,10 @@ ptsbe_status_t sv_sample_shots(Plan& p, const uint8_t* d_kraus, int64_t E, const
   int32_t bad = 0;
   HIP_TRY(hipMemcpyAsync(&bad, counters + 1, 4, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
+  if (p.profile) {
+    const ptsbe_status_t st = collect_window_events(p);
+    if (st != PTSBE_OK) return st;
+  }
   if (bad) return fail(PTSBE_ERR_NUMERIC, "an element had a non-finite marginal total");
   return PTSBE_OK;
 }
@@ -318,7 +356,7 @@ ptsbe_status_t sv_contract_batch(Plan& p, int j, const uint8_t* d_kraus, int64_t
     t0 = t1;
   }
   HIP_TRY(hipStreamSynchronize(s));
-  return PTSBE_OK;
+  return p.profile ? collect_window_events(p) : PTSBE_OK;
 }
 
 
@@ -519,6 +557,10 @@ ptsbe_status_t sv_sample_nonproportional(Plan& p, const uint8_t* d_kraus, int64_
   int32_t bad = 0;
   HIP_TRY(hipMemcpyAsync(&bad, L.counters + 1, 4, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
+  if (p.profile) {
+    const ptsbe_status_t st = collect_window_events(p);
+    if (st != PTSBE_OK) return st;
+  }
   *n_rows_out = rows;
   if (bad) return fail(PTSBE_ERR_NUMERIC, "an element had a non-finite marginal total");
   if (rows > capacity)

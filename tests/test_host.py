@@ -132,7 +132,7 @@ def test_error_codes():
     off.add_site(g, (2,), ch)                                         # site qubit not on the gate
     _expect_status(1, lambda: P.Plan(off, [3], device=-1))
     _expect_status(3, lambda: P.Plan(c, [10], device=-1, device_budget_bytes=64))
-    _expect_status(2, lambda: P.Plan(c, [10], device=-1, precision=2))   # split FP16: not built
+    _expect_status(1, lambda: P.Plan(c, [10], device=-1, precision=3))   # no such precision
 
 
 def test_untouched_qubit_gets_identity():
@@ -158,7 +158,11 @@ def test_method_selection():
     assert [p3.batch_info(j)["start"] for j in range(3)] == [0, 10, 20]
     assert p3.batch_info(0)["n_right_steps"] == 0
     _expect_status(2, lambda: P.Plan(wl3.circuit, wl3.batch_sizes, device=-1, method="network"))
-    _expect_status(2, lambda: P.Plan(wl3.circuit, wl3.batch_sizes, device=-1, precision=1))   # c64 only
+    # split precision on the statevector method: the gate clusters of its windows
+    for prec in (1, 2):
+        ps = P.Plan(wl3.circuit, wl3.batch_sizes, device=-1, precision=prec)
+        assert ps.method == "statevector" and ps.precision == prec
+        assert ps.sv_clusters >= ps.sv_windows and ps.sv_cluster_steps >= 2 * ps.sv_clusters
     _expect_status(2, lambda: P.Plan(wl3.circuit, [25], device=-1, method="statevector"))     # b > 12
     _expect_status(2, lambda: P.Plan(wl2.circuit, wl2.batch_sizes, device=-1, method="statevector"))  # n > 30
     with pytest.raises(ValueError):

@@ -266,6 +266,60 @@ def small_random_circuit(n: int, n_gates: int, rng: np.random.Generator,
     return c
 
 
+T_GATE = np.diag([1.0, np.exp(1j * np.pi / 4)]).astype(np.complex128)
+
+
+def controlled(u: np.ndarray) -> np.ndarray:
+    """Two-qubit controlled-u, control = first listed qubit (the high bit of the
+    matrix index 2 x[q0] + x[q1])."""
+    m = np.eye(4, dtype=np.complex128)
+    m[2:, 2:] = u
+    return m
+
+
+def rx(theta: float) -> np.ndarray:
+    return _rot(pauli_x, theta)
+
+
+def paper_random_circuit(n: int, n_gates: int, rng: np.random.Generator, p_lo: float = 0.02,
+                         p_hi: float = 0.2, two_qubit_frac: float = 0.2) -> Circuit:
+    """The random-circuit family of the paper's experiments (Sec. IV-B): single-qubit
+    gates H, X, Y, Z, T, Rx(theta) on a uniformly random qubit and nearest-neighbour
+    controlled gates CX, CY, CZ, CH, CRx(theta) on a uniformly random adjacent pair
+    (random control side), round(two_qubit_frac * n_gates) of the gates two-qubit,
+    in random positions; theta ~ U[0, 2 pi).  Every gate carries its own noise
+    channel with p ~ U[p_lo, p_hi]: after a single-qubit gate one Pauli error
+    (X, Y or Z, drawn uniformly) with probability p, after a two-qubit gate the
+    two-qubit depolarising channel of strength p (our reading of the noise model)."""
+    c = Circuit(n)
+    n2 = int(round(two_qubit_frac * n_gates))
+    is2 = np.zeros(n_gates, dtype=bool)
+    is2[rng.choice(n_gates, size=n2, replace=False)] = True
+    one = ("h", "x", "y", "z", "t", "rx")
+    two = ("cx", "cy", "cz", "ch", "crx")
+    paulis = (pauli_x, pauli_y, pauli_z)
+    for k in range(n_gates):
+        p = float(rng.uniform(p_lo, p_hi))
+        if is2[k] and n > 1:
+            a = int(rng.integers(0, n - 1))
+            qs = (a, a + 1) if rng.random() < 0.5 else (a + 1, a)
+            kind = two[int(rng.integers(0, len(two)))]
+            u = {"cx": pauli_x, "cy": pauli_y, "cz": pauli_z, "ch": HADAMARD}.get(kind)
+            if u is None:
+                u = rx(float(rng.uniform(0.0, 2 * np.pi)))
+            g = c.add_gate(qs, controlled(u))
+            c.add_site(g, qs, c.add_channel(depolarizing2(p)))
+        else:
+            q = int(rng.integers(0, n))
+            kind = one[int(rng.integers(0, len(one)))]
+            m = {"h": HADAMARD, "x": pauli_x, "y": pauli_y, "z": pauli_z, "t": T_GATE}.get(kind)
+            if m is None:
+                m = rx(float(rng.uniform(0.0, 2 * np.pi)))
+            g = c.add_gate((q,), m)
+            c.add_site(g, (q,), c.add_channel(pauli_channel(paulis[int(rng.integers(0, 3))], p)))
+    return c
+
+
 # ------------------------------------------------------------- benchmark workloads
 def chain10_d8() -> Workload:
     """10-qubit open chain, 8 brickwork layers of Haar SU(4) (complex64-rounded),
