@@ -268,6 +268,23 @@ ptsbe_status_t ptsbe_contract_batch(ptsbe_plan_t plan, int32_t j, const uint8_t*
                                     int32_t out_kind, void* d_out, double* d_elem_total,
                                     void* d_workspace, size_t workspace_bytes, void* stream);
 
+/* ptsbe_contract_batch without a caller workspace, for callers that cannot
+ * allocate device memory (serving loops and harnesses that forbid allocation):
+ * the workspace is a fixed array of PTSBE_NOALLOC_SCRATCH_BYTES in the library's
+ * own device memory, one per GPU, held until the process ends.  Same arguments,
+ * results and stream semantics as ptsbe_contract_batch (it also synchronises
+ * `stream` to check d_elem_traj); no device memory is allocated or freed.  Calls
+ * whose trajectories and elements do not fit the array (with the executor's
+ * chunking) return PTSBE_ERR_UNSUPPORTED with the sizes in ptsbe_last_error().
+ * Every call on a GPU uses the same array: calls that overlap on one GPU (other
+ * host threads, other streams) race and must be serialised by the caller.  No
+ * part of the array needs to start at zero. */
+#define PTSBE_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+ptsbe_status_t ptsbe_contract_batch_noalloc(ptsbe_plan_t plan, int32_t j, const uint8_t* d_kraus_idx,
+                                            int64_t E, const int32_t* d_elem_traj,
+                                            const uint64_t* d_elem_prefix, int64_t n_elems,
+                                            int32_t out_kind, void* d_out, double* d_elem_total, void* stream);
+
 /* Non-degenerate batched sampling, proportional mode (Sec. III-B).
  *   d_kraus_idx       [E][n_sites] uint8
  *   d_mult            [E] int64 multiplicities (NULL: all 1)

@@ -238,6 +238,21 @@ class Plan:
             out = torch.view_as_complex(out)
         return out, totals
 
+    def contract_batch_noalloc(self, j, kraus_dev, elem_traj_dev, elem_prefix_dev, out, totals=None,
+                               out_kind=OUT_POPULATION, stream=None):
+        """ptsbe_contract_batch_noalloc: the same contraction into caller-given
+        outputs (out: float32 [n_elems][2^b] populations, or float32 [n_elems][2^b][2]
+        amplitudes; totals: float64 [n_elems] or None), with the library's static
+        device scratch as the workspace (no device allocation by the library)."""
+        import torch
+        E = kraus_dev.shape[0]
+        U = elem_traj_dev.shape[0]
+        if stream is None:
+            stream = torch.cuda.current_stream(kraus_dev.device).cuda_stream
+        _lib.check(self._lib.ptsbe_contract_batch_noalloc(
+            self._h, int(j), _tptr(kraus_dev), int(E), _tptr(elem_traj_dev), _tptr(elem_prefix_dev), int(U),
+            int(out_kind), _tptr(out), _tptr(totals), C.c_void_p(stream)))
+
     def sample_shots(self, kraus_dev, shots_per_traj_dev, seed, mult_dev=None, workspace=None, stream=None,
                      want_traj=True):
         """ptsbe_sample_shots (proportional NBS); returns a dict of device tensors."""

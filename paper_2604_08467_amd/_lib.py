@@ -20,7 +20,7 @@ EXPORTS = [
     "ptsbe_ragged_autotune", "ptsbe_ragged_sample_shots", "ptsbe_plan_sv_schedule", "ptsbe_plan_right_sites",
     "ptsbe_nonproportional_workspace_size", "ptsbe_sample_nonproportional", "ptsbe_profile_read_sweeps",
     "ptsbe_plan_join_tiling", "ptsbe_plan_chunking",
-    "ptsbe_profile_read_windows",
+    "ptsbe_profile_read_windows", "ptsbe_contract_batch_noalloc",
 ]
 
 
@@ -107,6 +107,7 @@ def load():
     lib.ptsbe_sample_workspace_size.argtypes = [P, i64, i64, C.POINTER(sz)]
     lib.ptsbe_plan_chunking.argtypes = [P, i32, i64, i64, sz, P]
     lib.ptsbe_contract_batch.argtypes = [P, i32, P, i64, P, P, i64, i32, P, P, P, sz, P]
+    lib.ptsbe_contract_batch_noalloc.argtypes = [P, i32, P, i64, P, P, i64, i32, P, P, P]
     lib.ptsbe_sample_shots.argtypes = [P, P, i64, P, P, i32, u64, P, P, P, P, P, P, sz, P]
     lib.ptsbe_nonproportional_workspace_size.argtypes = [P, i64, i32, i32, i64, C.POINTER(sz)]
     lib.ptsbe_sample_nonproportional.argtypes = [P, P, i64, P, i32, i32, i64, u64, C.c_double, P, P, P, P, i64,
