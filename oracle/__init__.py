@@ -16,6 +16,8 @@ III-B of the paper):
                      variant, textbook density-matrix diagonal (pins)
 * ``tn``           - explicit ket / doubled tensor networks for one batch with the
                      prefix projected, contracted pairwise with numpy einsum
+* ``lightcone``    - the gates a doubled network keeps under the light cone
+                     (forward reachability over the gate dependency graph)
 * ``sampling``     - batch-wise conditional marginals and the per-shot sampler
                      (Sec. II-B), NBS bookkeeping (Sec. III-B), trajectory weights
 

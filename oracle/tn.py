@@ -18,13 +18,16 @@ The contraction order is the oracle's own sweep: tensors sorted by the highest
 qubit they touch (ascending for ``order="ltr"``, descending for ``"rtl"``), then
 by time, ket before bra; ``"inward"`` (default) sweeps the columns before the
 batch and the columns after it separately and then absorbs the batch columns
-between the two partial results.  No light-cone simplification is applied (the paper
-notes UPV precludes it, Sec. VI).
+between the two partial results.  ``light_cone=True`` (doubled networks only)
+keeps only the gates of ``lightcone.kept_gates``: the others cancel against their
+conjugate copies under the trace when they are unitary for every trajectory
+(Sec. VI names light-cone simplification under UPV as open).
 """
 import string
 
 import numpy as np
 
+from .lightcone import kept_gates
 from .upv import embed, inserted_operator, merged_gates, sites_of_gate
 
 LETTERS = string.ascii_letters
@@ -140,11 +143,18 @@ def _ops_explicit(circuit, kraus_row):
 
 
 def batch_network_value(circuit, kraus_row, start: int, b: int, prefix: int, kind: str,
-                        order: str = "inward", explicit: bool = False) -> np.ndarray:
+                        order: str = "inward", explicit: bool = False, light_cone: bool = False,
+                        keep=None) -> np.ndarray:
     """pi_p(x) (kind 'doubled') or amplitudes (kind 'ket') over the batch qubits,
-    index x = sum_k x_{start+k} 2^k."""
+    index x = sum_k x_{start+k} 2^k.  light_cone: drop the gates outside
+    ``lightcone.kept_gates(circuit, start + b)`` from a doubled network (``keep``:
+    a caller's own gate mask instead)."""
     n = circuit.n_qubits
     ops = _ops_explicit(circuit, kraus_row) if explicit else _ops_merged(circuit, kraus_row)
+    if (light_cone or keep is not None) and kind == "doubled":
+        assert not explicit, "the light cone selects merged gates"
+        mask = keep if keep is not None else kept_gates(circuit, start + b)
+        ops = [op for g, op in enumerate(ops) if mask[g]]
     net = _Net()
     ket_out = _ket_layer(net, n, ops, conj=False, key_shift=0)
     batch = list(range(start, start + b))

@@ -380,6 +380,73 @@ def test_gradient_value_matches_statevector_definition():
     assert abs(f - ref) < 1e-12
 
 
+def test_diagonal_observable_gradient_matches_central_difference():
+    """A general real diagonal observable with non-unitary Kraus (amplitude damping):
+    the oracle's adjoint gradient against FP64 central differences of its value."""
+    gr, c, kr, w, th, gp, ga, _ = _hea_case([W.depolarizing(0.1), W.amplitude_damping(0.2)], seed=5)
+    o = np.random.default_rng(6).normal(size=2 ** c.n_qubits)
+    g = gr.adjoint_gradient_obs(c, kr, w, th, gp, ga, o)
+    h = 1e-5
+    for k in range(len(th)):
+        tp, tm = th.copy(), th.copy()
+        tp[k] += h
+        tm[k] -= h
+        fd = (gr.value_obs(c, kr, w, tp, gp, ga, o) - gr.value_obs(c, kr, w, tm, gp, ga, o)) / (2 * h)
+        assert abs(fd - g[k]) < 1e-8, (k, fd, g[k])
+
+
+def test_gate_adjoint_matches_entrywise_finite_differences():
+    """2 dL/d conj(U_g) of the oracle against central differences of L under a real
+    (gives the real part) and an imaginary (the imaginary part) perturbation of
+    single entries of a fixed two-qubit gate and of a rotation gate's matrix."""
+    import copy
+    gr, c, kr, w, th, gp, ga, terms = _hea_case([W.depolarizing(0.1), W.amplitude_damping(0.2)], seed=7)
+    o = gr.zz_diagonal(c.n_qubits, terms)
+    adj = gr.gate_adjoint(c, kr, w, th, gp, ga, o=o)
+    fixed = [g for g in range(c.n_gates) if gp[g] < 0 and len(c.gate_qubits[g]) == 2][1]
+    rot = [g for g in range(c.n_gates) if gp[g] >= 0][3]
+    eps = 1e-6
+    for g, entries in ((fixed, [(0, 0), (1, 3), (3, 2)]), (rot, [(0, 1), (1, 1)])):
+        base = gr.rotation(ga[g], th[gp[g]]) if gp[g] >= 0 else c.gate_mats[g]
+        for (a, b) in entries:
+            for part in (1.0, 1j):
+                vals = []
+                for sgn in (1, -1):
+                    cc = copy.deepcopy(c)
+                    m = np.array(base, dtype=np.complex128)
+                    m[a, b] += sgn * eps * part
+                    cc.gate_mats[g] = m
+                    gp2 = gp.copy()
+                    gp2[g] = -1                  # the perturbed matrix replaces the rotation
+                    vals.append(gr.value_obs(cc, kr, w, th, gp2, ga, o))
+                fd = (vals[0] - vals[1]) / (2 * eps)
+                pred = adj[g][a, b].real if part == 1.0 else adj[g][a, b].imag
+                assert abs(fd - pred) < 1e-7, (g, a, b, part, fd, pred)
+
+
+def test_seeded_gradient_of_a_linear_functional():
+    """L = 2 Re sum_i <chi_i|psi_i> has psi-bar_i = chi_i: the oracle's seeded
+    gradient against central differences of L."""
+    gr, c, kr, w, th, gp, ga, _ = _hea_case([W.depolarizing(0.1)], seed=8)
+    rng = np.random.default_rng(9)
+    chis = [rng.normal(size=2 ** c.n_qubits) + 1j * rng.normal(size=2 ** c.n_qubits) for _ in kr]
+
+    def L(t):
+        tot = 0.0
+        for row, chi in zip(kr, chis):
+            psi = gr._forward_states(c, row, t, gp, ga)[3][-1]
+            tot += 2.0 * np.real(np.vdot(chi, psi))
+        return tot
+
+    g = gr.seeded_gradient(c, kr, th, gp, ga, chis)
+    h = 1e-5
+    for k in range(0, len(th), 2):
+        tp, tm = th.copy(), th.copy()
+        tp[k] += h
+        tm[k] -= h
+        assert abs((L(tp) - L(tm)) / (2 * h) - g[k]) < 1e-7, k
+
+
 def test_annihilated_trajectory_has_weight_zero_and_zero_shots():
     """Amplitude damping's K1 twice on a qubit with only a diagonal gate between
     maps every state to 0: Z = 0 exactly, the trajectory weight is 0, the
@@ -537,3 +604,83 @@ def test_nonproportional_direct_final_batch():
     assert counts == [1, 1]
     hist = np.bincount([r[0] >> 1 for r in rows], minlength=4) / N
     assert 0.5 * np.abs(hist - want).sum() <= 0.5 * math.sqrt(4 / N) + math.sqrt(math.log(1e9) / (2 * N))
+
+
+# ----------------------------------------------------------------- light cone
+def _brickwork_cone_count(n, depth, e):
+    """Kept gates of a brickwork chain (layer t pairs (q, q+1), q = t mod 2) for
+    measured qubits [0, e), by the light-speed argument: going back one layer,
+    the live prefix [0, r) grows by one qubit exactly when that layer has a gate
+    on the pair (r-1, r); every gate of the layer with q < r touches it."""
+    r, kept = e, 0
+    for t in reversed(range(depth)):
+        kept += sum(1 for q in range(t % 2, n - 1, 2) if q < r)
+        if r < n and (r - 1) % 2 == t % 2:
+            r += 1
+    return kept
+
+
+def test_light_cone_brickwork_count_closed_form():
+    """Forward reachability over the dependency graph agrees with the geometric
+    light cone of a brickwork chain (Pauli noise: every gate unitary)."""
+    from oracle import lightcone
+    rng = np.random.default_rng(3)
+    for n, depth in [(12, 4), (16, 6), (13, 5)]:
+        c = W.random_brickwork(n, depth, rng, 0.05)
+        for e in range(1, n + 1):
+            keep = lightcone.kept_gates(c, e)
+            assert int(keep.sum()) == _brickwork_cone_count(n, depth, e), (n, depth, e)
+            assert all(keep[g] for g in range(c.n_gates) if min(c.gate_qubits[g]) < e)
+
+
+def test_light_cone_doubled_network_equals_full_for_unitary_trajectories():
+    """Pauli channels: the pruned doubled network gives the full network's
+    marginal for every prefix of several batches, whatever the Kraus choices."""
+    rng = np.random.default_rng(5)
+    n = 9
+    c = W.random_brickwork(n, 5, rng, 0.3)
+    c2 = W.small_random_circuit(n, 30, rng, [W.depolarizing(0.3)], two_qubit_frac=0.6)
+    for circ in (c, c2):
+        S = len(circ.site_gate)
+        for trial in range(3):
+            kr = rng.integers(0, 4, size=S).astype(np.uint8)
+            for start, b in [(0, 3), (3, 2), (5, 2)]:
+                for prefix in range(0, 1 << start, max(1, (1 << start) // 3)):
+                    full = tn.batch_network_value(circ, kr, start, b, prefix, "doubled")
+                    cut = tn.batch_network_value(circ, kr, start, b, prefix, "doubled", light_cone=True)
+                    np.testing.assert_allclose(cut, full, rtol=0, atol=1e-12)
+
+
+def test_light_cone_keeps_non_unitary_gates_and_their_past():
+    """Amplitude damping on gates outside the measured qubits' light cone: keeping
+    those gates and their past reproduces the full network; the plain light cone
+    (a plausible mistake) does not."""
+    from oracle import lightcone
+    rng = np.random.default_rng(9)
+    n = 8
+    c = W.Circuit(n)
+    dep = c.add_channel(W.depolarizing(0.2))
+    ad = c.add_channel(W.amplitude_damping(0.6))
+    for layer in W.brickwork_1d(n, 4):
+        for (a, b2) in layer:
+            g = c.add_gate((a, b2), W.haar_su4(rng))
+            c.add_site(g, (a,), dep)
+            if a >= 5:
+                c.add_site(g, (b2,), ad)
+    S = len(c.site_gate)
+    start, b = 0, 2
+    plain = lightcone.kept_gates(c, start + b, respect_non_unitary=False)
+    full_keep = lightcone.kept_gates(c, start + b)
+    assert full_keep.sum() > plain.sum()
+    worst_plain = 0.0
+    for trial in range(4):
+        kr = np.zeros(S, dtype=np.uint8)
+        for s in range(S):
+            ch = c.site_channel[s]
+            kr[s] = rng.integers(0, 4) if ch == dep else 1     # the decay operator everywhere
+        full = tn.batch_network_value(c, kr, start, b, 0, "doubled")
+        cut = tn.batch_network_value(c, kr, start, b, 0, "doubled", light_cone=True)
+        np.testing.assert_allclose(cut, full, rtol=0, atol=1e-12)
+        wrong = tn.batch_network_value(c, kr, start, b, 0, "doubled", keep=plain)
+        worst_plain = max(worst_plain, float(np.abs(wrong - full).max()))
+    assert worst_plain > 1e-3
