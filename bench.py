@@ -156,11 +156,13 @@ def main():
                     help="exhaustive-paper workload: n x g points of the paper's random-circuit family")
     ap.add_argument("--final-batches", default="20,24,28", help="exhaustive-paper workload: b_f values")
     ap.add_argument("--workload", choices=["brickwork50", "ragged", "exhaustive", "batch-sweep", "grid5x5",
-                                           "exhaustive-paper"],
+                                           "exhaustive-paper", "hea20"],
                     default="brickwork50",
                     help="ragged: the ragged mix of circuits as one graph-captured ragged set; grid5x5: the 25-qubit "
                          "grid with amplitude damping, 16384 x 256 (statevector method, --precision c64|bf16|f16)")
     ap.add_argument("--ragged-max-qubits", type=int, default=26)
+    ap.add_argument("--ragged-scope", choices=["statevector", "all"], default="statevector",
+                    help="all: also the network-method plans of the mix, on a second stream")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -186,6 +188,9 @@ def main():
         return
     if args.workload == "exhaustive-paper":
         bench_exhaustive_paper(args)
+        return
+    if args.workload == "hea20":
+        bench_hea20(args)
         return
     if args.copy_calibration:
         n = 1 << 30
@@ -247,7 +252,7 @@ def main():
                 "frac": achieved / peak, "traffic": traffic if args.precision == "c64" else None,
                 "kernel": "qform_mfma_kernel<32,8> (doubled-network join as a real GEMM over K^2 folded slots, "
                           "FP32 MFMA)" if args.precision == "c64"
-                          else f"qform_split_kernel<32,4> (doubled-network join as the K^2-slot GEMM, {args.precision} "
+                          else f"qform_split_kernel<32,8> (doubled-network join as the K^2-slot GEMM, {args.precision} "
                                "hi+lo operands, three products on 16-bit MFMA, FP32 accumulate)",
                 "flops": "real bilinear form over K^2 folded slots: 2K^2 per row and x (K=32: 2048; "
                          "the plain complex product would be 8320)",
@@ -474,9 +479,9 @@ def bench_grid(args):
                      "launches": win["launches"], "avg_us": win["ms"] * 1e3 / max(win["launches"], 1),
                      "bytes_per_step": win["bytes"] / args.steps, "kernel_ms_per_step": win["ms"] / args.steps},
     }
+    print("grid5x5: error vs FP64 on the stored oracle marginals", file=sys.stderr, flush=True)
+    line["error_vs_fp64"] = grid_error_vs_fp64(plan, torch, dev)
     if not args.no_cpu_baseline:
-        print("grid5x5: error vs FP64 on the stored oracle marginals", file=sys.stderr, flush=True)
-        line["error_vs_fp64"] = grid_error_vs_fp64(plan, torch, dev)
         print("grid5x5: CPU oracle baseline", file=sys.stderr, flush=True)
         cores = min(host_cores(), E)
         budget = 20.0
@@ -493,6 +498,122 @@ def bench_grid(args):
                       f"{budget:.0f} s each ({min(g for g, _ in res)}..{max(g for g, _ in res)} of {G} gates "
                       f"applied; {wall:.1f} s wall); time per trajectory extrapolated linearly to all {G} gates, "
                       f"{m} shots per trajectory (marginals and draws not counted)"}
+    print(json.dumps(line), flush=True)
+
+
+def _oracle_hea20_worker(kraus_row, theta, gp, ga, terms):
+    """One trajectory of the 20-qubit ansatz through the FP64 oracle: the
+    adjoint gradient of <sum Z_i Z_i+1> and the value, one thread."""
+    from threadpoolctl import threadpool_limits
+
+    import workloads as W
+    from oracle import gradients as gr
+
+    c = W.hea20_l10().circuit
+    t0 = time.perf_counter()
+    with threadpool_limits(limits=1):
+        g = gr.adjoint_gradient(c, [kraus_row], [1.0], theta, gp, ga, terms)
+        f = gr.value(c, [kraus_row], [1.0], theta, gp, ga, terms)
+    return g, f, time.perf_counter() - t0
+
+
+def bench_hea20(args):
+    """The 20-qubit hardware-efficient ansatz (10 layers of RY RZ on every qubit and
+    a CNOT ladder, 400 angles in [0, 2 pi), depolarising 0.01 after every gate),
+    1024 trajectories: one step = the trajectory-weighted value of sum_i Z_i Z_i+1
+    and its gradient with respect to all 400 angles (ptsbe_expect_grad: windowed
+    forward with checkpoints, adjoint seed, windowed backward)."""
+    import numpy as np
+    import torch
+
+    import paper_2604_08467_amd as P
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    wl = W.hea20_l10()
+    c = wl.circuit
+    theta = W.hea20_angles().astype(np.float64)
+    gp, ga = W.rotation_spec(c)
+    terms = W.zz_chain_terms(c.n_qubits)
+    plan = P.Plan(c, [c.n_qubits])
+    E_req = args.traj if args.traj != 4096 else wl.n_traj
+    kr, mult, _, n_draws = plan.sample_trajectories(wl.pts_seed, E_req)
+    E = len(kr)
+    w = mult / mult.sum()
+    spec = P.GradSpec(len(theta), gp, ga, terms)
+    kd = torch.from_numpy(kr).to(dev)
+    wd = torch.from_numpy(w).to(dev)
+    td = torch.from_numpy(theta).to(dev)
+    ws = torch.empty(int(args.workspace_gb * (1 << 30)), dtype=torch.uint8, device=dev)
+    print(f"hea20: E={E}, {len(theta)} angles", file=sys.stderr, flush=True)
+
+    def step():
+        return plan.expect_grad(spec, kd, wd, td, want_grad=True, workspace=ws)
+
+    for k in range(args.warmup):
+        t_w = time.perf_counter()
+        out = step()
+        torch.cuda.synchronize()
+        print(f"hea20: warmup {k} {time.perf_counter() - t_w:.2f} s", file=sys.stderr, flush=True)
+    plan.profile_enable(1)
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        out = step()
+        torch.cuda.synchronize()
+        print(f"hea20: step {k} done at {time.perf_counter() - t0:.2f} s", file=sys.stderr, flush=True)
+    dt = time.perf_counter() - t0
+    win = plan.profile_read_windows()
+    plan.profile_enable(0)
+    t_v = time.perf_counter()
+    plan.expect_grad(spec, kd, wd, td, want_grad=False, workspace=ws)
+    torch.cuda.synchronize()
+    value_only_ms = (time.perf_counter() - t_v) * 1e3
+    achieved = win["bytes"] / (win["ms"] / 1e3) / 1e9 if win["ms"] > 0 else 0.0
+    line = {
+        "metric": "trajectory value+gradient evaluations/sec", "value": E * args.steps / dt,
+        "unit": "trajectories/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "c64", "data": "synthetic",
+        "config": {"workload": f"20-qubit hardware-efficient ansatz, 10 layers RY RZ + CNOT ladder, 400 angles, "
+                               f"depolarising 0.01, {E} trajectories; weighted <sum Z_i Z_i+1> and its gradient "
+                               f"(adjoint contraction)",
+                   "trajectories": E, "angles": len(theta), "pts_draws": int(n_draws),
+                   "value_only_ms": value_only_ms},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "adj_window_kernel (forward windows: checkpoint read, next written, 16 B per "
+                               "amplitude; backward windows: state read, adjoint state read and written, 24 B)",
+                     "launches": win["launches"], "avg_us": win["ms"] * 1e3 / max(win["launches"], 1),
+                     "bytes_per_step": win["bytes"] / args.steps, "kernel_ms_per_step": win["ms"] / args.steps},
+    }
+    if not args.no_cpu_baseline:
+        # the oracle on a bounded sample: trajectories 0.. (one worker process per
+        # core); the same trajectories, with their multiplicities as weights, on the
+        # GPU give the run's error against FP64
+        cores = min(host_cores(), E)
+        print(f"hea20: FP64 oracle on {cores} trajectories", file=sys.stderr, flush=True)
+        pick = list(range(cores))
+        wp = np.zeros(E)
+        wp[pick] = mult[pick] / mult[pick].sum()
+        t_c = time.perf_counter()
+        with _pool(cores) as pool:
+            futs = [pool.submit(_oracle_hea20_worker, kr[k], theta, gp, ga, terms) for k in pick]
+            gpu = plan.expect_grad(spec, kd, torch.from_numpy(wp).to(dev), td, want_grad=True, workspace=ws)
+            torch.cuda.synchronize()
+            res = [f.result() for f in futs]
+        wall = time.perf_counter() - t_c
+        g_ref = sum(wp[k] * r[0] for k, r in zip(pick, res))
+        f_ref = sum(wp[k] * r[1] for k, r in zip(pick, res))
+        g = gpu["grad"].cpu().numpy()
+        line["error_vs_fp64"] = {
+            "value_abs_error": abs(float(gpu["value"].item()) - f_ref),
+            "gradient_rel_l2_error": float(np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref)),
+            "gradient_max_abs_error": float(np.abs(g - g_ref).max()),
+            "reference": f"FP64 oracle adjoint gradient of trajectories 0..{cores - 1}, weighted by multiplicity"}
+        line["cpu_baseline"] = {
+            "value": cores / wall, "unit": "trajectories/s", "cores": cores, "kind": "oracle",
+            "sample": f"value and adjoint gradient of trajectories 0..{cores - 1}, one worker process per core "
+                      f"({wall:.1f} s wall, {np.mean([r[2] for r in res]):.1f} s per trajectory)"}
     print(json.dumps(line), flush=True)
 
 
@@ -647,9 +768,16 @@ def bench_batch_sweep(args):
 
 def bench_ragged(args):
     """Ragged mix of circuits (n ~ U{12..40}, depth 4..10, 1D/2D, E log-uniform
-    32..2048, 100 shots each): the circuits the statevector method takes
-    (n <= --ragged-max-qubits) run as one ragged set, graph-captured, after one
-    autotune pass.  One step = every shot of every such circuit."""
+    32..2048, 100 shots each).  Every circuit ptsbe_plan accepts runs in one step:
+    the statevector-method plans (n <= --ragged-max-qubits) as one ragged set,
+    graph-captured after one autotune pass, light circuits in the first waves;
+    with --ragged-scope all, the network-method plans run at the same time on a
+    second stream from a second host thread, lightest first.  Circuits no method
+    takes (2D beyond 30 qubits) are listed as excluded.  One step = every shot of
+    every included circuit; latency = completion time of each circuit from the
+    step's start (device stamps for the set, host clock for the network plans)."""
+    import threading
+
     import numpy as np
     import torch
 
@@ -659,24 +787,52 @@ def bench_ragged(args):
 
     dev = torch.device("cuda:0")
     mix = W.ragged_mix()
-    jobs, excluded = [], []
+    jobs, net_jobs, excluded = [], [], []
     t_plan = time.perf_counter()
     for k, c in enumerate(mix):
         n = c["circuit"].n_qubits
-        if n > args.ragged_max_qubits:
-            excluded.append(n)
+        try:
+            plan = P.Plan(c["circuit"], c["batch_sizes"], hypersamples=2)
+        except P.PtsbeError as e:
+            excluded.append({"n": n, "reason": str(e)[:120]})
             continue
-        plan = P.Plan(c["circuit"], c["batch_sizes"], method="statevector")
+        if plan.method == "statevector" and n > args.ragged_max_qubits:
+            if args.ragged_scope != "all":
+                excluded.append({"n": n, "reason": f"statevector plan beyond --ragged-max-qubits {args.ragged_max_qubits}"})
+                continue
+        if plan.method == "network" and args.ragged_scope != "all":
+            excluded.append({"n": n, "reason": "network-method plan (--ragged-scope all runs it)"})
+            continue
         kr, mult, _, _ = plan.sample_trajectories(c["pts_seed"], c["n_traj"])
-        jobs.append({"plan": plan, "kraus": torch.from_numpy(kr).to(dev), "mult": torch.from_numpy(mult).to(dev),
-                     "shots_per_traj": np.full(len(kr), c["shots_per_traj"], dtype=np.int64),
-                     "seed": c["shot_seed"]})
+        job = {"plan": plan, "kraus": torch.from_numpy(kr).to(dev), "mult": torch.from_numpy(mult).to(dev),
+               "shots_per_traj": np.full(len(kr), c["shots_per_traj"], dtype=np.int64), "seed": c["shot_seed"],
+               "n": n, "layout": c.get("layout", "")}
+        (jobs if plan.method == "statevector" else net_jobs).append(job)
     t_plan = time.perf_counter() - t_plan
-    print(f"ragged: {len(jobs)} plans + PTS in {t_plan:.1f} s", file=sys.stderr, flush=True)
+    print(f"ragged: {len(jobs)} statevector plans in the set, {len(net_jobs)} network plans, {len(excluded)} excluded; "
+          f"plans + PTS {t_plan:.1f} s", file=sys.stderr, flush=True)
+    net_ws_gb = min(48.0, args.workspace_gb / 3) if net_jobs else 0.0
+    # network plans lightest first (per-trajectory right-part bytes x trajectories)
+    def net_cost(j):
+        p = j["plan"]
+        return sum(p.batch_info(b)["bytes_per_traj"] for b in range(len(p.batch_sizes))) * j["kraus"].shape[0]
+    net_jobs.sort(key=net_cost)
     rs = RaggedSet()
     stream = torch.cuda.Stream(dev)
+    stream2 = torch.cuda.Stream(dev)
     with torch.cuda.stream(stream):
-        ws = torch.empty(int(args.workspace_gb * (1 << 30)), dtype=torch.uint8, device=dev)
+        ws = torch.empty(int((args.workspace_gb - net_ws_gb) * (1 << 30)), dtype=torch.uint8, device=dev)
+    ws2 = torch.empty(int(net_ws_gb * (1 << 30)), dtype=torch.uint8, device=dev) if net_jobs else None
+    net_md = [torch.from_numpy(j["shots_per_traj"]).to(dev) for j in net_jobs]
+
+    def run_network(t0, out_lat):
+        with torch.cuda.stream(stream2):
+            for j, md in zip(net_jobs, net_md):
+                j["plan"].sample_shots(j["kraus"], md, j["seed"], mult_dev=j["mult"], workspace=ws2,
+                                       stream=stream2.cuda_stream)
+                out_lat.append((time.perf_counter() - t0) * 1e3)
+
+    with torch.cuda.stream(stream):
         t_tune = time.perf_counter()
         best, ms = rs.autotune(jobs, workspace=ws, stream=stream.cuda_stream)
         print(f"ragged: autotune {time.perf_counter() - t_tune:.1f} s, windows "
@@ -684,44 +840,67 @@ def bench_ragged(args):
         outs = None
         for k in range(args.warmup):
             t_w = time.perf_counter()
+            nl = []
+            th = threading.Thread(target=run_network, args=(t_w, nl))
+            th.start()
             outs, lat = rs.sample_shots(jobs, graph=True, workspace=ws, stream=stream.cuda_stream, outputs=outs)
+            stream.synchronize()
+            th.join()
             print(f"ragged: warmup {k} {time.perf_counter() - t_w:.1f} s, {rs.info()}", file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        lats = []
+        lats, nlats = [], []
         for k in range(args.steps):
+            ts = time.perf_counter()
+            nl = []
+            th = threading.Thread(target=run_network, args=(ts, nl))
+            th.start()
             outs, lat = rs.sample_shots(jobs, graph=True, workspace=ws, stream=stream.cuda_stream, outputs=outs)
-            lats.append(lat)
-            print(f"ragged: step {k} done at {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+            stream.synchronize()
+            t_set = (time.perf_counter() - ts) * 1e3
+            th.join()
+            lats.append(lat / 1e3)
+            nlats.append(np.array(nl))
+            print(f"ragged: step {k} done at {time.perf_counter() - t0:.1f} s (set {t_set / 1e3:.1f} s)",
+                  file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
     info = rs.info()
-    M = sum(int(np.sum(j["shots_per_traj"])) for j in jobs)
-    lat = np.concatenate(lats) / 1e3   # ms
+    M = sum(int(np.sum(j["shots_per_traj"])) for j in jobs + net_jobs)
+    lat_all = np.concatenate([np.concatenate([a, b]) for a, b in zip(lats, nlats)])   # ms
+    lat_sv = np.concatenate(lats)
     # algorithmic bytes of the gate windows: read + write of every state once per window
     win_bytes = 0.0
     for jb, bw in zip(jobs, best):
         p = jb["plan"]
         win_bytes += float(jb["kraus"].shape[0]) * 16.0 * (2 ** p.n_qubits) * p.sv_windows_for(int(bw))
+    n_all = [j["n"] for j in jobs + net_jobs]
     line = {
         "metric": "sampled shots/sec", "value": M * args.steps / dt, "unit": "shots/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c64", "data": "synthetic",
         "config": {"workload": f"ragged mix of {len(mix)} circuits (n 12..40, depth 4..10, 1D/2D Haar SU(4), "
-                               f"depolarising 0.005, E log-uniform 32..2048, 100 shots); the {len(jobs)} with "
-                               f"n <= {args.ragged_max_qubits} as one graph-captured ragged set",
-                   "circuits": len(jobs), "excluded_circuits": len(excluded), "trajectories":
-                   int(sum(j["kraus"].shape[0] for j in jobs)), "shots": M, "waves": info["n_waves"],
-                   "graphs_replayed": info["graphs_replayed"],
-                   "latency_ms_p50": float(np.percentile(lat, 50)), "latency_ms_p99": float(np.percentile(lat, 99)),
+                               f"depolarising 0.005, E log-uniform 32..2048, 100 shots): {len(jobs)} statevector "
+                               f"plans as one graph-captured ragged set"
+                               + (f" + {len(net_jobs)} network-method plans on a second stream" if net_jobs else ""),
+                   "circuits": len(jobs) + len(net_jobs), "ragged_set_circuits": len(jobs),
+                   "network_circuits": len(net_jobs), "excluded_circuits": len(excluded),
+                   "excluded_reasons": sorted({e["reason"] for e in excluded}),
+                   "qubits_range": [int(min(n_all)), int(max(n_all))] if n_all else None,
+                   "trajectories": int(sum(j["kraus"].shape[0] for j in jobs + net_jobs)), "shots": M,
+                   "waves": info["n_waves"], "graphs_replayed": info["graphs_replayed"],
+                   "latency_ms_p50": float(np.percentile(lat_all, 50)), "latency_ms_p99": float(np.percentile(lat_all, 99)),
+                   "latency_ms_min": float(np.min(lat_all)),
+                   "ragged_set_latency_ms_p50": float(np.percentile(lat_sv, 50)),
+                   "ragged_set_latency_ms_p99": float(np.percentile(lat_sv, 99)),
                    "autotuned_windows": {str(w): int(np.sum(best == w)) for w in (10, 11, 12)},
                    "plan_and_pts_s": t_plan},
         "roofline": {"bound": "hbm", "achieved": win_bytes / (dt / args.steps) / 1e9, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": win_bytes / (dt / args.steps) / 1e9 / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "rg_window_kernel gate windows (state read+write per window), over the whole step time"},
+                     "kernel": "rg_window_kernel gate windows of the ragged set (state read+write per window), "
+                               "over the whole step time"},
     }
     print(json.dumps(line), flush=True)
-
 
 if __name__ == "__main__":
     main()

@@ -138,6 +138,22 @@ typedef struct {
                                    query and pre-sampling only, no device calls) */
   size_t device_budget_bytes;   /* 0: no limit; else plan constants must fit     */
   int32_t method;               /* PTSBE_METHOD_*                                 */
+  int32_t light_cone;           /* 1: every doubled network (batches before the
+                                   last) keeps only the gates in the past light
+                                   cone of its prefix and batch qubits, plus every
+                                   gate that is not unitary for some trajectory
+                                   (bare gate or a possible inserted K / sqrt(q)
+                                   with |M^dag M - I| > 1e-6) and that gate's
+                                   past: the removed gates meet their adjoints and
+                                   cancel under the trace (an extension of the
+                                   unified path; Sec. VI names light-cone
+                                   simplification under UPV as open).  The kept
+                                   set depends on channel types only, so one path
+                                   serves every trajectory.  Results equal the full
+                                   network's up to the removed gates' deviation
+                                   from unitarity.  0: full networks.  Network
+                                   method only (the statevector method ignores
+                                   it); other values: INVALID_ARG                */
 } ptsbe_plan_opts_t;
 
 typedef struct {
@@ -152,6 +168,7 @@ typedef struct {
                                    matrices applied on MFMA) in those windows    */
   int32_t sv_cluster_steps;     /* gates applied inside those clusters           */
   int32_t precision;            /* the plan's precision option                    */
+  int32_t light_cone;           /* the plan's light-cone option                   */
 } ptsbe_plan_info_t;
 
 /* Per-batch description of the unified path P^j (host-side cost model). */
@@ -178,6 +195,8 @@ typedef struct {
                                    runs as one LDS sweep)                        */
   int32_t n_right_fused_steps;  /* per-trajectory steps inside fused in-place runs */
   int32_t right_longest_run;    /* steps of the longest fused run                */
+  int32_t kept_gates;           /* gates in the batch's network (all of them
+                                   unless the light cone removed some)           */
 } ptsbe_batch_info_t;
 
 ptsbe_status_t ptsbe_plan(const ptsbe_circuit_t* circuit, const ptsbe_plan_opts_t* opts,
@@ -348,21 +367,61 @@ ptsbe_status_t ptsbe_sample_nonproportional(ptsbe_plan_t plan, const uint8_t* d_
                                             double* d_traj_weight, double* d_traj_norm, int64_t* stats_out,
                                             void* d_workspace, size_t workspace_bytes, void* stream);
 
-/* Differentiation of trajectory-averaged observables (an addition to the
- * paper's method; its networks and UPV merge are reused).
- *   - Rotation gates: gate g with gate_param[g] >= 0 has matrix
- *     exp(-i theta[gate_param[g]] P / 2), P = X, Y, Z for gate_axis[g] = 0, 1, 2;
- *     its matrix in the plan's circuit is ignored.  Several gates may share a
- *     parameter.
- *   - Observable O = sum_t zz_coef[t] Z_{zz_qubits[2t]} Z_{zz_qubits[2t+1]}.
- *   - Error sets are fixed; f = sum_i w_i <psi_i|O|psi_i> with psi_i the UPV-merged
- *     gates (Sec. III-A) applied in circuit order to |0...0> (n_qubits <= 30).
- *   - Gradient by the adjoint contraction: lambda_N = O psi_N,
- *     lambda_{k-1} = A_k^dag lambda_k and df/dtheta += 2 w_i Re <lambda_k|(dA_k/dtheta) psi_{k-1}>,
- *     where dA_k = (inserted operators of gate k) . dU_k/dtheta.  States psi_k are
- *     checkpointed every checkpoint_every gates in the forward pass and
- *     recomputed segment by segment in the backward pass (valid for non-unitary
- *     Kraus operators as well). */
+/* Differentiation of trajectory-averaged quantities (an addition to the paper's
+ * method; its unified gate schedule and UPV merge (Sec. III-A) are reused).
+ *   - Rotation gates: gate g with gate_param[g] >= 0 has the matrix
+ *     U_g = exp(-i theta[gate_param[g]] P / 2), P = X, Y, Z for gate_axis[g] = 0,
+ *     1, 2; its matrix in the plan's circuit is ignored.  Several gates may share
+ *     a parameter.  Other gates keep their matrix U_g.
+ *   - Error sets are fixed; psi_i is the trajectory's state: the UPV-merged gates
+ *     A_g = (inserted operators of g) U_g applied in circuit order to |0...0>
+ *     (n_qubits <= 30, any method).
+ *   - The quantity differentiated is L = sum_i w_i <psi_i|O|psi_i> for a
+ *     diagonal observable O (the ZZ terms, or d_obs_diag), or, with d_psi_bar,
+ *     any real L(psi_1, ..., psi_E) whose conjugate-Wirtinger derivative
+ *     psi-bar_i = dL / d conj(psi_i) the caller supplies (then dL = 2 Re sum_i
+ *     <psi-bar_i | d psi_i>).
+ *   - Adjoint contraction: the ket network of every trajectory is contracted
+ *     through LDS gate windows of at most 11 qubits, the state after each window
+ *     kept as a checkpoint; the backward pass walks the windows in reverse with
+ *     lambda = psi-bar (or w_i O psi_i), lambda_{k-1} = A_k^dag lambda_k, and
+ *     psi_{k-1} = A_k^dag psi_k when every inserted operator is unitary (mixed-
+ *     unitary channels), else recomputed from the window's checkpoint.  It gives
+ *     dL/dtheta = sum over gates of the parameter of Im <lambda_{k-1}|P|psi_{k-1}>
+ *     and the gate-tensor adjoint 2 dL/d conj(U_g) = 2 U_g sum_i sum_rest
+ *     lambda_{k-1} psi_{k-1}^dag (torch's convention for a real loss).  Sums over
+ *     trajectories and tiles are FP64 in a fixed order (deterministic). */
+typedef struct {
+  int32_t n_params;
+  const int32_t* gate_param;    /* [n_gates] (host) parameter index, -1 for fixed (NULL: none) */
+  const int32_t* gate_axis;     /* [n_gates] (host) 0 X, 1 Y, 2 Z                  */
+  int32_t n_terms;              /* O = sum_t zz_coef[t] Z_a Z_b when d_obs_diag is NULL */
+  const int32_t* zz_qubits;     /* [n_terms][2] (host), at most 64 terms          */
+  const double* zz_coef;        /* [n_terms] (host)                                */
+  const double* d_obs_diag;     /* [2^n] (device) real diagonal of O, or NULL      */
+} ptsbe_adjoint_spec_t;
+
+ptsbe_status_t ptsbe_adjoint_workspace_size(ptsbe_plan_t plan, const ptsbe_adjoint_spec_t* spec, int64_t E,
+                                            size_t* bytes);
+/*   d_kraus_idx [E][n_sites] uint8, d_weights [E] double w_i, d_theta [n_params]
+ *   double (device).  d_psi_bar: NULL, or [E][2^n] complex64 (interleaved, device)
+ *   seeds of the backward pass.  Outputs (device, each may be NULL):
+ *   d_traj_value [E] <psi_i|O|psi_i> and d_value [1] sum_i w_i <psi_i|O|psi_i>
+ *   (need an observable); d_grad [n_params] dL/dtheta; d_gate_adj [n_gates][16]
+ *   complex128 (interleaved; the first d*d entries, row-major in the gate's own
+ *   index order): 2 dL/d conj(U_g).  Without d_grad and d_gate_adj only the
+ *   forward pass runs.  Workspace: ptsbe_adjoint_workspace_size (trajectories
+ *   run in chunks that fit it).  Synchronises `stream`. */
+ptsbe_status_t ptsbe_contract_adjoint(ptsbe_plan_t plan, const ptsbe_adjoint_spec_t* spec,
+                                      const uint8_t* d_kraus_idx, int64_t E, const double* d_weights,
+                                      const double* d_theta, const void* d_psi_bar, double* d_traj_value,
+                                      double* d_value, double* d_grad, double* d_gate_adj, void* d_workspace,
+                                      size_t workspace_bytes, void* stream);
+
+/* The ZZ-observable form of the same contraction: f = sum_i w_i <psi_i|O|psi_i>
+ * with O = sum_t zz_coef[t] Z_a Z_b, its value and (d_grad non-NULL) its angle
+ * gradient.  checkpoint_every is kept for compatibility (must be >= 1; the
+ * checkpoints are the window boundaries). */
 typedef struct {
   int32_t n_params;
   const int32_t* gate_param;    /* [n_gates] (host) parameter index, -1 for fixed */
@@ -377,7 +436,7 @@ ptsbe_status_t ptsbe_expect_workspace_size(ptsbe_plan_t plan, const ptsbe_grad_s
                                            size_t* bytes);
 /*   d_kraus_idx [E][n_sites] uint8, d_weights [E] double w_i, d_theta [n_params] double;
  *   outputs: d_traj_value [E] <psi_i|O|psi_i> (may be NULL), d_value [1] f,
- *   d_grad [n_params] df/dtheta (NULL: value only).  Synchronises `stream`. */
+ *   d_grad [n_params] df/dtheta (NULL: value only, forward pass only).  Synchronises `stream`. */
 ptsbe_status_t ptsbe_expect_grad(ptsbe_plan_t plan, const ptsbe_grad_spec_t* spec, const uint8_t* d_kraus_idx,
                                  int64_t E, const double* d_weights, const double* d_theta,
                                  double* d_traj_value, double* d_value, double* d_grad, void* d_workspace,
@@ -466,7 +525,10 @@ ptsbe_status_t ptsbe_profile_read_sweeps(ptsbe_plan_t plan, double* step_ms, int
 /* Statevector-method gate windows (any level >= 1): total event time of the
  * window launches (events recorded on the launch stream), launches, and
  * algorithmic bytes (every trajectory state of the launch read and written once:
- * 16 * 2^n bytes per trajectory and window). */
+ * 16 * 2^n bytes per trajectory and window).  The windows of
+ * ptsbe_contract_adjoint count here too: 16 * 2^n bytes per trajectory for a
+ * forward window (checkpoint read, next checkpoint written) and 24 * 2^n for a
+ * backward window (state read, adjoint state read and written). */
 ptsbe_status_t ptsbe_profile_read_windows(ptsbe_plan_t plan, double* ms, int64_t* launches, double* bytes);
 
 #ifdef __cplusplus

@@ -16,7 +16,7 @@ import numpy as np
 from . import _lib
 from ._lib import PtsbeError
 
-__all__ = ["Plan", "PtsbeError", "GradSpec", "ExpectZZ", "load_library", "OUT_POPULATION", "OUT_AMPLITUDE"]
+__all__ = ["Plan", "PtsbeError", "GradSpec", "AdjointSpec", "ExpectZZ", "load_library", "OUT_POPULATION", "OUT_AMPLITUDE"]
 
 OUT_POPULATION = 0
 OUT_AMPLITUDE = 1
@@ -74,6 +74,25 @@ class _CircuitArrays:
             _ptr(self.site_channel, C.c_int32))
 
 
+class AdjointSpec:
+    """Rotation gates and a diagonal observable for Plan.contract_adjoint
+    (ptsbe_adjoint_spec_t): ZZ terms [(a, b), coef], or obs_diag, a float64 device
+    tensor of 2^n entries (kept alive by this object)."""
+
+    def __init__(self, n_params, gate_param, gate_axis, terms=(), obs_diag=None):
+        self.n_params = int(n_params)
+        self.gate_param = np.ascontiguousarray(gate_param, dtype=np.int32)
+        self.gate_axis = np.ascontiguousarray(gate_axis, dtype=np.int32)
+        terms = list(terms)
+        self.zz_qubits = np.ascontiguousarray([q for (q, _c) in terms] or [(0, 0)], dtype=np.int32).reshape(-1)
+        self.zz_coef = np.ascontiguousarray([cf for (_q, cf) in terms] or [0.0], dtype=np.float64)
+        self.obs_diag = obs_diag
+        self.struct = _lib.AdjointSpec_t(self.n_params, _ptr(self.gate_param, C.c_int32),
+                                         _ptr(self.gate_axis, C.c_int32), len(terms),
+                                         _ptr(self.zz_qubits, C.c_int32), _ptr(self.zz_coef, C.c_double),
+                                         _tptr(obs_diag))
+
+
 class GradSpec:
     """Rotation gates and ZZ observable for Plan.expect_grad (ptsbe_grad_spec_t)."""
 
@@ -97,7 +116,7 @@ class Plan:
     """ptsbe_plan: the unified contraction path of every batch (host, once)."""
 
     def __init__(self, circuit, batch_sizes, hypersamples=4, path_seed=0, device=0, precision=0,
-                 device_budget_bytes=0, method="auto"):
+                 device_budget_bytes=0, method="auto", light_cone=False):
         self._lib = _lib.load()
         self.n_qubits = circuit.n_qubits
         self.n_sites = len(circuit.site_gate)
@@ -107,7 +126,7 @@ class Plan:
         if method not in METHODS:
             raise ValueError(f"method must be one of {sorted(METHODS)}")
         opts = _lib.PlanOpts_t(len(bs), _ptr(bs, C.c_int32), int(hypersamples), int(path_seed), int(precision),
-                               int(device), int(device_budget_bytes), METHODS[method])
+                               int(device), int(device_budget_bytes), METHODS[method], int(light_cone))
         h = C.c_void_p()
         _lib.check(self._lib.ptsbe_plan(C.byref(arrs.struct), C.byref(opts), C.byref(h)))
         self._h = h
@@ -123,6 +142,7 @@ class Plan:
         self.sv_clusters = info.sv_clusters
         self.sv_cluster_steps = info.sv_cluster_steps
         self.precision = info.precision
+        self.light_cone = bool(info.light_cone)
 
     def sv_windows_for(self, window_qubits):
         """Gate windows (state passes) of the statevector schedule for windows of
@@ -344,6 +364,36 @@ class Plan:
             _tptr(traj), _tptr(value), _tptr(grad), _tptr(workspace), int(workspace.numel()), C.c_void_p(stream)))
         return {"value": value[0], "traj_values": traj, "grad": None if grad is None else grad[:spec.n_params]}
 
+    def contract_adjoint(self, spec, kraus_dev, weights_dev, theta_dev=None, psi_bar=None, want_grad=True,
+                         want_gate_adj=False, want_values=True, workspace=None, stream=None):
+        """ptsbe_contract_adjoint: values (with an observable), the angle gradient and
+        (want_gate_adj) the gate-tensor adjoints 2 dL/d conj(U_g), complex128 [n_gates][16].
+        psi_bar: complex64 device tensor [E][2^n], the seed dL/d conj(psi_i)."""
+        import torch
+        E = kraus_dev.shape[0]
+        dev = kraus_dev.device
+        value = torch.empty(1, dtype=torch.float64, device=dev) if want_values else None
+        traj = torch.empty(E, dtype=torch.float64, device=dev) if want_values else None
+        grad = torch.empty(max(spec.n_params, 1), dtype=torch.float64, device=dev) if want_grad else None
+        gadj = torch.empty((self.n_gates, 16, 2), dtype=torch.float64, device=dev) if want_gate_adj else None
+        if theta_dev is None:
+            theta_dev = torch.zeros(max(spec.n_params, 1), dtype=torch.float64, device=dev)
+        if psi_bar is not None:
+            psi_bar = torch.view_as_real(psi_bar.to(torch.complex64).contiguous()).contiguous()
+        if workspace is None:
+            b = C.c_size_t()
+            _lib.check(self._lib.ptsbe_adjoint_workspace_size(self._h, C.byref(spec.struct), int(E), C.byref(b)))
+            workspace = torch.empty(b.value, dtype=torch.uint8, device=dev)
+        if stream is None:
+            stream = torch.cuda.current_stream(dev).cuda_stream
+        _lib.check(self._lib.ptsbe_contract_adjoint(
+            self._h, C.byref(spec.struct), _tptr(kraus_dev), int(E), _tptr(weights_dev), _tptr(theta_dev),
+            _tptr(psi_bar), _tptr(traj), _tptr(value), _tptr(grad), _tptr(gadj), _tptr(workspace),
+            int(workspace.numel()), C.c_void_p(stream)))
+        return {"value": None if value is None else value[0], "traj_values": traj,
+                "grad": None if grad is None else grad[:spec.n_params],
+                "gate_adj": None if gadj is None else torch.view_as_complex(gadj)}
+
     # -------------------------------------------------------------- measurement
     def profile_enable(self, on=True):
         """on: False/0 off, True/1 join timing, 2 join and single HBM sweep-step timing."""
@@ -374,21 +424,26 @@ def _expect_zz_function():
     import torch
 
     class ExpectZZ(torch.autograd.Function):
-        """f(theta) = sum_i w_i <psi_i(theta)|O|psi_i(theta)> through the HIP library;
-        the forward call also runs the adjoint contraction, whose gradient the
-        backward returns (scaled by the incoming gradient)."""
+        """f(theta) = sum_i w_i <psi_i(theta)|O|psi_i(theta)> through the HIP library.
+        forward runs the forward contraction only (the value); backward runs the
+        adjoint contraction (forward windows with their checkpoints, then the
+        reverse pass seeded by grad_out w_i O psi_i) and returns the angle gradient."""
 
         @staticmethod
         def forward(ctx, theta, plan, spec, kraus_dev, weights_dev):
-            out = plan.expect_grad(spec, kraus_dev, weights_dev, theta.detach().to(torch.float64).contiguous(),
-                                   want_grad=True)
-            ctx.save_for_backward(out["grad"].to(theta.dtype))
+            th = theta.detach().to(torch.float64).contiguous()
+            out = plan.expect_grad(spec, kraus_dev, weights_dev, th, want_grad=False)
+            ctx.plan, ctx.spec, ctx.kraus, ctx.weights = plan, spec, kraus_dev, weights_dev
+            ctx.save_for_backward(th)
+            ctx.out_dtype = theta.dtype
             return out["value"].to(theta.dtype)
 
         @staticmethod
         def backward(ctx, gout):
-            (g,) = ctx.saved_tensors
-            return gout * g, None, None, None, None
+            (th,) = ctx.saved_tensors
+            w = ctx.weights * gout.to(torch.float64)
+            out = ctx.plan.expect_grad(ctx.spec, ctx.kraus, w, th, want_grad=True)
+            return out["grad"].to(ctx.out_dtype), None, None, None, None
 
     return ExpectZZ
 

@@ -19,8 +19,8 @@ EXPORTS = [
     "ptsbe_ragged_create", "ptsbe_ragged_destroy", "ptsbe_ragged_info", "ptsbe_ragged_workspace_size",
     "ptsbe_ragged_autotune", "ptsbe_ragged_sample_shots", "ptsbe_plan_sv_schedule", "ptsbe_plan_right_sites",
     "ptsbe_nonproportional_workspace_size", "ptsbe_sample_nonproportional", "ptsbe_profile_read_sweeps",
-    "ptsbe_plan_join_tiling", "ptsbe_plan_chunking",
-    "ptsbe_profile_read_windows", "ptsbe_contract_batch_noalloc",
+    "ptsbe_plan_join_tiling", "ptsbe_plan_chunking", "ptsbe_contract_batch_noalloc",
+    "ptsbe_profile_read_windows", "ptsbe_adjoint_workspace_size", "ptsbe_contract_adjoint",
 ]
 
 
@@ -46,7 +46,7 @@ class PlanOpts_t(C.Structure):
     _fields_ = [
         ("n_batches", C.c_int32), ("batch_sizes", C.POINTER(C.c_int32)), ("hypersamples", C.c_int32),
         ("path_seed", C.c_uint64), ("precision", C.c_int32), ("device", C.c_int32),
-        ("device_budget_bytes", C.c_size_t), ("method", C.c_int32),
+        ("device_budget_bytes", C.c_size_t), ("method", C.c_int32), ("light_cone", C.c_int32),
     ]
 
 
@@ -56,6 +56,7 @@ class PlanInfo_t(C.Structure):
         ("n_words", C.c_int32), ("max_kraus", C.c_int32), ("plan_device_bytes", C.c_int64),
         ("method", C.c_int32), ("sv_windows", C.c_int32), ("sv_windows_by_size", C.c_int32 * 3),
         ("sv_clusters", C.c_int32), ("sv_cluster_steps", C.c_int32), ("precision", C.c_int32),
+        ("light_cone", C.c_int32),
     ]
 
 
@@ -69,6 +70,7 @@ class BatchInfo_t(C.Structure):
         ("flops_per_traj", C.c_double), ("flops_per_elem", C.c_double),
         ("join_flops_per_elem", C.c_double), ("bytes_per_traj", C.c_double),
         ("n_right_launches", C.c_int32), ("n_right_fused_steps", C.c_int32), ("right_longest_run", C.c_int32),
+        ("kept_gates", C.c_int32),
     ]
 
 
@@ -77,6 +79,14 @@ class GradSpec_t(C.Structure):
         ("n_params", C.c_int32), ("gate_param", C.POINTER(C.c_int32)), ("gate_axis", C.POINTER(C.c_int32)),
         ("n_terms", C.c_int32), ("zz_qubits", C.POINTER(C.c_int32)), ("zz_coef", C.POINTER(C.c_double)),
         ("checkpoint_every", C.c_int32),
+    ]
+
+
+class AdjointSpec_t(C.Structure):
+    _fields_ = [
+        ("n_params", C.c_int32), ("gate_param", C.POINTER(C.c_int32)), ("gate_axis", C.POINTER(C.c_int32)),
+        ("n_terms", C.c_int32), ("zz_qubits", C.POINTER(C.c_int32)), ("zz_coef", C.POINTER(C.c_double)),
+        ("d_obs_diag", C.c_void_p),
     ]
 
 
@@ -120,6 +130,8 @@ def load():
                                        C.POINTER(C.c_double), C.POINTER(C.c_double)]
     lib.ptsbe_expect_workspace_size.argtypes = [P, C.POINTER(GradSpec_t), i64, C.POINTER(sz)]
     lib.ptsbe_expect_grad.argtypes = [P, C.POINTER(GradSpec_t), P, i64, P, P, P, P, P, P, sz, P]
+    lib.ptsbe_adjoint_workspace_size.argtypes = [P, C.POINTER(AdjointSpec_t), i64, C.POINTER(sz)]
+    lib.ptsbe_contract_adjoint.argtypes = [P, C.POINTER(AdjointSpec_t), P, i64, P, P, P, P, P, P, P, P, sz, P]
     for name in EXPORTS:
         f = getattr(lib, name)
         if name not in ("ptsbe_last_error", "ptsbe_plan_destroy", "ptsbe_ragged_destroy"):

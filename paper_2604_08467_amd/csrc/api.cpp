@@ -593,6 +593,7 @@ ptsbe_status_t ptsbe_plan(const ptsbe_circuit_t* c, const ptsbe_plan_opts_t* o, 
   p->G = (int)p->arity.size();
   // channels
   size_t koff = 0, poff = 0;
+  std::vector<char> ch_unitary;
   for (int ch = 0; ch < c->n_channels; ++ch) {
     int ar = c->ch_arity[ch], nk = c->ch_nkraus[ch];
     if (ar < 1 || ar > 2) return fail(PTSBE_ERR_UNSUPPORTED, "channel arity must be 1 or 2");
@@ -644,6 +645,23 @@ ptsbe_status_t ptsbe_plan(const ptsbe_circuit_t* c, const ptsbe_plan_opts_t* o, 
         ops[k][2 * i + 1] = K[k][i].imag() * sc;
       }
     }
+    // an inserted operator K / sqrt(q) that is unitary leaves the norm alone and
+    // can be undone by its adjoint (the windowed adjoint pass and the light cone
+    // use that)
+    bool ch_unit = true;
+    for (int k = 0; k < nk; ++k) {
+      if (!(q[k] > 0)) continue;
+      for (int r = 0; r < d; ++r)
+        for (int cc = 0; cc < d; ++cc) {
+          cd acc = 0;
+          for (int x = 0; x < d; ++x)
+            acc += std::conj(cd(ops[k][2 * (x * d + r)], ops[k][2 * (x * d + r) + 1])) *
+                   cd(ops[k][2 * (x * d + cc)], ops[k][2 * (x * d + cc) + 1]);
+          if (std::abs(acc - (r == cc ? 1.0 : 0.0)) > 1e-9) p->inserted_unitary = false;
+          if (std::abs(acc - (r == cc ? 1.0 : 0.0)) > ptsbe::kUnitaryTol) ch_unit = false;
+        }
+    }
+    ch_unitary.push_back(ch_unit ? 1 : 0);
     p->ch_ops.push_back(ops);
     p->ch_q.push_back(q);
     p->max_kraus = std::max(p->max_kraus, nk);
@@ -669,6 +687,23 @@ ptsbe_status_t ptsbe_plan(const ptsbe_circuit_t* c, const ptsbe_plan_opts_t* o, 
     p->gate_sites[g].push_back(s);
   }
   p->S = c->n_sites;
+  // light cone of doubled networks: which gates are unitary for every trajectory
+  if (o->light_cone != 0 && o->light_cone != 1) return fail(PTSBE_ERR_INVALID_ARG, "light_cone must be 0 or 1");
+  p->light_cone = o->light_cone == 1;
+  p->gate_unitary.assign((size_t)p->G, 1);
+  for (int g = 0; g < p->G; ++g) {
+    const int d = 1 << p->arity[(size_t)g];
+    const auto& m = p->mats[(size_t)g];
+    for (int r = 0; r < d; ++r)
+      for (int cc = 0; cc < d; ++cc) {
+        cd acc = 0;
+        for (int x = 0; x < d; ++x)
+          acc += std::conj(cd(m[2 * (x * d + r)], m[2 * (x * d + r) + 1])) * cd(m[2 * (x * d + cc)], m[2 * (x * d + cc) + 1]);
+        if (std::abs(acc - (r == cc ? 1.0 : 0.0)) > ptsbe::kUnitaryTol) p->gate_unitary[(size_t)g] = 0;
+      }
+    for (int st : p->gate_sites[(size_t)g])
+      if (!ch_unitary[(size_t)p->site_channel[(size_t)st]]) p->gate_unitary[(size_t)g] = 0;
+  }
   // contraction method and path
   if (o->method < PTSBE_METHOD_AUTO || o->method > PTSBE_METHOD_STATEVECTOR)
     return fail(PTSBE_ERR_INVALID_ARG, "unknown method");
@@ -829,6 +864,14 @@ ptsbe_status_t ptsbe_plan(const ptsbe_circuit_t* c, const ptsbe_plan_opts_t* o, 
       }
       HIP_TRY(hipMalloc(&p->d_rg_win[i], std::max<size_t>(1, w.size()) * sizeof(ptsbe::RgWindow)));
       HIP_TRY(hipMemcpy(p->d_rg_win[i], w.data(), w.size() * sizeof(ptsbe::RgWindow), hipMemcpyHostToDevice));
+      if (!p->sv_ops_plain[i].empty()) {
+        const auto& pw = p->sv_wins_plain[i];
+        const auto& po = p->sv_ops_plain[i];
+        HIP_TRY(hipMalloc(&p->d_sv_wins_plain[i], pw.size() * sizeof(ptsbe::SvWin)));
+        HIP_TRY(hipMemcpy(p->d_sv_wins_plain[i], pw.data(), pw.size() * sizeof(ptsbe::SvWin), hipMemcpyHostToDevice));
+        HIP_TRY(hipMalloc(&p->d_sv_ops_plain[i], po.size() * sizeof(ptsbe::SvOp)));
+        HIP_TRY(hipMemcpy(p->d_sv_ops_plain[i], po.data(), po.size() * sizeof(ptsbe::SvOp), hipMemcpyHostToDevice));
+      }
       const auto& so = p->sv_ops[i];
       if (!so.empty()) {
         HIP_TRY(hipMalloc(&p->d_sv_ops[i], so.size() * sizeof(ptsbe::SvOp)));
@@ -878,6 +921,10 @@ void ptsbe_plan_destroy(ptsbe_plan_t plan) {
     if (c) (void)hipFree(c);
   for (auto* o : p->d_sv_ops)
     if (o) (void)hipFree(o);
+  for (auto* o : p->d_sv_ops_plain)
+    if (o) (void)hipFree(o);
+  for (auto* o : p->d_sv_wins_plain)
+    if (o) (void)hipFree(o);
   delete p;
 }
 
@@ -903,6 +950,7 @@ ptsbe_status_t ptsbe_plan_query(ptsbe_plan_t plan, ptsbe_plan_info_t* out) {
       out->sv_cluster_steps += cd.len;
     }
   out->precision = p->precision;
+  out->light_cone = p->light_cone ? 1 : 0;
   return PTSBE_OK;
 }
 
@@ -1008,6 +1056,7 @@ ptsbe_status_t ptsbe_plan_batch_info(ptsbe_plan_t plan, int32_t j, ptsbe_batch_i
         out->right_longest_run = std::max(out->right_longest_run, sg.count);
       }
     }
+  out->kept_gates = bp.kept_gates;
   return PTSBE_OK;
 }
 

@@ -1,8 +1,6 @@
-// HIP kernels of the adjoint contraction (gradients of trajectory-averaged
-// observables with respect to rotation angles).  The ket network is contracted
-// in circuit order into a 2^n statevector per trajectory (qubit q = bit q); the
-// adjoint pass applies the conjugate-transposed merged gates to the observable's
-// seed lambda = O psi and reduces <lambda|(dA/dtheta) psi> gate by gate.
+// Helper kernels of the adjoint contraction: the merged gates A = S U(theta)
+// and their adjoints for every (trajectory, gate), state initialisation, copies
+// and the weighted value sum (the window passes are in adj_kernels.hip).
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
@@ -98,106 +96,6 @@ __global__ void copy_kernel(const float2* __restrict__ src, float2* __restrict__
     dst[id] = src[id];
 }
 
-__device__ inline float zz_value(uint32_t x, const int32_t* zq, const double* zc, int nt) {
-  float o = 0.f;
-  for (int t = 0; t < nt; ++t) {
-    const int za = 1 - 2 * (int)((x >> zq[2 * t]) & 1u);
-    const int zb = 1 - 2 * (int)((x >> zq[2 * t + 1]) & 1u);
-    o += (float)zc[t] * (float)(za * zb);
-  }
-  return o;
-}
-
-// lambda = O psi and value[job] = <psi|O|psi> (FP64 block reduction per job)
-__global__ void __launch_bounds__(256) observable_kernel(const float2* __restrict__ psi, float2* __restrict__ lam,
-                                                        int n, const int32_t* zq, const double* zc, int nt,
-                                                        double* __restrict__ value, int64_t job0) {
-  __shared__ double red[256];
-  const int64_t job = blockIdx.x;
-  const int64_t per = (int64_t)1 << n;
-  const float2* p = psi + job * per;
-  float2* l = lam + job * per;
-  double acc = 0.0;
-  for (int64_t x = threadIdx.x; x < per; x += 256) {
-    const float o = zz_value((uint32_t)x, zq, zc, nt);
-    const float2 v = p[x];
-    l[x] = make_float2(o * v.x, o * v.y);
-    acc += (double)o * ((double)v.x * v.x + (double)v.y * v.y);
-  }
-  red[threadIdx.x] = acc;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) value[job0 + job] = red[0];
-}
-
-// partial[traj][slot] = 2 w_traj Re sum_{a,b} dA[a][b] M[a][b],
-// M[a][b] = sum_rest conj(lambda[rest, a]) psi[rest, b] over the gate's qubits.
-__global__ void __launch_bounds__(256) grad_reduce_kernel(const float2* __restrict__ lam,
-                                                         const float2* __restrict__ psi, int n, int arity,
-                                                         int q0, int q1, const float2* __restrict__ dmerged,
-                                                         int n_slots, int slot, const double* __restrict__ w,
-                                                         int64_t job0, double* __restrict__ partial) {
-  __shared__ double red[256][2];
-  const int64_t job = blockIdx.x;
-  const int64_t traj = job0 + job;
-  const int64_t per = (int64_t)1 << n;
-  const float2* L = lam + job * per;
-  const float2* P = psi + job * per;
-  const float2* dA = dmerged + (traj * n_slots + slot) * 16;
-  const int d = arity == 2 ? 4 : 2;
-  // positions: for 2q gates index a = 2 x[q0] + x[q1]
-  int pos[2] = {q0, q1};
-  int plo = arity == 2 ? (q0 < q1 ? q0 : q1) : q0;
-  int phi = arity == 2 ? (q0 < q1 ? q1 : q0) : q0;
-  const int64_t nrest = per >> arity;
-  double re = 0.0;
-  for (int64_t m = threadIdx.x; m < nrest; m += 256) {
-    uint32_t base = (uint32_t)m;
-    base = ((base >> plo) << (plo + 1)) | (base & ((1u << plo) - 1u));
-    if (arity == 2) base = ((base >> phi) << (phi + 1)) | (base & ((1u << phi) - 1u));
-    float2 lv[4], pv[4];
-    for (int a = 0; a < d; ++a) {
-      uint32_t off = base;
-      if (arity == 2) {
-        off |= (uint32_t)((a >> 1) & 1) << pos[0];
-        off |= (uint32_t)(a & 1) << pos[1];
-      } else {
-        off |= (uint32_t)(a & 1) << pos[0];
-      }
-      lv[a] = L[off];
-      pv[a] = P[off];
-    }
-    // Re sum_ab dA[a][b] conj(l_a) p_b
-    for (int a = 0; a < d; ++a) {
-      float2 s = make_float2(0.f, 0.f);
-      for (int b = 0; b < d; ++b) s = cfma2(dA[a * d + b], pv[b], s);
-      re += (double)lv[a].x * s.x + (double)lv[a].y * s.y;
-    }
-  }
-  red[threadIdx.x][0] = re;
-  __syncthreads();
-  for (int wd = 128; wd > 0; wd >>= 1) {
-    if ((int)threadIdx.x < wd) red[threadIdx.x][0] += red[threadIdx.x + wd][0];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) partial[traj * n_slots + slot] = 2.0 * w[traj] * red[0][0];
-}
-
-// grad[p] = sum over trajectories and over the slots that use p (fixed order)
-__global__ void grad_sum_kernel(const double* __restrict__ partial, int64_t E, int n_slots,
-                                const int32_t* __restrict__ slot_param, int n_params, double* __restrict__ grad) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n_params) return;
-  double acc = 0.0;
-  for (int64_t t = 0; t < E; ++t)
-    for (int s = 0; s < n_slots; ++s)
-      if (slot_param[s] == p) acc += partial[t * n_slots + s];
-  grad[p] = acc;
-}
-
 __global__ void value_sum_kernel(const double* __restrict__ vals, const double* __restrict__ w, int64_t E,
                                  double* __restrict__ out) {
   __shared__ double red[256];
@@ -230,28 +128,6 @@ hipError_t launch_state_init(float2* psi, int64_t n_jobs, int n, hipStream_t str
 hipError_t launch_copy(const float2* src, float2* dst, int64_t n, hipStream_t stream) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(copy_kernel, dim3(grid_blocks((n + 255) / 256)), dim3(256), 0, stream, src, dst, n);
-  return hipGetLastError();
-}
-
-hipError_t launch_observable(const float2* psi, float2* lam, int64_t n_jobs, int n, const int32_t* zq,
-                             const double* zc, int nt, double* value, int64_t job0, hipStream_t stream) {
-  hipLaunchKernelGGL(observable_kernel, dim3((unsigned)n_jobs), dim3(256), 0, stream, psi, lam, n, zq, zc, nt, value,
-                     job0);
-  return hipGetLastError();
-}
-
-hipError_t launch_grad_reduce(const float2* lam, const float2* psi, int64_t n_jobs, int n, int arity, int q0, int q1,
-                              const float2* dmerged, int n_slots, int slot, const double* w, int64_t job0,
-                              double* partial, hipStream_t stream) {
-  hipLaunchKernelGGL(grad_reduce_kernel, dim3((unsigned)n_jobs), dim3(256), 0, stream, lam, psi, n, arity, q0, q1,
-                     dmerged, n_slots, slot, w, job0, partial);
-  return hipGetLastError();
-}
-
-hipError_t launch_grad_sum(const double* partial, int64_t E, int n_slots, const int32_t* slot_param, int n_params,
-                           double* grad, hipStream_t stream) {
-  hipLaunchKernelGGL(grad_sum_kernel, dim3((unsigned)((n_params + 63) / 64)), dim3(64), 0, stream, partial, E,
-                     n_slots, slot_param, n_params, grad);
   return hipGetLastError();
 }
 

@@ -119,7 +119,53 @@ static_assert(sizeof(SvOp) == 32, "SvOp is read as eight dwords");
 struct SvWin {
   int32_t op_off, n_ops, n_plain, cl_first, n_cl, np;
   int32_t P[12];
+  uint32_t other;           // bit mask of the state's qubits outside the window
 };
+
+// Op of an adjoint window (a plain gate in place on the tile): the gate's merged
+// matrix entry idx[a * d + b] is local entry (a, b); axis >= 0 marks a rotation
+// exp(-i theta P / 2) about P = X, Y, Z whose derivative is accumulated; nslot >= 0
+// receives the gate-tensor adjoint N = sum lambda psi^dag.
+struct AdjOp {
+  int8_t kind, p0, p1, axis;
+  int32_t gate, nslot, pad;
+  int8_t idx[16];
+};
+struct AdjWin {
+  int32_t op_off, n_ops, np;
+  int32_t P[12];
+};
+struct AdjArgs {
+  int n, np, n_ops, n_nslots, G, want_n;
+  int P[12];
+  uint32_t other;                 // bit mask of the qubits outside the window
+  int64_t n_jobs;
+  int32_t traj_base;
+  const float2* A;                // [E][G][16] merged gates
+  const float2* Ad;               // [E][G][16] their adjoints
+  const float2* psi_in;           // forward: input states; backward: states after (1) / before (2) the window
+  float2* psi_out;                // forward: output states
+  float2* lam;                    // backward: adjoint states, in place
+  double* wg_acc;                 // backward: [grid][n_ops + 32 n_nslots] per-workgroup sums
+};
+struct AdjSeedArgs {
+  const float2* psi;              // [n_jobs][2^n] final states
+  float2* lam;                    // [n_jobs][2^n] seed out (null: values only)
+  const float2* psi_bar;          // [E][2^n] caller's seed, or null (lambda = w O psi)
+  const double* obs_diag;         // [2^n] diagonal of O (the caller's or the ZZ terms')
+  const double* weights;          // [E]
+  double* part;                   // [n_jobs][64] partial values (workspace)
+  double* values;                 // [E] <psi|O|psi>, or null
+  int n;
+  int32_t traj_base;
+};
+size_t adj_window_lds_bytes(int mode, int np, int n_ops, int n_nslots);
+int adj_window_grid(int mode, size_t lds, int64_t tiles);
+hipError_t launch_adj_window(int mode, const AdjArgs& a, const AdjOp* d_ops, int grid, hipStream_t stream);
+hipError_t launch_adj_seed(const AdjSeedArgs& s, int64_t n_jobs, hipStream_t stream);
+hipError_t launch_adj_zz_diag(int n, const int32_t* zq, const double* zc, int n_terms, double* diag,
+                              hipStream_t stream);
+hipError_t launch_adj_reduce(const double* wg_acc, int n_wg, int width, double* tot, hipStream_t stream);
 
 // A run of steps executed by one launch: either one absorb step, or a fused
 // run of in-place steps whose positions lie in P (|P| = np <= kFuseMax).
@@ -153,6 +199,10 @@ struct SplitTable {
   std::vector<int64_t> lo, hi;
 };
 
+// Largest |M^dag M - I| entry for which a gate or an inserted operator counts as
+// unitary in the light cone (complex64-rounded unitaries sit near 1e-7).
+constexpr double kUnitaryTol = 1e-6;
+
 struct BatchPlan {
   int start = 0, size = 0;
   bool doubled = false;
@@ -172,6 +222,7 @@ struct BatchPlan {
   SplitTable t_x, t_k, t_b;         // T[t]: xT, lk, lb
   SplitTable o_x, o_b;              // output index: xT, xb
   double join_flops_per_elem = 0;
+  int kept_gates = 0;               // gates in this batch's network (light cone applied)
 };
 
 struct RgWindow;
@@ -233,9 +284,19 @@ struct Plan {
   std::vector<SvWin> sv_wins[3];
   std::vector<SvOp> sv_ops[3];
   SvOp* d_sv_ops[3] = {nullptr, nullptr, nullptr};
+  // the same windows with every step a plain op (ragged sets), on the device
+  std::vector<SvWin> sv_wins_plain[3];
+  std::vector<SvOp> sv_ops_plain[3];
+  SvWin* d_sv_wins_plain[3] = {nullptr, nullptr, nullptr};
+  SvOp* d_sv_ops_plain[3] = {nullptr, nullptr, nullptr};
   // fused in-place steps of every part and of the statevector schedule
   std::vector<FusedStep> fused;
   FusedStep* d_fused = nullptr;
+  bool inserted_unitary = true;                   // every inserted operator K / sqrt(q) is unitary
+  // light cone of doubled networks: gate_unitary[g] when the bare gate and every
+  // operator its sites may insert are unitary (to kUnitaryTol)
+  bool light_cone = false;
+  std::vector<char> gate_unitary;
 
   // measurement
   int profile = 0;                                // 1: time the MFMA join; 2: also single HBM sweep steps
@@ -263,6 +324,10 @@ void build_sv_schedule(Plan& p);
 // Compact ops of every statevector window set (p.sv_wins, p.sv_ops), from the
 // fused steps and clusters that build_sv_schedule made.
 void build_sv_ops(Plan& p);
+// Windows of at most wmax qubits and max_ops steps for the adjoint pass: the
+// statevector schedule's steps packed as in build_sv_schedule, in circuit order,
+// every step a plain op.
+void build_adj_windows(const Plan& p, int wmax, int max_ops, std::vector<AdjWin>& wins, std::vector<AdjOp>& ops);
 
 // kernels.hip: launchers (all asynchronous on `stream`)
 struct GateCtx {
@@ -500,13 +565,6 @@ hipError_t launch_sv_window(const SvWin& w, const SvOp* d_ops, const float2* mer
 // LDS bytes the window kernel needs for a window (0 if it cannot take it).
 size_t sv_window_lds_bytes(const SvWin& w);
 hipError_t launch_copy(const float2* src, float2* dst, int64_t n, hipStream_t stream);
-hipError_t launch_observable(const float2* psi, float2* lam, int64_t n_jobs, int n, const int32_t* zq,
-                             const double* zc, int nt, double* value, int64_t job0, hipStream_t stream);
-hipError_t launch_grad_reduce(const float2* lam, const float2* psi, int64_t n_jobs, int n, int arity, int q0,
-                              int q1, const float2* dmerged, int n_slots, int slot, const double* w,
-                              int64_t job0, double* partial, hipStream_t stream);
-hipError_t launch_grad_sum(const double* partial, int64_t E, int n_slots, const int32_t* slot_param,
-                           int n_params, double* grad, hipStream_t stream);
 hipError_t launch_value_sum(const double* vals, const double* w, int64_t E, double* out, hipStream_t stream);
 
 // ---------------------------------------------------------- statevector method
@@ -563,6 +621,8 @@ struct RgWindow {                    // one gate window of a statevector plan
 struct RgPiece {                     // trajectories [t0, t0 + nj) of one job inside a wave
   GateCtx g;                         // kraus / merged of the piece (local trajectory index)
   const RgWindow* win;               // the plan's windows (device)
+  const SvWin* swin;                 // the same windows as plain compact ops (device), or null
+  const SvOp* sops;
   const FusedStep* fused;            // the plan's fused steps (device)
   float2* psi;                       // [nj][2^n]
   uint64_t* shots;                   // the job's shot rows (device, one word per row)
@@ -594,7 +654,7 @@ struct RgWave {                      // device arrays of one wave (all in the wo
   int32_t n_jobs;
 };
 // window level l: entries (piece, first task) of the pieces with more than l windows
-struct RgLevel { const int32_t* piece; const int64_t* start; int32_t n; int64_t tasks; };
+struct RgLevel { const int32_t* piece; const int64_t* start; int32_t n; int64_t tasks; int32_t max_ops; };
 hipError_t launch_rg_start(const RgWave& w, hipStream_t s);
 hipError_t launch_rg_prepare(const RgWave& w, int grid, hipStream_t s);
 // grid: n_cu times the kernel's occupancy per CU

@@ -901,7 +901,9 @@ template <int K, int NC, bool F16>
 __global__ void __launch_bounds__(256) qform_split_kernel(QformArgs a) {
   typedef typename Split16<F16>::E E;
   typedef typename Split16<F16>::V bf16x8;
-  constexpr int ROWS = 64, KK = K * K, XT = 16 * NC, NST = KK / 32, KS = 2, NCH = NST / KS;
+  // NC = 8: one A operand (built and split per lane) feeds 24 MFMAs; the Theta
+  // chunk is then one k-step (LDS stays under 64 KB)
+  constexpr int ROWS = 64, KK = K * K, XT = 16 * NC, NST = KK / 32, KS = NC >= 8 ? 1 : 2, NCH = NST / KS;
   constexpr int U16 = KS * 2 * XT * 4;            // 16-byte units of Theta per chunk
   static_assert(NCH >= 1 && NST % KS == 0, "chunking");
   __shared__ bf16x8 Tb[2][KS][2][NC][64];          // [buf][k-step][plane][c][lane]
@@ -1675,7 +1677,7 @@ hipError_t launch_qform_split(const QformArgs& a, int n_traj, int max_rows, bool
   if (n_traj <= 0 || max_rows <= 0) return hipSuccess;
   const int tiles = (max_rows + 63) / 64;
   const int nx = 1 << a.xT_bits;
-  const int nc = nx >= 64 ? 4 : (nx >= 32 ? 2 : 1);
+  const int nc = nx >= 128 ? 8 : (nx >= 64 ? 4 : (nx >= 32 ? 2 : 1));
   const int xtiles = (nx + 16 * nc - 1) / (16 * nc);
   dim3 grid((unsigned)tiles, (unsigned)n_traj, (unsigned)xtiles);
 #define PTSBE_QSPLIT(KV, NCV)                                                                         \
@@ -1684,9 +1686,11 @@ hipError_t launch_qform_split(const QformArgs& a, int n_traj, int max_rows, bool
     else hipLaunchKernelGGL((qform_split_kernel<KV, NCV, false>), grid, dim3(256), 0, stream, a);     \
   } while (0)
   if (a.lk_bits == 4) {
-    if (nc == 4) PTSBE_QSPLIT(16, 4); else if (nc == 2) PTSBE_QSPLIT(16, 2); else PTSBE_QSPLIT(16, 1);
+    if (nc == 8) PTSBE_QSPLIT(16, 8); else if (nc == 4) PTSBE_QSPLIT(16, 4);
+    else if (nc == 2) PTSBE_QSPLIT(16, 2); else PTSBE_QSPLIT(16, 1);
   } else if (a.lk_bits == 5) {
-    if (nc == 4) PTSBE_QSPLIT(32, 4); else if (nc == 2) PTSBE_QSPLIT(32, 2); else PTSBE_QSPLIT(32, 1);
+    if (nc == 8) PTSBE_QSPLIT(32, 8); else if (nc == 4) PTSBE_QSPLIT(32, 4);
+    else if (nc == 2) PTSBE_QSPLIT(32, 2); else PTSBE_QSPLIT(32, 1);
   } else {
     return hipErrorInvalidValue;
   }

@@ -329,8 +329,31 @@ SplitTable make_out_table(const std::vector<int>& group, const std::vector<int>&
 
 }  // namespace
 
+// Gates of the doubled network for measured qubits [0, e) under the light cone
+// (an extension of the unified path that Sec. VI names as open): in rho = U rho0
+// U^dag traced over the later qubits, a unitary gate whose outputs reach no
+// measured qubit and no kept non-unitary operator meets its own adjoint and
+// cancels, U^dag U = I.  Walking back in time from the measured outputs, a gate is
+// kept when it touches a live qubit or is not unitary for some trajectory (its
+// sites may insert a non-unitary K / sqrt(q), whose K^dag K does not cancel); a
+// kept gate makes all its qubits live.  The kept set depends on the channel
+// types only, never on a trajectory's Kraus choices, so one path still serves
+// every error set.
+std::vector<char> light_cone_keep(const Plan& p, int e) {
+  std::vector<char> keep((size_t)p.G, 0), live((size_t)p.n, 0);
+  for (int q = 0; q < e; ++q) live[(size_t)q] = 1;
+  for (int g = p.G - 1; g >= 0; --g) {
+    bool k = !p.gate_unitary[(size_t)g];
+    for (int a = 0; a < p.arity[(size_t)g]; ++a) k = k || live[(size_t)p.qubits[(size_t)g][(size_t)a]];
+    if (!k) continue;
+    keep[(size_t)g] = 1;
+    for (int a = 0; a < p.arity[(size_t)g]; ++a) live[(size_t)p.qubits[(size_t)g][(size_t)a]] = 1;
+  }
+  return keep;
+}
+
 bool build_batch_plans(Plan& p, std::string& err) {
-  KetNet k = build_ket(p);
+  const KetNet k = build_ket(p);
   const int NL = k.n_labels;
   int f = (int)p.batch_sizes.size();
   p.batches.clear();
@@ -342,8 +365,18 @@ bool build_batch_plans(Plan& p, std::string& err) {
     bp.doubled = (j < f - 1);
     const int a = start, e = start + bp.size;
     auto cls = [&](int q) { return q < a ? 0 : (q < e ? 1 : 2); };  // prefix/batch/rest
+    // gates of this batch's network; with the light cone, a qubit's output is the
+    // last kept gate's (labels keep the full circuit's numbering), and a qubit
+    // with no kept gate drops out (its |0><0| traces to 1)
+    std::vector<char> keep = bp.doubled && p.light_cone ? light_cone_keep(p, e) : std::vector<char>((size_t)p.G, 1);
+    std::vector<int> final_label((size_t)p.n, -1);
+    for (int g = 0; g < p.G; ++g)
+      if (keep[(size_t)g])
+        for (int s = 0; s < p.arity[g]; ++s) final_label[(size_t)p.qubits[g][s]] = k.out_label[g][s];
+    bp.kept_gates = (int)std::count(keep.begin(), keep.end(), (char)1);
     std::vector<int> final_of(NL, -1);  // label -> qubit whose final output it is
-    for (int q = 0; q < p.n; ++q) final_of[k.final_label[q]] = q;
+    for (int q = 0; q < p.n; ++q)
+      if (final_label[(size_t)q] >= 0) final_of[final_label[(size_t)q]] = q;
     auto bra_label = [&](int L) {
       int q = final_of[L];
       if (q >= 0 && cls(q) != 0) return L;   // batch / rest outputs are shared
@@ -351,6 +384,7 @@ bool build_batch_plans(Plan& p, std::string& err) {
     };
     std::vector<NetTensor> left, right;
     for (int g = 0; g < p.G; ++g) {
+      if (!keep[(size_t)g]) continue;
       bool is_left = false;
       for (int s = 0; s < p.arity[g]; ++s) is_left |= cls(p.qubits[g][s]) == 0;
       for (int side = 0; side < (bp.doubled ? 2 : 1); ++side) {
@@ -399,13 +433,13 @@ bool build_batch_plans(Plan& p, std::string& err) {
         if (t.label[i] >= 0) right_labels.insert(t.label[i]);
     std::vector<int> xb_q, xT_q;
     for (int q = a; q < e; ++q) {
-      int L = k.final_label[q];
+      int L = final_label[(size_t)q];
       if (left_labels.count(L)) { bp.xb.push_back(L); xb_q.push_back(q); }
       else { bp.xT.push_back(L); xT_q.push_back(q); }
     }
     if (bp.doubled) {
       for (int q = e; q < p.n; ++q)
-        if (left_labels.count(k.final_label[q])) {
+        if (final_label[(size_t)q] >= 0 && left_labels.count(final_label[(size_t)q])) {
           err = "unsupported network: a later qubit's output lies on a gate that touches the prefix";
           return false;
         }
@@ -675,41 +709,54 @@ void cluster_order(const Plan& p, const std::vector<int>& steps, std::vector<int
   }
 }
 
-std::vector<Segment> sv_windows(Plan& p, int wmax, std::vector<AbsorbStep>* run, std::vector<ClusterDesc>& cls) {
-  std::vector<Segment> segs;
+// One window of at most wmax qubits (qubits 0..3 always in it) from the steps
+// `rest` still to apply, in order: a step joins if its qubits fit and no earlier
+// step left out touches them (so it commutes with every step it overtakes).
+// taken / left_out: the steps in order; Pv: the window's qubits, ascending.
+void pack_window(const Plan& p, const std::vector<int>& rest, int wmax, std::vector<int>& taken,
+                 std::vector<int>& left_out, std::vector<int>& Pv, size_t max_steps = (size_t)1 << 30) {
   const int n = p.n;
   const int cap = std::min(wmax, n);
   const int low = std::min(4, n);
+  std::set<int> P, blocked;
+  for (int q = 0; q < low; ++q) P.insert(q);
+  taken.clear();
+  left_out.clear();
+  for (int g : rest) {
+    const AbsorbStep& st = p.sv_steps[g];
+    bool free = true;
+    for (int k = 0; k < st.nK; ++k) free = free && !blocked.count(st.kpos[k]);
+    std::set<int> P2 = P;
+    for (int k = 0; k < st.nK; ++k) P2.insert(st.kpos[k]);
+    if (free && (int)P2.size() <= cap && taken.size() < max_steps) {
+      P = P2;
+      taken.push_back(g);
+    } else {
+      for (int k = 0; k < st.nK; ++k) blocked.insert(st.kpos[k]);
+      left_out.push_back(g);
+    }
+  }
+  // pad the window with the lowest qubits not yet in it
+  for (int q = 0; (int)P.size() < cap && q < n; ++q) P.insert(q);
+  Pv.assign(P.begin(), P.end());
+}
+
+std::vector<Segment> sv_windows(Plan& p, int wmax, std::vector<AbsorbStep>* run, std::vector<ClusterDesc>& cls) {
+  std::vector<Segment> segs;
+  const int n = p.n;
   std::vector<int> rest(p.sv_steps.size());
   for (size_t i = 0; i < rest.size(); ++i) rest[i] = (int)i;
   int64_t first = 0;
   while (!rest.empty()) {
-    std::set<int> P, blocked;
-    for (int q = 0; q < low; ++q) P.insert(q);
-    std::vector<int> taken, left_out;
-    for (int g : rest) {
-      const AbsorbStep& st = p.sv_steps[g];
-      bool free = true;
-      for (int k = 0; k < st.nK; ++k) free = free && !blocked.count(st.kpos[k]);
-      std::set<int> P2 = P;
-      for (int k = 0; k < st.nK; ++k) P2.insert(st.kpos[k]);
-      if (free && (int)P2.size() <= cap) {
-        P = P2;
-        taken.push_back(g);
-      } else {
-        for (int k = 0; k < st.nK; ++k) blocked.insert(st.kpos[k]);
-        left_out.push_back(g);
-      }
-    }
-    // pad the window with the lowest qubits not yet in it
-    for (int q = 0; (int)P.size() < cap && q < n; ++q) P.insert(q);
+    std::vector<int> taken, left_out, Pv;
+    pack_window(p, rest, wmax, taken, left_out, Pv);
+    std::set<int> P(Pv.begin(), Pv.end());
     Segment sg;
     sg.first = (int)first;
     sg.count = (int)taken.size();
     sg.fused = true;
     sg.r = n;
     sg.np = (int)P.size();
-    std::vector<int> Pv(P.begin(), P.end());
     for (int k = 0; k < sg.np; ++k) sg.P[k] = Pv[k];
     sg.fused_off = (int64_t)p.fused.size();
     std::vector<int> order;
@@ -768,8 +815,84 @@ void build_sv_schedule(Plan& p) {
   p.sv_segs = p.sv_win[2];
 }
 
+void build_adj_windows(const Plan& p, int wmax, int max_ops, std::vector<AdjWin>& wins, std::vector<AdjOp>& ops) {
+  wins.clear();
+  ops.clear();
+  std::vector<int> rest(p.sv_steps.size());
+  for (size_t i = 0; i < rest.size(); ++i) rest[i] = (int)i;
+  while (!rest.empty()) {
+    std::vector<int> taken, left_out, Pv;
+    pack_window(p, rest, wmax, taken, left_out, Pv, (size_t)std::max(max_ops, 1));
+    AdjWin w{};
+    w.op_off = (int32_t)ops.size();
+    w.n_ops = (int32_t)taken.size();
+    w.np = (int32_t)Pv.size();
+    for (int k = 0; k < w.np; ++k) w.P[k] = Pv[(size_t)k];
+    auto loc = [&](int q) { return (int)(std::find(Pv.begin(), Pv.end(), q) - Pv.begin()); };
+    for (int g : taken) {
+      const AbsorbStep& st = p.sv_steps[(size_t)g];
+      AdjOp op{};
+      op.kind = (int8_t)(st.nK == 1 ? kSvOpGate1 : kSvOpGate2);
+      op.p0 = (int8_t)loc(st.kpos[0]);
+      op.p1 = (int8_t)(st.nK == 2 ? loc(st.kpos[1]) : 0);
+      op.axis = -1;
+      op.nslot = -1;
+      op.gate = st.gate;
+      const int d = 1 << st.nK;
+      for (int a = 0; a < d; ++a)
+        for (int b = 0; b < d; ++b) op.idx[a * d + b] = (int8_t)(st.nB[a] + st.kB[b]);
+      ops.push_back(op);
+    }
+    wins.push_back(w);
+    rest = left_out;
+  }
+}
+
 void build_sv_ops(Plan& p) {
+  const uint32_t all = p.n >= 32 ? 0xFFFFFFFFu : ((1u << p.n) - 1u);
   for (int i = 0; i < 3; ++i) {
+    // plain form: every fused step of every window as its own op
+    std::vector<SvWin>& pw = p.sv_wins_plain[i];
+    std::vector<SvOp>& po = p.sv_ops_plain[i];
+    pw.clear();
+    po.clear();
+    bool pok = true;
+    for (const Segment& sg : p.sv_win[i]) {
+      SvWin w{};
+      w.op_off = (int32_t)po.size();
+      w.np = sg.np;
+      uint32_t win = 0;
+      for (int k = 0; k < kFuseMax; ++k) {
+        w.P[k] = sg.P[k];
+        if (k < sg.np) win |= 1u << sg.P[k];
+      }
+      w.other = all & ~win;
+      pok = pok && sg.P[0] == 0;
+      for (int s = 0; s < sg.count && pok; ++s) {
+        const FusedStep& f = p.fused[(size_t)(sg.fused_off + s)];
+        const bool plain = f.nH == 0 && f.nS == 0 && f.nK == f.nN && f.nK >= 1 && f.nK <= 2 &&
+                           f.noff[1] == f.koff[1] && (f.nK == 1 || (f.noff[2] == f.koff[2] && f.noff[3] == f.koff[3]));
+        if (!plain) { pok = false; break; }
+        SvOp op{};
+        op.kind = f.nK == 1 ? kSvOpGate1 : kSvOpGate2;
+        op.p0 = (int8_t)f.kloc[0];
+        op.p1 = (int8_t)(f.nK == 2 ? f.kloc[1] : 0);
+        op.conj = (int8_t)f.conj;
+        op.gate = f.gate;
+        op.slot = w.n_plain++;
+        const int d = 1 << f.nK;
+        for (int n = 0; n < d; ++n)
+          for (int k = 0; k < d; ++k) op.idx[n * d + k] = (int8_t)(f.nB[n] + f.kB[k]);
+        po.push_back(op);
+      }
+      if (!pok) break;
+      w.n_ops = (int32_t)po.size() - w.op_off;
+      pw.push_back(w);
+    }
+    if (!pok) {
+      pw.clear();
+      po.clear();
+    }
     std::vector<SvWin>& wins = p.sv_wins[i];
     std::vector<SvOp>& ops = p.sv_ops[i];
     wins.clear();
@@ -779,7 +902,12 @@ void build_sv_ops(Plan& p) {
       SvWin w{};
       w.op_off = (int32_t)ops.size();
       w.np = sg.np;
-      for (int k = 0; k < kFuseMax; ++k) w.P[k] = sg.P[k];
+      uint32_t win = 0;
+      for (int k = 0; k < kFuseMax; ++k) {
+        w.P[k] = sg.P[k];
+        if (k < sg.np) win |= 1u << sg.P[k];
+      }
+      w.other = all & ~win;
       ok = ok && sg.np >= 1 && sg.P[0] == 0;
       int cl_lo = -1, cl_hi = -1;
       for (int s = 0; s < sg.count && ok;) {

@@ -190,8 +190,15 @@ ptsbe_status_t ptsbe_ragged_autotune(ptsbe_ragged_t set, const ptsbe_ragged_job_
         for (int rep = 0; rep < 2; ++rep) {   // the first pass warms up
           HIP_TRY(hipEventRecord(ev[0], s));
           HIP_TRY(ptsbe::launch_state_init(psi, nt, p.n, s));
-          for (const ptsbe::Segment& sg : p.sv_win[w])
-            HIP_TRY(ptsbe::launch_fused(sg, p.d_fused, g, nt, nullptr, 0, nullptr, p.NW, psi, s));
+          // the pass the set runs: compact plain ops for 10..12-qubit windows, else the generic one
+          const bool compact = p.d_sv_ops_plain[w] && p.sv_wins_plain[w].size() == p.sv_win[w].size();
+          for (size_t k = 0; k < p.sv_win[w].size(); ++k) {
+            if (compact && p.sv_wins_plain[w][k].np >= 10 && p.sv_wins_plain[w][k].n_ops <= 224)
+              HIP_TRY(ptsbe::launch_sv_window(p.sv_wins_plain[w][k], p.d_sv_ops_plain[w], merged, p.G, nullptr, 0,
+                                              nt, 0, psi, p.n, PTSBE_C64, s));
+            else
+              HIP_TRY(ptsbe::launch_fused(p.sv_win[w][k], p.d_fused, g, nt, nullptr, 0, nullptr, p.NW, psi, s));
+          }
           HIP_TRY(hipEventRecord(ev[1], s));
         }
         HIP_TRY(hipEventSynchronize(ev[1]));
@@ -246,14 +253,16 @@ ptsbe_status_t ptsbe_ragged_sample_shots(ptsbe_ragged_t set, const ptsbe_ragged_
   }
   int32_t* bad_flag = (int32_t*)ar.take(256);
   if (!bad_flag) return fail(PTSBE_ERR_OUT_OF_MEMORY, "workspace too small");
-  // waves: jobs heaviest first (per-trajectory cost 2^n x windows), trajectories in order
+  // waves: jobs lightest first (per-trajectory cost 2^n x windows), trajectories in
+  // order, so that light circuits complete in the first waves; inside a wave the
+  // heaviest pieces come first in the task queues (no long task at the tail)
   std::vector<int> order(n_jobs);
   std::iota(order.begin(), order.end(), 0);
   auto cost = [&](int c) {
     const Plan& p = *reinterpret_cast<const Plan*>(jobs[c].plan);
     return (double)((int64_t)1 << p.n) * (double)p.sv_win[window_choice(*set, &p)].size();
   };
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost(a) > cost(b); });
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost(a) < cost(b); });
   // tables take at most this much; the rest is the wave arena
   int64_t total_T = 0;
   for (int c = 0; c < n_jobs; ++c) total_T += jobs[c].E;
@@ -285,6 +294,7 @@ ptsbe_status_t ptsbe_ragged_sample_shots(ptsbe_ragged_t set, const ptsbe_ragged_
       }
     }
     if (cur.T > 0) waves.push_back(cur);
+    for (auto& wv : waves) std::reverse(wv.pieces.begin(), wv.pieces.end());
   }
   // tables and launch descriptors of every wave
   struct WaveLaunch {
@@ -342,6 +352,11 @@ ptsbe_status_t ptsbe_ragged_sample_shots(ptsbe_ragged_t set, const ptsbe_ragged_
       pc.psi = (float2*)wa.take((size_t)ps.nj * ((size_t)8 << p.n));
       pc.win = p.d_rg_win[wc];
       pc.fused = p.d_fused;
+      // compact plain ops when every window of the set has them and a 10..12-qubit tile
+      bool compact = p.d_sv_wins_plain[wc] && p.sv_wins_plain[wc].size() == p.sv_win[wc].size();
+      for (const auto& wd : p.sv_wins_plain[wc]) compact = compact && wd.np >= 10 && wd.n_ops <= 224;
+      pc.swin = compact ? p.d_sv_wins_plain[wc] : nullptr;
+      pc.sops = compact ? p.d_sv_ops_plain[wc] : nullptr;
       pc.shots = jb.d_shots;
       pc.norms = norms[ps.job];
       pc.row0 = row;
@@ -423,10 +438,12 @@ ptsbe_status_t ptsbe_ragged_sample_shots(ptsbe_ragged_t set, const ptsbe_ragged_
       std::vector<int32_t> lp;
       std::vector<int64_t> ls;
       int64_t tasks = 0;
+      int32_t max_ops = 0;
       for (int k = 0; k < P; ++k) {
         if (pcs[k].n_win <= l) continue;
         const Plan& p = *reinterpret_cast<const Plan*>(jobs[pcs[k].job].plan);
         const int np = p.sv_win[window_choice(*set, &p)][l].np;
+        if (pcs[k].swin) max_ops = std::max(max_ops, p.sv_wins_plain[window_choice(*set, &p)][l].n_ops);
         lp.push_back(k);
         ls.push_back(tasks);
         tasks += (int64_t)pcs[k].nj << (pcs[k].n - np);
@@ -437,6 +454,7 @@ ptsbe_status_t ptsbe_ragged_sample_shots(ptsbe_ragged_t set, const ptsbe_ragged_
       if (!lv.piece || !lv.start) return fail(PTSBE_ERR_OUT_OF_MEMORY, "wave tables do not fit");
       lv.n = (int32_t)lp.size();
       lv.tasks = tasks;
+      lv.max_ops = max_ops;
       L.levels.push_back(lv);
     }
   }

@@ -12,6 +12,7 @@
 #include "device_util.h"
 #include "internal.h"
 #include "philox.h"
+#include "sv_tile.h"
 
 namespace ptsbe {
 namespace {
@@ -113,7 +114,7 @@ __global__ void __launch_bounds__(kRgThreads) rg_prepare_kernel(RgWave w) {
 __global__ void __launch_bounds__(kRgThreads) rg_window_kernel(RgWave w, RgLevel lv, int level) {
   extern __shared__ float2 lds[];
   float2* tile = lds;
-  float2* Gm = lds + (1 << kFuseMax);
+  float2* Gm = lds + (1 << kFuseMax);   // staged gates: generic chunks, or one 16-entry slot per op
   __shared__ uint64_t pw[1];
   if (threadIdx.x == 0) pw[0] = 0ull;
   // contiguous task ranges per workgroup: consecutive tiles of one trajectory
@@ -130,9 +131,29 @@ __global__ void __launch_bounds__(kRgThreads) rg_window_kernel(RgWave w, RgLevel
     const int64_t local = task - lv.start[e];
     const int64_t traj = local >> tb;
     const uint32_t t = (uint32_t)(local & (((int64_t)1 << tb) - 1));
-    const bool ready = &pc == last_pc && traj == last_traj && wd.n_fs <= kGateChunk;
-    window_tile_pass(pc.fused + wd.fused_off, wd.n_fs, wd.P, wd.np, pc.n, t, pc.psi + (traj << pc.n), pc.g,
-                     (int)traj, pw, tile, Gm, nullptr, ready);
+    const bool same = &pc == last_pc && traj == last_traj;
+    if (pc.swin) {
+      // compact plain ops (scalar-cache reads), gates staged once per trajectory
+      const SvWin& sw = pc.swin[level];
+      const SvOp* ops = pc.sops + sw.op_off;
+      if (!same) {
+        __syncthreads();   // nobody reads the previous trajectory's gates any more
+        for (int i = threadIdx.x; i < 16 * sw.n_ops; i += kRgThreads) {
+          const SvOp& op = ops[i >> 4];
+          const int el = i & 15, d2 = op.kind == kSvOpGate1 ? 4 : 16;
+          Gm[i] = el < d2 ? pc.g.merged[(traj * pc.g.G + op.gate) * 16 + op.idx[el]] : make_float2(0.f, 0.f);
+        }
+        __syncthreads();
+      }
+      float2* A = pc.psi + (traj << pc.n) + deposit_other(t, sw.other);
+      if (sw.np == 12) plain_tile_pass<12>(ops, sw.n_ops, sw.P, A, tile, Gm);
+      else if (sw.np == 11) plain_tile_pass<11>(ops, sw.n_ops, sw.P, A, tile, Gm);
+      else plain_tile_pass<10>(ops, sw.n_ops, sw.P, A, tile, Gm);
+    } else {
+      const bool ready = same && wd.n_fs <= kGateChunk && last_pc && !last_pc->swin;
+      window_tile_pass(pc.fused + wd.fused_off, wd.n_fs, wd.P, wd.np, pc.n, t, pc.psi + (traj << pc.n), pc.g,
+                       (int)traj, pw, tile, Gm, nullptr, ready);
+    }
     last_pc = &pc;
     last_traj = traj;
   }
@@ -420,7 +441,7 @@ hipError_t launch_rg_prepare(const RgWave& w, int grid, hipStream_t s) {
 
 hipError_t launch_rg_window(const RgWave& w, const RgLevel& lv, int level, int n_cu, hipStream_t s) {
   if (lv.tasks <= 0) return hipSuccess;
-  const size_t shmem = (((size_t)1 << kFuseMax) + 16 * kGateChunk) * sizeof(float2);
+  const size_t shmem = (((size_t)1 << kFuseMax) + 16 * (size_t)std::max(kGateChunk, (int)lv.max_ops)) * sizeof(float2);
   // a persistent grid is only as large as what fits on the chip at once
   int per_cu = 0;
   hipError_t err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, rg_window_kernel, kRgThreads, shmem);

@@ -343,3 +343,36 @@ def test_chunking_query_grows_with_the_workspace():
                 method="statevector")
     with pytest.raises(P.PtsbeError):
         sv.chunking("sample", 8, 100, 1 << 30)
+
+
+def test_light_cone_kept_gates_match_the_oracle():
+    """The planner's light cone keeps, per doubled batch, exactly the gates the
+    oracle's forward-reachability selection keeps (Pauli noise on the 50-qubit
+    brickwork; amplitude damping on part of a chain, whose gates and their past
+    must stay); the last (ket) batch keeps every gate; with the option off every
+    batch keeps every gate."""
+    from oracle import lightcone
+    P = _lib()
+    rng = np.random.default_rng(4)
+    ad = W.Circuit(24)
+    dep = ad.add_channel(W.depolarizing(0.05))
+    amp = ad.add_channel(W.amplitude_damping(0.1))
+    for layer in W.brickwork_1d(24, 5):
+        for (a, b) in layer:
+            g = ad.add_gate((a, b), W.haar_su4(rng))
+            ad.add_site(g, (a,), dep)
+            if a in (13, 19):
+                ad.add_site(g, (b,), amp)
+    wl = W.brickwork50_d6()
+    for c, bs in [(wl.circuit, wl.batch_sizes), (ad, [6, 6, 6, 6])]:
+        on = P.Plan(c, bs, hypersamples=2, device=-1, method="network", light_cone=True)
+        off = P.Plan(c, bs, hypersamples=2, device=-1, method="network")
+        assert on.light_cone and not off.light_cone
+        e = 0
+        for j, b in enumerate(bs):
+            e += b
+            want = int(lightcone.kept_gates(c, e).sum()) if j < len(bs) - 1 else c.n_gates
+            assert on.batch_info(j)["kept_gates"] == want, (j, want)
+            assert off.batch_info(j)["kept_gates"] == c.n_gates
+        assert on.batch_info(0)["kept_gates"] < c.n_gates
+    _expect_status(1, lambda: P.Plan(wl.circuit, wl.batch_sizes, device=-1, light_cone=2))
