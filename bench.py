@@ -160,6 +160,9 @@ def main():
                     default="brickwork50",
                     help="ragged: the ragged mix of circuits as one graph-captured ragged set; grid5x5: the 25-qubit "
                          "grid with amplitude damping, 16384 x 256 (statevector method, --precision c64|bf16|f16)")
+    ap.add_argument("--light-cone", choices=["on", "off"], default="on",
+                    help="network method: doubled networks keep only the gates in the light cone of the measured "
+                         "qubits (plus non-unitary gates and their past); off: full networks")
     ap.add_argument("--ragged-max-qubits", type=int, default=26)
     ap.add_argument("--ragged-scope", choices=["statevector", "all"], default="statevector",
                     help="all: also the network-method plans of the mix, on a second stream")
@@ -208,7 +211,9 @@ def main():
     dev = torch.device("cuda:0")
     wl = W.brickwork50_d6()
     c = wl.circuit
-    plan = P.Plan(c, wl.batch_sizes, hypersamples=8, precision={"c64": 0, "bf16": 1, "f16": 2}[args.precision])
+    lc = args.light_cone == "on"
+    plan = P.Plan(c, wl.batch_sizes, hypersamples=8, precision={"c64": 0, "bf16": 1, "f16": 2}[args.precision],
+                  light_cone=lc)
     kr, mult, _, n_draws = plan.sample_trajectories(wl.pts_seed, args.traj)
     E = len(kr)
     kd = torch.from_numpy(kr).to(dev)
@@ -266,6 +271,7 @@ def main():
         "config": {"workload": f"50-qubit 1D brickwork depth 6, Haar SU(4) c64, depolarising p=0.005, "
                                f"{E} trajectories x {args.shots} shots, batches [10]*5, proportional NBS",
                    "trajectories": E, "shots_per_traj": args.shots, "batch_sizes": wl.batch_sizes,
+                   "light_cone": lc, "kept_gates": [plan.batch_info(j)["kept_gates"] for j in range(len(wl.batch_sizes))],
                    "pts_draws": int(n_draws), "elements_per_batch": epb,
                    "unique_bitstrings_last_step": int(torch.unique(out["shots"][:, 0]).numel())},
         "roofline": roofline,
@@ -294,7 +300,7 @@ def bench_exhaustive(args):
     bf = args.final_batch
     bs = [10, 10, 10, bf] if bf <= 20 else [10, 40 - bf, bf]
     assert sum(bs) == 50
-    plan = P.Plan(wl.circuit, bs, hypersamples=8, method="network")
+    plan = P.Plan(wl.circuit, bs, hypersamples=8, method="network", light_cone=args.light_cone == "on")
     E_req = args.traj if args.traj != 4096 else 512
     kr, mult, _, _ = plan.sample_trajectories(wl.pts_seed, E_req)
     E = len(kr)
@@ -647,7 +653,7 @@ def bench_exhaustive_paper(args):
             row = {"n": n, "g": g, "b_f": bf, "batches": bs}
             try:
                 t_p = time.perf_counter()
-                plan = P.Plan(circ, bs, hypersamples=8, method="network")
+                plan = P.Plan(circ, bs, hypersamples=8, method="network", light_cone=args.light_cone == "on")
                 row["plan_s"] = round(time.perf_counter() - t_p, 3)
                 kr, mult, _, _ = plan.sample_trajectories(7100 + n + g, E_req)
                 E = len(kr)
@@ -792,7 +798,7 @@ def bench_ragged(args):
     for k, c in enumerate(mix):
         n = c["circuit"].n_qubits
         try:
-            plan = P.Plan(c["circuit"], c["batch_sizes"], hypersamples=2)
+            plan = P.Plan(c["circuit"], c["batch_sizes"], hypersamples=2, light_cone=args.light_cone == "on")
         except P.PtsbeError as e:
             excluded.append({"n": n, "reason": str(e)[:120]})
             continue

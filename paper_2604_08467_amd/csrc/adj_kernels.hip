@@ -19,6 +19,7 @@
 
 #include "device_util.h"
 #include "internal.h"
+#include "sv_tile.h"
 
 namespace ptsbe {
 namespace {
@@ -230,6 +231,519 @@ __global__ void __launch_bounds__(kAdjThreads) adj_window_kernel(AdjArgs a, cons
   }
 }
 
+// ---------------------------------------------------------------------------
+// Tile kernels for windows of 10..12 qubits with qubit 0 at tile bit 0 (the
+// statevector window layout): 16-byte amplitude pairs between HBM and a swizzled
+// LDS tile, ops read through the scalar cache.
+//
+__device__ inline float adj_wave_sum(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// Im(conj(l) . P s) summed over the pair (s0, s1), (l0, l1) of the rotation qubit,
+// P = X, Y, Z by axis 0, 1, 2.
+__device__ inline float adj_rot_term(int axis, float2 l0, float2 l1, float2 s0, float2 s1) {
+  float2 q0, q1;
+  if (axis == 0) { q0 = s1; q1 = s0; }
+  else if (axis == 1) { q0 = make_float2(s1.y, -s1.x); q1 = make_float2(-s0.y, s0.x); }
+  else { q0 = s0; q1 = make_float2(-s1.x, -s1.y); }
+  return l0.x * q0.y - l0.y * q0.x + l1.x * q1.y - l1.y * q1.x;
+}
+
+// Backward window with psi_{k-1} = A_k^dag psi_k (every inserted operator
+// unitary): per tile, psi (the state after the window) and lambda in LDS; for each
+// op, last first, one pass applies A_k^dag to both at the op's pairs or quads and
+// accumulates, in registers, the rotation derivative Im <lambda_{k-1}|P|psi_{k-1}>
+// and (WN) the gate adjoint N_ab = sum lambda_{k-1,a} conj(psi_{k-1,b}) from the
+// same amplitudes.  Per op the thread sums are reduced over each wavefront with
+// shuffles, the four wavefronts' sums are added in a fixed order after the op's
+// barrier (double-buffered by op parity) into FP64 workgroup accumulators.
+template <int NP, bool WN>
+__global__ void __launch_bounds__(kSvwThreads) adj_bwd_tile_kernel(AdjArgs a, const AdjOp* __restrict__ ops) {
+  constexpr int PPT = 1 << (NP - 9);
+  constexpr uint32_t nt = 1u << NP;
+  extern __shared__ floatx4_t adj_lds4[];
+  float2* T0 = reinterpret_cast<float2*>(adj_lds4);      // psi
+  float2* T1 = T0 + nt;                                  // lambda
+  float2* Gb = T1 + nt;                                  // [n_ops][16] adjoint matrices
+  double* red = reinterpret_cast<double*>(Gb + 16 * a.n_ops);   // [2][4][33] wavefront sums
+  double* acc = red + 2 * 4 * 33;                        // [n_ops + 32 n_nslots]
+  floatx4_t* T04 = reinterpret_cast<floatx4_t*>(T0);
+  floatx4_t* T14 = reinterpret_cast<floatx4_t*>(T1);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int width = a.n_ops + 32 * a.n_nslots;
+  const int tb = a.n - NP;
+  const int64_t total = a.n_jobs << tb;
+  const int64_t per = (total + gridDim.x - 1) / gridDim.x;
+  const int64_t b0 = (int64_t)blockIdx.x * per, b1 = b0 + per < total ? b0 + per : total;
+  for (int i = tid; i < width; i += kSvwThreads) acc[i] = 0.0;
+  const uint32_t lo = pair_lo(a.P), pt2 = swz(2u * tid);
+  int64_t last_job = -1;
+  for (int64_t bid = b0; bid < b1; ++bid) {
+    const int64_t job = bid >> tb;
+    if (job != last_job) {
+      const int traj = a.traj_base + (int)job;
+      for (int i = tid; i < 16 * a.n_ops; i += kSvwThreads) {
+        const AdjOp& op = ops[i >> 4];
+        const int e = i & 15, d2 = op.kind == kSvOpGate1 ? 4 : 16;
+        Gb[i] = e < d2 ? a.Ad[((int64_t)traj * a.G + op.gate) * 16 + op.idx[e]] : make_float2(0.f, 0.f);
+      }
+      last_job = job;
+    }
+    const uint32_t base = deposit_other((uint32_t)(bid & (((int64_t)1 << tb) - 1)), a.other);
+    const float2* Pin = a.psi_in + (job << a.n) + base;
+    float2* Lg = a.lam + (job << a.n) + base;
+    {
+      floatx4_t v[PPT], w[PPT];
+      load_pairs<NP>(Pin, a.P, lo, v);
+      load_pairs<NP>(Lg, a.P, lo, w);
+#pragma unroll
+      for (int i = 0; i < PPT; ++i) {
+        lds_put_pair(T04, pt2, i, v[i]);
+        lds_put_pair(T14, pt2, i, w[i]);
+      }
+    }
+    __syncthreads();
+    for (int k = a.n_ops - 1; k >= 0; --k) {
+      const uint4 wd = reinterpret_cast<const uint4*>(ops)[2 * k];
+      const int kind = (int)(wd.x & 0xffu), p0 = (int)((wd.x >> 8) & 0xffu), p1 = (int)((wd.x >> 16) & 0xffu);
+      const int axis = (int)(int8_t)((wd.x >> 24) & 0xffu), nslot = (int)wd.z;
+      const bool take_n = WN && nslot >= 0;
+      const float2* g = Gb + 16 * k;
+      float rot = 0.f;
+      float nac[32];
+      if (WN) {
+#pragma unroll
+        for (int i = 0; i < 32; ++i) nac[i] = 0.f;
+      }
+      int cnt = 0;   // sums this op reduces: rotation first, then 2 d^2 entries of N
+      if (kind == kSvOpGate1) {
+        const float2 g00 = g[0], g01 = g[1], g10 = g[2], g11 = g[3];
+        const uint32_t pt = swz(ins0(tid, p0)), so = swz(1u << p0);
+#pragma unroll 2
+        for (uint32_t i = 0; i < (nt >> 1) / kSvwThreads; ++i) {
+          const uint32_t l0 = pt ^ swz(ins0(kSvwThreads * i, p0)), l1 = l0 ^ so;
+          const float2 a0 = T0[l0], a1 = T0[l1], c0 = T1[l0], c1 = T1[l1];
+          const float2 s0 = cfma(g01, a1, cmul(g00, a0)), s1 = cfma(g11, a1, cmul(g10, a0));
+          const float2 m0 = cfma(g01, c1, cmul(g00, c0)), m1 = cfma(g11, c1, cmul(g10, c0));
+          T0[l0] = s0;
+          T0[l1] = s1;
+          T1[l0] = m0;
+          T1[l1] = m1;
+          if (axis >= 0) rot += adj_rot_term(axis, m0, m1, s0, s1);
+          if (take_n) {
+            const float2 L[2] = {m0, m1}, S[2] = {s0, s1};
+#pragma unroll
+            for (int x = 0; x < 2; ++x)
+#pragma unroll
+              for (int y = 0; y < 2; ++y) {
+                nac[2 * (x * 2 + y)] += L[x].x * S[y].x + L[x].y * S[y].y;       // l conj(s)
+                nac[2 * (x * 2 + y) + 1] += L[x].y * S[y].x - L[x].x * S[y].y;
+              }
+          }
+        }
+        cnt = take_n ? 9 : 1;
+      } else {
+        float2 gm[4][4];
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+          for (int y = 0; y < 4; ++y) gm[x][y] = g[x * 4 + y];
+        const int pa = p0 < p1 ? p0 : p1, pb = p0 < p1 ? p1 : p0;
+        const uint32_t pt = swz(ins0(ins0(tid, pa), pb));
+        const uint32_t s1 = swz(1u << p0), s2 = swz(1u << p1), s3 = s1 ^ s2;
+#pragma unroll 2
+        for (uint32_t i = 0; i < (nt >> 2) / kSvwThreads; ++i) {
+          const uint32_t lb = pt ^ swz(ins0(ins0(kSvwThreads * i, pa), pb));
+          const uint32_t off[4] = {lb, lb ^ s1, lb ^ s2, lb ^ s3};
+          float2 A[4], C[4], S[4], L[4];
+#pragma unroll
+          for (int x = 0; x < 4; ++x) {
+            A[x] = T0[off[x]];
+            C[x] = T1[off[x]];
+          }
+#pragma unroll
+          for (int x = 0; x < 4; ++x) {
+            S[x] = cfma(gm[x][3], A[3], cfma(gm[x][2], A[2], cfma(gm[x][1], A[1], cmul(gm[x][0], A[0]))));
+            L[x] = cfma(gm[x][3], C[3], cfma(gm[x][2], C[2], cfma(gm[x][1], C[1], cmul(gm[x][0], C[0]))));
+          }
+#pragma unroll
+          for (int x = 0; x < 4; ++x) {
+            T0[off[x]] = S[x];
+            T1[off[x]] = L[x];
+          }
+          if (take_n) {
+#pragma unroll
+            for (int x = 0; x < 4; ++x)
+#pragma unroll
+              for (int y = 0; y < 4; ++y) {
+                nac[2 * (x * 4 + y)] += L[x].x * S[y].x + L[x].y * S[y].y;
+                nac[2 * (x * 4 + y) + 1] += L[x].y * S[y].x - L[x].x * S[y].y;
+              }
+          }
+        }
+        cnt = take_n ? 33 : 0;
+      }
+      // wavefront sums into this op's staging slot (parity k & 1)
+      double* rs = red + (k & 1) * 4 * 33 + wave * 33;
+      if (axis >= 0) {
+        const float t = adj_wave_sum(rot);
+        if (lane == 0) rs[0] = (double)t;
+      }
+      if (take_n) {
+        const int m = kind == kSvOpGate1 ? 8 : 32;
+#pragma unroll
+        for (int i = 0; i < 32; ++i) {
+          if (i < m) {
+            const float t = adj_wave_sum(nac[i]);
+            if (lane == 0) rs[1 + i] = (double)t;
+          }
+        }
+      }
+      __syncthreads();   // the op's tiles and wavefront sums are complete
+      if (tid < cnt && (tid > 0 || axis >= 0)) {
+        const double* r0 = red + (k & 1) * 4 * 33;
+        const double t = r0[tid] + r0[33 + tid] + r0[66 + tid] + r0[99 + tid];
+        if (tid == 0) acc[k] += t;
+        else acc[a.n_ops + 32 * nslot + (tid - 1)] += t;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < PPT; ++i)
+      *reinterpret_cast<floatx4_t*>(Lg + (lo | pair_hi<NP>(a.P, i))) = lds_get_pair(T14, pt2, i);
+    __syncthreads();   // every thread has read its part of lambda, and acc is complete
+  }
+  __syncthreads();
+  double* out = a.wg_acc + (int64_t)blockIdx.x * width;
+  for (int i = tid; i < width; i += kSvwThreads) out[i] = acc[i];
+}
+
+// ---------------------------------------------------------------------------
+// Group passes: the ops of one group (at most kAdjGroupMax consecutive ops on at
+// most two tile positions, build_adj_groups) are applied in one pass over the
+// tile, each thread holding its pairs (one position) or quads (two positions)
+// in registers from one LDS read to one LDS write, with one barrier per group
+// instead of one per op.
+
+// 2 x 2 matrix (g00 g01; g10 g11) on the pair (x0, x1).
+__device__ inline void adj_g2(float2 g00, float2 g01, float2 g10, float2 g11, float2& x0, float2& x1) {
+  const float2 a0 = x0, a1 = x1;
+  x0 = cfma(g01, a1, cmul(g00, a0));
+  x1 = cfma(g11, a1, cmul(g10, a0));
+}
+
+// 4 x 4 matrix gm on a quad held in tile-position order (bit 0 <-> pa, bit 1 <->
+// pb); sw: the op's local bit 0 is pb (its index bits are swapped).
+__device__ inline void adj_g4(const float2 (&gm)[4][4], bool sw, float2 (&q)[4]) {
+  const float2 x0 = q[0], x1 = sw ? q[2] : q[1], x2 = sw ? q[1] : q[2], x3 = q[3];
+  float2 y[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) y[r] = cfma(gm[r][3], x3, cfma(gm[r][2], x2, cfma(gm[r][1], x1, cmul(gm[r][0], x0))));
+  q[0] = y[0];
+  q[1] = sw ? y[2] : y[1];
+  q[2] = sw ? y[1] : y[2];
+  q[3] = y[3];
+}
+
+// Forward window, one group pass per group: psi_out = A_window psi_in per tile.
+template <int NP>
+__global__ void __launch_bounds__(kSvwThreads) adj_fwd_group_kernel(AdjArgs a, const AdjOp* __restrict__ ops) {
+  constexpr int PPT = 1 << (NP - 9);
+  constexpr uint32_t nt = 1u << NP;
+  constexpr int NPR = (nt >> 1) / kSvwThreads, NQD = (nt >> 2) / kSvwThreads;
+  extern __shared__ floatx4_t adj_lds4[];
+  float2* T0 = reinterpret_cast<float2*>(adj_lds4);
+  float2* Gf = T0 + nt;                                  // [n_ops][16]
+  floatx4_t* T04 = adj_lds4;
+  const int tid = threadIdx.x;
+  const int tb = a.n - NP;
+  const int64_t total = a.n_jobs << tb;
+  const int64_t per = (total + gridDim.x - 1) / gridDim.x;
+  const int64_t b0 = (int64_t)blockIdx.x * per, b1 = b0 + per < total ? b0 + per : total;
+  const uint32_t lo = pair_lo(a.P), pt2 = swz(2u * tid);
+  int64_t last_job = -1;
+  for (int64_t bid = b0; bid < b1; ++bid) {
+    const int64_t job = bid >> tb;
+    if (job != last_job) {
+      // the previous tile ended with a barrier: nobody reads Gf any more
+      const int traj = a.traj_base + (int)job;
+      for (int i = tid; i < 16 * a.n_ops; i += kSvwThreads) {
+        const AdjOp& op = ops[i >> 4];
+        const int e = i & 15, d2 = op.kind == kSvOpGate1 ? 4 : 16;
+        Gf[i] = e < d2 ? a.A[((int64_t)traj * a.G + op.gate) * 16 + op.idx[e]] : make_float2(0.f, 0.f);
+      }
+      last_job = job;
+    }
+    const uint32_t base = deposit_other((uint32_t)(bid & (((int64_t)1 << tb) - 1)), a.other);
+    {
+      floatx4_t v[PPT];
+      load_pairs<NP>(a.psi_in + (job << a.n) + base, a.P, lo, v);
+#pragma unroll
+      for (int i = 0; i < PPT; ++i) lds_put_pair(T04, pt2, i, v[i]);
+    }
+    __syncthreads();
+    for (int gi = 0; gi < a.n_groups; ++gi) {
+      const uint4 gd = reinterpret_cast<const uint4*>(a.groups)[gi];
+      const int nq = (int)(gd.x & 0xffu), pa = (int)((gd.x >> 8) & 0xffu), pb = (int)((gd.x >> 16) & 0xffu);
+      const int cnt = (int)((gd.x >> 24) & 0xffu), first = (int)gd.y;
+      if (nq == 1) {
+        const uint32_t pt = swz(ins0(tid, pa)), so = swz(1u << pa);
+        float2 X0[NPR], X1[NPR];
+#pragma unroll
+        for (int i = 0; i < NPR; ++i) {
+          const uint32_t l0 = pt ^ swz(ins0(kSvwThreads * i, pa));
+          X0[i] = T0[l0];
+          X1[i] = T0[l0 ^ so];
+        }
+#pragma unroll 1
+        for (int j = 0; j < cnt; ++j) {
+          const float2* g = Gf + 16 * (first + j);
+          const float2 g00 = g[0], g01 = g[1], g10 = g[2], g11 = g[3];
+#pragma unroll
+          for (int i = 0; i < NPR; ++i) adj_g2(g00, g01, g10, g11, X0[i], X1[i]);
+        }
+#pragma unroll
+        for (int i = 0; i < NPR; ++i) {
+          const uint32_t l0 = pt ^ swz(ins0(kSvwThreads * i, pa));
+          T0[l0] = X0[i];
+          T0[l0 ^ so] = X1[i];
+        }
+      } else {
+        const uint32_t pt = swz(ins0(ins0(tid, pa), pb)), s1 = swz(1u << pa), s2 = swz(1u << pb);
+        float2 X[NQD][4];
+#pragma unroll
+        for (int i = 0; i < NQD; ++i) {
+          const uint32_t lb = pt ^ swz(ins0(ins0(kSvwThreads * i, pa), pb));
+          X[i][0] = T0[lb];
+          X[i][1] = T0[lb ^ s1];
+          X[i][2] = T0[lb ^ s2];
+          X[i][3] = T0[lb ^ s1 ^ s2];
+        }
+#pragma unroll 1
+        for (int j = 0; j < cnt; ++j) {
+          const int k = first + j;
+          const uint4 w = reinterpret_cast<const uint4*>(ops)[2 * k];
+          const int kind = (int)(w.x & 0xffu), p0 = (int)((w.x >> 8) & 0xffu);
+          const float2* g = Gf + 16 * k;
+          if (kind == kSvOpGate1) {
+            const float2 g00 = g[0], g01 = g[1], g10 = g[2], g11 = g[3];
+            const bool hi = p0 != pa;   // the op's qubit is quad bit 1
+#pragma unroll
+            for (int i = 0; i < NQD; ++i) {
+#pragma unroll
+              for (int h = 0; h < 2; ++h) {
+                const int e0 = hi ? h : 2 * h, e1 = hi ? h + 2 : 2 * h + 1;
+                adj_g2(g00, g01, g10, g11, X[i][e0], X[i][e1]);
+              }
+            }
+          } else {
+            float2 gm[4][4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+              for (int c = 0; c < 4; ++c) gm[r][c] = g[r * 4 + c];
+            const bool sw = p0 != pa;
+#pragma unroll
+            for (int i = 0; i < NQD; ++i) adj_g4(gm, sw, X[i]);
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < NQD; ++i) {
+          const uint32_t lb = pt ^ swz(ins0(ins0(kSvwThreads * i, pa), pb));
+          T0[lb] = X[i][0];
+          T0[lb ^ s1] = X[i][1];
+          T0[lb ^ s2] = X[i][2];
+          T0[lb ^ s1 ^ s2] = X[i][3];
+        }
+      }
+      __syncthreads();
+    }
+    {
+      float2* Po = a.psi_out + (job << a.n) + base;
+#pragma unroll
+      for (int i = 0; i < PPT; ++i)
+        *reinterpret_cast<floatx4_t*>(Po + (lo | pair_hi<NP>(a.P, i))) = lds_get_pair(T04, pt2, i);
+    }
+    __syncthreads();
+  }
+}
+
+// Backward window with unitary inserted operators, one group pass per group (in
+// reverse): each thread holds psi and lambda at its pairs or quads, applies the
+// group's A_k^dag last op first, and sums each rotation's
+// Im <lambda_{k-1}|P|psi_{k-1}> over its amplitudes, then over the wavefront
+// (shuffles, no barrier); after the group's barrier the four wavefronts' sums are
+// added in a fixed order (staging double-buffered by group parity).
+template <int NP>
+__global__ void __launch_bounds__(kSvwThreads) adj_bwd_group_kernel(AdjArgs a, const AdjOp* __restrict__ ops) {
+  constexpr int PPT = 1 << (NP - 9);
+  constexpr uint32_t nt = 1u << NP;
+  constexpr int NPR = (nt >> 1) / kSvwThreads, NQD = (nt >> 2) / kSvwThreads;
+  extern __shared__ floatx4_t adj_lds4[];
+  float2* T0 = reinterpret_cast<float2*>(adj_lds4);      // psi
+  float2* T1 = T0 + nt;                                  // lambda
+  float2* Gb = T1 + nt;                                  // [n_ops][16] adjoint matrices
+  double* red = reinterpret_cast<double*>(Gb + 16 * a.n_ops);   // [2][4][kAdjGroupMax]
+  double* acc = red + 2 * 4 * 33;                        // [n_ops] (the same layout bound as the per-op kernel)
+  floatx4_t* T04 = reinterpret_cast<floatx4_t*>(T0);
+  floatx4_t* T14 = reinterpret_cast<floatx4_t*>(T1);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tb = a.n - NP;
+  const int64_t total = a.n_jobs << tb;
+  const int64_t per = (total + gridDim.x - 1) / gridDim.x;
+  const int64_t b0 = (int64_t)blockIdx.x * per, b1 = b0 + per < total ? b0 + per : total;
+  for (int i = tid; i < a.n_ops; i += kSvwThreads) acc[i] = 0.0;
+  const uint32_t lo = pair_lo(a.P), pt2 = swz(2u * tid);
+  int64_t last_job = -1;
+  for (int64_t bid = b0; bid < b1; ++bid) {
+    const int64_t job = bid >> tb;
+    if (job != last_job) {
+      const int traj = a.traj_base + (int)job;
+      for (int i = tid; i < 16 * a.n_ops; i += kSvwThreads) {
+        const AdjOp& op = ops[i >> 4];
+        const int e = i & 15, d2 = op.kind == kSvOpGate1 ? 4 : 16;
+        Gb[i] = e < d2 ? a.Ad[((int64_t)traj * a.G + op.gate) * 16 + op.idx[e]] : make_float2(0.f, 0.f);
+      }
+      last_job = job;
+    }
+    const uint32_t base = deposit_other((uint32_t)(bid & (((int64_t)1 << tb) - 1)), a.other);
+    float2* Lg = a.lam + (job << a.n) + base;
+    {
+      floatx4_t v[PPT], w[PPT];
+      load_pairs<NP>(a.psi_in + (job << a.n) + base, a.P, lo, v);
+      load_pairs<NP>(Lg, a.P, lo, w);
+#pragma unroll
+      for (int i = 0; i < PPT; ++i) {
+        lds_put_pair(T04, pt2, i, v[i]);
+        lds_put_pair(T14, pt2, i, w[i]);
+      }
+    }
+    __syncthreads();
+    for (int gi = a.n_groups - 1; gi >= 0; --gi) {
+      const uint4 gd = reinterpret_cast<const uint4*>(a.groups)[gi];
+      const int nq = (int)(gd.x & 0xffu), pa = (int)((gd.x >> 8) & 0xffu), pb = (int)((gd.x >> 16) & 0xffu);
+      const int cnt = (int)((gd.x >> 24) & 0xffu), first = (int)gd.y;
+      double* rs = red + (gi & 1) * 4 * kAdjGroupMax + wave * kAdjGroupMax;   // wavefront sums, by op
+      if (nq == 1) {
+        const uint32_t pt = swz(ins0(tid, pa)), so = swz(1u << pa);
+        float2 S0[NPR], S1[NPR], L0[NPR], L1[NPR];
+#pragma unroll
+        for (int i = 0; i < NPR; ++i) {
+          const uint32_t l0 = pt ^ swz(ins0(kSvwThreads * i, pa));
+          S0[i] = T0[l0];
+          S1[i] = T0[l0 ^ so];
+          L0[i] = T1[l0];
+          L1[i] = T1[l0 ^ so];
+        }
+#pragma unroll 1
+        for (int j = cnt - 1; j >= 0; --j) {
+          const int k = first + j;
+          const uint4 w = reinterpret_cast<const uint4*>(ops)[2 * k];
+          const int axis = (int)(int8_t)((w.x >> 24) & 0xffu);
+          const float2* g = Gb + 16 * k;
+          const float2 g00 = g[0], g01 = g[1], g10 = g[2], g11 = g[3];
+          float rot = 0.f;
+#pragma unroll
+          for (int i = 0; i < NPR; ++i) {
+            adj_g2(g00, g01, g10, g11, S0[i], S1[i]);
+            adj_g2(g00, g01, g10, g11, L0[i], L1[i]);
+            if (axis >= 0) rot += adj_rot_term(axis, L0[i], L1[i], S0[i], S1[i]);
+          }
+          if (axis >= 0) {
+            const float t = adj_wave_sum(rot);
+            if (lane == 0) rs[j] = (double)t;
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < NPR; ++i) {
+          const uint32_t l0 = pt ^ swz(ins0(kSvwThreads * i, pa));
+          T0[l0] = S0[i];
+          T0[l0 ^ so] = S1[i];
+          T1[l0] = L0[i];
+          T1[l0 ^ so] = L1[i];
+        }
+      } else {
+        const uint32_t pt = swz(ins0(ins0(tid, pa), pb)), s1 = swz(1u << pa), s2 = swz(1u << pb);
+        float2 S[NQD][4], L[NQD][4];
+#pragma unroll
+        for (int i = 0; i < NQD; ++i) {
+          const uint32_t lb = pt ^ swz(ins0(ins0(kSvwThreads * i, pa), pb));
+          const uint32_t off[4] = {lb, lb ^ s1, lb ^ s2, lb ^ s1 ^ s2};
+#pragma unroll
+          for (int x = 0; x < 4; ++x) {
+            S[i][x] = T0[off[x]];
+            L[i][x] = T1[off[x]];
+          }
+        }
+#pragma unroll 1
+        for (int j = cnt - 1; j >= 0; --j) {
+          const int k = first + j;
+          const uint4 w = reinterpret_cast<const uint4*>(ops)[2 * k];
+          const int kind = (int)(w.x & 0xffu), p0 = (int)((w.x >> 8) & 0xffu);
+          const int axis = (int)(int8_t)((w.x >> 24) & 0xffu);
+          const float2* g = Gb + 16 * k;
+          if (kind == kSvOpGate1) {
+            const float2 g00 = g[0], g01 = g[1], g10 = g[2], g11 = g[3];
+            const bool hi = p0 != pa;   // the op's qubit is quad bit 1
+            float rot = 0.f;
+#pragma unroll
+            for (int i = 0; i < NQD; ++i) {
+#pragma unroll
+              for (int h = 0; h < 2; ++h) {
+                // pair h: quad entries (2h, 2h + 1) on bit 0, (h, h + 2) on bit 1
+                const int e0 = hi ? h : 2 * h, e1 = hi ? h + 2 : 2 * h + 1;
+                adj_g2(g00, g01, g10, g11, S[i][e0], S[i][e1]);
+                adj_g2(g00, g01, g10, g11, L[i][e0], L[i][e1]);
+                if (axis >= 0) rot += adj_rot_term(axis, L[i][e0], L[i][e1], S[i][e0], S[i][e1]);
+              }
+            }
+            if (axis >= 0) {
+              const float t = adj_wave_sum(rot);
+              if (lane == 0) rs[j] = (double)t;
+            }
+          } else {
+            float2 gm[4][4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+              for (int c = 0; c < 4; ++c) gm[r][c] = g[r * 4 + c];
+            const bool sw = p0 != pa;
+#pragma unroll
+            for (int i = 0; i < NQD; ++i) {
+              adj_g4(gm, sw, S[i]);
+              adj_g4(gm, sw, L[i]);
+            }
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < NQD; ++i) {
+          const uint32_t lb = pt ^ swz(ins0(ins0(kSvwThreads * i, pa), pb));
+          const uint32_t off[4] = {lb, lb ^ s1, lb ^ s2, lb ^ s1 ^ s2};
+#pragma unroll
+          for (int x = 0; x < 4; ++x) {
+            T0[off[x]] = S[i][x];
+            T1[off[x]] = L[i][x];
+          }
+        }
+      }
+      __syncthreads();   // the group's tiles and wavefront sums are complete
+      if (tid < cnt && ops[first + tid].axis >= 0) {
+        const double* r0 = red + (gi & 1) * 4 * kAdjGroupMax;
+        acc[first + tid] += r0[tid] + r0[kAdjGroupMax + tid] + r0[2 * kAdjGroupMax + tid] + r0[3 * kAdjGroupMax + tid];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < PPT; ++i)
+      *reinterpret_cast<floatx4_t*>(Lg + (lo | pair_hi<NP>(a.P, i))) = lds_get_pair(T14, pt2, i);
+    __syncthreads();   // every thread has read its part of lambda, and acc is complete
+  }
+  __syncthreads();
+  double* out = a.wg_acc + (int64_t)blockIdx.x * a.n_ops;
+  for (int i = tid; i < a.n_ops; i += kSvwThreads) out[i] = acc[i];
+}
+
 // The diagonal of O = sum_t c_t Z_a Z_b over the 2^n basis states (once per call).
 __global__ void adj_zz_diag_kernel(int n, const int32_t* __restrict__ zq, const double* __restrict__ zc, int n_terms,
                                    double* __restrict__ diag) {
@@ -309,33 +823,45 @@ __global__ void __launch_bounds__(256) adj_reduce_kernel(const double* __restric
 }  // namespace
 
 size_t adj_window_lds_bytes(int mode, int np, int n_ops, int n_nslots) {
+  // one layout bound for both kernel forms: the tile kernels' backward form adds
+  // double-buffered wavefront sums [2][4][33] ahead of the accumulators
   const size_t nt = (size_t)1 << np;
   const size_t tiles = mode == 0 ? 1 : (mode == 1 ? 2 : 3);
   const size_t gates = (mode == 0 || mode == 1) ? 1 : 2;
   return tiles * nt * sizeof(float2) + gates * 16 * (size_t)n_ops * sizeof(float2) +
-         (mode == 0 ? 0 : (4 + (size_t)n_ops + 32 * (size_t)n_nslots) * sizeof(double));
+         (mode == 0 ? 0 : (2 * 4 * 33 + (size_t)n_ops + 32 * (size_t)n_nslots) * sizeof(double));
 }
 
-int adj_window_grid(int mode, size_t lds, int64_t tiles) {
+namespace {
+using AdjKernel = void (*)(AdjArgs, const AdjOp*);
+// The kernel a window runs: the tile kernels for windows of 10..12 qubits with
+// qubit 0 at tile bit 0 (forward, and backward with unitary inserted operators);
+// otherwise the general kernel.
+AdjKernel adj_kernel(int mode, const AdjArgs& a) {
+  const bool tile = mode != 2 && a.np >= 10 && a.np <= 12 && a.P[0] == 0;
+  if (!tile) return mode == 0 ? adj_window_kernel<0> : (mode == 1 ? adj_window_kernel<1> : adj_window_kernel<2>);
+  if (mode == 0)
+    return a.np == 10 ? adj_fwd_group_kernel<10> : (a.np == 11 ? adj_fwd_group_kernel<11> : adj_fwd_group_kernel<12>);
+  if (a.want_n)   // gate adjoints: one op per pass (the N sums need every op's own amplitudes)
+    return a.np == 10 ? adj_bwd_tile_kernel<10, true>
+                      : (a.np == 11 ? adj_bwd_tile_kernel<11, true> : adj_bwd_tile_kernel<12, true>);
+  return a.np == 10 ? adj_bwd_group_kernel<10> : (a.np == 11 ? adj_bwd_group_kernel<11> : adj_bwd_group_kernel<12>);
+}
+}  // namespace
+
+int adj_window_grid(int mode, const AdjArgs& a, size_t lds) {
   int per_cu = 0, dev = 0, cus = 0;
-  hipError_t e = hipSuccess;
-  if (mode == 0) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, adj_window_kernel<0>, kAdjThreads, lds);
-  else if (mode == 1) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, adj_window_kernel<1>, kAdjThreads, lds);
-  else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, adj_window_kernel<2>, kAdjThreads, lds);
+  const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, adj_kernel(mode, a), kAdjThreads, lds);
   if (e != hipSuccess || hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return 0;
+  const int64_t tiles = a.n_jobs << (a.n - a.np);
   return (int)std::min<int64_t>(tiles, (int64_t)std::max(per_cu, 1) * std::max(cus, 1));
 }
 
 hipError_t launch_adj_window(int mode, const AdjArgs& a, const AdjOp* d_ops, int grid, hipStream_t stream) {
   const size_t lds = adj_window_lds_bytes(mode, a.np, a.n_ops, a.n_nslots);
-  if (mode == 0)
-    hipLaunchKernelGGL(adj_window_kernel<0>, dim3(grid), dim3(kAdjThreads), lds, stream, a, d_ops);
-  else if (mode == 1)
-    hipLaunchKernelGGL(adj_window_kernel<1>, dim3(grid), dim3(kAdjThreads), lds, stream, a, d_ops);
-  else
-    hipLaunchKernelGGL(adj_window_kernel<2>, dim3(grid), dim3(kAdjThreads), lds, stream, a, d_ops);
+  hipLaunchKernelGGL(adj_kernel(mode, a), dim3(grid), dim3(kAdjThreads), lds, stream, a, d_ops);
   return hipGetLastError();
 }
 

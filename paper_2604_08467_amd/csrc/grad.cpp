@@ -87,7 +87,7 @@ int adj_max_ops(const Plan& p, bool backward, bool recompute, bool want_adj) {
   const int np = std::min(kAdjWindowQubits, p.n);
   const size_t tiles = (size_t)(backward ? (recompute ? 3 : 2) : 1) << np;
   const size_t per_op = (size_t)(backward && recompute ? 2 : 1) * 16 * 8 + (backward ? 8 + (want_adj ? 256 : 0) : 0);
-  const size_t fixed = tiles * 8 + 64;
+  const size_t fixed = tiles * 8 + (backward ? 2 * 4 * 33 * 8 : 0) + 64;
   return (int)std::min<size_t>(1024, (65536 - fixed) / per_op);
 }
 
@@ -102,6 +102,7 @@ size_t adj_fixed_bytes(const Plan& p, int64_t E, size_t n_ops, size_t width_tota
   b += align256((size_t)E * p.G * 128) * 2;                  // merged gates and their adjoints
   b += align256(128) + align256((size_t)p.G * 4) * 3;        // (unused derivative slot), gate tables
   b += align256(n_ops * sizeof(ptsbe::AdjOp));
+  b += align256(std::max<size_t>(n_ops, 1) * sizeof(ptsbe::AdjGroup));     // op groups (at most one per op)
   b += align256((size_t)E * 8);                              // per-trajectory values
   b += align256(64 * 4) + align256(64 * 8);                  // ZZ terms (at most 64 kept on device)
   b += align256(width_total * 8);                            // per-window totals
@@ -162,6 +163,8 @@ ptsbe_status_t ptsbe_contract_adjoint(ptsbe_plan_t plan, const ptsbe_adjoint_spe
   std::vector<ptsbe::AdjWin> wins;
   std::vector<ptsbe::AdjOp> ops;
   ptsbe::build_adj_windows(*p, kAdjWindowQubits, adj_max_ops(*p, backward, recompute, want_adj), wins, ops);
+  std::vector<ptsbe::AdjGroup> groups;
+  ptsbe::build_adj_groups(wins, ops, groups);
   const int W = (int)wins.size();
   std::vector<int> width(W), tot_off(W + 1, 0);
   size_t max_width = 1;
@@ -192,6 +195,8 @@ ptsbe_status_t ptsbe_contract_adjoint(ptsbe_plan_t plan, const ptsbe_adjoint_spe
   int32_t* d_ga = (int32_t*)ar.take((size_t)G * 4);
   int32_t* d_gs = (int32_t*)ar.take((size_t)G * 4);
   ptsbe::AdjOp* d_ops = (ptsbe::AdjOp*)ar.take(std::max<size_t>(ops.size(), 1) * sizeof(ptsbe::AdjOp));
+  ptsbe::AdjGroup* d_groups =
+      (ptsbe::AdjGroup*)ar.take(std::max<size_t>(groups.size(), 1) * sizeof(ptsbe::AdjGroup));
   double* vals = (double*)ar.take((size_t)E * 8);
   int32_t* d_zq = (int32_t*)ar.take(64 * 4);
   double* d_zc = (double*)ar.take(64 * 8);
@@ -207,6 +212,8 @@ ptsbe_status_t ptsbe_contract_adjoint(ptsbe_plan_t plan, const ptsbe_adjoint_spe
   HIP_TRY(hipMemcpyAsync(d_gs, gslot.data(), (size_t)G * 4, hipMemcpyHostToDevice, s));
   if (!ops.empty())
     HIP_TRY(hipMemcpyAsync(d_ops, ops.data(), ops.size() * sizeof(ptsbe::AdjOp), hipMemcpyHostToDevice, s));
+  if (!groups.empty())
+    HIP_TRY(hipMemcpyAsync(d_groups, groups.data(), groups.size() * sizeof(ptsbe::AdjGroup), hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(d_zq, S.zq.data(), S.zq.size() * 4, hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(d_zc, S.zc.data(), S.zc.size() * 8, hipMemcpyHostToDevice, s));
   std::vector<double> zeros((size_t)std::max(tot_off[(size_t)W], 1), 0.0);
@@ -275,6 +282,8 @@ ptsbe_status_t ptsbe_contract_adjoint(ptsbe_plan_t plan, const ptsbe_adjoint_spe
       a.traj_base = (int32_t)t0;
       a.A = merged;
       a.Ad = dagger;
+      a.groups = d_groups + wd.group_off;
+      a.n_groups = wd.n_groups;
       return a;
     };
     // forward: window w maps checkpoint w to checkpoint w + 1 (values only: two buffers)
@@ -284,7 +293,7 @@ ptsbe_status_t ptsbe_contract_adjoint(ptsbe_plan_t plan, const ptsbe_adjoint_spe
       a.psi_in = ck[backward ? (size_t)w : (size_t)(w & 1)];
       a.psi_out = ck[backward ? (size_t)w + 1 : (size_t)((w + 1) & 1)];
       const size_t lds = ptsbe::adj_window_lds_bytes(0, wd.np, wd.n_ops, 0);
-      const int grid = ptsbe::adj_window_grid(0, lds, nj << (n - wd.np));
+      const int grid = ptsbe::adj_window_grid(0, a, lds);
       if (grid < 1) return fail(PTSBE_ERR_DEVICE, "occupancy query failed");
       HIP_TRY(timed_window(0, a, d_ops + wd.op_off, grid, 16.0));
     }
@@ -310,7 +319,7 @@ ptsbe_status_t ptsbe_contract_adjoint(ptsbe_plan_t plan, const ptsbe_adjoint_spe
         a.want_n = want_adj ? 1 : 0;
         a.wg_acc = d_wg;
         const size_t lds = ptsbe::adj_window_lds_bytes(bmode, wd.np, wd.n_ops, a.n_nslots);
-        const int grid = std::min(8192, ptsbe::adj_window_grid(bmode, lds, nj << (n - wd.np)));
+        const int grid = std::min(8192, ptsbe::adj_window_grid(bmode, a, lds));
         if (grid < 1) return fail(PTSBE_ERR_DEVICE, "occupancy query failed");
         HIP_TRY(timed_window(bmode, a, d_ops + wd.op_off, grid, 24.0));
         HIP_TRY(ptsbe::launch_adj_reduce(d_wg, grid, width[(size_t)w], d_tot + tot_off[(size_t)w], s));

@@ -128,13 +128,25 @@ struct SvWin {
 // receives the gate-tensor adjoint N = sum lambda psi^dag.
 struct AdjOp {
   int8_t kind, p0, p1, axis;
-  int32_t gate, nslot, pad;
+  int32_t gate, nslot;
+  int32_t slot;                   // the op's index in its window (staged matrix slot)
   int8_t idx[16];
 };
+static_assert(sizeof(AdjOp) == 32, "AdjOp is read as eight dwords");
 struct AdjWin {
   int32_t op_off, n_ops, np;
   int32_t P[12];
+  int32_t group_off, n_groups;    // the window's op groups (build_adj_groups)
 };
+// A run of consecutive ops of a window (after regrouping) on at most two tile
+// positions pa < pb (nq = 1: pa only), applied by a tile pass in registers.
+constexpr int kAdjGroupMax = 8;
+struct AdjGroup {
+  int8_t nq, pa, pb, n;           // positions used, the group's tile positions, op count
+  int32_t first;                  // index of the group's first op in the window
+  int32_t pad[2];
+};
+static_assert(sizeof(AdjGroup) == 16, "AdjGroup is read as four dwords");
 struct AdjArgs {
   int n, np, n_ops, n_nslots, G, want_n;
   int P[12];
@@ -147,6 +159,8 @@ struct AdjArgs {
   float2* psi_out;                // forward: output states
   float2* lam;                    // backward: adjoint states, in place
   double* wg_acc;                 // backward: [grid][n_ops + 32 n_nslots] per-workgroup sums
+  const AdjGroup* groups;         // the window's op groups (tile kernels)
+  int n_groups;
 };
 struct AdjSeedArgs {
   const float2* psi;              // [n_jobs][2^n] final states
@@ -160,7 +174,7 @@ struct AdjSeedArgs {
   int32_t traj_base;
 };
 size_t adj_window_lds_bytes(int mode, int np, int n_ops, int n_nslots);
-int adj_window_grid(int mode, size_t lds, int64_t tiles);
+int adj_window_grid(int mode, const AdjArgs& a, size_t lds);
 hipError_t launch_adj_window(int mode, const AdjArgs& a, const AdjOp* d_ops, int grid, hipStream_t stream);
 hipError_t launch_adj_seed(const AdjSeedArgs& s, int64_t n_jobs, hipStream_t stream);
 hipError_t launch_adj_zz_diag(int n, const int32_t* zq, const double* zc, int n_terms, double* diag,
@@ -328,6 +342,10 @@ void build_sv_ops(Plan& p);
 // statevector schedule's steps packed as in build_sv_schedule, in circuit order,
 // every step a plain op.
 void build_adj_windows(const Plan& p, int wmax, int max_ops, std::vector<AdjWin>& wins, std::vector<AdjOp>& ops);
+// Reorders each window's ops into groups of at most kAdjGroupMax ops on at most two
+// tile positions (an op only moves past ops on other positions) and fills the
+// windows' group ranges; slots follow the new order.
+void build_adj_groups(std::vector<AdjWin>& wins, std::vector<AdjOp>& ops, std::vector<AdjGroup>& groups);
 
 // kernels.hip: launchers (all asynchronous on `stream`)
 struct GateCtx {

@@ -837,6 +837,7 @@ void build_adj_windows(const Plan& p, int wmax, int max_ops, std::vector<AdjWin>
       op.p1 = (int8_t)(st.nK == 2 ? loc(st.kpos[1]) : 0);
       op.axis = -1;
       op.nslot = -1;
+      op.slot = (int32_t)(ops.size() - (size_t)w.op_off);
       op.gate = st.gate;
       const int d = 1 << st.nK;
       for (int a = 0; a < d; ++a)
@@ -846,6 +847,50 @@ void build_adj_windows(const Plan& p, int wmax, int max_ops, std::vector<AdjWin>
     wins.push_back(w);
     rest = left_out;
   }
+}
+
+void build_adj_groups(std::vector<AdjWin>& wins, std::vector<AdjOp>& ops, std::vector<AdjGroup>& groups) {
+  groups.clear();
+  std::vector<AdjOp> out;
+  out.reserve(ops.size());
+  for (AdjWin& w : wins) {
+    std::vector<AdjOp> rest(ops.begin() + w.op_off, ops.begin() + w.op_off + w.n_ops);
+    const int off = (int)out.size();
+    w.group_off = (int32_t)groups.size();
+    while (!rest.empty()) {
+      std::vector<AdjOp> left;
+      std::set<int> Q, blocked;
+      AdjGroup g{};
+      g.first = (int32_t)out.size() - off;
+      int count = 0;
+      for (AdjOp op : rest) {
+        const bool two = op.kind == kSvOpGate2;
+        std::set<int> Q2 = Q;
+        Q2.insert(op.p0);
+        if (two) Q2.insert(op.p1);
+        const bool free = !blocked.count(op.p0) && (!two || !blocked.count(op.p1));
+        if (free && Q2.size() <= 2 && count < kAdjGroupMax) {
+          Q = Q2;
+          op.slot = (int32_t)out.size() - off;
+          out.push_back(op);
+          ++count;
+        } else {
+          blocked.insert(op.p0);
+          if (two) blocked.insert(op.p1);
+          left.push_back(op);
+        }
+      }
+      g.n = (int8_t)count;
+      g.nq = (int8_t)Q.size();
+      g.pa = (int8_t)*Q.begin();
+      g.pb = (int8_t)*Q.rbegin();
+      groups.push_back(g);
+      rest = left;
+    }
+    w.op_off = off;
+    w.n_groups = (int32_t)groups.size() - w.group_off;
+  }
+  ops = out;
 }
 
 void build_sv_ops(Plan& p) {

@@ -146,9 +146,9 @@ __global__ void __launch_bounds__(kRgThreads) rg_window_kernel(RgWave w, RgLevel
         __syncthreads();
       }
       float2* A = pc.psi + (traj << pc.n) + deposit_other(t, sw.other);
-      if (sw.np == 12) plain_tile_pass<12>(ops, sw.n_ops, sw.P, A, tile, Gm);
-      else if (sw.np == 11) plain_tile_pass<11>(ops, sw.n_ops, sw.P, A, tile, Gm);
-      else plain_tile_pass<10>(ops, sw.n_ops, sw.P, A, tile, Gm);
+      if (sw.np == 12) plain_tile_pass<12>(ops, sw.n_ops, sw.P, A, A, tile, Gm);
+      else if (sw.np == 11) plain_tile_pass<11>(ops, sw.n_ops, sw.P, A, A, tile, Gm);
+      else plain_tile_pass<10>(ops, sw.n_ops, sw.P, A, A, tile, Gm);
     } else {
       const bool ready = same && wd.n_fs <= kGateChunk && last_pc && !last_pc->swin;
       window_tile_pass(pc.fused + wd.fused_off, wd.n_fs, wd.P, wd.np, pc.n, t, pc.psi + (traj << pc.n), pc.g,

@@ -342,17 +342,21 @@ __device__ inline floatx4_t lds_get_pair(const floatx4_t* tile4, uint32_t pt2, i
   return (e & 1u) ? floatx4_t{v[2], v[3], v[0], v[1]} : v;
 }
 
-// One tile of a window of plain gates (no clusters): pairs loaded, the ops
-// applied in LDS (gate matrices staged in Gs, one slot of 16 per op), pairs
-// stored.  A: the tile's first amplitude.  Ends with a barrier.
-template <int NP>
-__device__ inline void plain_tile_pass(const SvOp* __restrict__ ops, int n_ops, const int* P, float2* A,
-                                       float2* tile, const float2* Gs) {
+// One tile of a window of plain gates (no clusters): pairs loaded from Ain, the
+// ops applied in LDS (gate matrices staged in Gs), pairs stored to Aout (Ain and
+// Aout: the tile's first amplitude in the input and output states, which may be
+// the same).  Op records are 32 bytes with kind, p0 and p1 in the low three bytes
+// of the first dword and the staged matrix slot in the fourth (SvOp, AdjOp).
+// Ends with a barrier.
+template <int NP, typename Op>
+__device__ inline void plain_tile_pass(const Op* __restrict__ ops, int n_ops, const int* P, const float2* Ain,
+                                       float2* Aout, float2* tile, const float2* Gs) {
+  static_assert(sizeof(Op) == 32, "op records are eight dwords");
   constexpr int PPT = 1 << (NP - 9);
   floatx4_t* tile4 = reinterpret_cast<floatx4_t*>(tile);
   const uint32_t lo = pair_lo(P), pt2 = swz(2u * threadIdx.x);
   floatx4_t v[PPT];
-  load_pairs<NP>(A, P, lo, v);
+  load_pairs<NP>(Ain, P, lo, v);
 #pragma unroll
   for (int i = 0; i < PPT; ++i) lds_put_pair(tile4, pt2, i, v[i]);
   __syncthreads();
@@ -364,7 +368,7 @@ __device__ inline void plain_tile_pass(const SvOp* __restrict__ ops, int n_ops, 
   }
 #pragma unroll
   for (int i = 0; i < PPT; ++i)
-    *reinterpret_cast<floatx4_t*>(A + (lo | pair_hi<NP>(P, i))) = lds_get_pair(tile4, pt2, i);
+    *reinterpret_cast<floatx4_t*>(Aout + (lo | pair_hi<NP>(P, i))) = lds_get_pair(tile4, pt2, i);
   __syncthreads();
 }
 

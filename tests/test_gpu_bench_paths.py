@@ -16,6 +16,8 @@ batch-wise marginals, Sec. III-B for the shots):
   (224 join rows, four row tiles), plus a trajectory sharing its per-trajectory
   tensor and one with its own, in one call, against the explicit FP64 network.
 
+Both run with and without the light-cone option (the oracle keeps every gate).
+
 The oracle runs in spawned worker processes (numpy only)."""
 import sys
 
@@ -58,12 +60,13 @@ def _contract(plan, torch, dev, kd, traj, prefixes, j, ws=None, amp=False):
     return pop.cpu().numpy(), (None if tot is None else tot.cpu().numpy())
 
 
-def test_chain20_k32_join_chunks_and_shared_tensors_vs_statevector_oracle():
+@pytest.mark.parametrize("light_cone", [False, True], ids=["full", "light-cone"])
+def test_chain20_k32_join_chunks_and_shared_tensors_vs_statevector_oracle(light_cone):
     import paper_2604_08467_amd as P
     torch, dev = torch_dev()
     c = W.random_brickwork(20, 6, np.random.default_rng(2024), 0.005).round_to_complex64()
     bs, m, seed = [8, 8, 4], 1000, 2025
-    plan = P.Plan(c, bs, method="network")
+    plan = P.Plan(c, bs, method="network", light_cone=light_cone)
     bi = plan.batch_info(1)
     # K = 2^5 crossing wires and >= 128 values of x per row: the qform<32, 8> join
     assert bi["doubled"] and bi["crossing"] == 5 and bi["size"] - bi["join_rows_log2"] >= 7, bi
@@ -162,12 +165,13 @@ def test_chain20_k32_join_chunks_and_shared_tensors_vs_statevector_oracle():
     assert_shot_parity(mism, expect, E * m)
 
 
-def test_brickwork50_bench_join_many_prefixes_vs_tensor_network_oracle():
+@pytest.mark.parametrize("light_cone", [False, True], ids=["full", "light-cone"])
+def test_brickwork50_bench_join_many_prefixes_vs_tensor_network_oracle(light_cone):
     import paper_2604_08467_amd as P
     torch, dev = torch_dev()
     wl = W.brickwork50_d6()
     c = wl.circuit
-    plan = P.Plan(c, wl.batch_sizes, hypersamples=8)      # the benchmark's plan
+    plan = P.Plan(c, wl.batch_sizes, hypersamples=8, light_cone=light_cone)      # the benchmark's plan
     bi = plan.batch_info(1)
     assert bi["doubled"] and bi["crossing"] == 5 and bi["size"] - bi["join_rows_log2"] == 9, bi
     kr, _, _, _ = plan.sample_trajectories(wl.pts_seed, 64)

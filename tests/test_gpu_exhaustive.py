@@ -232,3 +232,34 @@ def test_statevector_chunking_does_not_change_rows():
     a = plan.sample_nonproportional(kd, 2, 353, final_draws=25)
     b = plan.sample_nonproportional(kd, 2, 353, final_draws=25, workspace=ws)
     assert torch.equal(a["bits"], b["bits"]) and torch.equal(a["p_prefix"], b["p_prefix"])
+
+
+@pytest.mark.parametrize("light_cone", [False, True], ids=["full", "light-cone"])
+def test_exhaustive_paper_random_circuit_bf20_vs_tensor_network_oracle(light_cone):
+    """The paper's random-circuit family at its scale (Sec. IV-B, V-A): 50 qubits,
+    200 gates, batches [10, 10, 10, 20] (b = 10, b_f = 20), two draws per prefix at
+    the non-final batches; every row of four trajectories against the oracle's
+    per-trajectory non-proportional sampler on explicit FP64 networks (doubled
+    networks for the draws, the ket network for the 2^20 final-batch values)."""
+    import paper_2604_08467_amd as P
+    from oracle import tn
+    torch, dev = torch_dev()
+    circ = W.paper_random_circuit(50, 200, np.random.default_rng(7250)).round_to_complex64()
+    bs, draws, thr, seed = [10, 10, 10, 20], 2, 1e-4, 7301
+    plan = P.Plan(circ, bs, method="network", hypersamples=4, light_cone=light_cone)
+    kr, mult, _, _ = plan.sample_trajectories(7350, 4)
+    out = plan.sample_nonproportional(to_dev(torch, dev, kr), draws, seed, thr, mult_dev=to_dev(torch, dev, mult))
+    torch.cuda.synchronize()
+    starts = sampling.batch_starts(bs)
+    ref_rows, ref_counts, Z = [], np.zeros(len(bs), dtype=np.int64), []
+    for i in range(len(kr)):
+        def mfn(j, prefix, i=i):
+            kind = "ket" if j == len(bs) - 1 else "doubled"
+            v = tn.batch_network_value(circ, kr[i], starts[j], bs[j], prefix, kind)
+            return np.abs(v) ** 2 if kind == "ket" else v
+        r, c = sampling.nonproportional_trajectory(mfn, i, circ.n_qubits, bs, draws, seed, thr)
+        ref_rows.extend((i,) + tuple(x) for x in r)
+        ref_counts += np.array(c)
+        Z.append(float(np.sum(mfn(0, 0))))
+    _compare(out, ref_rows, ref_counts, bs, thr, f"paper circuit n=50 g=200 b_f=20 (light cone {light_cone})")
+    np.testing.assert_allclose(out["norms"].cpu().numpy(), np.array(Z), rtol=1e-5)
