@@ -21,6 +21,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 FP32_MFMA_PEAK_TFLOPS = 157.3
+FP32_VECTOR_PEAK_TFLOPS = 157.3
 BF16_MFMA_PEAK_TFLOPS = 2500.0
 # the join kernel version that profiles/join_traffic.txt must name to be used
 SWEEP_KERNEL_TAG = "absorb_global_kernel<NK> single HBM sweep steps, 4 kept indices per thread"
@@ -74,14 +75,14 @@ def host_cores():
     return max(1, len(os.sched_getaffinity(0)))
 
 
-def cpu_baseline(wl, kr, budget_s=20.0):
+def cpu_baseline(wl, kr, bs, budget_s=20.0):
     """The FP64 oracle, as it stands, on a bounded sample, one worker process per
     host core: worker w samples shots of trajectory w (per-shot batch-wise
     sampling with memoised explicit-network marginals) for budget_s seconds."""
     n = min(host_cores(), len(kr))
     t0 = time.perf_counter()
     with _pool(n) as pool:
-        futs = [pool.submit(_oracle_shots_worker, wl.circuit, kr[w], w, wl.batch_sizes, wl.shot_seed, budget_s)
+        futs = [pool.submit(_oracle_shots_worker, wl.circuit, kr[w], w, bs, wl.shot_seed, budget_s)
                 for w in range(n)]
         res = [f.result() for f in futs]
     dt = time.perf_counter() - t0
@@ -91,7 +92,7 @@ def cpu_baseline(wl, kr, budget_s=20.0):
                       f"batch-wise sampling with memoised explicit FP64 networks, {dt:.1f} s wall)"}
 
 
-def error_vs_fp64(plan, wl, kr, kd, shots_dev, n_pick=8):
+def error_vs_fp64(plan, wl, kr, kd, shots_dev, bs, n_pick=8):
     """The run's own error against FP64: conditionals P(x | prefix) of the elements
     that n_pick of the step's shots passed through (every batch), from the GPU path
     (ptsbe_contract_batch on the same plan) and from the explicit FP64 network."""
@@ -102,7 +103,6 @@ def error_vs_fp64(plan, wl, kr, kd, shots_dev, n_pick=8):
     from oracle import sampling
 
     c = wl.circuit
-    bs = wl.batch_sizes
     starts = sampling.batch_starts(bs)
     f = len(bs)
     m = shots_dev.shape[0] // len(kr)
@@ -156,10 +156,13 @@ def main():
                     help="exhaustive-paper workload: n x g points of the paper's random-circuit family")
     ap.add_argument("--final-batches", default="20,24,28", help="exhaustive-paper workload: b_f values")
     ap.add_argument("--workload", choices=["brickwork50", "ragged", "exhaustive", "batch-sweep", "grid5x5",
-                                           "exhaustive-paper", "hea20"],
+                                           "exhaustive-paper", "hea20", "batch-tune"],
                     default="brickwork50",
                     help="ragged: the ragged mix of circuits as one graph-captured ragged set; grid5x5: the 25-qubit "
                          "grid with amplitude damping, 16384 x 256 (statevector method, --precision c64|bf16|f16)")
+    ap.add_argument("--batches", default="auto",
+                    help="brickwork50: uniform batch size b (the remainder last), or auto: the fastest of b = 3..10 "
+                         "measured by ptsbe_tune_batches before the timed region")
     ap.add_argument("--light-cone", choices=["on", "off"], default="on",
                     help="network method: doubled networks keep only the gates in the light cone of the measured "
                          "qubits (plus non-unitary gates and their past); off: full networks")
@@ -195,6 +198,9 @@ def main():
     if args.workload == "hea20":
         bench_hea20(args)
         return
+    if args.workload == "batch-tune":
+        bench_batch_tune(args)
+        return
     if args.copy_calibration:
         n = 1 << 30
         src = torch.ones(n, dtype=torch.uint8, device="cuda:0")
@@ -212,9 +218,9 @@ def main():
     wl = W.brickwork50_d6()
     c = wl.circuit
     lc = args.light_cone == "on"
-    plan = P.Plan(c, wl.batch_sizes, hypersamples=8, precision={"c64": 0, "bf16": 1, "f16": 2}[args.precision],
-                  light_cone=lc)
-    kr, mult, _, n_draws = plan.sample_trajectories(wl.pts_seed, args.traj)
+    prec = {"c64": 0, "bf16": 1, "f16": 2}[args.precision]
+    # error sets do not depend on the batch list: drawn once with any plan
+    kr, mult, _, n_draws = P.Plan(c, wl.batch_sizes, device=-1).sample_trajectories(wl.pts_seed, args.traj)
     E = len(kr)
     kd = torch.from_numpy(kr).to(dev)
     md = torch.full((E,), args.shots, dtype=torch.int64, device=dev)
@@ -222,6 +228,24 @@ def main():
     M = E * args.shots
     ws = torch.empty(int(args.workspace_gb * (1 << 30)), dtype=torch.uint8, device=dev)
     stream = torch.cuda.current_stream(dev)
+    tune = None
+    if args.batches == "auto":
+        # the batch list is chosen before the timed region by measured time (Sec. V-B),
+        # like the path: uniform lists b = 3..10 on the first 512 trajectories
+        cands = [_batch_list(c.n_qubits, b) for b in (3, 4, 5, 6, 8, 10)]
+        ns = min(512, E)
+        t_t = time.perf_counter()
+        times, best = P.tune_batches(c, cands, kd[:ns].contiguous(), md[:ns].contiguous(), wl.shot_seed,
+                                     mult_dev=multd[:ns].contiguous(), workspace=ws, hypersamples=8,
+                                     precision=prec, light_cone=lc)
+        bs = cands[best]
+        tune = {"candidates": cands, "candidate_ms": [round(float(t), 3) for t in times], "sample_trajectories": ns,
+                "tune_s": round(time.perf_counter() - t_t, 3)}
+        print(f"bench: batch lists {dict(zip(map(str, cands), tune['candidate_ms']))} -> {bs}", file=sys.stderr,
+              flush=True)
+    else:
+        bs = _batch_list(c.n_qubits, int(args.batches))
+    plan = P.Plan(c, bs, hypersamples=8, precision=prec, light_cone=lc)
 
     def step():
         return plan.sample_shots(kd, md, wl.shot_seed, mult_dev=multd, workspace=ws, want_traj=True)
@@ -237,6 +261,7 @@ def main():
     dt = time.perf_counter() - t0
     prof = plan.profile_read()
     sw = plan.profile_read_sweeps()
+    vm = plan.profile_read_lds_sweeps()
     plan.profile_enable(False)
     shots_per_s = M * args.steps / dt
     print(f"right-part sweeps, algorithmic bytes per step: single HBM steps {sw['step_bytes'] / args.steps / 1e9:.2f} "
@@ -262,6 +287,16 @@ def main():
                 "flops": "real bilinear form over K^2 folded slots: 2K^2 per row and x (K=32: 2048; "
                          "the plain complex product would be 8320)",
                 "launches": prof["join_launches"], "kernel_ms_per_step": prof["join_ms"] / args.steps}
+    if vm["ms"] > prof["join_ms"]:
+        # small batches: the per-element LDS sweeps dominate the step; plain FP32
+        # arithmetic in LDS, against the chip's FP32 vector peak
+        join = dict(roofline)
+        vm_rate = vm["flops"] / (vm["ms"] / 1e3) / 1e12 if vm["ms"] > 0 else 0.0
+        roofline = {"bound": "alu", "achieved": vm_rate, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": vm_rate / FP32_VECTOR_PEAK_TFLOPS, "traffic": None,
+                    "kernel": "part_vm_kernel (whole per-element parts swept in LDS, one gate absorbed per step)",
+                    "flops": "8 real flops per complex multiply-add of each absorbed gate",
+                    "launches": vm["launches"], "kernel_ms_per_step": vm["ms"] / args.steps, "join": join}
     line = {
         "metric": "sampled shots/sec", "value": shots_per_s, "unit": "shots/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3,
@@ -269,18 +304,18 @@ def main():
         "dtype": {"c64": "c64", "bf16": "c64+bf16x3", "f16": "c64+f16x3"}[args.precision],
         "data": "synthetic",
         "config": {"workload": f"50-qubit 1D brickwork depth 6, Haar SU(4) c64, depolarising p=0.005, "
-                               f"{E} trajectories x {args.shots} shots, batches [10]*5, proportional NBS",
-                   "trajectories": E, "shots_per_traj": args.shots, "batch_sizes": wl.batch_sizes,
-                   "light_cone": lc, "kept_gates": [plan.batch_info(j)["kept_gates"] for j in range(len(wl.batch_sizes))],
+                               f"{E} trajectories x {args.shots} shots, batches {bs}, proportional NBS",
+                   "trajectories": E, "shots_per_traj": args.shots, "batch_sizes": bs, "batch_tuning": tune,
+                   "light_cone": lc, "kept_gates": [plan.batch_info(j)["kept_gates"] for j in range(len(bs))],
                    "pts_draws": int(n_draws), "elements_per_batch": epb,
                    "unique_bitstrings_last_step": int(torch.unique(out["shots"][:, 0]).numel())},
         "roofline": roofline,
     }
     if not args.no_cpu_baseline:
         print("bench: error vs FP64 on sampled elements", file=sys.stderr, flush=True)
-        line["error_vs_fp64"] = error_vs_fp64(plan, wl, kr, kd, out["shots"])
+        line["error_vs_fp64"] = error_vs_fp64(plan, wl, kr, kd, out["shots"], bs)
         print("bench: CPU oracle baseline", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(wl, kr)
+        line["cpu_baseline"] = cpu_baseline(wl, kr, bs)
     print(json.dumps(line), flush=True)
 
 
@@ -702,6 +737,75 @@ def bench_exhaustive_paper(args):
     print(json.dumps(line), flush=True)
 
 
+def _batch_list(n, b):
+    """[b] * k with the remainder as the last batch."""
+    k, r = divmod(n, b)
+    bs = [b] * k
+    if r:
+        bs.append(r)
+    return bs
+
+
+def bench_batch_tune(args):
+    """Batch lists chosen by measurement (Sec. V-B: the batch sizes are the
+    interface's free parameter).  On the 50-qubit brickwork (depth 6, depolarising
+    0.005, light cone per --light-cone) ptsbe_tune_batches times proportional NBS of
+    a sample (the first 512 of the 4096 trajectories x 1000 shots) under the lists
+    [b] * k + remainder for b = 5, 6, 7, 8, 10, 12; then the full workload runs
+    --steps timed steps with the fastest list and with [10] * 5.  value = shots/s
+    of the full workload with the chosen list."""
+    import numpy as np
+    import torch
+
+    import paper_2604_08467_amd as P
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    wl = W.brickwork50_d6()
+    c = wl.circuit
+    lc = args.light_cone == "on"
+    plan0 = P.Plan(c, wl.batch_sizes, hypersamples=8, light_cone=lc)
+    kr, mult, _, _ = plan0.sample_trajectories(wl.pts_seed, args.traj)
+    E = len(kr)
+    kd = torch.from_numpy(kr).to(dev)
+    multd = torch.from_numpy(mult).to(dev)
+    md = torch.full((E,), args.shots, dtype=torch.int64, device=dev)
+    ws = torch.empty(int(args.workspace_gb * (1 << 30)), dtype=torch.uint8, device=dev)
+    cands = [_batch_list(c.n_qubits, b) for b in (5, 6, 7, 8, 10, 12)]
+    ns = min(512, E)
+    t_t = time.perf_counter()
+    times, best = P.tune_batches(c, cands, kd[:ns].contiguous(), md[:ns].contiguous(), wl.shot_seed,
+                                 mult_dev=multd[:ns].contiguous(), workspace=ws, hypersamples=8, light_cone=lc)
+    tune_s = time.perf_counter() - t_t
+    print(f"batch-tune: {dict(zip(map(str, cands), np.round(times, 2)))} -> {cands[best]} ({tune_s:.1f} s)",
+          file=sys.stderr, flush=True)
+    res = {}
+    for name, bs in (("tuned", cands[best]), ("default", list(wl.batch_sizes))):
+        plan = P.Plan(c, bs, hypersamples=8, light_cone=lc)
+        for _ in range(args.warmup):
+            plan.sample_shots(kd, md, wl.shot_seed, mult_dev=multd, workspace=ws, want_traj=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            out = plan.sample_shots(kd, md, wl.shot_seed, mult_dev=multd, workspace=ws, want_traj=False)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        res[name] = {"batch_sizes": bs, "ms_per_step": dt * 1e3, "shots_per_s": E * args.shots / dt,
+                     "elements_per_batch": [int(x) for x in out["elements_per_batch"]]}
+        print(f"batch-tune: {name} {bs}: {dt * 1e3:.1f} ms per step", file=sys.stderr, flush=True)
+    line = {
+        "metric": "sampled shots/sec", "value": res["tuned"]["shots_per_s"], "unit": "shots/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": res["tuned"]["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c64", "data": "synthetic",
+        "config": {"workload": f"50-qubit 1D brickwork depth 6, Haar SU(4) c64, depolarising p=0.005, {E} "
+                               f"trajectories x {args.shots} shots, proportional NBS, batch list chosen by "
+                               f"ptsbe_tune_batches on {ns} trajectories", "light_cone": lc,
+                   "candidates": cands, "candidate_ms": [round(float(t), 3) for t in times],
+                   "tune_s": tune_s, "tuned": res["tuned"], "default": res["default"]},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def bench_batch_sweep(args):
     """Contraction time of the final batch against its size b (Sec. V-B), and the
     host path-finding time of each plan: a 100-qubit 1D brickwork of 594 Haar SU(4)
@@ -778,8 +882,11 @@ def bench_ragged(args):
     the statevector-method plans (n <= --ragged-max-qubits) as one ragged set,
     graph-captured after one autotune pass, light circuits in the first waves;
     with --ragged-scope all, the network-method plans run at the same time on a
-    second stream from a second host thread, lightest first.  Circuits no method
-    takes (2D beyond 30 qubits) are listed as excluded.  One step = every shot of
+    second stream from a second host thread, lightest first, and the statevector
+    plans beyond --ragged-max-qubits run one call each after the set (their
+    states of up to 8.6 GB leave room for few trajectories per wave; they run
+    in the timed steps only).  Circuits no method takes (2D beyond 30 qubits) are
+    listed as excluded.  One step = every shot of
     every included circuit; latency = completion time of each circuit from the
     step's start (device stamps for the set, host clock for the network plans)."""
     import threading
@@ -793,7 +900,7 @@ def bench_ragged(args):
 
     dev = torch.device("cuda:0")
     mix = W.ragged_mix()
-    jobs, net_jobs, excluded = [], [], []
+    jobs, net_jobs, big_jobs, excluded = [], [], [], []
     t_plan = time.perf_counter()
     for k, c in enumerate(mix):
         n = c["circuit"].n_qubits
@@ -802,10 +909,10 @@ def bench_ragged(args):
         except P.PtsbeError as e:
             excluded.append({"n": n, "reason": str(e)[:120]})
             continue
-        if plan.method == "statevector" and n > args.ragged_max_qubits:
-            if args.ragged_scope != "all":
-                excluded.append({"n": n, "reason": f"statevector plan beyond --ragged-max-qubits {args.ragged_max_qubits}"})
-                continue
+        big = plan.method == "statevector" and n > args.ragged_max_qubits
+        if big and args.ragged_scope != "all":
+            excluded.append({"n": n, "reason": f"statevector plan beyond --ragged-max-qubits {args.ragged_max_qubits}"})
+            continue
         if plan.method == "network" and args.ragged_scope != "all":
             excluded.append({"n": n, "reason": "network-method plan (--ragged-scope all runs it)"})
             continue
@@ -813,9 +920,10 @@ def bench_ragged(args):
         job = {"plan": plan, "kraus": torch.from_numpy(kr).to(dev), "mult": torch.from_numpy(mult).to(dev),
                "shots_per_traj": np.full(len(kr), c["shots_per_traj"], dtype=np.int64), "seed": c["shot_seed"],
                "n": n, "layout": c.get("layout", "")}
-        (jobs if plan.method == "statevector" else net_jobs).append(job)
+        (net_jobs if plan.method != "statevector" else (big_jobs if big else jobs)).append(job)
     t_plan = time.perf_counter() - t_plan
-    print(f"ragged: {len(jobs)} statevector plans in the set, {len(net_jobs)} network plans, {len(excluded)} excluded; "
+    print(f"ragged: {len(jobs)} statevector plans in the set, {len(net_jobs)} network plans, {len(big_jobs)} "
+          f"statevector plans of more than {args.ragged_max_qubits} qubits, {len(excluded)} excluded; "
           f"plans + PTS {t_plan:.1f} s", file=sys.stderr, flush=True)
     net_ws_gb = min(48.0, args.workspace_gb / 3) if net_jobs else 0.0
     # network plans lightest first (per-trajectory right-part bytes x trajectories)
@@ -833,10 +941,27 @@ def bench_ragged(args):
 
     def run_network(t0, out_lat):
         with torch.cuda.stream(stream2):
-            for j, md in zip(net_jobs, net_md):
+            for k, (j, md) in enumerate(zip(net_jobs, net_md)):
                 j["plan"].sample_shots(j["kraus"], md, j["seed"], mult_dev=j["mult"], workspace=ws2,
                                        stream=stream2.cuda_stream)
                 out_lat.append((time.perf_counter() - t0) * 1e3)
+                print(f"ragged: network plan {k + 1}/{len(net_jobs)} (n={j['n']}, E={j['kraus'].shape[0]}) done "
+                      f"at {out_lat[-1] / 1e3:.1f} s", file=sys.stderr, flush=True)
+
+    # statevector plans too large for the set (states of up to 8.6 GB: a few
+    # trajectories fill a wave): after the set, one sampling call per circuit,
+    # lightest first
+    big_jobs.sort(key=lambda j: j["kraus"].shape[0] * (2 ** j["n"]) * j["plan"].sv_windows)
+    big_md = [torch.from_numpy(j["shots_per_traj"]).to(dev) for j in big_jobs]
+
+    def run_big(t0, out_lat):
+        for k, (j, md) in enumerate(zip(big_jobs, big_md)):
+            j["plan"].sample_shots(j["kraus"], md, j["seed"], mult_dev=j["mult"], workspace=ws,
+                                   stream=stream.cuda_stream, want_traj=False)
+            stream.synchronize()
+            out_lat.append((time.perf_counter() - t0) * 1e3)
+            print(f"ragged: large statevector plan {k + 1}/{len(big_jobs)} (n={j['n']}, "
+                  f"E={j['kraus'].shape[0]}) done at {out_lat[-1] / 1e3:.1f} s", file=sys.stderr, flush=True)
 
     with torch.cuda.stream(stream):
         t_tune = time.perf_counter()
@@ -864,15 +989,18 @@ def bench_ragged(args):
             outs, lat = rs.sample_shots(jobs, graph=True, workspace=ws, stream=stream.cuda_stream, outputs=outs)
             stream.synchronize()
             t_set = (time.perf_counter() - ts) * 1e3
+            print(f"ragged: step {k} set done at {t_set / 1e3:.1f} s", file=sys.stderr, flush=True)
+            bl = []
+            run_big(ts, bl)
             th.join()
             lats.append(lat / 1e3)
-            nlats.append(np.array(nl))
+            nlats.append(np.array(nl + bl))
             print(f"ragged: step {k} done at {time.perf_counter() - t0:.1f} s (set {t_set / 1e3:.1f} s)",
                   file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
     info = rs.info()
-    M = sum(int(np.sum(j["shots_per_traj"])) for j in jobs + net_jobs)
+    M = sum(int(np.sum(j["shots_per_traj"])) for j in jobs + net_jobs + big_jobs)
     lat_all = np.concatenate([np.concatenate([a, b]) for a, b in zip(lats, nlats)])   # ms
     lat_sv = np.concatenate(lats)
     # algorithmic bytes of the gate windows: read + write of every state once per window
@@ -880,7 +1008,8 @@ def bench_ragged(args):
     for jb, bw in zip(jobs, best):
         p = jb["plan"]
         win_bytes += float(jb["kraus"].shape[0]) * 16.0 * (2 ** p.n_qubits) * p.sv_windows_for(int(bw))
-    n_all = [j["n"] for j in jobs + net_jobs]
+    n_all = [j["n"] for j in jobs + net_jobs + big_jobs]
+    big_bytes = sum(float(j["kraus"].shape[0]) * 16.0 * (2 ** j["n"]) * j["plan"].sv_windows for j in big_jobs)
     line = {
         "metric": "sampled shots/sec", "value": M * args.steps / dt, "unit": "shots/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3,
@@ -888,12 +1017,15 @@ def bench_ragged(args):
         "config": {"workload": f"ragged mix of {len(mix)} circuits (n 12..40, depth 4..10, 1D/2D Haar SU(4), "
                                f"depolarising 0.005, E log-uniform 32..2048, 100 shots): {len(jobs)} statevector "
                                f"plans as one graph-captured ragged set"
-                               + (f" + {len(net_jobs)} network-method plans on a second stream" if net_jobs else ""),
-                   "circuits": len(jobs) + len(net_jobs), "ragged_set_circuits": len(jobs),
-                   "network_circuits": len(net_jobs), "excluded_circuits": len(excluded),
+                               + (f" + {len(net_jobs)} network-method plans on a second stream" if net_jobs else "")
+                               + (f" + {len(big_jobs)} statevector plans of more than {args.ragged_max_qubits} "
+                                  "qubits, one call each after the set" if big_jobs else ""),
+                   "circuits": len(jobs) + len(net_jobs) + len(big_jobs), "ragged_set_circuits": len(jobs),
+                   "network_circuits": len(net_jobs), "large_statevector_circuits": len(big_jobs),
+                   "excluded_circuits": len(excluded),
                    "excluded_reasons": sorted({e["reason"] for e in excluded}),
                    "qubits_range": [int(min(n_all)), int(max(n_all))] if n_all else None,
-                   "trajectories": int(sum(j["kraus"].shape[0] for j in jobs + net_jobs)), "shots": M,
+                   "trajectories": int(sum(j["kraus"].shape[0] for j in jobs + net_jobs + big_jobs)), "shots": M,
                    "waves": info["n_waves"], "graphs_replayed": info["graphs_replayed"],
                    "latency_ms_p50": float(np.percentile(lat_all, 50)), "latency_ms_p99": float(np.percentile(lat_all, 99)),
                    "latency_ms_min": float(np.min(lat_all)),
@@ -901,10 +1033,11 @@ def bench_ragged(args):
                    "ragged_set_latency_ms_p99": float(np.percentile(lat_sv, 99)),
                    "autotuned_windows": {str(w): int(np.sum(best == w)) for w in (10, 11, 12)},
                    "plan_and_pts_s": t_plan},
-        "roofline": {"bound": "hbm", "achieved": win_bytes / (dt / args.steps) / 1e9, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": win_bytes / (dt / args.steps) / 1e9 / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "rg_window_kernel gate windows of the ragged set (state read+write per window), "
-                               "over the whole step time"},
+        "roofline": {"bound": "hbm", "achieved": (win_bytes + big_bytes) / (dt / args.steps) / 1e9,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": (win_bytes + big_bytes) / (dt / args.steps) / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "gate windows of the statevector plans (rg_window_kernel in the set, sv_window_kernel "
+                               "for the large plans; state read+write per window), over the whole step time"},
     }
     print(json.dumps(line), flush=True)
 

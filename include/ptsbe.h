@@ -304,6 +304,29 @@ ptsbe_status_t ptsbe_contract_batch_noalloc(ptsbe_plan_t plan, int32_t j, const 
                                             const uint64_t* d_elem_prefix, int64_t n_elems,
                                             int32_t out_kind, void* d_out, double* d_elem_total, void* stream);
 
+/* Batch lists against measured time (Sec. V-B: the qubit batch sizes b_j are a
+ * free choice of the interface and set the contraction cost).  Candidate c is
+ * the list cand_sizes[cand_offsets[c] .. cand_offsets[c+1]) (host arrays,
+ * n_candidates + 1 offsets); each gets its own plan from base_opts with that
+ * list, then ptsbe_sample_shots (proportional mode) runs once untimed and once
+ * timed with HIP events on `stream`, on the caller's trajectories and shots
+ * (the same arguments as ptsbe_sample_shots; d_shots [M][n_words] receives each
+ * candidate's shots in turn, the last one's remain).  Error sets do not depend
+ * on the batch list, so d_kraus_idx serves every candidate.
+ *   times_ms  host double [n_candidates]: the timed call, or -1 when the list
+ *             cannot be planned or sampled (sizes not summing to n_qubits, a
+ *             batch wider than the sampler draws, a workspace too small)
+ *   best      host: index of the fastest candidate
+ * PTSBE_ERR_UNSUPPORTED when no candidate runs; a device error ends the call.
+ * Plans are built and destroyed inside the call (host path finding and device
+ * constants per candidate); synchronises `stream`. */
+ptsbe_status_t ptsbe_tune_batches(const ptsbe_circuit_t* circuit, const ptsbe_plan_opts_t* base_opts,
+                                  int32_t n_candidates, const int32_t* cand_offsets, const int32_t* cand_sizes,
+                                  const uint8_t* d_kraus_idx, int64_t E, const int64_t* d_mult,
+                                  const int64_t* d_shots_per_traj, uint64_t seed, uint64_t* d_shots,
+                                  void* d_workspace, size_t workspace_bytes, void* stream, double* times_ms,
+                                  int32_t* best);
+
 /* Non-degenerate batched sampling, proportional mode (Sec. III-B).
  *   d_kraus_idx       [E][n_sites] uint8
  *   d_mult            [E] int64 multiplicities (NULL: all 1)
@@ -530,6 +553,12 @@ ptsbe_status_t ptsbe_profile_read_sweeps(ptsbe_plan_t plan, double* step_ms, int
  * forward window (checkpoint read, next checkpoint written) and 24 * 2^n for a
  * backward window (state read, adjoint state read and written). */
 ptsbe_status_t ptsbe_profile_read_windows(ptsbe_plan_t plan, double* ms, int64_t* launches, double* bytes);
+/* Parts swept whole in LDS (network method; the per-element parts of small
+ * batches, and the leading steps of larger parts), any level >= 1: total event
+ * time of those launches, launches, and algorithmic flops (each absorbed gate: 8
+ * real flops per complex multiply-add, 8 * 2^(rank_out + contracted legs) per step
+ * and job). */
+ptsbe_status_t ptsbe_profile_read_lds_sweeps(ptsbe_plan_t plan, double* ms, int64_t* launches, double* flops);
 
 #ifdef __cplusplus
 }

@@ -405,6 +405,12 @@ class Plan:
         _lib.check(self._lib.ptsbe_profile_read_windows(self._h, C.byref(ms), C.byref(n), C.byref(b)))
         return {"ms": ms.value, "launches": n.value, "bytes": b.value}
 
+    def profile_read_lds_sweeps(self):
+        """ptsbe_profile_read_lds_sweeps: parts swept whole in LDS (ms, launches, flops)."""
+        ms, n, fl = C.c_double(), C.c_int64(), C.c_double()
+        _lib.check(self._lib.ptsbe_profile_read_lds_sweeps(self._h, C.byref(ms), C.byref(n), C.byref(fl)))
+        return {"ms": ms.value, "launches": n.value, "flops": fl.value}
+
     def profile_read_sweeps(self):
         ms, b, fb = C.c_double(), C.c_double(), C.c_double()
         n = C.c_int64()
@@ -418,6 +424,38 @@ class Plan:
                                                 C.byref(e)))
         return {"join_ms": a.value, "join_launches": b.value, "join_flops": c.value, "sweep_ms": d.value,
                 "sweep_bytes": e.value}
+
+
+def tune_batches(circuit, candidates, kraus_dev, shots_per_traj_dev, seed, mult_dev=None, workspace=None,
+                 hypersamples=4, path_seed=0, device=0, precision=0, method="auto", light_cone=False, stream=None):
+    """ptsbe_tune_batches: time proportional sampling of the given trajectories under
+    each candidate batch list (list of lists); returns (times_ms array, best index)."""
+    import torch
+    lib = _lib.load()
+    arrs = _CircuitArrays(circuit)
+    offs = np.zeros(len(candidates) + 1, dtype=np.int32)
+    for c, bs in enumerate(candidates):
+        offs[c + 1] = offs[c] + len(bs)
+    sizes = np.array([b for bs in candidates for b in bs], dtype=np.int32)
+    opts = _lib.PlanOpts_t(0, None, int(hypersamples), int(path_seed), int(precision), int(device), 0,
+                           METHODS[method], int(light_cone))
+    dev = kraus_dev.device
+    E = kraus_dev.shape[0]
+    M = int(shots_per_traj_dev.sum().item())
+    words = (circuit.n_qubits + 63) // 64
+    shots = torch.empty((max(M, 1), words), dtype=torch.int64, device=dev)
+    if workspace is None:
+        raise ValueError("tune_batches needs a workspace (device uint8 tensor)")
+    if stream is None:
+        stream = torch.cuda.current_stream(dev).cuda_stream
+    times = np.zeros(len(candidates), dtype=np.float64)
+    best = C.c_int32()
+    _lib.check(lib.ptsbe_tune_batches(
+        C.byref(arrs.struct), C.byref(opts), len(candidates), _ptr(offs, C.c_int32), _ptr(sizes, C.c_int32),
+        _tptr(kraus_dev), int(E), _tptr(mult_dev), _tptr(shots_per_traj_dev), int(seed), _tptr(shots),
+        _tptr(workspace), int(workspace.numel()), C.c_void_p(stream), times.ctypes.data_as(C.c_void_p),
+        C.byref(best)))
+    return times, best.value
 
 
 def _expect_zz_function():

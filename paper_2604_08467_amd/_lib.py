@@ -21,6 +21,7 @@ EXPORTS = [
     "ptsbe_nonproportional_workspace_size", "ptsbe_sample_nonproportional", "ptsbe_profile_read_sweeps",
     "ptsbe_plan_join_tiling", "ptsbe_plan_chunking", "ptsbe_contract_batch_noalloc",
     "ptsbe_profile_read_windows", "ptsbe_adjoint_workspace_size", "ptsbe_contract_adjoint",
+    "ptsbe_tune_batches", "ptsbe_profile_read_lds_sweeps",
 ]
 
 
@@ -122,6 +123,9 @@ def load():
     lib.ptsbe_nonproportional_workspace_size.argtypes = [P, i64, i32, i32, i64, C.POINTER(sz)]
     lib.ptsbe_sample_nonproportional.argtypes = [P, P, i64, P, i32, i32, i64, u64, C.c_double, P, P, P, P, i64,
                                                  C.POINTER(i64), P, P, P, P, sz, P]
+    lib.ptsbe_tune_batches.argtypes = [C.POINTER(Circuit_t), C.POINTER(PlanOpts_t), i32, P, P, P, i64, P, P, u64, P,
+                                       P, sz, P, P, C.POINTER(i32)]
+    lib.ptsbe_profile_read_lds_sweeps.argtypes = [P, C.POINTER(C.c_double), C.POINTER(i64), C.POINTER(C.c_double)]
     lib.ptsbe_profile_enable.argtypes = [P, i32]
     lib.ptsbe_profile_read_windows.argtypes = [P, C.POINTER(C.c_double), C.POINTER(i64), C.POINTER(C.c_double)]
     lib.ptsbe_profile_read_sweeps.argtypes = [P, C.POINTER(C.c_double), C.POINTER(i64), C.POINTER(C.c_double),

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libptsbe.so")
-SOURCES = ["api.cpp", "noalloc.cpp", "planner.cpp", "grad.cpp", "sv.cpp", "ragged.cpp", "kernels.hip", "grad_kernels.hip", "adj_kernels.hip", "sv_kernels.hip", "sv_window.hip", "ragged_kernels.hip"]
+SOURCES = ["api.cpp", "noalloc.cpp", "tune.cpp", "planner.cpp", "grad.cpp", "sv.cpp", "ragged.cpp", "kernels.hip", "grad_kernels.hip", "adj_kernels.hip", "sv_kernels.hip", "sv_window.hip", "ragged_kernels.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

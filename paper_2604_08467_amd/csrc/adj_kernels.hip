@@ -729,7 +729,7 @@ __global__ void __launch_bounds__(kSvwThreads) adj_bwd_group_kernel(AdjArgs a, c
         }
       }
       __syncthreads();   // the group's tiles and wavefront sums are complete
-      if (tid < cnt && ops[first + tid].axis >= 0) {
+      if (tid < cnt && ((gd.z >> tid) & 1u)) {
         const double* r0 = red + (gi & 1) * 4 * kAdjGroupMax;
         acc[first + tid] += r0[tid] + r0[kAdjGroupMax + tid] + r0[2 * kAdjGroupMax + tid] + r0[3 * kAdjGroupMax + tid];
       }

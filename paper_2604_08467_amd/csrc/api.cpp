@@ -106,6 +106,32 @@ size_t join_traj_bytes(const ptsbe::BatchPlan& bp) {
   return ((size_t)8 << bp.right.labels.size()) + layout + part_scratch_per_job(bp.right);
 }
 
+// One LDS sweep launch (part_vm_kernel) over the first n_steps steps of a part;
+// under profiling, HIP events on the launch stream and the steps' algorithmic
+// flops (8 per complex multiply-add: 8 2^(rC + nK) per step and job).
+ptsbe_status_t timed_part_vm(Plan& p, const ptsbe::PartPlan& pp, const ptsbe::AbsorbStep* d_steps, int n_steps,
+                             int peak, const ptsbe::GateCtx& g, int64_t n_jobs, const int32_t* job_traj,
+                             int32_t traj_base, const uint64_t* job_prefix, const ptsbe::InitArgs& init, float2* out,
+                             int out_rank, hipStream_t s) {
+  std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+  if (p.profile) {
+    HIP_TRY(hipEventCreate(&ev.first));
+    HIP_TRY(hipEventCreate(&ev.second));
+    HIP_TRY(hipEventRecord(ev.first, s));
+  }
+  HIP_TRY(ptsbe::launch_part_vm(d_steps, n_steps, peak, g, n_jobs, job_traj, traj_base, job_prefix, p.NW, init, out,
+                                out_rank, s));
+  if (p.profile) {
+    HIP_TRY(hipEventRecord(ev.second, s));
+    p.vm_evs.push_back(ev);
+    ++p.vm_launches;
+    double f = 0.0;
+    for (int i = 0; i < n_steps; ++i) f += 8.0 * std::ldexp(1.0, pp.steps[(size_t)i].rC + pp.steps[(size_t)i].nK);
+    p.vm_flops += f * (double)n_jobs;
+  }
+  return PTSBE_OK;
+}
+
 // Run one part (left or right) for n_jobs jobs; the result (rank = labels.size())
 // goes to out[job][2^rank].
 ptsbe_status_t run_part(Plan& p, const ptsbe::PartPlan& pp, const ptsbe::AbsorbStep* d_steps,
@@ -119,11 +145,9 @@ ptsbe_status_t run_part(Plan& p, const ptsbe::PartPlan& pp, const ptsbe::AbsorbS
     else HIP_TRY(ptsbe::launch_fill_one(out, n_jobs, s));
     return PTSBE_OK;
   }
-  if (part_uses_vm(pp)) {
-    HIP_TRY(ptsbe::launch_part_vm(d_steps, (int)pp.steps.size(), pp.peak, g, n_jobs, job_traj, traj_base,
-                                  job_prefix, p.NW, init, out, out_rank, s));
-    return PTSBE_OK;
-  }
+  if (part_uses_vm(pp))
+    return timed_part_vm(p, pp, d_steps, (int)pp.steps.size(), pp.peak, g, n_jobs, job_traj, traj_base, job_prefix,
+                         init, out, out_rank, s);
   const size_t mark = ar.used;
   float2* b0 = (float2*)ar.take((size_t)n_jobs * ((size_t)8 << pp.peak));
   float2* b1 = (float2*)ar.take((size_t)n_jobs * ((size_t)8 << pp.peak));
@@ -151,8 +175,9 @@ ptsbe_status_t run_part(Plan& p, const ptsbe::PartPlan& pp, const ptsbe::AbsorbS
     if (!pp.segs[si].fused) last_nf = si;
   float2* A = last_nf == nseg ? out : b0;
   if (h >= 2) {
-    HIP_TRY(ptsbe::launch_part_vm(d_steps, h, hpeak, g, n_jobs, job_traj, traj_base, job_prefix, p.NW, init, A,
-                                  pp.steps[(size_t)h - 1].rC, s));
+    const ptsbe_status_t st = timed_part_vm(p, pp, d_steps, h, hpeak, g, n_jobs, job_traj, traj_base, job_prefix,
+                                            init, A, pp.steps[(size_t)h - 1].rC, s);
+    if (st != PTSBE_OK) return st;
   } else {
     if (init.Vprev) HIP_TRY(ptsbe::launch_init_gather(init, n_jobs, job_prefix, p.NW, A, s));
     else HIP_TRY(ptsbe::launch_fill_one(A, n_jobs, s));   // rank-0 start: the scalar 1 per job
@@ -516,6 +541,14 @@ ptsbe_status_t collect_events(Plan& p, std::vector<EventPair>& evs) {
     (void)hipEventDestroy(e.second);
   }
   p.sweep_evs.clear();
+  for (auto& e : p.vm_evs) {
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, e.first, e.second));
+    p.vm_ms += ms;
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
+  p.vm_evs.clear();
   return PTSBE_OK;
 }
 
@@ -704,27 +737,6 @@ ptsbe_status_t ptsbe_plan(const ptsbe_circuit_t* c, const ptsbe_plan_opts_t* o, 
     for (int st : p->gate_sites[(size_t)g])
       if (!ch_unitary[(size_t)p->site_channel[(size_t)st]]) p->gate_unitary[(size_t)g] = 0;
   }
-  // contraction method and path
-  if (o->method < PTSBE_METHOD_AUTO || o->method > PTSBE_METHOD_STATEVECTOR)
-    return fail(PTSBE_ERR_INVALID_ARG, "unknown method");
-  std::string err;
-  bool sv_fits = p->n <= ptsbe::kSvMaxQubits;   // the statevector sampler takes batches of <= 12 qubits
-  for (int b : p->batch_sizes) sv_fits = sv_fits && b <= 12;
-  bool use_sv = o->method == PTSBE_METHOD_STATEVECTOR || (o->method == PTSBE_METHOD_AUTO && p->n <= 20 && sv_fits);
-  if (!use_sv) {
-    const bool net_ok = ptsbe::build_batch_plans(*p, err);
-    if (!net_ok) {
-      if (o->method == PTSBE_METHOD_NETWORK || !sv_fits) return fail(PTSBE_ERR_UNSUPPORTED, err);
-      use_sv = true;
-    }
-  }
-  if (use_sv) {
-    if (p->n > ptsbe::kSvMaxQubits) return fail(PTSBE_ERR_UNSUPPORTED, "the statevector method needs n_qubits <= 30");
-    for (int b : p->batch_sizes)
-      if (b > 12) return fail(PTSBE_ERR_UNSUPPORTED, "the statevector method samples batches of at most 12 qubits");
-    p->method = PTSBE_METHOD_STATEVECTOR;
-    ptsbe::build_sv_batches(*p);
-  }
   // statevector schedule: every gate in circuit order, in place on qubit positions
   if (p->n <= ptsbe::kSvMaxQubits) {
     for (int g = 0; g < p->G; ++g) {
@@ -755,6 +767,36 @@ ptsbe_status_t ptsbe_plan(const ptsbe_circuit_t* c, const ptsbe_plan_opts_t* o, 
       }
       p->sv_steps.push_back(st);
     }
+  }
+  // contraction method and path
+  if (o->method < PTSBE_METHOD_AUTO || o->method > PTSBE_METHOD_STATEVECTOR)
+    return fail(PTSBE_ERR_INVALID_ARG, "unknown method");
+  std::string err;
+  bool sv_fits = p->n <= ptsbe::kSvMaxQubits;   // the statevector sampler takes batches of <= 12 qubits
+  for (int b : p->batch_sizes) sv_fits = sv_fits && b <= 12;
+  bool use_sv = o->method == PTSBE_METHOD_STATEVECTOR || (o->method == PTSBE_METHOD_AUTO && p->n <= 20 && sv_fits);
+  if (!use_sv) {
+    const bool net_ok = ptsbe::build_batch_plans(*p, err);
+    if (!net_ok) {
+      if (o->method == PTSBE_METHOD_NETWORK || !sv_fits) return fail(PTSBE_ERR_UNSUPPORTED, err);
+      use_sv = true;
+    } else if (o->method == PTSBE_METHOD_AUTO && sv_fits) {
+      // both methods run: the one that moves fewer bytes per trajectory (the
+      // network method's per-trajectory parts against the statevector's window
+      // passes and marginal reads; per-element work is not counted)
+      double net_bytes = 0.0;
+      for (const auto& bp : p->batches) net_bytes += bp.right.bytes;
+      const double sv_bytes = (16.0 * ptsbe::count_sv_windows(*p, ptsbe::kFuseMax) + 8.0 * p->batch_sizes.size()) *
+                              std::ldexp(1.0, p->n);
+      use_sv = sv_bytes < net_bytes;
+    }
+  }
+  if (use_sv) {
+    if (p->n > ptsbe::kSvMaxQubits) return fail(PTSBE_ERR_UNSUPPORTED, "the statevector method needs n_qubits <= 30");
+    for (int b : p->batch_sizes)
+      if (b > 12) return fail(PTSBE_ERR_UNSUPPORTED, "the statevector method samples batches of at most 12 qubits");
+    p->method = PTSBE_METHOD_STATEVECTOR;
+    ptsbe::build_sv_batches(*p);
   }
   // device constants
   std::vector<ptsbe::DeviceGate> dg(p->G);
@@ -901,6 +943,10 @@ void ptsbe_plan_destroy(ptsbe_plan_t plan) {
   Plan* p = reinterpret_cast<Plan*>(plan);
   if (!p) return;
   for (auto& e : p->sweep_evs) {   // events of a profiled call that returned early
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
+  for (auto& e : p->vm_evs) {
     (void)hipEventDestroy(e.first);
     (void)hipEventDestroy(e.second);
   }
@@ -1682,6 +1728,13 @@ ptsbe_status_t ptsbe_profile_enable(ptsbe_plan_t plan, int32_t on) {
     (void)hipEventDestroy(e.second);
   }
   p->win_evs.clear();
+  for (auto& e : p->vm_evs) {
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
+  p->vm_evs.clear();
+  p->vm_ms = p->vm_flops = 0;
+  p->vm_launches = 0;
   p->profile = on;
   p->join_ms = p->sweep_ms = p->join_flops = p->sweep_bytes = p->fused_bytes = 0;
   p->join_launches = p->sweep_launches = 0;
@@ -1707,6 +1760,15 @@ ptsbe_status_t ptsbe_profile_read_sweeps(ptsbe_plan_t plan, double* step_ms, int
   if (step_launches) *step_launches = p->sweep_launches;
   if (step_bytes) *step_bytes = p->sweep_bytes;
   if (fused_bytes) *fused_bytes = p->fused_bytes;
+  return PTSBE_OK;
+}
+
+ptsbe_status_t ptsbe_profile_read_lds_sweeps(ptsbe_plan_t plan, double* ms, int64_t* launches, double* flops) {
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  if (!p) return fail(PTSBE_ERR_INVALID_ARG, "null plan");
+  if (ms) *ms = p->vm_ms;
+  if (launches) *launches = p->vm_launches;
+  if (flops) *flops = p->vm_flops;
   return PTSBE_OK;
 }
 

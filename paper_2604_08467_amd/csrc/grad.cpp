@@ -175,6 +175,12 @@ ptsbe_status_t ptsbe_contract_adjoint(ptsbe_plan_t plan, const ptsbe_adjoint_spe
       op.axis = (int8_t)(want_grad && S.gate_param[(size_t)op.gate] >= 0 ? S.gate_axis[(size_t)op.gate] : -1);
       op.nslot = want_adj ? k : -1;
     }
+    for (int gi = 0; gi < wd.n_groups; ++gi) {
+      ptsbe::AdjGroup& gr = groups[(size_t)(wd.group_off + gi)];
+      gr.rot_mask = 0;
+      for (int j = 0; j < gr.n; ++j)
+        if (ops[(size_t)(wd.op_off + gr.first + j)].axis >= 0) gr.rot_mask |= 1u << j;
+    }
     width[(size_t)w] = wd.n_ops + (want_adj ? 32 * wd.n_ops : 0);
     tot_off[(size_t)w + 1] = tot_off[(size_t)w] + width[(size_t)w];
     max_width = std::max<size_t>(max_width, (size_t)width[(size_t)w]);

@@ -144,7 +144,8 @@ constexpr int kAdjGroupMax = 8;
 struct AdjGroup {
   int8_t nq, pa, pb, n;           // positions used, the group's tile positions, op count
   int32_t first;                  // index of the group's first op in the window
-  int32_t pad[2];
+  uint32_t rot_mask;              // bit j: op first + j is a differentiated rotation
+  int32_t pad;
 };
 static_assert(sizeof(AdjGroup) == 16, "AdjGroup is read as four dwords");
 struct AdjArgs {
@@ -317,6 +318,10 @@ struct Plan {
   double join_ms = 0, sweep_ms = 0, join_flops = 0, sweep_bytes = 0, fused_bytes = 0;
   int64_t join_launches = 0, sweep_launches = 0;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> sweep_evs;   // recorded, not yet read
+  // whole parts swept in LDS (part_vm_kernel): event time, launches, algorithmic flops
+  double vm_ms = 0, vm_flops = 0;
+  int64_t vm_launches = 0;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> vm_evs;      // recorded, not yet read
   // statevector gate windows (any profile level): event time, launches, algorithmic bytes
   double win_ms = 0, win_bytes = 0;
   int64_t win_launches = 0;
@@ -341,6 +346,8 @@ void build_sv_ops(Plan& p);
 // Windows of at most wmax qubits and max_ops steps for the adjoint pass: the
 // statevector schedule's steps packed as in build_sv_schedule, in circuit order,
 // every step a plain op.
+// Gate windows of at most wmax qubits the statevector schedule needs (needs sv_steps).
+int count_sv_windows(const Plan& p, int wmax);
 void build_adj_windows(const Plan& p, int wmax, int max_ops, std::vector<AdjWin>& wins, std::vector<AdjOp>& ops);
 // Reorders each window's ops into groups of at most kAdjGroupMax ops on at most two
 // tile positions (an op only moves past ops on other positions) and fills the

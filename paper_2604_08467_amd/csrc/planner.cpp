@@ -806,6 +806,19 @@ std::vector<Segment> sv_windows(Plan& p, int wmax, std::vector<AbsorbStep>* run,
 }
 }  // namespace
 
+int count_sv_windows(const Plan& p, int wmax) {
+  std::vector<int> rest(p.sv_steps.size());
+  for (size_t i = 0; i < rest.size(); ++i) rest[i] = (int)i;
+  int w = 0;
+  while (!rest.empty()) {
+    std::vector<int> taken, left_out, Pv;
+    pack_window(p, rest, wmax, taken, left_out, Pv);
+    rest = left_out;
+    ++w;
+  }
+  return w;
+}
+
 void build_sv_schedule(Plan& p) {
   p.sv_run.clear();
   for (int i = 0; i < 3; ++i) {

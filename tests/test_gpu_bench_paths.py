@@ -166,16 +166,19 @@ def test_chain20_k32_join_chunks_and_shared_tensors_vs_statevector_oracle(light_
 
 
 @pytest.mark.parametrize("light_cone", [False, True], ids=["full", "light-cone"])
-def test_brickwork50_bench_join_many_prefixes_vs_tensor_network_oracle(light_cone):
+@pytest.mark.parametrize("bs,j", [([10] * 5, 1), ([5] * 10, 2)], ids=["b10", "b5"])
+def test_brickwork50_bench_join_many_prefixes_vs_tensor_network_oracle(bs, j, light_cone):
+    """The benchmark's plans (batch lists b = 10 and b = 5, the measured choice)
+    at the batch that starts at qubit 10."""
     import paper_2604_08467_amd as P
     torch, dev = torch_dev()
     wl = W.brickwork50_d6()
     c = wl.circuit
-    plan = P.Plan(c, wl.batch_sizes, hypersamples=8, light_cone=light_cone)      # the benchmark's plan
-    bi = plan.batch_info(1)
-    assert bi["doubled"] and bi["crossing"] == 5 and bi["size"] - bi["join_rows_log2"] == 9, bi
+    plan = P.Plan(c, bs, hypersamples=8, light_cone=light_cone)      # the benchmark's plan
+    bi = plan.batch_info(j)
+    assert bi["doubled"] and bi["crossing"] == 5 and bi["start"] == 10, bi
     kr, _, _, _ = plan.sample_trajectories(wl.pts_seed, 64)
-    rs = set(plan.right_sites(1).tolist())
+    rs = set(plan.right_sites(j).tolist())
     n_kraus = [c.channels[ch].kraus.shape[0] for ch in c.site_channel]
     # A: a trajectory with an error inside batch 1's per-trajectory part; A2: A with one
     # site outside that part changed (shares A's tensor); B: another trajectory
@@ -190,11 +193,11 @@ def test_brickwork50_bench_join_many_prefixes_vs_tensor_network_oracle(light_con
     pre += [int(x) for x in rng.choice(1024, 16, replace=False)]
     pre += [int(x) for x in rng.choice(1024, 16, replace=False)]
     traj = [0] * 112 + [1] * 16 + [2] * 16
-    _say(f"brickwork50: 144 batch-1 elements of 3 trajectories (A = {a}, B = {b}), oracle in workers")
+    _say(f"brickwork50 {bs[0]}: 144 elements of batch {j} of 3 trajectories (A = {a}, B = {b}), oracle in workers")
     with oracle_pool() as pool:
-        futs = [pool.submit(tn_value_job, c, rows[t], 10, 10, p, "doubled") for t, p in zip(traj, pre)]
+        futs = [pool.submit(tn_value_job, c, rows[t], 10, bs[j], p, "doubled") for t, p in zip(traj, pre)]
         kd = to_dev(torch, dev, rows)
-        pop, tot = _contract(plan, torch, dev, kd, traj, pre, 1)
+        pop, tot = _contract(plan, torch, dev, kd, traj, pre, j)
         refs = [f.result() for f in futs]
     worst = 0.0
     for e, ref in enumerate(refs):

@@ -144,8 +144,10 @@ def test_untouched_qubit_gets_identity():
 
 
 def test_method_selection():
-    """auto: statevector for n <= 20 or when the network sweep does not fit (n <= 30);
-    network otherwise.  Forced methods fail with UNSUPPORTED where they cannot run."""
+    """auto: statevector for n <= 20, when the network sweep does not fit, or when
+    (n <= 30) its window passes move fewer bytes per trajectory than the network
+    method's per-trajectory parts; network otherwise.  Forced methods fail with
+    UNSUPPORTED where they cannot run."""
     P = _lib()
     wl1, wl2, wl3 = W.chain10_d8(), W.brickwork50_d6(), W.grid5x5_d8((10, 10, 5))
     assert P.Plan(wl1.circuit, wl1.batch_sizes, device=-1).method == "statevector"
@@ -167,6 +169,20 @@ def test_method_selection():
     _expect_status(2, lambda: P.Plan(wl2.circuit, wl2.batch_sizes, device=-1, method="statevector"))  # n > 30
     with pytest.raises(ValueError):
         P.Plan(wl1.circuit, wl1.batch_sizes, device=-1, method="dense")
+    # between 21 and 30 qubits auto takes the method with fewer bytes per trajectory
+    rng = np.random.default_rng(12)
+    for layout, n, depth in [("2d", 24, 8), ("2d", 23, 4), ("1d", 24, 6), ("1d", 28, 4)]:
+        c = W.random_brickwork(n, depth, rng, 0.01, layout=layout)
+        bs = [10, 10, n - 20]
+        sv = P.Plan(c, bs, device=-1, method="statevector")
+        sv_bytes = (16.0 * sv.sv_windows + 8.0 * 3) * 2.0 ** n
+        try:
+            net = P.Plan(c, bs, device=-1, method="network")
+            net_bytes = sum(net.batch_info(j)["bytes_per_traj"] for j in range(3))
+        except P.PtsbeError:
+            net_bytes = float("inf")          # no feasible sweep
+        want = "statevector" if sv_bytes < net_bytes else "network"
+        assert P.Plan(c, bs, device=-1).method == want, (layout, n, net_bytes, sv_bytes)
 
 
 def test_statevector_windows_cover_small_circuits_in_one_launch():
