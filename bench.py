@@ -166,6 +166,9 @@ def main():
     ap.add_argument("--light-cone", choices=["on", "off"], default="on",
                     help="network method: doubled networks keep only the gates in the light cone of the measured "
                          "qubits (plus non-unitary gates and their past); off: full networks")
+    ap.add_argument("--subtree-reuse", choices=["on", "off"], default="off",
+                    help="network method: per-trajectory parts share partial sweeps between error sets that agree "
+                         "on the sites absorbed so far (bit-identical results)")
     ap.add_argument("--ragged-max-qubits", type=int, default=26)
     ap.add_argument("--ragged-scope", choices=["statevector", "all"], default="statevector",
                     help="all: also the network-method plans of the mix, on a second stream")
@@ -218,6 +221,7 @@ def main():
     wl = W.brickwork50_d6()
     c = wl.circuit
     lc = args.light_cone == "on"
+    sr = args.subtree_reuse == "on"
     prec = {"c64": 0, "bf16": 1, "f16": 2}[args.precision]
     # error sets do not depend on the batch list: drawn once with any plan
     kr, mult, _, n_draws = P.Plan(c, wl.batch_sizes, device=-1).sample_trajectories(wl.pts_seed, args.traj)
@@ -237,7 +241,7 @@ def main():
         t_t = time.perf_counter()
         times, best = P.tune_batches(c, cands, kd[:ns].contiguous(), md[:ns].contiguous(), wl.shot_seed,
                                      mult_dev=multd[:ns].contiguous(), workspace=ws, hypersamples=8,
-                                     precision=prec, light_cone=lc)
+                                     precision=prec, light_cone=lc, subtree_reuse=sr)
         bs = cands[best]
         tune = {"candidates": cands, "candidate_ms": [round(float(t), 3) for t in times], "sample_trajectories": ns,
                 "tune_s": round(time.perf_counter() - t_t, 3)}
@@ -245,7 +249,7 @@ def main():
               flush=True)
     else:
         bs = _batch_list(c.n_qubits, int(args.batches))
-    plan = P.Plan(c, bs, hypersamples=8, precision=prec, light_cone=lc)
+    plan = P.Plan(c, bs, hypersamples=8, precision=prec, light_cone=lc, subtree_reuse=sr)
 
     def step():
         return plan.sample_shots(kd, md, wl.shot_seed, mult_dev=multd, workspace=ws, want_traj=True)
@@ -306,7 +310,8 @@ def main():
         "config": {"workload": f"50-qubit 1D brickwork depth 6, Haar SU(4) c64, depolarising p=0.005, "
                                f"{E} trajectories x {args.shots} shots, batches {bs}, proportional NBS",
                    "trajectories": E, "shots_per_traj": args.shots, "batch_sizes": bs, "batch_tuning": tune,
-                   "light_cone": lc, "kept_gates": [plan.batch_info(j)["kept_gates"] for j in range(len(bs))],
+                   "light_cone": lc, "subtree_reuse": sr,
+                   "kept_gates": [plan.batch_info(j)["kept_gates"] for j in range(len(bs))],
                    "pts_draws": int(n_draws), "elements_per_batch": epb,
                    "unique_bitstrings_last_step": int(torch.unique(out["shots"][:, 0]).numel())},
         "roofline": roofline,

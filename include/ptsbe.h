@@ -154,6 +154,16 @@ typedef struct {
                                    from unitarity.  0: full networks.  Network
                                    method only (the statevector method ignores
                                    it); other values: INVALID_ARG                */
+  int32_t subtree_reuse;        /* 1: the per-trajectory parts of the network
+                                   method reuse partial sweeps between error sets
+                                   (Sec. VI names such caching as open): jobs whose
+                                   Kraus choices agree on every site absorbed so
+                                   far share the running tensor, and split only at
+                                   the launch that absorbs a site they disagree on.
+                                   Results are bit-identical to 0 (each group runs
+                                   on gates every member shares).  Parts swept
+                                   whole in LDS are not split.  0: off; other
+                                   values: INVALID_ARG                           */
 } ptsbe_plan_opts_t;
 
 typedef struct {
@@ -169,6 +179,7 @@ typedef struct {
   int32_t sv_cluster_steps;     /* gates applied inside those clusters           */
   int32_t precision;            /* the plan's precision option                    */
   int32_t light_cone;           /* the plan's light-cone option                   */
+  int32_t subtree_reuse;        /* the plan's subtree-reuse option                */
 } ptsbe_plan_info_t;
 
 /* Per-batch description of the unified path P^j (host-side cost model). */

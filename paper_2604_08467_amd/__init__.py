@@ -116,7 +116,7 @@ class Plan:
     """ptsbe_plan: the unified contraction path of every batch (host, once)."""
 
     def __init__(self, circuit, batch_sizes, hypersamples=4, path_seed=0, device=0, precision=0,
-                 device_budget_bytes=0, method="auto", light_cone=False):
+                 device_budget_bytes=0, method="auto", light_cone=False, subtree_reuse=False):
         self._lib = _lib.load()
         self.n_qubits = circuit.n_qubits
         self.n_sites = len(circuit.site_gate)
@@ -126,7 +126,8 @@ class Plan:
         if method not in METHODS:
             raise ValueError(f"method must be one of {sorted(METHODS)}")
         opts = _lib.PlanOpts_t(len(bs), _ptr(bs, C.c_int32), int(hypersamples), int(path_seed), int(precision),
-                               int(device), int(device_budget_bytes), METHODS[method], int(light_cone))
+                               int(device), int(device_budget_bytes), METHODS[method], int(light_cone),
+                               int(subtree_reuse))
         h = C.c_void_p()
         _lib.check(self._lib.ptsbe_plan(C.byref(arrs.struct), C.byref(opts), C.byref(h)))
         self._h = h
@@ -143,6 +144,7 @@ class Plan:
         self.sv_cluster_steps = info.sv_cluster_steps
         self.precision = info.precision
         self.light_cone = bool(info.light_cone)
+        self.subtree_reuse = bool(info.subtree_reuse)
 
     def sv_windows_for(self, window_qubits):
         """Gate windows (state passes) of the statevector schedule for windows of
@@ -427,7 +429,8 @@ class Plan:
 
 
 def tune_batches(circuit, candidates, kraus_dev, shots_per_traj_dev, seed, mult_dev=None, workspace=None,
-                 hypersamples=4, path_seed=0, device=0, precision=0, method="auto", light_cone=False, stream=None):
+                 hypersamples=4, path_seed=0, device=0, precision=0, method="auto", light_cone=False,
+                 subtree_reuse=False, stream=None):
     """ptsbe_tune_batches: time proportional sampling of the given trajectories under
     each candidate batch list (list of lists); returns (times_ms array, best index)."""
     import torch
@@ -438,7 +441,7 @@ def tune_batches(circuit, candidates, kraus_dev, shots_per_traj_dev, seed, mult_
         offs[c + 1] = offs[c] + len(bs)
     sizes = np.array([b for bs in candidates for b in bs], dtype=np.int32)
     opts = _lib.PlanOpts_t(0, None, int(hypersamples), int(path_seed), int(precision), int(device), 0,
-                           METHODS[method], int(light_cone))
+                           METHODS[method], int(light_cone), int(bool(subtree_reuse)))
     dev = kraus_dev.device
     E = kraus_dev.shape[0]
     M = int(shots_per_traj_dev.sum().item())

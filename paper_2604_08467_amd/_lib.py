@@ -48,6 +48,7 @@ class PlanOpts_t(C.Structure):
         ("n_batches", C.c_int32), ("batch_sizes", C.POINTER(C.c_int32)), ("hypersamples", C.c_int32),
         ("path_seed", C.c_uint64), ("precision", C.c_int32), ("device", C.c_int32),
         ("device_budget_bytes", C.c_size_t), ("method", C.c_int32), ("light_cone", C.c_int32),
+        ("subtree_reuse", C.c_int32),
     ]
 
 
@@ -57,7 +58,7 @@ class PlanInfo_t(C.Structure):
         ("n_words", C.c_int32), ("max_kraus", C.c_int32), ("plan_device_bytes", C.c_int64),
         ("method", C.c_int32), ("sv_windows", C.c_int32), ("sv_windows_by_size", C.c_int32 * 3),
         ("sv_clusters", C.c_int32), ("sv_cluster_steps", C.c_int32), ("precision", C.c_int32),
-        ("light_cone", C.c_int32),
+        ("light_cone", C.c_int32), ("subtree_reuse", C.c_int32),
     ]
 
 

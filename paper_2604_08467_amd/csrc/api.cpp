@@ -132,12 +132,76 @@ ptsbe_status_t timed_part_vm(Plan& p, const ptsbe::PartPlan& pp, const ptsbe::Ab
   return PTSBE_OK;
 }
 
+// Subtree reuse in a per-trajectory part (Sec. VI: cached intermediates between
+// error sets): jobs whose error sets agree on every noise site absorbed so far share
+// the running tensor, and a job gets its own copy only at the launch where a site it
+// disagrees on is absorbed.  Jobs are the distinct error patterns of the part (one
+// representative trajectory each); at each launch boundary the jobs are grouped by
+// their Kraus choices on the sites absorbed up to there, each group running once on
+// its first job's gates (identical for every member on those sites, so results are
+// bit-identical to running every job alone).
+struct PartTrie {
+  const uint8_t* h_kraus = nullptr;                 // host [E][S]
+  int64_t S = 0;
+  const std::vector<int32_t>* reps = nullptr;       // absolute trajectory of each job
+  std::vector<std::vector<int32_t>>* keep = nullptr;   // host sources of async uploads
+};
+
+// Jobs of the level that ends after step `end` (exclusive): the first job of every
+// group of equal Kraus choices on the sites absorbed so far, ascending; pos[r] =
+// index of job r's group in that list.  Incremental: `done` marks the sites
+// already absorbed (steps before `from`), and the groups refine the previous
+// level's (prev_pos, empty at the first level) by the choices on the new sites.
+void trie_level(const Plan& p, const ptsbe::PartPlan& pp, const PartTrie& t, int from, int end,
+                std::vector<char>& done, const std::vector<int32_t>& prev_pos, std::vector<int32_t>& first,
+                std::vector<int32_t>& pos) {
+  std::vector<int32_t> sites;
+  for (int i = from; i < end; ++i) {
+    const int gate = pp.steps[(size_t)i].gate;
+    if (gate < 0 || gate >= p.n_user_gates) continue;
+    for (int st : p.gate_sites[(size_t)gate])
+      if (!done[(size_t)st]) {
+        done[(size_t)st] = 1;
+        sites.push_back(st);
+      }
+  }
+  const std::vector<int32_t>& reps = *t.reps;
+  first.clear();
+  pos.assign(reps.size(), 0);
+  if (sites.empty() && !prev_pos.empty()) {      // no new site: the previous groups
+    std::vector<int32_t> seen_first;
+    for (size_t r = 0; r < reps.size(); ++r) {
+      const int32_t gi = prev_pos[r];
+      if ((size_t)gi >= seen_first.size()) seen_first.resize((size_t)gi + 1, -1);
+      if (seen_first[(size_t)gi] < 0) {
+        seen_first[(size_t)gi] = (int32_t)first.size();
+        first.push_back((int32_t)r);
+      }
+      pos[r] = seen_first[(size_t)gi];
+    }
+    return;
+  }
+  std::unordered_map<std::string, int32_t> seen;
+  std::string key(4 + sites.size(), '\0');
+  for (size_t r = 0; r < reps.size(); ++r) {
+    const int32_t gi = prev_pos.empty() ? 0 : prev_pos[r];
+    std::memcpy(&key[0], &gi, 4);
+    const uint8_t* kr = t.h_kraus + (int64_t)reps[r] * t.S;
+    for (size_t i = 0; i < sites.size(); ++i) key[4 + i] = (char)kr[sites[i]];
+    auto it = seen.emplace(key, (int32_t)first.size());
+    if (it.second) first.push_back((int32_t)r);
+    pos[r] = it.first->second;
+  }
+}
+
 // Run one part (left or right) for n_jobs jobs; the result (rank = labels.size())
-// goes to out[job][2^rank].
+// goes to out[job][2^rank].  With `trie` (per-trajectory parts; n_jobs ==
+// trie->reps->size(), job_traj the representatives on the device) launches run once
+// per group of jobs that agree on the sites absorbed so far.
 ptsbe_status_t run_part(Plan& p, const ptsbe::PartPlan& pp, const ptsbe::AbsorbStep* d_steps,
                         const ptsbe::GateCtx& g, int64_t n_jobs, const int32_t* job_traj, int32_t traj_base,
                         const uint64_t* job_prefix, const ptsbe::InitArgs& init, float2* out, Arena& ar,
-                        hipStream_t s) {
+                        hipStream_t s, const PartTrie* trie = nullptr) {
   if (n_jobs <= 0) return PTSBE_OK;
   const int out_rank = (int)pp.labels.size();
   if (pp.steps.empty()) {
@@ -152,6 +216,50 @@ ptsbe_status_t run_part(Plan& p, const ptsbe::PartPlan& pp, const ptsbe::AbsorbS
   float2* b0 = (float2*)ar.take((size_t)n_jobs * ((size_t)8 << pp.peak));
   float2* b1 = (float2*)ar.take((size_t)n_jobs * ((size_t)8 << pp.peak));
   if (!b0 || !b1) return fail(PTSBE_ERR_OUT_OF_MEMORY, "workspace too small for a sweep");
+  // subtree reuse: the current level's jobs (first job of each group), their
+  // trajectories on the device, and each job's group
+  int64_t cur_n = n_jobs;
+  const int32_t* cur_traj = job_traj;
+  std::vector<int32_t> lv_first, lv_pos;
+  auto upload = [&](std::vector<int32_t>&& v, int32_t** d) -> ptsbe_status_t {
+    *d = (int32_t*)ar.take(std::max<size_t>(v.size(), 1) * 4);
+    if (!*d) return fail(PTSBE_ERR_OUT_OF_MEMORY, "workspace too small (subtree reuse tables)");
+    trie->keep->push_back(std::move(v));
+    HIP_TRY(hipMemcpyAsync(*d, trie->keep->back().data(), trie->keep->back().size() * 4, hipMemcpyHostToDevice, s));
+    return PTSBE_OK;
+  };
+  // the jobs of the level ending after step `end`; returns the device gather index
+  // from the previous level (null when the job set does not grow)
+  std::vector<char> lv_done(trie ? p.site_gate.size() : 0, 0);
+  int lv_end = 0;
+  auto enter_level = [&](int end, int32_t** d_gather) -> ptsbe_status_t {
+    *d_gather = nullptr;
+    if (!trie) return PTSBE_OK;
+    std::vector<int32_t> first, pos;
+    trie_level(p, pp, *trie, lv_end, end, lv_done, lv_pos, first, pos);
+    lv_end = end;
+    if ((int64_t)first.size() == cur_n && !lv_first.empty()) {
+      lv_pos = std::move(pos);      // the same partition (group order may differ: keep the list)
+      return PTSBE_OK;
+    }
+    std::vector<int32_t> gidx(first.size()), trajs(first.size());
+    for (size_t k = 0; k < first.size(); ++k) {
+      gidx[k] = lv_first.empty() ? 0 : lv_pos[(size_t)first[k]];
+      trajs[k] = (*trie->reps)[(size_t)first[k]];
+    }
+    int32_t* dt = nullptr;
+    ptsbe_status_t st = upload(std::move(trajs), &dt);
+    if (st != PTSBE_OK) return st;
+    if (!lv_first.empty()) {
+      st = upload(std::move(gidx), d_gather);
+      if (st != PTSBE_OK) return st;
+    }
+    cur_n = (int64_t)first.size();
+    cur_traj = dt;
+    lv_first = std::move(first);
+    lv_pos = std::move(pos);
+    return PTSBE_OK;
+  };
   // the leading segments whose tensors all fit 2^kVmMaxRank entries run as one
   // LDS sweep (one launch) instead of one launch per step
   const size_t nseg = pp.segs.size();
@@ -169,24 +277,42 @@ ptsbe_status_t run_part(Plan& p, const ptsbe::PartPlan& pp, const ptsbe::AbsorbS
   }
   if (h < 2) s0 = 0;
   // the last rank-changing step writes the output; in-place runs after it work on
-  // the output directly (no final copy)
+  // the output directly (no final copy; with subtree reuse the job set may still
+  // grow, so the output is written by a final copy)
   size_t last_nf = nseg;
   for (size_t si = s0; si < nseg; ++si)
     if (!pp.segs[si].fused) last_nf = si;
+  if (trie) last_nf = nseg + 1;
   float2* A = last_nf == nseg ? out : b0;
+  int32_t* d_gather = nullptr;
+  {
+    const ptsbe_status_t st = enter_level(h >= 2 ? h : 0, &d_gather);
+    if (st != PTSBE_OK) return st;
+  }
   if (h >= 2) {
-    const ptsbe_status_t st = timed_part_vm(p, pp, d_steps, h, hpeak, g, n_jobs, job_traj, traj_base, job_prefix,
+    const ptsbe_status_t st = timed_part_vm(p, pp, d_steps, h, hpeak, g, cur_n, cur_traj, traj_base, job_prefix,
                                             init, A, pp.steps[(size_t)h - 1].rC, s);
     if (st != PTSBE_OK) return st;
   } else {
-    if (init.Vprev) HIP_TRY(ptsbe::launch_init_gather(init, n_jobs, job_prefix, p.NW, A, s));
-    else HIP_TRY(ptsbe::launch_fill_one(A, n_jobs, s));   // rank-0 start: the scalar 1 per job
+    if (init.Vprev) HIP_TRY(ptsbe::launch_init_gather(init, cur_n, job_prefix, p.NW, A, s));
+    else HIP_TRY(ptsbe::launch_fill_one(A, cur_n, s));   // rank-0 start: the scalar 1 per job
   }
+  int cur_rank = h >= 2 ? pp.steps[(size_t)h - 1].rC : (init.Vprev ? init.r0 : 0);
   for (size_t si = s0; si < nseg; ++si) {
     const ptsbe::Segment& sg = pp.segs[si];
+    if (trie) {
+      // the jobs of this launch: groups that agree on every site absorbed by its end
+      const ptsbe_status_t st = enter_level(sg.first + sg.count, &d_gather);
+      if (st != PTSBE_OK) return st;
+      if (d_gather) {
+        float2* D = A == b0 ? b1 : b0;
+        HIP_TRY(ptsbe::launch_gather_rows(A, d_gather, D, cur_n, cur_rank, s));
+        A = D;
+      }
+    }
     if (sg.fused) {   // a run of in-place steps, one tile pass, in place
-      HIP_TRY(ptsbe::launch_fused(sg, p.d_fused, g, n_jobs, job_traj, traj_base, job_prefix, p.NW, A, s));
-      if (p.profile) p.fused_bytes += (double)n_jobs * 16.0 * std::ldexp(1.0, sg.r);
+      HIP_TRY(ptsbe::launch_fused(sg, p.d_fused, g, cur_n, cur_traj, traj_base, job_prefix, p.NW, A, s));
+      if (p.profile) p.fused_bytes += (double)cur_n * 16.0 * std::ldexp(1.0, sg.r);
       continue;
     }
     const size_t i = (size_t)sg.first;
@@ -197,7 +323,7 @@ ptsbe_status_t run_part(Plan& p, const ptsbe::PartPlan& pp, const ptsbe::AbsorbS
       HIP_TRY(hipEventCreate(&ev.second));
       HIP_TRY(hipEventRecord(ev.first, s));
     }
-    HIP_TRY(ptsbe::launch_absorb_global(pp.steps[i], d_steps + i, g, n_jobs, job_traj, traj_base, job_prefix,
+    HIP_TRY(ptsbe::launch_absorb_global(pp.steps[i], d_steps + i, g, cur_n, cur_traj, traj_base, job_prefix,
                                         p.NW, A, C, s));
     if (p.profile >= 2) {
       HIP_TRY(hipEventRecord(ev.second, s));
@@ -205,9 +331,11 @@ ptsbe_status_t run_part(Plan& p, const ptsbe::PartPlan& pp, const ptsbe::AbsorbS
       ++p.sweep_launches;
     }
     A = C;
-    if (p.profile) p.sweep_bytes += (double)n_jobs * 8.0 *
+    cur_rank = pp.steps[i].rC;
+    if (p.profile) p.sweep_bytes += (double)cur_n * 8.0 *
                                     (std::ldexp(1.0, pp.steps[i].rA) + std::ldexp(1.0, pp.steps[i].rC));
   }
+  if (cur_n != n_jobs) return fail(PTSBE_ERR_DEVICE, "subtree reuse: the last level does not hold every job");
   if (A != out) HIP_TRY(ptsbe::launch_copy(A, out, n_jobs << out_rank, s));
   ar.used = mark;
   return PTSBE_OK;
@@ -363,6 +491,7 @@ ptsbe_status_t run_batch(Plan& p, int j, const uint8_t* d_kraus, const float2* m
       if (!k.empty()) (void)hipStreamSynchronize(s);
     }
   } sync_on_exit{s, keep};
+  std::vector<int32_t> trie_reps;                 // representatives of the chunk's right jobs (host)
   for (int64_t t0 = 0; t0 < E; t0 += t_cap) {
     const int64_t t1 = std::min<int64_t>(E, t0 + t_cap);
     const int64_t e0 = first[t0], e1 = first[t1];
@@ -398,8 +527,21 @@ ptsbe_status_t run_batch(Plan& p, int j, const uint8_t* d_kraus, const float2* m
     }
     float2* T = (float2*)ar.take((size_t)n_rt * ((size_t)8 << rT));
     if (!T) return fail(PTSBE_ERR_OUT_OF_MEMORY, "workspace too small (right part)");
+    PartTrie trie;
+    if (p.subtree_reuse && io.h_kraus && n_rt > 1 && !part_uses_vm(bp.right)) {
+      trie.h_kraus = io.h_kraus;
+      trie.S = S;
+      trie.keep = &keep;
+      trie_reps.clear();
+      if (d_rjob) {
+        trie_reps = keep[keep.size() - 2];                       // the representatives uploaded above
+      } else {
+        for (int64_t t = t0; t < t1; ++t) trie_reps.push_back((int32_t)t);
+      }
+      trie.reps = &trie_reps;
+    }
     ptsbe_status_t st = run_part(p, bp.right, d_right, g, n_rt, d_rjob, (int32_t)t0, nullptr,
-                                 ptsbe::InitArgs(), T, ar, s);
+                                 ptsbe::InitArgs(), T, ar, s, trie.reps ? &trie : nullptr);
     if (st != PTSBE_OK) return st;
     // last batch with at most two elements per trajectory: a GEMV on T's own layout
     // (T read once per element) beats the canonical copy plus the MFMA join
@@ -557,6 +699,9 @@ ptsbe_status_t collect_events(Plan& p, std::vector<EventPair>& evs) {
 extern "C" {
 
 const char* ptsbe_last_error(void) { return ptsbe::g_last_error.c_str(); }
+
+// Elements per trajectory and batch assumed by the automatic method choice.
+constexpr double kAutoElems = 64.0;
 
 ptsbe_status_t ptsbe_plan(const ptsbe_circuit_t* c, const ptsbe_plan_opts_t* o, ptsbe_plan_t* out) {
   if (!c || !o || !out) return fail(PTSBE_ERR_INVALID_ARG, "null argument");
@@ -723,6 +868,9 @@ ptsbe_status_t ptsbe_plan(const ptsbe_circuit_t* c, const ptsbe_plan_opts_t* o, 
   // light cone of doubled networks: which gates are unitary for every trajectory
   if (o->light_cone != 0 && o->light_cone != 1) return fail(PTSBE_ERR_INVALID_ARG, "light_cone must be 0 or 1");
   p->light_cone = o->light_cone == 1;
+  if (o->subtree_reuse != 0 && o->subtree_reuse != 1)
+    return fail(PTSBE_ERR_INVALID_ARG, "subtree_reuse must be 0 or 1");
+  p->subtree_reuse = o->subtree_reuse == 1;
   p->gate_unitary.assign((size_t)p->G, 1);
   for (int g = 0; g < p->G; ++g) {
     const int d = 1 << p->arity[(size_t)g];
@@ -781,14 +929,22 @@ ptsbe_status_t ptsbe_plan(const ptsbe_circuit_t* c, const ptsbe_plan_opts_t* o, 
       if (o->method == PTSBE_METHOD_NETWORK || !sv_fits) return fail(PTSBE_ERR_UNSUPPORTED, err);
       use_sv = true;
     } else if (o->method == PTSBE_METHOD_AUTO && sv_fits) {
-      // both methods run: the one that moves fewer bytes per trajectory (the
-      // network method's per-trajectory parts against the statevector's window
-      // passes and marginal reads; per-element work is not counted)
-      double net_bytes = 0.0;
-      for (const auto& bp : p->batches) net_bytes += bp.right.bytes;
-      const double sv_bytes = (16.0 * ptsbe::count_sv_windows(*p, ptsbe::kFuseMax) + 8.0 * p->batch_sizes.size()) *
-                              std::ldexp(1.0, p->n);
-      use_sv = sv_bytes < net_bytes;
+      // both methods run: a cost per trajectory in HBM-byte equivalents.  The
+      // network method pays its per-trajectory parts plus, per element, the left
+      // part and the join, counted for kAutoElems elements per batch (the shot
+      // count is not known here) at 25 flops per byte on MFMA joins and 0.5 on
+      // the generic join (measured on the ragged mix: generic joins of crossing
+      // 7..10 ran near 1 TFLOP/s); the statevector method pays its window passes
+      // and marginal reads.
+      double net = 0.0;
+      for (const auto& bp : p->batches) {
+        const int lkb = (int)bp.lk.size();
+        const bool mfma = bp.doubled ? ptsbe::qform_supported(lkb) : ptsbe::ketjoin_supported(lkb);
+        net += bp.right.bytes + kAutoElems * (bp.left.flops / 25.0 + bp.join_flops_per_elem / (mfma ? 25.0 : 0.5));
+      }
+      const double sv = (16.0 * ptsbe::count_sv_windows(*p, ptsbe::kFuseMax) + 8.0 * p->batch_sizes.size()) *
+                        std::ldexp(1.0, p->n);
+      use_sv = sv < net;
     }
   }
   if (use_sv) {
@@ -997,6 +1153,7 @@ ptsbe_status_t ptsbe_plan_query(ptsbe_plan_t plan, ptsbe_plan_info_t* out) {
     }
   out->precision = p->precision;
   out->light_cone = p->light_cone ? 1 : 0;
+  out->subtree_reuse = p->subtree_reuse ? 1 : 0;
   return PTSBE_OK;
 }
 

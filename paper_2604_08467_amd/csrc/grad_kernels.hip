@@ -110,7 +110,24 @@ __global__ void value_sum_kernel(const double* __restrict__ vals, const double* 
   if (threadIdx.x == 0) *out = red[0];
 }
 
+// dst[j] = src[idx[j]] for rows of `len` entries (len a power of two, 2^lb).
+__global__ void gather_rows_kernel(const float2* __restrict__ src, const int32_t* __restrict__ idx,
+                                   float2* __restrict__ dst, int64_t total, int lb) {
+  const int64_t len = (int64_t)1 << lb;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = src[(int64_t)idx[i >> lb] * len + (i & (len - 1))];
+}
+
 }  // namespace
+
+hipError_t launch_gather_rows(const float2* src, const int32_t* idx, float2* dst, int64_t n_rows, int row_bits,
+                              hipStream_t stream) {
+  const int64_t total = n_rows << row_bits;
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(gather_rows_kernel, dim3(grid_blocks((total + 255) / 256)), dim3(256), 0, stream, src, idx, dst,
+                     total, row_bits);
+  return hipGetLastError();
+}
 
 hipError_t launch_grad_gates(const GradGateArgs& a, hipStream_t stream) {
   const int64_t n = a.E * a.g.G;

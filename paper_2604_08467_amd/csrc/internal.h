@@ -312,6 +312,9 @@ struct Plan {
   // operator its sites may insert are unitary (to kUnitaryTol)
   bool light_cone = false;
   std::vector<char> gate_unitary;
+  // subtree reuse in the per-trajectory parts (launches shared by jobs that agree
+  // on the sites absorbed so far)
+  bool subtree_reuse = false;
 
   // measurement
   int profile = 0;                                // 1: time the MFMA join; 2: also single HBM sweep steps
@@ -590,6 +593,9 @@ hipError_t launch_sv_window(const SvWin& w, const SvOp* d_ops, const float2* mer
 // LDS bytes the window kernel needs for a window (0 if it cannot take it).
 size_t sv_window_lds_bytes(const SvWin& w);
 hipError_t launch_copy(const float2* src, float2* dst, int64_t n, hipStream_t stream);
+// dst row j (2^row_bits entries) = src row idx[j], for n_rows rows.
+hipError_t launch_gather_rows(const float2* src, const int32_t* idx, float2* dst, int64_t n_rows, int row_bits,
+                              hipStream_t stream);
 hipError_t launch_value_sum(const double* vals, const double* w, int64_t E, double* out, hipStream_t stream);
 
 // ---------------------------------------------------------- statevector method

@@ -145,8 +145,10 @@ def test_untouched_qubit_gets_identity():
 
 def test_method_selection():
     """auto: statevector for n <= 20, when the network sweep does not fit, or when
-    (n <= 30) its window passes move fewer bytes per trajectory than the network
-    method's per-trajectory parts; network otherwise.  Forced methods fail with
+    (n <= 30) its window passes cost less per trajectory than the network
+    method's per-trajectory parts plus 64 elements per batch of left parts and
+    joins (flops at 25 per byte on MFMA joins, 0.5 per byte otherwise); network
+    otherwise.  Forced methods fail with
     UNSUPPORTED where they cannot run."""
     P = _lib()
     wl1, wl2, wl3 = W.chain10_d8(), W.brickwork50_d6(), W.grid5x5_d8((10, 10, 5))
@@ -178,7 +180,12 @@ def test_method_selection():
         sv_bytes = (16.0 * sv.sv_windows + 8.0 * 3) * 2.0 ** n
         try:
             net = P.Plan(c, bs, device=-1, method="network")
-            net_bytes = sum(net.batch_info(j)["bytes_per_traj"] for j in range(3))
+            net_bytes = 0.0
+            for j in range(3):
+                bi = net.batch_info(j)
+                left = bi["flops_per_elem"] - bi["join_flops_per_elem"]
+                mfma = bi["crossing"] in ((4, 5) if bi["doubled"] else (2, 3, 4, 5, 6))
+                net_bytes += bi["bytes_per_traj"] + 64 * (left / 25 + bi["join_flops_per_elem"] / (25 if mfma else 0.5))
         except P.PtsbeError:
             net_bytes = float("inf")          # no feasible sweep
         want = "statevector" if sv_bytes < net_bytes else "network"
