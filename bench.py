@@ -278,16 +278,19 @@ def main():
     if os.path.exists(args.traffic_file):
         # "bytes_per_launch: N" written from two rocprofv3 counter runs of this command;
         # used only when its "kernel:" line names the join kernel as it is now
+        # and the batch list it was measured on is this run's
         kv = dict(ln.split(":", 1) for ln in open(args.traffic_file) if ":" in ln and not ln.startswith("#"))
-        if kv.get("kernel", "").strip() == JOIN_KERNEL_TAG and "bytes_per_launch" in kv:
+        if (kv.get("kernel", "").strip() == JOIN_KERNEL_TAG and "bytes_per_launch" in kv
+                and kv.get("batches", "").strip() == str(bs)):
             traffic = float(kv["bytes_per_launch"])
     peak = FP32_MFMA_PEAK_TFLOPS if args.precision == "c64" else BF16_MFMA_PEAK_TFLOPS   # fp16 dense = bf16 dense
     roofline = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                 "frac": achieved / peak, "traffic": traffic if args.precision == "c64" else None,
-                "kernel": "qform_mfma_kernel<32,8> (doubled-network join as a real GEMM over K^2 folded slots, "
-                          "FP32 MFMA)" if args.precision == "c64"
-                          else f"qform_split_kernel<32,8> (doubled-network join as the K^2-slot GEMM, {args.precision} "
-                               "hi+lo operands, three products on 16-bit MFMA, FP32 accumulate)",
+                "kernel": "qform_mfma_kernel<32,NC> (doubled-network join as a real GEMM over K^2 folded slots, "
+                          "FP32 MFMA; NC = 16-column x groups per workgroup, 8 for b = 10, 1..2 for b = 5)"
+                          if args.precision == "c64"
+                          else f"qform_split_kernel<32,NC> (doubled-network join as the K^2-slot GEMM, "
+                               f"{args.precision} hi+lo operands, three products on 16-bit MFMA, FP32 accumulate)",
                 "flops": "real bilinear form over K^2 folded slots: 2K^2 per row and x (K=32: 2048; "
                          "the plain complex product would be 8320)",
                 "launches": prof["join_launches"], "kernel_ms_per_step": prof["join_ms"] / args.steps}

@@ -107,6 +107,72 @@ __device__ inline void absorb_multi(const AbsorbStep& st, int sbase, const uint3
 }
 
 // ------------------------------------------------------------------ LDS sweep
+// One absorb step over the (job, kept index) items of a workgroup's jobs, for a
+// step with NK contracted and NN new legs (NK + NN <= 4: a gate tensor has at
+// most four legs).  The step's tables are read once into registers before the
+// item loop, and each item issues all of its LDS reads (2^NK entries of A,
+// 2^(NK+NN) gate entries) before its first product, so that a step costs one
+// round of scalar loads and one round of LDS latency instead of one per product.
+// Products are accumulated in the order of absorb_one (k ascending from zero),
+// so the results are the same bit for bit.
+template <int NK, int NN>
+__device__ __forceinline__ void vm_step(const AbsorbStep& st, int nj, int lnm, int buf_elems, const float2* bufA,
+                                        float2* bufC, const float2* G, const uint64_t* pw, int NW) {
+  constexpr int nk = 1 << NK, nn = 1 << NN;
+  int kpos[NK > 0 ? NK : 1], npos[NN > 0 ? NN : 1], hm[4], hw[4], sq[kMaxSlices], sw[kMaxSlices];
+  uint32_t koff[nk], noff[nn];
+  int kB[nk], nB[nn];
+#pragma unroll
+  for (int i = 0; i < NK; ++i) kpos[i] = st.kpos[i];
+#pragma unroll
+  for (int i = 0; i < NN; ++i) npos[i] = st.npos[i];
+#pragma unroll
+  for (int k = 0; k < nk; ++k) { koff[k] = st.koff[k]; kB[k] = st.kB[k]; }
+#pragma unroll
+  for (int n = 0; n < nn; ++n) { noff[n] = st.noff[n]; nB[n] = st.nB[n]; }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) { hm[i] = st.hm[i]; hw[i] = st.hw[i]; }
+#pragma unroll
+  for (int i = 0; i < kMaxSlices; ++i) { sq[i] = st.sq[i]; sw[i] = st.sw[i]; }
+  const int nH = st.nH, nS = st.nS;
+  const uint32_t mmask = (1u << lnm) - 1u;
+  const int items = nj << lnm;
+  for (int i = threadIdx.x; i < items; i += blockDim.x) {
+    const int j = i >> lnm;
+    const uint32_t m = (uint32_t)i & mmask;
+    const uint64_t* pj = pw + j * NW;
+    int hidx = 0;
+#pragma unroll
+    for (int t = 0; t < kMaxSlices; ++t)
+      if (t < nS) hidx += (int)bit_of_prefix(pj, sq[t]) * sw[t];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+      if (t < nH) hidx += (int)((m >> hm[t]) & 1u) * hw[t];
+    uint32_t abase = m, cbase = m;
+#pragma unroll
+    for (int t = 0; t < NK; ++t) abase = ((abase >> kpos[t]) << (kpos[t] + 1)) | (abase & ((1u << kpos[t]) - 1u));
+#pragma unroll
+    for (int t = 0; t < NN; ++t) cbase = ((cbase >> npos[t]) << (npos[t] + 1)) | (cbase & ((1u << npos[t]) - 1u));
+    const float2* Aj = bufA + (size_t)j * buf_elems;
+    const float2* Gj = G + 16 * j + hidx;
+    float2 a[nk], gv[nn][nk];
+#pragma unroll
+    for (int k = 0; k < nk; ++k) a[k] = Aj[abase + koff[k]];
+#pragma unroll
+    for (int n = 0; n < nn; ++n)
+#pragma unroll
+      for (int k = 0; k < nk; ++k) gv[n][k] = Gj[nB[n] + kB[k]];
+    float2* Cj = bufC + (size_t)j * buf_elems + cbase;
+#pragma unroll
+    for (int n = 0; n < nn; ++n) {
+      float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+      for (int k = 0; k < nk; ++k) acc = cfma(a[k], gv[n][k], acc);
+      Cj[noff[n]] = acc;
+    }
+  }
+}
+
 __device__ inline uint32_t init_offset(const InitArgs& in, uint32_t m, const uint64_t* pw) {
   for (int i = 0; i < in.nsl; ++i) {
     const int p = in.pos[i];
@@ -160,12 +226,24 @@ __global__ void __launch_bounds__(256) part_vm_kernel(const AbsorbStep* __restri
       if (gl && s + 1 < n_steps) gnext = gate_entry(g, steps[s + 1].gate, traj, steps[s + 1].conj, gi);
       __syncthreads();     // gates visible; previous step's C complete
       const int lnm = st.rC - st.nN;
-      const int items = nj << lnm;
-      for (int i = tid; i < items; i += nt) {
-        const int j = i >> lnm;
-        const uint32_t m = (uint32_t)i & ((1u << lnm) - 1u);
-        absorb_one(st, slice_base(st, pw + j * NW), m, bufA + (size_t)j * buf_elems, bufC + (size_t)j * buf_elems,
-                   G + 16 * j);
+      switch (st.nK * 8 + st.nN) {    // uniform: every thread takes the same case
+#define VM_CASE(K, N) \
+        case K * 8 + N: vm_step<K, N>(st, nj, lnm, buf_elems, bufA, bufC, G, pw, NW); break;
+        VM_CASE(0, 0) VM_CASE(0, 1) VM_CASE(0, 2) VM_CASE(0, 3) VM_CASE(0, 4)
+        VM_CASE(1, 0) VM_CASE(1, 1) VM_CASE(1, 2) VM_CASE(1, 3)
+        VM_CASE(2, 0) VM_CASE(2, 1) VM_CASE(2, 2)
+        VM_CASE(3, 0) VM_CASE(3, 1)
+        VM_CASE(4, 0)
+#undef VM_CASE
+        default: {
+          const int items = nj << lnm;
+          for (int i = tid; i < items; i += nt) {
+            const int j = i >> lnm;
+            const uint32_t m = (uint32_t)i & ((1u << lnm) - 1u);
+            absorb_one(st, slice_base(st, pw + j * NW), m, bufA + (size_t)j * buf_elems,
+                       bufC + (size_t)j * buf_elems, G + 16 * j);
+          }
+        }
       }
       float2* t = bufA; bufA = bufC; bufC = t;
     }
