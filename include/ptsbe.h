@@ -164,6 +164,14 @@ typedef struct {
                                    on gates every member shares).  Parts swept
                                    whole in LDS are not split.  0: off; other
                                    values: INVALID_ARG                           */
+  int32_t sample_kernel;        /* 0: automatic: batches of at most 5 qubits with
+                                   at most 4 shots per element on average sample
+                                   and split their elements one lane per element
+                                   (elements with more shots: one wavefront each);
+                                   1: one wavefront per element always.  Both give
+                                   the same shots bit for bit (the lane kernels
+                                   repeat the wavefront's FP64 operations in the
+                                   same order); other values: INVALID_ARG        */
 } ptsbe_plan_opts_t;
 
 typedef struct {

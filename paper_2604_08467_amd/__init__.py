@@ -110,13 +110,18 @@ class GradSpec:
 # contraction method of a plan: the sweep over each batch's network, or the
 # statevector of each trajectory (n <= 30); "auto" lets the planner choose
 METHODS = {"auto": 0, "network": 1, "statevector": 2}
+# sampling and element-splitting kernels: "auto" takes one lane per element for
+# batches of <= 5 qubits with few shots per element, "wavefront" one wavefront
+# per element always (the same shots bit for bit)
+SAMPLE_KERNELS = {"auto": 0, "wavefront": 1}
 
 
 class Plan:
     """ptsbe_plan: the unified contraction path of every batch (host, once)."""
 
     def __init__(self, circuit, batch_sizes, hypersamples=4, path_seed=0, device=0, precision=0,
-                 device_budget_bytes=0, method="auto", light_cone=False, subtree_reuse=False):
+                 device_budget_bytes=0, method="auto", light_cone=False, subtree_reuse=False,
+                 sample_kernel="auto"):
         self._lib = _lib.load()
         self.n_qubits = circuit.n_qubits
         self.n_sites = len(circuit.site_gate)
@@ -125,9 +130,11 @@ class Plan:
         bs = np.array(self.batch_sizes, dtype=np.int32)
         if method not in METHODS:
             raise ValueError(f"method must be one of {sorted(METHODS)}")
+        if sample_kernel not in SAMPLE_KERNELS:
+            raise ValueError(f"sample_kernel must be one of {sorted(SAMPLE_KERNELS)}")
         opts = _lib.PlanOpts_t(len(bs), _ptr(bs, C.c_int32), int(hypersamples), int(path_seed), int(precision),
                                int(device), int(device_budget_bytes), METHODS[method], int(light_cone),
-                               int(subtree_reuse))
+                               int(subtree_reuse), SAMPLE_KERNELS[sample_kernel])
         h = C.c_void_p()
         _lib.check(self._lib.ptsbe_plan(C.byref(arrs.struct), C.byref(opts), C.byref(h)))
         self._h = h

@@ -48,7 +48,7 @@ class PlanOpts_t(C.Structure):
         ("n_batches", C.c_int32), ("batch_sizes", C.POINTER(C.c_int32)), ("hypersamples", C.c_int32),
         ("path_seed", C.c_uint64), ("precision", C.c_int32), ("device", C.c_int32),
         ("device_budget_bytes", C.c_size_t), ("method", C.c_int32), ("light_cone", C.c_int32),
-        ("subtree_reuse", C.c_int32),
+        ("subtree_reuse", C.c_int32), ("sample_kernel", C.c_int32),
     ]
 
 

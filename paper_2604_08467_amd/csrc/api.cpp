@@ -871,6 +871,9 @@ ptsbe_status_t ptsbe_plan(const ptsbe_circuit_t* c, const ptsbe_plan_opts_t* o, 
   if (o->subtree_reuse != 0 && o->subtree_reuse != 1)
     return fail(PTSBE_ERR_INVALID_ARG, "subtree_reuse must be 0 or 1");
   p->subtree_reuse = o->subtree_reuse == 1;
+  if (o->sample_kernel != 0 && o->sample_kernel != 1)
+    return fail(PTSBE_ERR_INVALID_ARG, "sample_kernel must be 0 or 1");
+  p->sample_kernel = o->sample_kernel;
   p->gate_unitary.assign((size_t)p->G, 1);
   for (int g = 0; g < p->G; ++g) {
     const int d = 1 << p->arity[(size_t)g];
@@ -1606,6 +1609,9 @@ ptsbe_status_t ptsbe_sample_shots(ptsbe_plan_t plan, const uint8_t* d_kraus_idx,
     sa.elem_total = totals;
     sa.child_cnt = (j + 1 < f) ? child_cnt : nullptr;
     sa.bad_flag = counters + 1;
+    // few shots per element (later batches): one lane per element
+    const int lane_path = p->sample_kernel == 0 && bp.size <= 5 && M <= 4 * U ? 1 : 0;
+    sa.lane_path = lane_path;
     ptsbe_status_t st = run_batch(*p, j, d_kraus_idx, merged, E, io, ar, s, evs);
     if (st != PTSBE_OK) return st;
     if (j == 0) {
@@ -1627,6 +1633,7 @@ ptsbe_status_t ptsbe_sample_shots(ptsbe_plan_t plan, const uint8_t* d_kraus_idx,
       ca.out_traj = el[1 - cur].traj; ca.out_prefix = el[1 - cur].prefix;
       ca.out_shot_off = el[1 - cur].off; ca.out_shot_cnt = el[1 - cur].cnt; ca.out_shot_ids = el[1 - cur].ids;
       ca.out_parent = el[1 - cur].parent;
+      ca.lane_path = lane_path;
       HIP_TRY(ptsbe::launch_children(ca, s));
       cur = 1 - cur;
       U = nU;

@@ -315,6 +315,7 @@ struct Plan {
   // subtree reuse in the per-trajectory parts (launches shared by jobs that agree
   // on the sites absorbed so far)
   bool subtree_reuse = false;
+  int sample_kernel = 0;               // 0: automatic lane-per-element sampling, 1: wavefront per element
 
   // measurement
   int profile = 0;                                // 1: time the MFMA join; 2: also single HBM sweep steps
@@ -491,6 +492,7 @@ struct SampleArgs {
   int32_t* bad_flag;                     // set to 1 on a zero / non-finite total
   uint32_t tag = 2u;                     // Philox stream: 2 shot draws, 3 non-proportional draws
   double* p_cond = nullptr;              // [rows] P(x | prefix) of each draw (direct final batch), or null
+  int lane_path = 0;                     // b <= 5 and about one shot per element: one lane per element
 };
 hipError_t launch_sample(const SampleArgs& a, hipStream_t stream);
 
@@ -541,6 +543,7 @@ struct ChildArgs {
   const int32_t* child_off;
   int32_t* out_traj; uint64_t* out_prefix; int32_t* out_shot_off; int32_t* out_shot_cnt;
   int32_t* out_shot_ids;
+  int lane_path = 0;                     // b <= 5 and about one shot per element: one lane per element
 };
 hipError_t launch_children(const ChildArgs& a, hipStream_t stream);
 

@@ -182,8 +182,11 @@ __device__ inline uint32_t init_offset(const InitArgs& in, uint32_t m, const uin
   return m;
 }
 
+// gate entries staged per chunk of steps: [chunk steps][J][16] float2
+constexpr int kVmGateEntries = 1536;
+
 __global__ void __launch_bounds__(256) part_vm_kernel(const AbsorbStep* __restrict__ steps, int n_steps,
-                                                      int buf_elems, int J, GateCtx g, int64_t n_jobs,
+                                                      int buf_elems, int J, int chunk, GateCtx g, int64_t n_jobs,
                                                       const int32_t* __restrict__ job_traj, int32_t traj_base,
                                                       const uint64_t* __restrict__ job_prefix, int NW,
                                                       InitArgs init, float2* __restrict__ out, int out_rank) {
@@ -193,8 +196,8 @@ __global__ void __launch_bounds__(256) part_vm_kernel(const AbsorbStep* __restri
   extern __shared__ float2 lds[];
   float2* bufA = lds;                                   // [J][buf_elems]
   float2* bufC = lds + (size_t)J * buf_elems;           // [J][buf_elems]
-  float2* Gm = lds + 2 * (size_t)J * buf_elems;         // [2][J][16] gates of the step, double-buffered
-  uint64_t* pw = reinterpret_cast<uint64_t*>(Gm + 32 * J);   // [J][NW] prefixes
+  float2* Gm = lds + 2 * (size_t)J * buf_elems;         // [chunk][J][16] gates of a chunk of steps
+  uint64_t* pw = reinterpret_cast<uint64_t*>(Gm + (size_t)16 * J * chunk);   // [J][NW] prefixes
   const int tid = threadIdx.x, nt = blockDim.x;
   const int gj = tid >> 4, gi = tid & 15;               // the gate entry this thread loads (gj < J)
   const int64_t n_groups = (n_jobs + J - 1) / J;
@@ -214,16 +217,35 @@ __global__ void __launch_bounds__(256) part_vm_kernel(const AbsorbStep* __restri
     } else {
       for (int j = tid; j < nj; j += nt) bufA[(size_t)j * buf_elems] = make_float2(1.f, 0.f);
     }
-    // the gate of the next step is loaded while the current step computes
+    // the gates of a chunk of steps are staged in LDS at once: eight loads per
+    // thread in flight together (unconditional, from a valid trajectory, so that
+    // no load result is copied or waited for before the group's stores), the bra
+    // conjugation applied at the store
     const bool gl = gj < nj;
     const int traj = gl ? (job_traj ? job_traj[job0 + gj] : traj_base + (int)(job0 + gj)) : 0;
-    float2 gnext = make_float2(0.f, 0.f);
-    if (gl && n_steps > 0) gnext = gate_entry(g, steps[0].gate, traj, steps[0].conj, gi);
+    const float2* graw = g.merged + (int64_t)traj * g.G * 16 + gi;
+    int cs = 0;
     for (int s = 0; s < n_steps; ++s) {
       const AbsorbStep& st = steps[s];
-      float2* G = Gm + 16 * J * (s & 1);
-      if (gl) G[tid] = gnext;
-      if (gl && s + 1 < n_steps) gnext = gate_entry(g, steps[s + 1].gate, traj, steps[s + 1].conj, gi);
+      if (s == cs + chunk || s == 0) {
+        cs = s;
+        const int ce = n_steps - cs < chunk ? n_steps : cs + chunk;
+        __syncthreads();   // every thread is done with the previous chunk's gates
+        for (int s1 = cs; s1 < ce; s1 += 8) {
+          float2 v[8];
+#pragma unroll
+          for (int k = 0; k < 8; ++k) v[k] = graw[16 * steps[s1 + k < ce ? s1 + k : ce - 1].gate];
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            if (gl && s1 + k < ce) {
+              float2 x = v[k];
+              if (steps[s1 + k].conj) x.y = -x.y;
+              Gm[(size_t)(s1 + k - cs) * 16 * J + tid] = x;
+            }
+          }
+        }
+      }
+      const float2* G = Gm + (size_t)(s - cs) * 16 * J;
       __syncthreads();     // gates visible; previous step's C complete
       const int lnm = st.rC - st.nN;
       switch (st.nK * 8 + st.nN) {    // uniform: every thread takes the same case
@@ -1199,15 +1221,15 @@ __device__ inline void chunk_of(int n, int lane, int& c0, int& c1) {
   if (c0 > n) c0 = n;
 }
 
-__global__ void __launch_bounds__(64) sample_kernel(SampleArgs a) {
-  extern __shared__ int hist[];           // [2^b] shot counts per x (child counts only)
-  __shared__ double cend[64], exc[64];
+// One element sampled by the whole wavefront (hist: [2^b] shot counts per x,
+// used for child counts; cend, exc: [64] per-lane chunk ends and starts).
+__device__ void sample_element_wave(const SampleArgs& a, int64_t e, int* hist, double* cend, double* exc) {
   const int n = 1 << a.b;
   const int lane = threadIdx.x;
   const int nl = n < 64 ? n : 64;         // lanes with a non-empty chunk
   int c0, c1;
   chunk_of(n, lane, c0, c1);
-  for (int64_t e = blockIdx.x; e < a.n_elems; e += gridDim.x) {
+  {
     const float* pi = a.pop + e * (int64_t)n;
     const int off = a.elem_shot_off[e];
     const int cnt = a.elem_shot_cnt[e];
@@ -1306,8 +1328,116 @@ __global__ void __launch_bounds__(64) sample_kernel(SampleArgs a) {
   }
 }
 
-__global__ void __launch_bounds__(64) children_kernel(ChildArgs a) {
-  extern __shared__ int ism[];
+__global__ void __launch_bounds__(64) sample_kernel(SampleArgs a) {
+  extern __shared__ int hist[];
+  __shared__ double cend[64], exc[64];
+  for (int64_t e = blockIdx.x; e < a.n_elems; e += gridDim.x) sample_element_wave(a, e, hist, cend, exc);
+}
+
+// Elements with few shots and b <= 5, one lane per element (64 elements per
+// wavefront): a lane recomputes, in registers, exactly the FP64 operations of
+// sample_element_wave for 2^B <= 32 values (one value per chunk: the same
+// Hillis-Steele partial sums in the same order, the same chunk ends, the same
+// binary search), so both give the same draws bit for bit; elements with more
+// than kLaneShots shots are taken by the whole wavefront afterwards.  This
+// turns a chain of dependent loads per element into one per 64 elements.
+constexpr int kLaneShots = 16;
+
+template <int B>
+__global__ void __launch_bounds__(64) sample_lanes_kernel(SampleArgs a) {
+  extern __shared__ int hist[];
+  __shared__ double cend_s[64], exc_s[64];
+  constexpr int n = 1 << B;
+  const int lane = threadIdx.x;
+  for (int64_t base = (int64_t)blockIdx.x * 64; base < a.n_elems; base += (int64_t)gridDim.x * 64) {
+    const int64_t e = base + lane;
+    const bool mine = e < a.n_elems;
+    const int cnt = mine ? a.elem_shot_cnt[e] : 0;
+    const bool small = mine && cnt <= kLaneShots;
+    if (small) {
+      const float* pi = a.pop + e * (int64_t)n;
+      float p[n];
+      if (n >= 4 && (reinterpret_cast<uintptr_t>(a.pop) & 15) == 0) {
+#pragma unroll
+        for (int k = 0; k < n / 4; ++k) {
+          const float4 v = reinterpret_cast<const float4*>(pi)[k];
+          p[4 * k] = v.x; p[4 * k + 1] = v.y; p[4 * k + 2] = v.z; p[4 * k + 3] = v.w;
+        }
+      } else {
+#pragma unroll
+        for (int k = 0; k < n; ++k) p[k] = pi[k];
+      }
+      double sv[n], incl[n], cend[n];
+      int last_pos = -1;
+#pragma unroll
+      for (int L = 0; L < n; ++L) {
+        sv[L] = 0.0 + (double)p[L];
+        incl[L] = sv[L];
+        if (p[L] > 0.f) last_pos = L;
+      }
+#pragma unroll
+      for (int d = 1; d < n; d <<= 1)
+#pragma unroll
+        for (int L = n - 1; L >= d; --L) incl[L] = incl[L] + incl[L - d];
+      cend[0] = 0.0 + sv[0];
+#pragma unroll
+      for (int L = 1; L < n; ++L) cend[L] = incl[L - 1] + sv[L];
+      const double Z = cend[n - 1];
+      a.elem_total[e] = Z;
+      if (!(Z >= 0.0) || !isfinite(Z)) atomicExch(a.bad_flag, 1);
+      uint32_t seen = 0u;
+      if (cnt > 0) {
+        const int traj = a.elem_traj[e];
+        const int64_t tbase = a.traj_shot_base[traj];
+        const int off = a.elem_shot_off[e];
+        for (int i = 0; i < cnt; ++i) {
+          const int row = a.shot_ids[off + i];
+          const uint32_t t = (uint32_t)(row - tbase);
+          const double u = philox_uniform(a.seed, a.tag, (uint32_t)traj, (uint32_t)a.j, t, 0u);
+          const double target = u * Z;
+          int lo = 0, hi = n;
+#pragma unroll
+          for (int it = 0; it <= B; ++it) {
+            if (lo < hi) {
+              const int mid = (lo + hi) >> 1;
+              double cm = cend[0];
+#pragma unroll
+              for (int L = 1; L < n; ++L) cm = mid == L ? cend[L] : cm;
+              if (cm > target) hi = mid; else lo = mid + 1;
+            }
+          }
+          int x = lo < n ? lo : last_pos;
+          if (x < 0) x = 0;
+          a.shot_x[row] = x;
+          if (a.p_cond) {
+            float px = p[0];
+#pragma unroll
+            for (int L = 1; L < n; ++L) px = x == L ? p[L] : px;
+            a.p_cond[row] = Z > 0.0 ? (double)px / Z : 0.0;
+          }
+          if (a.shots) {
+            uint64_t* w = a.shots + (int64_t)row * a.NW;
+            const int wi = a.start >> 6, sh = a.start & 63;
+            w[wi] |= (uint64_t)x << sh;
+            if (sh + B > 64) w[wi + 1] |= (uint64_t)x >> (64 - sh);
+          }
+          seen |= 1u << x;
+        }
+      }
+      if (a.child_cnt) a.child_cnt[e] = __popc(seen);
+    }
+    // elements with more shots: the whole wavefront, one element at a time
+    uint64_t big = __ballot(mine && !small);
+    while (big) {
+      const int l = __ffsll((unsigned long long)big) - 1;
+      big &= big - 1;
+      sample_element_wave(a, base + l, hist, cend_s, exc_s);
+    }
+  }
+}
+
+// The children of one element, by the whole wavefront (ism: 3 * 2^b ints).
+__device__ void children_element_wave(const ChildArgs& a, int64_t e, int* ism) {
   const int n = 1 << a.b;
   int* hist = ism;          // counts per x
   int* start = ism + n;     // exclusive scan of counts (then the scatter cursor)
@@ -1315,9 +1445,9 @@ __global__ void __launch_bounds__(64) children_kernel(ChildArgs a) {
   const int lane = threadIdx.x;
   int c0, c1;
   chunk_of(n, lane, c0, c1);
-  for (int64_t e = blockIdx.x; e < a.n_elems; e += gridDim.x) {
+  {
     const int off = a.elem_shot_off[e], cnt = a.elem_shot_cnt[e];
-    if (cnt <= 0) continue;               // uniform over the wavefront
+    if (cnt <= 0) return;                 // uniform over the wavefront
     const int traj = a.elem_traj[e];
     const int64_t cbase = a.child_off[e];
     const uint64_t* pp = a.elem_prefix + e * a.NW;
@@ -1336,7 +1466,7 @@ __global__ void __launch_bounds__(64) children_kernel(ChildArgs a) {
         if (sh + a.b > 64) op[wi + 1] |= (uint64_t)x >> (64 - sh);
         a.out_shot_ids[off] = row;
       }
-      continue;
+      return;
     }
     for (int x = c0; x < c1; ++x) hist[x] = 0;
     __syncthreads();
@@ -1377,6 +1507,77 @@ __global__ void __launch_bounds__(64) children_kernel(ChildArgs a) {
       a.out_shot_ids[off + pos] = row;
     }
     __syncthreads();   // LDS is reused by the next element
+  }
+}
+
+__global__ void __launch_bounds__(64) children_kernel(ChildArgs a) {
+  extern __shared__ int ism[];
+  for (int64_t e = blockIdx.x; e < a.n_elems; e += gridDim.x) children_element_wave(a, e, ism);
+}
+
+// Elements with at most kLaneChildShots shots and b <= 5, one lane per element:
+// the same children as children_element_wave (ascending x, each child's shots
+// contiguous from off + the number of the element's shots with smaller x), with
+// the shots of a child in their order within the element.
+constexpr int kLaneChildShots = 4;
+
+__global__ void __launch_bounds__(64) children_lanes_kernel(ChildArgs a) {
+  extern __shared__ int ism[];
+  const int lane = threadIdx.x;
+  constexpr int T = kLaneChildShots;
+  for (int64_t base = (int64_t)blockIdx.x * 64; base < a.n_elems; base += (int64_t)gridDim.x * 64) {
+    const int64_t e = base + lane;
+    const bool mine = e < a.n_elems;
+    const int cnt = mine ? a.elem_shot_cnt[e] : 0;
+    if (mine && cnt > 0 && cnt <= T) {
+      const int off = a.elem_shot_off[e];
+      const int traj = a.elem_traj[e];
+      const int64_t cbase = a.child_off[e];
+      const uint64_t* pp = a.elem_prefix + e * a.NW;
+      const int wi = a.start >> 6, sh = a.start & 63;
+      int r[T], x[T];
+      uint32_t mask = 0u;
+#pragma unroll
+      for (int i = 0; i < T; ++i) {
+        r[i] = 0; x[i] = 0;
+        if (i < cnt) {
+          r[i] = a.shot_ids[off + i];
+          x[i] = a.shot_x[r[i]];
+          mask |= 1u << x[i];
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < T; ++i) {
+        if (i >= cnt) break;
+        int less = 0, before = 0, same = 0;
+#pragma unroll
+        for (int k = 0; k < T; ++k) {
+          if (k < cnt) {
+            less += x[k] < x[i];
+            same += x[k] == x[i];
+            if (k < i) before += x[k] == x[i];
+          }
+        }
+        a.out_shot_ids[off + less + before] = r[i];
+        if (before == 0) {               // first shot of its child
+          const int64_t c = cbase + __popc(mask & ((1u << x[i]) - 1u));
+          a.out_traj[c] = traj;
+          a.out_parent[c] = (int32_t)e;
+          a.out_shot_off[c] = off + less;
+          a.out_shot_cnt[c] = same;
+          uint64_t* op = a.out_prefix + c * a.NW;
+          for (int w = 0; w < a.NW; ++w) op[w] = pp[w];
+          op[wi] |= (uint64_t)x[i] << sh;
+          if (sh + a.b > 64) op[wi + 1] |= (uint64_t)x[i] >> (64 - sh);
+        }
+      }
+    }
+    uint64_t big = __ballot(mine && cnt > T);
+    while (big) {
+      const int l = __ffsll((unsigned long long)big) - 1;
+      big &= big - 1;
+      children_element_wave(a, base + l, ism);
+    }
   }
 }
 
@@ -1524,11 +1725,27 @@ __global__ void scan_block_sums(const int32_t* in, int64_t n, int32_t* sums) {
   if (threadIdx.x == 0) sums[blockIdx.x] = red[0];
 }
 
-__global__ void scan_sums_serial(int32_t* sums, int64_t nb, int32_t* total) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  int32_t acc = 0;
-  for (int64_t i = 0; i < nb; ++i) { int32_t v = sums[i]; sums[i] = acc; acc += v; }
-  *total = acc;
+// Exclusive scan of the block sums in place, one workgroup: thread t takes a
+// contiguous run of the sums, the run totals are scanned in LDS (integers, so
+// the result does not depend on the order of the additions).
+__global__ void __launch_bounds__(1024) scan_sums_block(int32_t* sums, int64_t nb, int32_t* total) {
+  __shared__ int32_t part[1024];
+  const int t = threadIdx.x;
+  const int64_t per = (nb + 1023) / 1024;
+  const int64_t lo = t * per < nb ? t * per : nb, hi = lo + per < nb ? lo + per : nb;
+  int32_t own = 0;
+  for (int64_t i = lo; i < hi; ++i) own += sums[i];
+  part[t] = own;
+  __syncthreads();
+  for (int d = 1; d < 1024; d <<= 1) {
+    const int32_t v = t >= d ? part[t - d] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  int32_t acc = part[t] - own;
+  for (int64_t i = lo; i < hi; ++i) { const int32_t v = sums[i]; sums[i] = acc; acc += v; }
+  if (t == 1023) *total = part[1023];
 }
 
 __global__ void scan_apply(const int32_t* in, int64_t n, const int32_t* sums, int32_t* out) {
@@ -1636,9 +1853,11 @@ hipError_t launch_part_vm(const AbsorbStep* d_steps, int n_steps, int peak, Gate
   // one job per workgroup from 2^10 entries on
   const int J = buf <= 64 ? 16 : (buf >= 1024 ? 1 : 1024 / buf);
   const int threads = J > 1 ? 256 : (buf / 2 < 64 ? 64 : (buf / 2 > 256 ? 256 : buf / 2));
-  const size_t shmem = (size_t)(2 * J * buf + 32 * J) * sizeof(float2) + (size_t)J * NW * sizeof(uint64_t);
+  const int chunk = kVmGateEntries / (16 * J) > 1 ? kVmGateEntries / (16 * J) : 1;
+  const size_t shmem = (size_t)(2 * J * buf + 16 * J * chunk) * sizeof(float2) + (size_t)J * NW * sizeof(uint64_t);
   hipLaunchKernelGGL(part_vm_kernel, dim3(grid_blocks((n_jobs + J - 1) / J)), dim3(threads), shmem, stream,
-                     d_steps, n_steps, buf, J, g, n_jobs, job_traj, traj_base, job_prefix, NW, init, out, out_rank);
+                     d_steps, n_steps, buf, J, chunk, g, n_jobs, job_traj, traj_base, job_prefix, NW, init, out,
+                     out_rank);
   return hipGetLastError();
 }
 
@@ -1846,6 +2065,18 @@ hipError_t launch_sample(const SampleArgs& a, hipStream_t stream) {
   if (a.n_elems <= 0) return hipSuccess;
   const int n = 1 << a.b;
   const size_t shmem = (size_t)n * sizeof(int);
+  if (a.lane_path && a.b <= 5) {
+    const unsigned grid = grid_blocks((a.n_elems + 63) / 64);
+    switch (a.b) {
+      case 0: hipLaunchKernelGGL(sample_lanes_kernel<0>, dim3(grid), dim3(64), shmem, stream, a); break;
+      case 1: hipLaunchKernelGGL(sample_lanes_kernel<1>, dim3(grid), dim3(64), shmem, stream, a); break;
+      case 2: hipLaunchKernelGGL(sample_lanes_kernel<2>, dim3(grid), dim3(64), shmem, stream, a); break;
+      case 3: hipLaunchKernelGGL(sample_lanes_kernel<3>, dim3(grid), dim3(64), shmem, stream, a); break;
+      case 4: hipLaunchKernelGGL(sample_lanes_kernel<4>, dim3(grid), dim3(64), shmem, stream, a); break;
+      default: hipLaunchKernelGGL(sample_lanes_kernel<5>, dim3(grid), dim3(64), shmem, stream, a); break;
+    }
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(sample_kernel, dim3(grid_blocks(a.n_elems)), dim3(64), shmem, stream, a);
   return hipGetLastError();
 }
@@ -1854,7 +2085,10 @@ hipError_t launch_children(const ChildArgs& a, hipStream_t stream) {
   if (a.n_elems <= 0) return hipSuccess;
   const int n = 1 << a.b;
   const size_t shmem = (size_t)3 * n * sizeof(int);
-  hipLaunchKernelGGL(children_kernel, dim3(grid_blocks(a.n_elems)), dim3(64), shmem, stream, a);
+  if (a.lane_path && a.b <= 5)
+    hipLaunchKernelGGL(children_lanes_kernel, dim3(grid_blocks((a.n_elems + 63) / 64)), dim3(64), shmem, stream, a);
+  else
+    hipLaunchKernelGGL(children_kernel, dim3(grid_blocks(a.n_elems)), dim3(64), shmem, stream, a);
   return hipGetLastError();
 }
 
@@ -1913,11 +2147,11 @@ hipError_t launch_scan_i32(const int32_t* in, int32_t* out, int64_t n, int32_t* 
                            hipStream_t stream) {
   const int64_t nb = (n + kScanBlock - 1) / kScanBlock;
   if (n <= 0) {
-    hipLaunchKernelGGL(scan_sums_serial, dim3(1), dim3(1), 0, stream, d_scratch, (int64_t)0, d_total);
+    hipLaunchKernelGGL(scan_sums_block, dim3(1), dim3(1024), 0, stream, d_scratch, (int64_t)0, d_total);
     return hipGetLastError();
   }
   hipLaunchKernelGGL(scan_block_sums, dim3((unsigned)nb), dim3(256), 0, stream, in, n, d_scratch);
-  hipLaunchKernelGGL(scan_sums_serial, dim3(1), dim3(1), 0, stream, d_scratch, nb, d_total);
+  hipLaunchKernelGGL(scan_sums_block, dim3(1), dim3(1024), 0, stream, d_scratch, nb, d_total);
   hipLaunchKernelGGL(scan_apply, dim3((unsigned)nb), dim3(256), 0, stream, in, n, d_scratch, out);
   return hipGetLastError();
 }

@@ -112,6 +112,15 @@ def _expect_status(code, fn):
     assert ei.value.status == code, str(ei.value)
 
 
+def test_sample_kernel_option():
+    P = _lib()
+    c = W.chain10_d8().circuit
+    for name in ("auto", "wavefront"):
+        assert P.Plan(c, [5, 5], device=-1, sample_kernel=name).n_qubits == 10
+    with pytest.raises(ValueError):
+        P.Plan(c, [5, 5], device=-1, sample_kernel="lanes")
+
+
 def test_error_codes():
     P = _lib()
     c = W.chain10_d8().circuit
