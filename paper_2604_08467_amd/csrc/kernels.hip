@@ -117,8 +117,10 @@ __device__ inline void absorb_multi(const AbsorbStep& st, int sbase, const uint3
 // so the results are the same bit for bit.
 template <int NK, int NN>
 __device__ __forceinline__ void vm_step(const AbsorbStep& st, int nj, int lnm, int buf_elems, const float2* bufA,
-                                        float2* bufC, const float2* G, const uint64_t* pw, int NW) {
+                                        float2* bufC, const float2* G, const int* slot, const uint64_t* pw, int NW) {
   constexpr int nk = 1 << NK, nn = 1 << NN;
+  const int items = nj << lnm;
+  if ((int)threadIdx.x >= items) return;   // waves without items skip the step's table reads
   int kpos[NK > 0 ? NK : 1], npos[NN > 0 ? NN : 1], hm[4], hw[4], sq[kMaxSlices], sw[kMaxSlices];
   uint32_t koff[nk], noff[nn];
   int kB[nk], nB[nn];
@@ -136,7 +138,6 @@ __device__ __forceinline__ void vm_step(const AbsorbStep& st, int nj, int lnm, i
   for (int i = 0; i < kMaxSlices; ++i) { sq[i] = st.sq[i]; sw[i] = st.sw[i]; }
   const int nH = st.nH, nS = st.nS;
   const uint32_t mmask = (1u << lnm) - 1u;
-  const int items = nj << lnm;
   for (int i = threadIdx.x; i < items; i += blockDim.x) {
     const int j = i >> lnm;
     const uint32_t m = (uint32_t)i & mmask;
@@ -154,7 +155,7 @@ __device__ __forceinline__ void vm_step(const AbsorbStep& st, int nj, int lnm, i
 #pragma unroll
     for (int t = 0; t < NN; ++t) cbase = ((cbase >> npos[t]) << (npos[t] + 1)) | (cbase & ((1u << npos[t]) - 1u));
     const float2* Aj = bufA + (size_t)j * buf_elems;
-    const float2* Gj = G + 16 * j + hidx;
+    const float2* Gj = G + 16 * slot[j] + hidx;
     float2 a[nk], gv[nn][nk];
 #pragma unroll
     for (int k = 0; k < nk; ++k) a[k] = Aj[abase + koff[k]];
@@ -182,29 +183,43 @@ __device__ inline uint32_t init_offset(const InitArgs& in, uint32_t m, const uin
   return m;
 }
 
-// gate entries staged per chunk of steps: [chunk steps][J][16] float2
-constexpr int kVmGateEntries = 1536;
+// gate entries staged per chunk of steps: [chunk steps][trajectory slots][16] float2
+constexpr int kVmGateEntries = 512;
+constexpr int kVmMaxJobs = 32;        // jobs per workgroup (one wavefront assigns the trajectory slots)
 
 __global__ void __launch_bounds__(256) part_vm_kernel(const AbsorbStep* __restrict__ steps, int n_steps,
-                                                      int buf_elems, int J, int chunk, GateCtx g, int64_t n_jobs,
+                                                      int buf_elems, int J, GateCtx g, int64_t n_jobs,
                                                       const int32_t* __restrict__ job_traj, int32_t traj_base,
                                                       const uint64_t* __restrict__ job_prefix, int NW,
                                                       InitArgs init, float2* __restrict__ out, int out_rank) {
   // J jobs per workgroup run the same step list in lockstep: each step's
   // descriptor is decoded once for all of them and the threads take
-  // (job, kept index) work items.
+  // (job, kept index) work items.  Consecutive jobs of one trajectory (the
+  // elements of a batch are grouped by trajectory) share one slot of gate
+  // entries, so a step stages 16 entries per distinct trajectory, not per job.
   extern __shared__ float2 lds[];
+  __shared__ int slot[kVmMaxJobs], slot_traj[kVmMaxJobs], n_slots_s;
   float2* bufA = lds;                                   // [J][buf_elems]
   float2* bufC = lds + (size_t)J * buf_elems;           // [J][buf_elems]
-  float2* Gm = lds + 2 * (size_t)J * buf_elems;         // [chunk][J][16] gates of a chunk of steps
-  uint64_t* pw = reinterpret_cast<uint64_t*>(Gm + (size_t)16 * J * chunk);   // [J][NW] prefixes
+  float2* Gm = lds + 2 * (size_t)J * buf_elems;         // [chunk][slots][16] gates of a chunk of steps
+  uint64_t* pw = reinterpret_cast<uint64_t*>(Gm + kVmGateEntries);   // [J][NW] prefixes
   const int tid = threadIdx.x, nt = blockDim.x;
-  const int gj = tid >> 4, gi = tid & 15;               // the gate entry this thread loads (gj < J)
   const int64_t n_groups = (n_jobs + J - 1) / J;
   for (int64_t grp = blockIdx.x; grp < n_groups; grp += gridDim.x) {
     const int64_t job0 = grp * J;
     const int nj = (int)(n_jobs - job0 < J ? n_jobs - job0 : J);
     for (int i = tid; i < nj * NW; i += nt) pw[i] = job_prefix ? job_prefix[job0 * NW + i] : 0ull;
+    if (tid < 64) {   // wavefront 0: a slot per run of equal trajectories
+      const bool live = tid < nj;
+      const int tj = live ? (job_traj ? job_traj[job0 + tid] : traj_base + (int)(job0 + tid)) : -1;
+      const int tprev = __shfl_up(tj, 1);
+      const bool start = live && (tid == 0 || tprev != tj);
+      const uint64_t starts = __ballot(start);
+      const int sl = __popcll(starts & ((2ull << tid) - 1ull)) - 1;
+      if (live) slot[tid] = sl;
+      if (start) slot_traj[sl] = tj;
+      if (tid == 0) n_slots_s = __popcll(starts);
+    }
     __syncthreads();
     if (init.Vprev) {
       const uint32_t n0 = 1u << init.r0;
@@ -217,13 +232,13 @@ __global__ void __launch_bounds__(256) part_vm_kernel(const AbsorbStep* __restri
     } else {
       for (int j = tid; j < nj; j += nt) bufA[(size_t)j * buf_elems] = make_float2(1.f, 0.f);
     }
-    // the gates of a chunk of steps are staged in LDS at once: eight loads per
-    // thread in flight together (unconditional, from a valid trajectory, so that
-    // no load result is copied or waited for before the group's stores), the bra
-    // conjugation applied at the store
-    const bool gl = gj < nj;
-    const int traj = gl ? (job_traj ? job_traj[job0 + gj] : traj_base + (int)(job0 + gj)) : 0;
-    const float2* graw = g.merged + (int64_t)traj * g.G * 16 + gi;
+    // the gates of a chunk of steps are staged in LDS at once: up to eight loads
+    // per thread in flight together (unconditional, from a valid trajectory, so
+    // that no load result is copied or waited for before the group's stores),
+    // the bra conjugation applied at the store
+    const int n_slots = n_slots_s;
+    const int per_step = 16 * n_slots;
+    const int chunk = kVmGateEntries / per_step > 1 ? kVmGateEntries / per_step : 1;
     int cs = 0;
     for (int s = 0; s < n_steps; ++s) {
       const AbsorbStep& st = steps[s];
@@ -231,26 +246,30 @@ __global__ void __launch_bounds__(256) part_vm_kernel(const AbsorbStep* __restri
         cs = s;
         const int ce = n_steps - cs < chunk ? n_steps : cs + chunk;
         __syncthreads();   // every thread is done with the previous chunk's gates
-        for (int s1 = cs; s1 < ce; s1 += 8) {
-          float2 v[8];
+        for (int e = tid; e < per_step; e += nt) {
+          const int sl = e >> 4, gi = e & 15;
+          const float2* graw = g.merged + (int64_t)slot_traj[sl] * g.G * 16 + gi;
+          for (int s1 = cs; s1 < ce; s1 += 8) {
+            float2 v[8];
 #pragma unroll
-          for (int k = 0; k < 8; ++k) v[k] = graw[16 * steps[s1 + k < ce ? s1 + k : ce - 1].gate];
+            for (int k = 0; k < 8; ++k) v[k] = graw[16 * steps[s1 + k < ce ? s1 + k : ce - 1].gate];
 #pragma unroll
-          for (int k = 0; k < 8; ++k) {
-            if (gl && s1 + k < ce) {
-              float2 x = v[k];
-              if (steps[s1 + k].conj) x.y = -x.y;
-              Gm[(size_t)(s1 + k - cs) * 16 * J + tid] = x;
+            for (int k = 0; k < 8; ++k) {
+              if (s1 + k < ce) {
+                float2 x = v[k];
+                if (steps[s1 + k].conj) x.y = -x.y;
+                Gm[(size_t)(s1 + k - cs) * per_step + e] = x;
+              }
             }
           }
         }
       }
-      const float2* G = Gm + (size_t)(s - cs) * 16 * J;
+      const float2* G = Gm + (size_t)(s - cs) * per_step;
       __syncthreads();     // gates visible; previous step's C complete
       const int lnm = st.rC - st.nN;
       switch (st.nK * 8 + st.nN) {    // uniform: every thread takes the same case
 #define VM_CASE(K, N) \
-        case K * 8 + N: vm_step<K, N>(st, nj, lnm, buf_elems, bufA, bufC, G, pw, NW); break;
+        case K * 8 + N: vm_step<K, N>(st, nj, lnm, buf_elems, bufA, bufC, G, slot, pw, NW); break;
         VM_CASE(0, 0) VM_CASE(0, 1) VM_CASE(0, 2) VM_CASE(0, 3) VM_CASE(0, 4)
         VM_CASE(1, 0) VM_CASE(1, 1) VM_CASE(1, 2) VM_CASE(1, 3)
         VM_CASE(2, 0) VM_CASE(2, 1) VM_CASE(2, 2)
@@ -263,7 +282,7 @@ __global__ void __launch_bounds__(256) part_vm_kernel(const AbsorbStep* __restri
             const int j = i >> lnm;
             const uint32_t m = (uint32_t)i & ((1u << lnm) - 1u);
             absorb_one(st, slice_base(st, pw + j * NW), m, bufA + (size_t)j * buf_elems,
-                       bufC + (size_t)j * buf_elems, G + 16 * j);
+                       bufC + (size_t)j * buf_elems, G + 16 * slot[j]);
           }
         }
       }
@@ -1849,15 +1868,14 @@ hipError_t launch_part_vm(const AbsorbStep* d_steps, int n_steps, int peak, Gate
                           const InitArgs& init, float2* out, int out_rank, hipStream_t stream) {
   if (n_jobs <= 0) return hipSuccess;
   const int buf = 1 << (peak > 0 ? peak : 0);
-  // small tensors: up to 16 jobs share a 256-thread workgroup (<= 16 KB of tensors);
-  // one job per workgroup from 2^10 entries on
-  const int J = buf <= 64 ? 16 : (buf >= 1024 ? 1 : 1024 / buf);
+  // small tensors: up to 32 jobs share a 256-thread workgroup (2048 entries of
+  // tensors: 32 KB of A and C buffers, so that rank-5 steps of parts that end at
+  // rank 6 still give every thread an item); one job per workgroup at 2^11 entries
+  const int J = buf >= 2048 ? 1 : (2048 / buf > kVmMaxJobs ? kVmMaxJobs : 2048 / buf);
   const int threads = J > 1 ? 256 : (buf / 2 < 64 ? 64 : (buf / 2 > 256 ? 256 : buf / 2));
-  const int chunk = kVmGateEntries / (16 * J) > 1 ? kVmGateEntries / (16 * J) : 1;
-  const size_t shmem = (size_t)(2 * J * buf + 16 * J * chunk) * sizeof(float2) + (size_t)J * NW * sizeof(uint64_t);
+  const size_t shmem = (size_t)(2 * J * buf + kVmGateEntries) * sizeof(float2) + (size_t)J * NW * sizeof(uint64_t);
   hipLaunchKernelGGL(part_vm_kernel, dim3(grid_blocks((n_jobs + J - 1) / J)), dim3(threads), shmem, stream,
-                     d_steps, n_steps, buf, J, chunk, g, n_jobs, job_traj, traj_base, job_prefix, NW, init, out,
-                     out_rank);
+                     d_steps, n_steps, buf, J, g, n_jobs, job_traj, traj_base, job_prefix, NW, init, out, out_rank);
   return hipGetLastError();
 }
 
