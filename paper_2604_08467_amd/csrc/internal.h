@@ -71,6 +71,11 @@ struct AbsorbStep {
   // legs / n of the new legs, the offset into A / C and the index into B
   uint32_t koff[16], noff[16];
   int32_t kB[16], nB[16];
+  // gate entries in the order the LDS sweep reads them: entry d of the staged
+  // gate is entry (gperm[d / 8] >> 4 (d % 8)) & 15 of B.  For steps without
+  // hyper or sliced legs d = n 2^nK + k (n-major, so a job's products read
+  // consecutive entries at fixed offsets); the identity otherwise
+  uint32_t gperm[2] = {0x76543210u, 0xFEDCBA98u};
 };
 
 // Local view of an in-place step (same bit positions in and out, rank

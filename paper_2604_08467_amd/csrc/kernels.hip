@@ -115,7 +115,9 @@ __device__ inline void absorb_multi(const AbsorbStep& st, int sbase, const uint3
 // round of scalar loads and one round of LDS latency instead of one per product.
 // Products are accumulated in the order of absorb_one (k ascending from zero),
 // so the results are the same bit for bit.
-template <int NK, int NN>
+// PLAIN: no hyper or sliced legs; the staged gate is in (n, k) order, so the
+// gate entries of a product are read at fixed offsets from the job's slot.
+template <int NK, int NN, bool PLAIN>
 __device__ __forceinline__ void vm_step(const AbsorbStep& st, int nj, int lnm, int buf_elems, const float2* bufA,
                                         float2* bufC, const float2* G, const int* slot, const uint64_t* pw, int NW) {
   constexpr int nk = 1 << NK, nn = 1 << NN;
@@ -143,12 +145,14 @@ __device__ __forceinline__ void vm_step(const AbsorbStep& st, int nj, int lnm, i
     const uint32_t m = (uint32_t)i & mmask;
     const uint64_t* pj = pw + j * NW;
     int hidx = 0;
+    if (!PLAIN) {
 #pragma unroll
-    for (int t = 0; t < kMaxSlices; ++t)
-      if (t < nS) hidx += (int)bit_of_prefix(pj, sq[t]) * sw[t];
+      for (int t = 0; t < kMaxSlices; ++t)
+        if (t < nS) hidx += (int)bit_of_prefix(pj, sq[t]) * sw[t];
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
-      if (t < nH) hidx += (int)((m >> hm[t]) & 1u) * hw[t];
+      for (int t = 0; t < 4; ++t)
+        if (t < nH) hidx += (int)((m >> hm[t]) & 1u) * hw[t];
+    }
     uint32_t abase = m, cbase = m;
 #pragma unroll
     for (int t = 0; t < NK; ++t) abase = ((abase >> kpos[t]) << (kpos[t] + 1)) | (abase & ((1u << kpos[t]) - 1u));
@@ -162,7 +166,7 @@ __device__ __forceinline__ void vm_step(const AbsorbStep& st, int nj, int lnm, i
 #pragma unroll
     for (int n = 0; n < nn; ++n)
 #pragma unroll
-      for (int k = 0; k < nk; ++k) gv[n][k] = Gj[nB[n] + kB[k]];
+      for (int k = 0; k < nk; ++k) gv[n][k] = PLAIN ? Gj[n * nk + k] : Gj[nB[n] + kB[k]];
     float2* Cj = bufC + (size_t)j * buf_elems + cbase;
 #pragma unroll
     for (int n = 0; n < nn; ++n) {
@@ -248,11 +252,15 @@ __global__ void __launch_bounds__(256) part_vm_kernel(const AbsorbStep* __restri
         __syncthreads();   // every thread is done with the previous chunk's gates
         for (int e = tid; e < per_step; e += nt) {
           const int sl = e >> 4, gi = e & 15;
-          const float2* graw = g.merged + (int64_t)slot_traj[sl] * g.G * 16 + gi;
+          const float2* graw = g.merged + (int64_t)slot_traj[sl] * g.G * 16;
           for (int s1 = cs; s1 < ce; s1 += 8) {
             float2 v[8];
 #pragma unroll
-            for (int k = 0; k < 8; ++k) v[k] = graw[16 * steps[s1 + k < ce ? s1 + k : ce - 1].gate];
+            for (int k = 0; k < 8; ++k) {
+              const AbsorbStep& sk = steps[s1 + k < ce ? s1 + k : ce - 1];
+              const uint32_t src = (sk.gperm[gi >> 3] >> (4 * (gi & 7))) & 15u;
+              v[k] = graw[16 * sk.gate + src];
+            }
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
               if (s1 + k < ce) {
@@ -268,15 +276,22 @@ __global__ void __launch_bounds__(256) part_vm_kernel(const AbsorbStep* __restri
       __syncthreads();     // gates visible; previous step's C complete
       const int lnm = st.rC - st.nN;
       switch (st.nK * 8 + st.nN) {    // uniform: every thread takes the same case
-#define VM_CASE(K, N) \
-        case K * 8 + N: vm_step<K, N>(st, nj, lnm, buf_elems, bufA, bufC, G, slot, pw, NW); break;
+#define VM_CASE(K, N)                                                                     \
+        case K * 8 + N:                                                                   \
+          if (st.nH == 0 && st.nS == 0)                                                   \
+            vm_step<K, N, true>(st, nj, lnm, buf_elems, bufA, bufC, G, slot, pw, NW);     \
+          else                                                                            \
+            vm_step<K, N, false>(st, nj, lnm, buf_elems, bufA, bufC, G, slot, pw, NW);    \
+          break;
         VM_CASE(0, 0) VM_CASE(0, 1) VM_CASE(0, 2) VM_CASE(0, 3) VM_CASE(0, 4)
         VM_CASE(1, 0) VM_CASE(1, 1) VM_CASE(1, 2) VM_CASE(1, 3)
         VM_CASE(2, 0) VM_CASE(2, 1) VM_CASE(2, 2)
         VM_CASE(3, 0) VM_CASE(3, 1)
         VM_CASE(4, 0)
 #undef VM_CASE
-        default: {
+        default: {   // not reached: a gate tensor has at most four legs, and the cases above take
+                     // every step with nK + nN <= 4 (the gate is staged in B's order for these only
+                     // when the step has hyper or sliced legs)
           const int items = nj << lnm;
           for (int i = tid; i < items; i += nt) {
             const int j = i >> lnm;

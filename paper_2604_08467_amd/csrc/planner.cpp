@@ -168,6 +168,16 @@ bool simulate(const std::vector<const NetTensor*>& order, const std::set<int>& k
       for (int i = 0; i < st.nN; ++i)
         if ((n >> i) & 1) { st.noff[n] += 1u << st.npos[i]; st.nB[n] += st.nw[i]; }
     }
+    st.gperm[0] = 0x76543210u; st.gperm[1] = 0xFEDCBA98u;
+    if (st.nH == 0 && st.nS == 0) {
+      const int nk = 1 << st.nK, nn = 1 << st.nN;
+      for (int n = 0; n < nn; ++n)
+        for (int k = 0; k < nk; ++k) {
+          const int d = n * nk + k;
+          const uint32_t src = (uint32_t)(st.nB[n] + st.kB[k]) & 15u;
+          st.gperm[d >> 3] = (st.gperm[d >> 3] & ~(15u << (4 * (d & 7)))) | (src << (4 * (d & 7)));
+        }
+    }
     out.peak = std::max(out.peak, std::max(st.rA, st.rC));
     double m = std::ldexp(1.0, st.rC - st.nN);
     out.flops += 8.0 * m * std::ldexp(1.0, st.nN + st.nK);
