@@ -206,8 +206,13 @@ __global__ void __launch_bounds__(256) part_vm_kernel(const AbsorbStep* __restri
   float2* bufA = lds;                                   // [J][buf_elems]
   float2* bufC = lds + (size_t)J * buf_elems;           // [J][buf_elems]
   float2* Gm = lds + 2 * (size_t)J * buf_elems;         // [chunk][slots][16] gates of a chunk of steps
-  uint64_t* pw = reinterpret_cast<uint64_t*>(Gm + kVmGateEntries);   // [J][NW] prefixes
+  int4* stab = reinterpret_cast<int4*>(Gm + kVmGateEntries);   // [n_steps] gate | conj << 31, gperm
+  uint64_t* pw = reinterpret_cast<uint64_t*>(stab + n_steps);  // [J][NW] prefixes
   const int tid = threadIdx.x, nt = blockDim.x;
+  // the step list's gate indices, once per workgroup (visible after the first barrier)
+  for (int s = tid; s < n_steps; s += nt)
+    stab[s] = make_int4(steps[s].gate | (steps[s].conj ? (int)0x80000000 : 0), (int)steps[s].gperm[0],
+                        (int)steps[s].gperm[1], 0);
   const int64_t n_groups = (n_jobs + J - 1) / J;
   for (int64_t grp = blockIdx.x; grp < n_groups; grp += gridDim.x) {
     const int64_t job0 = grp * J;
@@ -225,6 +230,37 @@ __global__ void __launch_bounds__(256) part_vm_kernel(const AbsorbStep* __restri
       if (tid == 0) n_slots_s = __popcll(starts);
     }
     __syncthreads();
+    const int n_slots = n_slots_s;
+    const int per_step = 16 * n_slots;
+    const int chunk = kVmGateEntries / per_step > 1 ? kVmGateEntries / per_step : 1;
+    // gates of the steps [c0, c1) in LDS, every (step, slot, entry) of the chunk
+    // spread over all threads, two loads per thread in flight together
+    // (unconditional, from a clamped valid entry), the bra conjugation applied at
+    // the store
+    auto stage = [&](int c0, int c1) {
+      const int E = (c1 - c0) * per_step;
+      for (int e0 = 0; e0 < E; e0 += 2 * nt) {
+        float2 v[2];
+        int dst[2];
+        bool neg[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          const int e = e0 + u * nt + tid;
+          dst[u] = e < E ? e : -1;
+          const int ec = e < E ? e : E - 1;
+          const int q = ec >> 4, gi = ec & 15;
+          const int si = q / n_slots, sl = q - si * n_slots;
+          const int4 sd = stab[c0 + si];
+          const uint32_t perm = (uint32_t)(gi < 8 ? sd.y : sd.z);
+          const uint32_t src = (perm >> (4 * (gi & 7))) & 15u;
+          neg[u] = sd.x < 0;
+          v[u] = g.merged[((int64_t)slot_traj[sl] * g.G + (sd.x & 0x7fffffff)) * 16 + src];
+        }
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+          if (dst[u] >= 0) Gm[dst[u]] = neg[u] ? make_float2(v[u].x, -v[u].y) : v[u];
+      }
+    };
     if (init.Vprev) {
       const uint32_t n0 = 1u << init.r0;
       for (int i = tid; i < nj * (int)n0; i += nt) {
@@ -236,41 +272,14 @@ __global__ void __launch_bounds__(256) part_vm_kernel(const AbsorbStep* __restri
     } else {
       for (int j = tid; j < nj; j += nt) bufA[(size_t)j * buf_elems] = make_float2(1.f, 0.f);
     }
-    // the gates of a chunk of steps are staged in LDS at once: up to eight loads
-    // per thread in flight together (unconditional, from a valid trajectory, so
-    // that no load result is copied or waited for before the group's stores),
-    // the bra conjugation applied at the store
-    const int n_slots = n_slots_s;
-    const int per_step = 16 * n_slots;
-    const int chunk = kVmGateEntries / per_step > 1 ? kVmGateEntries / per_step : 1;
     int cs = 0;
+    if (n_steps > 0) stage(0, n_steps < chunk ? n_steps : chunk);
     for (int s = 0; s < n_steps; ++s) {
       const AbsorbStep& st = steps[s];
-      if (s == cs + chunk || s == 0) {
+      if (s == cs + chunk) {
         cs = s;
-        const int ce = n_steps - cs < chunk ? n_steps : cs + chunk;
         __syncthreads();   // every thread is done with the previous chunk's gates
-        for (int e = tid; e < per_step; e += nt) {
-          const int sl = e >> 4, gi = e & 15;
-          const float2* graw = g.merged + (int64_t)slot_traj[sl] * g.G * 16;
-          for (int s1 = cs; s1 < ce; s1 += 8) {
-            float2 v[8];
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-              const AbsorbStep& sk = steps[s1 + k < ce ? s1 + k : ce - 1];
-              const uint32_t src = (sk.gperm[gi >> 3] >> (4 * (gi & 7))) & 15u;
-              v[k] = graw[16 * sk.gate + src];
-            }
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-              if (s1 + k < ce) {
-                float2 x = v[k];
-                if (steps[s1 + k].conj) x.y = -x.y;
-                Gm[(size_t)(s1 + k - cs) * per_step + e] = x;
-              }
-            }
-          }
-        }
+        stage(cs, n_steps - cs < chunk ? n_steps : cs + chunk);
       }
       const float2* G = Gm + (size_t)(s - cs) * per_step;
       __syncthreads();     // gates visible; previous step's C complete
@@ -1888,7 +1897,8 @@ hipError_t launch_part_vm(const AbsorbStep* d_steps, int n_steps, int peak, Gate
   // rank 6 still give every thread an item); one job per workgroup at 2^11 entries
   const int J = buf >= 2048 ? 1 : (2048 / buf > kVmMaxJobs ? kVmMaxJobs : 2048 / buf);
   const int threads = J > 1 ? 256 : (buf / 2 < 64 ? 64 : (buf / 2 > 256 ? 256 : buf / 2));
-  const size_t shmem = (size_t)(2 * J * buf + kVmGateEntries) * sizeof(float2) + (size_t)J * NW * sizeof(uint64_t);
+  const size_t shmem = (size_t)(2 * J * buf + kVmGateEntries) * sizeof(float2) + (size_t)n_steps * sizeof(int4) +
+                       (size_t)J * NW * sizeof(uint64_t);
   hipLaunchKernelGGL(part_vm_kernel, dim3(grid_blocks((n_jobs + J - 1) / J)), dim3(threads), shmem, stream,
                      d_steps, n_steps, buf, J, g, n_jobs, job_traj, traj_base, job_prefix, NW, init, out, out_rank);
   return hipGetLastError();
