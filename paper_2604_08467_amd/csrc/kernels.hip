@@ -262,12 +262,26 @@ __global__ void __launch_bounds__(256) part_vm_kernel(const AbsorbStep* __restri
       }
     };
     if (init.Vprev) {
+      // nt / J threads per job: one parent index per thread, and every entry's
+      // load issued before the first store (at most 8 per thread: J 2^r0 <= 2048)
       const uint32_t n0 = 1u << init.r0;
-      for (int i = tid; i < nj * (int)n0; i += nt) {
-        const int j = i >> init.r0;
-        const uint32_t m = (uint32_t)i & (n0 - 1u);
+      const int tpj = nt / J, j = tid / tpj, jl = tid - j * tpj;
+      if (j < nj) {
         const float2* src = init.Vprev + (int64_t)init.parent[job0 + j] * init.stride;
-        bufA[(size_t)j * buf_elems + m] = src[init_offset(init, m, pw + j * NW)];
+        const uint64_t* pj = pw + j * NW;
+        float2* dst = bufA + (size_t)j * buf_elems;
+        float2 v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const uint32_t m = (uint32_t)(jl + u * tpj);
+          if (m < n0) v[u] = src[init_offset(init, m, pj)];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const uint32_t m = (uint32_t)(jl + u * tpj);
+          if (m < n0) dst[m] = v[u];
+        }
+        for (uint32_t m = (uint32_t)(jl + 8 * tpj); m < n0; m += tpj) dst[m] = src[init_offset(init, m, pj)];
       }
     } else {
       for (int j = tid; j < nj; j += nt) bufA[(size_t)j * buf_elems] = make_float2(1.f, 0.f);
@@ -1897,10 +1911,13 @@ hipError_t launch_part_vm(const AbsorbStep* d_steps, int n_steps, int peak, Gate
   // rank 6 still give every thread an item); one job per workgroup at 2^11 entries
   const int J = buf >= 2048 ? 1 : (2048 / buf > kVmMaxJobs ? kVmMaxJobs : 2048 / buf);
   const int threads = J > 1 ? 256 : (buf / 2 < 64 ? 64 : (buf / 2 > 256 ? 256 : buf / 2));
-  const size_t shmem = (size_t)(2 * J * buf + kVmGateEntries) * sizeof(float2) + (size_t)n_steps * sizeof(int4) +
+  // jobs' tensors one entry apart beyond their size: the same index of
+  // neighbouring jobs falls in different LDS banks
+  const int stride = J > 1 ? buf + 1 : buf;
+  const size_t shmem = (size_t)(2 * J * stride + kVmGateEntries) * sizeof(float2) + (size_t)n_steps * sizeof(int4) +
                        (size_t)J * NW * sizeof(uint64_t);
   hipLaunchKernelGGL(part_vm_kernel, dim3(grid_blocks((n_jobs + J - 1) / J)), dim3(threads), shmem, stream,
-                     d_steps, n_steps, buf, J, g, n_jobs, job_traj, traj_base, job_prefix, NW, init, out, out_rank);
+                     d_steps, n_steps, stride, J, g, n_jobs, job_traj, traj_base, job_prefix, NW, init, out, out_rank);
   return hipGetLastError();
 }
 
