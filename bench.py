@@ -820,7 +820,9 @@ def bench_batch_sweep(args):
     gates (depth 12, depolarising p=0.005), batches [10, ..., remainder, b].  For each b
     the plan is built (timed on the host), 4 trajectories are drawn, and the final
     batch is contracted for them (one element each, empty prefix), timed with events
-    on the launch stream after one untimed call."""
+    on the launch stream after one untimed call.  From b = 22 the per-trajectory
+    tensor would exceed rank 31: the plan slices crossing wires (slice_bits) and
+    the part is contracted once per slice value (use --workspace-gb 200)."""
     import numpy as np
     import torch
 
@@ -833,7 +835,7 @@ def bench_batch_sweep(args):
     n_traj = 4
     ws = torch.empty(int(args.workspace_gb * (1 << 30)), dtype=torch.uint8, device=dev)
     table = []
-    for b in (8, 10, 12, 14, 16, 18, 20):
+    for b in (8, 10, 12, 14, 16, 18, 20, 22, 24):
         rest = 100 - b
         bs = [10] * (rest // 10) + ([rest % 10] if rest % 10 else []) + [b]
         t0 = time.perf_counter()
@@ -859,10 +861,12 @@ def bench_batch_sweep(args):
         sites = plan.right_sites(j)
         distinct = len({tuple(kr[t, sites]) for t in range(E)})
         bi = plan.batch_info(j)
+        # a sliced last batch contracts its per-trajectory part once per slice value
+        n_sl = 2 ** bi["slice_bits"]
         row = {"b": b, "batches": bs, "plan_s": round(t_plan, 3), "call_ms": round(call_ms, 3),
                "distinct_right_parts": distinct, "ms_per_right_part": round(call_ms / distinct, 3),
-               "right_rank": bi["right_rank"], "crossing": bi["crossing"],
-               "alg_bytes_per_right_part": bi["bytes_per_traj"], "alg_flops_per_elem": bi["flops_per_elem"]}
+               "right_rank": bi["right_rank"], "crossing": bi["crossing"], "slice_bits": bi["slice_bits"],
+               "alg_bytes_per_right_part": bi["bytes_per_traj"] * n_sl, "alg_flops_per_elem": bi["flops_per_elem"]}
         table.append(row)
         print(f"batch-sweep: b={b} plan {t_plan:.2f} s, {E} trajectories ({distinct} distinct right parts) in "
               f"{call_ms:.2f} ms", file=sys.stderr, flush=True)

@@ -172,6 +172,16 @@ typedef struct {
                                    the same shots bit for bit (the lane kernels
                                    repeat the wavefront's FP64 operations in the
                                    same order); other values: INVALID_ARG        */
+  int32_t max_part_rank;        /* 0: 31.  Largest rank of the last batch's
+                                   per-trajectory tensors: beyond it the wires
+                                   crossing to the per-element part are sliced
+                                   (each fixed to 0 and 1 in turn on both parts,
+                                   the join's amplitudes summed over the slices;
+                                   the sum over a contracted index split into
+                                   terms), as long as the slice bits fit the
+                                   unused bits of the last prefix word (n + s
+                                   bits, all in word n / 64); 4..31, other
+                                   values: INVALID_ARG                           */
 } ptsbe_plan_opts_t;
 
 typedef struct {
@@ -216,6 +226,10 @@ typedef struct {
   int32_t right_longest_run;    /* steps of the longest fused run                */
   int32_t kept_gates;           /* gates in the batch's network (all of them
                                    unless the light cone removed some)           */
+  int32_t slice_bits;           /* last batch: crossing wires sliced (the parts
+                                   are contracted 2^slice_bits times and the
+                                   join's amplitudes summed); 0 otherwise; the
+                                   crossing count above excludes them            */
 } ptsbe_batch_info_t;
 
 ptsbe_status_t ptsbe_plan(const ptsbe_circuit_t* circuit, const ptsbe_plan_opts_t* opts,

@@ -121,7 +121,7 @@ class Plan:
 
     def __init__(self, circuit, batch_sizes, hypersamples=4, path_seed=0, device=0, precision=0,
                  device_budget_bytes=0, method="auto", light_cone=False, subtree_reuse=False,
-                 sample_kernel="auto"):
+                 sample_kernel="auto", max_part_rank=0):
         self._lib = _lib.load()
         self.n_qubits = circuit.n_qubits
         self.n_sites = len(circuit.site_gate)
@@ -134,7 +134,7 @@ class Plan:
             raise ValueError(f"sample_kernel must be one of {sorted(SAMPLE_KERNELS)}")
         opts = _lib.PlanOpts_t(len(bs), _ptr(bs, C.c_int32), int(hypersamples), int(path_seed), int(precision),
                                int(device), int(device_budget_bytes), METHODS[method], int(light_cone),
-                               int(subtree_reuse), SAMPLE_KERNELS[sample_kernel])
+                               int(subtree_reuse), SAMPLE_KERNELS[sample_kernel], int(max_part_rank))
         h = C.c_void_p()
         _lib.check(self._lib.ptsbe_plan(C.byref(arrs.struct), C.byref(opts), C.byref(h)))
         self._h = h

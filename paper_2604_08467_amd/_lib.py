@@ -48,7 +48,7 @@ class PlanOpts_t(C.Structure):
         ("n_batches", C.c_int32), ("batch_sizes", C.POINTER(C.c_int32)), ("hypersamples", C.c_int32),
         ("path_seed", C.c_uint64), ("precision", C.c_int32), ("device", C.c_int32),
         ("device_budget_bytes", C.c_size_t), ("method", C.c_int32), ("light_cone", C.c_int32),
-        ("subtree_reuse", C.c_int32), ("sample_kernel", C.c_int32),
+        ("subtree_reuse", C.c_int32), ("sample_kernel", C.c_int32), ("max_part_rank", C.c_int32),
     ]
 
 
@@ -72,7 +72,7 @@ class BatchInfo_t(C.Structure):
         ("flops_per_traj", C.c_double), ("flops_per_elem", C.c_double),
         ("join_flops_per_elem", C.c_double), ("bytes_per_traj", C.c_double),
         ("n_right_launches", C.c_int32), ("n_right_fused_steps", C.c_int32), ("right_longest_run", C.c_int32),
-        ("kept_gates", C.c_int32),
+        ("kept_gates", C.c_int32), ("slice_bits", C.c_int32),
     ]
 
 

@@ -431,12 +431,15 @@ size_t join_layout_bytes(const ptsbe::BatchPlan& bp) {
 // scratch), half for the per-element tensors and populations.
 struct ChunkCaps { int64_t t_cap = 0, e_cap = 0; };
 ChunkCaps chunk_caps(const ptsbe::BatchPlan& bp, const ptsbe::PartPlan& left, int64_t E, bool own_V,
-                     bool chunk_pop, bool exh, size_t avail) {
+                     bool chunk_pop, bool exh, size_t avail, int NW = 0) {
+  // NW > 0: sliced last batch (per job: prefix words with the slice bits; per
+  // element: the amplitude sum and one slice's amplitudes)
   const size_t per_traj = ((size_t)8 << bp.right.labels.size()) + join_layout_bytes(bp) +
-                          part_scratch_per_job(bp.right);
+                          part_scratch_per_job(bp.right) + (size_t)NW * 8;
   const int exh_tile_bits = bp.size > 12 ? bp.size - 12 : 0;
   const size_t per_elem = (own_V ? ((size_t)8 << left.labels.size()) : 0) + part_scratch_per_job(left) +
-                          (chunk_pop ? ((size_t)4 << bp.size) : 0) + (exh ? 16 + ((size_t)12 << exh_tile_bits) : 0);
+                          (chunk_pop ? ((size_t)4 << bp.size) : 0) + (exh ? 16 + ((size_t)12 << exh_tile_bits) : 0) +
+                          (NW > 0 ? ((size_t)16 << bp.size) + (size_t)NW * 8 : 0);
   ChunkCaps c;
   c.t_cap = (int64_t)std::min<size_t>((size_t)E, (avail / 2) / per_traj);
   c.e_cap = (int64_t)((avail / 2) / per_elem);
@@ -446,11 +449,155 @@ ChunkCaps chunk_caps(const ptsbe::BatchPlan& bp, const ptsbe::PartPlan& left, in
   return c;
 }
 
+// Last batch with sliced crossing wires (slice_bits = s > 0): for each chunk of
+// trajectories and each chunk of their elements, both parts are contracted once
+// per slice value (the value's bits OR'ed into the jobs' prefix words at bits
+// n..n+s-1, which the sliced legs read) and the join's amplitudes are summed over
+// the 2^s values: the contraction over the sliced wires split into its terms.
+// Populations (and the sampling, exhaustive and total outputs) are formed from
+// the sums.  The per-trajectory part is recomputed per element chunk.
+ptsbe_status_t run_batch_sliced(Plan& p, int j, const uint8_t* d_kraus, const float2* merged, int64_t E,
+                                BatchIO& io, Arena& ar, hipStream_t s) {
+  const ptsbe::BatchPlan& bp = p.batches[j];
+  const ptsbe::GateCtx g = gate_ctx(p, d_kraus, merged);
+  // the sliced batch is the last one: no later batch resumes from its left
+  // tensors, so io.V_out (which would differ per slice) is not written
+  const size_t mark0 = ar.used;
+  int32_t* d_first = (int32_t*)ar.take((size_t)(E + 1) * 4);
+  if (!d_first) return fail(PTSBE_ERR_OUT_OF_MEMORY, "workspace too small (trajectory ranges)");
+  HIP_TRY(ptsbe::launch_traj_ranges(io.elem_traj, io.U, E, d_first, s));
+  std::vector<int32_t> first((size_t)E + 1);
+  HIP_TRY(hipMemcpyAsync(first.data(), d_first, (size_t)(E + 1) * 4, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  const ptsbe::PartPlan& left = io.resume ? bp.left_resume : bp.left;
+  const int rT = (int)bp.right.labels.size(), rV = (int)left.labels.size();
+  const Plan::JoinDev& jdv = io.resume ? p.join_dev_r[j] : p.join_dev[j];
+  const int lkb = (int)bp.lk.size();
+  const bool use_ket = ptsbe::ketjoin_supported(lkb);
+  const size_t layout_bytes = join_layout_bytes(bp);
+  const size_t nb = (size_t)1 << bp.size;
+  const bool chunk_pop = io.sample || io.exh;
+  const int exh_tile_bits = bp.size > 12 ? bp.size - 12 : 0;
+  const ChunkCaps caps = chunk_caps(bp, left, E, true, chunk_pop, io.exh != nullptr, ar.left(), p.NW);
+  if (caps.t_cap < 1 || caps.e_cap < 1)
+    return fail(PTSBE_ERR_OUT_OF_MEMORY, "workspace too small for one trajectory of batch " + std::to_string(j));
+  const ptsbe::AbsorbStep* d_left = p.d_steps + p.part_step_off[3 * j + (io.resume ? 2 : 0)];
+  const ptsbe::AbsorbStep* d_right = p.d_steps + p.part_step_off[3 * j + 1];
+  ptsbe::GemvTiling gtile{};
+  const bool gemv_tiled = bp.xb.size() <= 1 && ptsbe::make_gemv_tiling(bp, gtile);
+  const int wi = p.n >> 6, sh = p.n & 63;
+  const int64_t n_slices = (int64_t)1 << bp.slice_bits;
+  for (int64_t t0 = 0; t0 < E; t0 += caps.t_cap) {
+    const int64_t t1 = std::min<int64_t>(E, t0 + caps.t_cap), n_rt = t1 - t0;
+    const int64_t e0 = first[t0], e1 = first[t1];
+    if (e1 <= e0) continue;
+    const bool gemv = ptsbe::ketjoin_gemv_supported((int)bp.xb.size(), lkb, (int)bp.xT.size()) &&
+                      e1 - e0 <= 2 * (t1 - t0);
+    for (int64_t a0 = e0; a0 < e1; a0 += caps.e_cap) {
+      const int64_t a1 = std::min<int64_t>(e1, a0 + caps.e_cap), ne = a1 - a0;
+      const size_t mark = ar.used;
+      float2* T = (float2*)ar.take((size_t)n_rt * ((size_t)8 << rT));
+      float2* Tc = (!gemv && use_ket) ? (float2*)ar.take((size_t)n_rt * layout_bytes) : nullptr;
+      uint64_t* rpre = (uint64_t*)ar.take((size_t)n_rt * p.NW * 8);
+      float2* V = (float2*)ar.take((size_t)ne * ((size_t)8 << rV));
+      uint64_t* epre = (uint64_t*)ar.take((size_t)ne * p.NW * 8);
+      float2* acc = (float2*)ar.take((size_t)ne * nb * 8);
+      float2* amp = (float2*)ar.take((size_t)ne * nb * 8);
+      float* pop = chunk_pop ? (float*)ar.take((size_t)ne * nb * 4) : nullptr;
+      if (!T || (!gemv && use_ket && !Tc) || !rpre || !V || !epre || !acc || !amp || (chunk_pop && !pop))
+        return fail(PTSBE_ERR_OUT_OF_MEMORY, "workspace too small (sliced batch)");
+      HIP_TRY(hipMemsetAsync(acc, 0, (size_t)ne * nb * 8, s));
+      ptsbe::InitArgs init;
+      if (io.resume) {
+        init.Vprev = io.V_prev;
+        init.stride = io.V_prev_stride;
+        init.parent = io.parent + a0;
+        init.r0 = bp.resume_rank0;
+        init.nsl = (int)bp.resume_slice_pos.size();
+        for (int i = 0; i < init.nsl; ++i) { init.pos[i] = bp.resume_slice_pos[i]; init.q[i] = bp.resume_slice_q[i]; }
+      }
+      int64_t tA = t0, tB = t1 - 1;
+      while (tA + 1 < t1 && first[tA + 1] <= a0) ++tA;
+      while (tB > tA && first[tB] >= a1) --tB;
+      int64_t max_rows = 0;
+      for (int64_t t = tA; t <= tB; ++t) {
+        const int64_t lo = std::max<int64_t>(first[t], a0), hi = std::min<int64_t>(first[t + 1], a1);
+        max_rows = std::max<int64_t>(max_rows, (hi - lo) << bp.xb.size());
+      }
+      for (int64_t sv = 0; sv < n_slices; ++sv) {
+        const uint64_t bits = (uint64_t)sv << sh;
+        HIP_TRY(ptsbe::launch_prefix_or(nullptr, rpre, n_rt, p.NW, wi, bits, s));
+        ptsbe_status_t st = run_part(p, bp.right, d_right, g, n_rt, nullptr, (int32_t)t0, rpre, ptsbe::InitArgs(), T,
+                                     ar, s);
+        if (st != PTSBE_OK) return st;
+        if (Tc)
+          HIP_TRY(ptsbe::launch_permute_T(T, (int64_t)1 << rT, n_rt, p.d_tables, p.join_dev[j], (int)bp.xT.size(),
+                                          lkb, 0, Tc, s));
+        HIP_TRY(ptsbe::launch_prefix_or(io.elem_prefix + a0 * p.NW, epre, ne, p.NW, wi, bits, s));
+        st = run_part(p, left, d_left, g, ne, io.elem_traj + a0, 0, epre, init, V, ar, s);
+        if (st != PTSBE_OK) return st;
+        ptsbe::JoinArgs ja{};
+        ja.V = V; ja.v_stride = (int64_t)1 << rV;
+        ja.T = T; ja.t_stride = (int64_t)1 << rT;
+        ja.elem_traj = io.elem_traj + a0; ja.traj_base = (int32_t)t0; ja.tslot = nullptr;
+        ja.n_elems = ne;
+        ja.xb_bits = (int)bp.xb.size(); ja.lk_bits = lkb; ja.xT_bits = (int)bp.xT.size();
+        ja.tab = p.d_tables; ja.jd = jdv;
+        ja.b = bp.size; ja.doubled = 0;
+        ja.pop = nullptr;
+        ja.amp = amp;
+        if (gemv) {
+          if (gemv_tiled) HIP_TRY(ptsbe::launch_ketjoin_gemv_tiled(ja, gtile, s));
+          else HIP_TRY(ptsbe::launch_ketjoin_gemv(ja, s));
+        } else if (use_ket) {
+          ptsbe::QformArgs qa{};
+          qa.V = V; qa.v_stride = (int64_t)1 << rV; qa.v_base = a0;
+          qa.Tc = Tc; qa.Th = nullptr; qa.traj_base = (int32_t)t0; qa.tslot = nullptr;
+          qa.traj0 = (int32_t)tA;
+          qa.first = d_first; qa.e_lo = a0; qa.e_hi = a1;
+          qa.xb_bits = (int)bp.xb.size(); qa.lk_bits = lkb; qa.xT_bits = (int)bp.xT.size();
+          qa.b = bp.size; qa.tab = p.d_tables; qa.jd = jdv;
+          qa.pop = nullptr;
+          qa.amp = amp;
+          HIP_TRY(ptsbe::launch_ketjoin(qa, (int)(tB - tA + 1), (int)max_rows, s));
+        } else {
+          HIP_TRY(ptsbe::launch_join(ja, s));
+        }
+        HIP_TRY(ptsbe::launch_amp_accumulate(acc, amp, (int64_t)ne * (int64_t)nb, s));
+      }
+      float* pop_dst = chunk_pop ? pop : (io.pop_out ? io.pop_out + a0 * (int64_t)nb : nullptr);
+      if (pop_dst) HIP_TRY(ptsbe::launch_amp_population(acc, pop_dst, (int64_t)ne * (int64_t)nb, s));
+      if (io.amp_out)
+        HIP_TRY(hipMemcpyAsync(io.amp_out + a0 * (int64_t)nb, acc, (size_t)ne * nb * 8, hipMemcpyDeviceToDevice, s));
+      if (io.sample) {
+        ptsbe::SampleArgs sa = io.sa;
+        sa.pop = pop;
+        sa.n_elems = ne;
+        sa.elem_traj = io.elem_traj + a0;
+        sa.elem_shot_off = io.sa.elem_shot_off + a0;
+        sa.elem_shot_cnt = io.sa.elem_shot_cnt + a0;
+        sa.elem_total = io.sa.elem_total + a0;
+        sa.child_cnt = io.sa.child_cnt ? io.sa.child_cnt + a0 : nullptr;
+        HIP_TRY(ptsbe::launch_sample(sa, s));
+      } else if (io.exh) {
+        ptsbe_status_t st = exhaustive_chunk(bp, io, pop, a0, ne, exh_tile_bits, ar, s);
+        if (st != PTSBE_OK) return st;
+      } else if (io.totals && pop_dst) {
+        HIP_TRY(ptsbe::launch_row_totals(pop_dst, ne, bp.size, io.totals + a0, s));
+      }
+      ar.used = mark;
+    }
+  }
+  ar.used = mark0;
+  return PTSBE_OK;
+}
+
 ptsbe_status_t run_batch(Plan& p, int j, const uint8_t* d_kraus, const float2* merged, int64_t E, BatchIO& io,
                          Arena& ar, hipStream_t s, std::vector<EventPair>& evs) {
   const ptsbe::BatchPlan& bp = p.batches[j];
-  const ptsbe::GateCtx g = gate_ctx(p, d_kraus, merged);
   if (io.U <= 0) return PTSBE_OK;
+  if (bp.slice_bits > 0) return run_batch_sliced(p, j, d_kraus, merged, E, io, ar, s);
+  const ptsbe::GateCtx g = gate_ctx(p, d_kraus, merged);
   const size_t mark0 = ar.used;
   // element ranges per trajectory
   int32_t* d_first = (int32_t*)ar.take((size_t)(E + 1) * 4);
@@ -874,6 +1021,9 @@ ptsbe_status_t ptsbe_plan(const ptsbe_circuit_t* c, const ptsbe_plan_opts_t* o, 
   if (o->sample_kernel != 0 && o->sample_kernel != 1)
     return fail(PTSBE_ERR_INVALID_ARG, "sample_kernel must be 0 or 1");
   p->sample_kernel = o->sample_kernel;
+  if (o->max_part_rank != 0 && (o->max_part_rank < 4 || o->max_part_rank > 31))
+    return fail(PTSBE_ERR_INVALID_ARG, "max_part_rank must be 0 or 4..31");
+  p->max_part_rank = o->max_part_rank ? o->max_part_rank : 31;
   p->gate_unitary.assign((size_t)p->G, 1);
   for (int g = 0; g < p->G; ++g) {
     const int d = 1 << p->arity[(size_t)g];
@@ -1263,6 +1413,7 @@ ptsbe_status_t ptsbe_plan_batch_info(ptsbe_plan_t plan, int32_t j, ptsbe_batch_i
       }
     }
   out->kept_gates = bp.kept_gates;
+  out->slice_bits = bp.slice_bits;
   return PTSBE_OK;
 }
 
@@ -1336,8 +1487,12 @@ ptsbe_status_t ptsbe_contract_workspace_size(ptsbe_plan_t plan, int32_t j, int64
     return PTSBE_OK;
   }
   const auto& bp = p->batches[j];
-  const size_t per_traj = join_traj_bytes(bp);
-  const size_t per_elem = ((size_t)8 << bp.left.labels.size()) + part_scratch_per_job(bp.left);
+  // a sliced last batch also holds the jobs' prefix words with the slice bits and,
+  // per element, the amplitude sum and one slice's amplitudes
+  const size_t sl_traj = bp.slice_bits ? (size_t)p->NW * 8 : 0;
+  const size_t sl_elem = bp.slice_bits ? ((size_t)16 << bp.size) + (size_t)p->NW * 8 : 0;
+  const size_t per_traj = join_traj_bytes(bp) + sl_traj;
+  const size_t per_elem = ((size_t)8 << bp.left.labels.size()) + part_scratch_per_job(bp.left) + sl_elem;
   size_t t = (size_t)std::min<int64_t>(E, 256), e = (size_t)std::min<int64_t>(n_elems, 65536);
   *bytes = merged_bytes(*p, E) + (size_t)(E + 1) * 4 +
            2 * (std::max<size_t>(t, 1) * per_traj + std::max<size_t>(e, 1) * per_elem) + (1 << 20);

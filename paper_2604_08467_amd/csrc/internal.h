@@ -243,6 +243,12 @@ struct BatchPlan {
   SplitTable o_x, o_b;              // output index: xT, xb
   double join_flops_per_elem = 0;
   int kept_gates = 0;               // gates in this batch's network (light cone applied)
+  // last batch: crossing wires fixed to each of their 2^slice_bits values in
+  // turn (sliced legs read bit n + i of the job's prefix words for wire i),
+  // so that the per-trajectory tensor stays within max_part_rank; the join's
+  // amplitudes are summed over the slices
+  int slice_bits = 0;
+  std::vector<int> slice_labels;
 };
 
 struct RgWindow;
@@ -316,6 +322,7 @@ struct Plan {
   // light cone of doubled networks: gate_unitary[g] when the bare gate and every
   // operator its sites may insert are unitary (to kUnitaryTol)
   bool light_cone = false;
+  int max_part_rank = 31;              // last batch's per-trajectory tensor rank before slicing
   std::vector<char> gate_unitary;
   // subtree reuse in the per-trajectory parts (launches shared by jobs that agree
   // on the sites absorbed so far)
@@ -500,6 +507,13 @@ struct SampleArgs {
   int lane_path = 0;                     // b <= 5 and about one shot per element: one lane per element
 };
 hipError_t launch_sample(const SampleArgs& a, hipStream_t stream);
+
+// Sliced last batch: dst[i] = src[i] (zero when src is null) with `bits` OR'ed
+// into word wi of each of the n rows of NW words; acc[i] += amp[i]; pop[i] = |acc[i]|^2.
+hipError_t launch_prefix_or(const uint64_t* src, uint64_t* dst, int64_t n, int NW, int wi, uint64_t bits,
+                            hipStream_t stream);
+hipError_t launch_amp_accumulate(float2* acc, const float2* amp, int64_t n, hipStream_t stream);
+hipError_t launch_amp_population(const float2* acc, float* pop, int64_t n, hipStream_t stream);
 
 // Non-proportional NBS (Sec. III-B): element e of a non-final batch takes
 // `draws` fresh draws on the rows [e * draws, (e + 1) * draws); traj_base[t] is

@@ -2121,6 +2121,48 @@ hipError_t launch_row_totals(const float* pop, int64_t n_elems, int b, double* t
   return hipGetLastError();
 }
 
+__global__ void prefix_or_kernel(const uint64_t* __restrict__ src, uint64_t* __restrict__ dst, int64_t n, int NW,
+                                 int wi, uint64_t bits) {
+  for (int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; id < n * NW; id += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t v = src ? src[id] : 0ull;
+    dst[id] = (int)(id % NW) == wi ? (v | bits) : v;
+  }
+}
+
+__global__ void amp_accumulate_kernel(float2* __restrict__ acc, const float2* __restrict__ amp, int64_t n) {
+  for (int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; id < n; id += (int64_t)gridDim.x * blockDim.x) {
+    const float2 a = acc[id], b = amp[id];
+    acc[id] = make_float2(a.x + b.x, a.y + b.y);
+  }
+}
+
+__global__ void amp_population_kernel(const float2* __restrict__ acc, float* __restrict__ pop, int64_t n) {
+  for (int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; id < n; id += (int64_t)gridDim.x * blockDim.x) {
+    const float2 a = acc[id];
+    pop[id] = a.x * a.x + a.y * a.y;
+  }
+}
+
+hipError_t launch_prefix_or(const uint64_t* src, uint64_t* dst, int64_t n, int NW, int wi, uint64_t bits,
+                            hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(prefix_or_kernel, dim3(grid_blocks((n * NW + 255) / 256)), dim3(256), 0, stream, src, dst, n,
+                     NW, wi, bits);
+  return hipGetLastError();
+}
+
+hipError_t launch_amp_accumulate(float2* acc, const float2* amp, int64_t n, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(amp_accumulate_kernel, dim3(grid_blocks((n + 255) / 256)), dim3(256), 0, stream, acc, amp, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_amp_population(const float2* acc, float* pop, int64_t n, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(amp_population_kernel, dim3(grid_blocks((n + 255) / 256)), dim3(256), 0, stream, acc, pop, n);
+  return hipGetLastError();
+}
+
 hipError_t launch_sample(const SampleArgs& a, hipStream_t stream) {
   if (a.n_elems <= 0) return hipSuccess;
   const int n = 1 << a.b;

@@ -457,18 +457,59 @@ bool build_batch_plans(Plan& p, std::string& err) {
     for (int L : left_labels)
       if (L < NL && right_labels.count(L) && final_of[L] < 0) bp.lk.push_back(L);
     for (int L : bp.lk) bp.lb.push_back(L + NL);
-    std::set<int> keep_left(bp.lk.begin(), bp.lk.end());
-    keep_left.insert(bp.xb.begin(), bp.xb.end());
+    std::string e1;
     std::set<int> keep_right(bp.lk.begin(), bp.lk.end());
     keep_right.insert(bp.xT.begin(), bp.xT.end());
     if (bp.doubled) keep_right.insert(bp.lb.begin(), bp.lb.end());
-    std::string e1;
-    if (!plan_part(left, keep_left, p.hypersamples, p.path_seed * 1315423911ULL + 2 * j + 1, bp.left, e1)) {
-      err = "batch " + std::to_string(j) + " left part: " + e1;
+    bool right_ok = plan_part(right, keep_right, p.hypersamples, p.path_seed * 1315423911ULL + 2 * j + 2, bp.right, e1);
+    if (right_ok && !bp.doubled && bp.right.peak > p.max_part_rank) {
+      right_ok = false;
+      e1 = "per-trajectory tensor of rank " + std::to_string(bp.right.peak) + " above max_part_rank";
+    }
+    if (!right_ok && !bp.doubled) {
+      // Slicing (last batch): fix the first s crossing wires (the earliest labels)
+      // on both parts to each of their values in turn; sliced legs read prefix bit
+      // n + i, which must lie in the last prefix word, past the qubits' bits.
+      const std::vector<int> lk_all = bp.lk;
+      for (int sb = 1; sb <= (int)lk_all.size() && !right_ok; ++sb) {
+        if ((p.n >> 6) != ((p.n + sb - 1) >> 6) || p.n + sb > 64 * p.NW) break;
+        std::map<int, int> sl_idx;
+        for (int i = 0; i < sb; ++i) sl_idx[lk_all[(size_t)i]] = i;
+        auto slice_legs = [&](std::vector<NetTensor>& ts) {
+          for (auto& t : ts)
+            for (int i = 0; i < t.nlegs; ++i) {
+              auto it = t.label[i] >= 0 ? sl_idx.find(t.label[i]) : sl_idx.end();
+              if (it == sl_idx.end()) continue;
+              t.slice[i] = SL_PREFIX;
+              t.sq[i] = p.n + it->second;
+              t.label[i] = -1;
+            }
+        };
+        std::vector<NetTensor> right_s = right;
+        slice_legs(right_s);
+        std::set<int> keep_s(lk_all.begin() + sb, lk_all.end());
+        keep_s.insert(bp.xT.begin(), bp.xT.end());
+        std::string e2;
+        PartPlan rp;
+        if (!plan_part(right_s, keep_s, p.hypersamples, p.path_seed * 1315423911ULL + 2 * j + 2, rp, e2)) continue;
+        if (rp.peak > p.max_part_rank) continue;
+        right_ok = true;
+        bp.right = rp;
+        right = right_s;
+        slice_legs(left);
+        bp.slice_bits = sb;
+        bp.slice_labels.assign(lk_all.begin(), lk_all.begin() + sb);
+        bp.lk.assign(lk_all.begin() + sb, lk_all.end());
+      }
+    }
+    if (!right_ok) {
+      err = "batch " + std::to_string(j) + " right part: " + e1;
       return false;
     }
-    if (!plan_part(right, keep_right, p.hypersamples, p.path_seed * 1315423911ULL + 2 * j + 2, bp.right, e1)) {
-      err = "batch " + std::to_string(j) + " right part: " + e1;
+    std::set<int> keep_left(bp.lk.begin(), bp.lk.end());
+    keep_left.insert(bp.xb.begin(), bp.xb.end());
+    if (!plan_part(left, keep_left, p.hypersamples, p.path_seed * 1315423911ULL + 2 * j + 1, bp.left, e1)) {
+      err = "batch " + std::to_string(j) + " left part: " + e1;
       return false;
     }
     if ((int)bp.lk.size() > 12) {
@@ -488,7 +529,9 @@ bool build_batch_plans(Plan& p, std::string& err) {
       std::vector<std::pair<int, int>> sl;   // (position in parent tensor, qubit)
       for (size_t i = 0; i < plabels.size(); ++i) {
         auto it = std::find(pv.xb.begin(), pv.xb.end(), plabels[i]);
+        auto is = std::find(bp.slice_labels.begin(), bp.slice_labels.end(), plabels[i]);
         if (it != pv.xb.end()) sl.push_back({(int)i, pv.xb_qubits[it - pv.xb.begin()]});
+        else if (is != bp.slice_labels.end()) sl.push_back({(int)i, p.n + (int)(is - bp.slice_labels.begin())});
         else init.push_back(plabels[i]);
       }
       std::vector<NetTensor> delta;
@@ -519,7 +562,7 @@ bool build_batch_plans(Plan& p, std::string& err) {
     bp.t_b = make_table(bp.doubled ? bp.lb : std::vector<int>(), bp.right.labels);
     bp.o_x = make_out_table(bp.xT, xT_q, a);
     bp.o_b = make_out_table(bp.xb, xb_q, a);
-    double rows = std::ldexp(1.0, (int)bp.xb.size());
+    double rows = std::ldexp(1.0, (int)bp.xb.size() + bp.slice_bits);   // one join per slice
     double K = std::ldexp(1.0, (int)bp.lk.size());
     double X = std::ldexp(1.0, (int)bp.xT.size());
     if (bp.doubled && qform_supported((int)bp.lk.size())) {
