@@ -112,6 +112,34 @@ def _expect_status(code, fn):
     assert ei.value.status == code, str(ei.value)
 
 
+def test_last_batch_slicing_plan():
+    """max_part_rank: the last batch's crossing wires are sliced until its
+    per-trajectory tensor fits; the crossing count drops by the sliced wires and
+    the doubled batches are unchanged."""
+    P = _lib()
+    rng = np.random.default_rng(6060)
+    c = W.Circuit(12)
+    dep = c.add_channel(W.depolarizing(0.03))
+    for layer in W.brickwork_1d(12, 8):
+        for (q0, q1) in layer:
+            g = c.add_gate((q0, q1), W.haar_su4(rng))
+            c.add_site(g, (q0,), dep)
+    c = c.round_to_complex64()
+    full = P.Plan(c, [3, 3, 6], device=-1, method="network")
+    f2 = full.batch_info(2)
+    assert f2["slice_bits"] == 0
+    for cap in (9, 7, 5):
+        sl = P.Plan(c, [3, 3, 6], device=-1, method="network", max_part_rank=cap)
+        b2 = sl.batch_info(2)
+        assert b2["slice_bits"] > 0 and b2["right_peak_rank"] <= cap
+        assert b2["crossing"] + b2["slice_bits"] == f2["crossing"]
+        for j in (0, 1):
+            assert sl.batch_info(j)["slice_bits"] == 0
+            assert sl.batch_info(j)["right_rank"] == full.batch_info(j)["right_rank"]
+    for bad in (3, 32, -1):
+        _expect_status(1, lambda: P.Plan(c, [3, 3, 6], device=-1, method="network", max_part_rank=bad))
+
+
 def test_sample_kernel_option():
     P = _lib()
     c = W.chain10_d8().circuit
