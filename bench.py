@@ -155,6 +155,7 @@ def main():
     ap.add_argument("--points", default="50x200,50x400,100x600",
                     help="exhaustive-paper workload: n x g points of the paper's random-circuit family")
     ap.add_argument("--final-batches", default="20,24,28", help="exhaustive-paper workload: b_f values")
+    ap.add_argument("--sweep-sizes", default="8,10,12,14,16,18,20,22,24", help="batch-sweep workload: final batch sizes")
     ap.add_argument("--workload", choices=["brickwork50", "ragged", "exhaustive", "batch-sweep", "grid5x5",
                                            "exhaustive-paper", "hea20", "batch-tune"],
                     default="brickwork50",
@@ -835,7 +836,7 @@ def bench_batch_sweep(args):
     n_traj = 4
     ws = torch.empty(int(args.workspace_gb * (1 << 30)), dtype=torch.uint8, device=dev)
     table = []
-    for b in (8, 10, 12, 14, 16, 18, 20, 22, 24):
+    for b in [int(v) for v in args.sweep_sizes.split(",")]:
         rest = 100 - b
         bs = [10] * (rest // 10) + ([rest % 10] if rest % 10 else []) + [b]
         t0 = time.perf_counter()

@@ -492,7 +492,7 @@ ptsbe_status_t run_batch_sliced(Plan& p, int j, const uint8_t* d_kraus, const fl
     const int64_t e0 = first[t0], e1 = first[t1];
     if (e1 <= e0) continue;
     const bool gemv = ptsbe::ketjoin_gemv_supported((int)bp.xb.size(), lkb, (int)bp.xT.size()) &&
-                      e1 - e0 <= 2 * (t1 - t0);
+                      (lkb <= 6 || gemv_tiled) && e1 - e0 <= 2 * (t1 - t0);
     for (int64_t a0 = e0; a0 < e1; a0 += caps.e_cap) {
       const int64_t a1 = std::min<int64_t>(e1, a0 + caps.e_cap), ne = a1 - a0;
       const size_t mark = ar.used;
@@ -693,7 +693,7 @@ ptsbe_status_t run_batch(Plan& p, int j, const uint8_t* d_kraus, const float2* m
     // last batch with at most two elements per trajectory: a GEMV on T's own layout
     // (T read once per element) beats the canonical copy plus the MFMA join
     const bool gemv = !bp.doubled && ptsbe::ketjoin_gemv_supported((int)bp.xb.size(), lkb, (int)bp.xT.size()) &&
-                      e1 - e0 <= 2 * (t1 - t0);
+                      (lkb <= 6 || gemv_tiled) && e1 - e0 <= 2 * (t1 - t0);
     float2* Tc = nullptr;
     float* Th = nullptr;
     if (gemv) {

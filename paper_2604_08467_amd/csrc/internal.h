@@ -438,7 +438,8 @@ hipError_t launch_join(const JoinArgs& a, hipStream_t stream);
 // Last-batch join as an HBM-bound GEMV on the right part's own layout (no
 // canonical copy): for elements of at most 4 rows and at least 256 values of x.
 inline bool ketjoin_gemv_supported(int xb_bits, int lk_bits, int xT_bits) {
-  return xb_bits <= 2 && lk_bits <= 6 && xT_bits >= 8;
+  // ketjoin_gemv_kernel (k <= 64), or the tiled kernel (k in LDS chunks, x >= 2^12)
+  return (xb_bits <= 2 && lk_bits <= 6 && xT_bits >= 8) || (xb_bits <= 1 && lk_bits <= 12 && xT_bits >= 12);
 }
 hipError_t launch_ketjoin_gemv(const JoinArgs& a, hipStream_t stream);
 // Tiling of the GEMV join over x when T's x bits are scattered (xT >= 12): a

@@ -565,16 +565,19 @@ __global__ void __launch_bounds__(256) ketjoin_gemv_kernel(JoinArgs a) {
 // their T offsets, so a wavefront's reads are contiguous runs), accumulates all
 // k in registers, and the populations pass through LDS to be written in order
 // of their output offsets.
+// k is taken in chunks of kGemvKChunk (the chunk's V rows and T offsets staged in
+// LDS), so that crossings of up to 12 wires (a sliced last batch keeps many) fit.
+constexpr int kGemvKChunk = 512;
+
 template <int ROWS>
 __global__ void __launch_bounds__(256) ketjoin_gemv_tiled_kernel(JoinArgs a, GemvTiling g) {
-  __shared__ float2 Vs[ROWS][64];
-  __shared__ int64_t tk[64];
+  __shared__ float2 Vs[ROWS][kGemvKChunk];
+  __shared__ int64_t tk[kGemvKChunk];
   __shared__ float outs[ROWS][4096];
   const int nk = 1 << a.lk_bits;
   const int lo_b = a.xb_bits < 12 ? a.xb_bits : 12;
   const int lo_k = a.lk_bits < 12 ? a.lk_bits : 12;
   const int tid = threadIdx.x;
-  if (tid < nk) tk[tid] = tab(a.tab, a.jd.tk_lo, a.jd.tk_hi, lo_k, (uint32_t)tid);
   int64_t t_lo = 0, or_lo = 0, w_lo = 0;
   int l_lo = 0;
 #pragma unroll
@@ -596,13 +599,6 @@ __global__ void __launch_bounds__(256) ketjoin_gemv_tiled_kernel(JoinArgs a, Gem
     int64_t tbase = 0, obase = 0;
     for (int h = 0; h < g.n_hi; ++h)
       if ((tile >> h) & 1) { tbase += g.t_hi[h]; obase += g.o_hi[h]; }
-    __syncthreads();                       // Vs and outs of the previous tile are no longer read
-    if (tid < ROWS * nk) {
-      const int r = tid / nk, k = tid % nk;
-      Vs[r][k] = a.V[e * a.v_stride + tab(a.tab, a.jd.vr_lo, a.jd.vr_hi, lo_b, (uint32_t)r) +
-                     tab(a.tab, a.jd.vc_lo, a.jd.vc_hi, lo_k, (uint32_t)k)];
-    }
-    __syncthreads();
     const int32_t ti = a.elem_traj[e] - a.traj_base;
     const float2* T = a.T + (int64_t)(a.tslot ? a.tslot[ti] : ti) * a.t_stride + tbase + t_lo;
     float2 acc[16][ROWS];
@@ -610,20 +606,31 @@ __global__ void __launch_bounds__(256) ketjoin_gemv_tiled_kernel(JoinArgs a, Gem
     for (int j = 0; j < 16; ++j)
 #pragma unroll
       for (int r = 0; r < ROWS; ++r) acc[j][r] = make_float2(0.f, 0.f);
-    for (int k = 0; k < nk; ++k) {
-      const float2* Tk = T + tk[k];
-      float2 v[ROWS];
+    for (int k0 = 0; k0 < nk; k0 += kGemvKChunk) {
+      const int kn = nk - k0 < kGemvKChunk ? nk - k0 : kGemvKChunk;
+      __syncthreads();                     // Vs, tk and outs of the previous chunk or tile are no longer read
+      for (int i = tid; i < ROWS * kn; i += 256) {
+        const int r = i / kn, k = i % kn;
+        Vs[r][k] = a.V[e * a.v_stride + tab(a.tab, a.jd.vr_lo, a.jd.vr_hi, lo_b, (uint32_t)r) +
+                       tab(a.tab, a.jd.vc_lo, a.jd.vc_hi, lo_k, (uint32_t)(k0 + k))];
+      }
+      for (int k = tid; k < kn; k += 256) tk[k] = tab(a.tab, a.jd.tk_lo, a.jd.tk_hi, lo_k, (uint32_t)(k0 + k));
+      __syncthreads();
+      for (int k = 0; k < kn; ++k) {
+        const float2* Tk = T + tk[k];
+        float2 v[ROWS];
 #pragma unroll
-      for (int r = 0; r < ROWS; ++r) v[r] = Vs[r][k];
+        for (int r = 0; r < ROWS; ++r) v[r] = Vs[r][k];
 #pragma unroll
-      for (int j = 0; j < 16; ++j) {
-        int64_t hj = 0;
+        for (int j = 0; j < 16; ++j) {
+          int64_t hj = 0;
 #pragma unroll
-        for (int s = 0; s < 4; ++s)
-          if ((j >> s) & 1) hj += g.t_off[8 + s];
-        const float2 t = Tk[hj];
+          for (int s = 0; s < 4; ++s)
+            if ((j >> s) & 1) hj += g.t_off[8 + s];
+          const float2 t = Tk[hj];
 #pragma unroll
-        for (int r = 0; r < ROWS; ++r) acc[j][r] = cfma(v[r], t, acc[j][r]);
+          for (int r = 0; r < ROWS; ++r) acc[j][r] = cfma(v[r], t, acc[j][r]);
+        }
       }
     }
 #pragma unroll
@@ -2009,7 +2016,7 @@ hipError_t launch_ketjoin_gemv(const JoinArgs& a, hipStream_t stream) {
 
 hipError_t launch_ketjoin_gemv_tiled(const JoinArgs& a, const GemvTiling& g, hipStream_t stream) {
   if (a.n_elems <= 0) return hipSuccess;
-  if (a.doubled || a.xb_bits > 1 || a.lk_bits > 6 || a.xT_bits < 12 || g.n_hi != a.xT_bits - 12 || g.n_hi > 32)
+  if (a.doubled || a.xb_bits > 1 || a.lk_bits > 12 || a.xT_bits < 12 || g.n_hi != a.xT_bits - 12 || g.n_hi > 32)
     return hipErrorInvalidValue;
   const dim3 grid(grid_blocks(a.n_elems << g.n_hi));
   if (a.xb_bits == 0) hipLaunchKernelGGL(ketjoin_gemv_tiled_kernel<1>, grid, dim3(256), 0, stream, a, g);

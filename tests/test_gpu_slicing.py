@@ -159,3 +159,33 @@ def test_chain100_b22_sliced_against_b20():
     print(f"chain100 b22 ({bi['slice_bits']} sliced wires, rank {bi['right_peak_rank']}): P(prefix) {Z:.6g}, "
           f"max |P22 - P20| / P(prefix) = {err:.3g}", flush=True)
     assert err <= 1e-6
+
+
+@pytest.mark.parametrize("bs", [[6, 14], [7, 13]], ids=["rows2", "rows1"])
+@pytest.mark.parametrize("cap", [0, 20])
+def test_gemv_join_with_many_crossing_wires_vs_oracle(bs, cap):
+    """The last batch's GEMV join over T in its own layout with 2^11 crossing
+    values (k staged in LDS chunks of 512), unsliced and with the tensor capped at
+    rank 20 (sliced): a 20-qubit chain of depth 12, one element per trajectory,
+    populations against the FP64 statevector marginals."""
+    import paper_2604_08467_amd as P
+    torch, dev = torch_dev()
+    rng = np.random.default_rng(7070)
+    c = W.random_brickwork(20, 12, rng, 0.01).round_to_complex64()
+    plan = P.Plan(c, bs, method="network", max_part_rank=cap)
+    bi = plan.batch_info(1)
+    assert bi["crossing"] > 6 and bs[1] - bi["join_rows_log2"] >= 12
+    assert (bi["slice_bits"] > 0) == (cap > 0)
+    kr, _, _, _ = plan.sample_trajectories(7071, 6)
+    kd = to_dev(torch, dev, kr)
+    psis = oracle_states(c, kr)
+    pre = [int(p) for p in np.random.default_rng(7072).integers(0, 1 << bs[0], size=len(kr))]
+    pop, tot = _contract(plan, torch, dev, kd, range(len(kr)), pre, 1)
+    worst = 0.0
+    for i, p in enumerate(pre):
+        ref = sampling.marginal_from_state(psis[i], 20, bs[0], bs[1], p)
+        Z = max(float(ref.sum()), 1e-30)
+        worst = max(worst, np.abs(pop[i] - ref).max() / Z, abs(tot[i] - Z) / Z * 1e-1)
+    print(f"chain20 {bs} cap {cap}: crossing {bi['crossing']}, {bi['slice_bits']} sliced; max population err "
+          f"{worst:.3g} of Z", flush=True)
+    assert worst <= 1e-6
