@@ -11,6 +11,7 @@ trajectory pre-sampling happen before the timed region.
 Prints one JSON line (metric: sampled shots/s).
 """
 import argparse
+import glob
 import json
 import os
 import sys
@@ -25,7 +26,9 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3
 BF16_MFMA_PEAK_TFLOPS = 2500.0
 # the join kernel version that profiles/join_traffic.txt must name to be used
 SWEEP_KERNEL_TAG = "absorb_global_kernel<NK> single HBM sweep steps, 4 kept indices per thread"
-JOIN_KERNEL_TAG = "qform_mfma_kernel<32,8> bilinear slots"
+JOIN_KERNEL_TAG = "qform_mfma_kernel<32,NC> bilinear slots"
+# the LDS-sweep kernel version that profiles/lds_sweep_counters_brickwork50_b5.txt must name
+VM_KERNEL_TAG = "part_vm_kernel 64-job groups, trajectory gate slots, product-order gates, last step to HBM"
 
 
 def _oracle_shots_worker(circuit, kraus_row, traj, batch_sizes, seed, budget_s):
@@ -276,11 +279,13 @@ def main():
     join_s = prof["join_ms"] / 1e3
     achieved = prof["join_flops"] / join_s / 1e12 if join_s > 0 else 0.0
     traffic = None
-    if os.path.exists(args.traffic_file):
+    for tf in [args.traffic_file] + sorted(glob.glob(os.path.join(ROOT, "profiles", "join_traffic_*.txt"))):
+        if not os.path.exists(tf):
+            continue
         # "bytes_per_launch: N" written from two rocprofv3 counter runs of this command;
         # used only when its "kernel:" line names the join kernel as it is now
         # and the batch list it was measured on is this run's
-        kv = dict(ln.split(":", 1) for ln in open(args.traffic_file) if ":" in ln and not ln.startswith("#"))
+        kv = dict(ln.split(":", 1) for ln in open(tf) if ":" in ln and not ln.startswith("#"))
         if (kv.get("kernel", "").strip() == JOIN_KERNEL_TAG and "bytes_per_launch" in kv
                 and kv.get("batches", "").strip() == str(bs)):
             traffic = float(kv["bytes_per_launch"])
@@ -295,16 +300,31 @@ def main():
                 "flops": "real bilinear form over K^2 folded slots: 2K^2 per row and x (K=32: 2048; "
                          "the plain complex product would be 8320)",
                 "launches": prof["join_launches"], "kernel_ms_per_step": prof["join_ms"] / args.steps}
-    if vm["ms"] > prof["join_ms"]:
-        # small batches: the per-element LDS sweeps dominate the step; plain FP32
-        # arithmetic in LDS, against the chip's FP32 vector peak
-        join = dict(roofline)
+    vm_rec = None
+    if vm["ms"] > 0:
+        # the per-element LDS sweeps: plain FP32 arithmetic in LDS, against the
+        # chip's FP32 vector peak
         vm_rate = vm["flops"] / (vm["ms"] / 1e3) / 1e12 if vm["ms"] > 0 else 0.0
-        roofline = {"bound": "alu", "achieved": vm_rate, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                    "frac": vm_rate / FP32_VECTOR_PEAK_TFLOPS, "traffic": None,
-                    "kernel": "part_vm_kernel (whole per-element parts swept in LDS, one gate absorbed per step)",
-                    "flops": "8 real flops per complex multiply-add of each absorbed gate",
-                    "launches": vm["launches"], "kernel_ms_per_step": vm["ms"] / args.steps, "join": join}
+        vm_traffic = None
+        vm_file = os.path.join(ROOT, "profiles", "lds_sweep_counters_brickwork50_b5.txt")
+        if os.path.exists(vm_file) and vm["launches"] > 0:
+            # HBM bytes per step from two counter runs (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0),
+            # per launch; used only for the kernel version and batch list they were taken on
+            kv = dict(ln.split(":", 1) for ln in open(vm_file) if ":" in ln and not ln.startswith("#"))
+            if (kv.get("kernel_tag", "").strip() == VM_KERNEL_TAG and kv.get("batches", "").strip() == str(bs)
+                    and "fetch_bytes_per_step" in kv and "write_bytes_per_step" in kv):
+                per_step = float(kv["fetch_bytes_per_step"]) + float(kv["write_bytes_per_step"])
+                vm_traffic = per_step / (vm["launches"] / args.steps)
+        vm_rec = {"bound": "alu", "achieved": vm_rate, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                  "frac": vm_rate / FP32_VECTOR_PEAK_TFLOPS, "traffic": vm_traffic,
+                  "kernel": "part_vm_kernel (whole per-element parts swept in LDS, one gate absorbed per step)",
+                  "flops": "8 real flops per complex multiply-add of each absorbed gate",
+                  "launches": vm["launches"], "kernel_ms_per_step": vm["ms"] / args.steps}
+    # the kernel with the most event time is the roofline's; the other is reported beside it
+    if vm_rec is not None and vm["ms"] > prof["join_ms"]:
+        roofline = dict(vm_rec, join=roofline)
+    elif vm_rec is not None:
+        roofline = dict(roofline, lds_sweeps=vm_rec)
     line = {
         "metric": "sampled shots/sec", "value": shots_per_s, "unit": "shots/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3,

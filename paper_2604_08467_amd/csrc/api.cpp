@@ -119,8 +119,23 @@ ptsbe_status_t timed_part_vm(Plan& p, const ptsbe::PartPlan& pp, const ptsbe::Ab
     HIP_TRY(hipEventCreate(&ev.second));
     HIP_TRY(hipEventRecord(ev.first, s));
   }
-  HIP_TRY(ptsbe::launch_part_vm(d_steps, n_steps, peak, g, n_jobs, job_traj, traj_base, job_prefix, p.NW, init, out,
-                                out_rank, s));
+  // a last step that raises the rank past every other tensor of the sweep (the
+  // per-element parts of small batches end so) writes its output straight to HBM,
+  // so that the LDS buffers, and with them the jobs per workgroup, are sized for
+  // the ranks before it
+  int lds_peak = 0, direct = 0;
+  for (int i = 0; i < n_steps; ++i) {
+    const ptsbe::AbsorbStep& st = pp.steps[(size_t)i];
+    lds_peak = std::max(lds_peak, st.rA);
+    if (i + 1 < n_steps) lds_peak = std::max(lds_peak, st.rC);
+  }
+  if (n_steps > 0) {
+    const ptsbe::AbsorbStep& last = pp.steps[(size_t)n_steps - 1];
+    if (last.rC > lds_peak && last.rC == out_rank && last.nK <= 1 && last.nN > last.nK && last.nK + last.nN <= 4)
+      direct = 1;
+  }
+  HIP_TRY(ptsbe::launch_part_vm(d_steps, n_steps, direct ? lds_peak : peak, g, n_jobs, job_traj, traj_base, job_prefix,
+                                p.NW, init, out, out_rank, direct, s));
   if (p.profile) {
     HIP_TRY(hipEventRecord(ev.second, s));
     p.vm_evs.push_back(ev);

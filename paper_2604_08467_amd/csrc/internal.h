@@ -396,12 +396,15 @@ struct InitArgs {
   int pos[8] = {0, 0, 0, 0, 0, 0, 0, 0};   // sliced positions in the parent tensor (ascending)
   int q[8] = {0, 0, 0, 0, 0, 0, 0, 0};     // qubit whose prefix bit fixes each
 };
-// Run all steps of one part in LDS, one workgroup per job.
+// Run all steps of one part in LDS, up to 64 jobs per workgroup.
 // jobs: traj of job = job_traj ? job_traj[job] : job0 + job; prefix words of job.
+// peak: largest rank held in LDS; direct = 1: the last step (contracted legs <= 1,
+// more new legs than contracted) writes its output to `out` in HBM, its rank may
+// exceed peak.
 hipError_t launch_part_vm(const AbsorbStep* d_steps, int n_steps, int peak, GateCtx g,
                           int64_t n_jobs, const int32_t* job_traj, int32_t traj_base,
                           const uint64_t* job_prefix, int NW, const InitArgs& init, float2* out,
-                          int out_rank, hipStream_t stream);
+                          int out_rank, int direct, hipStream_t stream);
 hipError_t launch_init_gather(const InitArgs& init, int64_t n_jobs, const uint64_t* job_prefix, int NW,
                               float2* out, hipStream_t stream);
 // One absorb step over all jobs in global memory.

@@ -118,8 +118,11 @@ __device__ inline void absorb_multi(const AbsorbStep& st, int sbase, const uint3
 // PLAIN: no hyper or sliced legs; the staged gate is in (n, k) order, so the
 // gate entries of a product are read at fixed offsets from the job's slot.
 template <int NK, int NN, bool PLAIN>
+// C rows are c_stride apart from Cb: the LDS buffer, or the output in HBM for a
+// last step that raises the rank past every other tensor of the sweep.
 __device__ __forceinline__ void vm_step(const AbsorbStep& st, int nj, int lnm, int buf_elems, const float2* bufA,
-                                        float2* bufC, const float2* G, const int* slot, const uint64_t* pw, int NW) {
+                                        float2* Cb, int64_t c_stride, const float2* G, const int* slot,
+                                        const uint64_t* pw, int NW) {
   constexpr int nk = 1 << NK, nn = 1 << NN;
   const int items = nj << lnm;
   if ((int)threadIdx.x >= items) return;   // waves without items skip the step's table reads
@@ -167,7 +170,7 @@ __device__ __forceinline__ void vm_step(const AbsorbStep& st, int nj, int lnm, i
     for (int n = 0; n < nn; ++n)
 #pragma unroll
       for (int k = 0; k < nk; ++k) gv[n][k] = PLAIN ? Gj[n * nk + k] : Gj[nB[n] + kB[k]];
-    float2* Cj = bufC + (size_t)j * buf_elems + cbase;
+    float2* Cj = Cb + (int64_t)j * c_stride + cbase;
 #pragma unroll
     for (int n = 0; n < nn; ++n) {
       float2 acc = make_float2(0.f, 0.f);
@@ -189,13 +192,14 @@ __device__ inline uint32_t init_offset(const InitArgs& in, uint32_t m, const uin
 
 // gate entries staged per chunk of steps: [chunk steps][trajectory slots][16] float2
 constexpr int kVmGateEntries = 512;
-constexpr int kVmMaxJobs = 32;        // jobs per workgroup (one wavefront assigns the trajectory slots)
+constexpr int kVmMaxJobs = 64;        // jobs per workgroup (one wavefront assigns the trajectory slots)
 
 __global__ void __launch_bounds__(256) part_vm_kernel(const AbsorbStep* __restrict__ steps, int n_steps,
                                                       int buf_elems, int J, GateCtx g, int64_t n_jobs,
                                                       const int32_t* __restrict__ job_traj, int32_t traj_base,
                                                       const uint64_t* __restrict__ job_prefix, int NW,
-                                                      InitArgs init, float2* __restrict__ out, int out_rank) {
+                                                      InitArgs init, float2* __restrict__ out, int out_rank,
+                                                      int direct) {
   // J jobs per workgroup run the same step list in lockstep: each step's
   // descriptor is decoded once for all of them and the threads take
   // (job, kept index) work items.  Consecutive jobs of one trajectory (the
@@ -298,13 +302,31 @@ __global__ void __launch_bounds__(256) part_vm_kernel(const AbsorbStep* __restri
       const float2* G = Gm + (size_t)(s - cs) * per_step;
       __syncthreads();     // gates visible; previous step's C complete
       const int lnm = st.rC - st.nN;
+      if (direct && s == n_steps - 1) {
+        // the last step writes the output in HBM (its rank exceeds the LDS buffers)
+        float2* Co = out + job0 * ((int64_t)1 << out_rank);
+        const int64_t cst = (int64_t)1 << out_rank;
+        switch (st.nK * 8 + st.nN) {
+#define VM_OUT(K, N)                                                                       \
+          case K * 8 + N:                                                                  \
+            if (st.nH == 0 && st.nS == 0)                                                  \
+              vm_step<K, N, true>(st, nj, lnm, buf_elems, bufA, Co, cst, G, slot, pw, NW); \
+            else                                                                           \
+              vm_step<K, N, false>(st, nj, lnm, buf_elems, bufA, Co, cst, G, slot, pw, NW); \
+            break;
+          VM_OUT(0, 1) VM_OUT(0, 2) VM_OUT(0, 3) VM_OUT(0, 4) VM_OUT(1, 2) VM_OUT(1, 3)
+#undef VM_OUT
+          default: break;   // not reached: the host sets direct for these leg counts only
+        }
+        continue;
+      }
       switch (st.nK * 8 + st.nN) {    // uniform: every thread takes the same case
 #define VM_CASE(K, N)                                                                     \
         case K * 8 + N:                                                                   \
           if (st.nH == 0 && st.nS == 0)                                                   \
-            vm_step<K, N, true>(st, nj, lnm, buf_elems, bufA, bufC, G, slot, pw, NW);     \
+            vm_step<K, N, true>(st, nj, lnm, buf_elems, bufA, bufC, buf_elems, G, slot, pw, NW);  \
           else                                                                            \
-            vm_step<K, N, false>(st, nj, lnm, buf_elems, bufA, bufC, G, slot, pw, NW);    \
+            vm_step<K, N, false>(st, nj, lnm, buf_elems, bufA, bufC, buf_elems, G, slot, pw, NW); \
           break;
         VM_CASE(0, 0) VM_CASE(0, 1) VM_CASE(0, 2) VM_CASE(0, 3) VM_CASE(0, 4)
         VM_CASE(1, 0) VM_CASE(1, 1) VM_CASE(1, 2) VM_CASE(1, 3)
@@ -328,10 +350,11 @@ __global__ void __launch_bounds__(256) part_vm_kernel(const AbsorbStep* __restri
     }
     __syncthreads();
     const int64_t n_out = (int64_t)1 << out_rank;
-    for (int64_t i = tid; i < (int64_t)nj * n_out; i += nt) {
-      const int64_t j = i >> out_rank, k = i & (n_out - 1);
-      out[(job0 + j) * n_out + k] = bufA[j * buf_elems + k];
-    }
+    if (!direct || n_steps == 0)
+      for (int64_t i = tid; i < (int64_t)nj * n_out; i += nt) {
+        const int64_t j = i >> out_rank, k = i & (n_out - 1);
+        out[(job0 + j) * n_out + k] = bufA[j * buf_elems + k];
+      }
     __syncthreads();   // LDS is reused by the next group of this workgroup
   }
 }
@@ -1910,12 +1933,13 @@ hipError_t launch_init_gather(const InitArgs& init, int64_t n_jobs, const uint64
 
 hipError_t launch_part_vm(const AbsorbStep* d_steps, int n_steps, int peak, GateCtx g, int64_t n_jobs,
                           const int32_t* job_traj, int32_t traj_base, const uint64_t* job_prefix, int NW,
-                          const InitArgs& init, float2* out, int out_rank, hipStream_t stream) {
+                          const InitArgs& init, float2* out, int out_rank, int direct, hipStream_t stream) {
   if (n_jobs <= 0) return hipSuccess;
   const int buf = 1 << (peak > 0 ? peak : 0);
-  // small tensors: up to 32 jobs share a 256-thread workgroup (2048 entries of
-  // tensors: 32 KB of A and C buffers, so that rank-5 steps of parts that end at
-  // rank 6 still give every thread an item); one job per workgroup at 2^11 entries
+  // small tensors: up to 64 jobs share a 256-thread workgroup (2048 entries of
+  // tensors in the A and C buffers; peak is the largest rank held in LDS: with
+  // direct, the last step's larger output goes to HBM); one job per workgroup at
+  // 2^11 entries
   const int J = buf >= 2048 ? 1 : (2048 / buf > kVmMaxJobs ? kVmMaxJobs : 2048 / buf);
   const int threads = J > 1 ? 256 : (buf / 2 < 64 ? 64 : (buf / 2 > 256 ? 256 : buf / 2));
   // jobs' tensors one entry apart beyond their size: the same index of
@@ -1924,7 +1948,8 @@ hipError_t launch_part_vm(const AbsorbStep* d_steps, int n_steps, int peak, Gate
   const size_t shmem = (size_t)(2 * J * stride + kVmGateEntries) * sizeof(float2) + (size_t)n_steps * sizeof(int4) +
                        (size_t)J * NW * sizeof(uint64_t);
   hipLaunchKernelGGL(part_vm_kernel, dim3(grid_blocks((n_jobs + J - 1) / J)), dim3(threads), shmem, stream,
-                     d_steps, n_steps, stride, J, g, n_jobs, job_traj, traj_base, job_prefix, NW, init, out, out_rank);
+                     d_steps, n_steps, stride, J, g, n_jobs, job_traj, traj_base, job_prefix, NW, init, out, out_rank,
+                     direct);
   return hipGetLastError();
 }
 
