@@ -65,7 +65,12 @@ def _compare(out, ref_rows, ref_counts, bs, thr, tag):
     assert keys == sorted(keys)
 
 
-@pytest.mark.parametrize("method", ["network", "statevector"])
+# network-sliced: the last batch's per-trajectory tensor capped so that crossing
+# wires are sliced (2, 4 and 1 of them) and the join's amplitudes summed over slices
+SLICE_CAP = {(4, 4, 4): 6, (5, 7): 6, (3, 3, 3, 3): 5}
+
+
+@pytest.mark.parametrize("method", ["network", "statevector", "network-sliced"])
 @pytest.mark.parametrize("bs,draws,thr", [([4, 4, 4], 3, 1e-3), ([5, 7], 5, 0.0), ([3, 3, 3, 3], 2, 2e-3)],
                          ids=["4-4-4_k3", "5-7_k5", "3x4_k2"])
 def test_exhaustive_matches_oracle(bs, draws, thr, method):
@@ -73,7 +78,11 @@ def test_exhaustive_matches_oracle(bs, draws, thr, method):
     torch, dev = torch_dev()
     rng = np.random.default_rng(301)
     circ = W.random_brickwork(sum(bs), 5, rng, 0.02)
-    plan = P.Plan(circ, bs, method=method)
+    if method == "network-sliced":
+        plan = P.Plan(circ, bs, method="network", max_part_rank=SLICE_CAP[tuple(bs)])
+        assert plan.batch_info(len(bs) - 1)["slice_bits"] > 0
+    else:
+        plan = P.Plan(circ, bs, method=method)
     kr, mult, _, _ = plan.sample_trajectories(302, 12)
     out = plan.sample_nonproportional(to_dev(torch, dev, kr), draws, 303, thr, mult_dev=to_dev(torch, dev, mult))
     torch.cuda.synchronize()
