@@ -500,6 +500,8 @@ ptsbe_status_t run_batch_sliced(Plan& p, int j, const uint8_t* d_kraus, const fl
   const ptsbe::AbsorbStep* d_right = p.d_steps + p.part_step_off[3 * j + 1];
   ptsbe::GemvTiling gtile{};
   const bool gemv_tiled = bp.xb.size() <= 1 && ptsbe::make_gemv_tiling(bp, gtile);
+  ptsbe::GemvLanes glanes{};
+  const bool gemv_lanes = ptsbe::make_gemv_lanes(bp, glanes);
   const int wi = p.n >> 6, sh = p.n & 63;
   const int64_t n_slices = (int64_t)1 << bp.slice_bits;
   for (int64_t t0 = 0; t0 < E; t0 += caps.t_cap) {
@@ -507,7 +509,7 @@ ptsbe_status_t run_batch_sliced(Plan& p, int j, const uint8_t* d_kraus, const fl
     const int64_t e0 = first[t0], e1 = first[t1];
     if (e1 <= e0) continue;
     const bool gemv = ptsbe::ketjoin_gemv_supported((int)bp.xb.size(), lkb, (int)bp.xT.size()) &&
-                      (lkb <= 6 || gemv_tiled) && e1 - e0 <= 2 * (t1 - t0);
+                      (lkb <= 6 || gemv_tiled || gemv_lanes) && e1 - e0 <= 2 * (t1 - t0);
     for (int64_t a0 = e0; a0 < e1; a0 += caps.e_cap) {
       const int64_t a1 = std::min<int64_t>(e1, a0 + caps.e_cap), ne = a1 - a0;
       const size_t mark = ar.used;
@@ -562,7 +564,8 @@ ptsbe_status_t run_batch_sliced(Plan& p, int j, const uint8_t* d_kraus, const fl
         ja.pop = nullptr;
         ja.amp = amp;
         if (gemv) {
-          if (gemv_tiled) HIP_TRY(ptsbe::launch_ketjoin_gemv_tiled(ja, gtile, s));
+          if (gemv_lanes) HIP_TRY(ptsbe::launch_ketjoin_gemv_lanes(ja, glanes, s));
+          else if (gemv_tiled) HIP_TRY(ptsbe::launch_ketjoin_gemv_tiled(ja, gtile, s));
           else HIP_TRY(ptsbe::launch_ketjoin_gemv(ja, s));
         } else if (use_ket) {
           ptsbe::QformArgs qa{};
@@ -644,6 +647,8 @@ ptsbe_status_t run_batch(Plan& p, int j, const uint8_t* d_kraus, const float2* m
   const std::vector<int32_t> rsites = io.h_kraus ? right_sites(p, bp) : std::vector<int32_t>();
   ptsbe::GemvTiling gtile{};
   const bool gemv_tiled = !bp.doubled && bp.xb.size() <= 1 && ptsbe::make_gemv_tiling(bp, gtile);
+  ptsbe::GemvLanes glanes{};
+  const bool gemv_lanes = !bp.doubled && ptsbe::make_gemv_lanes(bp, glanes);
   const int64_t S = (int64_t)p.site_gate.size();
   std::vector<std::vector<int32_t>> keep;         // host sources of async uploads
   struct SyncOnExit {                             // on every return (errors included), the
@@ -708,7 +713,7 @@ ptsbe_status_t run_batch(Plan& p, int j, const uint8_t* d_kraus, const float2* m
     // last batch with at most two elements per trajectory: a GEMV on T's own layout
     // (T read once per element) beats the canonical copy plus the MFMA join
     const bool gemv = !bp.doubled && ptsbe::ketjoin_gemv_supported((int)bp.xb.size(), lkb, (int)bp.xT.size()) &&
-                      (lkb <= 6 || gemv_tiled) && e1 - e0 <= 2 * (t1 - t0);
+                      (lkb <= 6 || gemv_tiled || gemv_lanes) && e1 - e0 <= 2 * (t1 - t0);
     float2* Tc = nullptr;
     float* Th = nullptr;
     if (gemv) {
@@ -763,7 +768,8 @@ ptsbe_status_t run_batch(Plan& p, int j, const uint8_t* d_kraus, const float2* m
         HIP_TRY(hipEventRecord(ev.a, s));
       }
       if (gemv) {
-        if (gemv_tiled) HIP_TRY(ptsbe::launch_ketjoin_gemv_tiled(ja, gtile, s));
+        if (gemv_lanes) HIP_TRY(ptsbe::launch_ketjoin_gemv_lanes(ja, glanes, s));
+        else if (gemv_tiled) HIP_TRY(ptsbe::launch_ketjoin_gemv_tiled(ja, gtile, s));
         else HIP_TRY(ptsbe::launch_ketjoin_gemv(ja, s));
       } else if (use_mfma) {
         ptsbe::QformArgs qa{};

@@ -458,6 +458,24 @@ struct GemvTiling {
   int64_t t_hi[32], o_hi[32];
 };
 bool make_gemv_tiling(const BatchPlan& bp, GemvTiling& g);
+// GEMV join when the lowest T offsets belong to crossing wires (k): the 6 bits
+// of smallest T offset, x or k, go on the lanes of a wavefront (its reads are
+// then contiguous), each lane sums its k values over the k bits off the lanes,
+// and the lanes of one x are summed by shuffles.  A wavefront takes one value
+// of the x bits off the lanes at a time.
+struct GemvLanes {
+  int64_t lane_toff[6];  // T offset of lane bit i (the six smallest offsets)
+  int64_t lane_ooff[6];  // output offset of lane bit i when it is an x bit, else 0
+  int32_t lane_kbit[6];  // k value of lane bit i when it is a k bit, else 0
+  int32_t lane_is_k[6];
+  int32_t n_hx, n_hk;    // x and k bits off the lanes
+  int64_t hx_toff[32], hx_ooff[32];
+  int64_t hk_toff[12];
+  int32_t hk_kbit[12];
+};
+// false unless a k bit has the smallest T offset (the tiled GEMV serves the rest)
+bool make_gemv_lanes(const BatchPlan& bp, GemvLanes& g);
+hipError_t launch_ketjoin_gemv_lanes(const JoinArgs& a, const GemvLanes& g, hipStream_t stream);
 hipError_t launch_ketjoin_gemv_tiled(const JoinArgs& a, const GemvTiling& g, hipStream_t stream);
 struct QformArgs {
   const float2* V; int64_t v_stride; int64_t v_base;   // V rows of elements [v_base, ...)

@@ -684,6 +684,86 @@ __global__ void __launch_bounds__(256) ketjoin_gemv_tiled_kernel(JoinArgs a, Gem
   }
 }
 
+// GEMV join with the six lowest-offset bits of T on the lanes (GemvLanes): a
+// wavefront reads 64 neighbouring entries of T per k value off the lanes, each
+// lane accumulates its own k values, and the k lane bits are summed by a fixed
+// butterfly of shuffles.  A workgroup stages one element's V rows and the k
+// offsets off the lanes in LDS; its wavefronts take values of the x bits off the
+// lanes in turn.
+template <int ROWS>
+__global__ void __launch_bounds__(256) ketjoin_gemv_lanes_kernel(JoinArgs a, GemvLanes g, int64_t wg_per_elem) {
+  extern __shared__ float2 lds_gl[];
+  const int nk = 1 << a.lk_bits, nkh = 1 << g.n_hk;
+  float2* Vs = lds_gl;                                              // [ROWS][nk]
+  int64_t* khoff = reinterpret_cast<int64_t*>(Vs + ROWS * nk);      // [nkh] T offset of the k bits off the lanes
+  int* khval = reinterpret_cast<int*>(khoff + nkh);                 // [nkh] their k value
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lo_b = a.xb_bits < 12 ? a.xb_bits : 12, lo_k = a.lk_bits < 12 ? a.lk_bits : 12;
+  int64_t ltoff = 0, looff = 0;
+  int lkv = 0, kred = 0;
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    if ((lane >> i) & 1) { ltoff += g.lane_toff[i]; looff += g.lane_ooff[i]; lkv |= g.lane_kbit[i]; }
+    if (g.lane_is_k[i]) kred |= 1 << i;
+  }
+  const bool writer = (lane & kred) == 0;
+  for (int i = tid; i < nkh; i += 256) {
+    int64_t o = 0;
+    int v = 0;
+    for (int h = 0; h < g.n_hk; ++h)
+      if ((i >> h) & 1) { o += g.hk_toff[h]; v |= g.hk_kbit[h]; }
+    khoff[i] = o;
+    khval[i] = v;
+  }
+  const int64_t nxb = (int64_t)1 << g.n_hx;
+  const int64_t nout = (int64_t)1 << a.b;
+  int64_t obr[ROWS];
+#pragma unroll
+  for (int r = 0; r < ROWS; ++r) obr[r] = tab(a.tab, a.jd.ob_lo, a.jd.ob_hi, lo_b, (uint32_t)r);
+  for (int64_t bid = blockIdx.x; bid < a.n_elems * wg_per_elem; bid += gridDim.x) {
+    const int64_t e = bid / wg_per_elem, gi = bid % wg_per_elem;
+    __syncthreads();                       // the previous element's V rows are no longer read
+    for (int i = tid; i < ROWS * nk; i += 256) {
+      const int r = i / nk, k = i % nk;
+      Vs[i] = a.V[e * a.v_stride + tab(a.tab, a.jd.vr_lo, a.jd.vr_hi, lo_b, (uint32_t)r) +
+                  tab(a.tab, a.jd.vc_lo, a.jd.vc_hi, lo_k, (uint32_t)k)];
+    }
+    __syncthreads();
+    const int32_t ti = a.elem_traj[e] - a.traj_base;
+    const float2* T = a.T + (int64_t)(a.tslot ? a.tslot[ti] : ti) * a.t_stride + ltoff;
+    for (int64_t xb = gi * 4 + wave; xb < nxb; xb += wg_per_elem * 4) {
+      int64_t xto = 0, xoo = 0;
+      for (int h = 0; h < g.n_hx; ++h)
+        if ((xb >> h) & 1) { xto += g.hx_toff[h]; xoo += g.hx_ooff[h]; }
+      float2 acc[ROWS];
+#pragma unroll
+      for (int r = 0; r < ROWS; ++r) acc[r] = make_float2(0.f, 0.f);
+#pragma unroll 8
+      for (int kh = 0; kh < nkh; ++kh) {
+        const float2 t = T[xto + khoff[kh]];
+        const int kv = lkv | khval[kh];
+#pragma unroll
+        for (int r = 0; r < ROWS; ++r) acc[r] = cfma(Vs[r * nk + kv], t, acc[r]);
+      }
+#pragma unroll
+      for (int i = 0; i < 6; ++i)
+        if ((kred >> i) & 1)
+#pragma unroll
+          for (int r = 0; r < ROWS; ++r) {
+            acc[r].x += __shfl_xor(acc[r].x, 1 << i);
+            acc[r].y += __shfl_xor(acc[r].y, 1 << i);
+          }
+      if (writer)
+#pragma unroll
+        for (int r = 0; r < ROWS; ++r) {
+          const int64_t o = e * nout + looff + xoo + obr[r];
+          if (a.amp) a.amp[o] = acc[r];
+          if (a.pop) a.pop[o] = acc[r].x * acc[r].x + acc[r].y * acc[r].y;
+        }
+    }
+  }
+}
+
 // Gather the per-trajectory part T into the canonical layout used by the MFMA
 // join: Tc[x][k][k'] with k' fastest (K = 2^lk_bits), via the plan's tables.
 __global__ void permute_T_kernel(const float2* __restrict__ T, int64_t t_stride, int64_t n_traj,
@@ -2046,6 +2126,22 @@ hipError_t launch_ketjoin_gemv_tiled(const JoinArgs& a, const GemvTiling& g, hip
   const dim3 grid(grid_blocks(a.n_elems << g.n_hi));
   if (a.xb_bits == 0) hipLaunchKernelGGL(ketjoin_gemv_tiled_kernel<1>, grid, dim3(256), 0, stream, a, g);
   else hipLaunchKernelGGL(ketjoin_gemv_tiled_kernel<2>, grid, dim3(256), 0, stream, a, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_ketjoin_gemv_lanes(const JoinArgs& a, const GemvLanes& g, hipStream_t stream) {
+  if (a.n_elems <= 0) return hipSuccess;
+  if (a.doubled || a.xb_bits > 1 || a.lk_bits > 12 || g.n_hk > 10 || g.n_hx > 32) return hipErrorInvalidValue;
+  const int rows = 1 << a.xb_bits, nk = 1 << a.lk_bits, nkh = 1 << g.n_hk;
+  const size_t shmem = (size_t)rows * nk * sizeof(float2) + (size_t)nkh * (sizeof(int64_t) + sizeof(int));
+  const int64_t nxb = (int64_t)1 << g.n_hx;
+  // about 32 values of the off-lane x bits per wavefront, at most 2^20 workgroups
+  int64_t wpe = (nxb + 127) / 128;
+  if (wpe < 1) wpe = 1;
+  while (wpe > 1 && a.n_elems * wpe > ((int64_t)1 << 20)) wpe = (wpe + 1) / 2;
+  const dim3 grid(grid_blocks(a.n_elems * wpe));
+  if (rows == 1) hipLaunchKernelGGL(ketjoin_gemv_lanes_kernel<1>, grid, dim3(256), shmem, stream, a, g, wpe);
+  else hipLaunchKernelGGL(ketjoin_gemv_lanes_kernel<2>, grid, dim3(256), shmem, stream, a, g, wpe);
   return hipGetLastError();
 }
 

@@ -1064,6 +1064,43 @@ void build_sv_ops(Plan& p) {
 }
 
 
+bool make_gemv_lanes(const BatchPlan& bp, GemvLanes& g) {
+  const int nx = (int)bp.xT.size(), nk = (int)bp.lk.size();
+  const int rows = 1 << (int)bp.xb.size();
+  if (bp.doubled || bp.xb.size() > 1 || nk < 1 || nk > 12 || nx + nk < 6 || nx > 32) return false;
+  if ((size_t)rows * ((size_t)8 << nk) > 32768) return false;          // V rows staged in LDS
+  auto off = [](const SplitTable& t, int i) -> int64_t {
+    return i < t.lo_bits ? t.lo[(size_t)1 << i] : t.hi[(size_t)1 << (i - t.lo_bits)];
+  };
+  struct Bit { int64_t toff, ooff; int kbit; bool is_k; };
+  std::vector<Bit> bits;
+  for (int i = 0; i < nx; ++i) bits.push_back({off(bp.t_x, i), off(bp.o_x, i), 0, false});
+  for (int i = 0; i < nk; ++i) bits.push_back({off(bp.t_k, i), 0, 1 << i, true});
+  std::sort(bits.begin(), bits.end(), [](const Bit& a, const Bit& b) { return a.toff < b.toff; });
+  if (!bits[0].is_k) return false;
+  int n_hx = 0, n_hk = 0;
+  for (size_t q = 0; q < bits.size(); ++q) {
+    const Bit& b = bits[q];
+    if (q < 6) {
+      g.lane_toff[q] = b.toff;
+      g.lane_ooff[q] = b.is_k ? 0 : b.ooff;
+      g.lane_kbit[q] = b.is_k ? b.kbit : 0;
+      g.lane_is_k[q] = b.is_k ? 1 : 0;
+    } else if (b.is_k) {
+      g.hk_toff[n_hk] = b.toff;
+      g.hk_kbit[n_hk] = b.kbit;
+      ++n_hk;
+    } else {
+      g.hx_toff[n_hx] = b.toff;
+      g.hx_ooff[n_hx] = b.ooff;
+      ++n_hx;
+    }
+  }
+  g.n_hx = n_hx;
+  g.n_hk = n_hk;
+  return n_hk <= 10;
+}
+
 bool make_gemv_tiling(const BatchPlan& bp, GemvTiling& g) {
   const int nx = (int)bp.xT.size();
   if (nx < 12 || nx - 12 > 32) return false;
