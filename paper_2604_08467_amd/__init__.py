@@ -117,7 +117,14 @@ SAMPLE_KERNELS = {"auto": 0, "wavefront": 1}
 
 
 class Plan:
-    """ptsbe_plan: the unified contraction path of every batch (host, once)."""
+    """ptsbe_plan: the unified contraction path of every batch (host, once).
+
+    Options (ptsbe_plan_opts_t in include/ptsbe.h): light_cone prunes the doubled
+    networks to the measured qubits' past light cone; subtree_reuse shares partial
+    per-trajectory sweeps between error sets; sample_kernel "wavefront" forces one
+    wavefront per element in sampling and splitting (the default "auto" takes one
+    lane per element for small batches, with the same draws); max_part_rank caps the
+    last batch's per-trajectory tensor rank (0: 31), slicing crossing wires beyond it."""
 
     def __init__(self, circuit, batch_sizes, hypersamples=4, path_seed=0, device=0, precision=0,
                  device_budget_bytes=0, method="auto", light_cone=False, subtree_reuse=False,
