@@ -750,7 +750,7 @@ def bench_exhaustive_paper(args):
                 tot_rows += int(out["n_rows"])
                 tot_s += dt
                 del plan, outs, out
-            except Exception as e:      # a point beyond this build's limits is reported, not fatal
+            except Exception as e:      # a point beyond the library's limits is reported, not fatal
                 row["error"] = str(e)[:160]
             table.append(row)
             print(f"exhaustive-paper: {row}", file=sys.stderr, flush=True)
